@@ -1,0 +1,207 @@
+/*
+ * kpcg.h -- C ABI of the MI355X (gfx950) library for Tikhonov image
+ * deblurring with CG, PCG and flexible PCG preconditioned by a one-term
+ * Kronecker-product SVD approximation of the blur.
+ *
+ * Method: Chen, Ji & Nagy, "Half-Precision Kronecker Product SVD
+ * Preconditioner for Structured Inverse Problems" (arXiv:2311.15393).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - An image is an n x n float32 array, row-major and contiguous (element
+ *    (i, j) at i*n + j; i is the vertical index).  Images passed as `const
+ *    float *` / `float *` are DEVICE pointers owned by the caller.
+ *  - A PSF is a K x K float64 HOST array, row-major, K odd, centre (h, h),
+ *    h = (K-1)/2.  The library normalises nothing.  The blur A is the
+ *    zero-boundary true convolution
+ *        (A X)[i, j] = sum_{u,v=-h..h} P[h+u, h+v] X[i-u, j-v],
+ *    and A^T is the matching correlation (the paper does not state its
+ *    boundary condition or PSF centre; this is the reading taken).
+ *  - `stream` is a hipStream_t (NULL = default stream).  All device work is
+ *    enqueued on it.  Entry points that return scalars synchronise it.
+ *  - Every function returns an int status (0 = success / converged, > 0 a
+ *    solver outcome, < 0 an error; see KP_ERR_*), never throws, and leaves
+ *    no HIP error pending on success.
+ *  - A plan is not thread safe: use one plan per host thread / stream.
+ */
+#ifndef KPCG_H
+#define KPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define KP_OK               0   /* success; for solves: converged, the TRUE
+                                   relative residual (FP64) is <= tol      */
+#define KP_MAXIT            1   /* maxit iterations without convergence    */
+#define KP_BREAKDOWN        2   /* p.Hp <= 0, r.z <= 0 or a non-finite
+                                   scalar; x holds the last iterate        */
+#define KP_ERR_ARG         -1   /* null pointer, n < 1, K even, K > 2n-1,
+                                   lambda <= 0, tol <= 0, maxit < 1, a
+                                   non-finite argument, bad mode bits      */
+#define KP_ERR_UNSUPPORTED -2   /* boundary condition other than zero, or
+                                   K above KP_MAX_PSF                      */
+#define KP_ERR_HIP         -3   /* a HIP runtime call failed               */
+#define KP_ERR_SOLVER      -4   /* the FP64 factor SVD (rocSOLVER) failed  */
+#define KP_ERR_WORKSPACE   -5   /* caller workspace smaller than required  */
+
+#define KP_MAX_PSF 63           /* largest supported PSF support K          */
+#define KP_BC_ZERO  0           /* the only boundary condition supported   */
+
+/* ---- mode bits for pcg_solve / pcg_solve_batched --------------------- */
+#define KP_CG        0x000      /* no preconditioner                        */
+#define KP_PCG       0x001      /* PCG, Fletcher-Reeves beta (Section 3)    */
+#define KP_FPCG      0x002      /* flexible PCG, Polak-Ribiere beta
+                                   (Section 3, last paragraph)             */
+#define KP_SOLVER_MASK 0x003
+#define KP_P32       0x000      /* preconditioner factors and products FP32 */
+#define KP_P16       0x010      /* FP16 factors, FP16 MFMA, FP32 accumulate */
+#define KP_P8        0x020      /* FP8 e4m3 with 32-entry block scales      */
+#define KP_PREC_MASK 0x030
+#define KP_WARM      0x100      /* x holds the initial guess on entry       */
+
+typedef struct kp_plan_s *kp_plan_t;   /* opaque */
+
+/* Result of one solve. */
+typedef struct kp_info_s {
+    int32_t iters;          /* H_lambda applications (A, A^T pairs) in the
+                               iteration, as the paper counts iterations   */
+    int32_t status;         /* KP_OK, KP_MAXIT or KP_BREAKDOWN             */
+    int32_t replacements;   /* FP64 true-residual recomputations           */
+    int32_t reserved;
+    double  relres_rec;     /* recurrence ||r|| / ||A^T b|| at exit        */
+    double  relres_true;    /* FP64 ||A^T b - H x|| / ||A^T b|| at exit    */
+    double  lambda;
+    double  rhs_norm;       /* ||A^T b||_2                                 */
+} kp_info_t;
+
+/* Properties of a plan (the Kronecker approximation it holds). */
+typedef struct kp_plan_info_s {
+    int32_t n, k;
+    int32_t kron_terms;     /* numerical rank of the weighted PSF: the
+                               number of Kronecker terms needed to
+                               represent A exactly (Table 1's k)          */
+    int32_t reserved;
+    double  kp_rel_error;   /* ||A - A_r (x) A_c||_F / ||A||_F (Table 1)   */
+    double  sigma_c_max, sigma_c_min, sigma_r_max, sigma_r_min;
+    size_t  device_bytes;   /* device memory held by the plan              */
+} kp_plan_info_t;
+
+/*
+ * kp_workspace_size -- device bytes a plan for an n x n image and a K x K
+ * PSF needs.  `modes` is reserved (pass 0).  Returns 0 for invalid sizes.
+ */
+size_t kp_workspace_size(int n, int k, int modes);
+
+/*
+ * kp_setup -- build the one-term Kronecker approximation and its SVD.
+ *
+ * Section 3, eq. (AKronSVD) and Section 5, eq. (KronSumDecomp): A is
+ * approximated by the Frobenius-optimal Kronecker product A_r (x) A_c
+ * (built from the leading singular triple of the PSF weighted by
+ * sqrt(n - |k - h|) on both sides), and A_r, A_c are factorised by FP64
+ * SVDs on the device.  V_r, V_c are stored in FP32, FP16 and FP8 (with
+ * block scales), U_r, U_c in FP32, singular values in FP64 and FP32.
+ *
+ *   psf        host, K*K float64, row-major
+ *   k, n       PSF support (odd, <= KP_MAX_PSF, <= 2n-1), image size
+ *   bc         KP_BC_ZERO
+ *   workspace  device buffer of >= kp_workspace_size(n, k, 0) bytes that
+ *              the plan uses for all its device data (caller keeps
+ *              ownership and must keep it alive until kp_destroy), or
+ *              NULL to let the plan allocate and own its memory
+ *   ws_bytes   size of `workspace` (ignored if workspace is NULL)
+ *   plan       out: the new plan (NULL on error)
+ * Errors: KP_ERR_ARG, KP_ERR_UNSUPPORTED, KP_ERR_WORKSPACE, KP_ERR_HIP,
+ * KP_ERR_SOLVER.  Synchronises `stream`.
+ */
+int kp_setup(const double *psf, int k, int n, int bc, void *workspace,
+             size_t ws_bytes, void *stream, kp_plan_t *plan);
+
+/* kp_plan_query -- fill `out` with the plan's properties (host only). */
+int kp_plan_query(kp_plan_t plan, kp_plan_info_t *out);
+
+/*
+ * pcg_solve -- solve (A^T A + lambda^2 I) x = A^T b (eq. (tik:normal2)).
+ *
+ * Solver (mode & KP_SOLVER_MASK): CG, PCG with M = A_hat^T A_hat +
+ * lambda^2 I applied as Z = V_c (S .* (V_c^T R V_r)) V_r^T (eq.
+ * (PreconSolve)), or flexible PCG.  The same lambda is used in M and in the
+ * problem (Section 5.3).  Preconditioner precision: mode & KP_PREC_MASK.
+ * Vectors are FP32, matvecs FP32; the scalars alpha, beta, ||r|| are
+ * accumulated in FP64; the true residual c - H x is recomputed with FP64
+ * accumulation whenever the recurrence residual has fallen 100x since the
+ * last recomputation and before convergence is declared, and replaces the
+ * recurrence residual.
+ *
+ *   b       device, n*n float32 data
+ *   lambda  > 0, tol > 0 (relative to ||A^T b||), maxit >= 1
+ *   x       device, n*n float32: initial guess if mode & KP_WARM, else
+ *           ignored (x_0 = 0); on return the last iterate
+ *   info    out (may be NULL)
+ * Returns KP_OK (true relative residual <= tol), KP_MAXIT, KP_BREAKDOWN or
+ * an error.  Synchronises `stream` (it reads back the convergence state).
+ */
+int pcg_solve(kp_plan_t plan, const float *b, double lambda, double tol,
+              int maxit, int mode, float *x, kp_info_t *info, void *stream);
+
+/*
+ * gcv_lambda -- choose lambda on a grid with (weighted) GCV in the KP-SVD
+ * basis (Section 2.2, eqs. (GCVTikSVD) and (wGCVTikSVD), evaluated with the
+ * Kronecker approximation's SVD as in Section 5.1):
+ *   b_hat = U_c^T B U_r,  s_ij = s_c[i] s_r[j],
+ *   G_w(l) = N sum (l^2 b_hat/(s^2+l^2))^2 / (sum ((1-w) s^2 + l^2)/(s^2+l^2))^2
+ * omega = 1 gives GCV.  lambda_out = the grid value with the smallest score
+ * (ties: smallest index).  scores_out: ngrid FP64 scores (host, may be
+ * NULL).  grid: host array of ngrid > 0 positive values.  Synchronises.
+ */
+int gcv_lambda(kp_plan_t plan, const float *b, const double *grid, int ngrid,
+               double omega, double *lambda_out, double *scores_out,
+               void *stream);
+
+/*
+ * discrepancy_lambda -- the discrepancy principle in the KP-SVD basis
+ * (eq. (DSCTikSVD)): D(l) = sum (l^2 b_hat/(s^2+l^2))^2 - (eta*noise)^2.
+ * lambda_out = the largest grid value with D <= 0 (D grows with l), else
+ * grid[0].  values_out: ngrid FP64 values of D (may be NULL).
+ */
+int discrepancy_lambda(kp_plan_t plan, const float *b, const double *grid,
+                       int ngrid, double noise_norm, double eta,
+                       double *lambda_out, double *values_out, void *stream);
+
+/* kp_destroy -- release the plan (and its memory if it allocated it). */
+int kp_destroy(kp_plan_t plan);
+
+/* kp_strerror -- static description of a status code. */
+const char *kp_strerror(int status);
+
+/* ---- operator-level entry points (used by the parity tests) ---------- */
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1); FP32 in and out,
+   FP32 accumulation.  x and y must not alias. */
+int kp_blur(kp_plan_t plan, const float *x, float *y, int transpose,
+            void *stream);
+
+/* y = (A^T A + lambda^2 I) x with FP64 accumulation; y is FP64 (device). */
+int kp_normal_fp64(kp_plan_t plan, const float *x, double lambda, double *y,
+                   void *stream);
+
+/* z = M^{-1} r with the mode's preconditioner precision (mode &
+   KP_PREC_MASK), using the same kernels as the solver.  r, z device FP32,
+   must not alias. */
+int kp_precond(kp_plan_t plan, const float *r, double lambda, int mode,
+               float *z, void *stream);
+
+/* Copy the FP64 singular values s_c, s_r (host arrays of n) and, if not
+   NULL, V_c, V_r as FP64 row-major n x n host arrays (V[i*n + a] = V(i,a)). */
+int kp_get_factors(kp_plan_t plan, double *sc, double *sr, double *vc,
+                   double *vr);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KPCG_H */

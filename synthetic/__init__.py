@@ -1,0 +1,9 @@
+"""Seeded synthetic deblurring problems shared by the oracle tests, the GPU
+tests and the benchmark.  Holds no solver arithmetic."""
+from .problems import (Problem, true_image, psf_gaussian, psf_moffat_motion,
+                       make_problem, small_gaussian, mid_anisotropic, large_moffat,
+                       batch_problem, lambda_grid, random_image, BATCH_SIZES)
+
+__all__ = ["Problem", "true_image", "psf_gaussian", "psf_moffat_motion",
+           "make_problem", "small_gaussian", "mid_anisotropic", "large_moffat",
+           "batch_problem", "lambda_grid", "random_image", "BATCH_SIZES"]

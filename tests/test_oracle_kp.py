@@ -1,0 +1,135 @@
+"""Pins for the Kronecker approximation and the KP-SVD preconditioner."""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import kp as KP
+from oracle import operator as O
+
+
+def _dense_khat(c, a, n):
+    # A_hat = A_r (x) A_c in column-major vec ordering
+    return np.kron(KP.toeplitz_band(a, n), KP.toeplitz_band(c, n))
+
+
+@pytest.mark.parametrize("n,k,seed", [(9, 5, 0), (8, 3, 1), (7, 7, 2), (6, 5, 3)])
+def test_weighted_construction_equals_van_loan_pitsianis(n, k, seed):
+    """The weighted rank-1 PSF construction gives the same A_hat as the
+    brute-force nearest Kronecker product of the dense A (Section 5,
+    eq. (KronSumDecomp), argmin ||A - A_r (x) A_c||_F)."""
+    rng = np.random.default_rng(seed)
+    psf = rng.uniform(0, 1, (k, k))
+    psf /= psf.sum()
+    a_dense = O.dense_matrix(psf, n)
+    b, c = KP.van_loan_pitsianis(a_dense, n)
+    cc, aa, s = KP.kp_profiles(psf, n)
+    khat = _dense_khat(cc, aa, n)
+    assert np.abs(np.kron(b, c) - khat).max() < 1e-13
+    err_dense = np.linalg.norm(a_dense - khat) / np.linalg.norm(a_dense)
+    assert abs(KP.kp_error(s) - err_dense) < 1e-12
+
+
+def test_factor_toeplitz_orientation():
+    """A_hat X = A_c X A_r^T equals the dense A_hat acting on vec(X)."""
+    rng = np.random.default_rng(4)
+    n, k = 7, 5
+    psf = rng.uniform(0, 1, (k, k))
+    kp = KP.kp_svd(psf, n)
+    cc, aa, _ = KP.kp_profiles(psf, n)
+    x = rng.standard_normal((n, n))
+    lhs = O.vec(KP.kp_apply(kp, x))
+    rhs = _dense_khat(cc, aa, n) @ O.vec(x)
+    assert np.allclose(lhs, rhs, atol=1e-13)
+
+
+def test_separable_psf_is_exact():
+    """A rank-one PSF is exactly one Kronecker term (Section 5, Gaussian)."""
+    n = 10
+    g = np.exp(-np.arange(-3, 4) ** 2 / 4.0)
+    f = np.exp(-np.arange(-3, 4) ** 2 / 9.0)
+    psf = np.outer(g, f)
+    psf /= psf.sum()
+    kp = KP.kp_svd(psf, n)
+    assert KP.kp_terms(kp.s_psf) == 1
+    assert KP.kp_error(kp.s_psf) < 1e-14
+    x = np.random.default_rng(0).standard_normal((n, n))
+    assert np.allclose(KP.kp_apply(kp, x), O.blur(psf, x), atol=1e-14)
+
+
+def test_table1_gauss_row_order_of_magnitude():
+    """Table 1 prints ||A - A_hat||_F/||A||_F = 7.9195e-8 for the Gaussian
+    blur, where A is one Kronecker term up to rounding.  A float32-stored
+    Gaussian PSF reproduces that order (<= 1e-7); the other rows need
+    several terms."""
+    fixture = {}
+    with open(_golden("table1_kp_error.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                name, terms, err = line.split()
+                fixture[name] = (int(terms), float(err))
+    gauss_terms, gauss_err = fixture["Gauss"]
+    assert gauss_terms == 1
+    p = S.psf_gaussian(15, 2.0, 2.0, 0.0)
+    kp = KP.kp_svd(p, 128)
+    err = KP.kp_error(kp.s_psf)
+    assert err < 1e-7 and err > 0
+    assert math.floor(math.log10(gauss_err)) >= math.floor(math.log10(err)) - 1
+    # the non-separable workloads are not single Kronecker terms
+    q = S.psf_gaussian(31, 4.0, 2.0, math.radians(30))
+    assert KP.kp_error(KP.kp_svd(q, 64).s_psf) > 0.05
+    for name in ("Defocus", "Speckle", "Shake", "Motion"):
+        assert fixture[name][0] > 1 and fixture[name][1] > 0.1
+
+
+def _golden(name):
+    import os
+    return os.path.join(os.path.dirname(__file__), "golden", name)
+
+
+@pytest.mark.parametrize("n,k,lam", [(6, 3, 0.05), (8, 5, 0.01), (7, 7, 0.3)])
+def test_preconditioner_equals_dense_inverse(n, k, lam):
+    """z = M^{-1} r with M = A_hat^T A_hat + lambda^2 I (eq. (PreconSystem))
+    through eq. (PreconSolve) equals the dense inverse."""
+    rng = np.random.default_rng(n + k)
+    psf = rng.uniform(0, 1, (k, k))
+    psf /= psf.sum()
+    kp = KP.kp_svd(psf, n)
+    cc, aa, _ = KP.kp_profiles(psf, n)
+    khat = _dense_khat(cc, aa, n)
+    m = khat.T @ khat + lam * lam * np.eye(n * n)
+    r = rng.standard_normal((n, n))
+    z_ref = np.linalg.solve(m, O.vec(r))
+    z = O.vec(KP.precond_solve(kp, lam, r))
+    assert np.linalg.norm(z - z_ref) <= 1e-10 * np.linalg.norm(z_ref)
+
+
+def test_preconditioner_sign_and_order_invariance():
+    rng = np.random.default_rng(9)
+    n, k, lam = 12, 5, 0.02
+    psf = S.psf_moffat_motion(k, 3.0, 2.5, 4.0, 0.3)
+    kp = KP.kp_svd(psf, n)
+    r = rng.standard_normal((n, n))
+    z = KP.precond_solve(kp, lam, r)
+    sg = rng.choice([-1.0, 1.0], n)
+    perm = rng.permutation(n)
+    kp.Vc = (kp.Vc * sg)[:, perm]
+    kp.sc = kp.sc[perm]
+    kp.Vr = kp.Vr[:, ::-1] * -1
+    kp.sr = kp.sr[::-1]
+    z2 = KP.precond_solve(kp, lam, r)
+    assert np.allclose(z, z2, atol=1e-11 * np.abs(z).max())
+
+
+def test_preconditioner_inverts_h_when_separable():
+    """M^{-1} H_lambda = I when A is exactly one Kronecker term."""
+    n, lam = 8, 0.03
+    g = np.exp(-np.arange(-2, 3) ** 2 / 3.0)
+    psf = np.outer(g, g[::-1] * np.linspace(1, 2, 5))
+    psf /= psf.sum()
+    kp = KP.kp_svd(psf, n)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((n, n))
+    hx = O.normal_op(psf, lam, x)
+    assert np.allclose(KP.precond_solve(kp, lam, hx), x, atol=1e-10)
