@@ -132,10 +132,11 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t *out);
  * lambda^2 I applied as Z = V_c (S .* (V_c^T R V_r)) V_r^T (eq.
  * (PreconSolve)), or flexible PCG.  The same lambda is used in M and in the
  * problem (Section 5.3).  Preconditioner precision: mode & KP_PREC_MASK.
- * Vectors are FP32, matvecs FP32; the scalars alpha, beta, ||r|| are
- * accumulated in FP64; the true residual c - H x is recomputed with FP64
- * accumulation whenever the recurrence residual has fallen 100x since the
- * last recomputation and before convergence is declared, and replaces the
+ * Vectors are FP32, matvecs FP32; the solution is accumulated in FP64 on
+ * the device and the scalars alpha, beta, ||r|| are accumulated and kept in
+ * FP64; the true residual c - H x is recomputed with FP64 accumulation
+ * whenever the recurrence residual has fallen 1000x since the last
+ * recomputation and before convergence is declared, and replaces the
  * recurrence residual.
  *
  *   b       device, n*n float32 data
@@ -195,6 +196,15 @@ int kp_normal_fp64(kp_plan_t plan, const float *x, double lambda, double *y,
    must not alias. */
 int kp_precond(kp_plan_t plan, const float *r, double lambda, int mode,
                float *z, void *stream);
+
+/* Timing helpers for the benchmark: launch the blur kernel of kp_blur (or
+   the preconditioner chain of kp_precond) `reps` times back to back on
+   `stream`, bracketed by HIP events, and return the mean time per launch
+   (per chain for kp_time_precond) in *avg_ms.  Synchronises. */
+int kp_time_blur(kp_plan_t plan, const float *x, float *y, int transpose,
+                 int reps, float *avg_ms, void *stream);
+int kp_time_precond(kp_plan_t plan, const float *r, double lambda, int mode,
+                    float *z, int reps, float *avg_ms, void *stream);
 
 /* Copy the FP64 singular values s_c, s_r (host arrays of n) and, if not
    NULL, V_c, V_r as FP64 row-major n x n host arrays (V[i*n + a] = V(i,a)). */

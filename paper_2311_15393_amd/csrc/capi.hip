@@ -1,0 +1,550 @@
+// C ABI of libkpcg: plans, the (P)CG driver and the parameter-choice calls.
+//
+// The driver keeps all iteration scalars on the device (see Ctrl in
+// common.h).  It enqueues blocks of iterations whose kernels turn into
+// no-ops once the device marks the solve finished, and synchronises only at
+// block boundaries to read the small control block.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+using namespace kpcg;
+
+struct kp_plan_s {
+  Plan P;
+};
+
+namespace kpcg {
+int build_factors(Plan& P, const double* psf_host, hipStream_t s);
+hipError_t launch_pupdate_from(const Plan& P, const float* z, hipStream_t s);
+}
+
+namespace {
+
+constexpr int TAP_CHUNK = 16;
+constexpr size_t ALIGN = 256;
+
+struct Bump {
+  char* base;
+  size_t cur = 0;
+  template <typename T>
+  T* take(size_t count) {
+    cur = (cur + ALIGN - 1) / ALIGN * ALIGN;
+    T* p = base ? reinterpret_cast<T*>(base + cur) : nullptr;
+    cur += count * sizeof(T);
+    return p;
+  }
+};
+
+size_t layout(int n, int k, char* base, Plan* P) {
+  Bump b{base};
+  const size_t nn = (size_t)n * n;
+  const int kq = (k + TAP_CHUNK - 1) / TAP_CHUNK * TAP_CHUNK;
+  const size_t nsc = (size_t)n * ((n + 31) / 32);
+  Plan tmp;
+  Plan& Q = P ? *P : tmp;
+  Q.taps32 = b.take<float>((size_t)k * kq);
+  Q.taps32_flip = b.take<float>((size_t)k * kq);
+  Q.taps64 = b.take<double>((size_t)k * kq);
+  Q.taps64_flip = b.take<double>((size_t)k * kq);
+  Q.sc = b.take<double>(n);
+  Q.sr = b.take<double>(n);
+  Q.sc2 = b.take<float>(n);
+  Q.sr2 = b.take<float>(n);
+  Q.Vc32 = b.take<float>(nn);
+  Q.VcT32 = b.take<float>(nn);
+  Q.Vr32 = b.take<float>(nn);
+  Q.VrT32 = b.take<float>(nn);
+  Q.Vc16 = b.take<__half>(nn);
+  Q.VcT16 = b.take<__half>(nn);
+  Q.Vr16 = b.take<__half>(nn);
+  Q.VrT16 = b.take<__half>(nn);
+  Q.Vc8 = b.take<uint8_t>(nn);
+  Q.VcT8 = b.take<uint8_t>(nn);
+  Q.Vr8 = b.take<uint8_t>(nn);
+  Q.VrT8 = b.take<uint8_t>(nn);
+  Q.Vc8s = b.take<uint8_t>(nsc);
+  Q.VcT8s = b.take<uint8_t>(nsc);
+  Q.Vr8s = b.take<uint8_t>(nsc);
+  Q.VrT8s = b.take<uint8_t>(nsc);
+  Q.UcT32 = b.take<float>(nn);
+  Q.UrT32 = b.take<float>(nn);
+  Q.r = b.take<float>(nn);
+  Q.p = b.take<float>(nn);
+  Q.q = b.take<float>(nn);
+  Q.w = b.take<float>(nn);
+  Q.z = b.take<float>(nn);
+  Q.c64 = b.take<double>(nn);
+  Q.y64 = b.take<double>(nn);
+  Q.x64 = b.take<double>(nn);
+  Q.t1 = b.take<float>(nn);
+  Q.t2 = b.take<float>(nn);
+  Q.t3 = b.take<float>(nn);
+  Q.t1s = b.take<uint8_t>(nsc);
+  Q.t2s = b.take<uint8_t>(nsc);
+  Q.t3s = b.take<uint8_t>(nsc);
+  Q.rs = b.take<uint8_t>(nsc);
+  Q.r8 = b.take<uint8_t>(nn);
+  Q.spec = b.take<double>((((nn * sizeof(float)) + ALIGN - 1) / ALIGN * ALIGN) / sizeof(double) +
+                          128 + 2 * 64 * 256);
+  Q.ctrl = b.take<Ctrl>(1);
+  Q.partials = b.take<double>((size_t)NSLOTS * MAX_PARTIALS);
+  (void)Q;
+  return (b.cur + ALIGN - 1) / ALIGN * ALIGN;
+}
+
+bool valid_sizes(int n, int k) {
+  return n >= 1 && n <= 2048 && k >= 1 && (k & 1) == 1 && k <= 2 * n - 1;
+}
+
+#define HIP_OR(x, code)                   \
+  do {                                    \
+    if ((x) != hipSuccess) return (code); \
+  } while (0)
+#define HIPCHK(x) HIP_OR(x, KP_ERR_HIP)
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+bool fp8_available() { return launch_precond_fp8(Plan{}, nullptr, nullptr, nullptr, false, 0.f,
+                                                 nullptr) != hipErrorNotSupported; }
+
+int read_ctrl(Plan& P, hipStream_t s, Ctrl& out) {
+  HIPCHK(hipMemcpyAsync(P.host_ctrl, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::memcpy(&out, P.host_ctrl, sizeof(Ctrl));
+  return KP_OK;
+}
+
+int write_ctrl(Plan& P, hipStream_t s, const Ctrl& c) {
+  // the pinned buffer's second half stages host -> device writes
+  Ctrl* stage = P.host_ctrl + 1;
+  HIPCHK(hipStreamSynchronize(s));
+  std::memcpy(stage, &c, sizeof(Ctrl));
+  HIPCHK(hipMemcpyAsync(P.ctrl, stage, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+  return KP_OK;
+}
+
+// one iteration after the matvecs: update, preconditioner, direction
+hipError_t enqueue_tail(Plan& P, int solver, int prec, float lam2, hipStream_t s) {
+  hipError_t e;
+  if (solver == KP_CG) return launch_pupdate_from(P, P.r, s);
+  e = launch_precond(P, P.r, P.z, P.w, prec, true, lam2, s);
+  if (e != hipSuccess) return e;
+  return launch_pupdate_from(P, P.z, s);
+}
+
+hipError_t enqueue_iteration(Plan& P, int solver, int prec, float lam2, hipStream_t s) {
+  hipError_t e;
+  e = launch_blur_f32(P, P.p, P.q, false, s, P.ctrl);           // q = A p
+  if (e != hipSuccess) return e;
+  e = launch_blur_normal(P, P.q, P.p, P.w, lam2, s);            // w = A^T q + l^2 p, alpha
+  if (e != hipSuccess) return e;
+  e = launch_update(P, s);                                      // x, r, ||r||
+  if (e != hipSuccess) return e;
+  return enqueue_tail(P, solver, prec, lam2, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t kp_workspace_size(int n, int k, int modes) {
+  (void)modes;
+  if (!valid_sizes(n, k)) return 0;
+  return layout(n, k, nullptr, nullptr);
+}
+
+int kp_setup(const double* psf, int k, int n, int bc, void* workspace, size_t ws_bytes,
+             void* stream, kp_plan_t* plan) {
+  if (plan == nullptr) return KP_ERR_ARG;
+  *plan = nullptr;
+  if (psf == nullptr || !valid_sizes(n, k)) {
+    if (psf != nullptr && n >= 1 && k >= 1 && (k & 1) && k <= 2 * n - 1 && n > 2048)
+      return KP_ERR_UNSUPPORTED;
+    return KP_ERR_ARG;
+  }
+  if (bc != KP_BC_ZERO) return KP_ERR_UNSUPPORTED;
+  if (k > KP_MAX_PSF) return KP_ERR_UNSUPPORTED;
+  for (int i = 0; i < k * k; ++i)
+    if (!std::isfinite(psf[i])) return KP_ERR_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+  kp_plan_s* h = new (std::nothrow) kp_plan_s();
+  if (!h) return KP_ERR_ARG;
+  Plan& P = h->P;
+  P.n = n;
+  P.k = k;
+  P.kq = (k + TAP_CHUNK - 1) / TAP_CHUNK * TAP_CHUNK;
+  const size_t need = layout(n, k, nullptr, nullptr);
+  char* base = nullptr;
+  if (workspace != nullptr) {
+    if (ws_bytes < need || !aligned16(workspace)) {
+      delete h;
+      return KP_ERR_WORKSPACE;
+    }
+    base = reinterpret_cast<char*>(workspace);
+    P.owns = false;
+  } else {
+    if (hipMalloc(&base, need) != hipSuccess) {
+      delete h;
+      return KP_ERR_HIP;
+    }
+    P.owns = true;
+  }
+  P.base = base;
+  P.bytes = need;
+  layout(n, k, base, &P);
+  if (hipHostMalloc(reinterpret_cast<void**>(&P.host_ctrl), 2 * sizeof(Ctrl)) != hipSuccess) {
+    if (P.owns) hipFree(base);
+    delete h;
+    return KP_ERR_HIP;
+  }
+  std::memset(P.host_ctrl, 0, 2 * sizeof(Ctrl));
+  int rc = KP_OK;
+  if (hipMemsetAsync(P.ctrl, 0, sizeof(Ctrl), s) != hipSuccess) rc = KP_ERR_HIP;
+  if (rc == KP_OK) rc = build_factors(P, psf, s);
+  if (rc != KP_OK) {
+    hipStreamSynchronize(s);
+    hipHostFree(P.host_ctrl);
+    if (P.owns) hipFree(base);
+    delete h;
+    return rc;
+  }
+  *plan = h;
+  return KP_OK;
+}
+
+int kp_plan_query(kp_plan_t plan, kp_plan_info_t* out) {
+  if (!plan || !out) return KP_ERR_ARG;
+  const Plan& P = plan->P;
+  out->n = P.n;
+  out->k = P.k;
+  out->kron_terms = P.terms;
+  out->reserved = 0;
+  out->kp_rel_error = P.kp_err;
+  out->sigma_c_max = P.sc_max;
+  out->sigma_c_min = P.sc_min;
+  out->sigma_r_max = P.sr_max;
+  out->sigma_r_min = P.sr_min;
+  out->device_bytes = P.bytes;
+  return KP_OK;
+}
+
+int kp_destroy(kp_plan_t plan) {
+  if (!plan) return KP_ERR_ARG;
+  Plan& P = plan->P;
+  if (P.host_ctrl) hipHostFree(P.host_ctrl);
+  if (P.owns && P.base) hipFree(P.base);
+  delete plan;
+  return KP_OK;
+}
+
+const char* kp_strerror(int status) {
+  switch (status) {
+    case KP_OK: return "success (solve: true relative residual <= tol)";
+    case KP_MAXIT: return "maximum number of iterations reached";
+    case KP_BREAKDOWN: return "breakdown: non-positive curvature or non-finite scalar";
+    case KP_ERR_ARG: return "invalid argument";
+    case KP_ERR_UNSUPPORTED: return "unsupported configuration";
+    case KP_ERR_HIP: return "HIP runtime error";
+    case KP_ERR_SOLVER: return "FP64 factor SVD failed";
+    case KP_ERR_WORKSPACE: return "workspace too small or misaligned";
+    default: return "unknown status";
+  }
+}
+
+int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int maxit, int mode,
+              float* x, kp_info_t* info, void* stream) {
+  if (!plan || !b || !x) return KP_ERR_ARG;
+  if (!(lambda > 0.0) || !std::isfinite(lambda) || !(tol > 0.0) || !std::isfinite(tol) ||
+      maxit < 1)
+    return KP_ERR_ARG;
+  if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM)) != 0) return KP_ERR_ARG;
+  const int solver = mode & KP_SOLVER_MASK;
+  const int prec = mode & KP_PREC_MASK;
+  if (solver == 3 || prec == KP_PREC_MASK) return KP_ERR_ARG;
+  if (!aligned16(b) || !aligned16(x)) return KP_ERR_ARG;
+  if (solver != KP_CG && prec == KP_P8 && !fp8_available()) return KP_ERR_UNSUPPORTED;
+  Plan& P = plan->P;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t N = (size_t)P.n * P.n;
+  const double lam2d = lambda * lambda;
+  const float lam2 = (float)lam2d;
+
+  Ctrl c;
+  std::memset(&c, 0, sizeof(c));
+  c.tol_rel2 = tol * tol;
+  c.lam2 = lam2d;
+  c.maxit = maxit;
+  c.solver = solver;
+  c.prec = prec;
+  c.first = 1;
+  c.done = RUNNING;
+  c.pscale = 1.0f;
+  c.zscale = (float)(1.0 / lam2d);
+  int rc = write_ctrl(P, s, c);
+  if (rc != KP_OK) return rc;
+  HIPCHK(hipMemsetAsync(P.p, 0, N * sizeof(float), s));
+  HIPCHK(hipMemsetAsync(P.w, 0, N * sizeof(float), s));
+  if (mode & KP_WARM) HIPCHK(launch_convert_x(P, x, false, s));
+  else HIPCHK(hipMemsetAsync(P.x64, 0, N * sizeof(double), s));
+
+  int replacements = 0;
+  HIPCHK(launch_rhs(P, b, s));                                  // c = A^T b, r = c
+  if (mode & KP_WARM) {
+    HIPCHK(launch_true_residual(P, P.x64, lam2d, true, s));     // r = c - H x0
+    ++replacements;
+  }
+  Ctrl hc;
+  if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
+  if (!(hc.gamma0sq > 0.0) || !std::isfinite(hc.gamma0sq)) {
+    const bool zero = hc.gamma0sq == 0.0;
+    HIPCHK(hipMemsetAsync(x, 0, N * sizeof(float), s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->status = zero ? KP_OK : KP_BREAKDOWN;
+      info->lambda = lambda;
+    }
+    return zero ? KP_OK : KP_BREAKDOWN;
+  }
+
+  // first direction: p = z_0 (CG: p = r_0)
+  if (hc.done == RUNNING) HIPCHK(enqueue_tail(P, solver, prec, lam2, s));
+  if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
+
+  int block = 4;
+  while (hc.done == RUNNING || hc.done == PENDING) {
+    if (hc.done == PENDING) {
+      // the recurrence residual met the tolerance or fell 1/REPLACE_DROP:
+      // recompute it in FP64 and continue from the true residual
+      HIPCHK(launch_true_residual(P, P.x64, lam2d, true, s));
+      ++replacements;
+      if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
+      if (hc.done != RUNNING) break;
+      if (hc.iter >= maxit) {
+        hc.done = MAXIT;
+        break;
+      }
+      HIPCHK(enqueue_tail(P, solver, prec, lam2, s));
+    }
+    const int todo = maxit - hc.iter;
+    const int m = block < todo ? block : todo;
+    for (int it = 0; it < m; ++it) HIPCHK(enqueue_iteration(P, solver, prec, lam2, s));
+    if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
+    if (block < 32) block *= 2;
+    if (hc.done == RUNNING && hc.iter >= maxit) hc.done = MAXIT;
+  }
+
+  double true_rr = hc.true_rr;
+  if (hc.done != CONVERGED) {
+    HIPCHK(launch_true_residual(P, P.x64, lam2d, false, s));
+    Ctrl t;
+    if ((rc = read_ctrl(P, s, t)) != KP_OK) return rc;
+    true_rr = t.true_rr;
+  }
+  HIPCHK(launch_convert_x(P, x, true, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int status;
+  if (hc.done == CONVERGED) status = KP_OK;
+  else if (hc.done == BREAKDOWN) status = KP_BREAKDOWN;
+  else status = (true_rr <= hc.tol2) ? KP_OK : KP_MAXIT;
+  if (info) {
+    info->iters = hc.iter;
+    info->status = status;
+    info->replacements = replacements;
+    info->reserved = 0;
+    info->relres_rec = std::sqrt(hc.rr / hc.gamma0sq);
+    info->relres_true = std::sqrt(true_rr / hc.gamma0sq);
+    info->lambda = lambda;
+    info->rhs_norm = std::sqrt(hc.gamma0sq);
+  }
+  return status;
+}
+
+static int spectral_call(kp_plan_t plan, const float* b, const double* grid, int ngrid,
+                         double omega, double noise2, int kind, double* scores_host,
+                         void* stream) {
+  Plan& P = plan->P;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t N = (size_t)P.n * P.n;
+  char* spec = reinterpret_cast<char*>(P.spec);
+  double* grid_dev = reinterpret_cast<double*>(spec + ((N * sizeof(float) + 255) / 256) * 256);
+  double* out_dev = grid_dev + 64;
+  HIPCHK(hipMemcpyAsync(grid_dev, grid, sizeof(double) * ngrid, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_spectrum(P, b, s));
+  HIPCHK(launch_spectral_scores(P, grid_dev, ngrid, omega, noise2, kind, out_dev, s));
+  HIPCHK(hipMemcpyAsync(scores_host, out_dev, sizeof(double) * ngrid, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return KP_OK;
+}
+
+static bool valid_grid(const double* grid, int ngrid) {
+  if (!grid || ngrid < 1 || ngrid > 64) return false;
+  for (int g = 0; g < ngrid; ++g)
+    if (!(grid[g] > 0.0) || !std::isfinite(grid[g])) return false;
+  return true;
+}
+
+int gcv_lambda(kp_plan_t plan, const float* b, const double* grid, int ngrid, double omega,
+               double* lambda_out, double* scores_out, void* stream) {
+  if (!plan || !b || !lambda_out || !valid_grid(grid, ngrid) || !std::isfinite(omega))
+    return KP_ERR_ARG;
+  if (!aligned16(b)) return KP_ERR_ARG;
+  double sc[64];
+  int rc = spectral_call(plan, b, grid, ngrid, omega, 0.0, 0, sc, stream);
+  if (rc != KP_OK) return rc;
+  int best = 0;
+  for (int g = 1; g < ngrid; ++g)
+    if (sc[g] < sc[best]) best = g;
+  *lambda_out = grid[best];
+  if (scores_out) std::memcpy(scores_out, sc, sizeof(double) * ngrid);
+  return KP_OK;
+}
+
+int discrepancy_lambda(kp_plan_t plan, const float* b, const double* grid, int ngrid,
+                       double noise_norm, double eta, double* lambda_out, double* values_out,
+                       void* stream) {
+  if (!plan || !b || !lambda_out || !valid_grid(grid, ngrid) || !(noise_norm >= 0.0) ||
+      !(eta > 0.0) || !std::isfinite(noise_norm * eta))
+    return KP_ERR_ARG;
+  if (!aligned16(b)) return KP_ERR_ARG;
+  double d[64];
+  const double eps = eta * noise_norm;
+  int rc = spectral_call(plan, b, grid, ngrid, 1.0, eps * eps, 1, d, stream);
+  if (rc != KP_OK) return rc;
+  int pick = -1;
+  for (int g = 0; g < ngrid; ++g)
+    if (d[g] <= 0.0) pick = g;
+  *lambda_out = grid[pick < 0 ? 0 : pick];
+  if (values_out) std::memcpy(values_out, d, sizeof(double) * ngrid);
+  return KP_OK;
+}
+
+int kp_blur(kp_plan_t plan, const float* x, float* y, int transpose, void* stream) {
+  if (!plan || !x || !y || x == y) return KP_ERR_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(launch_blur_f32(plan->P, x, y, transpose != 0, s, nullptr));
+  HIPCHK(hipStreamSynchronize(s));
+  return KP_OK;
+}
+
+int kp_normal_fp64(kp_plan_t plan, const float* x, double lambda, double* y, void* stream) {
+  if (!plan || !x || !y || !(lambda >= 0.0) || !std::isfinite(lambda)) return KP_ERR_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(launch_normal_fp64(plan->P, x, lambda * lambda, y, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return KP_OK;
+}
+
+int kp_precond(kp_plan_t plan, const float* r, double lambda, int mode, float* z,
+               void* stream) {
+  if (!plan || !r || !z || r == z || !(lambda > 0.0) || !std::isfinite(lambda))
+    return KP_ERR_ARG;
+  const int prec = mode & KP_PREC_MASK;
+  if (prec == KP_PREC_MASK) return KP_ERR_ARG;
+  if (prec == KP_P8 && !fp8_available()) return KP_ERR_UNSUPPORTED;
+  if (!aligned16(r) || !aligned16(z)) return KP_ERR_ARG;
+  Plan& P = plan->P;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Ctrl c;
+  std::memset(&c, 0, sizeof(c));
+  c.lam2 = lambda * lambda;
+  c.prec = prec;
+  c.done = RUNNING;
+  int rc = write_ctrl(P, s, c);
+  if (rc != KP_OK) return rc;
+  HIPCHK(launch_norm_scale(P, r, s));
+  HIPCHK(launch_precond(P, r, z, nullptr, prec, false, (float)(lambda * lambda), s));
+  HIPCHK(hipStreamSynchronize(s));
+  return KP_OK;
+}
+
+int kp_time_blur(kp_plan_t plan, const float* x, float* y, int transpose, int reps,
+                 float* avg_ms, void* stream) {
+  if (!plan || !x || !y || x == y || reps < 1 || !avg_ms) return KP_ERR_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int rc = KP_OK;
+  if (hipEventRecord(e0, s) != hipSuccess) rc = KP_ERR_HIP;
+  for (int i = 0; i < reps && rc == KP_OK; ++i)
+    if (launch_blur_f32(plan->P, x, y, transpose != 0, s, nullptr) != hipSuccess)
+      rc = KP_ERR_HIP;
+  if (rc == KP_OK && hipEventRecord(e1, s) != hipSuccess) rc = KP_ERR_HIP;
+  if (rc == KP_OK && hipEventSynchronize(e1) != hipSuccess) rc = KP_ERR_HIP;
+  float ms = 0.f;
+  if (rc == KP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = KP_ERR_HIP;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *avg_ms = ms / reps;
+  return rc;
+}
+
+int kp_time_precond(kp_plan_t plan, const float* r, double lambda, int mode, float* z,
+                    int reps, float* avg_ms, void* stream) {
+  if (!plan || !r || !z || r == z || reps < 1 || !avg_ms || !(lambda > 0.0)) return KP_ERR_ARG;
+  const int prec = mode & KP_PREC_MASK;
+  if (prec == KP_PREC_MASK) return KP_ERR_ARG;
+  if (prec == KP_P8 && !fp8_available()) return KP_ERR_UNSUPPORTED;
+  Plan& P = plan->P;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Ctrl c;
+  std::memset(&c, 0, sizeof(c));
+  c.lam2 = lambda * lambda;
+  c.prec = prec;
+  c.done = RUNNING;
+  int rc = write_ctrl(P, s, c);
+  if (rc != KP_OK) return rc;
+  HIPCHK(launch_norm_scale(P, r, s));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  if (hipEventRecord(e0, s) != hipSuccess) rc = KP_ERR_HIP;
+  for (int i = 0; i < reps && rc == KP_OK; ++i)
+    if (launch_precond(P, r, z, nullptr, prec, false, (float)(lambda * lambda), s) != hipSuccess)
+      rc = KP_ERR_HIP;
+  if (rc == KP_OK && hipEventRecord(e1, s) != hipSuccess) rc = KP_ERR_HIP;
+  if (rc == KP_OK && hipEventSynchronize(e1) != hipSuccess) rc = KP_ERR_HIP;
+  float ms = 0.f;
+  if (rc == KP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = KP_ERR_HIP;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *avg_ms = ms / reps;
+  return rc;
+}
+
+int kp_get_factors(kp_plan_t plan, double* sc, double* sr, double* vc, double* vr) {
+  if (!plan || !sc || !sr) return KP_ERR_ARG;
+  Plan& P = plan->P;
+  const int n = P.n;
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(sc, P.sc, sizeof(double) * n, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(sr, P.sr, sizeof(double) * n, hipMemcpyDeviceToHost));
+  if (vc || vr) {
+    const size_t nn = (size_t)n * n;
+    float* tmp = new (std::nothrow) float[nn];
+    if (!tmp) return KP_ERR_ARG;
+    int rc = KP_OK;
+    if (vc) {
+      if (hipMemcpy(tmp, P.Vc32, sizeof(float) * nn, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = KP_ERR_HIP;
+      else
+        for (size_t i = 0; i < nn; ++i) vc[i] = tmp[i];
+    }
+    if (vr && rc == KP_OK) {
+      if (hipMemcpy(tmp, P.Vr32, sizeof(float) * nn, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = KP_ERR_HIP;
+      else
+        for (size_t i = 0; i < nn; ++i) vr[i] = tmp[i];
+    }
+    delete[] tmp;
+    return rc;
+  }
+  return KP_OK;
+}
+
+}  // extern "C"

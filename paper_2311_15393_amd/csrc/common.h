@@ -1,0 +1,233 @@
+// Internal declarations shared by the HIP translation units of libkpcg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "kpcg.h"
+
+namespace kpcg {
+
+// ---------------------------------------------------------------------------
+// Device-resident solver state.  Every kernel of an iteration reads `done`
+// on entry and returns at once if it is set, so the host can enqueue a block
+// of iterations and synchronise only at block boundaries.
+// ---------------------------------------------------------------------------
+enum DoneState : int {
+  RUNNING = 0,
+  CONVERGED = 1,   // set only after the FP64 true residual met the tolerance
+  MAXIT = 2,
+  BREAKDOWN = 3,
+  PENDING = 4,     // the recurrence residual met the tolerance; the host
+                   // must confirm with the true residual
+};
+
+enum Slot : int {
+  SLOT_DELTA = 0,  // p . Hp
+  SLOT_RR = 1,     // ||r||^2
+  SLOT_RZ = 2,     // r . z
+  SLOT_ZW = 3,     // z . Hp (flexible update)
+  SLOT_TRUE = 4,   // true residual ||c - Hx||^2
+  SLOT_RHS = 5,    // ||A^T b||^2
+  SLOT_NORM = 6,   // standalone norms
+  NSLOTS = 8
+};
+
+constexpr int MAX_PARTIALS = 16384;
+
+// The recurrence residual is replaced by the FP64 true residual whenever it
+// has fallen by this factor (in norm) since the last recomputation: beyond
+// that, FP32 matvec rounding (about 1e-6 of ||r|| at the last recomputation)
+// would no longer be small against ||r||.
+constexpr double REPLACE_DROP = 1e-3;
+
+struct Ctrl {
+  double rho;       // r . z (r . r for CG)
+  double rho_prev;
+  double delta;     // p . Hp
+  double alpha, beta;
+  double rr;        // ||r||^2 (recurrence, or the last true residual)
+  double rz, zw;
+  double gamma0sq;  // ||A^T b||^2
+  double tol2;      // tol^2 ||A^T b||^2
+  double tol_rel2;  // tol^2
+  double lam2;      // lambda^2
+  double true_rr;
+  double repl2;     // recompute the true residual once ||r||^2 falls below this
+  float pscale;     // power-of-two scale applied to r before FP16 rounding
+  float zscale;     // 1 / (pscale * lambda^2)
+  int iter, maxit;
+  int done;
+  int solver;       // KP_CG / KP_PCG / KP_FPCG
+  int prec;         // KP_P32 / KP_P16 / KP_P8
+  int first;        // 1 while the initial z is being formed (beta = 0)
+  unsigned cnt[NSLOTS];
+};
+
+// ---------------------------------------------------------------------------
+// reductions: deterministic two-stage sums (per-block FP64 partials, summed
+// in a fixed order by whichever block finishes last)
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the block; the result is valid in thread 0.
+template <int NT>
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) t += sh[w];
+  }
+  return t;
+}
+
+// Publish this block's partial(s) for slots [slot, slot+nv) and return true
+// (in every thread) in the block that arrives last.
+template <int NT, int NV>
+__device__ inline bool publish_partials(const double (&v)[NV], double* partials,
+                                        unsigned* counter, int slot, int nblocks,
+                                        int bid) {
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      __hip_atomic_store(&partials[(slot + k) * MAX_PARTIALS + bid], v[k],
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const unsigned t = atomicAdd(counter, 1u);
+    last = (t == (unsigned)(nblocks - 1));
+  }
+  __syncthreads();
+  return last != 0;
+}
+
+// Fixed-order sum of the published partials of one slot (last block only);
+// valid in thread 0.
+template <int NT>
+__device__ inline double gather_partials(const double* partials, int slot, int nblocks,
+                                         double* sh) {
+  __threadfence();
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += NT)
+    s += __hip_atomic_load(&partials[slot * MAX_PARTIALS + i], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  return block_sum<NT>(s, sh);
+}
+
+// Power of two s with s * sqrt(rr) < 2^14 (keeps every FP16 intermediate of
+// the preconditioner below 65504, since V is orthogonal).
+__device__ inline float fp16_residual_scale(double rr) {
+  if (!(rr > 0.0) || !isfinite(rr)) return 1.0f;
+  int e;
+  frexp(sqrt(rr), &e);
+  int p = 14 - e;
+  p = p > 126 ? 126 : (p < -126 ? -126 : p);
+  return ldexpf(1.0f, p);
+}
+
+__device__ inline void set_scales(Ctrl* c, double rr) {
+  const float s = (c->prec == KP_P16) ? fp16_residual_scale(rr) : 1.0f;
+  c->pscale = s;
+  c->zscale = (float)(1.0 / ((double)s * c->lam2));
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct Plan {
+  int n = 0, k = 0, kq = 0;       // kq: PSF row length padded to the tap chunk
+  bool owns = false;
+  void* base = nullptr;
+  size_t bytes = 0;
+
+  // blur taps (row-major K x kq, zero padded): P for A^T, flipped P for A
+  float* taps32 = nullptr;
+  float* taps32_flip = nullptr;
+  double* taps64 = nullptr;
+  double* taps64_flip = nullptr;
+
+  // KP-SVD factors
+  double* sc = nullptr;          // singular values of A_c (descending)
+  double* sr = nullptr;
+  float* sc2 = nullptr;          // squares in FP32
+  float* sr2 = nullptr;
+  float* Vc32 = nullptr;         // row-major Vc[i][a]
+  float* VcT32 = nullptr;        // row-major Vc^T
+  float* Vr32 = nullptr;
+  float* VrT32 = nullptr;
+  __half* Vc16 = nullptr;
+  __half* VcT16 = nullptr;
+  __half* Vr16 = nullptr;
+  __half* VrT16 = nullptr;
+  uint8_t* Vc8 = nullptr;        // e4m3 codes, row-major, + block exponents
+  uint8_t* VcT8 = nullptr;
+  uint8_t* Vr8 = nullptr;
+  uint8_t* VrT8 = nullptr;
+  uint8_t* Vc8s = nullptr;       // E8M0 exponents, [rows][n/32]
+  uint8_t* VcT8s = nullptr;
+  uint8_t* Vr8s = nullptr;
+  uint8_t* VrT8s = nullptr;
+  float* UcT32 = nullptr;        // row-major Uc^T
+  float* UrT32 = nullptr;        // row-major Ur^T
+
+  // solver vectors
+  float *r = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *z = nullptr;
+  double *c64 = nullptr, *y64 = nullptr;
+  double* x64 = nullptr;         // FP64 solution accumulator
+  // preconditioner intermediates (sized for FP32)
+  void *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
+  uint8_t *t1s = nullptr, *t2s = nullptr, *t3s = nullptr, *rs = nullptr;  // FP8 block exponents
+  uint8_t* r8 = nullptr;                                                 // FP8 residual codes
+  double* spec = nullptr;        // spectral scratch (GCV)
+  Ctrl* ctrl = nullptr;
+  double* partials = nullptr;
+  Ctrl* host_ctrl = nullptr;     // pinned
+
+  // properties
+  double kp_err = 0.0;
+  int terms = 0;
+  double sc_max = 0, sc_min = 0, sr_max = 0, sr_min = 0;
+};
+
+// ---------------------------------------------------------------------------
+// launchers (return hipError_t)
+// ---------------------------------------------------------------------------
+hipError_t launch_blur_f32(const Plan& P, const float* src, float* dst, bool transpose,
+                           hipStream_t s, const Ctrl* ctrl);
+hipError_t launch_blur_normal(const Plan& P, const float* q, const float* p, float* w,
+                              float lam2, hipStream_t s);
+hipError_t launch_rhs(const Plan& P, const float* b, hipStream_t s);
+hipError_t launch_true_residual(const Plan& P, const double* x64, double lam2, bool fin,
+                                hipStream_t s);
+hipError_t launch_normal_fp64(const Plan& P, const float* x, double lam2, double* y,
+                              hipStream_t s);
+
+hipError_t launch_update(const Plan& P, hipStream_t s);
+hipError_t launch_convert_x(const Plan& P, float* x, bool to_f32, hipStream_t s);
+hipError_t launch_pupdate(const Plan& P, hipStream_t s);
+hipError_t launch_norm_scale(const Plan& P, const float* v, hipStream_t s);
+hipError_t launch_init_ctrl(const Plan& P, const Ctrl& host, hipStream_t s);
+
+hipError_t launch_precond(const Plan& P, const float* r, float* z, const float* w,
+                          int prec, bool finalize, float lam2, hipStream_t s);
+hipError_t launch_precond_fp8(const Plan& P, const float* r, float* z, const float* w,
+                              bool finalize, float lam2, hipStream_t s);
+hipError_t launch_spectral_gemms(const Plan& P, const float* b, float* out, hipStream_t s);
+
+hipError_t launch_spectrum(const Plan& P, const float* b, hipStream_t s);
+hipError_t launch_spectral_scores(const Plan& P, const double* grid_dev, int ngrid,
+                                  double omega, double noise2, int kind, double* out_dev,
+                                  hipStream_t s);
+
+}  // namespace kpcg

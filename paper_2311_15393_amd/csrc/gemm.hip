@@ -1,0 +1,316 @@
+// Preconditioner solve z = M^{-1} r on MFMA.
+//
+// Section 3, eq. (PreconSolve): Z = V_c (S .* (V_c^T R V_r)) V_r^T, with
+// vec(S) = diag(D^{-1}), S[i][j] = 1/(s_c[i]^2 s_r[j]^2 + lambda^2), and the
+// factors stored -- and the products computed -- in reduced precision.
+//
+// Four n x n x n GEMMs, each written as C = A * Bt^T with both operands
+// K-contiguous in memory (so every operand feeds the MFMA straight from LDS):
+//   1. T1  = Vc^T  * R      A = VcT (stored), B = R read row-major from the
+//                            FP32 residual, scaled and rounded while staged
+//   2. T   = T1    * Vr     A = T1, Bt = VrT (stored); epilogue T2 = S' .* T,
+//                            written transposed for stage 3
+//   3. T3  = Vc    * T2     A = Vc (stored), Bt = T2^T
+//   4. Z   = T3    * Vr^T   A = T3, Bt = Vr (stored); epilogue z = Z * zscale,
+//                            with the FP64 dots r.z and z.(Hp) of the iteration
+// S' = lambda^2 S lies in (0, 1] (lambda^2 folded out, restored by zscale =
+// 1/(pscale lambda^2)); for FP16 the residual is scaled by a power of two
+// pscale so that ||pscale r|| < 2^14, which keeps every FP16 intermediate
+// below 65504 (V orthogonal).  This replaces the paper's literal "S in
+// half precision", which overflows FP16 for lambda < 3.9e-3.
+//
+// Tiles: 64 x 64 per workgroup, 4 waves in 2 x 2, each wave 32 x 32 as 2 x 2
+// MFMA 16x16 blocks; FP32 uses v_mfma_f32_16x16x4_f32, FP16
+// v_mfma_f32_16x16x32_f16, both accumulating in FP32.
+#include "common.h"
+
+namespace kpcg {
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MT;
+template <> struct MT<float> {
+  static constexpr int BK = 16;     // k per LDS stage
+  static constexpr int VEC = 4;     // elements per 16-byte load
+  static constexpr int PAD = 4;
+};
+template <> struct MT<_Float16> {
+  static constexpr int BK = 32;
+  static constexpr int VEC = 8;
+  static constexpr int PAD = 8;
+};
+
+constexpr int GT = 256;  // threads per GEMM workgroup
+constexpr int BM = 64, BN = 64;
+
+// ---------------------------------------------------------------------------
+// operand staging into LDS (s[row][k], k contiguous)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void stage_kcontig(T (*s)[MT<T>::BK + MT<T>::PAD], const T* __restrict__ g,
+                                     int row0, int k0, int n) {
+  constexpr int BK = MT<T>::BK, VEC = MT<T>::VEC;
+  const int row = threadIdx.x / (BK / VEC);
+  const int kc = (threadIdx.x % (BK / VEC)) * VEC;
+  const int gr = row0 + row, gk = k0 + kc;
+  T* dst = &s[row][kc];
+  if (gr < n && gk + VEC <= n) {
+    const float4 v = *reinterpret_cast<const float4*>(g + (size_t)gr * n + gk);
+    *reinterpret_cast<float4*>(dst) = v;
+  } else {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+      dst[e] = (gr < n && gk + e < n) ? g[(size_t)gr * n + gk + e] : T(0);
+  }
+}
+
+// B tile from a row-major FP32 matrix src[k][j] (contraction over its rows),
+// multiplied by `scale` and rounded to T while being transposed into s[j][k].
+template <typename T>
+__device__ inline void stage_from_f32_rows(T (*s)[MT<T>::BK + MT<T>::PAD],
+                                           const float* __restrict__ src, int k0, int j0,
+                                           int n, float scale) {
+  constexpr int BK = MT<T>::BK;
+  constexpr int PER = BK * BN / GT;          // floats per thread (4 or 8)
+  constexpr int TPR = BN / PER;              // threads per k row
+  const int k = threadIdx.x / TPR;
+  const int jc = (threadIdx.x % TPR) * PER;
+  const int gk = k0 + k;
+#pragma unroll
+  for (int e4 = 0; e4 < PER; e4 += 4) {
+    const int gj = j0 + jc + e4;
+    float4 v;
+    if (gk < n && gj + 4 <= n) {
+      v = *reinterpret_cast<const float4*>(src + (size_t)gk * n + gj);
+    } else {
+      v.x = (gk < n && gj + 0 < n) ? src[(size_t)gk * n + gj + 0] : 0.f;
+      v.y = (gk < n && gj + 1 < n) ? src[(size_t)gk * n + gj + 1] : 0.f;
+      v.z = (gk < n && gj + 2 < n) ? src[(size_t)gk * n + gj + 2] : 0.f;
+      v.w = (gk < n && gj + 3 < n) ? src[(size_t)gk * n + gj + 3] : 0.f;
+    }
+    s[jc + e4 + 0][k] = (T)(v.x * scale);
+    s[jc + e4 + 1][k] = (T)(v.y * scale);
+    s[jc + e4 + 2][k] = (T)(v.z * scale);
+    s[jc + e4 + 3][k] = (T)(v.w * scale);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MFMA step over one LDS stage
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void mma_stage(const T (*sA)[MT<T>::BK + MT<T>::PAD],
+                                 const T (*sB)[MT<T>::BK + MT<T>::PAD], float4_t (&acc)[2][2],
+                                 int wm, int wn, int lane) {
+  const int r16 = lane & 15, g = lane >> 4;
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int kk = 0; kk < MT<T>::BK; kk += 4) {
+      float a[2], b[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) a[mi] = sA[wm * 32 + mi * 16 + r16][kk + g];
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) b[ni] = sB[wn * 32 + ni * 16 + r16][kk + g];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
+  } else {
+    half8_t a[2], b[2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+      a[mi] = *reinterpret_cast<const half8_t*>(&sA[wm * 32 + mi * 16 + r16][g * 8]);
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+      b[ni] = *reinterpret_cast<const half8_t*>(&sB[wn * 32 + ni * 16 + r16][g * 8]);
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// epilogues: lane holds C[i0 + 4*(lane>>4) + v][j0 + (lane&15)], v = 0..3
+// ---------------------------------------------------------------------------
+template <typename T>
+struct GEpiStore {                       // row-major store
+  T* C; int n;
+  static constexpr bool kReduce = false;
+  __device__ void apply(int i, int j, float v, double&, double&) const {
+    C[(size_t)i * n + j] = (T)v;
+  }
+};
+
+template <typename T>
+struct GEpiSPrimeT {                     // T2^T[j][i] = S'[i][j] * T[i][j]
+  T* C; const float* sc2; const float* sr2; float lam2; int n;
+  static constexpr bool kReduce = false;
+  __device__ void apply(int i, int j, float v, double&, double&) const {
+    const float sp = lam2 / fmaf(sc2[i], sr2[j], lam2);
+    C[(size_t)j * n + i] = (T)(sp * v);
+  }
+};
+
+template <bool REDUCE>
+struct GEpiFinal {                       // z (already scaled) ; r.z ; z.w
+  float* z; const float* r; const float* w; int n;
+  static constexpr bool kReduce = REDUCE;
+  __device__ void apply(int i, int j, float v, double& d0, double& d1) const {
+    const size_t o = (size_t)i * n + j;
+    const float zv = v;
+    z[o] = zv;
+    if constexpr (REDUCE) {
+      d0 += (double)r[o] * zv;
+      d1 += (double)zv * w[o];
+    }
+  }
+};
+
+__device__ inline void fin_rz(Ctrl* c, double rz, double zw) {
+  c->rz = rz;
+  c->zw = zw;
+  if (!(rz > 0.0) || !isfinite(rz) || !isfinite(zw)) {
+    c->done = BREAKDOWN;
+    return;
+  }
+  if (c->first) {
+    c->beta = 0.0;
+    c->first = 0;
+  } else if (c->solver == KP_PCG) {
+    c->beta = rz / c->rho;               // Fletcher-Reeves
+  } else {
+    c->beta = -zw / c->delta;            // Polak-Ribiere = -alpha (z.Hp) / rho
+  }
+  c->rho = rz;
+}
+
+// ---------------------------------------------------------------------------
+// the GEMM kernel: C[n x n] = A[n x n] * Bt^T (or * B from FP32 rows)
+// ---------------------------------------------------------------------------
+template <typename T, bool B_FROM_F32, class Epi>
+__global__ __launch_bounds__(GT) void gemm_kernel(const T* __restrict__ A,
+                                                  const void* __restrict__ Bsrc, int n,
+                                                  Epi epi, Ctrl* ctrl, int skip_if_done,
+                                                  int scale_mode, double* partials) {
+  if (skip_if_done && ctrl->done != RUNNING) return;
+  constexpr int BK = MT<T>::BK, LD = BK + MT<T>::PAD;
+  __shared__ __align__(16) T sA[BM][LD];
+  __shared__ __align__(16) T sB[BN][LD];
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  // scale_mode bit 0: scale the FP32 B source by pscale; bit 1: scale the
+  // output by zscale (both set on the device from ||r||)
+  const float bscale = (scale_mode & 1) ? ctrl->pscale : 1.0f;
+  const float oscale = (scale_mode & 2) ? ctrl->zscale : 1.0f;
+
+  float4_t acc[2][2];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = 0; k0 < n; k0 += BK) {
+    stage_kcontig<T>(sA, A, m0, k0, n);
+    if constexpr (B_FROM_F32)
+      stage_from_f32_rows<T>(sB, reinterpret_cast<const float*>(Bsrc), k0, n0, n, bscale);
+    else
+      stage_kcontig<T>(sB, reinterpret_cast<const T*>(Bsrc), n0, k0, n);
+    __syncthreads();
+    mma_stage<T>(sA, sB, acc, wm, wn, lane);
+    __syncthreads();
+  }
+
+  double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) {
+      const int j = n0 + wn * 32 + ni * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = m0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + v;
+        if (i < n && j < n) epi.apply(i, j, acc[mi][ni][v] * oscale, d0, d1);
+      }
+    }
+  if constexpr (Epi::kReduce) {
+    __shared__ double sh[GT / 64];
+    const double s0 = block_sum<GT>(d0, sh);
+    const double s1 = block_sum<GT>(d1, sh);
+    const int nb = gridDim.x * gridDim.y;
+    const double v2[2] = {s0, s1};
+    if (publish_partials<GT, 2>(v2, partials, &ctrl->cnt[SLOT_RZ], SLOT_RZ, nb,
+                                blockIdx.y * gridDim.x + blockIdx.x)) {
+      const double rz = gather_partials<GT>(partials, SLOT_RZ, nb, sh);
+      const double zw = gather_partials<GT>(partials, SLOT_ZW, nb, sh);
+      if (threadIdx.x == 0) {
+        fin_rz(ctrl, rz, zw);
+        __hip_atomic_store(&ctrl->cnt[SLOT_RZ], 0u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+}
+
+template <typename T, bool BF, class Epi>
+static hipError_t run_gemm(const Plan& P, const T* A, const void* B, Epi epi, int skip,
+                           int scale_mode, hipStream_t s) {
+  const int n = P.n;
+  dim3 grid((n + BN - 1) / BN, (n + BM - 1) / BM);
+  if ((long)grid.x * grid.y > MAX_PARTIALS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gemm_kernel<T, BF, Epi>), grid, dim3(GT), 0, s, A, B, n, epi, P.ctrl,
+                     skip, scale_mode, P.partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t precond_chain(const Plan& P, const T* VcT, const T* Vc, const T* Vr,
+                                const T* VrT, const float* r, float* z, const float* w,
+                                bool finalize, float lam2, hipStream_t s) {
+  const int n = P.n;
+  const int skip = finalize ? 1 : 0;
+  T* t1 = reinterpret_cast<T*>(P.t1);
+  T* t2 = reinterpret_cast<T*>(P.t2);
+  T* t3 = reinterpret_cast<T*>(P.t3);
+  hipError_t e;
+  e = run_gemm<T, true>(P, VcT, r, GEpiStore<T>{t1, n}, skip, 1, s);
+  if (e != hipSuccess) return e;
+  e = run_gemm<T, false>(P, t1, VrT, GEpiSPrimeT<T>{t2, P.sc2, P.sr2, lam2, n}, skip, 0, s);
+  if (e != hipSuccess) return e;
+  e = run_gemm<T, false>(P, Vc, t2, GEpiStore<T>{t3, n}, skip, 0, s);
+  if (e != hipSuccess) return e;
+  return finalize ? run_gemm<T, false>(P, t3, Vr, GEpiFinal<true>{z, r, w, n}, skip, 2, s)
+                  : run_gemm<T, false>(P, t3, Vr, GEpiFinal<false>{z, r, w, n}, skip, 2, s);
+}
+
+hipError_t launch_precond(const Plan& P, const float* r, float* z, const float* w, int prec,
+                          bool finalize, float lam2, hipStream_t s) {
+  if (prec == KP_P16)
+    return precond_chain<_Float16>(P, reinterpret_cast<const _Float16*>(P.VcT16),
+                                   reinterpret_cast<const _Float16*>(P.Vc16),
+                                   reinterpret_cast<const _Float16*>(P.Vr16),
+                                   reinterpret_cast<const _Float16*>(P.VrT16), r, z, w,
+                                   finalize, lam2, s);
+  if (prec == KP_P32)
+    return precond_chain<float>(P, P.VcT32, P.Vc32, P.Vr32, P.VrT32, r, z, w, finalize, lam2,
+                                s);
+  return launch_precond_fp8(P, r, z, w, finalize, lam2, s);
+}
+
+// plain FP32 GEMM C = A * B (B from FP32 rows) then C2 = C * Bt^T, used for the
+// spectral coefficients b_hat = Uc^T B Ur of the parameter-choice rules
+hipError_t launch_spectral_gemms(const Plan& P, const float* b, float* out, hipStream_t s) {
+  const int n = P.n;
+  float* t1 = reinterpret_cast<float*>(P.t1);
+  hipError_t e = run_gemm<float, true>(P, P.UcT32, b, GEpiStore<float>{t1, n}, 0, 0, s);
+  if (e != hipSuccess) return e;
+  return run_gemm<float, false>(P, t1, P.UrT32, GEpiStore<float>{out, n}, 0, 0, s);
+}
+
+}  // namespace kpcg

@@ -1,0 +1,281 @@
+// Construction of the Kronecker approximation and its SVD on the device.
+//
+// Section 3, eq. (AKronSVD) and Section 5, eq. (KronSumDecomp).  The
+// paper builds the Frobenius-optimal term A_r (x) A_c with IR Tools without
+// stating the construction.  Reading used: A = sum_{u,v} P[u][v] Z_v (x) Z_u
+// over shift matrices with disjoint supports and ||Z_d||_F^2 = n - |d|, so
+//   ||A - T(a) (x) T(c)||_F^2 = sum w_u w_v (P[u][v] - c_u a_v)^2,
+//   w_k = n - |k - h|,
+// minimised by the leading singular triple (s1, u1, v1) of
+// W^{1/2} P W^{1/2}: c = sqrt(s1) u1 / sqrt(w), a = sqrt(s1) v1 / sqrt(w).
+// A_c = T(c) (acts on the row index), A_r = T(a), T(f)[i][i'] = f[h+i-i'].
+// Both factors get FP64 SVDs (rocSOLVER gesvd; the paper also computes them
+// in double), after which V_c, V_r are stored in FP32 / FP16 / FP8 with
+// block exponents, U_c, U_r in FP32 and the singular values in FP64.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace kpcg {
+
+// Weighted PSF, column-major K x K for the solver.
+__global__ void weighted_psf_kernel(const double* __restrict__ psf, int K, int n,
+                                    double* __restrict__ pw) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= K * K) return;
+  const int k = idx / K, l = idx - k * K;          // psf[k][l] row-major
+  const int h = (K - 1) / 2;
+  const double wk = (double)(n - abs(k - h)), wl = (double)(n - abs(l - h));
+  pw[k + (size_t)l * K] = sqrt(wk * wl) * psf[idx];
+}
+
+// Profiles c (column factor) and a (row factor) from the leading singular
+// triple; sign fixed so that sum(c) > 0.  One block.
+__global__ void profiles_kernel(const double* __restrict__ S, const double* __restrict__ U,
+                                const double* __restrict__ Vt, int K, int n,
+                                double* __restrict__ c, double* __restrict__ a) {
+  __shared__ double red[64];
+  const int h = (K - 1) / 2;
+  const double s1 = sqrt(S[0]);
+  double part = 0.0;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) part += U[k];
+  red[threadIdx.x] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) t += red[i];
+    red[0] = t;
+  }
+  __syncthreads();
+  const double sg = red[0] < 0.0 ? -1.0 : 1.0;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double w = sqrt((double)(n - abs(k - h)));
+    c[k] = sg * s1 * U[k] / w;                      // U(k, 0)
+    a[k] = sg * s1 * Vt[(size_t)k * K] / w;         // Vt(0, k)
+  }
+}
+
+// Column-major banded Toeplitz T(f)[i][i'] = f[h + i - i'].
+__global__ void toeplitz_kernel(const double* __restrict__ f, int K, int n,
+                                double* __restrict__ t) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * n) return;
+  const int i = (int)(idx % n), ip = (int)(idx / n);   // t[i + ip*n]
+  const int h = (K - 1) / 2, d = i - ip;
+  t[idx] = (d >= -h && d <= h) ? f[h + d] : 0.0;
+}
+
+// From the column-major gesvd outputs: Vt (n x n, Vt(a,i) = V(i,a)) and U.
+//   Vrm[i*n+a]  = V(i,a)   = Vt[a + i*n]   (same memory order)
+//   VTrm[a*n+i] = V(i,a)                   (transpose)
+//   UTrm[a*n+i] = U(i,a)   = U[i + a*n]    (same memory order)
+__global__ void factors_kernel(const double* __restrict__ Vt, const double* __restrict__ U,
+                               int n, float* __restrict__ V32, float* __restrict__ VT32,
+                               _Float16* __restrict__ V16, _Float16* __restrict__ VT16,
+                               float* __restrict__ UT32) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * n) return;
+  const int a = (int)(idx % n), i = (int)(idx / n);
+  const double v = Vt[idx];                 // V(i, a) at row-major [i][a]
+  V32[idx] = (float)v;
+  V16[idx] = (_Float16)v;
+  VT32[(size_t)a * n + i] = (float)v;
+  VT16[(size_t)a * n + i] = (_Float16)v;
+  UT32[idx] = (float)U[idx];
+}
+
+__global__ void sigma_kernel(const double* __restrict__ s, int n, float* __restrict__ s2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) s2[i] = (float)(s[i] * s[i]);
+}
+
+// Taps for the direct blur: row-major K x KQ, zero padded; flip = 180 deg.
+__global__ void taps_kernel(const double* __restrict__ psf, int K, int KQ,
+                            float* __restrict__ t32, float* __restrict__ t32f,
+                            double* __restrict__ t64, double* __restrict__ t64f) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= K * KQ) return;
+  const int a = idx / KQ, b = idx - a * KQ;
+  double v = 0.0, vf = 0.0;
+  if (b < K) {
+    v = psf[a * K + b];
+    vf = psf[(K - 1 - a) * K + (K - 1 - b)];
+  }
+  t32[idx] = (float)v;
+  t32f[idx] = (float)vf;
+  t64[idx] = v;
+  t64f[idx] = vf;
+}
+
+// ---------------------------------------------------------------------------
+// FP8 e4m3 copies of the factors with one power-of-two exponent per 32
+// consecutive entries along the contraction dimension of each GEMM that
+// consumes them (every stored factor is K-contiguous, so: per row, per 32
+// columns).
+// ---------------------------------------------------------------------------
+__device__ inline int e8m0_for_amax(float amax) {
+  // smallest e with amax * 2^-e <= 448 ; returned biased by 127
+  if (!(amax > 0.0f)) return 0;            // 2^-127: any exponent works for a zero block
+  int e;
+  const float m = frexpf(amax / 448.0f, &e);   // amax/448 = m 2^e, m in [0.5,1)
+  if (m == 0.5f) e -= 1;
+  e += 127;
+  return e < 1 ? 1 : (e > 254 ? 254 : e);
+}
+
+__device__ inline uint8_t to_e4m3(float v) {
+  // RNE with saturation to +-448 (the value is already scaled into range)
+  const int packed = __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false);
+  return (uint8_t)(packed & 0xff);
+}
+
+__global__ void quant_rows_e4m3_kernel(const float* __restrict__ src, int n,
+                                       uint8_t* __restrict__ codes,
+                                       uint8_t* __restrict__ exps) {
+  // one thread per (row, 32-block)
+  const int nb = (n + 31) / 32;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * nb) return;
+  const int row = idx / nb, blk = idx - row * nb;
+  const int j0 = blk * 32, j1 = min(n, j0 + 32);
+  float amax = 0.0f;
+  for (int j = j0; j < j1; ++j) amax = fmaxf(amax, fabsf(src[(size_t)row * n + j]));
+  const int eb = e8m0_for_amax(amax);
+  exps[idx] = (uint8_t)eb;
+  const float inv = ldexpf(1.0f, 127 - eb);
+  for (int j = j0; j < j1; ++j)
+    codes[(size_t)row * n + j] = to_e4m3(src[(size_t)row * n + j] * inv);
+}
+
+#define SCHK(x)                                                     \
+  do {                                                              \
+    rocblas_status st_ = (x);                                       \
+    if (st_ != rocblas_status_success) { rc = KP_ERR_SOLVER; goto done; } \
+  } while (0)
+#define HCHK(x)                                                     \
+  do {                                                              \
+    if ((x) != hipSuccess) { rc = KP_ERR_HIP; goto done; }           \
+  } while (0)
+
+int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
+  const int n = P.n, K = P.k;
+  const size_t nn = (size_t)n * n;
+  int rc = KP_OK;
+  rocblas_handle handle = nullptr;
+  double *dpsf = nullptr, *pw = nullptr, *spsf = nullptr, *upsf = nullptr, *vpsf = nullptr,
+         *e = nullptr, *prof = nullptr, *T = nullptr, *U = nullptr, *Vt = nullptr;
+  rocblas_int* info = nullptr;
+  std::vector<double> hs(K);
+  rocblas_int hinfo = 0;
+  const int nthr = 256;
+  const unsigned gnn = (unsigned)((nn + nthr - 1) / nthr);
+
+  HCHK(hipMalloc(&dpsf, sizeof(double) * K * K));
+  HCHK(hipMalloc(&pw, sizeof(double) * K * K));
+  HCHK(hipMalloc(&spsf, sizeof(double) * K));
+  HCHK(hipMalloc(&upsf, sizeof(double) * K * K));
+  HCHK(hipMalloc(&vpsf, sizeof(double) * K * K));
+  HCHK(hipMalloc(&e, sizeof(double) * (n > K ? n : K)));
+  HCHK(hipMalloc(&prof, sizeof(double) * 2 * K));
+  HCHK(hipMalloc(&T, sizeof(double) * nn));
+  HCHK(hipMalloc(&U, sizeof(double) * nn));
+  HCHK(hipMalloc(&Vt, sizeof(double) * nn));
+  HCHK(hipMalloc(&info, sizeof(rocblas_int)));
+  HCHK(hipMemcpyAsync(dpsf, psf_host, sizeof(double) * K * K, hipMemcpyHostToDevice, s));
+
+  SCHK(rocblas_create_handle(&handle));
+  SCHK(rocblas_set_stream(handle, s));
+
+  // blur taps
+  hipLaunchKernelGGL(taps_kernel, dim3((K * P.kq + 255) / 256), dim3(256), 0, s, dpsf, K, P.kq,
+                     P.taps32, P.taps32_flip, P.taps64, P.taps64_flip);
+  HCHK(hipGetLastError());
+
+  // weighted PSF SVD
+  hipLaunchKernelGGL(weighted_psf_kernel, dim3((K * K + 255) / 256), dim3(256), 0, s, dpsf, K,
+                     n, pw);
+  HCHK(hipGetLastError());
+  SCHK(rocsolver_dgesvd(handle, rocblas_svect_all, rocblas_svect_all, K, K, pw, K, spsf, upsf,
+                        K, vpsf, K, e, rocblas_outofplace, info));
+  HCHK(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+  HCHK(hipMemcpyAsync(hs.data(), spsf, sizeof(double) * K, hipMemcpyDeviceToHost, s));
+  HCHK(hipStreamSynchronize(s));
+  if (hinfo != 0) { rc = KP_ERR_SOLVER; goto done; }
+  hipLaunchKernelGGL(profiles_kernel, dim3(1), dim3(64), 0, s, spsf, upsf, vpsf, K, n, prof,
+                     prof + K);
+  HCHK(hipGetLastError());
+
+  {
+    double tot = 0.0, rest = 0.0;
+    for (int i = 0; i < K; ++i) tot += hs[i] * hs[i];
+    for (int i = 1; i < K; ++i) rest += hs[i] * hs[i];
+    P.kp_err = tot > 0 ? std::sqrt(rest / tot) : 0.0;
+    int t = 0;
+    for (int i = 0; i < K; ++i)
+      if (hs[i] > 1e-12 * hs[0]) ++t;
+    P.terms = t;
+  }
+
+  // the two factors: c -> A_c (column factor), a -> A_r (row factor)
+  for (int f = 0; f < 2; ++f) {
+    const double* prof_f = prof + f * K;
+    double* sig = f == 0 ? P.sc : P.sr;
+    hipLaunchKernelGGL(toeplitz_kernel, dim3(gnn), dim3(nthr), 0, s, prof_f, K, n, T);
+    HCHK(hipGetLastError());
+    SCHK(rocsolver_dgesvd(handle, rocblas_svect_all, rocblas_svect_all, n, n, T, n, sig, U, n,
+                          Vt, n, e, rocblas_outofplace, info));
+    HCHK(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+    HCHK(hipStreamSynchronize(s));
+    if (hinfo != 0) { rc = KP_ERR_SOLVER; goto done; }
+    if (f == 0) {
+      hipLaunchKernelGGL(factors_kernel, dim3(gnn), dim3(nthr), 0, s, Vt, U, n, P.Vc32, P.VcT32,
+                         reinterpret_cast<_Float16*>(P.Vc16),
+                         reinterpret_cast<_Float16*>(P.VcT16), P.UcT32);
+      hipLaunchKernelGGL(sigma_kernel, dim3((n + 255) / 256), dim3(256), 0, s, P.sc, n, P.sc2);
+    } else {
+      hipLaunchKernelGGL(factors_kernel, dim3(gnn), dim3(nthr), 0, s, Vt, U, n, P.Vr32, P.VrT32,
+                         reinterpret_cast<_Float16*>(P.Vr16),
+                         reinterpret_cast<_Float16*>(P.VrT16), P.UrT32);
+      hipLaunchKernelGGL(sigma_kernel, dim3((n + 255) / 256), dim3(256), 0, s, P.sr, n, P.sr2);
+    }
+    HCHK(hipGetLastError());
+  }
+
+  // FP8 copies with 32-entry block exponents along each row
+  {
+    const int nb = (n + 31) / 32;
+    const unsigned g8 = (unsigned)((n * nb + 255) / 256);
+    hipLaunchKernelGGL(quant_rows_e4m3_kernel, dim3(g8), dim3(256), 0, s, P.Vc32, n, P.Vc8,
+                       P.Vc8s);
+    hipLaunchKernelGGL(quant_rows_e4m3_kernel, dim3(g8), dim3(256), 0, s, P.VcT32, n, P.VcT8,
+                       P.VcT8s);
+    hipLaunchKernelGGL(quant_rows_e4m3_kernel, dim3(g8), dim3(256), 0, s, P.Vr32, n, P.Vr8,
+                       P.Vr8s);
+    hipLaunchKernelGGL(quant_rows_e4m3_kernel, dim3(g8), dim3(256), 0, s, P.VrT32, n, P.VrT8,
+                       P.VrT8s);
+    HCHK(hipGetLastError());
+  }
+
+  {
+    double v[4];
+    HCHK(hipMemcpyAsync(&v[0], P.sc, sizeof(double), hipMemcpyDeviceToHost, s));
+    HCHK(hipMemcpyAsync(&v[1], P.sc + n - 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    HCHK(hipMemcpyAsync(&v[2], P.sr, sizeof(double), hipMemcpyDeviceToHost, s));
+    HCHK(hipMemcpyAsync(&v[3], P.sr + n - 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    HCHK(hipStreamSynchronize(s));
+    P.sc_max = v[0]; P.sc_min = v[1]; P.sr_max = v[2]; P.sr_min = v[3];
+  }
+
+done:
+  hipStreamSynchronize(s);
+  if (handle) rocblas_destroy_handle(handle);
+  hipFree(dpsf); hipFree(pw); hipFree(spsf); hipFree(upsf); hipFree(vpsf); hipFree(e);
+  hipFree(prof); hipFree(T); hipFree(U); hipFree(Vt); hipFree(info);
+  return rc;
+}
+
+}  // namespace kpcg

@@ -1,0 +1,167 @@
+// Fused vector kernels of the (P)CG iteration.
+//
+// The paper keeps everything outside the preconditioner solve in double
+// precision (Section 1, mixed-precision paragraph).  Here the vectors are
+// FP32 in HBM and every scalar that steers the iteration (||r||^2, alpha,
+// beta, the convergence test) is accumulated and kept in FP64 on the device.
+// These kernels are HBM-bound: 16-byte accesses, grid-stride loops with a
+// fixed grid so the FP64 reductions are deterministic.
+#include "common.h"
+
+namespace kpcg {
+
+constexpr int VT = 256;          // threads per block
+constexpr int VMAXB = 1024;      // blocks per vector kernel
+
+static inline int vec_blocks(int n4) {
+  int b = (n4 + VT - 1) / VT;
+  return b < 1 ? 1 : (b > VMAXB ? VMAXB : b);
+}
+
+__device__ inline void fin_update(Ctrl* c, double S) {
+  c->rr = S;
+  c->iter += 1;
+  if (c->solver == KP_CG) {
+    c->rho_prev = c->rho;
+    c->beta = S / c->rho;
+    c->rho = S;
+  }
+  set_scales(c, S);
+  if (!isfinite(S)) c->done = BREAKDOWN;
+  else if (S <= c->tol2 || S <= c->repl2) c->done = PENDING;
+  else if (c->iter >= c->maxit) c->done = MAXIT;
+}
+
+// x += alpha p (FP64 accumulator) ; r -= alpha w ; ||r||^2
+__global__ __launch_bounds__(VT) void update_kernel(double* __restrict__ x,
+                                                    float* __restrict__ r,
+                                                    const float* __restrict__ p,
+                                                    const float* __restrict__ w, int N,
+                                                    Ctrl* ctrl, double* partials) {
+  if (ctrl->done != RUNNING) return;
+  const double ad = ctrl->alpha;
+  const float a = (float)ad;
+  const int n4 = N >> 2;
+  double d = 0.0;
+  double2* x2 = reinterpret_cast<double2*>(x);
+  float4* r4 = reinterpret_cast<float4*>(r);
+  const float4* p4 = reinterpret_cast<const float4*>(p);
+  const float4* w4 = reinterpret_cast<const float4*>(w);
+  for (int i = blockIdx.x * VT + threadIdx.x; i < n4; i += gridDim.x * VT) {
+    double2 xa = x2[2 * i], xb = x2[2 * i + 1];
+    float4 rv = r4[i];
+    const float4 pv = p4[i], wv = w4[i];
+    xa.x = fma(ad, (double)pv.x, xa.x); xa.y = fma(ad, (double)pv.y, xa.y);
+    xb.x = fma(ad, (double)pv.z, xb.x); xb.y = fma(ad, (double)pv.w, xb.y);
+    rv.x = fmaf(-a, wv.x, rv.x); rv.y = fmaf(-a, wv.y, rv.y);
+    rv.z = fmaf(-a, wv.z, rv.z); rv.w = fmaf(-a, wv.w, rv.w);
+    x2[2 * i] = xa;
+    x2[2 * i + 1] = xb;
+    r4[i] = rv;
+    d += (double)rv.x * rv.x + (double)rv.y * rv.y + (double)rv.z * rv.z +
+         (double)rv.w * rv.w;
+  }
+  if (blockIdx.x == 0) {
+    for (int i = 4 * n4 + threadIdx.x; i < N; i += VT) {
+      x[i] = fma(ad, (double)p[i], x[i]);
+      const float rv = fmaf(-a, w[i], r[i]);
+      r[i] = rv;
+      d += (double)rv * rv;
+    }
+  }
+  __shared__ double sh[VT / 64];
+  const double bs = block_sum<VT>(d, sh);
+  const double v1[1] = {bs};
+  if (publish_partials<VT, 1>(v1, partials, &ctrl->cnt[SLOT_RR], SLOT_RR, gridDim.x,
+                              blockIdx.x)) {
+    const double S = gather_partials<VT>(partials, SLOT_RR, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      fin_update(ctrl, S);
+      __hip_atomic_store(&ctrl->cnt[SLOT_RR], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(VT) void pupdate_kernel(float* __restrict__ p,
+                                                     const float* __restrict__ z, int N,
+                                                     const Ctrl* __restrict__ ctrl) {
+  if (ctrl->done != RUNNING) return;
+  const float b = (float)ctrl->beta;
+  const int n4 = N >> 2;
+  float4* p4 = reinterpret_cast<float4*>(p);
+  const float4* z4 = reinterpret_cast<const float4*>(z);
+  for (int i = blockIdx.x * VT + threadIdx.x; i < n4; i += gridDim.x * VT) {
+    float4 pv = p4[i];
+    const float4 zv = z4[i];
+    pv.x = fmaf(b, pv.x, zv.x); pv.y = fmaf(b, pv.y, zv.y);
+    pv.z = fmaf(b, pv.z, zv.z); pv.w = fmaf(b, pv.w, zv.w);
+    p4[i] = pv;
+  }
+  if (blockIdx.x == 0)
+    for (int i = 4 * n4 + threadIdx.x; i < N; i += VT) p[i] = fmaf(b, p[i], z[i]);
+}
+
+// ||v||^2 -> rr and the preconditioner scales (standalone preconditioner use)
+__global__ __launch_bounds__(VT) void norm_scale_kernel(const float* __restrict__ v, int N,
+                                                        Ctrl* ctrl, double* partials) {
+  double d = 0.0;
+  for (int i = blockIdx.x * VT + threadIdx.x; i < N; i += gridDim.x * VT)
+    d += (double)v[i] * v[i];
+  __shared__ double sh[VT / 64];
+  const double bs = block_sum<VT>(d, sh);
+  const double v1[1] = {bs};
+  if (publish_partials<VT, 1>(v1, partials, &ctrl->cnt[SLOT_NORM], SLOT_NORM, gridDim.x,
+                              blockIdx.x)) {
+    const double S = gather_partials<VT>(partials, SLOT_NORM, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      ctrl->rr = S;
+      set_scales(ctrl, S);
+      __hip_atomic_store(&ctrl->cnt[SLOT_NORM], 0u, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+hipError_t launch_update(const Plan& P, hipStream_t s) {
+  const int N = P.n * P.n;
+  hipLaunchKernelGGL(update_kernel, dim3(vec_blocks(N >> 2)), dim3(VT), 0, s, P.x64, P.r,
+                     P.p, P.w, N, P.ctrl, P.partials);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(VT) void convert_x_kernel(double* __restrict__ x64,
+                                                       float* __restrict__ x, int N,
+                                                       int to_f32) {
+  for (int i = blockIdx.x * VT + threadIdx.x; i < N; i += gridDim.x * VT) {
+    if (to_f32) x[i] = (float)x64[i];
+    else x64[i] = (double)x[i];
+  }
+}
+
+hipError_t launch_convert_x(const Plan& P, float* x, bool to_f32, hipStream_t s) {
+  const int N = P.n * P.n;
+  hipLaunchKernelGGL(convert_x_kernel, dim3(vec_blocks(N >> 2)), dim3(VT), 0, s, P.x64, x, N,
+                     to_f32 ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_pupdate_from(const Plan& P, const float* z, hipStream_t s) {
+  const int N = P.n * P.n;
+  hipLaunchKernelGGL(pupdate_kernel, dim3(vec_blocks(N >> 2)), dim3(VT), 0, s, P.p, z, N,
+                     P.ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_pupdate(const Plan& P, hipStream_t s) {
+  return launch_pupdate_from(P, P.z, s);
+}
+
+hipError_t launch_norm_scale(const Plan& P, const float* v, hipStream_t s) {
+  const int N = P.n * P.n;
+  hipLaunchKernelGGL(norm_scale_kernel, dim3(vec_blocks(N >> 2)), dim3(VT), 0, s, v, N,
+                     P.ctrl, P.partials);
+  return hipGetLastError();
+}
+
+}  // namespace kpcg

@@ -1,0 +1,260 @@
+"""Thin ctypes binding of libkpcg (the C ABI declared in include/kpcg.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device buffers are torch CUDA tensors (float32, contiguous, n x n);
+torch supplies device memory and the stream.  The binding fails loudly if the
+shared library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libkpcg.so")
+
+# status codes and mode bits (mirror include/kpcg.h)
+KP_OK, KP_MAXIT, KP_BREAKDOWN = 0, 1, 2
+KP_ERR_ARG, KP_ERR_UNSUPPORTED, KP_ERR_HIP, KP_ERR_SOLVER, KP_ERR_WORKSPACE = -1, -2, -3, -4, -5
+KP_CG, KP_PCG, KP_FPCG = 0x000, 0x001, 0x002
+KP_P32, KP_P16, KP_P8 = 0x000, 0x010, 0x020
+KP_WARM = 0x100
+KP_MAX_PSF = 63
+
+
+class KPError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {strerror(status)} (status {status})")
+        self.status = status
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("replacements", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("relres_rec", ctypes.c_double), ("relres_true", ctypes.c_double),
+                ("lambda_", ctypes.c_double), ("rhs_norm", ctypes.c_double)]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("kron_terms", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("kp_rel_error", ctypes.c_double),
+                ("sigma_c_max", ctypes.c_double), ("sigma_c_min", ctypes.c_double),
+                ("sigma_r_max", ctypes.c_double), ("sigma_r_min", ctypes.c_double),
+                ("device_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_SIGS = {
+    "kp_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "kp_setup": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP,
+                                ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "kp_plan_query": (ctypes.c_int, [_VP, ctypes.POINTER(_PlanInfo)]),
+    "pcg_solve": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_int, _VP, ctypes.POINTER(_Info), _VP]),
+    "gcv_lambda": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, ctypes.c_double, _VP, _VP,
+                                  _VP]),
+    "discrepancy_lambda": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_double, _VP, _VP, _VP]),
+    "kp_destroy": (ctypes.c_int, [_VP]),
+    "kp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "kp_blur": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
+    "kp_normal_fp64": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP]),
+    "kp_precond": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP, _VP]),
+    "kp_get_factors": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "kp_time_blur": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_float), _VP]),
+    "kp_time_precond": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP,
+                                       ctypes.c_int, ctypes.POINTER(ctypes.c_float), _VP]),
+}
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raises if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libkpcg not built: {path} is missing "
+                          "(run python -m paper_2311_15393_amd.build)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    return load().kp_strerror(int(status)).decode()
+
+
+def _check(status: int, what: str, ok=(KP_OK,)):
+    if status not in ok:
+        raise KPError(status, what)
+    return status
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _dev_image(t, n, name, dtype=None):
+    import torch
+    dtype = dtype or torch.float32
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype or tuple(t.shape) != (n, n) or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {n}x{n} {dtype} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    iters: int
+    status: int
+    replacements: int
+    relres_rec: float
+    relres_true: float
+    lam: float
+    rhs_norm: float
+
+
+def workspace_size(n: int, k: int) -> int:
+    return int(load().kp_workspace_size(n, k, 0))
+
+
+class Plan:
+    """kp_setup / kp_destroy around one PSF and image size."""
+
+    def __init__(self, psf: np.ndarray, n: int, bc: int = 0, stream=None, workspace=None):
+        lib = load()
+        psf = np.ascontiguousarray(psf, dtype=np.float64)
+        if psf.ndim != 2 or psf.shape[0] != psf.shape[1]:
+            raise ValueError("psf must be a square 2-D array")
+        self.n, self.k = int(n), int(psf.shape[0])
+        self._ws = workspace
+        wptr, wbytes = None, 0
+        if workspace is not None:
+            wptr, wbytes = ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+        h = ctypes.c_void_p()
+        st = lib.kp_setup(psf.ctypes.data_as(ctypes.c_void_p), self.k, self.n, int(bc), wptr,
+                          wbytes, _stream(stream), ctypes.byref(h))
+        _check(st, "kp_setup")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().kp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- properties -------------------------------------------------------
+    def query(self) -> dict:
+        pi = _PlanInfo()
+        _check(load().kp_plan_query(self._h, ctypes.byref(pi)), "kp_plan_query")
+        return {f: getattr(pi, f) for f, _ in _PlanInfo._fields_ if f != "reserved"}
+
+    def factors(self, with_v: bool = True):
+        n = self.n
+        sc, sr = np.empty(n), np.empty(n)
+        vc = np.empty((n, n)) if with_v else None
+        vr = np.empty((n, n)) if with_v else None
+        p = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+        _check(load().kp_get_factors(self._h, p(sc), p(sr), p(vc), p(vr)), "kp_get_factors")
+        return sc, sr, vc, vr
+
+    # -- the hot path -----------------------------------------------------
+    def solve(self, b, lam: float, tol: float = 1e-6, maxit: int = 1000,
+              mode: int = KP_FPCG | KP_P16, x=None, stream=None, raise_on_fail=True):
+        import torch
+        bp = _dev_image(b, self.n, "b")
+        if x is None:
+            x = torch.empty_like(b)
+        xp = _dev_image(x, self.n, "x")
+        info = _Info()
+        st = load().pcg_solve(self._h, bp, float(lam), float(tol), int(maxit), int(mode), xp,
+                              ctypes.byref(info), _stream(stream))
+        if st < 0 or (raise_on_fail and st not in (KP_OK, KP_MAXIT)):
+            raise KPError(st, "pcg_solve")
+        return x, SolveInfo(info.iters, st, info.replacements, info.relres_rec,
+                            info.relres_true, info.lambda_, info.rhs_norm)
+
+    def gcv(self, b, grid, omega: float = 1.0, stream=None):
+        bp = _dev_image(b, self.n, "b")
+        grid = np.ascontiguousarray(grid, dtype=np.float64)
+        out = ctypes.c_double()
+        scores = np.empty(grid.size)
+        _check(load().gcv_lambda(self._h, bp, grid.ctypes.data_as(ctypes.c_void_p), grid.size,
+                                 float(omega), ctypes.byref(out),
+                                 scores.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+               "gcv_lambda")
+        return out.value, scores
+
+    def discrepancy(self, b, grid, noise_norm: float, eta: float = 1.0, stream=None):
+        bp = _dev_image(b, self.n, "b")
+        grid = np.ascontiguousarray(grid, dtype=np.float64)
+        out = ctypes.c_double()
+        vals = np.empty(grid.size)
+        _check(load().discrepancy_lambda(self._h, bp, grid.ctypes.data_as(ctypes.c_void_p),
+                                         grid.size, float(noise_norm), float(eta),
+                                         ctypes.byref(out),
+                                         vals.ctypes.data_as(ctypes.c_void_p),
+                                         _stream(stream)), "discrepancy_lambda")
+        return out.value, vals
+
+    # -- operator-level entry points -------------------------------------
+    def blur(self, x, y, transpose: bool = False, stream=None):
+        _check(load().kp_blur(self._h, _dev_image(x, self.n, "x"), _dev_image(y, self.n, "y"),
+                              int(bool(transpose)), _stream(stream)), "kp_blur")
+        return y
+
+    def normal_fp64(self, x, lam: float, y, stream=None):
+        import torch
+        _check(load().kp_normal_fp64(self._h, _dev_image(x, self.n, "x"), float(lam),
+                                     _dev_image(y, self.n, "y", torch.float64),
+                                     _stream(stream)), "kp_normal_fp64")
+        return y
+
+    def time_blur(self, x, y, transpose: bool = False, reps: int = 20, stream=None) -> float:
+        ms = ctypes.c_float()
+        _check(load().kp_time_blur(self._h, _dev_image(x, self.n, "x"),
+                                   _dev_image(y, self.n, "y"), int(bool(transpose)), int(reps),
+                                   ctypes.byref(ms), _stream(stream)), "kp_time_blur")
+        return float(ms.value)
+
+    def time_precond(self, r, lam: float, mode: int, z, reps: int = 20, stream=None) -> float:
+        ms = ctypes.c_float()
+        _check(load().kp_time_precond(self._h, _dev_image(r, self.n, "r"), float(lam), int(mode),
+                                      _dev_image(z, self.n, "z"), int(reps), ctypes.byref(ms),
+                                      _stream(stream)), "kp_time_precond")
+        return float(ms.value)
+
+    def precond(self, r, lam: float, mode: int, z, stream=None):
+        _check(load().kp_precond(self._h, _dev_image(r, self.n, "r"), float(lam), int(mode),
+                                 _dev_image(z, self.n, "z"), _stream(stream)), "kp_precond")
+        return z

@@ -1,0 +1,155 @@
+"""End-to-end parity of pcg_solve / gcv_lambda against the FP64 oracle.
+
+Parity measure: ||x - x_lambda|| / ||x_lambda|| with x_lambda the exact
+Tikhonov minimiser computed by the oracle (eq. (tik:normal2)).  Bars: 1e-5
+for the FP32 preconditioner, 1e-4 for FP16 (and for CG), the solver
+tolerance chosen tight enough that the iteration error is below the bar.
+"""
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import kp as KP
+from oracle import lam as L
+from oracle import solvers as SV
+from tests.gpu_util import rel, require_gpu, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _modes():
+    from paper_2311_15393_amd import KP_CG, KP_FPCG, KP_P16, KP_P32, KP_PCG
+    return {"cg": KP_CG, "pcg32": KP_PCG | KP_P32, "fpcg32": KP_FPCG | KP_P32,
+            "pcg16": KP_PCG | KP_P16, "fpcg16": KP_FPCG | KP_P16}
+
+
+_XLAM = {}
+
+
+def _xlam(prob):
+    key = (prob.kind, prob.n, prob.seed, prob.lam)
+    if key not in _XLAM:
+        _XLAM[key] = SV.x_lambda(prob.psf, prob.b.astype(np.float64), prob.lam)
+    return _XLAM[key]
+
+
+@pytest.mark.parametrize("mode,tol,bar,maxit", [
+    ("cg", 1e-8, 1e-4, 400), ("pcg32", 1e-9, 1e-5, 50), ("fpcg32", 1e-9, 1e-5, 50),
+    ("pcg16", 1e-8, 1e-4, 50), ("fpcg16", 1e-8, 1e-4, 50)])
+def test_small_gaussian(mode, tol, bar, maxit):
+    """64 x 64, separable Gaussian (K = 15): one Kronecker term, so the FP32
+    KP-preconditioned iteration needs only a couple of iterations."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_OK, Plan
+    prob = S.small_gaussian(0)
+    say(f"small gaussian {mode}")
+    ref = _xlam(prob)
+    with Plan(prob.psf, prob.n) as plan:
+        x, info = plan.solve(to_dev(prob.b), prob.lam, tol=tol, maxit=maxit,
+                             mode=_modes()[mode])
+        got = to_host(x)
+    err = rel(got, ref)
+    say(f"  iters={info.iters} status={info.status} relres_true={info.relres_true:.2e} err={err:.2e}")
+    assert info.status == KP_OK
+    assert info.relres_true <= tol
+    assert err <= bar
+    if mode in ("pcg32", "fpcg32"):
+        assert info.iters <= 3
+
+
+@pytest.mark.parametrize("mode,tol,bar", [
+    ("cg", 1e-8, 1e-4), ("pcg32", 1e-8, 1e-5), ("fpcg32", 1e-8, 1e-5),
+    ("pcg16", 1e-7, 1e-4), ("fpcg16", 1e-7, 1e-4)])
+def test_mid_anisotropic(mode, tol, bar):
+    """256 x 256, rotated anisotropic Gaussian (K = 31), lambda = 0.01."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_OK, Plan
+    prob = S.mid_anisotropic(0)
+    say(f"mid anisotropic {mode}")
+    ref = _xlam(prob)
+    with Plan(prob.psf, prob.n) as plan:
+        x, info = plan.solve(to_dev(prob.b), prob.lam, tol=tol, maxit=3000,
+                             mode=_modes()[mode])
+        got = to_host(x)
+    err = rel(got, ref)
+    say(f"  iters={info.iters} repl={info.replacements} relres_true={info.relres_true:.2e} err={err:.2e}")
+    assert info.status == KP_OK and info.relres_true <= tol
+    assert err <= bar
+
+
+@pytest.mark.parametrize("n,k", [(37, 9), (100, 15), (130, 31)])
+def test_ragged_sizes(n, k):
+    """Image sizes that leave partial tiles in every kernel."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, KP_P32, KP_PCG, Plan
+    rng = np.random.default_rng(n)
+    psf = S.psf_moffat_motion(k, 3.0, 2.5, 4.0, 1.0)
+    prob = S.make_problem(n, psf, rng, 0.01, 0.02, n, f"ragged{k}")
+    say(f"ragged n={n} k={k}")
+    ref = _xlam(prob)
+    with Plan(psf, n) as plan:
+        for mode, bar in ((KP_PCG | KP_P32, 1e-5), (KP_FPCG | KP_P16, 1e-4)):
+            x, info = plan.solve(to_dev(prob.b), prob.lam, tol=1e-8, maxit=500, mode=mode)
+            err = rel(to_host(x), ref)
+            say(f"  mode={mode:#x} iters={info.iters} err={err:.2e}")
+            assert info.status == KP_OK and err <= bar
+
+
+def test_edge_cases():
+    torch = require_gpu()
+    from paper_2311_15393_amd import (KP_BREAKDOWN, KP_ERR_ARG, KP_FPCG, KP_MAXIT, KP_OK, KP_P16,
+                                      KP_PCG, KP_WARM, KPError, Plan)
+    prob = S.small_gaussian(1)
+    with Plan(prob.psf, prob.n) as plan:
+        say("edge: zero data")
+        z = torch.zeros((prob.n, prob.n), device="cuda")
+        x, info = plan.solve(z, 0.02, mode=KP_FPCG | KP_P16)
+        assert info.status == KP_OK and info.iters == 0 and not to_host(x).any()
+        say("edge: maxit = 1")
+        x, info = plan.solve(to_dev(prob.b), 0.02, tol=1e-12, maxit=1, mode=0)
+        assert info.status == KP_MAXIT and info.iters == 1
+        say("edge: warm start from the converged solution")
+        x, info = plan.solve(to_dev(prob.b), 0.02, tol=1e-7, maxit=50, mode=KP_PCG)
+        x2, info2 = plan.solve(to_dev(prob.b), 0.02, tol=1e-6, maxit=50,
+                               mode=KP_PCG | KP_WARM, x=x.clone())
+        assert info2.status == KP_OK and info2.iters == 0
+        say("edge: invalid arguments")
+        for kw in ({"lam": -1.0}, {"lam": 0.0}, {"lam": float("nan")}, {"tol": 0.0},
+                   {"maxit": 0}, {"mode": 3}, {"mode": 0x30}, {"mode": 0x1000}):
+            args = {"lam": 0.02, "tol": 1e-6, "maxit": 10, "mode": KP_PCG}
+            args.update(kw)
+            with pytest.raises(KPError) as ei:
+                plan.solve(to_dev(prob.b), args["lam"], tol=args["tol"],
+                           maxit=args["maxit"], mode=args["mode"])
+            assert ei.value.status == KP_ERR_ARG
+        say("edge: non-finite data")
+        bad = to_dev(prob.b)
+        bad[3, 5] = float("nan")
+        with pytest.raises(KPError) as ei:
+            plan.solve(bad, 0.02, mode=KP_PCG)
+        assert ei.value.status == KP_BREAKDOWN
+
+
+def test_gcv_and_discrepancy_match_oracle():
+    """KP-basis GCV and discrepancy on the 32-point grid (eqs. (GCVTikSVD),
+    (DSCTikSVD)): same grid choice as the oracle, scores to 1e-5 relative
+    (b_hat from FP32 factors and FP32 MFMA GEMMs)."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import Plan
+    prob = S.mid_anisotropic(2)
+    grid = S.lambda_grid()
+    kp = KP.kp_svd(prob.psf, prob.n)
+    s2, bh2 = L.spectrum(kp, prob.b.astype(np.float64))
+    g_ref = L.gcv(s2, bh2, grid)
+    d_ref = L.discrepancy(s2, bh2, grid, prob.noise_norm)
+    with Plan(prob.psf, prob.n) as plan:
+        lam_g, g = plan.gcv(to_dev(prob.b), grid)
+        lam_w, gw = plan.gcv(to_dev(prob.b), grid, omega=3.0)
+        lam_d, d = plan.discrepancy(to_dev(prob.b), grid, prob.noise_norm)
+    say(f"gcv lam={lam_g:.4g} dp lam={lam_d:.4g}")
+    assert lam_g == grid[L.grid_argmin(g_ref)]
+    assert np.allclose(g, g_ref, rtol=1e-5)
+    assert np.allclose(gw, L.gcv(s2, bh2, grid, 3.0), rtol=1e-5)
+    assert lam_w == grid[L.grid_argmin(L.gcv(s2, bh2, grid, 3.0))]
+    assert np.allclose(d, d_ref, rtol=1e-5, atol=1e-6 * prob.noise_norm ** 2)
+    assert lam_d == grid[L.grid_discrepancy(d_ref)]

@@ -1,0 +1,89 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+include/kpcg.h declares, and rejects invalid arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kpcg.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted({n for n in names if not n.startswith("__")})
+
+
+def _lib():
+    from paper_2311_15393_amd import kpcg
+    if not os.path.exists(kpcg.LIB_PATH):
+        pytest.skip("libkpcg.so not built")
+    return kpcg.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("kp_workspace_size", "kp_setup", "pcg_solve", "gcv_lambda",
+                     "kp_destroy", "kp_strerror"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_2311_15393_amd import kpcg
+    assert set(_declared_functions()) <= set(kpcg.exported_symbols())
+
+
+def test_strerror_and_workspace_size():
+    from paper_2311_15393_amd import kpcg
+    _lib()
+    assert "invalid" in kpcg.strerror(kpcg.KP_ERR_ARG)
+    assert kpcg.strerror(12345) == "unknown status"
+    assert kpcg.workspace_size(0, 3) == 0
+    assert kpcg.workspace_size(64, 4) == 0          # even support
+    assert kpcg.workspace_size(4, 9) == 0           # K > 2n - 1
+    small, big = kpcg.workspace_size(64, 15), kpcg.workspace_size(1024, 63)
+    assert 0 < small < big
+    assert big < 200 * 2 ** 20
+
+
+@pytest.mark.parametrize("k,n,bc,expect", [
+    (4, 16, 0, -1),       # even K
+    (15, 4, 0, -1),       # K > 2n - 1
+    (15, 0, 0, -1),       # n < 1
+    (15, 64, 1, -2),      # non-zero boundary condition
+    (65, 64, 0, -2),      # K above the supported maximum
+])
+def test_setup_rejects_bad_arguments_without_gpu(k, n, bc, expect):
+    lib = _lib()
+    psf = np.ones((k, k)) / (k * k) if k > 0 else np.ones((1, 1))
+    h = ctypes.c_void_p()
+    st = lib.kp_setup(psf.ctypes.data_as(ctypes.c_void_p), k, n, bc, None, 0, None,
+                      ctypes.byref(h))
+    assert st == expect and not h.value
+
+
+def test_setup_rejects_non_finite_psf():
+    lib = _lib()
+    psf = np.ones((5, 5))
+    psf[2, 2] = np.nan
+    h = ctypes.c_void_p()
+    st = lib.kp_setup(psf.ctypes.data_as(ctypes.c_void_p), 5, 16, 0, None, 0, None,
+                      ctypes.byref(h))
+    assert st == -1
+
+
+def test_null_plan_arguments():
+    lib = _lib()
+    assert lib.kp_destroy(None) == -1
+    assert lib.pcg_solve(None, None, 0.1, 1e-6, 10, 0, None, None, None) == -1
+    assert lib.gcv_lambda(None, None, None, 0, 1.0, None, None, None) == -1
