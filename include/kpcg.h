@@ -89,6 +89,9 @@ typedef struct kp_plan_info_s {
     double  kp_rel_error;   /* ||A - A_r (x) A_c||_F / ||A||_F (Table 1)   */
     double  sigma_c_max, sigma_c_min, sigma_r_max, sigma_r_min;
     size_t  device_bytes;   /* device memory held by the plan              */
+    int32_t blur_config;    /* blur tile shape picked by the setup-time
+                               autotuner (index into its candidate list)  */
+    float   blur_config_ms[8]; /* autotuner time per candidate (ms)       */
 } kp_plan_info_t;
 
 /*

@@ -51,7 +51,6 @@ struct EpiStoreF32 {
     float* o = dst + (size_t)i * n + j0;
     for (int c = 0; c < cnt; ++c) o[c] = (float)v[c];
   }
-  __device__ void finalize(Ctrl*, double) const {}
 };
 
 struct EpiStoreF64 {
@@ -63,7 +62,6 @@ struct EpiStoreF64 {
     double* o = dst + (size_t)i * n + j0;
     for (int c = 0; c < cnt; ++c) o[c] = (double)v[c];
   }
-  __device__ void finalize(Ctrl*, double) const {}
 };
 
 // w = A^T q + lambda^2 p and delta = p . w  (the H p product of CG)
@@ -80,11 +78,6 @@ struct EpiNormalW {
       w[o + c] = wv;
       d += (double)pv * (double)wv;
     }
-  }
-  __device__ void finalize(Ctrl* c, double S) const {
-    c->delta = S;
-    if (!(S > 0.0) || !isfinite(S)) c->done = BREAKDOWN;
-    else c->alpha = c->rho / S;
   }
 };
 
@@ -103,19 +96,11 @@ struct EpiRhs {
       d += cv * cv;
     }
   }
-  __device__ void finalize(Ctrl* c, double S) const {
-    c->gamma0sq = S;
-    c->rr = S;
-    c->rho = S;
-    c->tol2 = c->tol_rel2 * S;
-    c->repl2 = REPLACE_DROP * REPLACE_DROP * S;
-    set_scales(c, S);
-  }
 };
 
 // r = c - A^T y - lambda^2 x with y = A x in FP64: the true residual
 struct EpiTrueRes {
-  const double* c64; const double* x; float* r; double lam2; int n; int fin;
+  const double* c64; const double* x; float* r; double lam2; int n;
   static constexpr bool kReduce = true;
   static constexpr int kSlot = SLOT_TRUE;
   template <typename Acc>
@@ -126,20 +111,6 @@ struct EpiTrueRes {
       r[o + c] = (float)rv;
       d += rv * rv;
     }
-  }
-  __device__ void finalize(Ctrl* c, double S) const {
-    c->true_rr = S;
-    if (!fin) return;
-    c->rr = S;
-    c->repl2 = REPLACE_DROP * REPLACE_DROP * S;
-    set_scales(c, S);
-    if (c->solver == KP_CG) {
-      if (c->done == PENDING) c->beta = S / c->rho_prev;
-      c->rho = S;
-    }
-    if (!isfinite(S)) c->done = BREAKDOWN;
-    else if (S <= c->tol2) c->done = CONVERGED;
-    else if (c->done == PENDING) c->done = RUNNING;
   }
 };
 
@@ -210,21 +181,10 @@ __global__ __launch_bounds__(TX* TY) void blur_kernel(
   }
   if constexpr (Epi::kReduce) {
     __shared__ double sh[NT / 64];
-    const double bs = block_sum<NT>(d, sh);
-    const int nb = gridDim.x * gridDim.y;
-    const double v1[1] = {bs};
-    if (publish_partials<NT, 1>(v1, partials, &ctrl->cnt[Epi::kSlot], Epi::kSlot, nb,
-                                blockIdx.y * gridDim.x + blockIdx.x)) {
-      const double S = gather_partials<NT>(partials, Epi::kSlot, nb, sh);
-      if (threadIdx.x == 0) {
-        epi.finalize(ctrl, S);
-        __hip_atomic_store(&ctrl->cnt[Epi::kSlot], 0u, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
+    const double v1[1] = {block_sum<NT>(d, sh)};
+    write_partials<1>(v1, partials, Epi::kSlot, blockIdx.y * gridDim.x + blockIdx.x);
   }
 }
-
 
 // ---------------------------------------------------------------------------
 // launch configurations
@@ -249,33 +209,119 @@ static hipError_t run_blur(const Plan& P, const In* src, const Tap* taps, Epi ep
   const size_t lds = (size_t)(TH + K - 1) * ldw * sizeof(In);
   dim3 grid((n + TW - 1) / TW, (n + TH - 1) / TH);
   if ((long)grid.x * grid.y > MAX_PARTIALS) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((blur_kernel<TX, TY, RX, RY, BC, In, Acc, Tap, Epi>), grid, dim3(TX * TY),
-                     lds, s, src, taps, n, K, KQ, ldw, epi, ctrl, skip, P.partials);
+  auto kern = blur_kernel<TX, TY, RX, RY, BC, In, Acc, Tap, Epi>;
+  if (lds > 65536) {
+    // beyond 64 KB the kernel must opt in to the larger dynamic LDS size
+    static size_t granted = 65536;
+    if (lds > granted) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      granted = lds;
+    }
+  }
+  hipLaunchKernelGGL(kern, grid, dim3(TX * TY), lds, s, src, taps, n, K, KQ, ldw, epi, ctrl,
+                     skip, P.partials);
   return hipGetLastError();
 }
 
-// FP32 tiles: 64 x 32 outputs, 8 per thread in a row.
-#define KP_F32_CFG 8, 32, 8, 1
-// FP64-input tiles (true residual second pass): 32 x 16 outputs.
-#define KP_F64IN_CFG 8, 16, 4, 1
+template <int TX, int TY, int RX, int RY>
+static int blur_blocks(int n) {
+  return ((n + TX * RX - 1) / (TX * RX)) * ((n + TY * RY - 1) / (TY * RY));
+}
+
+// FP32 tile shapes (TX threads across x RX columns each, TY threads down x
+// RY rows each); the plan picks the fastest for its (n, K) at setup.
+#define KP_CFG0 8, 32, 8, 1     // 64 x 32 tile, 256 threads
+#define KP_CFG1 8, 16, 8, 1     // 64 x 16 tile, 128 threads
+#define KP_CFG2 8, 32, 8, 2     // 64 x 64 tile, 256 threads, 2 rows / thread
+#define KP_CFG3 16, 16, 8, 1    // 128 x 16 tile, 256 threads
+#define KP_CFG4 8, 64, 8, 1     // 64 x 64 tile, 512 threads
+#define KP_CFG5 16, 16, 4, 2    // 64 x 32 tile, 256 threads, 4 x 2 per thread
+constexpr int NUM_BLUR_CFG = 6;
+// FP32 input, FP64 accumulation (right-hand side)
+#define KP_F32_CFG KP_CFG0
+// FP64-input tiles (true residual): 64 x 64 outputs, 512 threads, 129 KB LDS at K = 63
+#define KP_F64IN_CFG 8, 64, 8, 1
+
+template <class Epi>
+static hipError_t blur_dispatch(int cfg, const Plan& P, const float* src, const float* taps,
+                                Epi epi, Ctrl* ctrl, int skip, hipStream_t s, int* nb) {
+  const int n = P.n;
+  switch (cfg) {
+    case 1: *nb = blur_blocks<KP_CFG1>(n);
+      return run_blur<KP_CFG1, float, float, float>(P, src, taps, epi, ctrl, skip, s);
+    case 2: *nb = blur_blocks<KP_CFG2>(n);
+      return run_blur<KP_CFG2, float, float, float>(P, src, taps, epi, ctrl, skip, s);
+    case 3: *nb = blur_blocks<KP_CFG3>(n);
+      return run_blur<KP_CFG3, float, float, float>(P, src, taps, epi, ctrl, skip, s);
+    case 4: *nb = blur_blocks<KP_CFG4>(n);
+      return run_blur<KP_CFG4, float, float, float>(P, src, taps, epi, ctrl, skip, s);
+    case 5: *nb = blur_blocks<KP_CFG5>(n);
+      return run_blur<KP_CFG5, float, float, float>(P, src, taps, epi, ctrl, skip, s);
+    default: *nb = blur_blocks<KP_CFG0>(n);
+      return run_blur<KP_CFG0, float, float, float>(P, src, taps, epi, ctrl, skip, s);
+  }
+}
 
 hipError_t launch_blur_f32(const Plan& P, const float* src, float* dst, bool transpose,
                            hipStream_t s, const Ctrl* ctrl) {
   EpiStoreF32 e{dst, P.n};
-  return run_blur<KP_F32_CFG, float, float, float>(
-      P, src, transpose ? P.taps32 : P.taps32_flip, e, const_cast<Ctrl*>(ctrl),
-      ctrl != nullptr, s);
+  int nb;
+  return blur_dispatch(P.blur_cfg, P, src, transpose ? P.taps32 : P.taps32_flip, e,
+                       const_cast<Ctrl*>(ctrl), ctrl != nullptr, s, &nb);
 }
 
 hipError_t launch_blur_normal(const Plan& P, const float* q, const float* p, float* w,
-                                  float lam2, hipStream_t s) {
+                              float lam2, hipStream_t s) {
   EpiNormalW e{p, w, lam2, P.n};
-  return run_blur<KP_F32_CFG, float, float, float>(P, q, P.taps32, e, P.ctrl, 1, s);
+  int nb;
+  hipError_t err = blur_dispatch(P.blur_cfg, P, q, P.taps32, e, P.ctrl, 1, s, &nb);
+  if (err != hipSuccess) return err;
+  return launch_scalar(P, SC_ALPHA, nb, s);
+}
+
+// Autotuner: time every FP32 tile shape on this plan's (n, K) and keep the
+// fastest (3 timed launches each after one warm-up; scratch vectors p, q).
+hipError_t autotune_blur(Plan& P, hipStream_t s, float* times_ms) {
+  hipEvent_t e0, e1;
+  hipError_t err = hipEventCreate(&e0);
+  if (err != hipSuccess) return err;
+  err = hipEventCreate(&e1);
+  if (err != hipSuccess) return err;
+  err = hipMemsetAsync(P.p, 0, sizeof(float) * (size_t)P.n * P.n, s);
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int c = 0; c < NUM_BLUR_CFG && err == hipSuccess; ++c) {
+    EpiStoreF32 e{P.q, P.n};
+    int nb;
+    err = blur_dispatch(c, P, P.p, P.taps32_flip, e, nullptr, 0, s, &nb);
+    if (err != hipSuccess) break;
+    err = hipEventRecord(e0, s);
+    for (int it = 0; it < 3 && err == hipSuccess; ++it)
+      err = blur_dispatch(c, P, P.p, P.taps32_flip, e, nullptr, 0, s, &nb);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    ms /= 3.f;
+    if (times_ms) times_ms[c] = ms;
+    if (err == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  P.blur_cfg = best;
+  return err;
 }
 
 hipError_t launch_rhs(const Plan& P, const float* b, hipStream_t s) {
   EpiRhs e{P.c64, P.r, P.n};
-  return run_blur<KP_F32_CFG, float, double, double>(P, b, P.taps64, e, P.ctrl, 0, s);
+  hipError_t err = run_blur<KP_F32_CFG, float, double, double>(P, b, P.taps64, e, P.ctrl, 0, s);
+  if (err != hipSuccess) return err;
+  return launch_scalar(P, SC_RHS, blur_blocks<KP_F32_CFG>(P.n), s);
 }
 
 hipError_t launch_true_residual(const Plan& P, const double* x, double lam2, bool fin,
@@ -284,8 +330,10 @@ hipError_t launch_true_residual(const Plan& P, const double* x, double lam2, boo
   hipError_t err =
       run_blur<KP_F64IN_CFG, double, double, double>(P, x, P.taps64_flip, e1, P.ctrl, 0, s);
   if (err != hipSuccess) return err;
-  EpiTrueRes e2{P.c64, x, P.r, lam2, P.n, fin ? 1 : 0};
-  return run_blur<KP_F64IN_CFG, double, double, double>(P, P.y64, P.taps64, e2, P.ctrl, 0, s);
+  EpiTrueRes e2{P.c64, x, P.r, lam2, P.n};
+  err = run_blur<KP_F64IN_CFG, double, double, double>(P, P.y64, P.taps64, e2, P.ctrl, 0, s);
+  if (err != hipSuccess) return err;
+  return launch_scalar(P, fin ? SC_TRUE : SC_TRUE_INFO, blur_blocks<KP_F64IN_CFG>(P.n), s);
 }
 
 // y = (A^T A + lam2 I) x with FP64 accumulation (test entry point)
@@ -298,7 +346,6 @@ struct EpiNormal64 {
     const size_t o = (size_t)i * n + j0;
     for (int c = 0; c < cnt; ++c) y[o + c] = (double)v[c] + lam2 * (double)x[o + c];
   }
-  __device__ void finalize(Ctrl*, double) const {}
 };
 
 hipError_t launch_normal_fp64(const Plan& P, const float* x, double lam2, double* y,

@@ -107,8 +107,6 @@ bool valid_sizes(int n, int k) {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-bool fp8_available() { return launch_precond_fp8(Plan{}, nullptr, nullptr, nullptr, false, 0.f,
-                                                 nullptr) != hipErrorNotSupported; }
 
 int read_ctrl(Plan& P, hipStream_t s, Ctrl& out) {
   HIPCHK(hipMemcpyAsync(P.host_ctrl, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -205,6 +203,7 @@ int kp_setup(const double* psf, int k, int n, int bc, void* workspace, size_t ws
   int rc = KP_OK;
   if (hipMemsetAsync(P.ctrl, 0, sizeof(Ctrl), s) != hipSuccess) rc = KP_ERR_HIP;
   if (rc == KP_OK) rc = build_factors(P, psf, s);
+  if (rc == KP_OK && autotune_blur(P, s, P.blur_times) != hipSuccess) rc = KP_ERR_HIP;
   if (rc != KP_OK) {
     hipStreamSynchronize(s);
     hipHostFree(P.host_ctrl);
@@ -229,6 +228,8 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t* out) {
   out->sigma_r_max = P.sr_max;
   out->sigma_r_min = P.sr_min;
   out->device_bytes = P.bytes;
+  out->blur_config = P.blur_cfg;
+  for (int i = 0; i < 8; ++i) out->blur_config_ms[i] = P.blur_times[i];
   return KP_OK;
 }
 
@@ -266,7 +267,8 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
   const int prec = mode & KP_PREC_MASK;
   if (solver == 3 || prec == KP_PREC_MASK) return KP_ERR_ARG;
   if (!aligned16(b) || !aligned16(x)) return KP_ERR_ARG;
-  if (solver != KP_CG && prec == KP_P8 && !fp8_available()) return KP_ERR_UNSUPPORTED;
+  if (solver != KP_CG && prec == KP_P8 && !fp8_supported_size(plan->P.n))
+    return KP_ERR_UNSUPPORTED;
   Plan& P = plan->P;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t N = (size_t)P.n * P.n;
@@ -445,7 +447,7 @@ int kp_precond(kp_plan_t plan, const float* r, double lambda, int mode, float* z
     return KP_ERR_ARG;
   const int prec = mode & KP_PREC_MASK;
   if (prec == KP_PREC_MASK) return KP_ERR_ARG;
-  if (prec == KP_P8 && !fp8_available()) return KP_ERR_UNSUPPORTED;
+  if (prec == KP_P8 && !fp8_supported_size(plan->P.n)) return KP_ERR_UNSUPPORTED;
   if (!aligned16(r) || !aligned16(z)) return KP_ERR_ARG;
   Plan& P = plan->P;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -489,7 +491,7 @@ int kp_time_precond(kp_plan_t plan, const float* r, double lambda, int mode, flo
   if (!plan || !r || !z || r == z || reps < 1 || !avg_ms || !(lambda > 0.0)) return KP_ERR_ARG;
   const int prec = mode & KP_PREC_MASK;
   if (prec == KP_PREC_MASK) return KP_ERR_ARG;
-  if (prec == KP_P8 && !fp8_available()) return KP_ERR_UNSUPPORTED;
+  if (prec == KP_P8 && !fp8_supported_size(plan->P.n)) return KP_ERR_UNSUPPORTED;
   Plan& P = plan->P;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Ctrl c;

@@ -63,7 +63,7 @@ struct Ctrl {
   int solver;       // KP_CG / KP_PCG / KP_FPCG
   int prec;         // KP_P32 / KP_P16 / KP_P8
   int first;        // 1 while the initial z is being formed (beta = 0)
-  unsigned cnt[NSLOTS];
+  int nb[NSLOTS];   // number of partials last written to each slot
 };
 
 // ---------------------------------------------------------------------------
@@ -92,37 +92,17 @@ __device__ inline double block_sum(double v, double* sh) {
   return t;
 }
 
-// Publish this block's partial(s) for slots [slot, slot+nv) and return true
-// (in every thread) in the block that arrives last.
-template <int NT, int NV>
-__device__ inline bool publish_partials(const double (&v)[NV], double* partials,
-                                        unsigned* counter, int slot, int nblocks,
-                                        int bid) {
-  __shared__ int last;
+// Write this block's partial sum(s) (valid in thread 0) for slots
+// [slot, slot + nv).  A single-block scalar kernel sums them afterwards in a
+// fixed order, so no atomics or fences are needed and the result is
+// deterministic.
+template <int NV>
+__device__ inline void write_partials(const double (&v)[NV], double* partials, int slot,
+                                      int bid) {
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
-      __hip_atomic_store(&partials[(slot + k) * MAX_PARTIALS + bid], v[k],
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned t = atomicAdd(counter, 1u);
-    last = (t == (unsigned)(nblocks - 1));
+    for (int k = 0; k < NV; ++k) partials[(slot + k) * MAX_PARTIALS + bid] = v[k];
   }
-  __syncthreads();
-  return last != 0;
-}
-
-// Fixed-order sum of the published partials of one slot (last block only);
-// valid in thread 0.
-template <int NT>
-__device__ inline double gather_partials(const double* partials, int slot, int nblocks,
-                                         double* sh) {
-  __threadfence();
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nblocks; i += NT)
-    s += __hip_atomic_load(&partials[slot * MAX_PARTIALS + i], __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-  return block_sum<NT>(s, sh);
 }
 
 // Power of two s with s * sqrt(rr) < 2^14 (keeps every FP16 intermediate of
@@ -194,6 +174,9 @@ struct Plan {
   double* partials = nullptr;
   Ctrl* host_ctrl = nullptr;     // pinned
 
+  int blur_cfg = 0;              // tile shape of the FP32 blur (autotuned)
+  float blur_times[8] = {};      // autotuner timings (ms) per shape
+
   // properties
   double kp_err = 0.0;
   int terms = 0;
@@ -208,6 +191,7 @@ hipError_t launch_blur_f32(const Plan& P, const float* src, float* dst, bool tra
 hipError_t launch_blur_normal(const Plan& P, const float* q, const float* p, float* w,
                               float lam2, hipStream_t s);
 hipError_t launch_rhs(const Plan& P, const float* b, hipStream_t s);
+hipError_t autotune_blur(Plan& P, hipStream_t s, float* times_ms);
 hipError_t launch_true_residual(const Plan& P, const double* x64, double lam2, bool fin,
                                 hipStream_t s);
 hipError_t launch_normal_fp64(const Plan& P, const float* x, double lam2, double* y,
@@ -217,12 +201,26 @@ hipError_t launch_update(const Plan& P, hipStream_t s);
 hipError_t launch_convert_x(const Plan& P, float* x, bool to_f32, hipStream_t s);
 hipError_t launch_pupdate(const Plan& P, hipStream_t s);
 hipError_t launch_norm_scale(const Plan& P, const float* v, hipStream_t s);
+
+// single-block kernels that turn per-block partials into the iteration's
+// scalars (see scalar_kernel in vec.hip)
+enum ScalarKind : int {
+  SC_ALPHA = 0,    // delta = p.Hp -> alpha, breakdown test
+  SC_RR = 1,       // ||r||^2 -> convergence / replacement test, FP16 scale, CG beta
+  SC_BETA = 2,     // r.z, z.Hp -> beta (Fletcher-Reeves or Polak-Ribiere)
+  SC_RHS = 3,      // ||A^T b||^2 -> tolerances
+  SC_TRUE = 4,     // true residual ||c - Hx||^2 -> converged / continue
+  SC_TRUE_INFO = 5,// true residual for reporting only
+  SC_NORM = 6,     // ||r||^2 -> preconditioner scales only
+};
+hipError_t launch_scalar(const Plan& P, int kind, int nb, hipStream_t s);
 hipError_t launch_init_ctrl(const Plan& P, const Ctrl& host, hipStream_t s);
 
 hipError_t launch_precond(const Plan& P, const float* r, float* z, const float* w,
                           int prec, bool finalize, float lam2, hipStream_t s);
 hipError_t launch_precond_fp8(const Plan& P, const float* r, float* z, const float* w,
                               bool finalize, float lam2, hipStream_t s);
+bool fp8_supported_size(int n);   // the FP8 chain needs n to be a multiple of 128
 hipError_t launch_spectral_gemms(const Plan& P, const float* b, float* out, hipStream_t s);
 
 hipError_t launch_spectrum(const Plan& P, const float* b, hipStream_t s);

@@ -22,6 +22,8 @@
 // Tiles: 64 x 64 per workgroup, 4 waves in 2 x 2, each wave 32 x 32 as 2 x 2
 // MFMA 16x16 blocks; FP32 uses v_mfma_f32_16x16x4_f32, FP16
 // v_mfma_f32_16x16x32_f16, both accumulating in FP32.
+#include <type_traits>
+
 #include "common.h"
 
 namespace kpcg {
@@ -32,77 +34,105 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 
 template <typename T> struct MT;
 template <> struct MT<float> {
-  static constexpr int BK = 16;     // k per LDS stage
+  static constexpr int BK = 32;     // k per LDS stage
   static constexpr int VEC = 4;     // elements per 16-byte load
   static constexpr int PAD = 4;
+  static constexpr int KM = 4;      // k per MFMA
 };
 template <> struct MT<_Float16> {
-  static constexpr int BK = 32;
+  static constexpr int BK = 64;
   static constexpr int VEC = 8;
   static constexpr int PAD = 8;
+  static constexpr int KM = 32;
 };
 
 constexpr int GT = 256;  // threads per GEMM workgroup
 constexpr int BM = 64, BN = 64;
 
-// ---------------------------------------------------------------------------
-// operand staging into LDS (s[row][k], k contiguous)
-// ---------------------------------------------------------------------------
 template <typename T>
-__device__ inline void stage_kcontig(T (*s)[MT<T>::BK + MT<T>::PAD], const T* __restrict__ g,
-                                     int row0, int k0, int n) {
-  constexpr int BK = MT<T>::BK, VEC = MT<T>::VEC;
-  const int row = threadIdx.x / (BK / VEC);
-  const int kc = (threadIdx.x % (BK / VEC)) * VEC;
-  const int gr = row0 + row, gk = k0 + kc;
-  T* dst = &s[row][kc];
-  if (gr < n && gk + VEC <= n) {
-    const float4 v = *reinterpret_cast<const float4*>(g + (size_t)gr * n + gk);
-    *reinterpret_cast<float4*>(dst) = v;
-  } else {
-#pragma unroll
-    for (int e = 0; e < VEC; ++e)
-      dst[e] = (gr < n && gk + e < n) ? g[(size_t)gr * n + gk + e] : T(0);
-  }
-}
+using Tile = T[BM][MT<T>::BK + MT<T>::PAD];
 
-// B tile from a row-major FP32 matrix src[k][j] (contraction over its rows),
-// multiplied by `scale` and rounded to T while being transposed into s[j][k].
+// ---------------------------------------------------------------------------
+// operand staging: global -> registers (issued one stage ahead) -> LDS
+// (s[row][k], k contiguous).  Each thread moves two 16-byte vectors per
+// K-contiguous operand and BK*BN/(4*GT) float4 of an FP32 row-major source.
+// ---------------------------------------------------------------------------
 template <typename T>
-__device__ inline void stage_from_f32_rows(T (*s)[MT<T>::BK + MT<T>::PAD],
-                                           const float* __restrict__ src, int k0, int j0,
-                                           int n, float scale) {
-  constexpr int BK = MT<T>::BK;
-  constexpr int PER = BK * BN / GT;          // floats per thread (4 or 8)
-  constexpr int TPR = BN / PER;              // threads per k row
-  const int k = threadIdx.x / TPR;
-  const int jc = (threadIdx.x % TPR) * PER;
-  const int gk = k0 + k;
+struct KContig {
+  static constexpr int BK = MT<T>::BK, VEC = MT<T>::VEC, PER_ROW = BK / VEC;
+  static constexpr int NV = BM * BK / VEC / GT;      // = 2
+  float4 reg[NV];
+  __device__ void load(const T* __restrict__ g, int row0, int k0, int n, bool vec_ok) {
 #pragma unroll
-  for (int e4 = 0; e4 < PER; e4 += 4) {
-    const int gj = j0 + jc + e4;
-    float4 v;
-    if (gk < n && gj + 4 <= n) {
-      v = *reinterpret_cast<const float4*>(src + (size_t)gk * n + gj);
-    } else {
-      v.x = (gk < n && gj + 0 < n) ? src[(size_t)gk * n + gj + 0] : 0.f;
-      v.y = (gk < n && gj + 1 < n) ? src[(size_t)gk * n + gj + 1] : 0.f;
-      v.z = (gk < n && gj + 2 < n) ? src[(size_t)gk * n + gj + 2] : 0.f;
-      v.w = (gk < n && gj + 3 < n) ? src[(size_t)gk * n + gj + 3] : 0.f;
+    for (int v = 0; v < NV; ++v) {
+      const int id = threadIdx.x + GT * v;
+      const int row = id / PER_ROW, kc = (id % PER_ROW) * VEC;
+      const int gr = row0 + row, gk = k0 + kc;
+      if (vec_ok && gr < n && gk + VEC <= n) {
+        reg[v] = *reinterpret_cast<const float4*>(g + (size_t)gr * n + gk);
+      } else {
+        T tmp[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          tmp[e] = (gr < n && gk + e < n) ? g[(size_t)gr * n + gk + e] : T(0);
+        reg[v] = *reinterpret_cast<const float4*>(tmp);
+      }
     }
-    s[jc + e4 + 0][k] = (T)(v.x * scale);
-    s[jc + e4 + 1][k] = (T)(v.y * scale);
-    s[jc + e4 + 2][k] = (T)(v.z * scale);
-    s[jc + e4 + 3][k] = (T)(v.w * scale);
   }
-}
+  __device__ void store(Tile<T>& s) const {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int id = threadIdx.x + GT * v;
+      const int row = id / PER_ROW, kc = (id % PER_ROW) * VEC;
+      *reinterpret_cast<float4*>(&s[row][kc]) = reg[v];
+    }
+  }
+};
+
+// B tile from a row-major FP32 matrix src[k][j] (contraction over its rows):
+// scaled and rounded to T, transposed into s[j][k].
+template <typename T>
+struct FromF32Rows {
+  static constexpr int BK = MT<T>::BK;
+  static constexpr int NV = BK * BN / 4 / GT;        // float4 per thread
+  static constexpr int TPR = BN / 4;                 // threads per k row
+  float4 reg[NV];
+  __device__ void load(const float* __restrict__ src, int j0, int k0, int n, bool vec_ok) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int id = threadIdx.x + GT * v;
+      const int k = id / TPR, jc = (id % TPR) * 4;
+      const int gk = k0 + k, gj = j0 + jc;
+      if (vec_ok && gk < n && gj + 4 <= n) {
+        reg[v] = *reinterpret_cast<const float4*>(src + (size_t)gk * n + gj);
+      } else {
+        float4 t;
+        t.x = (gk < n && gj + 0 < n) ? src[(size_t)gk * n + gj + 0] : 0.f;
+        t.y = (gk < n && gj + 1 < n) ? src[(size_t)gk * n + gj + 1] : 0.f;
+        t.z = (gk < n && gj + 2 < n) ? src[(size_t)gk * n + gj + 2] : 0.f;
+        t.w = (gk < n && gj + 3 < n) ? src[(size_t)gk * n + gj + 3] : 0.f;
+        reg[v] = t;
+      }
+    }
+  }
+  __device__ void store(Tile<T>& s, float scale) const {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int id = threadIdx.x + GT * v;
+      const int k = id / TPR, jc = (id % TPR) * 4;
+      s[jc + 0][k] = (T)(reg[v].x * scale);
+      s[jc + 1][k] = (T)(reg[v].y * scale);
+      s[jc + 2][k] = (T)(reg[v].z * scale);
+      s[jc + 3][k] = (T)(reg[v].w * scale);
+    }
+  }
+};
 
 // ---------------------------------------------------------------------------
-// MFMA step over one LDS stage
+// MFMA over one LDS stage: wave (wm, wn) owns a 32 x 32 block of C
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ inline void mma_stage(const T (*sA)[MT<T>::BK + MT<T>::PAD],
-                                 const T (*sB)[MT<T>::BK + MT<T>::PAD], float4_t (&acc)[2][2],
+__device__ inline void mma_stage(const Tile<T>& sA, const Tile<T>& sB, float4_t (&acc)[2][2],
                                  int wm, int wn, int lane) {
   const int r16 = lane & 15, g = lane >> 4;
   if constexpr (sizeof(T) == 4) {
@@ -120,18 +150,22 @@ __device__ inline void mma_stage(const T (*sA)[MT<T>::BK + MT<T>::PAD],
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
     }
   } else {
-    half8_t a[2], b[2];
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-      a[mi] = *reinterpret_cast<const half8_t*>(&sA[wm * 32 + mi * 16 + r16][g * 8]);
+    for (int kk = 0; kk < MT<T>::BK; kk += 32) {
+      half8_t a[2], b[2];
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
-      b[ni] = *reinterpret_cast<const half8_t*>(&sB[wn * 32 + ni * 16 + r16][g * 8]);
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < 2; ++mi)
+        a[mi] = *reinterpret_cast<const half8_t*>(&sA[wm * 32 + mi * 16 + r16][kk + g * 8]);
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni)
-        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+        b[ni] = *reinterpret_cast<const half8_t*>(&sB[wn * 32 + ni * 16 + r16][kk + g * 8]);
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] =
+              __builtin_amdgcn_mfma_f32_16x16x32_f16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
   }
 }
 
@@ -172,24 +206,6 @@ struct GEpiFinal {                       // z (already scaled) ; r.z ; z.w
   }
 };
 
-__device__ inline void fin_rz(Ctrl* c, double rz, double zw) {
-  c->rz = rz;
-  c->zw = zw;
-  if (!(rz > 0.0) || !isfinite(rz) || !isfinite(zw)) {
-    c->done = BREAKDOWN;
-    return;
-  }
-  if (c->first) {
-    c->beta = 0.0;
-    c->first = 0;
-  } else if (c->solver == KP_PCG) {
-    c->beta = rz / c->rho;               // Fletcher-Reeves
-  } else {
-    c->beta = -zw / c->delta;            // Polak-Ribiere = -alpha (z.Hp) / rho
-  }
-  c->rho = rz;
-}
-
 // ---------------------------------------------------------------------------
 // the GEMM kernel: C[n x n] = A[n x n] * Bt^T (or * B from FP32 rows)
 // ---------------------------------------------------------------------------
@@ -199,12 +215,13 @@ __global__ __launch_bounds__(GT) void gemm_kernel(const T* __restrict__ A,
                                                   Epi epi, Ctrl* ctrl, int skip_if_done,
                                                   int scale_mode, double* partials) {
   if (skip_if_done && ctrl->done != RUNNING) return;
-  constexpr int BK = MT<T>::BK, LD = BK + MT<T>::PAD;
-  __shared__ __align__(16) T sA[BM][LD];
-  __shared__ __align__(16) T sB[BN][LD];
+  constexpr int BK = MT<T>::BK;
+  __shared__ __align__(16) Tile<T> sA[2];
+  __shared__ __align__(16) Tile<T> sB[2];
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wm = wv >> 1, wn = wv & 1;
+  const bool vec_ok = (n % 8) == 0;
   // scale_mode bit 0: scale the FP32 B source by pscale; bit 1: scale the
   // output by zscale (both set on the device from ||r||)
   const float bscale = (scale_mode & 1) ? ctrl->pscale : 1.0f;
@@ -216,14 +233,31 @@ __global__ __launch_bounds__(GT) void gemm_kernel(const T* __restrict__ A,
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = float4_t{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < n; k0 += BK) {
-    stage_kcontig<T>(sA, A, m0, k0, n);
+  KContig<T> la;
+  using BL = typename std::conditional<B_FROM_F32, FromF32Rows<T>, KContig<T>>::type;
+  BL lb;
+  auto load = [&](int k0) {
+    la.load(A, m0, k0, n, vec_ok);
     if constexpr (B_FROM_F32)
-      stage_from_f32_rows<T>(sB, reinterpret_cast<const float*>(Bsrc), k0, n0, n, bscale);
+      lb.load(reinterpret_cast<const float*>(Bsrc), n0, k0, n, vec_ok);
     else
-      stage_kcontig<T>(sB, reinterpret_cast<const T*>(Bsrc), n0, k0, n);
-    __syncthreads();
-    mma_stage<T>(sA, sB, acc, wm, wn, lane);
+      lb.load(reinterpret_cast<const T*>(Bsrc), n0, k0, n, vec_ok);
+  };
+  auto store = [&](int buf) {
+    la.store(sA[buf]);
+    if constexpr (B_FROM_F32) lb.store(sB[buf], bscale);
+    else lb.store(sB[buf]);
+  };
+
+  const int nk = (n + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);       // next stage in flight during the MFMAs
+    mma_stage<T>(sA[cur], sB[cur], acc, wm, wn, lane);
+    if (kt + 1 < nk) store(cur ^ 1);
     __syncthreads();
   }
 
@@ -243,18 +277,8 @@ __global__ __launch_bounds__(GT) void gemm_kernel(const T* __restrict__ A,
     __shared__ double sh[GT / 64];
     const double s0 = block_sum<GT>(d0, sh);
     const double s1 = block_sum<GT>(d1, sh);
-    const int nb = gridDim.x * gridDim.y;
     const double v2[2] = {s0, s1};
-    if (publish_partials<GT, 2>(v2, partials, &ctrl->cnt[SLOT_RZ], SLOT_RZ, nb,
-                                blockIdx.y * gridDim.x + blockIdx.x)) {
-      const double rz = gather_partials<GT>(partials, SLOT_RZ, nb, sh);
-      const double zw = gather_partials<GT>(partials, SLOT_ZW, nb, sh);
-      if (threadIdx.x == 0) {
-        fin_rz(ctrl, rz, zw);
-        __hip_atomic_store(&ctrl->cnt[SLOT_RZ], 0u, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
+    write_partials<2>(v2, partials, SLOT_RZ, blockIdx.y * gridDim.x + blockIdx.x);
   }
 }
 
@@ -285,8 +309,11 @@ static hipError_t precond_chain(const Plan& P, const T* VcT, const T* Vc, const 
   if (e != hipSuccess) return e;
   e = run_gemm<T, false>(P, Vc, t2, GEpiStore<T>{t3, n}, skip, 0, s);
   if (e != hipSuccess) return e;
-  return finalize ? run_gemm<T, false>(P, t3, Vr, GEpiFinal<true>{z, r, w, n}, skip, 2, s)
-                  : run_gemm<T, false>(P, t3, Vr, GEpiFinal<false>{z, r, w, n}, skip, 2, s);
+  if (!finalize) return run_gemm<T, false>(P, t3, Vr, GEpiFinal<false>{z, r, w, n}, skip, 2, s);
+  e = run_gemm<T, false>(P, t3, Vr, GEpiFinal<true>{z, r, w, n}, skip, 2, s);
+  if (e != hipSuccess) return e;
+  const int nb = ((n + BN - 1) / BN) * ((n + BM - 1) / BM);
+  return launch_scalar(P, SC_BETA, nb, s);
 }
 
 hipError_t launch_precond(const Plan& P, const float* r, float* z, const float* w, int prec,

@@ -11,25 +11,11 @@
 namespace kpcg {
 
 constexpr int VT = 256;          // threads per block
-constexpr int VMAXB = 1024;      // blocks per vector kernel
+constexpr int VMAXB = 512;       // blocks per vector kernel
 
 static inline int vec_blocks(int n4) {
   int b = (n4 + VT - 1) / VT;
   return b < 1 ? 1 : (b > VMAXB ? VMAXB : b);
-}
-
-__device__ inline void fin_update(Ctrl* c, double S) {
-  c->rr = S;
-  c->iter += 1;
-  if (c->solver == KP_CG) {
-    c->rho_prev = c->rho;
-    c->beta = S / c->rho;
-    c->rho = S;
-  }
-  set_scales(c, S);
-  if (!isfinite(S)) c->done = BREAKDOWN;
-  else if (S <= c->tol2 || S <= c->repl2) c->done = PENDING;
-  else if (c->iter >= c->maxit) c->done = MAXIT;
 }
 
 // x += alpha p (FP64 accumulator) ; r -= alpha w ; ||r||^2
@@ -70,16 +56,8 @@ __global__ __launch_bounds__(VT) void update_kernel(double* __restrict__ x,
     }
   }
   __shared__ double sh[VT / 64];
-  const double bs = block_sum<VT>(d, sh);
-  const double v1[1] = {bs};
-  if (publish_partials<VT, 1>(v1, partials, &ctrl->cnt[SLOT_RR], SLOT_RR, gridDim.x,
-                              blockIdx.x)) {
-    const double S = gather_partials<VT>(partials, SLOT_RR, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      fin_update(ctrl, S);
-      __hip_atomic_store(&ctrl->cnt[SLOT_RR], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  const double v1[1] = {block_sum<VT>(d, sh)};
+  write_partials<1>(v1, partials, SLOT_RR, blockIdx.x);
 }
 
 // p = z + beta p
@@ -109,25 +87,18 @@ __global__ __launch_bounds__(VT) void norm_scale_kernel(const float* __restrict_
   for (int i = blockIdx.x * VT + threadIdx.x; i < N; i += gridDim.x * VT)
     d += (double)v[i] * v[i];
   __shared__ double sh[VT / 64];
-  const double bs = block_sum<VT>(d, sh);
-  const double v1[1] = {bs};
-  if (publish_partials<VT, 1>(v1, partials, &ctrl->cnt[SLOT_NORM], SLOT_NORM, gridDim.x,
-                              blockIdx.x)) {
-    const double S = gather_partials<VT>(partials, SLOT_NORM, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      ctrl->rr = S;
-      set_scales(ctrl, S);
-      __hip_atomic_store(&ctrl->cnt[SLOT_NORM], 0u, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  const double v1[1] = {block_sum<VT>(d, sh)};
+  write_partials<1>(v1, partials, SLOT_NORM, blockIdx.x);
 }
 
 hipError_t launch_update(const Plan& P, hipStream_t s) {
   const int N = P.n * P.n;
-  hipLaunchKernelGGL(update_kernel, dim3(vec_blocks(N >> 2)), dim3(VT), 0, s, P.x64, P.r,
-                     P.p, P.w, N, P.ctrl, P.partials);
-  return hipGetLastError();
+  const int nb = vec_blocks(N >> 2);
+  hipLaunchKernelGGL(update_kernel, dim3(nb), dim3(VT), 0, s, P.x64, P.r, P.p, P.w, N, P.ctrl,
+                     P.partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_scalar(P, SC_RR, nb, s);
 }
 
 __global__ __launch_bounds__(VT) void convert_x_kernel(double* __restrict__ x64,
@@ -159,8 +130,110 @@ hipError_t launch_pupdate(const Plan& P, hipStream_t s) {
 
 hipError_t launch_norm_scale(const Plan& P, const float* v, hipStream_t s) {
   const int N = P.n * P.n;
-  hipLaunchKernelGGL(norm_scale_kernel, dim3(vec_blocks(N >> 2)), dim3(VT), 0, s, v, N,
-                     P.ctrl, P.partials);
+  const int nb = vec_blocks(N >> 2);
+  hipLaunchKernelGGL(norm_scale_kernel, dim3(nb), dim3(VT), 0, s, v, N, P.ctrl, P.partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_scalar(P, SC_NORM, nb, s);
+}
+
+// ---------------------------------------------------------------------------
+// scalar kernel: one block sums the partials of the kernel before it in a
+// fixed order and applies the (P)CG scalar logic; thread 0 updates Ctrl
+// ---------------------------------------------------------------------------
+constexpr int ST = 256;
+
+__device__ inline double sum_slot(const double* partials, int slot, int nb, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += ST) s += partials[slot * MAX_PARTIALS + i];
+  return block_sum<ST>(s, sh);
+}
+
+__global__ __launch_bounds__(ST) void scalar_kernel(Ctrl* __restrict__ c,
+                                                    const double* __restrict__ partials,
+                                                    int kind, int nb) {
+  __shared__ double sh[ST / 64];
+  const int done = c->done;
+  if ((kind == SC_ALPHA || kind == SC_RR || kind == SC_BETA) && done != RUNNING) return;
+  const int slot = kind == SC_ALPHA ? SLOT_DELTA
+                 : kind == SC_RR ? SLOT_RR
+                 : kind == SC_BETA ? SLOT_RZ
+                 : kind == SC_RHS ? SLOT_RHS
+                 : kind == SC_NORM ? SLOT_NORM : SLOT_TRUE;
+  const double S = sum_slot(partials, slot, nb, sh);
+  const double S2 = kind == SC_BETA ? sum_slot(partials, SLOT_ZW, nb, sh) : 0.0;
+  if (threadIdx.x != 0) return;
+  switch (kind) {
+    case SC_ALPHA:                          // delta = p . Hp
+      c->delta = S;
+      if (!(S > 0.0) || !isfinite(S)) c->done = BREAKDOWN;
+      else c->alpha = c->rho / S;
+      break;
+    case SC_RR:                             // after x += alpha p, r -= alpha w
+      c->rr = S;
+      c->iter += 1;
+      if (c->solver == KP_CG) {
+        c->rho_prev = c->rho;
+        c->beta = S / c->rho;
+        c->rho = S;
+      }
+      set_scales(c, S);
+      if (!isfinite(S)) c->done = BREAKDOWN;
+      else if (S <= c->tol2 || S <= c->repl2) c->done = PENDING;
+      break;
+    case SC_BETA: {                         // r.z and z.Hp after z = M^{-1} r
+      const double rz = S, zw = S2;
+      c->rz = rz;
+      c->zw = zw;
+      if (!(rz > 0.0) || !isfinite(rz) || !isfinite(zw)) {
+        c->done = BREAKDOWN;
+      } else {
+        if (c->first) {
+          c->beta = 0.0;
+          c->first = 0;
+        } else if (c->solver == KP_PCG) {
+          c->beta = rz / c->rho;            // Fletcher-Reeves
+        } else {
+          c->beta = -zw / c->delta;         // Polak-Ribiere = -alpha (z.Hp) / rho
+        }
+        c->rho = rz;
+      }
+      break;
+    }
+    case SC_RHS:                            // c = A^T b
+      c->gamma0sq = S;
+      c->rr = S;
+      c->rho = S;
+      c->tol2 = c->tol_rel2 * S;
+      c->repl2 = REPLACE_DROP * REPLACE_DROP * S;
+      set_scales(c, S);
+      break;
+    case SC_TRUE:                           // r = c - H x replaced the recurrence
+      c->true_rr = S;
+      c->rr = S;
+      c->repl2 = REPLACE_DROP * REPLACE_DROP * S;
+      set_scales(c, S);
+      if (c->solver == KP_CG) {
+        if (done == PENDING) c->beta = S / c->rho_prev;
+        c->rho = S;
+      }
+      if (!isfinite(S)) c->done = BREAKDOWN;
+      else if (S <= c->tol2) c->done = CONVERGED;
+      else if (done == PENDING) c->done = RUNNING;
+      break;
+    case SC_TRUE_INFO:
+      c->true_rr = S;
+      break;
+    case SC_NORM:
+      c->rr = S;
+      set_scales(c, S);
+      break;
+  }
+}
+
+hipError_t launch_scalar(const Plan& P, int kind, int nb, hipStream_t s) {
+  if (nb > MAX_PARTIALS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(ST), 0, s, P.ctrl, P.partials, kind, nb);
   return hipGetLastError();
 }
 

@@ -44,7 +44,8 @@ class _PlanInfo(ctypes.Structure):
                 ("kp_rel_error", ctypes.c_double),
                 ("sigma_c_max", ctypes.c_double), ("sigma_c_min", ctypes.c_double),
                 ("sigma_r_max", ctypes.c_double), ("sigma_r_min", ctypes.c_double),
-                ("device_bytes", ctypes.c_size_t)]
+                ("device_bytes", ctypes.c_size_t), ("blur_config", ctypes.c_int32),
+                ("blur_config_ms", ctypes.c_float * 8)]
 
 
 _lib = None
@@ -177,7 +178,9 @@ class Plan:
     def query(self) -> dict:
         pi = _PlanInfo()
         _check(load().kp_plan_query(self._h, ctypes.byref(pi)), "kp_plan_query")
-        return {f: getattr(pi, f) for f, _ in _PlanInfo._fields_ if f != "reserved"}
+        out = {f: getattr(pi, f) for f, _ in _PlanInfo._fields_ if f != "reserved"}
+        out["blur_config_ms"] = list(out["blur_config_ms"])
+        return out
 
     def factors(self, with_v: bool = True):
         n = self.n

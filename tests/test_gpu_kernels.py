@@ -152,3 +152,48 @@ def test_precond_fp16_matches_emulated_chain(n, k, lam):
     assert 0.5 * e_emul <= e_gpu <= 1.5 * e_emul
     assert d <= 0.5 * e_emul
     assert 1e-5 < e_emul < 2e-2
+
+
+@pytest.mark.parametrize("n,k,lam", [(128, 15, 0.02), (256, 31, 0.01), (1024, 63, 0.003)])
+def test_precond_fp8_matches_emulated_chain(n, k, lam):
+    """FP8 e4m3 chain with 32-entry block exponents on the block-scaled MFMA,
+    vs the oracle's emulation with the same block structure (exponent from
+    the block's largest magnitude, e4m3 round-to-nearest-even, exact
+    products).  As for FP16, the GPU's FP32 accumulation moves a few
+    roundings to the neighbouring code: its error against exact arithmetic
+    must be of the emulation's size and its distance to the emulation at
+    most half of that."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_P8, Plan
+    say(f"precond8 n={n} k={k}")
+    psf = _psf("moffat", k, 21)
+    r = S.random_image(np.random.default_rng(23), n) * 1e-3
+    with Plan(psf, n) as plan:
+        sc, sr, vc, vr = _gpu_factors(plan)
+        z = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        plan.precond(to_dev(r), lam, KP_P8, z)
+        got = to_host(z)
+    emul = Q.precond_fp8(vc, vr, sc, sr, lam, r.astype(np.float64))
+    exact = Q.precond_fp32(vc, vr, sc, sr, lam, r)
+    e_emul = rel(emul, exact)
+    e_gpu = rel(got, exact)
+    d = rel(got, emul)
+    say(f"  |gpu-exact|={e_gpu:.3e} |emul-exact|={e_emul:.3e} |gpu-emul|={d:.3e}")
+    assert 0.5 * e_emul <= e_gpu <= 1.5 * e_emul
+    assert d <= 0.5 * e_emul
+    assert 1e-3 < e_emul < 0.2
+
+
+def test_fp8_rejects_unsupported_size():
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_ERR_UNSUPPORTED, KP_FPCG, KP_P8, KPError, Plan
+    psf = _psf("gauss", 9)
+    with Plan(psf, 96) as plan:
+        z = torch.empty((96, 96), dtype=torch.float32, device="cuda")
+        r = to_dev(S.random_image(np.random.default_rng(1), 96))
+        with pytest.raises(KPError) as ei:
+            plan.precond(r, 0.01, KP_P8, z)
+        assert ei.value.status == KP_ERR_UNSUPPORTED
+        with pytest.raises(KPError) as ei:
+            plan.solve(r, 0.01, mode=KP_FPCG | KP_P8)
+        assert ei.value.status == KP_ERR_UNSUPPORTED

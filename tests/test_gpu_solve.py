@@ -18,9 +18,9 @@ pytestmark = pytest.mark.gpu
 
 
 def _modes():
-    from paper_2311_15393_amd import KP_CG, KP_FPCG, KP_P16, KP_P32, KP_PCG
+    from paper_2311_15393_amd import KP_CG, KP_FPCG, KP_P8, KP_P16, KP_P32, KP_PCG
     return {"cg": KP_CG, "pcg32": KP_PCG | KP_P32, "fpcg32": KP_FPCG | KP_P32,
-            "pcg16": KP_PCG | KP_P16, "fpcg16": KP_FPCG | KP_P16}
+            "pcg16": KP_PCG | KP_P16, "fpcg16": KP_FPCG | KP_P16, "fpcg8": KP_FPCG | KP_P8}
 
 
 _XLAM = {}
@@ -59,7 +59,7 @@ def test_small_gaussian(mode, tol, bar, maxit):
 
 @pytest.mark.parametrize("mode,tol,bar", [
     ("cg", 1e-8, 1e-4), ("pcg32", 1e-8, 1e-5), ("fpcg32", 1e-8, 1e-5),
-    ("pcg16", 1e-7, 1e-4), ("fpcg16", 1e-7, 1e-4)])
+    ("pcg16", 1e-7, 1e-4), ("fpcg16", 1e-7, 1e-4), ("fpcg8", 1e-7, 1e-4)])
 def test_mid_anisotropic(mode, tol, bar):
     """256 x 256, rotated anisotropic Gaussian (K = 31), lambda = 0.01."""
     torch = require_gpu()
@@ -153,3 +153,30 @@ def test_gcv_and_discrepancy_match_oracle():
     assert lam_w == grid[L.grid_argmin(L.gcv(s2, bh2, grid, 3.0))]
     assert np.allclose(d, d_ref, rtol=1e-5, atol=1e-6 * prob.noise_norm ** 2)
     assert lam_d == grid[L.grid_discrepancy(d_ref)]
+
+
+@pytest.mark.parametrize("mode", ["fpcg16", "fpcg8", "pcg32"])
+def test_large_moffat_full_size(mode):
+    """1024 x 1024, Moffat + motion PSF (K = 63), lambda from the GPU's KP-GCV
+    (same grid index as the oracle): the benchmark's configuration, checked
+    against the oracle's x_lambda at full size."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_OK, Plan
+    prob = S.large_moffat(0)
+    grid = S.lambda_grid()
+    say(f"large moffat {mode}")
+    with Plan(prob.psf, prob.n) as plan:
+        b = to_dev(prob.b)
+        lam, _ = plan.gcv(b, grid)
+        kp = KP.kp_svd(prob.psf, prob.n)
+        s2, bh2 = L.spectrum(kp, prob.b.astype(np.float64))
+        assert lam == grid[L.grid_argmin(L.gcv(s2, bh2, grid))]
+        key = ("large", prob.seed, lam)
+        if key not in _XLAM:
+            _XLAM[key] = SV.x_lambda_iterative(prob.psf, prob.b.astype(np.float64), lam, kp=kp,
+                                               check=False)[0]
+        ref = _XLAM[key]
+        x, info = plan.solve(b, lam, tol=1e-6, maxit=300, mode=_modes()[mode])
+        err = rel(to_host(x), ref)
+    say(f"  lam={lam:.4g} iters={info.iters} repl={info.replacements} err={err:.2e}")
+    assert info.status == KP_OK and err <= 1e-4
