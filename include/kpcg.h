@@ -63,6 +63,8 @@ extern "C" {
 #define KP_P8        0x020      /* FP8 e4m3 with 32-entry block scales      */
 #define KP_PREC_MASK 0x030
 #define KP_WARM      0x100      /* x holds the initial guess on entry       */
+#define KP_BATCH_EAGER 0x200    /* pcg_solve_batched: launch every iteration
+                                   eagerly instead of replaying a hipGraph */
 
 typedef struct kp_plan_s *kp_plan_t;   /* opaque */
 
@@ -77,6 +79,8 @@ typedef struct kp_info_s {
     double  relres_true;    /* FP64 ||A^T b - H x|| / ||A^T b|| at exit    */
     double  lambda;
     double  rhs_norm;       /* ||A^T b||_2                                 */
+    double  misfit;         /* ||A x - b||_2 (pcg_solve_batched only; 0 for
+                               pcg_solve)                                 */
 } kp_info_t;
 
 /* Properties of a plan (the Kronecker approximation it holds). */
@@ -176,6 +180,32 @@ int gcv_lambda(kp_plan_t plan, const float *b, const double *grid, int ngrid,
 int discrepancy_lambda(kp_plan_t plan, const float *b, const double *grid,
                        int ngrid, double noise_norm, double eta,
                        double *lambda_out, double *values_out, void *stream);
+
+/*
+ * pcg_solve_batched -- many solves of eq. (tik:normal2) in one set of
+ * launches: item i solves with plan plans[plan_of_item[i]] (its PSF and
+ * image size), data b[i], parameter lambdas[i], writing x[i].  All items
+ * share tol, maxit and mode (solver and preconditioner bits as pcg_solve;
+ * KP_P8 and KP_WARM are not supported here; KP_BATCH_EAGER launches the
+ * iterations eagerly instead of replaying a captured hipGraph).  Uneven
+ * image sizes and PSF supports are allowed.  Each phase of an iteration is
+ * one launch over the tiles of all items still iterating; each item stops
+ * on its own (converged, maxit, breakdown).  infos[i] receives item i's
+ * outcome, including its data misfit ||A x - b||.
+ *
+ *   plans, nplans   array of plan handles and its length
+ *   b, x            arrays of nitems device pointers (FP32 n_i x n_i, 16-byte
+ *                   aligned); lambdas: host array of nitems values > 0
+ *   plan_of_item    host array of nitems indices into plans
+ * Device memory for the items' vectors is allocated for the duration of
+ * the call (about 56 n_i^2 bytes per item).  Synchronises `stream`.
+ * Returns KP_OK if every item converged, KP_MAXIT / KP_BREAKDOWN if some
+ * did not (see infos), or an error.
+ */
+int pcg_solve_batched(const kp_plan_t *plans, int nplans, const float *const *b,
+                      const double *lambdas, const int *plan_of_item, int nitems,
+                      double tol, int maxit, int mode, float *const *x,
+                      kp_info_t *infos, void *stream);
 
 /* kp_destroy -- release the plan (and its memory if it allocated it). */
 int kp_destroy(kp_plan_t plan);

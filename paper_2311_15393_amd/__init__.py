@@ -4,9 +4,11 @@ ctypes binding (kpcg.py)."""
 from .kpcg import (KP_CG, KP_PCG, KP_FPCG, KP_P32, KP_P16, KP_P8, KP_WARM, KP_OK, KP_MAXIT,
                    KP_BREAKDOWN, KP_ERR_ARG, KP_ERR_UNSUPPORTED, KP_ERR_HIP, KP_ERR_SOLVER,
                    KP_ERR_WORKSPACE, KP_MAX_PSF, KPError, Plan, SolveInfo, load, strerror,
-                   workspace_size, exported_symbols, LIB_PATH)
+                   workspace_size, exported_symbols, LIB_PATH, KP_BATCH_EAGER,
+                   solve_batched)
 
 __all__ = ["KP_CG", "KP_PCG", "KP_FPCG", "KP_P32", "KP_P16", "KP_P8", "KP_WARM", "KP_OK",
            "KP_MAXIT", "KP_BREAKDOWN", "KP_ERR_ARG", "KP_ERR_UNSUPPORTED", "KP_ERR_HIP",
            "KP_ERR_SOLVER", "KP_ERR_WORKSPACE", "KP_MAX_PSF", "KPError", "Plan", "SolveInfo",
-           "load", "strerror", "workspace_size", "exported_symbols", "LIB_PATH"]
+           "load", "strerror", "workspace_size", "exported_symbols", "LIB_PATH",
+           "KP_BATCH_EAGER", "solve_batched"]

@@ -1,0 +1,719 @@
+// Batched solves: many (problem, lambda) items of uneven size in one set of
+// launches.
+//
+// Each phase of the (P)CG iteration is ONE launch over the tiles of every
+// item that is still active: a device tile table maps blockIdx.x to (item,
+// tile), and a per-item descriptor gives the item's size, PSF taps, KP-SVD
+// factors, vectors and control block.  Items converge, break down or hit
+// maxit independently (every kernel checks its item's state first).  Items
+// are grouped by the blur tile shape the setup-time autotuner chose for
+// their plan, so each group's blur launch uses its own shape.  The host
+// enqueues a block of iterations once into a hipGraph (on a private stream)
+// and replays it, reading back the items' control blocks between replays to
+// run the FP64 true-residual recomputations the items ask for.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "blur_core.h"
+#include "gemm_core.h"
+
+namespace kpcg {
+
+constexpr int MAXP_ITEM = 1024;   // partial sums per item and slot
+constexpr int VCH = 4096;         // floats per vector-kernel block
+
+struct ItemDesc {
+  int n, k, kq;
+  int nb_blur, nb_blur64, nb_gemm, nb_vec;   // blocks per item of each launch kind
+  int ntx_blur, ntx_blur64, ntx_gemm;        // tiles across of each launch kind
+  int prec;
+  float lam2f;
+  double lam2;
+  const float *taps32, *taps32_flip;
+  const double *taps64, *taps64_flip;
+  const _Float16 *VcT16, *Vc16, *Vr16, *VrT16;
+  const float *VcT32, *Vc32, *Vr32, *VrT32;
+  const float *sc2, *sr2;
+  const float* b;
+  float* x;
+  float *r, *p, *q, *w, *z;
+  double *x64, *c64, *y64;
+  void *t1, *t2, *t3;
+  Ctrl* ctrl;
+  double* partials;                          // [NSLOTS][MAXP_ITEM]
+};
+
+struct TileRef {
+  int item;
+  int t;                                     // tile index within the item
+};
+
+enum RunMode : int { RM_RUNNING = 0, RM_PENDING = 1, RM_ALL = 2, RM_RESUME = 3, RM_FINISHED = 4 };
+
+__device__ inline bool item_active(const Ctrl* c, int mode) {
+  const int d = c->done;
+  switch (mode) {
+    case RM_RUNNING: return d == RUNNING;
+    case RM_PENDING: return d == PENDING;
+    case RM_RESUME: return d == RUNNING && c->resume;
+    case RM_FINISHED: return d == MAXIT || d == BREAKDOWN;
+    default: return true;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batched blur
+// ---------------------------------------------------------------------------
+enum BlurKind : int { BK_A = 0, BK_AT_NORMAL = 1, BK_RHS = 2, BK_TRUE1 = 3, BK_TRUE2 = 4,
+                      BK_MISFIT = 5 };
+
+// ||A x - b||^2 for the data-misfit report
+struct EpiMisfit {
+  const float* b; int n;
+  static constexpr bool kReduce = true;
+  static constexpr int kSlot = SLOT_NORM;
+  template <typename Acc>
+  __device__ void row(int i, int j0, int cnt, const Acc* v, double& d) const {
+    const size_t o = (size_t)i * n + j0;
+    for (int c = 0; c < cnt; ++c) {
+      const double e = (double)v[c] - (double)b[o + c];
+      d += e * e;
+    }
+  }
+};
+
+template <int TX, int TY, int RX, int RY, int KIND>
+__global__ __launch_bounds__(TX* TY) void blur_batched_kernel(const ItemDesc* __restrict__ items,
+                                                              const TileRef* __restrict__ tiles,
+                                                              int mode) {
+  const TileRef tr = tiles[blockIdx.x];
+  const ItemDesc& it = items[tr.item];
+  if (!item_active(it.ctrl, mode)) return;
+  constexpr int TW = TX * RX, TH = TY * RY;
+  const int n = it.n;
+  if constexpr (KIND == BK_TRUE1 || KIND == BK_TRUE2) {
+    const int ty = tr.t / it.ntx_blur64, tx = tr.t - ty * it.ntx_blur64;
+    const int ldw = lds_width<TX, TY, RX, RY, double>(it.kq);
+    double* out = it.partials + SLOT_TRUE * MAXP_ITEM + tr.t;
+    if constexpr (KIND == BK_TRUE1) {
+      EpiStoreF64 e{it.y64, n};
+      blur_tile<TX, TY, RX, RY, BC, double, double, double, EpiStoreF64>(
+          it.x64, it.taps64_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, out);
+    } else {
+      EpiTrueRes e{it.c64, it.x64, it.r, it.lam2, n};
+      blur_tile<TX, TY, RX, RY, BC, double, double, double, EpiTrueRes>(
+          it.y64, it.taps64, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, out);
+    }
+  } else {
+    const int ty = tr.t / it.ntx_blur, tx = tr.t - ty * it.ntx_blur;
+    const int ldw = lds_width<TX, TY, RX, RY, float>(it.kq);
+    if constexpr (KIND == BK_A) {
+      EpiStoreF32 e{it.q, n};
+      blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiStoreF32>(
+          it.p, it.taps32_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, nullptr);
+    } else if constexpr (KIND == BK_AT_NORMAL) {
+      EpiNormalW e{it.p, it.w, it.lam2f, n};
+      blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiNormalW>(
+          it.q, it.taps32, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
+          it.partials + SLOT_DELTA * MAXP_ITEM + tr.t);
+    } else if constexpr (KIND == BK_RHS) {
+      EpiRhs e{it.c64, it.r, n};
+      blur_tile<TX, TY, RX, RY, BC, float, double, double, EpiRhs>(
+          it.b, it.taps64, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
+          it.partials + SLOT_RHS * MAXP_ITEM + tr.t);
+    } else {
+      EpiMisfit e{it.b, n};
+      blur_tile<TX, TY, RX, RY, BC, float, double, double, EpiMisfit>(
+          it.x, it.taps64_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
+          it.partials + SLOT_NORM * MAXP_ITEM + tr.t);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batched GEMM stages of the preconditioner solve
+// ---------------------------------------------------------------------------
+template <typename T, int STAGE>
+__global__ __launch_bounds__(GT) void gemm_batched_kernel(const ItemDesc* __restrict__ items,
+                                                          const TileRef* __restrict__ tiles,
+                                                          int mode) {
+  const TileRef tr = tiles[blockIdx.x];
+  const ItemDesc& it = items[tr.item];
+  if (!item_active(it.ctrl, mode)) return;
+  const int n = it.n;
+  const int ty = tr.t / it.ntx_gemm, tx = tr.t - ty * it.ntx_gemm;
+  const int m0 = ty * BM, n0 = tx * BN;
+  T* t1 = reinterpret_cast<T*>(it.t1);
+  T* t2 = reinterpret_cast<T*>(it.t2);
+  T* t3 = reinterpret_cast<T*>(it.t3);
+  const bool f16 = sizeof(T) == 2;
+  const T* VcT = f16 ? (const T*)it.VcT16 : (const T*)it.VcT32;
+  const T* Vc = f16 ? (const T*)it.Vc16 : (const T*)it.Vc32;
+  const T* Vr = f16 ? (const T*)it.Vr16 : (const T*)it.Vr32;
+  const T* VrT = f16 ? (const T*)it.VrT16 : (const T*)it.VrT32;
+  if constexpr (STAGE == 1) {
+    gemm_tile<T, true, GEpiStore<T>>(VcT, it.r, n, m0, n0, GEpiStore<T>{t1, n},
+                                     it.ctrl->pscale, 1.0f, nullptr, MAXP_ITEM);
+  } else if constexpr (STAGE == 2) {
+    gemm_tile<T, false, GEpiSPrimeT<T>>(t1, VrT, n, m0, n0,
+                                        GEpiSPrimeT<T>{t2, it.sc2, it.sr2, it.lam2f, n}, 1.0f,
+                                        1.0f, nullptr, MAXP_ITEM);
+  } else if constexpr (STAGE == 3) {
+    gemm_tile<T, false, GEpiStore<T>>(Vc, t2, n, m0, n0, GEpiStore<T>{t3, n}, 1.0f, 1.0f,
+                                      nullptr, MAXP_ITEM);
+  } else {
+    gemm_tile<T, false, GEpiFinal<true>>(t3, Vr, n, m0, n0, GEpiFinal<true>{it.z, it.r, it.w, n},
+                                         1.0f, it.ctrl->zscale,
+                                         it.partials + SLOT_RZ * MAXP_ITEM + tr.t, MAXP_ITEM);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batched vector kernels (one block per VCH floats of an item)
+// ---------------------------------------------------------------------------
+enum VecKind : int { VK_UPDATE = 0, VK_PUPDATE_Z = 1, VK_PUPDATE_R = 2, VK_INIT = 3,
+                     VK_TO_F32 = 4, VK_FROM_F32 = 5 };
+
+template <int KIND>
+__global__ __launch_bounds__(256) void vec_batched_kernel(const ItemDesc* __restrict__ items,
+                                                          const TileRef* __restrict__ tiles,
+                                                          int mode) {
+  const TileRef tr = tiles[blockIdx.x];
+  const ItemDesc& it = items[tr.item];
+  if (!item_active(it.ctrl, mode)) return;
+  const int N = it.n * it.n;
+  const int e0 = tr.t * VCH, e1 = min(N, e0 + VCH);
+  double d = 0.0;
+  if constexpr (KIND == VK_UPDATE) {
+    const double ad = it.ctrl->alpha;
+    const float a = (float)ad;
+    for (int i = e0 + threadIdx.x; i < e1; i += 256) {
+      it.x64[i] = fma(ad, (double)it.p[i], it.x64[i]);
+      const float rv = fmaf(-a, it.w[i], it.r[i]);
+      it.r[i] = rv;
+      d += (double)rv * rv;
+    }
+  } else if constexpr (KIND == VK_PUPDATE_Z || KIND == VK_PUPDATE_R) {
+    const float bt = (float)it.ctrl->beta;
+    const float* z = KIND == VK_PUPDATE_Z ? it.z : it.r;
+    for (int i = e0 + threadIdx.x; i < e1; i += 256) it.p[i] = fmaf(bt, it.p[i], z[i]);
+  } else if constexpr (KIND == VK_INIT) {
+    for (int i = e0 + threadIdx.x; i < e1; i += 256) {
+      it.p[i] = 0.0f;
+      it.w[i] = 0.0f;
+      it.x64[i] = 0.0;
+    }
+  } else if constexpr (KIND == VK_TO_F32) {
+    for (int i = e0 + threadIdx.x; i < e1; i += 256) it.x[i] = (float)it.x64[i];
+  } else {
+    for (int i = e0 + threadIdx.x; i < e1; i += 256) it.x64[i] = (double)it.x[i];
+  }
+  if constexpr (KIND == VK_UPDATE) {
+    __shared__ double sh[4];
+    const double s = block_sum<256>(d, sh);
+    if (threadIdx.x == 0) it.partials[SLOT_RR * MAXP_ITEM + tr.t] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batched scalar kernel: one block per item
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void scalar_batched_kernel(const ItemDesc* __restrict__ items,
+                                                             int kind, int mode) {
+  const ItemDesc& it = items[blockIdx.x];
+  Ctrl* c = it.ctrl;
+  if (!item_active(c, mode)) return;
+  __shared__ double sh[4];
+  const int done = c->done;
+  int slot, nb;
+  switch (kind) {
+    case SC_ALPHA: slot = SLOT_DELTA; nb = it.nb_blur; break;
+    case SC_RR: slot = SLOT_RR; nb = it.nb_vec; break;
+    case SC_BETA: slot = SLOT_RZ; nb = it.nb_gemm; break;
+    case SC_RHS: slot = SLOT_RHS; nb = it.nb_blur; break;
+    case SC_NORM: slot = SLOT_NORM; nb = it.nb_blur; break;
+    default: slot = SLOT_TRUE; nb = it.nb_blur64; break;
+  }
+  double s = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    s += it.partials[slot * MAXP_ITEM + i];
+    if (kind == SC_BETA) s2 += it.partials[SLOT_ZW * MAXP_ITEM + i];
+  }
+  const double S = block_sum<256>(s, sh);
+  const double S2 = block_sum<256>(s2, sh);
+  if (threadIdx.x != 0) return;
+  switch (kind) {
+    case SC_ALPHA:
+      c->delta = S;
+      if (!(S > 0.0) || !isfinite(S)) c->done = BREAKDOWN;
+      else c->alpha = c->rho / S;
+      break;
+    case SC_RR:
+      c->rr = S;
+      c->iter += 1;
+      if (c->solver == KP_CG) {
+        c->rho_prev = c->rho;
+        c->beta = S / c->rho;
+        c->rho = S;
+      }
+      set_scales(c, S);
+      if (!isfinite(S)) c->done = BREAKDOWN;
+      else if (S <= c->tol2 || S <= c->repl2) c->done = PENDING;
+      else if (c->iter >= c->maxit) c->done = MAXIT;
+      break;
+    case SC_BETA:
+      c->rz = S;
+      c->zw = S2;
+      if (!(S > 0.0) || !isfinite(S) || !isfinite(S2)) {
+        c->done = BREAKDOWN;
+      } else {
+        if (c->first) { c->beta = 0.0; c->first = 0; }
+        else if (c->solver == KP_PCG) c->beta = S / c->rho;
+        else c->beta = -S2 / c->delta;
+        c->rho = S;
+      }
+      break;
+    case SC_RHS:
+      c->gamma0sq = S;
+      c->rr = S;
+      c->rho = S;
+      c->tol2 = c->tol_rel2 * S;
+      c->repl2 = REPLACE_DROP * REPLACE_DROP * S;
+      set_scales(c, S);
+      if (!(S > 0.0) || !isfinite(S)) c->done = S == 0.0 ? CONVERGED : BREAKDOWN;
+      break;
+    case SC_TRUE:
+      c->true_rr = S;
+      c->rr = S;
+      c->repl2 = REPLACE_DROP * REPLACE_DROP * S;
+      set_scales(c, S);
+      if (c->solver == KP_CG) {
+        if (done == PENDING) c->beta = S / c->rho_prev;
+        c->rho = S;
+      }
+      if (!isfinite(S)) c->done = BREAKDOWN;
+      else if (S <= c->tol2) c->done = CONVERGED;
+      else if (c->iter >= c->maxit) c->done = MAXIT;
+      else { c->done = RUNNING; c->resume = 1; }
+      c->repl += 1;
+      break;
+    case SC_TRUE_INFO:
+      c->true_rr = S;
+      break;
+    case SC_NORM:
+      c->misfit2 = S;
+      break;
+  }
+}
+
+__global__ void clear_resume_kernel(const ItemDesc* __restrict__ items, int nitems) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nitems) items[i].ctrl->resume = 0;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct Batch {
+  int nitems = 0;
+  int mode = 0, solver = 0, prec = 0;
+  std::vector<ItemDesc> h_items;
+  ItemDesc* d_items = nullptr;
+  // tile tables (device) and their lengths
+  struct Group { int cfg; TileRef* tiles; int ntiles; size_t lds; };
+  std::vector<Group> blur_groups;            // FP32 blur, one per tile shape
+  TileRef *t_blur64 = nullptr, *t_gemm = nullptr, *t_vec = nullptr;
+  int n_blur64 = 0, n_gemm = 0, n_vec = 0;
+  size_t lds64 = 0;
+  void* mem = nullptr;                       // one allocation for everything
+  Ctrl* h_ctrl = nullptr;                    // pinned mirror of the items' Ctrl
+  Ctrl* d_ctrl = nullptr;
+  hipStream_t s = nullptr;
+};
+
+// Kernels needing more than 64 KB of LDS must opt in before their first
+// launch (done for every shape before graph capture starts).
+template <int TX, int TY, int RX, int RY, int KIND>
+static hipError_t ensure_lds(size_t lds) {
+  static size_t granted = 65536;
+  if (lds <= granted) return hipSuccess;
+  auto kern = blur_batched_kernel<TX, TY, RX, RY, KIND>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) granted = lds;
+  return e;
+}
+
+template <int TX, int TY, int RX, int RY, int KIND>
+static hipError_t launch_blur_b(const Batch& B, const TileRef* tiles, int ntiles, size_t lds,
+                                int mode) {
+  if (ntiles == 0) return hipSuccess;
+  hipError_t e = ensure_lds<TX, TY, RX, RY, KIND>(lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((blur_batched_kernel<TX, TY, RX, RY, KIND>), dim3(ntiles), dim3(TX * TY),
+                     lds, B.s, B.d_items, tiles, mode);
+  return hipGetLastError();
+}
+
+template <int KIND>
+static hipError_t ensure_groups(const Batch& B) {
+  for (const auto& g : B.blur_groups) {
+    hipError_t e;
+    switch (g.cfg) {
+      case 1: e = ensure_lds<KP_CFG1, KIND>(g.lds); break;
+      case 2: e = ensure_lds<KP_CFG2, KIND>(g.lds); break;
+      case 3: e = ensure_lds<KP_CFG3, KIND>(g.lds); break;
+      case 4: e = ensure_lds<KP_CFG4, KIND>(g.lds); break;
+      case 5: e = ensure_lds<KP_CFG5, KIND>(g.lds); break;
+      default: e = ensure_lds<KP_CFG0, KIND>(g.lds); break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int KIND>
+static hipError_t blur_groups_launch(const Batch& B, int mode) {
+  for (const auto& g : B.blur_groups) {
+    hipError_t e;
+    switch (g.cfg) {
+      case 1: e = launch_blur_b<KP_CFG1, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+      case 2: e = launch_blur_b<KP_CFG2, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+      case 3: e = launch_blur_b<KP_CFG3, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+      case 4: e = launch_blur_b<KP_CFG4, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+      case 5: e = launch_blur_b<KP_CFG5, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+      default: e = launch_blur_b<KP_CFG0, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int KIND>
+static hipError_t vec_launch(const Batch& B, int mode) {
+  if (B.n_vec == 0) return hipSuccess;
+  hipLaunchKernelGGL(vec_batched_kernel<KIND>, dim3(B.n_vec), dim3(256), 0, B.s, B.d_items,
+                     B.t_vec, mode);
+  return hipGetLastError();
+}
+
+static hipError_t scalar_launch(const Batch& B, int kind, int mode) {
+  hipLaunchKernelGGL(scalar_batched_kernel, dim3(B.nitems), dim3(256), 0, B.s, B.d_items, kind,
+                     mode);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t precond_b(const Batch& B, int mode) {
+  hipError_t e;
+  hipLaunchKernelGGL((gemm_batched_kernel<T, 1>), dim3(B.n_gemm), dim3(GT), 0, B.s, B.d_items,
+                     B.t_gemm, mode);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((gemm_batched_kernel<T, 2>), dim3(B.n_gemm), dim3(GT), 0, B.s, B.d_items,
+                     B.t_gemm, mode);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((gemm_batched_kernel<T, 3>), dim3(B.n_gemm), dim3(GT), 0, B.s, B.d_items,
+                     B.t_gemm, mode);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((gemm_batched_kernel<T, 4>), dim3(B.n_gemm), dim3(GT), 0, B.s, B.d_items,
+                     B.t_gemm, mode);
+  return hipGetLastError();
+}
+
+// z = M^{-1} r, r.z, beta, p = z + beta p (or the CG direction update)
+static hipError_t tail_b(const Batch& B, int mode) {
+  hipError_t e;
+  if (B.solver == KP_CG) return vec_launch<VK_PUPDATE_R>(B, mode);
+  e = B.prec == KP_P16 ? precond_b<_Float16>(B, mode) : precond_b<float>(B, mode);
+  if (e != hipSuccess) return e;
+  if ((e = scalar_launch(B, SC_BETA, mode)) != hipSuccess) return e;
+  return vec_launch<VK_PUPDATE_Z>(B, mode);
+}
+
+static hipError_t iteration_b(const Batch& B) {
+  hipError_t e;
+  if ((e = blur_groups_launch<BK_A>(B, RM_RUNNING)) != hipSuccess) return e;
+  if ((e = blur_groups_launch<BK_AT_NORMAL>(B, RM_RUNNING)) != hipSuccess) return e;
+  if ((e = scalar_launch(B, SC_ALPHA, RM_RUNNING)) != hipSuccess) return e;
+  if ((e = vec_launch<VK_UPDATE>(B, RM_RUNNING)) != hipSuccess) return e;
+  if ((e = scalar_launch(B, SC_RR, RM_RUNNING)) != hipSuccess) return e;
+  return tail_b(B, RM_RUNNING);
+}
+
+static hipError_t true_residual_b(const Batch& B, int mode, int kind) {
+  hipError_t e;
+  if (B.n_blur64 == 0) return hipSuccess;
+  auto k1 = blur_batched_kernel<KP_F64IN_CFG, BK_TRUE1>;
+  auto k2 = blur_batched_kernel<KP_F64IN_CFG, BK_TRUE2>;
+  if (B.lds64 > 65536) {
+    static size_t granted = 65536;
+    if (B.lds64 > granted) {
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(k1),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)B.lds64);
+      if (e != hipSuccess) return e;
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(k2),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)B.lds64);
+      if (e != hipSuccess) return e;
+      granted = B.lds64;
+    }
+  }
+  hipLaunchKernelGGL(k1, dim3(B.n_blur64), dim3(512), B.lds64, B.s, B.d_items, B.t_blur64, mode);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k2, dim3(B.n_blur64), dim3(512), B.lds64, B.s, B.d_items, B.t_blur64, mode);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return scalar_launch(B, kind, mode);
+}
+
+static int read_ctrls(Batch& B) {
+  if (hipMemcpyAsync(B.h_ctrl, B.d_ctrl, sizeof(Ctrl) * B.nitems, hipMemcpyDeviceToHost, B.s) !=
+          hipSuccess ||
+      hipStreamSynchronize(B.s) != hipSuccess)
+    return KP_ERR_HIP;
+  return KP_OK;
+}
+
+static void destroy_batch(Batch& B) {
+  if (B.s) hipStreamSynchronize(B.s);
+  if (B.mem) hipFree(B.mem);
+  if (B.h_ctrl) hipHostFree(B.h_ctrl);
+  if (B.s) hipStreamDestroy(B.s);
+  B.mem = nullptr;
+  B.h_ctrl = nullptr;
+  B.s = nullptr;
+}
+
+int batched_solve(Plan* const* plans, const float* const* b, const double* lambdas,
+                  const int* plan_of_item, int nitems, double tol, int maxit, int mode,
+                  float* const* x, kp_info_t* infos, hipStream_t user_stream) {
+  Batch B;
+  B.nitems = nitems;
+  B.mode = mode;
+  B.solver = mode & KP_SOLVER_MASK;
+  B.prec = mode & KP_PREC_MASK;
+  const bool eager = (mode & KP_BATCH_EAGER) != 0;
+
+  // ---- sizes of the batch allocation
+  size_t total = 0;
+  auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+  std::vector<size_t> off_item(nitems);
+  for (int i = 0; i < nitems; ++i) {
+    const size_t nn = (size_t)plans[plan_of_item[i]]->n * plans[plan_of_item[i]]->n;
+    off_item[i] = total;
+    total += align(nn * 4) * 5;              // r p q w z
+    total += align(nn * 8) * 3;              // x64 c64 y64
+    total += align(nn * 4) * 3;              // t1 t2 t3
+    total += align(sizeof(double) * NSLOTS * MAXP_ITEM);
+  }
+  const size_t off_ctrl = total;
+  total += align(sizeof(Ctrl) * nitems);
+  const size_t off_desc = total;
+  total += align(sizeof(ItemDesc) * nitems);
+
+  // ---- tile tables (host)
+  std::vector<std::vector<TileRef>> grp_tiles(NUM_BLUR_CFG);
+  std::vector<size_t> grp_lds(NUM_BLUR_CFG, 0);
+  std::vector<TileRef> t64, tg, tv;
+  B.h_items.resize(nitems);
+  for (int i = 0; i < nitems; ++i) {
+    const Plan& P = *plans[plan_of_item[i]];
+    ItemDesc& d = B.h_items[i];
+    std::memset(&d, 0, sizeof(d));
+    const int n = P.n, cfg = P.blur_cfg;
+    d.n = n; d.k = P.k; d.kq = P.kq; d.prec = B.prec;
+    int tw, th;
+    size_t lds;
+    switch (cfg) {
+      case 1: tw = 64; th = 16; lds = (size_t)(16 + P.k - 1) * lds_width<KP_CFG1, float>(P.kq) * 4; break;
+      case 2: tw = 64; th = 64; lds = (size_t)(64 + P.k - 1) * lds_width<KP_CFG2, float>(P.kq) * 4; break;
+      case 3: tw = 128; th = 16; lds = (size_t)(16 + P.k - 1) * lds_width<KP_CFG3, float>(P.kq) * 4; break;
+      case 4: tw = 64; th = 64; lds = (size_t)(64 + P.k - 1) * lds_width<KP_CFG4, float>(P.kq) * 4; break;
+      case 5: tw = 64; th = 32; lds = (size_t)(32 + P.k - 1) * lds_width<KP_CFG5, float>(P.kq) * 4; break;
+      default: tw = 64; th = 32; lds = (size_t)(32 + P.k - 1) * lds_width<KP_CFG0, float>(P.kq) * 4; break;
+    }
+    d.ntx_blur = (n + tw - 1) / tw;
+    d.nb_blur = d.ntx_blur * ((n + th - 1) / th);
+    for (int t = 0; t < d.nb_blur; ++t) grp_tiles[cfg].push_back(TileRef{i, t});
+    grp_lds[cfg] = grp_lds[cfg] > lds ? grp_lds[cfg] : lds;
+    d.ntx_blur64 = (n + 63) / 64;
+    d.nb_blur64 = d.ntx_blur64 * d.ntx_blur64;
+    for (int t = 0; t < d.nb_blur64; ++t) t64.push_back(TileRef{i, t});
+    const size_t l64 = (size_t)(64 + P.k - 1) * lds_width<KP_F64IN_CFG, double>(P.kq) * 8;
+    B.lds64 = B.lds64 > l64 ? B.lds64 : l64;
+    d.ntx_gemm = (n + BN - 1) / BN;
+    d.nb_gemm = d.ntx_gemm * ((n + BM - 1) / BM);
+    for (int t = 0; t < d.nb_gemm; ++t) tg.push_back(TileRef{i, t});
+    d.nb_vec = (n * n + VCH - 1) / VCH;
+    for (int t = 0; t < d.nb_vec; ++t) tv.push_back(TileRef{i, t});
+    if (d.nb_blur > MAXP_ITEM || d.nb_blur64 > MAXP_ITEM || d.nb_gemm > MAXP_ITEM ||
+        d.nb_vec > MAXP_ITEM)
+      return KP_ERR_UNSUPPORTED;
+  }
+  size_t ntab = t64.size() + tg.size() + tv.size();
+  for (auto& g : grp_tiles) ntab += g.size();
+  const size_t off_tab = total;
+  total += align(sizeof(TileRef) * ntab);
+
+  if (hipStreamCreateWithFlags(&B.s, hipStreamNonBlocking) != hipSuccess) return KP_ERR_HIP;
+  if (hipMalloc(&B.mem, total) != hipSuccess) {
+    destroy_batch(B);
+    return KP_ERR_HIP;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&B.h_ctrl), sizeof(Ctrl) * nitems) != hipSuccess) {
+    destroy_batch(B);
+    return KP_ERR_HIP;
+  }
+  char* base = reinterpret_cast<char*>(B.mem);
+  B.d_ctrl = reinterpret_cast<Ctrl*>(base + off_ctrl);
+  B.d_items = reinterpret_cast<ItemDesc*>(base + off_desc);
+
+  for (int i = 0; i < nitems; ++i) {
+    const Plan& P = *plans[plan_of_item[i]];
+    ItemDesc& d = B.h_items[i];
+    const size_t nn = (size_t)P.n * P.n;
+    char* p = base + off_item[i];
+    auto take = [&](size_t bytes) { char* q = p; p += align(bytes); return q; };
+    d.r = (float*)take(nn * 4); d.p = (float*)take(nn * 4); d.q = (float*)take(nn * 4);
+    d.w = (float*)take(nn * 4); d.z = (float*)take(nn * 4);
+    d.x64 = (double*)take(nn * 8); d.c64 = (double*)take(nn * 8); d.y64 = (double*)take(nn * 8);
+    d.t1 = take(nn * 4); d.t2 = take(nn * 4); d.t3 = take(nn * 4);
+    d.partials = (double*)take(sizeof(double) * NSLOTS * MAXP_ITEM);
+    d.ctrl = B.d_ctrl + i;
+    d.lam2 = lambdas[i] * lambdas[i];
+    d.lam2f = (float)d.lam2;
+    d.taps32 = P.taps32; d.taps32_flip = P.taps32_flip;
+    d.taps64 = P.taps64; d.taps64_flip = P.taps64_flip;
+    d.VcT16 = (const _Float16*)P.VcT16; d.Vc16 = (const _Float16*)P.Vc16;
+    d.Vr16 = (const _Float16*)P.Vr16; d.VrT16 = (const _Float16*)P.VrT16;
+    d.VcT32 = P.VcT32; d.Vc32 = P.Vc32; d.Vr32 = P.Vr32; d.VrT32 = P.VrT32;
+    d.sc2 = P.sc2; d.sr2 = P.sr2;
+    d.b = b[i];
+    d.x = x[i];
+    Ctrl& c = B.h_ctrl[i];
+    std::memset(&c, 0, sizeof(c));
+    c.tol_rel2 = tol * tol;
+    c.lam2 = d.lam2;
+    c.maxit = maxit;
+    c.solver = B.solver;
+    c.prec = B.prec;
+    c.first = 1;
+    c.done = RUNNING;
+    c.pscale = 1.0f;
+    c.zscale = (float)(1.0 / d.lam2);
+  }
+  // tables
+  std::vector<TileRef> all;
+  all.reserve(ntab);
+  size_t cur = 0;
+  TileRef* dtab = reinterpret_cast<TileRef*>(base + off_tab);
+  for (int c = 0; c < NUM_BLUR_CFG; ++c) {
+    if (grp_tiles[c].empty()) continue;
+    B.blur_groups.push_back(Batch::Group{c, dtab + cur, (int)grp_tiles[c].size(), grp_lds[c]});
+    all.insert(all.end(), grp_tiles[c].begin(), grp_tiles[c].end());
+    cur += grp_tiles[c].size();
+  }
+  B.t_blur64 = dtab + cur; B.n_blur64 = (int)t64.size();
+  all.insert(all.end(), t64.begin(), t64.end()); cur += t64.size();
+  B.t_gemm = dtab + cur; B.n_gemm = (int)tg.size();
+  all.insert(all.end(), tg.begin(), tg.end()); cur += tg.size();
+  B.t_vec = dtab + cur; B.n_vec = (int)tv.size();
+  all.insert(all.end(), tv.begin(), tv.end()); cur += tv.size();
+
+  int rc = KP_OK;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev = nullptr;
+#define BCHK(x)                                  \
+  do {                                           \
+    if ((x) != hipSuccess) { rc = KP_ERR_HIP; goto out; } \
+  } while (0)
+  // order after the caller's stream
+  BCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  BCHK(hipEventRecord(ev, user_stream));
+  BCHK(hipStreamWaitEvent(B.s, ev, 0));
+  BCHK(hipMemcpyAsync(B.d_items, B.h_items.data(), sizeof(ItemDesc) * nitems,
+                      hipMemcpyHostToDevice, B.s));
+  BCHK(hipMemcpyAsync(dtab, all.data(), sizeof(TileRef) * ntab, hipMemcpyHostToDevice, B.s));
+  BCHK(hipMemcpyAsync(B.d_ctrl, B.h_ctrl, sizeof(Ctrl) * nitems, hipMemcpyHostToDevice, B.s));
+  BCHK(hipStreamSynchronize(B.s));
+
+  // x_0 = 0, c = A^T b (FP64), ||c||, then the first direction
+  BCHK(vec_launch<VK_INIT>(B, RM_ALL));
+  BCHK(blur_groups_launch<BK_RHS>(B, RM_ALL));          // FP32 input, FP64 accumulation
+  BCHK(scalar_launch(B, SC_RHS, RM_ALL));
+  BCHK(tail_b(B, RM_RUNNING));
+  if ((rc = read_ctrls(B)) != KP_OK) goto out;
+
+  {
+    const int block = 8;
+    BCHK(ensure_groups<BK_A>(B));
+    BCHK(ensure_groups<BK_AT_NORMAL>(B));
+    if (!eager) {
+      BCHK(hipStreamBeginCapture(B.s, hipStreamCaptureModeThreadLocal));
+      for (int it = 0; it < block; ++it) {
+        if (iteration_b(B) != hipSuccess) {
+          hipStreamEndCapture(B.s, &graph);
+          rc = KP_ERR_HIP;
+          goto out;
+        }
+      }
+      BCHK(hipStreamEndCapture(B.s, &graph));
+      BCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    for (int guard = 0; guard < 1000000; ++guard) {
+      int running = 0, pending = 0;
+      for (int i = 0; i < nitems; ++i) {
+        running += B.h_ctrl[i].done == RUNNING;
+        pending += B.h_ctrl[i].done == PENDING;
+      }
+      if (!running && !pending) break;
+      if (pending) {
+        BCHK(true_residual_b(B, RM_PENDING, SC_TRUE));
+        BCHK(tail_b(B, RM_RESUME));
+        hipLaunchKernelGGL(clear_resume_kernel, dim3((nitems + 255) / 256), dim3(256), 0, B.s,
+                           B.d_items, nitems);
+        BCHK(hipGetLastError());
+      }
+      if (running || pending) {
+        if (eager) {
+          for (int it = 0; it < block; ++it) BCHK(iteration_b(B));
+        } else {
+          BCHK(hipGraphLaunch(exec, B.s));
+        }
+      }
+      if ((rc = read_ctrls(B)) != KP_OK) goto out;
+    }
+  }
+  // report: true residual of unconverged items, x in FP32, data misfit
+  BCHK(true_residual_b(B, RM_FINISHED, SC_TRUE_INFO));
+  BCHK(vec_launch<VK_TO_F32>(B, RM_ALL));
+  BCHK(blur_groups_launch<BK_MISFIT>(B, RM_ALL));
+  BCHK(scalar_launch(B, SC_NORM, RM_ALL));
+  if ((rc = read_ctrls(B)) != KP_OK) goto out;
+  for (int i = 0; i < nitems; ++i) {
+    const Ctrl& c = B.h_ctrl[i];
+    kp_info_t& inf = infos[i];
+    std::memset(&inf, 0, sizeof(inf));
+    inf.iters = c.iter;
+    inf.status = c.done == CONVERGED ? KP_OK : (c.done == BREAKDOWN ? KP_BREAKDOWN : KP_MAXIT);
+    if (c.done == MAXIT && c.true_rr <= c.tol2) inf.status = KP_OK;
+    inf.relres_rec = c.gamma0sq > 0 ? std::sqrt(c.rr / c.gamma0sq) : 0.0;
+    inf.relres_true = c.gamma0sq > 0 ? std::sqrt(c.true_rr / c.gamma0sq) : 0.0;
+    inf.lambda = lambdas[i];
+    inf.rhs_norm = std::sqrt(c.gamma0sq);
+    inf.misfit = std::sqrt(c.misfit2);
+    inf.replacements = c.repl;
+  }
+  BCHK(hipEventRecord(ev, B.s));
+  BCHK(hipStreamWaitEvent(user_stream, ev, 0));
+out:
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  if (ev) hipEventDestroy(ev);
+  destroy_batch(B);
+  return rc;
+#undef BCHK
+}
+
+}  // namespace kpcg

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "common.h"
 
@@ -362,8 +363,38 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
     info->relres_true = std::sqrt(true_rr / hc.gamma0sq);
     info->lambda = lambda;
     info->rhs_norm = std::sqrt(hc.gamma0sq);
+    info->misfit = 0.0;
   }
   return status;
+}
+
+int pcg_solve_batched(const kp_plan_t* plans, int nplans, const float* const* b,
+                      const double* lambdas, const int* plan_of_item, int nitems, double tol,
+                      int maxit, int mode, float* const* x, kp_info_t* infos, void* stream) {
+  if (!plans || nplans < 1 || !b || !lambdas || !plan_of_item || nitems < 1 || !x || !infos)
+    return KP_ERR_ARG;
+  if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 1) return KP_ERR_ARG;
+  if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM | KP_BATCH_EAGER)) != 0) return KP_ERR_ARG;
+  if ((mode & KP_SOLVER_MASK) == 3 || (mode & KP_PREC_MASK) == KP_PREC_MASK) return KP_ERR_ARG;
+  if ((mode & KP_WARM) || (mode & KP_PREC_MASK) == KP_P8) return KP_ERR_UNSUPPORTED;
+  std::vector<Plan*> ps(nplans);
+  for (int i = 0; i < nplans; ++i) {
+    if (!plans[i]) return KP_ERR_ARG;
+    ps[i] = &plans[i]->P;
+  }
+  for (int i = 0; i < nitems; ++i) {
+    if (plan_of_item[i] < 0 || plan_of_item[i] >= nplans) return KP_ERR_ARG;
+    if (!b[i] || !x[i] || !aligned16(b[i]) || !aligned16(x[i])) return KP_ERR_ARG;
+    if (!(lambdas[i] > 0.0) || !std::isfinite(lambdas[i])) return KP_ERR_ARG;
+  }
+  // every plan's own solve state must be idle: the batch only reads factors
+  const int rc = batched_solve(ps.data(), b, lambdas, plan_of_item, nitems, tol, maxit, mode, x,
+                               infos, reinterpret_cast<hipStream_t>(stream));
+  if (rc != KP_OK) return rc;
+  int worst = KP_OK;
+  for (int i = 0; i < nitems; ++i)
+    if (infos[i].status > worst) worst = infos[i].status;
+  return worst;
 }
 
 static int spectral_call(kp_plan_t plan, const float* b, const double* grid, int ngrid,

@@ -63,7 +63,10 @@ struct Ctrl {
   int solver;       // KP_CG / KP_PCG / KP_FPCG
   int prec;         // KP_P32 / KP_P16 / KP_P8
   int first;        // 1 while the initial z is being formed (beta = 0)
-  int nb[NSLOTS];   // number of partials last written to each slot
+  int resume;       // batched solves: the direction update is still owed after
+                    // a true-residual recomputation
+  int repl;         // true-residual recomputations that replaced r
+  double misfit2;   // ||A x - b||^2 (batched solves)
 };
 
 // ---------------------------------------------------------------------------
@@ -221,6 +224,10 @@ hipError_t launch_precond(const Plan& P, const float* r, float* z, const float* 
 hipError_t launch_precond_fp8(const Plan& P, const float* r, float* z, const float* w,
                               bool finalize, float lam2, hipStream_t s);
 bool fp8_supported_size(int n);   // the FP8 chain needs n to be a multiple of 128
+
+int batched_solve(Plan* const* plans, const float* const* b, const double* lambdas,
+                  const int* plan_of_item, int nitems, double tol, int maxit, int mode,
+                  float* const* x, kp_info_t* infos, hipStream_t user_stream);
 hipError_t launch_spectral_gemms(const Plan& P, const float* b, float* out, hipStream_t s);
 
 hipError_t launch_spectrum(const Plan& P, const float* b, hipStream_t s);

@@ -1,0 +1,267 @@
+// Shared body of the MFMA GEMM kernels of the preconditioner solve
+// (single-problem and batched launches): one workgroup computes one 64 x 64
+// tile of C = A * Bt^T, both operands K-contiguous, or of C = A * B with B
+// read from a row-major FP32 matrix, scaled and rounded while staged.
+// 4 waves in 2 x 2, each wave 32 x 32 as 2 x 2 MFMA 16x16 blocks; FP32 uses
+// v_mfma_f32_16x16x4_f32, FP16 v_mfma_f32_16x16x32_f16, both accumulating in
+// FP32.  Stages are double-buffered in LDS with the next stage's global loads
+// in flight during the MFMAs.
+#pragma once
+
+#include <type_traits>
+
+#include "common.h"
+
+namespace kpcg {
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+
+
+template <typename T> struct MT;
+template <> struct MT<float> {
+  static constexpr int BK = 32;     // k per LDS stage
+  static constexpr int VEC = 4;     // elements per 16-byte load
+  static constexpr int PAD = 4;
+  static constexpr int KM = 4;      // k per MFMA
+};
+template <> struct MT<_Float16> {
+  static constexpr int BK = 64;
+  static constexpr int VEC = 8;
+  static constexpr int PAD = 8;
+  static constexpr int KM = 32;
+};
+
+constexpr int GT = 256;  // threads per GEMM workgroup
+constexpr int BM = 64, BN = 64;
+
+template <typename T>
+using Tile = T[BM][MT<T>::BK + MT<T>::PAD];
+
+// ---------------------------------------------------------------------------
+// operand staging: global -> registers (issued one stage ahead) -> LDS
+// (s[row][k], k contiguous).  Each thread moves two 16-byte vectors per
+// K-contiguous operand and BK*BN/(4*GT) float4 of an FP32 row-major source.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct KContig {
+  static constexpr int BK = MT<T>::BK, VEC = MT<T>::VEC, PER_ROW = BK / VEC;
+  static constexpr int NV = BM * BK / VEC / GT;      // = 2
+  float4 reg[NV];
+  __device__ void load(const T* __restrict__ g, int row0, int k0, int n, bool vec_ok) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int id = threadIdx.x + GT * v;
+      const int row = id / PER_ROW, kc = (id % PER_ROW) * VEC;
+      const int gr = row0 + row, gk = k0 + kc;
+      if (vec_ok && gr < n && gk + VEC <= n) {
+        reg[v] = *reinterpret_cast<const float4*>(g + (size_t)gr * n + gk);
+      } else {
+        T tmp[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          tmp[e] = (gr < n && gk + e < n) ? g[(size_t)gr * n + gk + e] : T(0);
+        reg[v] = *reinterpret_cast<const float4*>(tmp);
+      }
+    }
+  }
+  __device__ void store(Tile<T>& s) const {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int id = threadIdx.x + GT * v;
+      const int row = id / PER_ROW, kc = (id % PER_ROW) * VEC;
+      *reinterpret_cast<float4*>(&s[row][kc]) = reg[v];
+    }
+  }
+};
+
+// B tile from a row-major FP32 matrix src[k][j] (contraction over its rows):
+// scaled and rounded to T, transposed into s[j][k].
+template <typename T>
+struct FromF32Rows {
+  static constexpr int BK = MT<T>::BK;
+  static constexpr int NV = BK * BN / 4 / GT;        // float4 per thread
+  static constexpr int TPR = BN / 4;                 // threads per k row
+  float4 reg[NV];
+  __device__ void load(const float* __restrict__ src, int j0, int k0, int n, bool vec_ok) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int id = threadIdx.x + GT * v;
+      const int k = id / TPR, jc = (id % TPR) * 4;
+      const int gk = k0 + k, gj = j0 + jc;
+      if (vec_ok && gk < n && gj + 4 <= n) {
+        reg[v] = *reinterpret_cast<const float4*>(src + (size_t)gk * n + gj);
+      } else {
+        float4 t;
+        t.x = (gk < n && gj + 0 < n) ? src[(size_t)gk * n + gj + 0] : 0.f;
+        t.y = (gk < n && gj + 1 < n) ? src[(size_t)gk * n + gj + 1] : 0.f;
+        t.z = (gk < n && gj + 2 < n) ? src[(size_t)gk * n + gj + 2] : 0.f;
+        t.w = (gk < n && gj + 3 < n) ? src[(size_t)gk * n + gj + 3] : 0.f;
+        reg[v] = t;
+      }
+    }
+  }
+  __device__ void store(Tile<T>& s, float scale) const {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int id = threadIdx.x + GT * v;
+      const int k = id / TPR, jc = (id % TPR) * 4;
+      s[jc + 0][k] = (T)(reg[v].x * scale);
+      s[jc + 1][k] = (T)(reg[v].y * scale);
+      s[jc + 2][k] = (T)(reg[v].z * scale);
+      s[jc + 3][k] = (T)(reg[v].w * scale);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// MFMA over one LDS stage: wave (wm, wn) owns a 32 x 32 block of C
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void mma_stage(const Tile<T>& sA, const Tile<T>& sB, float4_t (&acc)[2][2],
+                                 int wm, int wn, int lane) {
+  const int r16 = lane & 15, g = lane >> 4;
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int kk = 0; kk < MT<T>::BK; kk += 4) {
+      float a[2], b[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) a[mi] = sA[wm * 32 + mi * 16 + r16][kk + g];
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) b[ni] = sB[wn * 32 + ni * 16 + r16][kk + g];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < MT<T>::BK; kk += 32) {
+      half8_t a[2], b[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+        a[mi] = *reinterpret_cast<const half8_t*>(&sA[wm * 32 + mi * 16 + r16][kk + g * 8]);
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+        b[ni] = *reinterpret_cast<const half8_t*>(&sB[wn * 32 + ni * 16 + r16][kk + g * 8]);
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] =
+              __builtin_amdgcn_mfma_f32_16x16x32_f16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// epilogues: lane holds C[i0 + 4*(lane>>4) + v][j0 + (lane&15)], v = 0..3
+// ---------------------------------------------------------------------------
+template <typename T>
+struct GEpiStore {                       // row-major store
+  T* C; int n;
+  static constexpr bool kReduce = false;
+  __device__ void apply(int i, int j, float v, double&, double&) const {
+    C[(size_t)i * n + j] = (T)v;
+  }
+};
+
+template <typename T>
+struct GEpiSPrimeT {                     // T2^T[j][i] = S'[i][j] * T[i][j]
+  T* C; const float* sc2; const float* sr2; float lam2; int n;
+  static constexpr bool kReduce = false;
+  __device__ void apply(int i, int j, float v, double&, double&) const {
+    const float sp = lam2 / fmaf(sc2[i], sr2[j], lam2);
+    C[(size_t)j * n + i] = (T)(sp * v);
+  }
+};
+
+template <bool REDUCE>
+struct GEpiFinal {                       // z (already scaled) ; r.z ; z.w
+  float* z; const float* r; const float* w; int n;
+  static constexpr bool kReduce = REDUCE;
+  __device__ void apply(int i, int j, float v, double& d0, double& d1) const {
+    const size_t o = (size_t)i * n + j;
+    const float zv = v;
+    z[o] = zv;
+    if constexpr (REDUCE) {
+      d0 += (double)r[o] * zv;
+      d1 += (double)zv * w[o];
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// the GEMM kernel: C[n x n] = A[n x n] * Bt^T (or * B from FP32 rows)
+// ---------------------------------------------------------------------------
+template <typename T, bool B_FROM_F32, class Epi>
+__device__ inline void gemm_tile(const T* __restrict__ A, const void* __restrict__ Bsrc,
+                                 int n, int m0, int n0, Epi epi, float bscale, float oscale,
+                                 double* partial_out, int slot_stride) {
+  constexpr int BK = MT<T>::BK;
+  __shared__ __align__(16) Tile<T> sA[2];
+  __shared__ __align__(16) Tile<T> sB[2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const bool vec_ok = (n % 8) == 0;
+
+  float4_t acc[2][2];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+  KContig<T> la;
+  using BL = typename std::conditional<B_FROM_F32, FromF32Rows<T>, KContig<T>>::type;
+  BL lb;
+  auto load = [&](int k0) {
+    la.load(A, m0, k0, n, vec_ok);
+    if constexpr (B_FROM_F32)
+      lb.load(reinterpret_cast<const float*>(Bsrc), n0, k0, n, vec_ok);
+    else
+      lb.load(reinterpret_cast<const T*>(Bsrc), n0, k0, n, vec_ok);
+  };
+  auto store = [&](int buf) {
+    la.store(sA[buf]);
+    if constexpr (B_FROM_F32) lb.store(sB[buf], bscale);
+    else lb.store(sB[buf]);
+  };
+
+  const int nk = (n + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);       // next stage in flight during the MFMAs
+    mma_stage<T>(sA[cur], sB[cur], acc, wm, wn, lane);
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) {
+      const int j = n0 + wn * 32 + ni * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = m0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + v;
+        if (i < n && j < n) epi.apply(i, j, acc[mi][ni][v] * oscale, d0, d1);
+      }
+    }
+  if constexpr (Epi::kReduce) {
+    __shared__ double sh[GT / 64];
+    const double s0 = block_sum<GT>(d0, sh);
+    const double s1 = block_sum<GT>(d1, sh);
+    if (threadIdx.x == 0) {
+      partial_out[0] = s0;
+      partial_out[slot_stride] = s1;
+    }
+  }
+}
+
+}  // namespace kpcg

@@ -22,6 +22,7 @@ KP_ERR_ARG, KP_ERR_UNSUPPORTED, KP_ERR_HIP, KP_ERR_SOLVER, KP_ERR_WORKSPACE = -1
 KP_CG, KP_PCG, KP_FPCG = 0x000, 0x001, 0x002
 KP_P32, KP_P16, KP_P8 = 0x000, 0x010, 0x020
 KP_WARM = 0x100
+KP_BATCH_EAGER = 0x200
 KP_MAX_PSF = 63
 
 
@@ -35,7 +36,8 @@ class _Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("replacements", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("relres_rec", ctypes.c_double), ("relres_true", ctypes.c_double),
-                ("lambda_", ctypes.c_double), ("rhs_norm", ctypes.c_double)]
+                ("lambda_", ctypes.c_double), ("rhs_norm", ctypes.c_double),
+                ("misfit", ctypes.c_double)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -63,6 +65,9 @@ _SIGS = {
     "discrepancy_lambda": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, ctypes.c_double,
                                           ctypes.c_double, _VP, _VP, _VP]),
     "kp_destroy": (ctypes.c_int, [_VP]),
+    "pcg_solve_batched": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP, ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, _VP,
+                                         _VP, _VP]),
     "kp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "kp_blur": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
     "kp_normal_fp64": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP]),
@@ -132,6 +137,7 @@ class SolveInfo:
     relres_true: float
     lam: float
     rhs_norm: float
+    misfit: float = 0.0
 
 
 def workspace_size(n: int, k: int) -> int:
@@ -205,7 +211,7 @@ class Plan:
         if st < 0 or (raise_on_fail and st not in (KP_OK, KP_MAXIT)):
             raise KPError(st, "pcg_solve")
         return x, SolveInfo(info.iters, st, info.replacements, info.relres_rec,
-                            info.relres_true, info.lambda_, info.rhs_norm)
+                            info.relres_true, info.lambda_, info.rhs_norm, info.misfit)
 
     def gcv(self, b, grid, omega: float = 1.0, stream=None):
         bp = _dev_image(b, self.n, "b")
@@ -261,3 +267,32 @@ class Plan:
         _check(load().kp_precond(self._h, _dev_image(r, self.n, "r"), float(lam), int(mode),
                                  _dev_image(z, self.n, "z"), _stream(stream)), "kp_precond")
         return z
+
+
+def solve_batched(plans, bs, lambdas, plan_of_item, tol: float = 1e-6, maxit: int = 1000,
+                  mode: int = KP_FPCG | KP_P16, xs=None, stream=None):
+    """pcg_solve_batched: item i solves with plans[plan_of_item[i]], data bs[i]
+    (CUDA float32 n_i x n_i), parameter lambdas[i].  Returns (xs, infos, status)."""
+    import torch
+    lib = load()
+    nitems = len(bs)
+    if not (len(lambdas) == nitems == len(plan_of_item)):
+        raise ValueError("bs, lambdas and plan_of_item must have the same length")
+    if xs is None:
+        xs = [torch.empty_like(b) for b in bs]
+    hp = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    bp = (ctypes.c_void_p * nitems)(*[_dev_image(b, plans[plan_of_item[i]].n, "b").value
+                                      for i, b in enumerate(bs)])
+    xp = (ctypes.c_void_p * nitems)(*[_dev_image(x, plans[plan_of_item[i]].n, "x").value
+                                      for i, x in enumerate(xs)])
+    lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+    poi = np.ascontiguousarray(plan_of_item, dtype=np.int32)
+    infos = (_Info * nitems)()
+    st = lib.pcg_solve_batched(hp, len(plans), bp, lam.ctypes.data_as(ctypes.c_void_p),
+                               poi.ctypes.data_as(ctypes.c_void_p), nitems, float(tol),
+                               int(maxit), int(mode), xp, infos, _stream(stream))
+    if st < 0:
+        raise KPError(st, "pcg_solve_batched")
+    out = [SolveInfo(i.iters, i.status, i.replacements, i.relres_rec, i.relres_true, i.lambda_,
+                     i.rhs_norm, i.misfit) for i in infos]
+    return xs, out, st

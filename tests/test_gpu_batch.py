@@ -1,0 +1,150 @@
+"""Batched solves (pcg_solve_batched) against the FP64 oracle: uneven image
+sizes and PSF supports, several lambda per problem, one set of launches."""
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import operator as O
+from oracle import solvers as SV
+from tests.gpu_util import rel, require_gpu, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+_CACHE = {}
+
+
+def _small_batch():
+    """Five problems, uneven sizes (one ragged), two lambda each."""
+    if "probs" not in _CACHE:
+        specs = [(64, 15, "g"), (100, 9, "m"), (128, 31, "m"), (192, 21, "g"), (256, 31, "m")]
+        probs = []
+        for idx, (n, k, kind) in enumerate(specs):
+            rng = np.random.default_rng(500 + idx)
+            psf = (S.psf_gaussian(k, 1.5 + idx * 0.5, 2.5, 0.3 * idx) if kind == "g"
+                   else S.psf_moffat_motion(k, 3.0 + idx, 2.5, 3.0 + idx, 0.5 * idx))
+            probs.append(S.make_problem(n, psf, rng, 0.01 + 0.005 * idx, None, 500 + idx,
+                                        f"batch{idx}"))
+        lams = [0.01, 0.05]
+        items = [(p, lam) for p in range(len(probs)) for lam in lams]
+        _CACHE["probs"] = probs
+        _CACHE["items"] = items
+    return _CACHE["probs"], _CACHE["items"]
+
+
+def _xlam(probs, p, lam):
+    key = (p, lam)
+    if key not in _CACHE:
+        prob = probs[p]
+        _CACHE[key] = SV.x_lambda(prob.psf, prob.b.astype(np.float64), lam)
+    return _CACHE[key]
+
+
+def _run(plans, probs, items, mode, tol, maxit=500):
+    from paper_2311_15393_amd import solve_batched
+    bs = [to_dev(probs[p].b) for p, _ in items]
+    lams = [lam for _, lam in items]
+    poi = [p for p, _ in items]
+    xs, infos, st = solve_batched(plans, bs, lams, poi, tol=tol, maxit=maxit, mode=mode)
+    return [to_host(x) for x in xs], infos, st
+
+
+@pytest.mark.parametrize("mode_name,bar,tol", [("fpcg16", 1e-4, 1e-8), ("pcg32", 1e-5, 1e-9),
+                                               ("cg", 1e-4, 1e-8)])
+def test_batched_items_match_oracle(mode_name, bar, tol):
+    require_gpu()
+    from paper_2311_15393_amd import KP_CG, KP_FPCG, KP_OK, KP_P16, KP_P32, KP_PCG, Plan
+    mode = {"fpcg16": KP_FPCG | KP_P16, "pcg32": KP_PCG | KP_P32, "cg": KP_CG}[mode_name]
+    probs, items = _small_batch()
+    plans = [Plan(p.psf, p.n) for p in probs]
+    say(f"batched {mode_name}: {len(items)} items")
+    xs, infos, st = _run(plans, probs, items, mode, tol, maxit=2000)
+    for (p, lam), x, inf in zip(items, xs, infos):
+        err = rel(x, _xlam(probs, p, lam))
+        say(f"  n={probs[p].n} k={probs[p].k} lam={lam} iters={inf.iters} "
+            f"status={inf.status} err={err:.2e}")
+        assert inf.status == KP_OK and inf.relres_true <= tol
+        assert err <= bar
+    assert st == KP_OK
+    for pl in plans:
+        pl.close()
+
+
+def test_graph_replay_matches_eager_launches():
+    """The captured iteration block, replayed with host synchronisation and
+    true-residual work between replays, gives bit-identical results to
+    launching every kernel eagerly (all reductions are deterministic)."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_BATCH_EAGER, KP_FPCG, KP_P16, Plan
+    probs, items = _small_batch()
+    plans = [Plan(p.psf, p.n) for p in probs]
+    mode = KP_FPCG | KP_P16
+    xg, ig, _ = _run(plans, probs, items, mode, 1e-8)
+    xe, ie, _ = _run(plans, probs, items, mode | KP_BATCH_EAGER, 1e-8)
+    for a, b, i1, i2 in zip(xg, xe, ig, ie):
+        assert i1.iters == i2.iters and i1.replacements == i2.replacements
+        assert np.array_equal(a, b)
+    assert max(i.iters for i in ig) > 8          # more than one replay happened
+    for pl in plans:
+        pl.close()
+
+
+def test_batched_misfit_report():
+    """infos[i].misfit = ||A x_i - b_i|| (FP64-accumulated blur of the result)."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_FPCG, KP_P16, Plan
+    probs, items = _small_batch()
+    plans = [Plan(p.psf, p.n) for p in probs]
+    xs, infos, _ = _run(plans, probs, items, KP_FPCG | KP_P16, 1e-7)
+    for (p, lam), x, inf in zip(items, xs, infos):
+        prob = probs[p]
+        ref = float(np.linalg.norm(O.blur(prob.psf, x.astype(np.float32).astype(np.float64))
+                                   - prob.b.astype(np.float64)))
+        assert abs(inf.misfit - ref) <= 1e-6 * ref
+    for pl in plans:
+        pl.close()
+
+
+def test_batched_rejects_bad_arguments():
+    require_gpu()
+    import torch
+    from paper_2311_15393_amd import (KP_ERR_ARG, KP_ERR_UNSUPPORTED, KP_FPCG, KP_P8, KP_P16,
+                                      KPError, Plan, solve_batched)
+    probs, items = _small_batch()
+    plan = Plan(probs[0].psf, probs[0].n)
+    b = to_dev(probs[0].b)
+    with pytest.raises(KPError) as ei:
+        solve_batched([plan], [b], [-1.0], [0], mode=KP_FPCG | KP_P16)
+    assert ei.value.status == KP_ERR_ARG
+    with pytest.raises(KPError) as ei:
+        solve_batched([plan], [b], [0.01], [0], mode=KP_FPCG | KP_P8)
+    assert ei.value.status == KP_ERR_UNSUPPORTED
+    plan.close()
+
+
+def test_uneven_batch_sample_full_sizes():
+    """Four problems of the uneven-size workload (sizes from {128,...,1024},
+    supports 15..63, Gaussian or Moffat), four lambda around each problem's
+    KP-GCV choice: every item converges and meets the FP16 bar."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, Plan
+    probs = [S.batch_problem(i) for i in range(4)]
+    plans = [Plan(p.psf, p.n) for p in probs]
+    grid = S.lambda_grid()
+    items = []
+    for pi, (prob, plan) in enumerate(zip(probs, plans)):
+        lam_g, _ = plan.gcv(to_dev(prob.b), grid)
+        for f in (0.3, 1.0, 3.0):
+            items.append((pi, float(np.clip(lam_g * f, 1e-4, 1.0))))
+    say(f"uneven sample: sizes {[p.n for p in probs]} supports {[p.k for p in probs]}")
+    xs, infos, st = _run(plans, probs, items, KP_FPCG | KP_P16, 1e-7, maxit=1000)
+    checked = 0
+    for (p, lam), x, inf in zip(items, xs, infos):
+        assert inf.status == KP_OK, (p, lam, inf)
+        if lam == items[3 * p + 1][1] and probs[p].n <= 512:
+            err = rel(x, SV.x_lambda(probs[p].psf, probs[p].b.astype(np.float64), lam))
+            say(f"  n={probs[p].n} k={probs[p].k} lam={lam:.3g} iters={inf.iters} err={err:.2e}")
+            assert err <= 1e-4
+            checked += 1
+    assert checked >= 1
+    for pl in plans:
+        pl.close()
