@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="skip the oracle parts (for profiler runs)")
+    ap.add_argument("--batch", type=int, default=0, metavar="P",
+                    help="also run the uneven batched workload with P problems x 16 lambda")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the solve of one image fits one MI355X); "
@@ -211,6 +213,8 @@ def main():
         }
         log(f"[bench] cpu oracle solve {cpu_s:.2f}s iters={out.iters}")
 
+    batch = run_batch(args.batch, dev) if args.batch else None
+
     head = results["fp16_kp_fpcg"]
     line = {
         "metric": METRIC,
@@ -235,6 +239,7 @@ def main():
             "kp_rel_error": pinfo["kp_rel_error"],
             "blur_tile_config": pinfo["blur_config"],
             "precond_fp16_chain_us": prec_ms * 1e3,
+            "batched": batch,
         },
         "roofline": {
             "bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VALU_PEAK / 1e12,
@@ -246,6 +251,77 @@ def main():
     }
     print(json.dumps(line), flush=True)
     plan.close()
+
+
+def run_batch(nprob: int, dev):
+    """Uneven batch: problems of sizes {128,...,1024}, supports 15..63, each
+    with 16 lambda values log-spaced over lambda_gcv * 10^[-1.5, 1.5] (KP-GCV
+    on the 32-point grid picks lambda_gcv), all solved by one batched FP16
+    FPCG call; the sweep is scored by KP-GCV and by the discrepancy principle
+    on the solves' actual misfits."""
+    import torch
+    import synthetic as S
+    from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, Plan, solve_batched
+
+    t0 = time.time()
+    probs = [S.batch_problem(i) for i in range(nprob)]
+    gen_s = time.time() - t0
+    t0 = time.time()
+    plans = [Plan(p.psf, p.n) for p in probs]
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    grid = S.lambda_grid()
+    bs_dev = [torch.from_numpy(p.b).to(dev) for p in probs]
+    items, sweeps = [], []
+    for pi, (p, plan) in enumerate(zip(probs, plans)):
+        lam_g, _ = plan.gcv(bs_dev[pi], grid)
+        sweep = np.clip(lam_g * 10.0 ** np.linspace(-1.5, 1.5, 16), 1e-4, 1.0)
+        sweeps.append(sweep)
+        items += [(pi, float(l)) for l in sweep]
+    bs = [bs_dev[pi] for pi, _ in items]
+    lams = [l for _, l in items]
+    poi = [pi for pi, _ in items]
+    log(f"[bench] batch: {nprob} problems x 16 lambda = {len(items)} solves, "
+        f"{sum(p.n * p.n for p in probs) * 16 / 1e6:.1f} Mpx; setup {setup_s:.1f}s")
+    xs = [torch.empty_like(b) for b in bs]
+    solve_batched(plans, bs, lams, poi, tol=1e-6, maxit=1000, mode=KP_FPCG | KP_P16, xs=xs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, infos, st = solve_batched(plans, bs, lams, poi, tol=1e-6, maxit=1000,
+                                  mode=KP_FPCG | KP_P16, xs=xs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    iters = np.array([i.iters for i in infos])
+    ok = sum(i.status == KP_OK for i in infos)
+    # score each problem's sweep: KP-GCV (16 points) and discrepancy on misfits
+    errs_gcv, errs_dp = [], []
+    for pi, (p, plan) in enumerate(zip(probs, plans)):
+        sweep = sweeps[pi]
+        _, g = plan.gcv(bs_dev[pi], sweep)
+        idx = [k for k, (q, _) in enumerate(items) if q == pi]
+        mis = np.array([infos[k].misfit for k in idx])
+        d = mis ** 2 - p.noise_norm ** 2
+        below = np.nonzero(d <= 0)[0]
+        k_dp = int(below[-1]) if below.size else 0
+        k_gcv = int(np.argmin(g))
+        xt = p.x_true
+        for kk, store in ((k_gcv, errs_gcv), (k_dp, errs_dp)):
+            x = xs[idx[kk]].cpu().numpy().astype(np.float64)
+            store.append(float(np.linalg.norm(x - xt) / np.linalg.norm(xt)))
+    out = {
+        "problems": nprob, "solves": len(items), "wall_s": wall,
+        "solves_per_s": len(items) / wall, "converged": ok,
+        "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
+        "setup_s_total": setup_s, "tol": 1e-6, "mode": "fp16_kp_fpcg",
+        "err_vs_true_gcv_pick_mean": float(np.mean(errs_gcv)),
+        "err_vs_true_dp_pick_mean": float(np.mean(errs_dp)),
+    }
+    log(f"[bench] batch: {wall:.3f}s for {len(items)} solves ({len(items) / wall:.1f}/s), "
+        f"converged {ok}, iters mean {iters.mean():.1f} max {iters.max()}; "
+        f"error vs x_true at GCV pick {np.mean(errs_gcv):.3f}, DP pick {np.mean(errs_dp):.3f}")
+    for pl in plans:
+        pl.close()
+    return out
 
 
 if __name__ == "__main__":

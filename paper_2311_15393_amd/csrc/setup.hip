@@ -9,13 +9,16 @@
 // minimised by the leading singular triple (s1, u1, v1) of
 // W^{1/2} P W^{1/2}: c = sqrt(s1) u1 / sqrt(w), a = sqrt(s1) v1 / sqrt(w).
 // A_c = T(c) (acts on the row index), A_r = T(a), T(f)[i][i'] = f[h+i-i'].
-// Both factors get FP64 SVDs (rocSOLVER gesvd; the paper also computes them
-// in double), after which V_c, V_r are stored in FP32 / FP16 / FP8 with
-// block exponents, U_c, U_r in FP32 and the singular values in FP64.
+// Both factors get FP64 SVDs (the paper also computes them in double):
+// rocSOLVER's symmetric eigensolver when the profile is symmetric (every
+// point-symmetric PSF), its general SVD otherwise.  V_c, V_r are then stored
+// in FP32 / FP16 / FP8 with block exponents, U_c, U_r in FP32 and the
+// singular values in FP64.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "common.h"
@@ -88,6 +91,38 @@ __global__ void factors_kernel(const double* __restrict__ Vt, const double* __re
   UT32[idx] = (float)U[idx];
 }
 
+// Symmetric factors (point-symmetric PSFs give symmetric Toeplitz factors):
+// from the eigendecomposition T = Q diag(w) Q^T, the SVD has s_a = |w_p(a)|
+// in descending order, V(:,a) = Q(:,p(a)), U(:,a) = sign(w_p(a)) Q(:,p(a)).
+// rank_kernel computes the order p (ties by index), gather_eig_kernel writes
+// s, Vt (column-major, Vt(a,i) = V(i,a)) and U (column-major) in the layout
+// the general SVD path produces.
+__global__ void rank_kernel(const double* __restrict__ w, int n, int* __restrict__ perm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double ai = fabs(w[i]);
+  int r = 0;
+  for (int j = 0; j < n; ++j) {
+    const double aj = fabs(w[j]);
+    r += (aj > ai) || (aj == ai && j < i);
+  }
+  perm[r] = i;
+}
+
+__global__ void gather_eig_kernel(const double* __restrict__ Q, const double* __restrict__ w,
+                                  const int* __restrict__ perm, int n, double* __restrict__ sig,
+                                  double* __restrict__ Vt, double* __restrict__ U) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * n) return;
+  const int i = (int)(idx % n), a = (int)(idx / n);      // element (i, a)
+  const int p = perm[a];
+  const double q = Q[i + (size_t)p * n];
+  const double sg = w[p] < 0.0 ? -1.0 : 1.0;
+  Vt[a + (size_t)i * n] = q;
+  U[i + (size_t)a * n] = sg * q;
+  if (i == 0) sig[a] = fabs(w[p]);
+}
+
 __global__ void sigma_kernel(const double* __restrict__ s, int n, float* __restrict__ s2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) s2[i] = (float)(s[i] * s[i]);
@@ -119,7 +154,7 @@ __global__ void taps_kernel(const double* __restrict__ psf, int K, int KQ,
 // ---------------------------------------------------------------------------
 __device__ inline int e8m0_for_amax(float amax) {
   // smallest e with amax * 2^-e <= 448 ; returned biased by 127
-  if (!(amax > 0.0f)) return 0;            // 2^-127: any exponent works for a zero block
+  if (!(amax > 0.0f)) return 1;            // any exponent works for an all-zero block
   int e;
   const float m = frexpf(amax / 448.0f, &e);   // amax/448 = m 2^e, m in [0.5,1)
   if (m == 0.5f) e -= 1;
@@ -161,6 +196,13 @@ __global__ void quant_rows_e4m3_kernel(const float* __restrict__ src, int n,
     if ((x) != hipSuccess) { rc = KP_ERR_HIP; goto done; }           \
   } while (0)
 
+// KPCG_GENERAL_SVD=1 forces the general SVD for every factor (used to check
+// that both paths give the same preconditioner).
+static bool force_general_svd() {
+  const char* v = std::getenv("KPCG_GENERAL_SVD");
+  return v != nullptr && v[0] == '1';
+}
+
 int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
   const int n = P.n, K = P.k;
   const size_t nn = (size_t)n * n;
@@ -169,6 +211,9 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
   double *dpsf = nullptr, *pw = nullptr, *spsf = nullptr, *upsf = nullptr, *vpsf = nullptr,
          *e = nullptr, *prof = nullptr, *T = nullptr, *U = nullptr, *Vt = nullptr;
   rocblas_int* info = nullptr;
+  double* wv = nullptr;
+  int* perm = nullptr;
+  bool symmetric[2] = {false, false};
   std::vector<double> hs(K);
   rocblas_int hinfo = 0;
   const int nthr = 256;
@@ -185,6 +230,8 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
   HCHK(hipMalloc(&U, sizeof(double) * nn));
   HCHK(hipMalloc(&Vt, sizeof(double) * nn));
   HCHK(hipMalloc(&info, sizeof(rocblas_int)));
+  HCHK(hipMalloc(&wv, sizeof(double) * n));
+  HCHK(hipMalloc(&perm, sizeof(int) * n));
   HCHK(hipMemcpyAsync(dpsf, psf_host, sizeof(double) * K * K, hipMemcpyHostToDevice, s));
 
   SCHK(rocblas_create_handle(&handle));
@@ -210,6 +257,20 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
   HCHK(hipGetLastError());
 
   {
+    // symmetric profiles give symmetric Toeplitz factors: use the
+    // (much faster) symmetric eigensolver for them
+    std::vector<double> hp(2 * K);
+    HCHK(hipMemcpyAsync(hp.data(), prof, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s));
+    HCHK(hipStreamSynchronize(s));
+    for (int f = 0; f < 2; ++f) {
+      double mx = 0.0, asym = 0.0;
+      for (int k = 0; k < K; ++k) mx = std::fmax(mx, std::fabs(hp[f * K + k]));
+      for (int k = 0; k < K; ++k)
+        asym = std::fmax(asym, std::fabs(hp[f * K + k] - hp[f * K + K - 1 - k]));
+      symmetric[f] = asym <= 1e-13 * mx && !force_general_svd();
+    }
+  }
+  {
     double tot = 0.0, rest = 0.0;
     for (int i = 0; i < K; ++i) tot += hs[i] * hs[i];
     for (int i = 1; i < K; ++i) rest += hs[i] * hs[i];
@@ -226,8 +287,17 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
     double* sig = f == 0 ? P.sc : P.sr;
     hipLaunchKernelGGL(toeplitz_kernel, dim3(gnn), dim3(nthr), 0, s, prof_f, K, n, T);
     HCHK(hipGetLastError());
-    SCHK(rocsolver_dgesvd(handle, rocblas_svect_all, rocblas_svect_all, n, n, T, n, sig, U, n,
-                          Vt, n, e, rocblas_outofplace, info));
+    if (symmetric[f]) {
+      SCHK(rocsolver_dsyevd(handle, rocblas_evect_original, rocblas_fill_upper, n, T, n, wv, e,
+                            info));
+      hipLaunchKernelGGL(rank_kernel, dim3((n + 255) / 256), dim3(256), 0, s, wv, n, perm);
+      hipLaunchKernelGGL(gather_eig_kernel, dim3(gnn), dim3(nthr), 0, s, T, wv, perm, n, sig, Vt,
+                         U);
+      HCHK(hipGetLastError());
+    } else {
+      SCHK(rocsolver_dgesvd(handle, rocblas_svect_all, rocblas_svect_all, n, n, T, n, sig, U, n,
+                            Vt, n, e, rocblas_outofplace, info));
+    }
     HCHK(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
     HCHK(hipStreamSynchronize(s));
     if (hinfo != 0) { rc = KP_ERR_SOLVER; goto done; }
@@ -274,7 +344,8 @@ done:
   hipStreamSynchronize(s);
   if (handle) rocblas_destroy_handle(handle);
   hipFree(dpsf); hipFree(pw); hipFree(spsf); hipFree(upsf); hipFree(vpsf); hipFree(e);
-  hipFree(prof); hipFree(T); hipFree(U); hipFree(Vt); hipFree(info);
+  hipFree(prof); hipFree(T); hipFree(U); hipFree(Vt); hipFree(info); hipFree(wv);
+  hipFree(perm);
   return rc;
 }
 

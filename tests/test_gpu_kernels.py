@@ -74,15 +74,16 @@ def test_normal_fp64_matches_oracle(n, k):
     assert np.all(np.abs(got - ref) <= 4 * k * k * u64 * absref + 1e-300)
 
 
-@pytest.mark.parametrize("n,k", [(64, 15), (100, 31), (256, 31)])
-def test_factor_svd_matches_oracle(n, k):
+@pytest.mark.parametrize("n,k,kind", [(64, 15, "moffat"), (100, 31, "moffat"),
+                                      (256, 31, "moffat"), (96, 15, "rand"), (200, 31, "rand")])
+def test_factor_svd_matches_oracle(n, k, kind):
     """Singular values of the Kronecker factors (device FP64 SVD) and the
     quality measure of Table 1 match the oracle; V is compared through the
     sign-free projector V diag(s^2) V^T = A_c^T A_c."""
     require_gpu()
     from paper_2311_15393_amd import Plan
-    say(f"factors n={n} k={k}")
-    psf = _psf("moffat", k, 5)
+    say(f"factors n={n} k={k} {kind}")
+    psf = _psf(kind, k, 5)
     kp = KP.kp_svd(psf, n)
     with Plan(psf, n) as plan:
         info = plan.query()
@@ -197,3 +198,22 @@ def test_fp8_rejects_unsupported_size():
         with pytest.raises(KPError) as ei:
             plan.solve(r, 0.01, mode=KP_FPCG | KP_P8)
         assert ei.value.status == KP_ERR_UNSUPPORTED
+
+
+def test_symmetric_and_general_factor_paths_agree(monkeypatch):
+    """Point-symmetric PSFs take the symmetric eigensolver path; forcing the
+    general SVD must give the same preconditioner (V and s are unique up to
+    signs and rotations inside repeated singular values, M^{-1} is not)."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_P32, Plan
+    n, k, lam = 128, 31, 0.01
+    psf = _psf("moffat", k, 31)
+    r = to_dev(S.random_image(np.random.default_rng(3), n))
+    outs = []
+    for general in ("0", "1"):
+        monkeypatch.setenv("KPCG_GENERAL_SVD", general)
+        with Plan(psf, n) as plan:
+            z = torch.empty((n, n), dtype=torch.float32, device="cuda")
+            plan.precond(r, lam, KP_P32, z)
+            outs.append(to_host(z))
+    assert rel(outs[0], outs[1]) < 1e-5
