@@ -30,6 +30,20 @@ sys.path.insert(0, ROOT)
 METRIC = "1024^2 deblur PCG solves/s at rel err <=1e-4 vs FP64; FP16-KP vs FP32-KP vs none"
 HBM_PEAK = 8.0e12
 FP32_VALU_PEAK = 157.3e12
+# solver modes and their iteration caps
+MODES = {"fp16_kp_fpcg": 200, "fp32_kp_pcg": 200, "fp8_kp_fpcg": 400, "none_cg": 3000}
+# Bytes of the plain copy launched by --profile-only to calibrate the HBM
+# counters (FETCH_SIZE / WRITE_SIZE): 64 Mi floats read, 64 Mi written.
+COPY_CALIB_FLOATS = 64 * 1024 * 1024
+
+# HBM traffic of one forward-blur launch at the 1024^2, K=63 workload, from
+# two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
+# `python bench.py --profile-only --modes fp16_kp_fpcg --steps 2 --warmup 1`,
+# each divided by the same counter's reading per byte of the calibration copy.
+# `sources_sha256` is the hash of the blur sources the counters were taken
+# on; when the sources differ the figure no longer describes the kernel and
+# is reported as null.
+BLUR_TRAFFIC = None
 
 
 def log(*a):
@@ -43,6 +57,23 @@ def blur_flops(n: int, k: int) -> float:
     h = (k - 1) // 2
     t = n * k - h * (h + 1)
     return 2.0 * float(t) * float(t)
+
+
+def blur_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("blur_core.h", "blur.hip"):
+        with open(os.path.join(ROOT, "paper_2311_15393_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def blur_traffic():
+    """Counter-measured HBM bytes per forward-blur launch, or None when no
+    measurement exists for the current blur sources."""
+    if BLUR_TRAFFIC is None or BLUR_TRAFFIC["sources_sha256"] != blur_sources_sha256():
+        return None
+    return BLUR_TRAFFIC["bytes_per_launch"]
 
 
 def cpu_threads() -> int:
@@ -64,6 +95,8 @@ def main():
                     help="skip the oracle parts (for profiler runs)")
     ap.add_argument("--batch", type=int, default=0, metavar="P",
                     help="also run the uneven batched workload with P problems x 16 lambda")
+    ap.add_argument("--modes", default=",".join(MODES),
+                    help="comma list of solver modes to run (the first FP16 one is the headline)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the solve of one image fits one MI355X); "
@@ -161,12 +194,11 @@ def main():
         dt = time.perf_counter() - t0
         return dt / steps * 1e3, iters
 
-    modes = {
-        "fp16_kp_fpcg": (KP_FPCG | KP_P16, 200),
-        "fp32_kp_pcg": (KP_PCG | KP_P32, 200),
-        "fp8_kp_fpcg": (KP_FPCG | KP_P8, 400),
-        "none_cg": (KP_CG, 3000),
-    }
+    mode_bits = {"fp16_kp_fpcg": KP_FPCG | KP_P16, "fp32_kp_pcg": KP_PCG | KP_P32,
+                 "fp8_kp_fpcg": KP_FPCG | KP_P8, "none_cg": KP_CG}
+    chosen = [m for m in args.modes.split(",") if m]
+    assert "fp16_kp_fpcg" in chosen and all(m in MODES for m in chosen), args.modes
+    modes = {m: (mode_bits[m], MODES[m]) for m in chosen}
     results = {}
     for name, (mode, maxit) in modes.items():
         tol, info, err = pick_tol(mode, maxit)
@@ -191,6 +223,15 @@ def main():
     log(f"[bench] blur kernel {blur_ms * 1e3:.1f} us ({achieved / 1e12:.2f} TFLOP/s); "
         f"FP16 preconditioner chain {prec_ms * 1e3:.1f} us "
         f"({prec_flops / (prec_ms * 1e-3) / 1e12:.1f} TFLOP/s)")
+
+    if args.profile_only:
+        # plain copy of known size for the counter calibration
+        src = torch.ones(COPY_CALIB_FLOATS, device=dev, dtype=torch.float32)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu_baseline = None
     if not args.profile_only and not args.no_cpu_baseline:
@@ -243,7 +284,7 @@ def main():
         },
         "roofline": {
             "bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VALU_PEAK / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK, "traffic": blur_traffic(),
             "kernel": "blur_kernel (direct convolution A p, FP32)",
             "avg_us": blur_ms * 1e3,
         },

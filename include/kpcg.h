@@ -207,8 +207,131 @@ int pcg_solve_batched(const kp_plan_t *plans, int nplans, const float *const *b,
                       double tol, int maxit, int mode, float *const *x,
                       kp_info_t *infos, void *stream);
 
+/*
+ * opt_lambda -- the optimal-error rule in the KP-SVD basis, eq. (OptTikSVD):
+ *   x_hat = V_c^T X_true V_r,  O(l) = sum (s b_hat/(s^2+l^2) - x_hat)^2,
+ * which needs the true image (synthetic problems only: the targets the
+ * lambda network is trained on).  x_true: device FP32 n x n.  lambda_out =
+ * grid argmin (ties: smallest index); scores_out: ngrid values (may be
+ * NULL).  grid: host, 1..64 positive values.  Synchronises.
+ */
+int opt_lambda(kp_plan_t plan, const float *b, const float *x_true,
+               const double *grid, int ngrid, double *lambda_out,
+               double *scores_out, void *stream);
+
 /* kp_destroy -- release the plan (and its memory if it allocated it). */
 int kp_destroy(kp_plan_t plan);
+
+/* ---- learned choice of lambda ------------------------------------------
+ *
+ * The paper picks lambda by GCV, weighted GCV or the discrepancy principle
+ * in the KP-SVD basis (Section 2.2, Section 5.1) and leaves a systematic
+ * choice of these parameters open (Section 5.1, Section 6).  These entry
+ * points are the library's extension for that: a network maps KP-SVD
+ * spectral features of b to log10(lambda), and GCV judges its answer.
+ *
+ * Features (kp_features): with c = V_c^T B V_r and s_ij = s_c[i] s_r[j],
+ * 64 bins of log10(s) over [-8, 0) (s < 1e-8 -> bin 0, s >= 1 -> bin 63);
+ *   f[k]      = log10(max(mean of c^2 over bin k, 1e-30))  (empty: 1e-30)
+ *   f[64 + k] = log10(count of bin k / n^2 + 1e-12).
+ * Network: 128 -> 256 -> 256 -> 256 -> 1, exact GELU z Phi(z) after each
+ * hidden layer, linear output, on features standardised by the model's
+ * per-feature mean and scale.  Hidden layers: FP16 weights and activations
+ * on MFMA with FP32 accumulation; output layer, backward pass and Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on FP32 master weights.
+ * Loss: mean over the batch of (y - t)^2 (t = log10 lambda target).
+ *
+ * Parameters are one flat FP32 array of KP_MLP_NPARAM values, weights
+ * [out][in] row-major: W1 (256x128), b1 (256), W2 (256x256), b2, W3
+ * (256x256), b3, W4 (1x256), b4 (1).
+ * A model is not thread safe: one host thread / stream at a time.
+ */
+#define KP_MLP_NFEAT   128
+#define KP_MLP_HIDDEN  256
+#define KP_MLP_NPARAM  164865
+
+typedef struct kp_mlp_s *kp_mlp_t;   /* opaque */
+
+/* Outcome of kp_lambda_learned. */
+typedef struct kp_lambda_info_s {
+    double  lambda;        /* the choice: lambda_pred, or lambda_gcv on
+                              fallback                                     */
+    double  lambda_pred;   /* 10^(network output), clipped to the grid's
+                              range                                        */
+    double  lambda_gcv;    /* GCV grid argmin                              */
+    double  gcv_ratio;     /* G(lambda_pred) / min_grid G - 1              */
+    int32_t fell_back;     /* 1 if gcv_ratio > tau                         */
+    int32_t reserved;
+} kp_lambda_info_t;
+
+/* kp_features -- the 128 features of b (device FP32 n x n) into
+   features_out (device, 128 floats). */
+int kp_features(kp_plan_t plan, const float *b, float *features_out,
+                void *stream);
+
+/* mlp_workspace_size -- device bytes of a model for batches of at most
+   max_batch rows (1 <= max_batch <= 65536); 0 if out of range. */
+size_t mlp_workspace_size(int max_batch);
+
+/* mlp_create -- a model in `workspace` (device, >= mlp_workspace_size
+   bytes, 16-byte aligned; NULL: the library allocates).  Parameters start
+   at zero and the normaliser at mean 0, scale 1: set both before use. */
+int mlp_create(int max_batch, void *workspace, size_t ws_bytes, void *stream,
+               kp_mlp_t *mlp);
+
+/* mlp_set_params / mlp_get_params -- copy the KP_MLP_NPARAM FP32 master
+   parameters from / to a host array.  Setting them resets Adam's moments
+   and step count.  Synchronise. */
+int mlp_set_params(kp_mlp_t mlp, const float *params, void *stream);
+int mlp_get_params(kp_mlp_t mlp, float *params, void *stream);
+
+/* mlp_set_normalizer / mlp_get_normalizer -- the per-feature mean and
+   scale (host arrays of 128; scales must be finite and > 0).  Synchronise. */
+int mlp_set_normalizer(kp_mlp_t mlp, const float *mean, const float *scale,
+                       void *stream);
+int mlp_get_normalizer(kp_mlp_t mlp, float *mean, float *scale, void *stream);
+
+/* mlp_fit_normalizer -- set the normaliser to the per-feature mean and
+   population standard deviation of nb rows (device, nb x 128 FP32); a
+   feature with deviation below 1e-6 gets scale 1. */
+int mlp_fit_normalizer(kp_mlp_t mlp, const float *features, int nb,
+                       void *stream);
+
+/* lambda_predict -- network outputs (log10 lambda) of nb feature rows
+   (device, nb x 128 FP32) into log10_lambda (device, nb FP64).  Any nb >= 1
+   (processed max_batch rows at a time).  Does not synchronise. */
+int lambda_predict(kp_mlp_t mlp, const float *features, int nb,
+                   double *log10_lambda, void *stream);
+
+/* mlp_train_step -- one Adam step on the minibatch rows[0..nb) (host
+   array of indices into the nrows feature rows / targets; NULL: rows
+   0..nb-1) of features (device, nrows x 128) and targets (device, nrows
+   FP32 log10 lambda), with learning rate lr > 0.  1 <= nb <= max_batch.
+   loss_out (host, may be NULL): the minibatch loss before the step;
+   giving it synchronises. */
+int mlp_train_step(kp_mlp_t mlp, const float *features, const float *targets,
+                   int nrows, const int *rows, int nb, float lr,
+                   double *loss_out, void *stream);
+
+/* mlp_gradients -- loss and the gradient of the loss (host array of
+   KP_MLP_NPARAM FP32, same layout as the parameters) on rows 0..nb-1,
+   without updating.  Synchronises. */
+int mlp_gradients(kp_mlp_t mlp, const float *features, const float *targets,
+                  int nb, float *grads, double *loss_out, void *stream);
+
+/* mlp_destroy -- release the model. */
+int mlp_destroy(kp_mlp_t mlp);
+
+/*
+ * kp_lambda_learned -- lambda for b from the network, judged by GCV:
+ * features of b -> network -> lambda_pred (clipped to [min grid, max grid]);
+ * G (eq. (GCVTikSVD) in the KP-SVD basis) on the grid and at lambda_pred;
+ * if G(lambda_pred) / min_grid G - 1 > tau the GCV grid argmin is used.
+ * grid: host, 1..63 positive values; tau >= 0.  Synchronises.
+ */
+int kp_lambda_learned(kp_plan_t plan, kp_mlp_t mlp, const float *b,
+                      const double *grid, int ngrid, double tau,
+                      kp_lambda_info_t *info, void *stream);
 
 /* kp_strerror -- static description of a status code. */
 const char *kp_strerror(int status);

@@ -9,13 +9,9 @@
 #include <new>
 #include <vector>
 
-#include "common.h"
+#include "capi_internal.h"
 
 using namespace kpcg;
-
-struct kp_plan_s {
-  Plan P;
-};
 
 namespace kpcg {
 int build_factors(Plan& P, const double* psf_host, hipStream_t s);
@@ -100,13 +96,6 @@ bool valid_sizes(int n, int k) {
   return n >= 1 && n <= 2048 && k >= 1 && (k & 1) == 1 && k <= 2 * n - 1;
 }
 
-#define HIP_OR(x, code)                   \
-  do {                                    \
-    if ((x) != hipSuccess) return (code); \
-  } while (0)
-#define HIPCHK(x) HIP_OR(x, KP_ERR_HIP)
-
-bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 
 int read_ctrl(Plan& P, hipStream_t s, Ctrl& out) {
@@ -397,29 +386,42 @@ int pcg_solve_batched(const kp_plan_t* plans, int nplans, const float* const* b,
   return worst;
 }
 
-static int spectral_call(kp_plan_t plan, const float* b, const double* grid, int ngrid,
-                         double omega, double noise2, int kind, double* scores_host,
-                         void* stream) {
+}  // extern "C"
+
+namespace kpcg {
+
+int spectral_call(kp_plan_t plan, const float* b, const double* grid, int ngrid, double omega,
+                  double noise2, int kind, double* scores_host, void* stream,
+                  const float* x_true) {
   Plan& P = plan->P;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t N = (size_t)P.n * P.n;
   char* spec = reinterpret_cast<char*>(P.spec);
   double* grid_dev = reinterpret_cast<double*>(spec + ((N * sizeof(float) + 255) / 256) * 256);
   double* out_dev = grid_dev + 64;
+  float* xhat = nullptr;
   HIPCHK(hipMemcpyAsync(grid_dev, grid, sizeof(double) * ngrid, hipMemcpyHostToDevice, s));
+  if (kind == 2) {
+    xhat = reinterpret_cast<float*>(P.t2);
+    HIPCHK(launch_vbasis_gemms(P, x_true, xhat, s));
+  }
   HIPCHK(launch_spectrum(P, b, s));
-  HIPCHK(launch_spectral_scores(P, grid_dev, ngrid, omega, noise2, kind, out_dev, s));
+  HIPCHK(launch_spectral_scores(P, grid_dev, ngrid, omega, noise2, kind, out_dev, s, xhat));
   HIPCHK(hipMemcpyAsync(scores_host, out_dev, sizeof(double) * ngrid, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   return KP_OK;
 }
 
-static bool valid_grid(const double* grid, int ngrid) {
-  if (!grid || ngrid < 1 || ngrid > 64) return false;
+bool valid_grid(const double* grid, int ngrid, int max_points) {
+  if (!grid || ngrid < 1 || ngrid > max_points) return false;
   for (int g = 0; g < ngrid; ++g)
     if (!(grid[g] > 0.0) || !std::isfinite(grid[g])) return false;
   return true;
 }
+
+}  // namespace kpcg
+
+extern "C" {
 
 int gcv_lambda(kp_plan_t plan, const float* b, const double* grid, int ngrid, double omega,
                double* lambda_out, double* scores_out, void* stream) {

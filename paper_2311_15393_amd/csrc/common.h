@@ -233,6 +233,9 @@ hipError_t launch_spectral_gemms(const Plan& P, const float* b, float* out, hipS
 hipError_t launch_spectrum(const Plan& P, const float* b, hipStream_t s);
 hipError_t launch_spectral_scores(const Plan& P, const double* grid_dev, int ngrid,
                                   double omega, double noise2, int kind, double* out_dev,
-                                  hipStream_t s);
+                                  hipStream_t s, const float* xhat = nullptr);
+hipError_t launch_vbasis_gemms(const Plan& P, const float* b, float* out, hipStream_t s);
+// 128 features of b (see spectral.hip) into out (device, 128 floats)
+hipError_t launch_features(const Plan& P, const float* b, float* out, hipStream_t s);
 
 }  // namespace kpcg

@@ -99,4 +99,14 @@ hipError_t launch_spectral_gemms(const Plan& P, const float* b, float* out, hipS
   return run_gemm<float, false>(P, t1, P.UrT32, GEpiStore<float>{out, n}, 0, 0, s);
 }
 
+// the same two GEMMs in the right singular bases: out = Vc^T B Vr (features
+// of the data, and x_hat of the optimal-error score)
+hipError_t launch_vbasis_gemms(const Plan& P, const float* b, float* out, hipStream_t s) {
+  const int n = P.n;
+  float* t1 = reinterpret_cast<float*>(P.t1);
+  hipError_t e = run_gemm<float, true>(P, P.VcT32, b, GEpiStore<float>{t1, n}, 0, 0, s);
+  if (e != hipSuccess) return e;
+  return run_gemm<float, false>(P, t1, P.VrT32, GEpiStore<float>{out, n}, 0, 0, s);
+}
+
 }  // namespace kpcg

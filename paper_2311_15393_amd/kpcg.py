@@ -24,6 +24,7 @@ KP_P32, KP_P16, KP_P8 = 0x000, 0x010, 0x020
 KP_WARM = 0x100
 KP_BATCH_EAGER = 0x200
 KP_MAX_PSF = 63
+KP_MLP_NFEAT, KP_MLP_HIDDEN, KP_MLP_NPARAM = 128, 256, 164865
 
 
 class KPError(RuntimeError):
@@ -48,6 +49,12 @@ class _PlanInfo(ctypes.Structure):
                 ("sigma_r_max", ctypes.c_double), ("sigma_r_min", ctypes.c_double),
                 ("device_bytes", ctypes.c_size_t), ("blur_config", ctypes.c_int32),
                 ("blur_config_ms", ctypes.c_float * 8)]
+
+
+class _LambdaInfo(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("lambda_pred", ctypes.c_double),
+                ("lambda_gcv", ctypes.c_double), ("gcv_ratio", ctypes.c_double),
+                ("fell_back", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -77,6 +84,22 @@ _SIGS = {
                                     ctypes.POINTER(ctypes.c_float), _VP]),
     "kp_time_precond": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP,
                                        ctypes.c_int, ctypes.POINTER(ctypes.c_float), _VP]),
+    "opt_lambda": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP, _VP]),
+    "kp_features": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "mlp_workspace_size": (ctypes.c_size_t, [ctypes.c_int]),
+    "mlp_create": (ctypes.c_int, [ctypes.c_int, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "mlp_set_params": (ctypes.c_int, [_VP, _VP, _VP]),
+    "mlp_get_params": (ctypes.c_int, [_VP, _VP, _VP]),
+    "mlp_set_normalizer": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "mlp_get_normalizer": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "mlp_fit_normalizer": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP]),
+    "lambda_predict": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP, _VP]),
+    "mlp_train_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP, ctypes.c_int,
+                                      ctypes.c_float, _VP, _VP]),
+    "mlp_gradients": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP, _VP, _VP]),
+    "mlp_destroy": (ctypes.c_int, [_VP]),
+    "kp_lambda_learned": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int, ctypes.c_double,
+                                         ctypes.POINTER(_LambdaInfo), _VP]),
 }
 
 
@@ -236,6 +259,41 @@ class Plan:
                                          _stream(stream)), "discrepancy_lambda")
         return out.value, vals
 
+    def opt(self, b, x_true, grid, stream=None):
+        """opt_lambda: optimal-error rule in the KP basis (needs the true image)."""
+        grid = np.ascontiguousarray(grid, dtype=np.float64)
+        out = ctypes.c_double()
+        scores = np.empty(grid.size)
+        _check(load().opt_lambda(self._h, _dev_image(b, self.n, "b"),
+                                 _dev_image(x_true, self.n, "x_true"),
+                                 grid.ctypes.data_as(ctypes.c_void_p), grid.size,
+                                 ctypes.byref(out), scores.ctypes.data_as(ctypes.c_void_p),
+                                 _stream(stream)), "opt_lambda")
+        return out.value, scores
+
+    def features(self, b, out=None, stream=None):
+        """kp_features: the 128 spectral features of b into out (CUDA float32, 128)."""
+        import torch
+        if out is None:
+            out = torch.empty(KP_MLP_NFEAT, device=b.device, dtype=torch.float32)
+        _check_vec(out, KP_MLP_NFEAT, "out")
+        _check(load().kp_features(self._h, _dev_image(b, self.n, "b"),
+                                  ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+               "kp_features")
+        return out
+
+    def lambda_learned(self, mlp, b, grid, tau: float, stream=None) -> dict:
+        """kp_lambda_learned: the network's lambda, judged by GCV (fallback)."""
+        grid = np.ascontiguousarray(grid, dtype=np.float64)
+        info = _LambdaInfo()
+        _check(load().kp_lambda_learned(self._h, mlp._h, _dev_image(b, self.n, "b"),
+                                        grid.ctypes.data_as(ctypes.c_void_p), grid.size,
+                                        float(tau), ctypes.byref(info), _stream(stream)),
+               "kp_lambda_learned")
+        return {"lambda": info.lambda_, "lambda_pred": info.lambda_pred,
+                "lambda_gcv": info.lambda_gcv, "gcv_ratio": info.gcv_ratio,
+                "fell_back": bool(info.fell_back)}
+
     # -- operator-level entry points -------------------------------------
     def blur(self, x, y, transpose: bool = False, stream=None):
         _check(load().kp_blur(self._h, _dev_image(x, self.n, "x"), _dev_image(y, self.n, "y"),
@@ -267,6 +325,130 @@ class Plan:
         _check(load().kp_precond(self._h, _dev_image(r, self.n, "r"), float(lam), int(mode),
                                  _dev_image(z, self.n, "z"), _stream(stream)), "kp_precond")
         return z
+
+
+def _check_vec(t, count, name, dtype=None):
+    import torch
+    dtype = dtype or torch.float32
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype or t.numel() != count or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of {count} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mlp:
+    """mlp_create / mlp_destroy: the lambda-predicting network (include/kpcg.h)."""
+
+    def __init__(self, max_batch: int = 1024, stream=None, workspace=None):
+        lib = load()
+        self.max_batch = int(max_batch)
+        self._ws = workspace
+        wptr, wbytes = None, 0
+        if workspace is not None:
+            wptr = ctypes.c_void_p(workspace.data_ptr())
+            wbytes = workspace.numel() * workspace.element_size()
+        h = ctypes.c_void_p()
+        _check(lib.mlp_create(self.max_batch, wptr, wbytes, _stream(stream), ctypes.byref(h)),
+               "mlp_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, stream=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != KP_MLP_NPARAM:
+            raise ValueError(f"expected {KP_MLP_NPARAM} parameters")
+        _check(load().mlp_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p),
+                                     _stream(stream)), "mlp_set_params")
+
+    def get_params(self, stream=None) -> np.ndarray:
+        p = np.empty(KP_MLP_NPARAM, dtype=np.float32)
+        _check(load().mlp_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p),
+                                     _stream(stream)), "mlp_get_params")
+        return p
+
+    def set_normalizer(self, mean, scale, stream=None):
+        m = np.ascontiguousarray(mean, dtype=np.float32)
+        s = np.ascontiguousarray(scale, dtype=np.float32)
+        if m.size != KP_MLP_NFEAT or s.size != KP_MLP_NFEAT:
+            raise ValueError("normaliser needs 128 means and 128 scales")
+        _check(load().mlp_set_normalizer(self._h, m.ctypes.data_as(ctypes.c_void_p),
+                                         s.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+               "mlp_set_normalizer")
+
+    def get_normalizer(self, stream=None):
+        m = np.empty(KP_MLP_NFEAT, dtype=np.float32)
+        s = np.empty(KP_MLP_NFEAT, dtype=np.float32)
+        _check(load().mlp_get_normalizer(self._h, m.ctypes.data_as(ctypes.c_void_p),
+                                         s.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+               "mlp_get_normalizer")
+        return m, s
+
+    def fit_normalizer(self, features, stream=None):
+        nb = _feature_rows(features)
+        _check(load().mlp_fit_normalizer(self._h, ctypes.c_void_p(features.data_ptr()), nb,
+                                         _stream(stream)), "mlp_fit_normalizer")
+
+    def predict(self, features, out=None, stream=None):
+        """lambda_predict: log10(lambda) for each feature row (CUDA float64 out)."""
+        import torch
+        nb = _feature_rows(features)
+        if out is None:
+            out = torch.empty(nb, device=features.device, dtype=torch.float64)
+        _check_vec(out, nb, "out", torch.float64)
+        _check(load().lambda_predict(self._h, ctypes.c_void_p(features.data_ptr()), nb,
+                                     ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+               "lambda_predict")
+        return out
+
+    def train_step(self, features, targets, lr: float, rows=None, want_loss: bool = False,
+                   stream=None):
+        """mlp_train_step on rows (host int array or None = all rows)."""
+        import torch
+        nrows = _feature_rows(features)
+        _check_vec(targets, nrows, "targets")
+        if rows is None:
+            rp, nb = None, nrows
+        else:
+            rows = np.ascontiguousarray(rows, dtype=np.int32)
+            rp, nb = rows.ctypes.data_as(ctypes.c_void_p), rows.size
+        loss = ctypes.c_double()
+        _check(load().mlp_train_step(self._h, ctypes.c_void_p(features.data_ptr()),
+                                     ctypes.c_void_p(targets.data_ptr()), nrows, rp, nb,
+                                     float(lr), ctypes.byref(loss) if want_loss else None,
+                                     _stream(stream)), "mlp_train_step")
+        return loss.value if want_loss else None
+
+    def gradients(self, features, targets, stream=None):
+        """mlp_gradients: (loss, flat FP32 gradient) on all rows, no update."""
+        nb = _feature_rows(features)
+        _check_vec(targets, nb, "targets")
+        g = np.empty(KP_MLP_NPARAM, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(load().mlp_gradients(self._h, ctypes.c_void_p(features.data_ptr()),
+                                    ctypes.c_void_p(targets.data_ptr()), nb,
+                                    g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss),
+                                    _stream(stream)), "mlp_gradients")
+        return loss.value, g
+
+
+def _feature_rows(features) -> int:
+    import torch
+    if (not isinstance(features, torch.Tensor) or not features.is_cuda
+            or features.dtype != torch.float32 or features.dim() != 2
+            or features.shape[1] != KP_MLP_NFEAT or not features.is_contiguous()):
+        raise ValueError("features must be a contiguous CUDA float32 (rows, 128) tensor")
+    return int(features.shape[0])
 
 
 def solve_batched(plans, bs, lambdas, plan_of_item, tol: float = 1e-6, maxit: int = 1000,

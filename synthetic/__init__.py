@@ -2,8 +2,10 @@
 tests and the benchmark.  Holds no solver arithmetic."""
 from .problems import (Problem, true_image, psf_gaussian, psf_moffat_motion,
                        make_problem, small_gaussian, mid_anisotropic, large_moffat,
-                       batch_problem, lambda_grid, random_image, BATCH_SIZES)
+                       batch_problem, lambda_grid, random_image, BATCH_SIZES, mixed_psf,
+                       training_group, TRAIN_SEED0, VAL_SEED0)
 
 __all__ = ["Problem", "true_image", "psf_gaussian", "psf_moffat_motion",
            "make_problem", "small_gaussian", "mid_anisotropic", "large_moffat",
-           "batch_problem", "lambda_grid", "random_image", "BATCH_SIZES"]
+           "batch_problem", "lambda_grid", "random_image", "BATCH_SIZES", "mixed_psf",
+           "training_group", "TRAIN_SEED0", "VAL_SEED0"]

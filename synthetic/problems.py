@@ -203,27 +203,50 @@ def large_moffat(seed: int = 0, n: int = 1024, k: int = 63) -> Problem:
 BATCH_SIZES = (128, 256, 384, 512, 768, 1024)
 
 
-def batch_problem(index: int, batch_seed: int = 0, sizes=BATCH_SIZES,
-                  kmax: int = 63) -> Problem:
-    """Problem `index` of the uneven batch: size uniform over `sizes`, PSF a
-    rotated anisotropic Gaussian (sigma ~ U[1.5,5], theta ~ U[0,pi)) or the
-    Moffat + motion blur by a fair coin, support odd in [15, kmax], noise
-    U[0.5%, 3%]."""
-    seed = 10000 * (batch_seed + 1) + index
-    rng = np.random.default_rng(seed)
-    n = int(rng.choice(np.asarray(sizes)))
+def mixed_psf(rng: np.random.Generator, n: int, kmax: int = 63):
+    """A PSF from the uneven batch's mix: support odd uniform in [15, kmax]
+    (at most 2n-1), then by a fair coin a rotated anisotropic Gaussian
+    (sigma ~ U[1.5,5], theta ~ U[0,pi)) or the Moffat + motion blur
+    (alpha ~ U[3,8], beta 2.5, length ~ U[3,9], angle ~ U[0,pi))."""
     k = int(rng.choice(np.arange(15, kmax + 1, 2)))
     k = min(k, 2 * n - 1)
     if rng.uniform() < 0.5:
         sx, sy = rng.uniform(1.5, 5.0, size=2)
-        psf = psf_gaussian(k, sx, sy, rng.uniform(0.0, math.pi))
-        kind = f"gauss{k}"
-    else:
-        psf = psf_moffat_motion(k, rng.uniform(3.0, 8.0), 2.5,
-                                rng.uniform(3.0, 9.0), rng.uniform(0.0, math.pi))
-        kind = f"moffat{k}"
+        return psf_gaussian(k, sx, sy, rng.uniform(0.0, math.pi)), f"gauss{k}"
+    psf = psf_moffat_motion(k, rng.uniform(3.0, 8.0), 2.5,
+                            rng.uniform(3.0, 9.0), rng.uniform(0.0, math.pi))
+    return psf, f"moffat{k}"
+
+
+def batch_problem(index: int, batch_seed: int = 0, sizes=BATCH_SIZES,
+                  kmax: int = 63) -> Problem:
+    """Problem `index` of the uneven batch: size uniform over `sizes`, PSF from
+    `mixed_psf`, noise U[0.5%, 3%]."""
+    seed = 10000 * (batch_seed + 1) + index
+    rng = np.random.default_rng(seed)
+    n = int(rng.choice(np.asarray(sizes)))
+    psf, kind = mixed_psf(rng, n, kmax)
     nu = rng.uniform(0.005, 0.03)
     return make_problem(n, psf, rng, nu, None, seed, kind)
+
+
+TRAIN_SEED0 = 100000      # training groups of the learned-lambda workload
+VAL_SEED0 = 120000        # its validation groups
+
+
+def training_group(group: int, per_psf: int = 8, n: int = 256, seed0: int = TRAIN_SEED0,
+                   kmax: int = 63) -> list:
+    """Problems of the learned-lambda workload: group `group` draws one PSF
+    from the uneven batch's mix (seed seed0 + group) and `per_psf` images
+    with their own noise level U[0.5%, 3%]; all n x n."""
+    seed = seed0 + group
+    rng = np.random.default_rng(seed)
+    psf, kind = mixed_psf(rng, n, kmax)
+    out = []
+    for _ in range(per_psf):
+        nu = rng.uniform(0.005, 0.03)
+        out.append(make_problem(n, psf, rng, nu, None, seed, kind))
+    return out
 
 
 def lambda_grid(count: int = 32, lo: float = 1e-4, hi: float = 1.0) -> np.ndarray:
