@@ -43,7 +43,13 @@ COPY_CALIB_FLOATS = 64 * 1024 * 1024
 # `sources_sha256` is the hash of the blur sources the counters were taken
 # on; when the sources differ the figure no longer describes the kernel and
 # is reported as null.
-BLUR_TRAFFIC = None
+BLUR_TRAFFIC = {
+    "kernel": "blur_kernel<8, 64, 8, 1, 16, float, float, float, EpiStoreF32>",
+    "fetch_kib_raw": 4114.7, "write_kib_raw": 4096.0,       # per launch, as counted
+    "fetch_scale": 1.99978, "write_scale": 1.0,              # copy bytes / counter
+    "bytes_per_launch": 12620340,
+    "sources_sha256": "747d6d8a3d8b50b3c16aed611c0fdd58cdfced48f492a5dd24470ede961c43c8",
+}
 
 
 def log(*a):
@@ -138,6 +144,11 @@ def main():
     gcv_ms = (time.perf_counter() - t0) / 5 * 1e3
     gidx = int(np.argmin(np.abs(grid - lam)))
     log(f"[bench] gcv lambda={lam:.4g} (grid index {gidx}) {gcv_ms:.2f} ms")
+
+    learned = time_learned_lambda(plan, b, grid, dev)
+    log(f"[bench] learned lambda: kp_lambda_learned {learned['lambda_learned_ms']:.2f} ms at "
+        f"{n}^2; lambda_predict {learned['predict_samples_per_s'] / 1e6:.2f} M rows/s; "
+        f"train step (256 rows) {learned['train_step_ms']:.3f} ms")
 
     oracle = {}
     if not args.profile_only:
@@ -280,6 +291,7 @@ def main():
             "kp_rel_error": pinfo["kp_rel_error"],
             "blur_tile_config": pinfo["blur_config"],
             "precond_fp16_chain_us": prec_ms * 1e3,
+            "learned_lambda": learned,
             "batched": batch,
         },
         "roofline": {
@@ -292,6 +304,51 @@ def main():
     }
     print(json.dumps(line), flush=True)
     plan.close()
+
+
+def time_learned_lambda(plan, b, grid, dev) -> dict:
+    """Cost of the learned-lambda path (network kernels with untrained
+    weights: the timing does not depend on the weights): features +
+    prediction + GCV check for one image, batched inference, and one Adam
+    training step on 256 rows."""
+    import torch
+    from paper_2311_15393_amd import Mlp
+    from paper_2311_15393_amd.lambda_net import init_params
+    mlp = Mlp(max_batch=4096)
+    mlp.set_params(init_params(0))
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    feats = torch.randn((4096, 128), device=dev, generator=g)
+    tgt = torch.randn(4096, device=dev, generator=g)
+    mlp.fit_normalizer(feats)
+    out = torch.empty(4096, device=dev, dtype=torch.float64)
+    plan.lambda_learned(mlp, b, grid, tau=0.1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        plan.lambda_learned(mlp, b, grid, tau=0.1)
+    ll_ms = (time.perf_counter() - t0) / 5 * 1e3
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    mlp.predict(feats, out=out)
+    e0.record(s)
+    for _ in range(20):
+        mlp.predict(feats, out=out)
+    e1.record(s)
+    e1.synchronize()
+    pred_ms = e0.elapsed_time(e1) / 20
+    rows = np.arange(256, dtype=np.int32)
+    mlp.train_step(feats, tgt, 1e-4, rows=rows)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(50):
+        mlp.train_step(feats, tgt, 1e-4, rows=rows)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) / 50 * 1e3
+    mlp.close()
+    return {"lambda_learned_ms": ll_ms, "predict_rows": 4096, "predict_ms": pred_ms,
+            "predict_samples_per_s": 4096 / (pred_ms * 1e-3),
+            "train_step_ms": step_ms, "train_samples_per_s": 256 / (step_ms * 1e-3)}
 
 
 def run_batch(nprob: int, dev):

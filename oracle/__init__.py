@@ -1,7 +1,7 @@
 """Plain FP64 CPU oracle for KP-SVD-preconditioned Tikhonov deblurring.
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product library imports, calls or
-links this package; only the tests, the graft smoke check and the benchmark's
+links this package; only the tests, __graft_entry__.smoke() and the benchmark's
 CPU-baseline leg do.  It shares no code with the HIP library.
 
 It follows Chen, Ji & Nagy, "Half-Precision Kronecker Product SVD

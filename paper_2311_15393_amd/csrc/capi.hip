@@ -307,7 +307,14 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
   if (hc.done == RUNNING) HIPCHK(enqueue_tail(P, solver, prec, lam2, s));
   if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
 
+  // Iterations are enqueued in blocks; kernels enqueued after the device has
+  // marked the solve finished exit at once but still cost a launch each.
+  // Once a contraction rate of ||r||^2 has been observed, a block is sized
+  // to reach the next stopping point (tolerance or replacement threshold).
   int block = 4;
+  double rate = 0.0;                   // mean per-iteration factor of ||r||^2
+  double rr_mark = hc.rr;
+  int it_mark = hc.iter;
   while (hc.done == RUNNING || hc.done == PENDING) {
     if (hc.done == PENDING) {
       // the recurrence residual met the tolerance or fell 1/REPLACE_DROP:
@@ -321,11 +328,21 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
         break;
       }
       HIPCHK(enqueue_tail(P, solver, prec, lam2, s));
+      rr_mark = hc.rr;
+      it_mark = hc.iter;
     }
     const int todo = maxit - hc.iter;
-    const int m = block < todo ? block : todo;
+    int m = block;
+    if (rate > 0.0 && rate < 1.0 && hc.rr > 0.0) {
+      const double target = hc.tol2 > hc.repl2 ? hc.tol2 : hc.repl2;
+      const double need = std::ceil(std::log(target / hc.rr) / std::log(rate));
+      m = need < 1.0 ? 1 : (need > 32.0 ? 32 : (int)need);
+    }
+    m = m < todo ? m : todo;
     for (int it = 0; it < m; ++it) HIPCHK(enqueue_iteration(P, solver, prec, lam2, s));
     if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
+    if (hc.iter > it_mark && hc.rr > 0.0 && rr_mark > 0.0 && hc.rr < rr_mark)
+      rate = std::pow(hc.rr / rr_mark, 1.0 / (hc.iter - it_mark));
     if (block < 32) block *= 2;
     if (hc.done == RUNNING && hc.iter >= maxit) hc.done = MAXIT;
   }
