@@ -40,6 +40,9 @@ extern "C" {
 #define KP_MAXIT            1   /* maxit iterations without convergence    */
 #define KP_BREAKDOWN        2   /* p.Hp <= 0, r.z <= 0 or a non-finite
                                    scalar; x holds the last iterate        */
+#define KP_OK_FALLBACK      3   /* converged after the automatic restart
+                                   with the FP32 preconditioner (pcg_solve
+                                   with KP_P16 / KP_P8 only)               */
 #define KP_ERR_ARG         -1   /* null pointer, n < 1, K even, K > 2n-1,
                                    lambda <= 0, tol <= 0, maxit < 1, a
                                    non-finite argument, bad mode bits      */
@@ -65,6 +68,7 @@ extern "C" {
 #define KP_WARM      0x100      /* x holds the initial guess on entry       */
 #define KP_BATCH_EAGER 0x200    /* pcg_solve_batched: launch every iteration
                                    eagerly instead of replaying a hipGraph */
+#define KP_NO_FALLBACK 0x400    /* pcg_solve: no FP32 restart on failure    */
 
 typedef struct kp_plan_s *kp_plan_t;   /* opaque */
 
@@ -74,7 +78,8 @@ typedef struct kp_info_s {
                                iteration, as the paper counts iterations   */
     int32_t status;         /* KP_OK, KP_MAXIT or KP_BREAKDOWN             */
     int32_t replacements;   /* FP64 true-residual recomputations           */
-    int32_t reserved;
+    int32_t fallback;       /* 1 if pcg_solve restarted with the FP32
+                               preconditioner                              */
     double  relres_rec;     /* recurrence ||r|| / ||A^T b|| at exit        */
     double  relres_true;    /* FP64 ||A^T b - H x|| / ||A^T b|| at exit    */
     double  lambda;
@@ -151,8 +156,14 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t *out);
  *   x       device, n*n float32: initial guess if mode & KP_WARM, else
  *           ignored (x_0 = 0); on return the last iterate
  *   info    out (may be NULL)
- * Returns KP_OK (true relative residual <= tol), KP_MAXIT, KP_BREAKDOWN or
- * an error.  Synchronises `stream` (it reads back the convergence state).
+ * If a solve with the FP16 or FP8 preconditioner ends in KP_MAXIT or
+ * KP_BREAKDOWN (with a finite iterate), it is restarted from its last
+ * iterate with the FP32 preconditioner and its own budget of maxit
+ * iterations (info->iters counts both runs, info->fallback = 1); mode bit
+ * KP_NO_FALLBACK turns this off.
+ * Returns KP_OK (true relative residual <= tol), KP_OK_FALLBACK, KP_MAXIT,
+ * KP_BREAKDOWN or an error.  Synchronises `stream` (it reads back the
+ * convergence state).
  */
 int pcg_solve(kp_plan_t plan, const float *b, double lambda, double tol,
               int maxit, int mode, float *x, kp_info_t *info, void *stream);

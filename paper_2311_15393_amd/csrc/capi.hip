@@ -237,6 +237,8 @@ const char* kp_strerror(int status) {
     case KP_OK: return "success (solve: true relative residual <= tol)";
     case KP_MAXIT: return "maximum number of iterations reached";
     case KP_BREAKDOWN: return "breakdown: non-positive curvature or non-finite scalar";
+    case KP_OK_FALLBACK:
+      return "success after restarting with the FP32 preconditioner";
     case KP_ERR_ARG: return "invalid argument";
     case KP_ERR_UNSUPPORTED: return "unsupported configuration";
     case KP_ERR_HIP: return "HIP runtime error";
@@ -246,13 +248,12 @@ const char* kp_strerror(int status) {
   }
 }
 
-int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int maxit, int mode,
-              float* x, kp_info_t* info, void* stream) {
-  if (!plan || !b || !x) return KP_ERR_ARG;
-  if (!(lambda > 0.0) || !std::isfinite(lambda) || !(tol > 0.0) || !std::isfinite(tol) ||
-      maxit < 1)
-    return KP_ERR_ARG;
-  if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM)) != 0) return KP_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int maxit, int mode,
+               float* x, kp_info_t* info, void* stream) {
   const int solver = mode & KP_SOLVER_MASK;
   const int prec = mode & KP_PREC_MASK;
   if (solver == 3 || prec == KP_PREC_MASK) return KP_ERR_ARG;
@@ -364,7 +365,7 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
     info->iters = hc.iter;
     info->status = status;
     info->replacements = replacements;
-    info->reserved = 0;
+    info->fallback = 0;
     info->relres_rec = std::sqrt(hc.rr / hc.gamma0sq);
     info->relres_true = std::sqrt(true_rr / hc.gamma0sq);
     info->lambda = lambda;
@@ -372,6 +373,47 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
     info->misfit = 0.0;
   }
   return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int maxit, int mode,
+              float* x, kp_info_t* info, void* stream) {
+  if (!plan || !b || !x) return KP_ERR_ARG;
+  if (!(lambda > 0.0) || !std::isfinite(lambda) || !(tol > 0.0) || !std::isfinite(tol) ||
+      maxit < 1)
+    return KP_ERR_ARG;
+  if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM | KP_NO_FALLBACK)) != 0)
+    return KP_ERR_ARG;
+  kp_info_t first;
+  const int st = solve_once(plan, b, lambda, tol, maxit, mode & ~KP_NO_FALLBACK, x, &first,
+                            stream);
+  if (st < 0) return st;
+  const int solver = mode & KP_SOLVER_MASK, prec = mode & KP_PREC_MASK;
+  const bool retry = (st == KP_MAXIT || st == KP_BREAKDOWN) && solver != KP_CG &&
+                     prec != KP_P32 && !(mode & KP_NO_FALLBACK) &&
+                     std::isfinite(first.relres_true);
+  if (!retry) {
+    if (info) *info = first;
+    return st;
+  }
+  // reduced-precision preconditioner did not reach tol: restart from the last
+  // iterate with the FP32 preconditioner (its own budget of maxit iterations)
+  kp_info_t second;
+  const int st2 = solve_once(plan, b, lambda, tol, maxit,
+                             (mode & (KP_SOLVER_MASK | KP_NO_FALLBACK)) | KP_P32 | KP_WARM, x,
+                             &second, stream);
+  if (st2 < 0) return st2;
+  if (info) {
+    *info = second;
+    info->iters = first.iters + second.iters;
+    info->replacements = first.replacements + second.replacements;
+    info->fallback = 1;
+    info->status = st2 == KP_OK ? KP_OK_FALLBACK : st2;
+  }
+  return st2 == KP_OK ? KP_OK_FALLBACK : st2;
 }
 
 int pcg_solve_batched(const kp_plan_t* plans, int nplans, const float* const* b,

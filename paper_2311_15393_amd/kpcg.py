@@ -17,12 +17,13 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libkpcg.so")
 
 # status codes and mode bits (mirror include/kpcg.h)
-KP_OK, KP_MAXIT, KP_BREAKDOWN = 0, 1, 2
+KP_OK, KP_MAXIT, KP_BREAKDOWN, KP_OK_FALLBACK = 0, 1, 2, 3
 KP_ERR_ARG, KP_ERR_UNSUPPORTED, KP_ERR_HIP, KP_ERR_SOLVER, KP_ERR_WORKSPACE = -1, -2, -3, -4, -5
 KP_CG, KP_PCG, KP_FPCG = 0x000, 0x001, 0x002
 KP_P32, KP_P16, KP_P8 = 0x000, 0x010, 0x020
 KP_WARM = 0x100
 KP_BATCH_EAGER = 0x200
+KP_NO_FALLBACK = 0x400
 KP_MAX_PSF = 63
 KP_MLP_NFEAT, KP_MLP_HIDDEN, KP_MLP_NPARAM = 128, 256, 164865
 
@@ -35,7 +36,7 @@ class KPError(RuntimeError):
 
 class _Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("replacements", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("replacements", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("relres_rec", ctypes.c_double), ("relres_true", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("rhs_norm", ctypes.c_double),
                 ("misfit", ctypes.c_double)]
@@ -161,6 +162,7 @@ class SolveInfo:
     lam: float
     rhs_norm: float
     misfit: float = 0.0
+    fallback: int = 0
 
 
 def workspace_size(n: int, k: int) -> int:
@@ -231,10 +233,11 @@ class Plan:
         info = _Info()
         st = load().pcg_solve(self._h, bp, float(lam), float(tol), int(maxit), int(mode), xp,
                               ctypes.byref(info), _stream(stream))
-        if st < 0 or (raise_on_fail and st not in (KP_OK, KP_MAXIT)):
+        if st < 0 or (raise_on_fail and st not in (KP_OK, KP_OK_FALLBACK, KP_MAXIT)):
             raise KPError(st, "pcg_solve")
         return x, SolveInfo(info.iters, st, info.replacements, info.relres_rec,
-                            info.relres_true, info.lambda_, info.rhs_norm, info.misfit)
+                            info.relres_true, info.lambda_, info.rhs_norm, info.misfit,
+                            info.fallback)
 
     def gcv(self, b, grid, omega: float = 1.0, stream=None):
         bp = _dev_image(b, self.n, "b")

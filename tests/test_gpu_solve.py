@@ -180,3 +180,34 @@ def test_large_moffat_full_size(mode):
         err = rel(to_host(x), ref)
     say(f"  lam={lam:.4g} iters={info.iters} repl={info.replacements} err={err:.2e}")
     assert info.status == KP_OK and err <= 1e-4
+
+
+def test_fp32_fallback_after_reduced_precision_failure():
+    """pcg_solve restarts a failed FP16/FP8 solve from its last iterate with
+    the FP32 preconditioner: at 1024^2 the FP8 preconditioner needs more than
+    10 iterations to reach 1e-6 (about 29), so with maxit = 10 the FP8 run
+    stops at KP_MAXIT, and the FP32 restart (about 6 iterations from
+    scratch) converges within its own 10.  KP_NO_FALLBACK keeps the failure."""
+    require_gpu()
+    from paper_2311_15393_amd import (KP_FPCG, KP_MAXIT, KP_NO_FALLBACK, KP_OK_FALLBACK, KP_P8,
+                                      Plan)
+    prob = S.large_moffat(0)
+    grid = S.lambda_grid()
+    with Plan(prob.psf, prob.n) as plan:
+        b = to_dev(prob.b)
+        lam, _ = plan.gcv(b, grid)
+        x, info = plan.solve(b, lam, tol=1e-6, maxit=10, mode=KP_FPCG | KP_P8 | KP_NO_FALLBACK,
+                             raise_on_fail=False)
+        say(f"  fp8, no fallback: status={info.status} iters={info.iters}")
+        assert info.status == KP_MAXIT and info.iters == 10 and info.fallback == 0
+        x, info = plan.solve(b, lam, tol=1e-6, maxit=10, mode=KP_FPCG | KP_P8)
+        say(f"  fp8 + fallback: status={info.status} iters={info.iters} "
+            f"relres={info.relres_true:.2e}")
+        assert info.status == KP_OK_FALLBACK and info.fallback == 1
+        assert 10 < info.iters <= 20 and info.relres_true <= 1e-6
+        key = ("large", prob.seed, lam)
+        if key not in _XLAM:
+            kp = KP.kp_svd(prob.psf, prob.n)
+            _XLAM[key] = SV.x_lambda_iterative(prob.psf, prob.b.astype(np.float64), lam, kp=kp,
+                                               check=False)[0]
+        assert rel(to_host(x), _XLAM[key]) <= 1e-4

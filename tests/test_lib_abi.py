@@ -87,3 +87,16 @@ def test_null_plan_arguments():
     assert lib.kp_destroy(None) == -1
     assert lib.pcg_solve(None, None, 0.1, 1e-6, 10, 0, None, None, None) == -1
     assert lib.gcv_lambda(None, None, None, 0, 1.0, None, None, None) == -1
+
+
+def test_binding_constants_match_header():
+    """Every KP_* integer constant the binding mirrors equals the header's."""
+    from paper_2311_15393_amd import kpcg
+    src = open(HEADER).read()
+    defs = dict(re.findall(r"^#define\s+(KP_\w+)\s+(-?(?:0x[0-9a-fA-F]+|\d+))", src, flags=re.M))
+    checked = 0
+    for name, val in defs.items():
+        if hasattr(kpcg, name):
+            assert getattr(kpcg, name) == int(val, 0), name
+            checked += 1
+    assert checked >= 20
