@@ -21,24 +21,33 @@
 //
 // Tiles: 64 x 64 per workgroup, 4 waves in 2 x 2, each wave 32 x 32 as 2 x 2
 // MFMA 16x16 blocks; FP32 uses v_mfma_f32_16x16x4_f32, FP16
-// v_mfma_f32_16x16x32_f16, both accumulating in FP32.
+// v_mfma_f32_16x16x32_f16, both accumulating in FP32.  The contraction is
+// split over four such wave groups per workgroup, reduced in LDS.
 #include "gemm_core.h"
 
 namespace kpcg {
 
+// contraction split over GEMM_KS wave groups per workgroup (see
+// gemm_tile_splitk): at n = 1024 a 64 x 64 tile grid is only 256
+// workgroups, one per CU, so the k-loop's global latency is otherwise exposed
+constexpr int GEMM_KS = 4;
+
 template <typename T, bool B_FROM_F32, class Epi>
-__global__ __launch_bounds__(GT) void gemm_kernel(const T* __restrict__ A,
-                                                  const void* __restrict__ Bsrc, int n,
-                                                  Epi epi, Ctrl* ctrl, int skip_if_done,
-                                                  int scale_mode, double* partials) {
+__global__ __launch_bounds__(GT * GEMM_KS) void gemm_kernel(const T* __restrict__ A,
+                                                            const void* __restrict__ Bsrc, int n,
+                                                            Epi epi, Ctrl* ctrl, int skip_if_done,
+                                                            int scale_mode, double* partials) {
+  extern __shared__ __align__(16) char gemm_lds[];
   if (skip_if_done && ctrl->done != RUNNING) return;
   // scale_mode bit 0: scale the FP32 B source by pscale; bit 1: scale the
   // output by zscale (both set on the device from ||r||)
   const float bscale = (scale_mode & 1) ? ctrl->pscale : 1.0f;
   const float oscale = (scale_mode & 2) ? ctrl->zscale : 1.0f;
   const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-  gemm_tile<T, B_FROM_F32, Epi>(A, Bsrc, n, blockIdx.y * BM, blockIdx.x * BN, epi, bscale,
-                                oscale, partials + SLOT_RZ * MAX_PARTIALS + bid, MAX_PARTIALS);
+  gemm_tile_splitk<T, B_FROM_F32, Epi, GEMM_KS>(A, Bsrc, n, blockIdx.y * BM, blockIdx.x * BN,
+                                                epi, bscale, oscale,
+                                                partials + SLOT_RZ * MAX_PARTIALS + bid,
+                                                MAX_PARTIALS, gemm_lds);
 }
 
 template <typename T, bool BF, class Epi>
@@ -47,8 +56,17 @@ static hipError_t run_gemm(const Plan& P, const T* A, const void* B, Epi epi, in
   const int n = P.n;
   dim3 grid((n + BN - 1) / BN, (n + BM - 1) / BM);
   if ((long)grid.x * grid.y > MAX_PARTIALS) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gemm_kernel<T, BF, Epi>), grid, dim3(GT), 0, s, A, B, n, epi, P.ctrl,
-                     skip, scale_mode, P.partials);
+  constexpr size_t lds = gemm_splitk_lds<T>(GEMM_KS);
+  auto kern = gemm_kernel<T, BF, Epi>;
+  static bool granted = false;          // once per instantiation
+  if (!granted) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    granted = true;
+  }
+  hipLaunchKernelGGL(kern, grid, dim3(GT * GEMM_KS), lds, s, A, B, n, epi, P.ctrl, skip,
+                     scale_mode, P.partials);
   return hipGetLastError();
 }
 

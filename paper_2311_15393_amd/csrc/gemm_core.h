@@ -49,10 +49,11 @@ struct KContig {
   static constexpr int BK = MT<T>::BK, VEC = MT<T>::VEC, PER_ROW = BK / VEC;
   static constexpr int NV = BM * BK / VEC / GT;      // = 2
   float4 reg[NV];
-  __device__ void load(const T* __restrict__ g, int row0, int k0, int n, bool vec_ok) {
+  __device__ void load(const T* __restrict__ g, int row0, int k0, int n, bool vec_ok,
+                       int tid = threadIdx.x) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int id = threadIdx.x + GT * v;
+      const int id = tid + GT * v;
       const int row = id / PER_ROW, kc = (id % PER_ROW) * VEC;
       const int gr = row0 + row, gk = k0 + kc;
       if (vec_ok && gr < n && gk + VEC <= n) {
@@ -66,10 +67,10 @@ struct KContig {
       }
     }
   }
-  __device__ void store(Tile<T>& s) const {
+  __device__ void store(Tile<T>& s, int tid = threadIdx.x) const {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int id = threadIdx.x + GT * v;
+      const int id = tid + GT * v;
       const int row = id / PER_ROW, kc = (id % PER_ROW) * VEC;
       *reinterpret_cast<float4*>(&s[row][kc]) = reg[v];
     }
@@ -84,10 +85,11 @@ struct FromF32Rows {
   static constexpr int NV = BK * BN / 4 / GT;        // float4 per thread
   static constexpr int TPR = BN / 4;                 // threads per k row
   float4 reg[NV];
-  __device__ void load(const float* __restrict__ src, int j0, int k0, int n, bool vec_ok) {
+  __device__ void load(const float* __restrict__ src, int j0, int k0, int n, bool vec_ok,
+                       int tid = threadIdx.x) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int id = threadIdx.x + GT * v;
+      const int id = tid + GT * v;
       const int k = id / TPR, jc = (id % TPR) * 4;
       const int gk = k0 + k, gj = j0 + jc;
       if (vec_ok && gk < n && gj + 4 <= n) {
@@ -102,10 +104,10 @@ struct FromF32Rows {
       }
     }
   }
-  __device__ void store(Tile<T>& s, float scale) const {
+  __device__ void store(Tile<T>& s, float scale, int tid = threadIdx.x) const {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const int id = threadIdx.x + GT * v;
+      const int id = tid + GT * v;
       const int k = id / TPR, jc = (id % TPR) * 4;
       s[jc + 0][k] = (T)(reg[v].x * scale);
       s[jc + 1][k] = (T)(reg[v].y * scale);
@@ -257,6 +259,124 @@ __device__ inline void gemm_tile(const T* __restrict__ A, const void* __restrict
     __shared__ double sh[GT / 64];
     const double s0 = block_sum<GT>(d0, sh);
     const double s1 = block_sum<GT>(d1, sh);
+    if (threadIdx.x == 0) {
+      partial_out[0] = s0;
+      partial_out[slot_stride] = s1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the same tile with the contraction split over KS groups of four waves
+// (GT * KS threads): group g walks k-tiles [g nk / KS, (g+1) nk / KS) with
+// its own double-buffered LDS stages, then groups 1..KS-1 hand their
+// accumulators to group 0 through LDS, which adds them in group order and
+// runs the epilogue.  KS times the waves of gemm_tile per CU hide the global
+// latency of the k-loop; the order of the sums is fixed, so results are
+// deterministic.  `lds` is dynamic shared memory of gemm_splitk_lds<T>(KS)
+// bytes.
+// ---------------------------------------------------------------------------
+template <typename T>
+constexpr size_t gemm_splitk_lds(int ks) {
+  return (size_t)4 * ks * sizeof(Tile<T>);
+}
+
+template <typename T, bool B_FROM_F32, class Epi, int KS>
+__device__ inline void gemm_tile_splitk(const T* __restrict__ A, const void* __restrict__ Bsrc,
+                                        int n, int m0, int n0, Epi epi, float bscale,
+                                        float oscale, double* partial_out, int slot_stride,
+                                        char* lds) {
+  constexpr int BK = MT<T>::BK;
+  static_assert((KS - 1) * 4 * 16 * 64 * sizeof(float) <= gemm_splitk_lds<T>(KS),
+                "reduction buffer must fit in the stage buffers");
+  Tile<T>* sA = reinterpret_cast<Tile<T>*>(lds);     // [KS][2]
+  Tile<T>* sB = sA + 2 * KS;                          // [KS][2]
+  const int kg = threadIdx.x / GT, tid = threadIdx.x % GT;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const bool vec_ok = (n % 8) == 0;
+
+  float4_t acc[2][2];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+  KContig<T> la;
+  using BL = typename std::conditional<B_FROM_F32, FromF32Rows<T>, KContig<T>>::type;
+  BL lb;
+  Tile<T>* myA = sA + 2 * kg;
+  Tile<T>* myB = sB + 2 * kg;
+  auto load = [&](int k0) {
+    la.load(A, m0, k0, n, vec_ok, tid);
+    if constexpr (B_FROM_F32)
+      lb.load(reinterpret_cast<const float*>(Bsrc), n0, k0, n, vec_ok, tid);
+    else
+      lb.load(reinterpret_cast<const T*>(Bsrc), n0, k0, n, vec_ok, tid);
+  };
+  auto store = [&](int buf) {
+    la.store(myA[buf], tid);
+    if constexpr (B_FROM_F32) lb.store(myB[buf], bscale, tid);
+    else lb.store(myB[buf], tid);
+  };
+
+  const int nk = (n + BK - 1) / BK;
+  const int kb = kg * nk / KS, ke = (kg + 1) * nk / KS;
+  const int cnt = ke - kb;
+  const int steps = (nk + KS - 1) / KS;              // the same barrier count in every group
+  if (cnt > 0) {
+    load(kb * BK);
+    store(0);
+  }
+  __syncthreads();
+  for (int st = 0; st < steps; ++st) {
+    const int cur = st & 1;
+    const bool more = st + 1 < cnt;
+    if (more) load((kb + st + 1) * BK);
+    if (st < cnt) mma_stage<T>(myA[cur], myB[cur], acc, wm, wn, lane);
+    if (more) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  // cross-group reduction (the stage buffers are free after the last barrier)
+  float* red = reinterpret_cast<float*>(lds);
+  if (kg > 0) {
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          red[(((kg - 1) * 4 + wv) * 16 + (mi * 2 + ni) * 4 + v) * 64 + lane] = acc[mi][ni][v];
+  }
+  __syncthreads();
+  double d0 = 0.0, d1 = 0.0;
+  if (kg == 0) {
+#pragma unroll
+    for (int g = 1; g < KS; ++g)
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc[mi][ni][v] += red[(((g - 1) * 4 + wv) * 16 + (mi * 2 + ni) * 4 + v) * 64 + lane];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) {
+        const int j = n0 + wn * 32 + ni * 16 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = m0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + v;
+          if (i < n && j < n) epi.apply(i, j, acc[mi][ni][v] * oscale, d0, d1);
+        }
+      }
+  }
+  if constexpr (Epi::kReduce) {
+    __shared__ double sh[GT * KS / 64];
+    const double s0 = block_sum<GT * KS>(d0, sh);
+    const double s1 = block_sum<GT * KS>(d1, sh);
     if (threadIdx.x == 0) {
       partial_out[0] = s0;
       partial_out[slot_stride] = s1;
