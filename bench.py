@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "1024^2 deblur PCG solves/s at rel err <=1e-4 vs FP64; FP16-KP vs FP32-KP vs none"
 HBM_PEAK = 8.0e12
 FP32_VALU_PEAK = 157.3e12
+FP16_MFMA_PEAK = 2.5e15
 # solver modes and their iteration caps
 MODES = {"fp16_kp_fpcg": 200, "fp32_kp_pcg": 200, "fp8_kp_fpcg": 400, "none_cg": 3000}
 # Bytes of the plain copy launched by --profile-only to calibrate the HBM
@@ -44,7 +45,7 @@ COPY_CALIB_FLOATS = 64 * 1024 * 1024
 # on; when the sources differ the figure no longer describes the kernel and
 # is reported as null.
 BLUR_TRAFFIC = {
-    "kernel": "blur_kernel<8, 64, 8, 1, 16, float, float, float, EpiStoreF32>",
+    "kernel": "blur_kernel<4, EpiStoreF32>",          # VALU tile shape 4 = (8, 64, 8, 1)
     "fetch_kib_raw": 4114.7, "write_kib_raw": 4096.0,       # per launch, as counted
     "fetch_scale": 1.99978, "write_scale": 1.0,              # copy bytes / counter
     "bytes_per_launch": 12620340,
@@ -68,18 +69,28 @@ def blur_flops(n: int, k: int) -> float:
 def blur_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("blur_core.h", "blur.hip"):
+    for f in ("blur_core.h", "blur.hip", "blur_mfma.hip"):
         with open(os.path.join(ROOT, "paper_2311_15393_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def blur_traffic():
-    """Counter-measured HBM bytes per forward-blur launch, or None when no
-    measurement exists for the current blur sources."""
-    if BLUR_TRAFFIC is None or BLUR_TRAFFIC["sources_sha256"] != blur_sources_sha256():
+def blur_traffic(kernel: str):
+    """Counter-measured HBM bytes per forward-blur launch of `kernel`, or None
+    when no measurement exists for it and the current blur sources."""
+    if (BLUR_TRAFFIC is None or BLUR_TRAFFIC["kernel"] != kernel
+            or BLUR_TRAFFIC["sources_sha256"] != blur_sources_sha256()):
         return None
     return BLUR_TRAFFIC["bytes_per_launch"]
+
+
+def mfma_blur_flops(n: int, k: int) -> float:
+    """FP16 MFMA flops the MFMA blur issues per launch: per 64 x 64 tile, 4
+    waves x K tap rows x NCH chunks x 4 blocks x 3 split products of
+    16x16x32 (16384 flop)."""
+    nch = (k + 15 + 31) // 32
+    tiles = ((n + 63) // 64) ** 2
+    return tiles * 4.0 * k * nch * 4 * 3 * 16384
 
 
 def cpu_threads() -> int:
@@ -222,7 +233,7 @@ def main():
         log(f"[bench] {name}: tol={tol:.0e} iters={info.iters} err={err:.2e} "
             f"{ms:.3f} ms/solve")
 
-    # dominant kernel: the direct-convolution matvec (two per iteration)
+    # dominant kernel: the blur matvec (two per iteration), as autotuned
     p = torch.randn((n, n), device=dev, dtype=torch.float32)
     q = torch.empty_like(p)
     plan.time_blur(p, q, reps=3)
@@ -243,6 +254,28 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
+
+    if pinfo["blur_config"] == 6:
+        kname = f"blur_mfma_kernel<{(k + 46) // 32}, EpiStoreF32>"
+        issued = mfma_blur_flops(n, k) / (blur_ms * 1e-3)
+        roofline = {
+            "bound": "mfma", "achieved": achieved / 1e12, "peak": FP16_MFMA_PEAK / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / FP16_MFMA_PEAK,
+            "traffic": blur_traffic(kname),
+            "kernel": kname + " (A p on FP16-split MFMA; achieved = algorithmic convolution "
+                              "flops / time)",
+            "avg_us": blur_ms * 1e3,
+            "mfma_issued_tflops": issued / 1e12, "mfma_issued_frac": issued / FP16_MFMA_PEAK,
+        }
+    else:
+        kname = "blur_kernel<{}, EpiStoreF32>".format(pinfo["blur_config"])
+        roofline = {
+            "bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VALU_PEAK / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK,
+            "traffic": blur_traffic(kname),
+            "kernel": kname + " (direct convolution A p, FP32 VALU)",
+            "avg_us": blur_ms * 1e3,
+        }
 
     cpu_baseline = None
     if not args.profile_only and not args.no_cpu_baseline:
@@ -294,12 +327,7 @@ def main():
             "learned_lambda": learned,
             "batched": batch,
         },
-        "roofline": {
-            "bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VALU_PEAK / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK, "traffic": blur_traffic(),
-            "kernel": "blur_kernel (direct convolution A p, FP32)",
-            "avg_us": blur_ms * 1e3,
-        },
+        "roofline": roofline,
         "cpu_baseline": cpu_baseline,
     }
     print(json.dumps(line), flush=True)

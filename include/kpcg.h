@@ -373,6 +373,13 @@ int kp_time_blur(kp_plan_t plan, const float *x, float *y, int transpose,
 int kp_time_precond(kp_plan_t plan, const float *r, double lambda, int mode,
                     float *z, int reps, float *avg_ms, void *stream);
 
+/* Blur kernel used by pcg_solve and kp_blur: 0..5 are FP32-VALU tile shapes,
+   6 the FP16-split MFMA kernel; kp_setup's autotuner picks the fastest.
+   kp_set_blur_config overrides the choice (cfg in 0..6; *prev, if not NULL,
+   receives the previous one). */
+#define KP_BLUR_MFMA 6
+int kp_set_blur_config(kp_plan_t plan, int cfg, int *prev);
+
 /* Copy the FP64 singular values s_c, s_r (host arrays of n) and, if not
    NULL, V_c, V_r as FP64 row-major n x n host arrays (V[i*n + a] = V(i,a)). */
 int kp_get_factors(kp_plan_t plan, double *sc, double *sr, double *vc,

@@ -520,7 +520,7 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
     const Plan& P = *plans[plan_of_item[i]];
     ItemDesc& d = B.h_items[i];
     std::memset(&d, 0, sizeof(d));
-    const int n = P.n, cfg = P.blur_cfg;
+    const int n = P.n, cfg = P.blur_cfg_valu;
     d.n = n; d.k = P.k; d.kq = P.kq; d.prec = B.prec;
     int tw, th;
     size_t lds;

@@ -69,6 +69,8 @@ static hipError_t blur_dispatch(int cfg, const Plan& P, const float* src, const 
                                 Epi epi, Ctrl* ctrl, int skip, hipStream_t s, int* nb) {
   const int n = P.n;
   switch (cfg) {
+    case BLUR_CFG_MFMA: *nb = mfma_blocks(n);
+      return launch_blur_mfma(P, src, taps == P.taps32, epi, ctrl, skip, s);
     case 1: *nb = blur_blocks<KP_CFG1>(n);
       return run_blur<KP_CFG1, float, float, float>(P, src, taps, epi, ctrl, skip, s);
     case 2: *nb = blur_blocks<KP_CFG2>(n);
@@ -101,8 +103,9 @@ hipError_t launch_blur_normal(const Plan& P, const float* q, const float* p, flo
   return launch_scalar(P, SC_ALPHA, nb, s);
 }
 
-// Autotuner: time every FP32 tile shape on this plan's (n, K) and keep the
-// fastest (3 timed launches each after one warm-up; scratch vectors p, q).
+// Autotuner: time every FP32-VALU tile shape and the MFMA kernel on this
+// plan's (n, K) and keep the fastest (3 timed launches each after one
+// warm-up; scratch vectors p, q); the batched path uses the fastest VALU shape.
 hipError_t autotune_blur(Plan& P, hipStream_t s, float* times_ms) {
   hipEvent_t e0, e1;
   hipError_t err = hipEventCreate(&e0);
@@ -110,9 +113,9 @@ hipError_t autotune_blur(Plan& P, hipStream_t s, float* times_ms) {
   err = hipEventCreate(&e1);
   if (err != hipSuccess) return err;
   err = hipMemsetAsync(P.p, 0, sizeof(float) * (size_t)P.n * P.n, s);
-  int best = 0;
-  float best_ms = 1e30f;
-  for (int c = 0; c < NUM_BLUR_CFG && err == hipSuccess; ++c) {
+  int best = 0, best_valu = 0;
+  float best_ms = 1e30f, best_valu_ms = 1e30f;
+  for (int c = 0; c <= BLUR_CFG_MFMA && err == hipSuccess; ++c) {
     EpiStoreF32 e{P.q, P.n};
     int nb;
     err = blur_dispatch(c, P, P.p, P.taps32_flip, e, nullptr, 0, s, &nb);
@@ -130,10 +133,15 @@ hipError_t autotune_blur(Plan& P, hipStream_t s, float* times_ms) {
       best_ms = ms;
       best = c;
     }
+    if (err == hipSuccess && c < NUM_BLUR_CFG && ms < best_valu_ms) {
+      best_valu_ms = ms;
+      best_valu = c;
+    }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   P.blur_cfg = best;
+  P.blur_cfg_valu = best_valu;
   return err;
 }
 

@@ -190,7 +190,8 @@ __device__ inline void blur_tile(const In* __restrict__ src, const Tap* __restri
 #define KP_CFG3 16, 16, 8, 1    // 128 x 16 tile, 256 threads
 #define KP_CFG4 8, 64, 8, 1     // 64 x 64 tile, 512 threads
 #define KP_CFG5 16, 16, 4, 2    // 64 x 32 tile, 256 threads, 4 x 2 per thread
-constexpr int NUM_BLUR_CFG = 6;
+constexpr int NUM_BLUR_CFG = 6;        // FP32-VALU tile shapes
+constexpr int BLUR_CFG_MFMA = 6;       // the MFMA kernel (blur_mfma.hip)
 constexpr int BC = 16;
 // FP32 input, FP64 accumulation (right-hand side)
 #define KP_F32_CFG KP_CFG0
@@ -206,5 +207,10 @@ __host__ __device__ inline int lds_width(int kq) {
   w = (w + NV - 1) / NV * NV;
   return w;
 }
+
+// the MFMA blur (blur_mfma.hip): A^T if transpose, else A
+template <class Epi>
+hipError_t launch_blur_mfma(const Plan& P, const float* src, bool transpose, Epi epi,
+                            Ctrl* ctrl, int skip, hipStream_t s);
 
 }  // namespace kpcg

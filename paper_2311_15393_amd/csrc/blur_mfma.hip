@@ -1,0 +1,236 @@
+// The blur matvecs (A p and A^T q, Section 5.2: the most expensive part of an
+// iteration) on FP16 MFMA with a two-term split of both operands.
+//
+//     out[i][j] = sum_{a,b < K} Q[a][b] in[i + a - h][j + b - h]
+//
+// For each tap row a, a 16 x 16 block of outputs is a product of the 16 x 32
+// input windows (row-shifted by a) with the banded Toeplitz 32 x 16 matrices
+// T_{a,t}[k][c] = Q[a][32 t + k - c], t = 0 .. NCH-1, NCH = ceil((K+15)/32);
+// T_{a,t} does not depend on where the block sits, so its MFMA fragments are
+// built once per plan (mfma_taps_kernel).  v_mfma_f32_16x16x32_f16 takes the
+// inputs and taps as hi + lo FP16 pairs (power-of-two scaled: per tile for the
+// input, per plan for the taps, so the hi parts sit in [2^13, 2^14)), and the
+// three products hi*hi, hi*lo, lo*hi accumulate in FP32.  FP16 x FP16
+// products are exact in FP32, so the only extra error over an FP32 direct
+// convolution is the dropped lo*lo term (2^-22 relative) and FP16 underflow of
+// entries below 2^-27 of their tile's largest.
+//
+// Workgroup: 64 x 64 outputs, 4 waves of 16 rows x 64 columns.  The
+// (64+K-1) x (48+32 NCH) input tile is staged in LDS as hi and lo planes;
+// per tap row a wave reads 8 A-fragment pairs from LDS, 2 NCH tap fragments
+// from the L2-resident table, and issues 12 NCH MFMAs.
+#include "blur_core.h"
+
+namespace kpcg {
+
+typedef _Float16 mh8_t __attribute__((ext_vector_type(8)));
+typedef float mf4_t __attribute__((ext_vector_type(4)));
+
+constexpr int MB_TM = 64, MB_TN = 64, MB_NT = 256;
+
+__host__ __device__ constexpr int mb_width(int nch) { return MB_TN - 16 + 32 * nch; }
+__host__ __device__ constexpr int mb_pitch(int nch) { return mb_width(nch) + 8; }
+inline size_t mb_lds_bytes(int nch, int K) {
+  return (size_t)2 * (MB_TM + K - 1) * mb_pitch(nch) * sizeof(_Float16);
+}
+
+// tap fragments: entry ((a * nch + t) * 2 + part) * 64 + lane holds the 8
+// halves T_{a,t}[8 g + e][c] (c = lane mod 16, g = lane div 16), part 0 = hi,
+// 1 = lo of Q * 2^exq
+__global__ __launch_bounds__(256) void mfma_taps_kernel(const float* __restrict__ taps, int K,
+                                                        int KQ, int nch, int exq,
+                                                        mh8_t* __restrict__ out) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= K * nch * 2 * 64) return;
+  const int lane = idx & 63;
+  int rest = idx >> 6;
+  const int part = rest & 1;
+  rest >>= 1;
+  const int t = rest % nch, a = rest / nch;
+  const int c = lane & 15, g = lane >> 4;
+  mh8_t v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int b = 32 * t + 8 * g + e - c;
+    const float q = (b >= 0 && b < K) ? taps[a * KQ + b] : 0.0f;
+    const float s = ldexpf(q, exq);
+    const _Float16 hi = (_Float16)s;
+    v[e] = part == 0 ? hi : (_Float16)(s - (float)hi);
+  }
+  out[idx] = v;
+}
+
+template <int NCH, class Epi>
+__global__ __launch_bounds__(MB_NT) void blur_mfma_kernel(const float* __restrict__ src,
+                                                          const mh8_t* __restrict__ bfrag,
+                                                          int n, int K, int exq, Epi epi,
+                                                          Ctrl* ctrl, int skip_if_done,
+                                                          double* partials) {
+  extern __shared__ __align__(16) unsigned char mb_lds[];
+  if (skip_if_done && ctrl->done != RUNNING) return;
+  constexpr int W = mb_width(NCH), PITCH = mb_pitch(NCH);
+  constexpr int NU = 4 + 2 * (NCH - 1);       // distinct 16-column window offsets
+  const int h = (K - 1) >> 1;
+  const int rows = MB_TM + K - 1;
+  const int cvalid = MB_TN + K - 1;
+  const int i0 = blockIdx.y * MB_TM, j0 = blockIdx.x * MB_TN;
+  _Float16* shi = reinterpret_cast<_Float16*>(mb_lds);
+  _Float16* slo = shi + rows * PITCH;
+  __shared__ float red[MB_NT / 64];
+
+  // input scale: 2^ex with the tile's largest |x| * 2^ex in [2^13, 2^14)
+  float mx = 0.0f;
+  for (int idx = threadIdx.x; idx < rows * W; idx += MB_NT) {
+    const int r = idx / W, c = idx - r * W;
+    const int gi = i0 - h + r, gj = j0 - h + c;
+    if (c < cvalid && (unsigned)gi < (unsigned)n && (unsigned)gj < (unsigned)n)
+      mx = fmaxf(mx, fabsf(src[(size_t)gi * n + gj]));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  const int ex = (mx > 0.0f && mx <= 3.0e38f) ? 13 - ilogbf(mx) : 0;
+  for (int idx = threadIdx.x; idx < rows * W; idx += MB_NT) {
+    const int r = idx / W, c = idx - r * W;
+    const int gi = i0 - h + r, gj = j0 - h + c;
+    float v = 0.0f;
+    if (c < cvalid && (unsigned)gi < (unsigned)n && (unsigned)gj < (unsigned)n)
+      v = ldexpf(src[(size_t)gi * n + gj], ex);
+    const _Float16 hi = (_Float16)v;
+    shi[r * PITCH + c] = hi;
+    slo[r * PITCH + c] = (_Float16)(v - (float)hi);
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 15, g = lane >> 4;
+  mf4_t acc[4];
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) acc[jb] = mf4_t{0.f, 0.f, 0.f, 0.f};
+
+  mh8_t bh[NCH], bl[NCH];
+#pragma unroll
+  for (int t = 0; t < NCH; ++t) {
+    bh[t] = bfrag[(t * 2 + 0) * 64 + lane];
+    bl[t] = bfrag[(t * 2 + 1) * 64 + lane];
+  }
+  for (int a = 0; a < K; ++a) {
+    // next tap row's fragments in flight during this row's MFMAs
+    mh8_t nh[NCH], nl[NCH];
+    const int an = a + 1 < K ? a + 1 : a;
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+      nh[t] = bfrag[((an * NCH + t) * 2 + 0) * 64 + lane];
+      nl[t] = bfrag[((an * NCH + t) * 2 + 1) * 64 + lane];
+    }
+    const int off = (w * 16 + a + m) * PITCH + 8 * g;
+    mh8_t ah[NU], al[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      ah[u] = *reinterpret_cast<const mh8_t*>(shi + off + 16 * u);
+      al[u] = *reinterpret_cast<const mh8_t*>(slo + off + 16 * u);
+    }
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bh[t], acc[jb], 0, 0, 0);
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bl[t], acc[jb], 0, 0, 0);
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[jb + 2 * t], bh[t], acc[jb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+      bh[t] = nh[t];
+      bl[t] = nl[t];
+    }
+  }
+
+  const float oscale = ldexpf(1.0f, -(ex + exq));
+  double d = 0.0;
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) {
+    const int j = j0 + 16 * jb + m;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + w * 16 + 4 * g + v;
+      if (i < n && j < n) {
+        const float val = acc[jb][v] * oscale;
+        epi.row(i, j, 1, &val, d);
+      }
+    }
+  }
+  if constexpr (Epi::kReduce) {
+    __shared__ double sh[MB_NT / 64];
+    const double s = block_sum<MB_NT>(d, sh);
+    if (threadIdx.x == 0)
+      partials[Epi::kSlot * MAX_PARTIALS + blockIdx.y * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+int mfma_nch(int K) { return (K + 15 + 31) / 32; }
+
+size_t mfma_taps_count(int K) { return (size_t)K * mfma_nch(K) * 2 * 64; }
+
+hipError_t build_mfma_taps(const Plan& P, hipStream_t s) {
+  const int K = P.k, nch = mfma_nch(K);
+  const size_t cnt = mfma_taps_count(K);
+  const unsigned blocks = (unsigned)((cnt + 255) / 256);
+  mh8_t* tab = reinterpret_cast<mh8_t*>(P.mfma_taps);
+  hipLaunchKernelGGL(mfma_taps_kernel, dim3(blocks), dim3(256), 0, s, P.taps32, K, P.kq, nch,
+                     P.mfma_exq, tab);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mfma_taps_kernel, dim3(blocks), dim3(256), 0, s, P.taps32_flip, K, P.kq,
+                     nch, P.mfma_exq, tab + cnt);
+  return hipGetLastError();
+}
+
+template <int NCH, class Epi>
+static hipError_t run_mfma(const Plan& P, const float* src, const mh8_t* tab, Epi epi,
+                           Ctrl* ctrl, int skip, hipStream_t s) {
+  const int n = P.n;
+  dim3 grid((n + MB_TN - 1) / MB_TN, (n + MB_TM - 1) / MB_TM);
+  if ((long)grid.x * grid.y > MAX_PARTIALS) return hipErrorInvalidValue;
+  const size_t lds = mb_lds_bytes(NCH, P.k);
+  auto kern = blur_mfma_kernel<NCH, Epi>;
+  if (lds > 65536) {
+    static size_t granted = 65536;      // once per instantiation, the largest K seen
+    if (lds > granted) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      granted = lds;
+    }
+  }
+  hipLaunchKernelGGL(kern, grid, dim3(MB_NT), lds, s, src, tab, n, P.k, P.mfma_exq, epi, ctrl,
+                     skip, P.partials);
+  return hipGetLastError();
+}
+
+int mfma_blocks(int n) { return ((n + MB_TN - 1) / MB_TN) * ((n + MB_TM - 1) / MB_TM); }
+
+// transpose: A^T (taps32, table 0), else A (taps32_flip, table 1)
+template <class Epi>
+hipError_t launch_blur_mfma(const Plan& P, const float* src, bool transpose, Epi epi,
+                            Ctrl* ctrl, int skip, hipStream_t s) {
+  const mh8_t* tab = reinterpret_cast<const mh8_t*>(P.mfma_taps) +
+                     (transpose ? 0 : mfma_taps_count(P.k));
+  switch (mfma_nch(P.k)) {
+    case 1: return run_mfma<1>(P, src, tab, epi, ctrl, skip, s);
+    case 2: return run_mfma<2>(P, src, tab, epi, ctrl, skip, s);
+    default: return run_mfma<3>(P, src, tab, epi, ctrl, skip, s);
+  }
+}
+
+template hipError_t launch_blur_mfma<EpiStoreF32>(const Plan&, const float*, bool, EpiStoreF32,
+                                                  Ctrl*, int, hipStream_t);
+template hipError_t launch_blur_mfma<EpiNormalW>(const Plan&, const float*, bool, EpiNormalW,
+                                                 Ctrl*, int, hipStream_t);
+
+}  // namespace kpcg

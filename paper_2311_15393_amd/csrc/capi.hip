@@ -9,6 +9,7 @@
 #include <new>
 #include <vector>
 
+#include "blur_core.h"
 #include "capi_internal.h"
 
 using namespace kpcg;
@@ -46,6 +47,7 @@ size_t layout(int n, int k, char* base, Plan* P) {
   Q.taps32_flip = b.take<float>((size_t)k * kq);
   Q.taps64 = b.take<double>((size_t)k * kq);
   Q.taps64_flip = b.take<double>((size_t)k * kq);
+  Q.mfma_taps = b.take<uint8_t>(2 * mfma_taps_count(k) * 16);
   Q.sc = b.take<double>(n);
   Q.sr = b.take<double>(n);
   Q.sc2 = b.take<float>(n);
@@ -609,6 +611,13 @@ int kp_time_precond(kp_plan_t plan, const float* r, double lambda, int mode, flo
   hipEventDestroy(e1);
   *avg_ms = ms / reps;
   return rc;
+}
+
+int kp_set_blur_config(kp_plan_t plan, int cfg, int* prev) {
+  if (!plan || cfg < 0 || cfg > BLUR_CFG_MFMA) return KP_ERR_ARG;
+  if (prev) *prev = plan->P.blur_cfg;
+  plan->P.blur_cfg = cfg;
+  return KP_OK;
 }
 
 int kp_get_factors(kp_plan_t plan, double* sc, double* sr, double* vc, double* vr) {

@@ -139,6 +139,10 @@ struct Plan {
   float* taps32_flip = nullptr;
   double* taps64 = nullptr;
   double* taps64_flip = nullptr;
+  // MFMA fragments of the banded Toeplitz tap blocks (blur_mfma.hip): the
+  // table for taps32, then the one for taps32_flip; taps scaled by 2^mfma_exq
+  void* mfma_taps = nullptr;
+  int mfma_exq = 0;
 
   // KP-SVD factors
   double* sc = nullptr;          // singular values of A_c (descending)
@@ -177,8 +181,9 @@ struct Plan {
   double* partials = nullptr;
   Ctrl* host_ctrl = nullptr;     // pinned
 
-  int blur_cfg = 0;              // tile shape of the FP32 blur (autotuned)
-  float blur_times[8] = {};      // autotuner timings (ms) per shape
+  int blur_cfg = 0;              // blur kernel (autotuned; BLUR_CFG_MFMA = MFMA)
+  int blur_cfg_valu = 0;         // fastest FP32-VALU tile shape (batched path)
+  float blur_times[8] = {};      // autotuner timings (ms) per candidate
 
   // properties
   double kp_err = 0.0;
@@ -229,6 +234,13 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
                   const int* plan_of_item, int nitems, double tol, int maxit, int mode,
                   float* const* x, kp_info_t* infos, hipStream_t user_stream);
 hipError_t launch_spectral_gemms(const Plan& P, const float* b, float* out, hipStream_t s);
+
+// MFMA blur (blur_mfma.hip): chunks per tap row, table entries per
+// orientation (16 bytes each), workgroups per launch, table construction
+int mfma_nch(int K);
+size_t mfma_taps_count(int K);
+int mfma_blocks(int n);
+hipError_t build_mfma_taps(const Plan& P, hipStream_t s);
 
 hipError_t launch_spectrum(const Plan& P, const float* b, hipStream_t s);
 hipError_t launch_spectral_scores(const Plan& P, const double* grid_dev, int ngrid,

@@ -240,6 +240,13 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
   // blur taps
   hipLaunchKernelGGL(taps_kernel, dim3((K * P.kq + 255) / 256), dim3(256), 0, s, dpsf, K, P.kq,
                      P.taps32, P.taps32_flip, P.taps64, P.taps64_flip);
+  {
+    // MFMA tap fragments, scaled so the largest |tap| sits in [2^13, 2^14)
+    float mx = 0.0f;
+    for (int i = 0; i < K * K; ++i) mx = std::fmax(mx, std::fabs((float)psf_host[i]));
+    P.mfma_exq = mx > 0.0f ? 13 - std::ilogb(mx) : 0;
+    HCHK(build_mfma_taps(P, s));
+  }
   HCHK(hipGetLastError());
 
   // weighted PSF SVD

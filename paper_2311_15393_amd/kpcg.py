@@ -25,6 +25,7 @@ KP_WARM = 0x100
 KP_BATCH_EAGER = 0x200
 KP_NO_FALLBACK = 0x400
 KP_MAX_PSF = 63
+KP_BLUR_MFMA = 6
 KP_MLP_NFEAT, KP_MLP_HIDDEN, KP_MLP_NPARAM = 128, 256, 164865
 
 
@@ -85,6 +86,7 @@ _SIGS = {
                                     ctypes.POINTER(ctypes.c_float), _VP]),
     "kp_time_precond": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP,
                                        ctypes.c_int, ctypes.POINTER(ctypes.c_float), _VP]),
+    "kp_set_blur_config": (ctypes.c_int, [_VP, ctypes.c_int, _VP]),
     "opt_lambda": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP, _VP]),
     "kp_features": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "mlp_workspace_size": (ctypes.c_size_t, [ctypes.c_int]),
@@ -323,6 +325,14 @@ class Plan:
                                       _dev_image(z, self.n, "z"), int(reps), ctypes.byref(ms),
                                       _stream(stream)), "kp_time_precond")
         return float(ms.value)
+
+    def set_blur_config(self, cfg: int) -> int:
+        """kp_set_blur_config: force the blur kernel (0..5 VALU shapes, 6 MFMA);
+        returns the previous choice."""
+        prev = ctypes.c_int()
+        _check(load().kp_set_blur_config(self._h, int(cfg), ctypes.byref(prev)),
+               "kp_set_blur_config")
+        return prev.value
 
     def precond(self, r, lam: float, mode: int, z, stream=None):
         _check(load().kp_precond(self._h, _dev_image(r, self.n, "r"), float(lam), int(mode),

@@ -31,17 +31,31 @@ BLUR_CASES = [(64, 15, "gauss"), (100, 15, "rand"), (256, 31, "gauss"), (131, 63
 
 
 @pytest.mark.parametrize("n,k,kind", BLUR_CASES)
-def test_blur_matches_oracle(n, k, kind):
-    """FP32 direct convolution vs FP64: |y - y64| <= gamma_{K^2} (|P| * |x|)
-    + u |y| elementwise (any summation order, FP32 products and sums)."""
+@pytest.mark.parametrize("cfg", [0, 6])
+def test_blur_matches_oracle(n, k, kind, cfg):
+    """Blur vs FP64, elementwise.
+    VALU shapes (cfg 0..5), FP32 products and sums in any order:
+        |y - y64| <= gamma_{K^2+1} (|P| * |x|) + u |y|.
+    MFMA kernel (cfg 6): x and P are split into FP16 hi + lo (scaled by
+    powers of two), the hi*hi, hi*lo, lo*hi products are exact in FP32 and
+    summed in FP32 (3 K^2 terms); the representation error and the dropped
+    lo*lo term are each at most 2^-22 relative per product, and FP16
+    underflow costs at most 2^-25 of the scaled unit per entry:
+        |y - y64| <= (gamma_{3K^2+1} + 2^-20) (|P| * |x|) + u |y|
+                     + 2^-30 max|x| sum|P|."""
     torch = require_gpu()
     from paper_2311_15393_amd import Plan
-    say(f"blur n={n} k={k} {kind}")
+    say(f"blur n={n} k={k} {kind} cfg={cfg}")
     psf = _psf(kind, k, n)
     x = S.random_image(np.random.default_rng(n + k), n)
     xd = to_dev(x)
-    g = (k * k + 1) * U32 / (1 - (k * k + 1) * U32)
+    if cfg == 6:
+        t = 3 * k * k + 1
+        g = t * U32 / (1 - t * U32) + 2.0 ** -20
+    else:
+        g = (k * k + 1) * U32 / (1 - (k * k + 1) * U32)
     with Plan(psf, n) as plan:
+        plan.set_blur_config(cfg)
         for tr in (False, True):
             y = torch.empty_like(xd)
             plan.blur(xd, y, transpose=tr)
@@ -50,7 +64,52 @@ def test_blur_matches_oracle(n, k, kind):
             ref = O.blur_t(psf, x64) if tr else O.blur(psf, x64)
             absref = O.blur_t(np.abs(psf), np.abs(x64)) if tr else O.blur(np.abs(psf), np.abs(x64))
             bound = g * absref + U32 * np.abs(ref)
+            if cfg == 6:
+                bound = bound + 2.0 ** -30 * np.abs(x64).max() * np.abs(psf).sum()
             assert np.all(np.abs(got - ref) <= bound), (tr, np.max(np.abs(got - ref) / bound))
+
+
+def test_blur_mfma_high_dynamic_range():
+    """MFMA blur on an image whose tiles mix values of 1 and 1e-6 (worst case
+    for a per-tile scale): the error stays within the MFMA bound above."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_BLUR_MFMA, Plan
+    n, k = 200, 31
+    psf = _psf("moffat", k, 4)
+    rng = np.random.default_rng(3)
+    x = (rng.uniform(0, 1, (n, n)) * np.where(rng.uniform(size=(n, n)) < 0.5, 1.0, 1e-6))
+    x = x.astype(np.float32)
+    t = 3 * k * k + 1
+    g = t * U32 / (1 - t * U32) + 2.0 ** -20
+    with Plan(psf, n) as plan:
+        plan.set_blur_config(KP_BLUR_MFMA)
+        y = torch.empty_like(to_dev(x))
+        plan.blur(to_dev(x), y)
+        x64 = x.astype(np.float64)
+        ref = O.blur(psf, x64)
+        bound = (g * O.blur(np.abs(psf), np.abs(x64)) + U32 * np.abs(ref)
+                 + 2.0 ** -30 * np.abs(x64).max() * np.abs(psf).sum())
+        err = np.abs(to_host(y) - ref)
+        say(f"hdr: max err/bound {np.max(err / bound):.3f}")
+        assert np.all(err <= bound)
+
+
+@pytest.mark.parametrize("cfg", [0, 6])
+def test_solve_with_each_blur_kernel(cfg):
+    """The FP16-KP FPCG solve at 256^2 reaches the same x_lambda with the VALU
+    and the MFMA blur."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, Plan
+    from oracle import solvers as SV
+    prob = S.mid_anisotropic(0)
+    with Plan(prob.psf, prob.n) as plan:
+        plan.set_blur_config(cfg)
+        x, info = plan.solve(to_dev(prob.b), prob.lam, tol=1e-7, maxit=3000,
+                             mode=KP_FPCG | KP_P16)
+    ref = SV.x_lambda(prob.psf, prob.b.astype(np.float64), prob.lam)
+    err = rel(to_host(x), ref)
+    say(f"cfg={cfg}: iters={info.iters} err={err:.2e}")
+    assert info.status == KP_OK and err <= 1e-4
 
 
 @pytest.mark.parametrize("n,k", [(64, 15), (100, 31), (256, 63)])
