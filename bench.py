@@ -45,11 +45,11 @@ COPY_CALIB_FLOATS = 64 * 1024 * 1024
 # on; when the sources differ the figure no longer describes the kernel and
 # is reported as null.
 BLUR_TRAFFIC = {
-    "kernel": "blur_kernel<4, EpiStoreF32>",          # VALU tile shape 4 = (8, 64, 8, 1)
-    "fetch_kib_raw": 4114.7, "write_kib_raw": 4096.0,       # per launch, as counted
-    "fetch_scale": 1.99978, "write_scale": 1.0,              # copy bytes / counter
-    "bytes_per_launch": 12620340,
-    "sources_sha256": "747d6d8a3d8b50b3c16aed611c0fdd58cdfced48f492a5dd24470ede961c43c8",
+    "kernel": "blur_mfma_kernel<3, EpiStoreF32>",
+    "fetch_kib_raw": 5510.8, "write_kib_raw": 4096.0,       # per launch, as counted
+    "fetch_scale": 1.99977, "write_scale": 1.0,              # copy bytes / counter
+    "bytes_per_launch": 15479100,
+    "sources_sha256": "1986b91cf991a215abbb5812f4e14ac3b1553de333b23fc47eba4cd0a5c48d8a",
 }
 
 
