@@ -158,10 +158,23 @@ hipError_t launch_true_residual(const Plan& P, const double* x, double lam2, boo
   hipError_t err =
       run_blur<KP_F64IN_CFG, double, double, double>(P, x, P.taps64_flip, e1, P.ctrl, 0, s);
   if (err != hipSuccess) return err;
-  EpiTrueRes e2{P.c64, x, P.r, lam2, P.n};
+  EpiTrueRes e2{P.c64, x, P.r, lam2, P.n, P.xa64, P.ra64};
   err = run_blur<KP_F64IN_CFG, double, double, double>(P, P.y64, P.taps64, e2, P.ctrl, 0, s);
   if (err != hipSuccess) return err;
   return launch_scalar(P, fin ? SC_TRUE : SC_TRUE_INFO, blur_blocks<KP_F64IN_CFG>(P.n), s);
+}
+
+hipError_t launch_anchor_residual(const Plan& P, double lam2, bool fin, hipStream_t s) {
+  // q = fp32(x - x_a), z = A q, r = r_a - A^T z - lam2 (x - x_a)
+  hipError_t err = launch_diff32(P, P.q, s);
+  if (err != hipSuccess) return err;
+  err = launch_blur_f32(P, P.q, P.z, false, s, nullptr);
+  if (err != hipSuccess) return err;
+  EpiAnchorRes e{P.x64, P.xa64, P.ra64, P.r, lam2, P.n};
+  int nb;
+  err = blur_dispatch(P.blur_cfg, P, P.z, P.taps32, e, P.ctrl, 0, s, &nb);
+  if (err != hipSuccess) return err;
+  return launch_scalar(P, fin ? SC_TRUE : SC_TRUE_INFO, nb, s);
 }
 
 // y = (A^T A + lam2 I) x with FP64 accumulation (test entry point)

@@ -97,17 +97,46 @@ struct EpiRhs {
   }
 };
 
-// r = c - A^T y - lambda^2 x with y = A x in FP64: the true residual
+// r = c - A^T y - lambda^2 x with y = A x in FP64: the true residual; also
+// records (x, r) in FP64 as the anchor of later residuals (EpiAnchorRes)
 struct EpiTrueRes {
   const double* c64; const double* x; float* r; double lam2; int n;
+  double* xa = nullptr; double* ra = nullptr;
   static constexpr bool kReduce = true;
   static constexpr int kSlot = SLOT_TRUE;
   template <typename Acc>
   __device__ void row(int i, int j0, int cnt, const Acc* v, double& d) const {
     const size_t o = (size_t)i * n + j0;
     for (int c = 0; c < cnt; ++c) {
-      const double rv = c64[o + c] - (double)v[c] - lam2 * x[o + c];
+      const double xv = x[o + c];
+      const double rv = c64[o + c] - (double)v[c] - lam2 * xv;
       r[o + c] = (float)rv;
+      if (xa) {                        // anchor recorded unless not asked for
+        xa[o + c] = xv;
+        ra[o + c] = rv;
+      }
+      d += rv * rv;
+    }
+  }
+};
+
+// r = r_a - (A^T A dx + lambda^2 dx), dx = x - x_a: the true residual from
+// the anchor, with v = A^T A fp32(dx) from the FP32 blur and the rest in
+// FP64; the anchor moves to (x, r).  Pointwise in ra / xa, so the in-place
+// update is safe.
+struct EpiAnchorRes {
+  const double* x; double* xa; double* ra; float* r; double lam2; int n;
+  static constexpr bool kReduce = true;
+  static constexpr int kSlot = SLOT_TRUE;
+  template <typename Acc>
+  __device__ void row(int i, int j0, int cnt, const Acc* v, double& d) const {
+    const size_t o = (size_t)i * n + j0;
+    for (int c = 0; c < cnt; ++c) {
+      const double xv = x[o + c];
+      const double rv = ra[o + c] - ((double)v[c] + lam2 * (xv - xa[o + c]));
+      r[o + c] = (float)rv;
+      xa[o + c] = xv;
+      ra[o + c] = rv;
       d += rv * rv;
     }
   }

@@ -276,5 +276,7 @@ template hipError_t launch_blur_mfma<EpiStoreF32>(const Plan&, const float*, boo
                                                   Ctrl*, int, hipStream_t);
 template hipError_t launch_blur_mfma<EpiNormalW>(const Plan&, const float*, bool, EpiNormalW,
                                                  Ctrl*, int, hipStream_t);
+template hipError_t launch_blur_mfma<EpiAnchorRes>(const Plan&, const float*, bool,
+                                                   EpiAnchorRes, Ctrl*, int, hipStream_t);
 
 }  // namespace kpcg

@@ -22,6 +22,7 @@ hipError_t launch_pupdate_from(const Plan& P, const float* z, hipStream_t s);
 namespace {
 
 constexpr int TAP_CHUNK = 16;
+constexpr double ANCHOR_REL = 1e-2;
 constexpr size_t ALIGN = 256;
 
 struct Bump {
@@ -78,6 +79,8 @@ size_t layout(int n, int k, char* base, Plan* P) {
   Q.c64 = b.take<double>(nn);
   Q.y64 = b.take<double>(nn);
   Q.x64 = b.take<double>(nn);
+  Q.xa64 = b.take<double>(nn);
+  Q.ra64 = b.take<double>(nn);
   Q.t1 = b.take<float>(nn);
   Q.t2 = b.take<float>(nn);
   Q.t3 = b.take<float>(nn);
@@ -267,6 +270,7 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   const size_t N = (size_t)P.n * P.n;
   const double lam2d = lambda * lambda;
   const float lam2 = (float)lam2d;
+  double hc_gamma0sq = 0.0;
 
   Ctrl c;
   std::memset(&c, 0, sizeof(c));
@@ -287,6 +291,16 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   else HIPCHK(hipMemsetAsync(P.x64, 0, N * sizeof(double), s));
 
   int replacements = 0;
+  // After an FP64 true residual r_a at x_a, later ones are computed as
+  // r_a - H (x - x_a) with FP32 matvecs on the small step x - x_a: exact in
+  // exact arithmetic, with an error of ~1e-6 ||r_a||.  Used once
+  // ||r_a|| <= ANCHOR_REL ||A^T b||, so the error stays ~1e-9 ||A^T b||.
+  double anchor_rr = -1.0;                                       // none yet
+  auto true_residual = [&](bool fin) -> hipError_t {
+    if (anchor_rr >= 0.0 && anchor_rr <= ANCHOR_REL * ANCHOR_REL * hc_gamma0sq)
+      return launch_anchor_residual(P, lam2d, fin, s);
+    return launch_true_residual(P, P.x64, lam2d, fin, s);
+  };
   HIPCHK(launch_rhs(P, b, s));                                  // c = A^T b, r = c
   if (mode & KP_WARM) {
     HIPCHK(launch_true_residual(P, P.x64, lam2d, true, s));     // r = c - H x0
@@ -294,6 +308,8 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   }
   Ctrl hc;
   if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
+  hc_gamma0sq = hc.gamma0sq;
+  if (mode & KP_WARM) anchor_rr = hc.true_rr;
   if (!(hc.gamma0sq > 0.0) || !std::isfinite(hc.gamma0sq)) {
     const bool zero = hc.gamma0sq == 0.0;
     HIPCHK(hipMemsetAsync(x, 0, N * sizeof(float), s));
@@ -322,9 +338,10 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
     if (hc.done == PENDING) {
       // the recurrence residual met the tolerance or fell 1/REPLACE_DROP:
       // recompute it in FP64 and continue from the true residual
-      HIPCHK(launch_true_residual(P, P.x64, lam2d, true, s));
+      HIPCHK(true_residual(true));
       ++replacements;
       if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
+      anchor_rr = hc.true_rr;
       if (hc.done != RUNNING) break;
       if (hc.iter >= maxit) {
         hc.done = MAXIT;
@@ -352,7 +369,7 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
 
   double true_rr = hc.true_rr;
   if (hc.done != CONVERGED) {
-    HIPCHK(launch_true_residual(P, P.x64, lam2d, false, s));
+    HIPCHK(true_residual(false));
     Ctrl t;
     if ((rc = read_ctrl(P, s, t)) != KP_OK) return rc;
     true_rr = t.true_rr;

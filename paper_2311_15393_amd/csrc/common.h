@@ -172,6 +172,8 @@ struct Plan {
   float *r = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *z = nullptr;
   double *c64 = nullptr, *y64 = nullptr;
   double* x64 = nullptr;         // FP64 solution accumulator
+  double* xa64 = nullptr;        // anchor: x and its true residual c - H x (FP64)
+  double* ra64 = nullptr;
   // preconditioner intermediates (sized for FP32)
   void *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
   uint8_t *t1s = nullptr, *t2s = nullptr, *t3s = nullptr, *rs = nullptr;  // FP8 block exponents
@@ -200,6 +202,11 @@ hipError_t launch_blur_normal(const Plan& P, const float* q, const float* p, flo
                               float lam2, hipStream_t s);
 hipError_t launch_rhs(const Plan& P, const float* b, hipStream_t s);
 hipError_t autotune_blur(Plan& P, hipStream_t s, float* times_ms);
+// r = r_a - H (x - x_a) from the anchor (x_a, r_a) of the last true residual,
+// with the FP32 blur kernels on the difference and FP64 epilogue arithmetic;
+// moves the anchor to x
+hipError_t launch_anchor_residual(const Plan& P, double lam2, bool fin, hipStream_t s);
+hipError_t launch_diff32(const Plan& P, float* d, hipStream_t s);
 hipError_t launch_true_residual(const Plan& P, const double* x64, double lam2, bool fin,
                                 hipStream_t s);
 hipError_t launch_normal_fp64(const Plan& P, const float* x, double lam2, double* y,

@@ -117,6 +117,21 @@ hipError_t launch_convert_x(const Plan& P, float* x, bool to_f32, hipStream_t s)
   return hipGetLastError();
 }
 
+// d = fp32(x - x_a): the step since the anchor
+__global__ __launch_bounds__(VT) void diff32_kernel(const double* __restrict__ x64,
+                                                    const double* __restrict__ xa64,
+                                                    float* __restrict__ d, int N) {
+  for (int i = blockIdx.x * VT + threadIdx.x; i < N; i += gridDim.x * VT)
+    d[i] = (float)(x64[i] - xa64[i]);
+}
+
+hipError_t launch_diff32(const Plan& P, float* d, hipStream_t s) {
+  const int N = P.n * P.n;
+  hipLaunchKernelGGL(diff32_kernel, dim3(vec_blocks(N >> 2)), dim3(VT), 0, s, P.x64, P.xa64, d,
+                     N);
+  return hipGetLastError();
+}
+
 hipError_t launch_pupdate_from(const Plan& P, const float* z, hipStream_t s) {
   const int N = P.n * P.n;
   hipLaunchKernelGGL(pupdate_kernel, dim3(vec_blocks(N >> 2)), dim3(VT), 0, s, P.p, z, N,
