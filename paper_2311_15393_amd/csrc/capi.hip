@@ -306,6 +306,15 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
     HIPCHK(launch_true_residual(P, P.x64, lam2d, true, s));     // r = c - H x0
     ++replacements;
   }
+  // first direction p = z_0 (CG: p = r_0) and a first block of iterations,
+  // enqueued without reading the state back: zero or non-finite data marks
+  // the solve finished on the device and the kernels then exit at once
+  int block = 4;
+  HIPCHK(enqueue_tail(P, solver, prec, lam2, s));
+  {
+    const int m = block < maxit ? block : maxit;
+    for (int it = 0; it < m; ++it) HIPCHK(enqueue_iteration(P, solver, prec, lam2, s));
+  }
   Ctrl hc;
   if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
   hc_gamma0sq = hc.gamma0sq;
@@ -322,45 +331,61 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
     return zero ? KP_OK : KP_BREAKDOWN;
   }
 
-  // first direction: p = z_0 (CG: p = r_0)
-  if (hc.done == RUNNING) HIPCHK(enqueue_tail(P, solver, prec, lam2, s));
-  if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
-
   // Iterations are enqueued in blocks; kernels enqueued after the device has
   // marked the solve finished exit at once but still cost a launch each.
   // Once a contraction rate of ||r||^2 has been observed, a block is sized
   // to reach the next stopping point (tolerance or replacement threshold).
-  int block = 4;
   double rate = 0.0;                   // mean per-iteration factor of ||r||^2
-  double rr_mark = hc.rr;
-  int it_mark = hc.iter;
+  double rr_mark = (mode & KP_WARM) ? hc.true_rr : hc.gamma0sq;
+  int it_mark = 0;
+  if (hc.iter > 0 && hc.rr > 0.0 && hc.rr < rr_mark)
+    rate = std::pow(hc.rr / rr_mark, 1.0 / hc.iter);
+  if (block < 32) block *= 2;
+  if (hc.done == RUNNING && hc.iter >= maxit) hc.done = MAXIT;
+  bool anchor_pending = false;         // true residual run since the last read
   while (hc.done == RUNNING || hc.done == PENDING) {
     if (hc.done == PENDING) {
       // the recurrence residual met the tolerance or fell 1/REPLACE_DROP:
       // recompute it in FP64 and continue from the true residual
       HIPCHK(true_residual(true));
       ++replacements;
-      if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
-      anchor_rr = hc.true_rr;
-      if (hc.done != RUNNING) break;
-      if (hc.iter >= maxit) {
-        hc.done = MAXIT;
-        break;
+      const int todo = maxit - hc.iter;
+      if (hc.rr <= hc.tol2 || todo <= 0) {
+        // may have converged (or no budget left): read before going on
+        if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
+        anchor_rr = hc.true_rr;
+        anchor_pending = false;
+        if (hc.done != RUNNING) break;
+        if (hc.iter >= maxit) {
+          hc.done = MAXIT;
+          break;
+        }
+      } else {
+        // re-anchoring away from the tolerance: continue without a round trip
+        anchor_pending = true;
       }
       HIPCHK(enqueue_tail(P, solver, prec, lam2, s));
-      rr_mark = hc.rr;
+      rr_mark = hc.rr;                 // restart the rate estimate from here
       it_mark = hc.iter;
     }
     const int todo = maxit - hc.iter;
     int m = block;
     if (rate > 0.0 && rate < 1.0 && hc.rr > 0.0) {
-      const double target = hc.tol2 > hc.repl2 ? hc.tol2 : hc.repl2;
+      // after an unread re-anchoring the device's threshold is
+      // REPLACE_DROP^2 times the new residual, which the recurrence value
+      // at the replacement approximates
+      const double repl2 = anchor_pending ? REPLACE_DROP * REPLACE_DROP * hc.rr : hc.repl2;
+      const double target = hc.tol2 > repl2 ? hc.tol2 : repl2;
       const double need = std::ceil(std::log(target / hc.rr) / std::log(rate));
       m = need < 1.0 ? 1 : (need > 32.0 ? 32 : (int)need);
     }
     m = m < todo ? m : todo;
     for (int it = 0; it < m; ++it) HIPCHK(enqueue_iteration(P, solver, prec, lam2, s));
     if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
+    if (anchor_pending) {
+      anchor_rr = hc.true_rr;
+      anchor_pending = false;
+    }
     if (hc.iter > it_mark && hc.rr > 0.0 && rr_mark > 0.0 && hc.rr < rr_mark)
       rate = std::pow(hc.rr / rr_mark, 1.0 / (hc.iter - it_mark));
     if (block < 32) block *= 2;

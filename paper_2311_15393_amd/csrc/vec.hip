@@ -222,6 +222,9 @@ __global__ __launch_bounds__(ST) void scalar_kernel(Ctrl* __restrict__ c,
       c->tol2 = c->tol_rel2 * S;
       c->repl2 = REPLACE_DROP * REPLACE_DROP * S;
       set_scales(c, S);
+      // zero data: x = 0 is the solution; non-finite data: nothing to do
+      if (!(S > 0.0)) c->done = S == 0.0 ? CONVERGED : BREAKDOWN;
+      else if (!isfinite(S)) c->done = BREAKDOWN;
       break;
     case SC_TRUE:                           // r = c - H x replaced the recurrence
       c->true_rr = S;
