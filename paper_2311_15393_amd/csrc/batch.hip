@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "blur_core.h"
+#include "blur_mfma.h"
 #include "gemm_core.h"
 
 namespace kpcg {
@@ -40,9 +41,15 @@ struct ItemDesc {
   float* x;
   float *r, *p, *q, *w, *z;
   double *x64, *c64, *y64;
+  double *xa64, *ra64;                       // anchor (x_a, r_a) of the true residuals
   void *t1, *t2, *t3;
   Ctrl* ctrl;
   double* partials;                          // [NSLOTS][MAXP_ITEM]
+  // fast blur (A p, A^T q, anchored residuals): MFMA if the plan's autotuner
+  // chose it, else its fastest VALU shape
+  int use_mfma, nch, exq, ntx_mfma, nb_fast;
+  const void* mfma_taps;                     // table for taps32, then for taps32_flip
+  size_t mfma_count;                         // entries per orientation
 };
 
 struct TileRef {
@@ -50,13 +57,19 @@ struct TileRef {
   int t;                                     // tile index within the item
 };
 
-enum RunMode : int { RM_RUNNING = 0, RM_PENDING = 1, RM_ALL = 2, RM_RESUME = 3, RM_FINISHED = 4 };
+enum RunMode : int { RM_RUNNING = 0, RM_PENDING = 1, RM_ALL = 2, RM_RESUME = 3, RM_FINISHED = 4,
+                     RM_PEND_FULL = 5, RM_PEND_ANCH = 6 };
+
+// batched scalar kind: true residual from the anchor (fast-blur partials)
+constexpr int SC_TRUE_ANCH = 100;
 
 __device__ inline bool item_active(const Ctrl* c, int mode) {
   const int d = c->done;
   switch (mode) {
     case RM_RUNNING: return d == RUNNING;
     case RM_PENDING: return d == PENDING;
+    case RM_PEND_FULL: return d == PENDING && !c->anchor;
+    case RM_PEND_ANCH: return d == PENDING && c->anchor;
     case RM_RESUME: return d == RUNNING && c->resume;
     case RM_FINISHED: return d == MAXIT || d == BREAKDOWN;
     default: return true;
@@ -67,7 +80,7 @@ __device__ inline bool item_active(const Ctrl* c, int mode) {
 // batched blur
 // ---------------------------------------------------------------------------
 enum BlurKind : int { BK_A = 0, BK_AT_NORMAL = 1, BK_RHS = 2, BK_TRUE1 = 3, BK_TRUE2 = 4,
-                      BK_MISFIT = 5 };
+                      BK_MISFIT = 5, BK_ANC1 = 6, BK_ANC2 = 7 };
 
 // ||A x - b||^2 for the data-misfit report
 struct EpiMisfit {
@@ -102,7 +115,7 @@ __global__ __launch_bounds__(TX* TY) void blur_batched_kernel(const ItemDesc* __
       blur_tile<TX, TY, RX, RY, BC, double, double, double, EpiStoreF64>(
           it.x64, it.taps64_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, out);
     } else {
-      EpiTrueRes e{it.c64, it.x64, it.r, it.lam2, n};
+      EpiTrueRes e{it.c64, it.x64, it.r, it.lam2, n, it.xa64, it.ra64};
       blur_tile<TX, TY, RX, RY, BC, double, double, double, EpiTrueRes>(
           it.y64, it.taps64, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, out);
     }
@@ -118,6 +131,15 @@ __global__ __launch_bounds__(TX* TY) void blur_batched_kernel(const ItemDesc* __
       blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiNormalW>(
           it.q, it.taps32, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
           it.partials + SLOT_DELTA * MAXP_ITEM + tr.t);
+    } else if constexpr (KIND == BK_ANC1) {
+      EpiStoreF32 e{it.z, n};
+      blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiStoreF32>(
+          it.q, it.taps32_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, nullptr);
+    } else if constexpr (KIND == BK_ANC2) {
+      EpiAnchorRes e{it.x64, it.xa64, it.ra64, it.r, it.lam2, n};
+      blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiAnchorRes>(
+          it.z, it.taps32, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
+          it.partials + SLOT_TRUE * MAXP_ITEM + tr.t);
     } else if constexpr (KIND == BK_RHS) {
       EpiRhs e{it.c64, it.r, n};
       blur_tile<TX, TY, RX, RY, BC, float, double, double, EpiRhs>(
@@ -129,6 +151,36 @@ __global__ __launch_bounds__(TX* TY) void blur_batched_kernel(const ItemDesc* __
           it.x, it.taps64_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
           it.partials + SLOT_NORM * MAXP_ITEM + tr.t);
     }
+  }
+}
+
+// the MFMA blur over the tile table (items whose plan chose it), 64 x 64 tiles
+template <int NCH, int KIND>
+__global__ __launch_bounds__(MB_NT) void blur_mfma_batched_kernel(
+    const ItemDesc* __restrict__ items, const TileRef* __restrict__ tiles, int mode) {
+  extern __shared__ __align__(16) unsigned char mb_lds[];
+  const TileRef tr = tiles[blockIdx.x];
+  const ItemDesc& it = items[tr.item];
+  if (!item_active(it.ctrl, mode)) return;
+  const int n = it.n;
+  const int ty = tr.t / it.ntx_mfma, tx = tr.t - ty * it.ntx_mfma;
+  const mh8_t* tabT = reinterpret_cast<const mh8_t*>(it.mfma_taps);   // A^T
+  const mh8_t* tabA = tabT + it.mfma_count;                            // A
+  const int i0 = ty * MB_TM, j0 = tx * MB_TN;
+  if constexpr (KIND == BK_A) {
+    blur_mfma_tile<NCH>(it.p, tabA, n, it.k, it.exq, i0, j0, EpiStoreF32{it.q, n}, nullptr,
+                        mb_lds);
+  } else if constexpr (KIND == BK_AT_NORMAL) {
+    blur_mfma_tile<NCH>(it.q, tabT, n, it.k, it.exq, i0, j0,
+                        EpiNormalW{it.p, it.w, it.lam2f, n},
+                        it.partials + SLOT_DELTA * MAXP_ITEM + tr.t, mb_lds);
+  } else if constexpr (KIND == BK_ANC1) {
+    blur_mfma_tile<NCH>(it.q, tabA, n, it.k, it.exq, i0, j0, EpiStoreF32{it.z, n}, nullptr,
+                        mb_lds);
+  } else {
+    blur_mfma_tile<NCH>(it.z, tabT, n, it.k, it.exq, i0, j0,
+                        EpiAnchorRes{it.x64, it.xa64, it.ra64, it.r, it.lam2, n},
+                        it.partials + SLOT_TRUE * MAXP_ITEM + tr.t, mb_lds);
   }
 }
 
@@ -174,7 +226,7 @@ __global__ __launch_bounds__(GT) void gemm_batched_kernel(const ItemDesc* __rest
 // batched vector kernels (one block per VCH floats of an item)
 // ---------------------------------------------------------------------------
 enum VecKind : int { VK_UPDATE = 0, VK_PUPDATE_Z = 1, VK_PUPDATE_R = 2, VK_INIT = 3,
-                     VK_TO_F32 = 4, VK_FROM_F32 = 5 };
+                     VK_TO_F32 = 4, VK_FROM_F32 = 5, VK_DIFF = 6 };
 
 template <int KIND>
 __global__ __launch_bounds__(256) void vec_batched_kernel(const ItemDesc* __restrict__ items,
@@ -207,6 +259,8 @@ __global__ __launch_bounds__(256) void vec_batched_kernel(const ItemDesc* __rest
     }
   } else if constexpr (KIND == VK_TO_F32) {
     for (int i = e0 + threadIdx.x; i < e1; i += 256) it.x[i] = (float)it.x64[i];
+  } else if constexpr (KIND == VK_DIFF) {         // q = fp32(x - x_a)
+    for (int i = e0 + threadIdx.x; i < e1; i += 256) it.q[i] = (float)(it.x64[i] - it.xa64[i]);
   } else {
     for (int i = e0 + threadIdx.x; i < e1; i += 256) it.x64[i] = (double)it.x[i];
   }
@@ -229,7 +283,8 @@ __global__ __launch_bounds__(256) void scalar_batched_kernel(const ItemDesc* __r
   const int done = c->done;
   int slot, nb;
   switch (kind) {
-    case SC_ALPHA: slot = SLOT_DELTA; nb = it.nb_blur; break;
+    case SC_ALPHA: slot = SLOT_DELTA; nb = it.nb_fast; break;
+    case SC_TRUE_ANCH: slot = SLOT_TRUE; nb = it.nb_fast; break;
     case SC_RR: slot = SLOT_RR; nb = it.nb_vec; break;
     case SC_BETA: slot = SLOT_RZ; nb = it.nb_gemm; break;
     case SC_RHS: slot = SLOT_RHS; nb = it.nb_blur; break;
@@ -285,7 +340,9 @@ __global__ __launch_bounds__(256) void scalar_batched_kernel(const ItemDesc* __r
       if (!(S > 0.0) || !isfinite(S)) c->done = S == 0.0 ? CONVERGED : BREAKDOWN;
       break;
     case SC_TRUE:
+    case SC_TRUE_ANCH:
       c->true_rr = S;
+      c->anchor = S <= ANCHOR_REL * ANCHOR_REL * c->gamma0sq ? 1 : 0;
       c->rr = S;
       c->repl2 = REPLACE_DROP * REPLACE_DROP * S;
       set_scales(c, S);
@@ -323,7 +380,10 @@ struct Batch {
   ItemDesc* d_items = nullptr;
   // tile tables (device) and their lengths
   struct Group { int cfg; TileRef* tiles; int ntiles; size_t lds; };
-  std::vector<Group> blur_groups;            // FP32 blur, one per tile shape
+  std::vector<Group> blur_groups;            // FP32 blur, one per tile shape (all items)
+  // fast blur groups (A, A^T A, anchored residuals): cfg 0..5 VALU shapes
+  // of items without MFMA, BLUR_CFG_MFMA + nch for MFMA items
+  std::vector<Group> fast_groups;
   TileRef *t_blur64 = nullptr, *t_gemm = nullptr, *t_vec = nullptr;
   int n_blur64 = 0, n_gemm = 0, n_vec = 0;
   size_t lds64 = 0;
@@ -391,6 +451,81 @@ static hipError_t blur_groups_launch(const Batch& B, int mode) {
   return hipSuccess;
 }
 
+template <int NCH, int KIND>
+static hipError_t ensure_lds_mfma(size_t lds) {
+  static size_t granted = 65536;
+  if (lds <= granted) return hipSuccess;
+  auto kern = blur_mfma_batched_kernel<NCH, KIND>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) granted = lds;
+  return e;
+}
+
+template <int NCH, int KIND>
+static hipError_t launch_mfma_b(const Batch& B, const TileRef* tiles, int ntiles, size_t lds,
+                                int mode) {
+  if (ntiles == 0) return hipSuccess;
+  hipError_t e = ensure_lds_mfma<NCH, KIND>(lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((blur_mfma_batched_kernel<NCH, KIND>), dim3(ntiles), dim3(MB_NT), lds, B.s,
+                     B.d_items, tiles, mode);
+  return hipGetLastError();
+}
+
+// A p, A^T q (+ lambda^2 p, delta) and the anchored residual's two blurs, on
+// each item's fast blur
+template <int KIND>
+static hipError_t fast_launch(const Batch& B, int mode) {
+  for (const auto& g : B.fast_groups) {
+    hipError_t e;
+    if (g.cfg >= BLUR_CFG_MFMA) {
+      switch (g.cfg - BLUR_CFG_MFMA) {
+        case 1: e = launch_mfma_b<1, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+        case 2: e = launch_mfma_b<2, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+        default: e = launch_mfma_b<3, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+      }
+    } else {
+      switch (g.cfg) {
+        case 1: e = launch_blur_b<KP_CFG1, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+        case 2: e = launch_blur_b<KP_CFG2, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+        case 3: e = launch_blur_b<KP_CFG3, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+        case 4: e = launch_blur_b<KP_CFG4, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+        case 5: e = launch_blur_b<KP_CFG5, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+        default: e = launch_blur_b<KP_CFG0, KIND>(B, g.tiles, g.ntiles, g.lds, mode); break;
+      }
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// LDS opt-in of every fast-group kernel, before graph capture
+template <int KIND>
+static hipError_t ensure_fast(const Batch& B) {
+  for (const auto& g : B.fast_groups) {
+    hipError_t e;
+    if (g.cfg >= BLUR_CFG_MFMA) {
+      switch (g.cfg - BLUR_CFG_MFMA) {
+        case 1: e = ensure_lds_mfma<1, KIND>(g.lds); break;
+        case 2: e = ensure_lds_mfma<2, KIND>(g.lds); break;
+        default: e = ensure_lds_mfma<3, KIND>(g.lds); break;
+      }
+    } else {
+      switch (g.cfg) {
+        case 1: e = ensure_lds<KP_CFG1, KIND>(g.lds); break;
+        case 2: e = ensure_lds<KP_CFG2, KIND>(g.lds); break;
+        case 3: e = ensure_lds<KP_CFG3, KIND>(g.lds); break;
+        case 4: e = ensure_lds<KP_CFG4, KIND>(g.lds); break;
+        case 5: e = ensure_lds<KP_CFG5, KIND>(g.lds); break;
+        default: e = ensure_lds<KP_CFG0, KIND>(g.lds); break;
+      }
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <int KIND>
 static hipError_t vec_launch(const Batch& B, int mode) {
   if (B.n_vec == 0) return hipSuccess;
@@ -434,8 +569,8 @@ static hipError_t tail_b(const Batch& B, int mode) {
 
 static hipError_t iteration_b(const Batch& B) {
   hipError_t e;
-  if ((e = blur_groups_launch<BK_A>(B, RM_RUNNING)) != hipSuccess) return e;
-  if ((e = blur_groups_launch<BK_AT_NORMAL>(B, RM_RUNNING)) != hipSuccess) return e;
+  if ((e = fast_launch<BK_A>(B, RM_RUNNING)) != hipSuccess) return e;
+  if ((e = fast_launch<BK_AT_NORMAL>(B, RM_RUNNING)) != hipSuccess) return e;
   if ((e = scalar_launch(B, SC_ALPHA, RM_RUNNING)) != hipSuccess) return e;
   if ((e = vec_launch<VK_UPDATE>(B, RM_RUNNING)) != hipSuccess) return e;
   if ((e = scalar_launch(B, SC_RR, RM_RUNNING)) != hipSuccess) return e;
@@ -464,6 +599,17 @@ static hipError_t true_residual_b(const Batch& B, int mode, int kind) {
   hipLaunchKernelGGL(k2, dim3(B.n_blur64), dim3(512), B.lds64, B.s, B.d_items, B.t_blur64, mode);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return scalar_launch(B, kind, mode);
+}
+
+// true residuals of the items that asked for one: FP64 for items without a
+// usable anchor, r_a - H (x - x_a) on the fast blur for the others
+static hipError_t pending_residuals_b(const Batch& B) {
+  hipError_t e;
+  if ((e = true_residual_b(B, RM_PEND_FULL, SC_TRUE)) != hipSuccess) return e;
+  if ((e = vec_launch<VK_DIFF>(B, RM_PEND_ANCH)) != hipSuccess) return e;
+  if ((e = fast_launch<BK_ANC1>(B, RM_PEND_ANCH)) != hipSuccess) return e;
+  if ((e = fast_launch<BK_ANC2>(B, RM_PEND_ANCH)) != hipSuccess) return e;
+  return scalar_launch(B, SC_TRUE_ANCH, RM_PEND_ANCH);
 }
 
 static int read_ctrls(Batch& B) {
@@ -502,7 +648,7 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
     const size_t nn = (size_t)plans[plan_of_item[i]]->n * plans[plan_of_item[i]]->n;
     off_item[i] = total;
     total += align(nn * 4) * 5;              // r p q w z
-    total += align(nn * 8) * 3;              // x64 c64 y64
+    total += align(nn * 8) * 5;              // x64 c64 y64 xa64 ra64
     total += align(nn * 4) * 3;              // t1 t2 t3
     total += align(sizeof(double) * NSLOTS * MAXP_ITEM);
   }
@@ -514,6 +660,9 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
   // ---- tile tables (host)
   std::vector<std::vector<TileRef>> grp_tiles(NUM_BLUR_CFG);
   std::vector<size_t> grp_lds(NUM_BLUR_CFG, 0);
+  // fast groups: VALU shapes 0..5, then MFMA with nch = 1, 2, 3 (index 6 + nch - 1)
+  std::vector<std::vector<TileRef>> fast_tiles(NUM_BLUR_CFG + 3);
+  std::vector<size_t> fast_lds(NUM_BLUR_CFG + 3, 0);
   std::vector<TileRef> t64, tg, tv;
   B.h_items.resize(nitems);
   for (int i = 0; i < nitems; ++i) {
@@ -536,6 +685,23 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
     d.nb_blur = d.ntx_blur * ((n + th - 1) / th);
     for (int t = 0; t < d.nb_blur; ++t) grp_tiles[cfg].push_back(TileRef{i, t});
     grp_lds[cfg] = grp_lds[cfg] > lds ? grp_lds[cfg] : lds;
+    d.use_mfma = P.blur_cfg == BLUR_CFG_MFMA ? 1 : 0;
+    d.nch = mfma_nch(P.k);
+    d.exq = P.mfma_exq;
+    d.mfma_taps = P.mfma_taps;
+    d.mfma_count = mfma_taps_count(P.k);
+    d.ntx_mfma = (n + MB_TN - 1) / MB_TN;
+    if (d.use_mfma) {
+      const int fg = NUM_BLUR_CFG + d.nch - 1;
+      d.nb_fast = d.ntx_mfma * ((n + MB_TM - 1) / MB_TM);
+      for (int t = 0; t < d.nb_fast; ++t) fast_tiles[fg].push_back(TileRef{i, t});
+      const size_t ml = mb_lds_bytes(d.nch, P.k);
+      fast_lds[fg] = fast_lds[fg] > ml ? fast_lds[fg] : ml;
+    } else {
+      d.nb_fast = d.nb_blur;
+      for (int t = 0; t < d.nb_blur; ++t) fast_tiles[cfg].push_back(TileRef{i, t});
+      fast_lds[cfg] = fast_lds[cfg] > lds ? fast_lds[cfg] : lds;
+    }
     d.ntx_blur64 = (n + 63) / 64;
     d.nb_blur64 = d.ntx_blur64 * d.ntx_blur64;
     for (int t = 0; t < d.nb_blur64; ++t) t64.push_back(TileRef{i, t});
@@ -547,11 +713,12 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
     d.nb_vec = (n * n + VCH - 1) / VCH;
     for (int t = 0; t < d.nb_vec; ++t) tv.push_back(TileRef{i, t});
     if (d.nb_blur > MAXP_ITEM || d.nb_blur64 > MAXP_ITEM || d.nb_gemm > MAXP_ITEM ||
-        d.nb_vec > MAXP_ITEM)
+        d.nb_vec > MAXP_ITEM || d.nb_fast > MAXP_ITEM)
       return KP_ERR_UNSUPPORTED;
   }
   size_t ntab = t64.size() + tg.size() + tv.size();
   for (auto& g : grp_tiles) ntab += g.size();
+  for (auto& g : fast_tiles) ntab += g.size();
   const size_t off_tab = total;
   total += align(sizeof(TileRef) * ntab);
 
@@ -577,6 +744,7 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
     d.r = (float*)take(nn * 4); d.p = (float*)take(nn * 4); d.q = (float*)take(nn * 4);
     d.w = (float*)take(nn * 4); d.z = (float*)take(nn * 4);
     d.x64 = (double*)take(nn * 8); d.c64 = (double*)take(nn * 8); d.y64 = (double*)take(nn * 8);
+    d.xa64 = (double*)take(nn * 8); d.ra64 = (double*)take(nn * 8);
     d.t1 = take(nn * 4); d.t2 = take(nn * 4); d.t3 = take(nn * 4);
     d.partials = (double*)take(sizeof(double) * NSLOTS * MAXP_ITEM);
     d.ctrl = B.d_ctrl + i;
@@ -613,6 +781,13 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
     all.insert(all.end(), grp_tiles[c].begin(), grp_tiles[c].end());
     cur += grp_tiles[c].size();
   }
+  for (int c = 0; c < NUM_BLUR_CFG + 3; ++c) {
+    if (fast_tiles[c].empty()) continue;
+    const int gid = c < NUM_BLUR_CFG ? c : BLUR_CFG_MFMA + (c - NUM_BLUR_CFG + 1);
+    B.fast_groups.push_back(Batch::Group{gid, dtab + cur, (int)fast_tiles[c].size(), fast_lds[c]});
+    all.insert(all.end(), fast_tiles[c].begin(), fast_tiles[c].end());
+    cur += fast_tiles[c].size();
+  }
   B.t_blur64 = dtab + cur; B.n_blur64 = (int)t64.size();
   all.insert(all.end(), t64.begin(), t64.end()); cur += t64.size();
   B.t_gemm = dtab + cur; B.n_gemm = (int)tg.size();
@@ -647,8 +822,8 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
 
   {
     const int block = 8;
-    BCHK(ensure_groups<BK_A>(B));
-    BCHK(ensure_groups<BK_AT_NORMAL>(B));
+    BCHK(ensure_fast<BK_A>(B));
+    BCHK(ensure_fast<BK_AT_NORMAL>(B));
     if (!eager) {
       BCHK(hipStreamBeginCapture(B.s, hipStreamCaptureModeThreadLocal));
       for (int it = 0; it < block; ++it) {
@@ -669,7 +844,7 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
       }
       if (!running && !pending) break;
       if (pending) {
-        BCHK(true_residual_b(B, RM_PENDING, SC_TRUE));
+        BCHK(pending_residuals_b(B));
         BCHK(tail_b(B, RM_RESUME));
         hipLaunchKernelGGL(clear_resume_kernel, dim3((nitems + 255) / 256), dim3(256), 0, B.s,
                            B.d_items, nitems);

@@ -22,23 +22,9 @@
 // wave reads NU = 2 NCH + 2 A-fragment pairs from LDS and 2 NCH tap fragments
 // from the L2-resident table (prefetched two rows ahead), and issues 12 NCH
 // MFMAs.
-#include "blur_core.h"
+#include "blur_mfma.h"
 
 namespace kpcg {
-
-typedef _Float16 mh8_t __attribute__((ext_vector_type(8)));
-typedef float mf4_t __attribute__((ext_vector_type(4)));
-typedef _Float16 mh2_t __attribute__((ext_vector_type(2)));
-
-constexpr int MB_TM = 64, MB_TN = 64, MB_NT = 512;   // 2 groups of 4 waves
-
-__host__ __device__ constexpr int mb_width(int nch) { return MB_TN - 16 + 32 * nch; }
-__host__ __device__ constexpr int mb_pitch(int nch) { return mb_width(nch) + 8; }
-// hi and lo planes, then the second wave group's partial accumulators
-inline size_t mb_lds_bytes(int nch, int K) {
-  return (size_t)2 * (MB_TM + K - 1) * mb_pitch(nch) * sizeof(_Float16) +
-         (size_t)4 * 16 * 64 * sizeof(float);
-}
 
 // tap fragments: entry ((a * nch + t) * 2 + part) * 64 + lane holds the 8
 // halves T_{a,t}[8 g + e][c] (c = lane mod 16, g = lane div 16), part 0 = hi,
@@ -74,147 +60,10 @@ __global__ __launch_bounds__(MB_NT) void blur_mfma_kernel(const float* __restric
                                                           double* partials) {
   extern __shared__ __align__(16) unsigned char mb_lds[];
   if (skip_if_done && ctrl->done != RUNNING) return;
-  constexpr int W = mb_width(NCH), PITCH = mb_pitch(NCH), W2 = W / 2;
-  constexpr int NU = 4 + 2 * (NCH - 1);       // distinct 16-column window offsets
-  constexpr int PF = 2;                       // tap rows of fragments in flight
-  // column pairs per thread: the tile is at most (48 + 32 NCH)^2 entries
-  constexpr int NVP = ((48 + 32 * NCH) * (48 + 32 * NCH) / 2 + MB_NT - 1) / MB_NT;
-  const int h = (K - 1) >> 1;
-  const int rows = MB_TM + K - 1;
-  const int cvalid = MB_TN + K - 1;
-  const int i0 = blockIdx.y * MB_TM, j0 = blockIdx.x * MB_TN;
-  _Float16* shi = reinterpret_cast<_Float16*>(mb_lds);
-  _Float16* slo = shi + rows * PITCH;
-  __shared__ float red[MB_NT / 64];
-
-  // stage the tile once through registers (two columns per slot), find its
-  // largest |x|, then write the scaled hi / lo planes: the scale 2^ex puts
-  // that largest value in [2^13, 2^14)
-  float v0[NVP], v1[NVP];
-  float mx = 0.0f;
-#pragma unroll
-  for (int q = 0; q < NVP; ++q) {
-    const int idx = threadIdx.x + q * MB_NT;
-    float a0 = 0.0f, a1 = 0.0f;
-    if (idx < rows * W2) {
-      const int r = idx / W2, c = 2 * (idx - r * W2);
-      const int gi = i0 - h + r, gj = j0 - h + c;
-      if ((unsigned)gi < (unsigned)n) {
-        if (c < cvalid && (unsigned)gj < (unsigned)n) a0 = src[(size_t)gi * n + gj];
-        if (c + 1 < cvalid && (unsigned)(gj + 1) < (unsigned)n) a1 = src[(size_t)gi * n + gj + 1];
-      }
-    }
-    v0[q] = a0;
-    v1[q] = a1;
-    mx = fmaxf(mx, fmaxf(fabsf(a0), fabsf(a1)));
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  mx = red[0];
-#pragma unroll
-  for (int i = 1; i < MB_NT / 64; ++i) mx = fmaxf(mx, red[i]);
-  const int ex = (mx > 0.0f && mx <= 3.0e38f) ? 13 - ilogbf(mx) : 0;
-#pragma unroll
-  for (int q = 0; q < NVP; ++q) {
-    const int idx = threadIdx.x + q * MB_NT;
-    if (idx < rows * W2) {
-      const int r = idx / W2, c = 2 * (idx - r * W2);
-      const float a0 = ldexpf(v0[q], ex), a1 = ldexpf(v1[q], ex);
-      const _Float16 h0 = (_Float16)a0, h1 = (_Float16)a1;
-      const mh2_t hh = {h0, h1};
-      const mh2_t ll = {(_Float16)(a0 - (float)h0), (_Float16)(a1 - (float)h1)};
-      *reinterpret_cast<mh2_t*>(shi + r * PITCH + c) = hh;
-      *reinterpret_cast<mh2_t*>(slo + r * PITCH + c) = ll;
-    }
-  }
-  __syncthreads();
-
-  // wave group grp (4 waves, one 16-row strip each) takes tap rows
-  // [grp * ceil(K/2), ...); the groups' sums meet in LDS at the end
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int w = wv & 3, grp = wv >> 2;
-  const int m = lane & 15, g = lane >> 4;
-  const int half = (K + 1) >> 1;
-  const int abeg = grp * half, aend = grp ? K : half;
-  mf4_t acc[4];
-#pragma unroll
-  for (int jb = 0; jb < 4; ++jb) acc[jb] = mf4_t{0.f, 0.f, 0.f, 0.f};
-
-  // tap fragments of rows a .. a + PF in a ring of PF + 1 register slots;
-  // slot entries 2t / 2t+1 are the hi / lo fragments of chunk t
-  mh8_t bq[PF + 1][2 * NCH];
-#pragma unroll
-  for (int p = 0; p < PF; ++p) {
-    const int ap = abeg + p < aend ? abeg + p : aend - 1;
-#pragma unroll
-    for (int t = 0; t < 2 * NCH; ++t) bq[p][t] = bfrag[(ap * NCH * 2 + t) * 64 + lane];
-  }
-  for (int a0 = abeg; a0 < aend; a0 += PF + 1) {
-#pragma unroll
-    for (int sl = 0; sl <= PF; ++sl) {
-      const int a = a0 + sl;
-      if (a < aend) {
-        const int an = a + PF < aend ? a + PF : aend - 1;
-#pragma unroll
-        for (int t = 0; t < 2 * NCH; ++t)
-          bq[(sl + PF) % (PF + 1)][t] = bfrag[(an * NCH * 2 + t) * 64 + lane];
-        const int off = (w * 16 + a + m) * PITCH + 8 * g;
-        mh8_t ah[NU], al[NU];
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          ah[u] = *reinterpret_cast<const mh8_t*>(shi + off + 16 * u);
-          al[u] = *reinterpret_cast<const mh8_t*>(slo + off + 16 * u);
-        }
-#pragma unroll
-        for (int t = 0; t < NCH; ++t) {
-          const mh8_t bh = bq[sl][2 * t], bl = bq[sl][2 * t + 1];
-#pragma unroll
-          for (int jb = 0; jb < 4; ++jb)
-            acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bh, acc[jb], 0, 0, 0);
-#pragma unroll
-          for (int jb = 0; jb < 4; ++jb)
-            acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bl, acc[jb], 0, 0, 0);
-#pragma unroll
-          for (int jb = 0; jb < 4; ++jb)
-            acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[jb + 2 * t], bh, acc[jb], 0, 0, 0);
-        }
-      }
-    }
-  }
-
-  float* redacc = reinterpret_cast<float*>(slo + rows * PITCH);
-  if (grp == 1) {
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) redacc[((w * 4 + jb) * 4 + v) * 64 + lane] = acc[jb][v];
-  }
-  __syncthreads();
-  double d = 0.0;
-  if (grp == 0) {
-    const float oscale = ldexpf(1.0f, -(ex + exq));
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-      const int j = j0 + 16 * jb + m;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + w * 16 + 4 * g + v;
-        const float tot = acc[jb][v] + redacc[((w * 4 + jb) * 4 + v) * 64 + lane];
-        if (i < n && j < n) {
-          const float val = tot * oscale;
-          epi.row(i, j, 1, &val, d);
-        }
-      }
-    }
-  }
-  if constexpr (Epi::kReduce) {
-    __shared__ double sh[MB_NT / 64];
-    const double s = block_sum<MB_NT>(d, sh);
-    if (threadIdx.x == 0)
-      partials[Epi::kSlot * MAX_PARTIALS + blockIdx.y * gridDim.x + blockIdx.x] = s;
-  }
+  blur_mfma_tile<NCH, Epi>(src, bfrag, n, K, exq, blockIdx.y * MB_TM, blockIdx.x * MB_TN, epi,
+                           partials + Epi::kSlot * MAX_PARTIALS + blockIdx.y * gridDim.x +
+                               blockIdx.x,
+                           mb_lds);
 }
 
 int mfma_nch(int K) { return (K + 15 + 31) / 32; }

@@ -22,7 +22,6 @@ hipError_t launch_pupdate_from(const Plan& P, const float* z, hipStream_t s);
 namespace {
 
 constexpr int TAP_CHUNK = 16;
-constexpr double ANCHOR_REL = 1e-2;
 constexpr size_t ALIGN = 256;
 
 struct Bump {

@@ -67,7 +67,14 @@ struct Ctrl {
                     // a true-residual recomputation
   int repl;         // true-residual recomputations that replaced r
   double misfit2;   // ||A x - b||^2 (batched solves)
+  int anchor;       // batched solves: (x_a, r_a) holds a true residual small
+                    // enough (<= ANCHOR_REL ||A^T b||) to anchor the next one
+  int pad_;
 };
+
+// A true residual r_a at x_a anchors later ones, r = r_a - H (x - x_a) with
+// FP32 matvecs on the step, once ||r_a|| <= ANCHOR_REL ||A^T b||.
+constexpr double ANCHOR_REL = 1e-2;
 
 // ---------------------------------------------------------------------------
 // reductions: deterministic two-stage sums (per-block FP64 partials, summed
