@@ -148,3 +148,32 @@ def test_uneven_batch_sample_full_sizes():
     assert checked >= 1
     for pl in plans:
         pl.close()
+
+
+def test_batch_mixes_valu_and_mfma_items():
+    """Items whose plans use the VALU blur and items on the MFMA blur (all
+    three chunk counts) in one batch: each item still reaches the oracle's
+    x_lambda."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_BLUR_MFMA, KP_FPCG, KP_OK, KP_P16, Plan
+    probs, _ = _small_batch()
+    plans = [Plan(p.psf, p.n) for p in probs]
+    # K = 15, 9, 31, 21, 31: chunk counts 1, 1, 2, 2, 2; alternate the kernels
+    for i, pl in enumerate(plans):
+        pl.set_blur_config(KP_BLUR_MFMA if i % 2 == 0 else 0)
+    big = S.batch_problem(7)                       # n = 128, K = 55: three chunks
+    extra = Plan(big.psf, big.n)
+    extra.set_blur_config(KP_BLUR_MFMA)
+    allp = probs + [big]
+    allplans = plans + [extra]
+    items = [(i, lam) for i in range(len(allp)) for lam in (0.02,)]
+    xs, infos, st = _run(allplans, allp, items, KP_FPCG | KP_P16, 1e-7, maxit=1000)
+    for (p, lam), x, inf in zip(items, xs, infos):
+        assert inf.status == KP_OK, (allp[p].n, allp[p].k, inf)
+        if allp[p].n <= 256:
+            err = rel(x, _xlam(allp, p, lam))
+            say(f"  n={allp[p].n} k={allp[p].k} mfma={p % 2 == 0 or p == len(allp) - 1} "
+                f"iters={inf.iters} err={err:.2e}")
+            assert err <= 1e-4
+    for pl in allplans:
+        pl.close()
