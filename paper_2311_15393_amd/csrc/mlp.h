@@ -39,6 +39,10 @@ constexpr size_t MLP_H16_W2 = MLP_H16_W1 + (size_t)MLP_NH * MLP_NF;
 constexpr size_t MLP_H16_W3 = MLP_H16_W2 + (size_t)MLP_NH * MLP_NH;
 constexpr size_t MLP_H16_N = MLP_H16_W3 + (size_t)MLP_NH * MLP_NH;
 
+// contraction slices of the backward GEMMs and their partial-sum buffer
+constexpr int MLP_KSPLIT_MAX = 16;
+constexpr size_t MLP_PART_FLOATS = (size_t)1 << 20;
+
 struct Mlp {
   int max_batch = 0;
   bool owns = false;
@@ -65,6 +69,7 @@ struct Mlp {
   float* dza = nullptr;          // [B][256] dL/dz ping-pong
   float* dzb = nullptr;
   double* loss = nullptr;        // [1]
+  float* gpart = nullptr;        // [MLP_PART_FLOATS] sliced backward GEMM partials
   double* host_loss = nullptr;   // pinned
 };
 

@@ -22,6 +22,8 @@ namespace {
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
+inline unsigned blocks_for(size_t count) { return (unsigned)((count + 255) / 256); }
+
 constexpr float kInvSqrt2 = 0.70710678118654752f;
 constexpr float kInvSqrt2Pi = 0.39894228040143268f;
 
@@ -218,7 +220,7 @@ struct EpiGeluBack {                   // dz[m][n] = c g'(z[m][n])
 };
 
 template <class AL, class BL, class Epi>
-__global__ __launch_bounds__(256) void mlp_gemm_kernel(int M, int N, int K, AL A, BL B, Epi epi) {
+__device__ inline void mlp_gemm_body(int M, int N, int K, AL A, BL B, Epi epi) {
   __shared__ float sA[BKK][BT + 4];
   __shared__ float sB[BKK][BT + 4];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -265,9 +267,73 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(int M, int N, int K, AL A
 }
 
 template <class AL, class BL, class Epi>
-hipError_t run_mlp_gemm(int M, int N, int K, AL A, BL B, Epi epi, hipStream_t s) {
-  dim3 grid((N + BT - 1) / BT, (M + BT - 1) / BT);
-  hipLaunchKernelGGL((mlp_gemm_kernel<AL, BL, Epi>), grid, dim3(256), 0, s, M, N, K, A, B, epi);
+__global__ __launch_bounds__(256) void mlp_gemm_kernel(int M, int N, int K, AL A, BL B, Epi epi) {
+  mlp_gemm_body(M, N, K, A, B, epi);
+}
+
+// the operands shifted to a contraction slice: A(m, k0 + k), B(k0 + k, n)
+template <class AL>
+struct ASlice {
+  AL a; int k0;
+  static constexpr bool KFAST = AL::KFAST;
+  __device__ float at(int m, int k) const { return a.at(m, k0 + k); }
+};
+template <class BL>
+struct BSlice {
+  BL b; int k0;
+  __device__ float at(int k, int n) const { return b.at(k0 + k, n); }
+};
+
+// the same product over the contraction slice [z kc, (z+1) kc) (z = blockIdx.z),
+// raw sums to part[z][m][n]
+struct EpiPart {
+  float* part; int M, N;
+  __device__ void store(int m, int n, float c) const {
+    part[((size_t)blockIdx.z * M + m) * N + n] = c;
+  }
+};
+
+template <class AL, class BL>
+__global__ __launch_bounds__(256) void mlp_gemm_slice_kernel(int M, int N, int K, int kc, AL A,
+                                                             BL B, float* part) {
+  const int k0 = blockIdx.z * kc;
+  const int kn = K - k0 < kc ? K - k0 : kc;
+  mlp_gemm_body(M, N, kn, ASlice<AL>{A, k0}, BSlice<BL>{B, k0}, EpiPart{part, M, N});
+}
+
+// out[m][n] = sum over slices in order, then the epilogue
+template <class Epi>
+__global__ __launch_bounds__(256) void mlp_slice_sum_kernel(int M, int N, int ks,
+                                                            const float* __restrict__ part,
+                                                            Epi epi) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (size_t)M * N) return;
+  float acc = 0.f;
+  for (int z = 0; z < ks; ++z) acc += part[(size_t)z * M * N + e];
+  epi.store((int)(e / N), (int)(e % N), acc);
+}
+
+// A grid of a few tiles leaves the GPU idle through a long contraction: split
+// it into slices (partial products summed in a fixed order afterwards) so
+// that at least ~128 workgroups run.
+template <class AL, class BL, class Epi>
+hipError_t run_mlp_gemm(const Mlp& M_, int M, int N, int K, AL A, BL B, Epi epi, hipStream_t s) {
+  const int tiles = ((N + BT - 1) / BT) * ((M + BT - 1) / BT);
+  int ks = 1;
+  while (ks < MLP_KSPLIT_MAX && tiles * ks < 128 && K / (2 * ks) >= 32) ks *= 2;
+  if (ks == 1 || (size_t)ks * M * N > MLP_PART_FLOATS) {
+    dim3 grid((N + BT - 1) / BT, (M + BT - 1) / BT);
+    hipLaunchKernelGGL((mlp_gemm_kernel<AL, BL, Epi>), grid, dim3(256), 0, s, M, N, K, A, B, epi);
+    return hipGetLastError();
+  }
+  const int kc = (K + ks - 1) / ks;
+  dim3 grid((N + BT - 1) / BT, (M + BT - 1) / BT, ks);
+  hipLaunchKernelGGL((mlp_gemm_slice_kernel<AL, BL>), grid, dim3(256), 0, s, M, N, K, kc, A, B,
+                     M_.gpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((mlp_slice_sum_kernel<Epi>), dim3(blocks_for((size_t)M * N)), dim3(256), 0,
+                     s, M, N, ks, M_.gpart, epi);
   return hipGetLastError();
 }
 
@@ -325,8 +391,6 @@ __global__ __launch_bounds__(MLP_NF) void mlp_norm_kernel(const float* __restric
   scale[f] = sd < 1e-6 ? 1.0f : (float)sd;
 }
 
-inline unsigned blocks_for(size_t count) { return (unsigned)((count + 255) / 256); }
-
 }  // namespace
 
 size_t mlp_layout(int max_batch, char* base, Mlp* M) {
@@ -360,6 +424,7 @@ size_t mlp_layout(int max_batch, char* base, Mlp* M) {
   Q.dza = reinterpret_cast<float*>(take(B * MLP_NH * 4));
   Q.dzb = reinterpret_cast<float*>(take(B * MLP_NH * 4));
   Q.loss = reinterpret_cast<double*>(take(8));
+  Q.gpart = reinterpret_cast<float*>(take(MLP_PART_FLOATS * 4));
   return (cur + 255) / 256 * 256;
 }
 
@@ -418,7 +483,7 @@ hipError_t mlp_backward(const Mlp& M, const float* t, const int* rows, int nb, h
   for (int l = 2; l >= 0; --l) {
     const Layer& L = layers[l];
     // dW[o][i] = sum_b dz[b][o] h[b][i]
-    e = run_mlp_gemm(MLP_NH, L.in, nb, AMajorM{dz, MLP_NH},
+    e = run_mlp_gemm(M, MLP_NH, L.in, nb, AMajorM{dz, MLP_NH},
                      BRows<_Float16>{reinterpret_cast<const _Float16*>(L.hin), L.in},
                      EpiGrad{M.grads + L.offW, L.in}, s);
     if (e != hipSuccess) return e;
@@ -427,7 +492,7 @@ hipError_t mlp_backward(const Mlp& M, const float* t, const int* rows, int nb, h
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (l == 0) break;
     // dz_prev[b][i] = (sum_o dz[b][o] W[o][i]) g'(z_prev[b][i])
-    e = run_mlp_gemm(nb, L.in, MLP_NH, AMajorK{dz, MLP_NH},
+    e = run_mlp_gemm(M, nb, L.in, MLP_NH, AMajorK{dz, MLP_NH},
                      BRows<_Float16>{M.w16 + L.offH16, L.in},
                      EpiGeluBack{dzn, L.zprev, L.in}, s);
     if (e != hipSuccess) return e;
