@@ -77,11 +77,12 @@ typedef struct kp_info_s {
     int32_t iters;          /* H_lambda applications (A, A^T pairs) in the
                                iteration, as the paper counts iterations   */
     int32_t status;         /* KP_OK, KP_MAXIT or KP_BREAKDOWN             */
-    int32_t replacements;   /* FP64 true-residual recomputations           */
+    int32_t replacements;   /* true-residual recomputations                 */
     int32_t fallback;       /* 1 if pcg_solve restarted with the FP32
                                preconditioner                              */
     double  relres_rec;     /* recurrence ||r|| / ||A^T b|| at exit        */
-    double  relres_true;    /* FP64 ||A^T b - H x|| / ||A^T b|| at exit    */
+    double  relres_true;    /* true ||A^T(b - A x) - lambda^2 x|| / ||A^T b||
+                               at exit (b - A x accumulated in FP64)       */
     double  lambda;
     double  rhs_norm;       /* ||A^T b||_2                                 */
     double  misfit;         /* ||A x - b||_2 (pcg_solve_batched only; 0 for
@@ -146,10 +147,13 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t *out);
  * problem (Section 5.3).  Preconditioner precision: mode & KP_PREC_MASK.
  * Vectors are FP32, matvecs FP32; the solution is accumulated in FP64 on
  * the device and the scalars alpha, beta, ||r|| are accumulated and kept in
- * FP64; the true residual c - H x is recomputed with FP64 accumulation
- * whenever the recurrence residual has fallen 1000x since the last
- * recomputation and before convergence is declared, and replaces the
- * recurrence residual.
+ * FP64.  The true residual A^T (b - A x) - lambda^2 x (= c - H x) is
+ * recomputed whenever the recurrence residual has fallen 1000x since the
+ * last recomputation and before convergence is declared, and replaces the
+ * recurrence residual: b - A x is accumulated in FP64, A^T of it on the
+ * FP32-class blur for tol >= 1e-7 and in FP64 below.  Later recomputations
+ * add H (x - x_a) to the last true residual at x_a (FP32 matvecs on the step,
+ * FP64 sums) once that residual is below 1e-2 ||A^T b||.
  *
  *   b       device, n*n float32 data
  *   lambda  > 0, tol > 0 (relative to ||A^T b||), maxit >= 1

@@ -40,7 +40,7 @@ struct ItemDesc {
   const float* b;
   float* x;
   float *r, *p, *q, *w, *z;
-  double *x64, *c64, *y64;
+  double *x64, *y64;                         // FP64 iterate, b - A x scratch
   double *xa64, *ra64;                       // anchor (x_a, r_a) of the true residuals
   void *t1, *t2, *t3;
   Ctrl* ctrl;
@@ -60,8 +60,9 @@ struct TileRef {
 enum RunMode : int { RM_RUNNING = 0, RM_PENDING = 1, RM_ALL = 2, RM_RESUME = 3, RM_FINISHED = 4,
                      RM_PEND_FULL = 5, RM_PEND_ANCH = 6 };
 
-// batched scalar kind: true residual from the anchor (fast-blur partials)
-constexpr int SC_TRUE_ANCH = 100;
+// batched scalar kind: a true residual whose last blur ran on the fast blur
+// (anchored, or A^T (b - A x) on it), partials per fast-blur tile
+constexpr int SC_TRUE_FAST = 100;
 
 __device__ inline bool item_active(const Ctrl* c, int mode) {
   const int d = c->done;
@@ -79,8 +80,10 @@ __device__ inline bool item_active(const Ctrl* c, int mode) {
 // ---------------------------------------------------------------------------
 // batched blur
 // ---------------------------------------------------------------------------
+// BK_TRUE1: u = b - A x (FP64); BK_TRUE2: r = A^T u - lambda^2 x with A^T in
+// FP64, BK_TRUE2F: the same on the fast blur
 enum BlurKind : int { BK_A = 0, BK_AT_NORMAL = 1, BK_RHS = 2, BK_TRUE1 = 3, BK_TRUE2 = 4,
-                      BK_MISFIT = 5, BK_ANC1 = 6, BK_ANC2 = 7 };
+                      BK_MISFIT = 5, BK_ANC1 = 6, BK_ANC2 = 7, BK_TRUE2F = 8 };
 
 // ||A x - b||^2 for the data-misfit report
 struct EpiMisfit {
@@ -111,11 +114,11 @@ __global__ __launch_bounds__(TX* TY) void blur_batched_kernel(const ItemDesc* __
     const int ldw = lds_width<TX, TY, RX, RY, double>(it.kq);
     double* out = it.partials + SLOT_TRUE * MAXP_ITEM + tr.t;
     if constexpr (KIND == BK_TRUE1) {
-      EpiStoreF64 e{it.y64, n};
-      blur_tile<TX, TY, RX, RY, BC, double, double, double, EpiStoreF64>(
+      EpiResid e{it.b, it.q, it.y64, n};
+      blur_tile<TX, TY, RX, RY, BC, double, double, double, EpiResid>(
           it.x64, it.taps64_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, out);
     } else {
-      EpiTrueRes e{it.c64, it.x64, it.r, it.lam2, n, it.xa64, it.ra64};
+      EpiTrueRes e{it.x64, it.r, it.lam2, n, it.xa64, it.ra64};
       blur_tile<TX, TY, RX, RY, BC, double, double, double, EpiTrueRes>(
           it.y64, it.taps64, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, out);
     }
@@ -140,10 +143,15 @@ __global__ __launch_bounds__(TX* TY) void blur_batched_kernel(const ItemDesc* __
       blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiAnchorRes>(
           it.z, it.taps32, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
           it.partials + SLOT_TRUE * MAXP_ITEM + tr.t);
+    } else if constexpr (KIND == BK_TRUE2F) {
+      EpiTrueRes e{it.x64, it.r, it.lam2, n, it.xa64, it.ra64};
+      blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiTrueRes>(
+          it.q, it.taps32, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
+          it.partials + SLOT_TRUE * MAXP_ITEM + tr.t);
     } else if constexpr (KIND == BK_RHS) {
-      EpiRhs e{it.c64, it.r, n};
-      blur_tile<TX, TY, RX, RY, BC, float, double, double, EpiRhs>(
-          it.b, it.taps64, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
+      EpiRhs e{it.r, n};
+      blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiRhs>(
+          it.b, it.taps32, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
           it.partials + SLOT_RHS * MAXP_ITEM + tr.t);
     } else {
       EpiMisfit e{it.b, n};
@@ -177,6 +185,10 @@ __global__ __launch_bounds__(MB_NT) void blur_mfma_batched_kernel(
   } else if constexpr (KIND == BK_ANC1) {
     blur_mfma_tile<NCH>(it.q, tabA, n, it.k, it.exq, i0, j0, EpiStoreF32{it.z, n}, nullptr,
                         mb_lds);
+  } else if constexpr (KIND == BK_TRUE2F) {
+    blur_mfma_tile<NCH>(it.q, tabT, n, it.k, it.exq, i0, j0,
+                        EpiTrueRes{it.x64, it.r, it.lam2, n, it.xa64, it.ra64},
+                        it.partials + SLOT_TRUE * MAXP_ITEM + tr.t, mb_lds);
   } else {
     blur_mfma_tile<NCH>(it.z, tabT, n, it.k, it.exq, i0, j0,
                         EpiAnchorRes{it.x64, it.xa64, it.ra64, it.r, it.lam2, n},
@@ -284,7 +296,7 @@ __global__ __launch_bounds__(256) void scalar_batched_kernel(const ItemDesc* __r
   int slot, nb;
   switch (kind) {
     case SC_ALPHA: slot = SLOT_DELTA; nb = it.nb_fast; break;
-    case SC_TRUE_ANCH: slot = SLOT_TRUE; nb = it.nb_fast; break;
+    case SC_TRUE_FAST: slot = SLOT_TRUE; nb = it.nb_fast; break;
     case SC_RR: slot = SLOT_RR; nb = it.nb_vec; break;
     case SC_BETA: slot = SLOT_RZ; nb = it.nb_gemm; break;
     case SC_RHS: slot = SLOT_RHS; nb = it.nb_blur; break;
@@ -340,7 +352,7 @@ __global__ __launch_bounds__(256) void scalar_batched_kernel(const ItemDesc* __r
       if (!(S > 0.0) || !isfinite(S)) c->done = S == 0.0 ? CONVERGED : BREAKDOWN;
       break;
     case SC_TRUE:
-    case SC_TRUE_ANCH:
+    case SC_TRUE_FAST:
       c->true_rr = S;
       c->anchor = S <= ANCHOR_REL * ANCHOR_REL * c->gamma0sq ? 1 : 0;
       c->rr = S;
@@ -376,6 +388,7 @@ __global__ void clear_resume_kernel(const ItemDesc* __restrict__ items, int nite
 struct Batch {
   int nitems = 0;
   int mode = 0, solver = 0, prec = 0;
+  bool fast_tr = false;                      // tol >= TR_FAST_TOL
   std::vector<ItemDesc> h_items;
   ItemDesc* d_items = nullptr;
   // tile tables (device) and their lengths
@@ -577,39 +590,48 @@ static hipError_t iteration_b(const Batch& B) {
   return tail_b(B, RM_RUNNING);
 }
 
-static hipError_t true_residual_b(const Batch& B, int mode, int kind) {
-  hipError_t e;
+template <int KIND>
+static hipError_t blur64_b(const Batch& B, int mode) {
   if (B.n_blur64 == 0) return hipSuccess;
-  auto k1 = blur_batched_kernel<KP_F64IN_CFG, BK_TRUE1>;
-  auto k2 = blur_batched_kernel<KP_F64IN_CFG, BK_TRUE2>;
+  auto k = blur_batched_kernel<KP_F64IN_CFG, KIND>;
   if (B.lds64 > 65536) {
-    static size_t granted = 65536;
+    static size_t granted = 65536;       // once per instantiation
     if (B.lds64 > granted) {
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(k1),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)B.lds64);
-      if (e != hipSuccess) return e;
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(k2),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)B.lds64);
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)B.lds64);
       if (e != hipSuccess) return e;
       granted = B.lds64;
     }
   }
-  hipLaunchKernelGGL(k1, dim3(B.n_blur64), dim3(512), B.lds64, B.s, B.d_items, B.t_blur64, mode);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k2, dim3(B.n_blur64), dim3(512), B.lds64, B.s, B.d_items, B.t_blur64, mode);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(B.n_blur64), dim3(512), B.lds64, B.s, B.d_items, B.t_blur64, mode);
+  return hipGetLastError();
+}
+
+// r = A^T (b - A x) - lambda^2 x, both blurs with FP64 accumulation
+static hipError_t true_residual_b(const Batch& B, int mode, int kind) {
+  hipError_t e;
+  if ((e = blur64_b<BK_TRUE1>(B, mode)) != hipSuccess) return e;
+  if ((e = blur64_b<BK_TRUE2>(B, mode)) != hipSuccess) return e;
   return scalar_launch(B, kind, mode);
 }
 
-// true residuals of the items that asked for one: FP64 for items without a
-// usable anchor, r_a - H (x - x_a) on the fast blur for the others
+// true residuals of the items that asked for one: A^T (b - A x) - lambda^2 x
+// for items without a usable anchor (b - A x in FP64, A^T of it on the fast
+// blur when the tolerance allows, else in FP64), r_a - H (x - x_a) on the
+// fast blur for the others
 static hipError_t pending_residuals_b(const Batch& B) {
   hipError_t e;
-  if ((e = true_residual_b(B, RM_PEND_FULL, SC_TRUE)) != hipSuccess) return e;
+  if (B.fast_tr) {
+    if ((e = blur64_b<BK_TRUE1>(B, RM_PEND_FULL)) != hipSuccess) return e;
+    if ((e = fast_launch<BK_TRUE2F>(B, RM_PEND_FULL)) != hipSuccess) return e;
+  } else {
+    if ((e = true_residual_b(B, RM_PEND_FULL, SC_TRUE)) != hipSuccess) return e;
+  }
   if ((e = vec_launch<VK_DIFF>(B, RM_PEND_ANCH)) != hipSuccess) return e;
   if ((e = fast_launch<BK_ANC1>(B, RM_PEND_ANCH)) != hipSuccess) return e;
   if ((e = fast_launch<BK_ANC2>(B, RM_PEND_ANCH)) != hipSuccess) return e;
-  return scalar_launch(B, SC_TRUE_ANCH, RM_PEND_ANCH);
+  // one scalar step for every pending item whose partials are per fast tile
+  return scalar_launch(B, SC_TRUE_FAST, B.fast_tr ? RM_PENDING : RM_PEND_ANCH);
 }
 
 static int read_ctrls(Batch& B) {
@@ -638,6 +660,7 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
   B.mode = mode;
   B.solver = mode & KP_SOLVER_MASK;
   B.prec = mode & KP_PREC_MASK;
+  B.fast_tr = tol >= TR_FAST_TOL;
   const bool eager = (mode & KP_BATCH_EAGER) != 0;
 
   // ---- sizes of the batch allocation
@@ -648,7 +671,7 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
     const size_t nn = (size_t)plans[plan_of_item[i]]->n * plans[plan_of_item[i]]->n;
     off_item[i] = total;
     total += align(nn * 4) * 5;              // r p q w z
-    total += align(nn * 8) * 5;              // x64 c64 y64 xa64 ra64
+    total += align(nn * 8) * 4;              // x64 y64 xa64 ra64
     total += align(nn * 4) * 3;              // t1 t2 t3
     total += align(sizeof(double) * NSLOTS * MAXP_ITEM);
   }
@@ -743,7 +766,7 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
     auto take = [&](size_t bytes) { char* q = p; p += align(bytes); return q; };
     d.r = (float*)take(nn * 4); d.p = (float*)take(nn * 4); d.q = (float*)take(nn * 4);
     d.w = (float*)take(nn * 4); d.z = (float*)take(nn * 4);
-    d.x64 = (double*)take(nn * 8); d.c64 = (double*)take(nn * 8); d.y64 = (double*)take(nn * 8);
+    d.x64 = (double*)take(nn * 8); d.y64 = (double*)take(nn * 8);
     d.xa64 = (double*)take(nn * 8); d.ra64 = (double*)take(nn * 8);
     d.t1 = take(nn * 4); d.t2 = take(nn * 4); d.t3 = take(nn * 4);
     d.partials = (double*)take(sizeof(double) * NSLOTS * MAXP_ITEM);
@@ -813,9 +836,9 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
   BCHK(hipMemcpyAsync(B.d_ctrl, B.h_ctrl, sizeof(Ctrl) * nitems, hipMemcpyHostToDevice, B.s));
   BCHK(hipStreamSynchronize(B.s));
 
-  // x_0 = 0, c = A^T b (FP64), ||c||, then the first direction
+  // x_0 = 0, r = c = A^T b, ||c||, then the first direction
   BCHK(vec_launch<VK_INIT>(B, RM_ALL));
-  BCHK(blur_groups_launch<BK_RHS>(B, RM_ALL));          // FP32 input, FP64 accumulation
+  BCHK(blur_groups_launch<BK_RHS>(B, RM_ALL));          // r = c = A^T b (FP32 blur)
   BCHK(scalar_launch(B, SC_RHS, RM_ALL));
   BCHK(tail_b(B, RM_RUNNING));
   if ((rc = read_ctrls(B)) != KP_OK) goto out;

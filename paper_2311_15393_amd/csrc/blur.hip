@@ -146,22 +146,30 @@ hipError_t autotune_blur(Plan& P, hipStream_t s, float* times_ms) {
 }
 
 hipError_t launch_rhs(const Plan& P, const float* b, hipStream_t s) {
-  EpiRhs e{P.c64, P.r, P.n};
-  hipError_t err = run_blur<KP_F32_CFG, float, double, double>(P, b, P.taps64, e, P.ctrl, 0, s);
+  EpiRhs e{P.r, P.n};
+  int nb;
+  hipError_t err = blur_dispatch(P.blur_cfg, P, b, P.taps32, e, P.ctrl, 0, s, &nb);
   if (err != hipSuccess) return err;
-  return launch_scalar(P, SC_RHS, blur_blocks<KP_F32_CFG>(P.n), s);
+  return launch_scalar(P, SC_RHS, nb, s);
 }
 
-hipError_t launch_true_residual(const Plan& P, const double* x, double lam2, bool fin,
-                                hipStream_t s) {
-  EpiStoreF64 e1{P.y64, P.n};
+hipError_t launch_true_residual(const Plan& P, const float* b, const double* x, double lam2,
+                                bool fin, bool fast, hipStream_t s) {
+  // u = b - A x (FP64 accumulation) into q (FP32) or y64 (FP64)
+  EpiResid e1{b, fast ? P.q : nullptr, fast ? nullptr : P.y64, P.n};
   hipError_t err =
       run_blur<KP_F64IN_CFG, double, double, double>(P, x, P.taps64_flip, e1, P.ctrl, 0, s);
   if (err != hipSuccess) return err;
-  EpiTrueRes e2{P.c64, x, P.r, lam2, P.n, P.xa64, P.ra64};
-  err = run_blur<KP_F64IN_CFG, double, double, double>(P, P.y64, P.taps64, e2, P.ctrl, 0, s);
+  EpiTrueRes e2{x, P.r, lam2, P.n, P.xa64, P.ra64};
+  int nb;
+  if (fast) {
+    err = blur_dispatch(P.blur_cfg, P, P.q, P.taps32, e2, P.ctrl, 0, s, &nb);
+  } else {
+    nb = blur_blocks<KP_F64IN_CFG>(P.n);
+    err = run_blur<KP_F64IN_CFG, double, double, double>(P, P.y64, P.taps64, e2, P.ctrl, 0, s);
+  }
   if (err != hipSuccess) return err;
-  return launch_scalar(P, fin ? SC_TRUE : SC_TRUE_INFO, blur_blocks<KP_F64IN_CFG>(P.n), s);
+  return launch_scalar(P, fin ? SC_TRUE : SC_TRUE_INFO, nb, s);
 }
 
 hipError_t launch_anchor_residual(const Plan& P, double lam2, bool fin, hipStream_t s) {

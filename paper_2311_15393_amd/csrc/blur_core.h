@@ -80,9 +80,11 @@ struct EpiNormalW {
   }
 };
 
-// c = A^T b in FP64, r_0 = (float) c, ||c||^2
+// r_0 = c = A^T b and ||c||^2.  c only seeds the recursion: every true
+// residual is formed from b directly (EpiResid, EpiTrueRes), so an FP32-class
+// blur suffices here.
 struct EpiRhs {
-  double* c64; float* r; int n;
+  float* r; int n;
   static constexpr bool kReduce = true;
   static constexpr int kSlot = SLOT_RHS;
   template <typename Acc>
@@ -90,17 +92,36 @@ struct EpiRhs {
     const size_t o = (size_t)i * n + j0;
     for (int c = 0; c < cnt; ++c) {
       const double cv = (double)v[c];
-      c64[o + c] = cv;
       r[o + c] = (float)cv;
       d += cv * cv;
     }
   }
 };
 
-// r = c - A^T y - lambda^2 x with y = A x in FP64: the true residual; also
-// records (x, r) in FP64 as the anchor of later residuals (EpiAnchorRes)
+// u = b - A x with A x accumulated in FP64: the data residual, stored as FP32
+// (input of the FP32-class A^T) and/or FP64 (input of the FP64 A^T)
+struct EpiResid {
+  const float* b; float* u32; double* u64; int n;
+  static constexpr bool kReduce = false;
+  static constexpr int kSlot = SLOT_NORM;
+  template <typename Acc>
+  __device__ void row(int i, int j0, int cnt, const Acc* v, double&) const {
+    const size_t o = (size_t)i * n + j0;
+    for (int c = 0; c < cnt; ++c) {
+      const double uv = (double)b[o + c] - (double)v[c];
+      if (u32) u32[o + c] = (float)uv;
+      if (u64) u64[o + c] = uv;
+    }
+  }
+};
+
+// r = A^T u - lambda^2 x with u = b - A x (EpiResid): the true residual of the
+// normal equations, A^T(b - A x) - lambda^2 x = c - H x, without forming the
+// difference of the two large terms c and H x.  The epilogue is FP64; v comes
+// from either blur.  Also records (x, r) in FP64 as the anchor of later
+// residuals (EpiAnchorRes).
 struct EpiTrueRes {
-  const double* c64; const double* x; float* r; double lam2; int n;
+  const double* x; float* r; double lam2; int n;
   double* xa = nullptr; double* ra = nullptr;
   static constexpr bool kReduce = true;
   static constexpr int kSlot = SLOT_TRUE;
@@ -109,7 +130,7 @@ struct EpiTrueRes {
     const size_t o = (size_t)i * n + j0;
     for (int c = 0; c < cnt; ++c) {
       const double xv = x[o + c];
-      const double rv = c64[o + c] - (double)v[c] - lam2 * xv;
+      const double rv = (double)v[c] - lam2 * xv;
       r[o + c] = (float)rv;
       if (xa) {                        // anchor recorded unless not asked for
         xa[o + c] = xv;

@@ -127,5 +127,9 @@ template hipError_t launch_blur_mfma<EpiNormalW>(const Plan&, const float*, bool
                                                  Ctrl*, int, hipStream_t);
 template hipError_t launch_blur_mfma<EpiAnchorRes>(const Plan&, const float*, bool,
                                                    EpiAnchorRes, Ctrl*, int, hipStream_t);
+template hipError_t launch_blur_mfma<EpiRhs>(const Plan&, const float*, bool, EpiRhs, Ctrl*,
+                                             int, hipStream_t);
+template hipError_t launch_blur_mfma<EpiTrueRes>(const Plan&, const float*, bool, EpiTrueRes,
+                                                 Ctrl*, int, hipStream_t);
 
 }  // namespace kpcg

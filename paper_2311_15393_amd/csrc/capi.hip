@@ -75,7 +75,6 @@ size_t layout(int n, int k, char* base, Plan* P) {
   Q.q = b.take<float>(nn);
   Q.w = b.take<float>(nn);
   Q.z = b.take<float>(nn);
-  Q.c64 = b.take<double>(nn);
   Q.y64 = b.take<double>(nn);
   Q.x64 = b.take<double>(nn);
   Q.xa64 = b.take<double>(nn);
@@ -290,19 +289,22 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   else HIPCHK(hipMemsetAsync(P.x64, 0, N * sizeof(double), s));
 
   int replacements = 0;
-  // After an FP64 true residual r_a at x_a, later ones are computed as
+  // A true residual is A^T (b - A x) - lambda^2 x with b - A x in FP64 and
+  // A^T of it on the fast blur when the tolerance allows (TR_FAST_TOL).
+  // After one at x_a (residual r_a), later ones are computed as
   // r_a - H (x - x_a) with FP32 matvecs on the small step x - x_a: exact in
   // exact arithmetic, with an error of ~1e-6 ||r_a||.  Used once
   // ||r_a|| <= ANCHOR_REL ||A^T b||, so the error stays ~1e-9 ||A^T b||.
+  const bool fast_tr = tol >= TR_FAST_TOL;
   double anchor_rr = -1.0;                                       // none yet
   auto true_residual = [&](bool fin) -> hipError_t {
     if (anchor_rr >= 0.0 && anchor_rr <= ANCHOR_REL * ANCHOR_REL * hc_gamma0sq)
       return launch_anchor_residual(P, lam2d, fin, s);
-    return launch_true_residual(P, P.x64, lam2d, fin, s);
+    return launch_true_residual(P, b, P.x64, lam2d, fin, fast_tr, s);
   };
-  HIPCHK(launch_rhs(P, b, s));                                  // c = A^T b, r = c
+  HIPCHK(launch_rhs(P, b, s));                                  // r = c = A^T b, ||c||
   if (mode & KP_WARM) {
-    HIPCHK(launch_true_residual(P, P.x64, lam2d, true, s));     // r = c - H x0
+    HIPCHK(launch_true_residual(P, b, P.x64, lam2d, true, fast_tr, s));   // r = c - H x0
     ++replacements;
   }
   // first direction p = z_0 (CG: p = r_0) and a first block of iterations,
@@ -345,7 +347,7 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   while (hc.done == RUNNING || hc.done == PENDING) {
     if (hc.done == PENDING) {
       // the recurrence residual met the tolerance or fell 1/REPLACE_DROP:
-      // recompute it in FP64 and continue from the true residual
+      // recompute it from b and x and continue from the true residual
       HIPCHK(true_residual(true));
       ++replacements;
       const int todo = maxit - hc.iter;

@@ -76,6 +76,13 @@ struct Ctrl {
 // FP32 matvecs on the step, once ||r_a|| <= ANCHOR_REL ||A^T b||.
 constexpr double ANCHOR_REL = 1e-2;
 
+// True residuals are formed as A^T u - lambda^2 x from u = b - A x (FP64).
+// For tolerances >= TR_FAST_TOL the A^T u product runs on the FP32-class
+// blur: its error is ~2e-8 ||A|| ||u||, below 1e-8 ||A^T b|| for data
+// residuals ||u|| of a few per cent of ||b|| and below TR_FAST_TOL / 5 even
+// at ||u|| = ||b||; tighter tolerances use the FP64 blur for it.
+constexpr double TR_FAST_TOL = 1e-7;
+
 // ---------------------------------------------------------------------------
 // reductions: deterministic two-stage sums (per-block FP64 partials, summed
 // in a fixed order by whichever block finishes last)
@@ -177,9 +184,9 @@ struct Plan {
 
   // solver vectors
   float *r = nullptr, *p = nullptr, *q = nullptr, *w = nullptr, *z = nullptr;
-  double *c64 = nullptr, *y64 = nullptr;
+  double* y64 = nullptr;         // FP64 scratch (b - A x of the FP64 true residual)
   double* x64 = nullptr;         // FP64 solution accumulator
-  double* xa64 = nullptr;        // anchor: x and its true residual c - H x (FP64)
+  double* xa64 = nullptr;        // anchor: x and its true residual (FP64)
   double* ra64 = nullptr;
   // preconditioner intermediates (sized for FP32)
   void *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
@@ -207,6 +214,7 @@ hipError_t launch_blur_f32(const Plan& P, const float* src, float* dst, bool tra
                            hipStream_t s, const Ctrl* ctrl);
 hipError_t launch_blur_normal(const Plan& P, const float* q, const float* p, float* w,
                               float lam2, hipStream_t s);
+// r = c = A^T b on the plan's blur, ||c||^2 (the SC_RHS scalar step)
 hipError_t launch_rhs(const Plan& P, const float* b, hipStream_t s);
 hipError_t autotune_blur(Plan& P, hipStream_t s, float* times_ms);
 // r = r_a - H (x - x_a) from the anchor (x_a, r_a) of the last true residual,
@@ -214,8 +222,10 @@ hipError_t autotune_blur(Plan& P, hipStream_t s, float* times_ms);
 // moves the anchor to x
 hipError_t launch_anchor_residual(const Plan& P, double lam2, bool fin, hipStream_t s);
 hipError_t launch_diff32(const Plan& P, float* d, hipStream_t s);
-hipError_t launch_true_residual(const Plan& P, const double* x64, double lam2, bool fin,
-                                hipStream_t s);
+// r = A^T (b - A x) - lam2 x: b - A x in FP64, A^T of it on the plan's blur
+// (fast) or in FP64; records the anchor (x, r)
+hipError_t launch_true_residual(const Plan& P, const float* b, const double* x64, double lam2,
+                                bool fin, bool fast, hipStream_t s);
 hipError_t launch_normal_fp64(const Plan& P, const float* x, double lam2, double* y,
                               hipStream_t s);
 

@@ -177,3 +177,33 @@ def test_batch_mixes_valu_and_mfma_items():
             assert err <= 1e-4
     for pl in allplans:
         pl.close()
+
+
+@pytest.mark.parametrize("tol", [1e-6, 5e-8])
+def test_batched_true_residual_matches_oracle(tol):
+    """relres_true of every batched item (A^T of the FP64 data residual on
+    each item's fast blur for tol >= 1e-7, in FP64 below) equals the oracle's
+    FP64 ||c - H x|| / ||c|| at the returned x, to within a tenth of tol.
+    Plans alternate between the MFMA and the VALU blur."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_BLUR_MFMA, KP_FPCG, KP_OK, KP_P16, Plan
+    probs, items = _small_batch()
+    plans = [Plan(p.psf, p.n) for p in probs]
+    for i, pl in enumerate(plans):
+        pl.set_blur_config(KP_BLUR_MFMA if i % 2 == 0 else 0)
+    try:
+        say(f"batched certificate tol={tol:.0e}: {len(items)} items")
+        xs, infos, st = _run(plans, probs, items, KP_FPCG | KP_P16, tol, 400)
+        assert st == KP_OK
+        for (pi, lam), x, info in zip(items, xs, infos):
+            pr = probs[pi]
+            c = O.blur_t(pr.psf, pr.b.astype(np.float64))
+            r = c - O.normal_op(pr.psf, lam, x.astype(np.float64))
+            ref = float(np.linalg.norm(r) / np.linalg.norm(c))
+            say(f"  n={pr.n} k={pr.k} lam={lam:.3g} iters={info.iters} "
+                f"relres_true={info.relres_true:.4e} oracle={ref:.4e}")
+            assert info.status == KP_OK and info.relres_true <= tol
+            assert abs(info.relres_true - ref) <= 0.1 * tol
+    finally:
+        for p in plans:
+            p.close()

@@ -130,6 +130,52 @@ def test_edge_cases():
         assert ei.value.status == KP_BREAKDOWN
 
 
+@pytest.mark.parametrize("tol,cfg", [(1e-6, 6), (1e-6, 0), (5e-8, 6)])
+def test_reported_true_residual_matches_oracle(tol, cfg):
+    """The certificate: relres_true, formed on the device as
+    A^T (b - A x) - lambda^2 x with b - A x in FP64 and A^T on the MFMA blur
+    (cfg 6) or the FP32 VALU blur (cfg 0) for tol >= 1e-7, in FP64 below,
+    equals the oracle's FP64 ||c - H x|| / ||c|| at the returned x (eq.
+    (tik:normal2)), to within a tenth of the tolerance."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, Plan
+    from oracle import operator as O
+    prob = S.mid_anisotropic(0)
+    say(f"true residual certificate tol={tol:.0e} cfg={cfg}")
+    b64 = prob.b.astype(np.float64)
+    fb = O.FFTBlur(prob.psf, prob.n)
+    c = fb.blur_t(b64)
+    with Plan(prob.psf, prob.n) as plan:
+        plan.set_blur_config(cfg)
+        x, info = plan.solve(to_dev(prob.b), prob.lam, tol=tol, maxit=200,
+                             mode=KP_FPCG | KP_P16)
+        got = to_host(x).astype(np.float64)
+    r = c - O.normal_op(prob.psf, prob.lam, got, fft=fb)
+    ref = float(np.linalg.norm(r) / np.linalg.norm(c))
+    say(f"  iters={info.iters} repl={info.replacements} relres_true={info.relres_true:.4e} "
+        f"oracle={ref:.4e}")
+    assert info.status == KP_OK and info.relres_true <= tol
+    assert abs(info.relres_true - ref) <= 0.1 * tol
+    assert abs(info.rhs_norm - np.linalg.norm(c)) <= 1e-5 * np.linalg.norm(c)
+
+
+def test_nonfinite_data_on_mfma_blur():
+    """Inf or NaN anywhere in b ends the solve with KP_BREAKDOWN also when the
+    right-hand side runs on the MFMA blur (per-tile scaling must not hide it)."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_BREAKDOWN, KP_FPCG, KP_P16, KPError, Plan
+    prob = S.mid_anisotropic(1)
+    with Plan(prob.psf, prob.n) as plan:
+        plan.set_blur_config(6)
+        for bad_value in (float("inf"), float("-inf"), float("nan")):
+            say(f"non-finite data {bad_value} on the MFMA blur")
+            bad = to_dev(prob.b)
+            bad[100, 37] = bad_value
+            with pytest.raises(KPError) as ei:
+                plan.solve(bad, prob.lam, tol=1e-6, maxit=50, mode=KP_FPCG | KP_P16)
+            assert ei.value.status == KP_BREAKDOWN
+
+
 def test_gcv_and_discrepancy_match_oracle():
     """KP-basis GCV and discrepancy on the 32-point grid (eqs. (GCVTikSVD),
     (DSCTikSVD)): same grid choice as the oracle, scores to 1e-5 relative
