@@ -30,6 +30,23 @@ on tiny images, and against exactness for separable PSFs.
 
 Column factor A_c = T(c) acts from the left (vertical, row index i), row
 factor A_r = T(a) from the right (horizontal), so A_hat X = A_c X A_r^T.
+
+Exact diagonal in the KP basis (an extension of the paper's preconditioner):
+the same weighted SVD gives all terms of eq. (KronSumDecomp),
+A = sum_k T(a_k) (x) T(c_k) with c_k = sqrt(s_k) u_k / sqrt(w),
+a_k = sqrt(s_k) v_k / sqrt(w), exact once every nonzero s_k is kept (the
+paper reports 9 and 10 terms for its motion and shake blurs, Section 5, where
+the one-term preconditioner helps least).  Keeping V = V_r (x) V_c from the
+leading term, the diagonal of V^T A^T A V is, for basis image
+E_ij = v_c,i v_r,j^T,
+
+    D0[i, j] = ||A E_ij||_F^2
+             = sum_{k,l} (B_k^T B_l)[i, i] (C_k^T C_l)[j, j],
+    B_k = T(c_k) V_c,  C_k = T(a_k) V_r,
+
+and S[i, j] = 1 / (D0[i, j] + lambda^2) replaces 1 / (s_c[i]^2 s_r[j]^2 +
+lambda^2) in eq. (PreconSolve): the Frobenius-nearest matrix to H_lambda of
+the form V diag(.) V^T.  With one term D0 = s_c^2 s_r^2 exactly.
 """
 from __future__ import annotations
 
@@ -121,15 +138,52 @@ def kp_apply(kp: KPSVD, x: np.ndarray) -> np.ndarray:
     return kp.Ac @ x @ kp.Ar.T
 
 
-def precond_diag(kp: KPSVD, lam: float) -> np.ndarray:
-    """S[i, j] = 1 / (s_c[i]^2 s_r[j]^2 + lambda^2), vec(S) = diag(D^{-1})."""
-    return 1.0 / (np.outer(kp.sc ** 2, kp.sr ** 2) + lam * lam)
+def precond_diag(kp: KPSVD, lam: float, d0: np.ndarray | None = None) -> np.ndarray:
+    """S[i, j] = 1 / (s_c[i]^2 s_r[j]^2 + lambda^2), vec(S) = diag(D^{-1});
+    with d0 (exact_diag) S[i, j] = 1 / (d0[i, j] + lambda^2)."""
+    base = np.outer(kp.sc ** 2, kp.sr ** 2) if d0 is None else d0
+    return 1.0 / (base + lam * lam)
 
 
-def precond_solve(kp: KPSVD, lam: float, r: np.ndarray) -> np.ndarray:
+def precond_solve(kp: KPSVD, lam: float, r: np.ndarray,
+                  d0: np.ndarray | None = None) -> np.ndarray:
     """z = M^{-1} r as Z = V_c (S .* (V_c^T R V_r)) V_r^T (eq. (PreconSolve))."""
     t = kp.Vc.T @ r @ kp.Vr
-    return kp.Vc @ (precond_diag(kp, lam) * t) @ kp.Vr.T
+    return kp.Vc @ (precond_diag(kp, lam, d0) * t) @ kp.Vr.T
+
+
+def kp_all_terms(psf: np.ndarray, n: int, rel: float = 1e-12):
+    """All terms of eq. (KronSumDecomp) from the weighted PSF SVD: lists of
+    column profiles c_k and row profiles a_k with P = sum_k c_k a_k^T, for the
+    singular values s_k > rel * s_1."""
+    k = psf.shape[0]
+    sw = np.sqrt(weights(k, n))
+    u, s, vt = np.linalg.svd(sw[:, None] * psf * sw[None, :])
+    t = kp_terms(s, rel)
+    cs = [np.sqrt(s[i]) * u[:, i] / sw for i in range(t)]
+    as_ = [np.sqrt(s[i]) * vt[i, :] / sw for i in range(t)]
+    return cs, as_
+
+
+def kron_sum_apply(cs, as_, x: np.ndarray) -> np.ndarray:
+    """A X = sum_k T(c_k) X T(a_k)^T (eq. (KronSumDecomp) in matrix form)."""
+    n = x.shape[0]
+    return sum(toeplitz_band(c, n) @ x @ toeplitz_band(a, n).T for c, a in zip(cs, as_))
+
+
+def exact_diag(kp: KPSVD, psf: np.ndarray, rel: float = 1e-12) -> np.ndarray:
+    """D0[i, j] = ||A (v_c,i v_r,j^T)||_F^2 through the Kronecker sum:
+    sum over term pairs (k, l) of the column dot products of B_k = T(c_k) V_c
+    times those of C_k = T(a_k) V_r."""
+    n = kp.n
+    cs, as_ = kp_all_terms(psf, n, rel)
+    B = [toeplitz_band(c, n) @ kp.Vc for c in cs]
+    C = [toeplitz_band(a, n) @ kp.Vr for a in as_]
+    d0 = np.zeros((n, n))
+    for k in range(len(cs)):
+        for l in range(len(cs)):
+            d0 += np.outer(np.sum(B[k] * B[l], axis=0), np.sum(C[k] * C[l], axis=0))
+    return d0
 
 
 def van_loan_pitsianis(a_dense: np.ndarray, n: int):

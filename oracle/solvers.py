@@ -135,10 +135,14 @@ def solve(op: NormalOperator, b: np.ndarray, mode: str = PCG, tol: float = 1e-6,
     return res
 
 
-def kp_preconditioner(psf: np.ndarray, n: int, lam: float, kp: kpmod.KPSVD | None = None):
-    """z = M^{-1} r with the exact FP64 KP-SVD factors."""
+def kp_preconditioner(psf: np.ndarray, n: int, lam: float, kp: kpmod.KPSVD | None = None,
+                      exact_diag: bool = False):
+    """z = M^{-1} r with the exact FP64 KP-SVD factors; exact_diag uses
+    S = 1 / (diag(V^T A^T A V) + lambda^2) (kp.exact_diag) instead of the
+    one-term singular values."""
     kp = kp if kp is not None else kpmod.kp_svd(psf, n)
-    return lambda r: kpmod.precond_solve(kp, lam, r)
+    d0 = kpmod.exact_diag(kp, psf) if exact_diag else None
+    return lambda r: kpmod.precond_solve(kp, lam, r, d0)
 
 
 def true_residual(op: NormalOperator, b: np.ndarray, x: np.ndarray) -> float:
