@@ -10,8 +10,10 @@ pcg_solve of (A^T A + lambda^2 I) x = A^T b with the FP16 KP-SVD
 preconditioner and flexible PCG, from b resident in HBM to x resident in
 HBM, at the loosest tolerance (1e-5, tightened 10x at a time) whose solution
 is within 1e-4 relative error of the FP64 oracle's x_lambda.  The same
-measurement is made for the FP32 preconditioner (PCG) and for no
-preconditioner (CG); their numbers are reported beside the headline value.
+measurement is made for the FP32 preconditioner (PCG), the FP8 one and for
+no preconditioner (CG), and for the FP16 / FP32 preconditioners with the
+exact KP-basis diagonal (KP_EXACT_DIAG) in place of the one-term singular
+values; their numbers are reported beside the headline value.
 """
 from __future__ import annotations
 
@@ -32,7 +34,8 @@ HBM_PEAK = 8.0e12
 FP32_VALU_PEAK = 157.3e12
 FP16_MFMA_PEAK = 2.5e15
 # solver modes and their iteration caps
-MODES = {"fp16_kp_fpcg": 200, "fp32_kp_pcg": 200, "fp8_kp_fpcg": 400, "none_cg": 3000}
+MODES = {"fp16_kp_fpcg": 200, "fp32_kp_pcg": 200, "fp8_kp_fpcg": 400, "none_cg": 3000,
+         "fp16_kpdiag_fpcg": 200, "fp32_kpdiag_pcg": 200}
 # Bytes of the plain copy launched by --profile-only to calibrate the HBM
 # counters (FETCH_SIZE / WRITE_SIZE): 64 Mi floats read, 64 Mi written.
 COPY_CALIB_FLOATS = 64 * 1024 * 1024
@@ -122,7 +125,8 @@ def main():
 
     import torch
     import synthetic as S
-    from paper_2311_15393_amd import KP_CG, KP_FPCG, KP_OK, KP_P8, KP_P16, KP_P32, KP_PCG, Plan
+    from paper_2311_15393_amd import (KP_CG, KP_EXACT_DIAG, KP_FPCG, KP_OK, KP_P8, KP_P16, KP_P32,
+                                      KP_PCG, Plan)
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -216,8 +220,11 @@ def main():
         dt = time.perf_counter() - t0
         return dt / steps * 1e3, iters
 
+    # the paper's one-term S (kp) and the exact KP-basis diagonal (kpdiag)
     mode_bits = {"fp16_kp_fpcg": KP_FPCG | KP_P16, "fp32_kp_pcg": KP_PCG | KP_P32,
-                 "fp8_kp_fpcg": KP_FPCG | KP_P8, "none_cg": KP_CG}
+                 "fp8_kp_fpcg": KP_FPCG | KP_P8, "none_cg": KP_CG,
+                 "fp16_kpdiag_fpcg": KP_FPCG | KP_P16 | KP_EXACT_DIAG,
+                 "fp32_kpdiag_pcg": KP_PCG | KP_P32 | KP_EXACT_DIAG}
     chosen = [m for m in args.modes.split(",") if m]
     assert "fp16_kp_fpcg" in chosen and all(m in MODES for m in chosen), args.modes
     modes = {m: (mode_bits[m], MODES[m]) for m in chosen}

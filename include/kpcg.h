@@ -69,6 +69,16 @@ extern "C" {
 #define KP_BATCH_EAGER 0x200    /* pcg_solve_batched: launch every iteration
                                    eagerly instead of replaying a hipGraph */
 #define KP_NO_FALLBACK 0x400    /* pcg_solve: no FP32 restart on failure    */
+#define KP_EXACT_DIAG 0x800     /* preconditioner S = 1 / (D0 + lambda^2) with
+                                   D0 = diag(V^T A^T A V), the exact diagonal
+                                   of A^T A in the one-term KP basis V =
+                                   V_r (x) V_c, built from every term of eq.
+                                   (KronSumDecomp) (Section 5), in place of
+                                   1 / (s_c^2 s_r^2 + lambda^2) (eq.
+                                   (PreconSolve)).  Same V, same kernels and
+                                   cost per iteration; equal to the default
+                                   for separable PSFs.  An extension of the
+                                   paper's preconditioner.                 */
 
 typedef struct kp_plan_s *kp_plan_t;   /* opaque */
 
@@ -164,7 +174,7 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t *out);
  * KP_BREAKDOWN (with a finite iterate), it is restarted from its last
  * iterate with the FP32 preconditioner and its own budget of maxit
  * iterations (info->iters counts both runs, info->fallback = 1); mode bit
- * KP_NO_FALLBACK turns this off.
+ * KP_NO_FALLBACK turns this off (the restart keeps KP_EXACT_DIAG).
  * Returns KP_OK (true relative residual <= tol), KP_OK_FALLBACK, KP_MAXIT,
  * KP_BREAKDOWN or an error.  Synchronises `stream` (it reads back the
  * convergence state).
@@ -200,8 +210,9 @@ int discrepancy_lambda(kp_plan_t plan, const float *b, const double *grid,
  * pcg_solve_batched -- many solves of eq. (tik:normal2) in one set of
  * launches: item i solves with plan plans[plan_of_item[i]] (its PSF and
  * image size), data b[i], parameter lambdas[i], writing x[i].  All items
- * share tol, maxit and mode (solver and preconditioner bits as pcg_solve;
- * KP_P8 and KP_WARM are not supported here; KP_BATCH_EAGER launches the
+ * share tol, maxit and mode (solver and preconditioner bits and
+ * KP_EXACT_DIAG as pcg_solve; KP_P8 and KP_WARM are not supported here;
+ * KP_BATCH_EAGER launches the
  * iterations eagerly instead of replaying a captured hipGraph).  Uneven
  * image sizes and PSF supports are allowed.  Each phase of an iteration is
  * one launch over the tiles of all items still iterating; each item stops
@@ -363,8 +374,8 @@ int kp_normal_fp64(kp_plan_t plan, const float *x, double lambda, double *y,
                    void *stream);
 
 /* z = M^{-1} r with the mode's preconditioner precision (mode &
-   KP_PREC_MASK), using the same kernels as the solver.  r, z device FP32,
-   must not alias. */
+   KP_PREC_MASK) and S table (KP_EXACT_DIAG), using the same kernels as the
+   solver.  r, z device FP32, must not alias. */
 int kp_precond(kp_plan_t plan, const float *r, double lambda, int mode,
                float *z, void *stream);
 
@@ -383,6 +394,13 @@ int kp_time_precond(kp_plan_t plan, const float *r, double lambda, int mode,
    receives the previous one). */
 #define KP_BLUR_MFMA 6
 int kp_set_blur_config(kp_plan_t plan, int cfg, int *prev);
+
+/* Copy the exact KP-basis diagonal D0[i][j] = ||A (v_c,i v_r,j^T)||_F^2
+   (the table KP_EXACT_DIAG uses; built by kp_setup from all Kronecker terms
+   with FP64 arithmetic, stored FP32) to the host array d0 (n*n, row-major:
+   i indexes the column factor's singular vectors, j the row factor's).
+   Synchronises the device. */
+int kp_get_diag(kp_plan_t plan, float *d0);
 
 /* Copy the FP64 singular values s_c, s_r (host arrays of n) and, if not
    NULL, V_c, V_r as FP64 row-major n x n host arrays (V[i*n + a] = V(i,a)). */

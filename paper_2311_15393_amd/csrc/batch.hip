@@ -37,6 +37,7 @@ struct ItemDesc {
   const _Float16 *VcT16, *Vc16, *Vr16, *VrT16;
   const float *VcT32, *Vc32, *Vr32, *VrT32;
   const float *sc2, *sr2;
+  const float* d0;                           // exact KP-basis diagonal (KP_EXACT_DIAG) or null
   const float* b;
   float* x;
   float *r, *p, *q, *w, *z;
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(GT) void gemm_batched_kernel(const ItemDesc* __rest
                                      it.ctrl->pscale, 1.0f, nullptr, MAXP_ITEM);
   } else if constexpr (STAGE == 2) {
     gemm_tile<T, false, GEpiSPrimeT<T>>(t1, VrT, n, m0, n0,
-                                        GEpiSPrimeT<T>{t2, it.sc2, it.sr2, it.lam2f, n}, 1.0f,
+                                        GEpiSPrimeT<T>{t2, it.sc2, it.sr2, it.lam2f, n, it.d0}, 1.0f,
                                         1.0f, nullptr, MAXP_ITEM);
   } else if constexpr (STAGE == 3) {
     gemm_tile<T, false, GEpiStore<T>>(Vc, t2, n, m0, n0, GEpiStore<T>{t3, n}, 1.0f, 1.0f,
@@ -779,6 +780,7 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
     d.Vr16 = (const _Float16*)P.Vr16; d.VrT16 = (const _Float16*)P.VrT16;
     d.VcT32 = P.VcT32; d.Vc32 = P.Vc32; d.Vr32 = P.Vr32; d.VrT32 = P.VrT32;
     d.sc2 = P.sc2; d.sr2 = P.sr2;
+    d.d0 = (mode & KP_EXACT_DIAG) ? P.d0 : nullptr;
     d.b = b[i];
     d.x = x[i];
     Ctrl& c = B.h_ctrl[i];

@@ -52,6 +52,7 @@ size_t layout(int n, int k, char* base, Plan* P) {
   Q.sr = b.take<double>(n);
   Q.sc2 = b.take<float>(n);
   Q.sr2 = b.take<float>(n);
+  Q.d0 = b.take<float>(nn);
   Q.Vc32 = b.take<float>(nn);
   Q.VcT32 = b.take<float>(nn);
   Q.Vr32 = b.take<float>(nn);
@@ -266,6 +267,7 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   Plan& P = plan->P;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t N = (size_t)P.n * P.n;
+  P.sprime_d0 = (mode & KP_EXACT_DIAG) ? P.d0 : nullptr;
   const double lam2d = lambda * lambda;
   const float lam2 = (float)lam2d;
   double hc_gamma0sq = 0.0;
@@ -430,7 +432,7 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
   if (!(lambda > 0.0) || !std::isfinite(lambda) || !(tol > 0.0) || !std::isfinite(tol) ||
       maxit < 1)
     return KP_ERR_ARG;
-  if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM | KP_NO_FALLBACK)) != 0)
+  if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM | KP_NO_FALLBACK | KP_EXACT_DIAG)) != 0)
     return KP_ERR_ARG;
   kp_info_t first;
   const int st = solve_once(plan, b, lambda, tol, maxit, mode & ~KP_NO_FALLBACK, x, &first,
@@ -448,7 +450,9 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
   // iterate with the FP32 preconditioner (its own budget of maxit iterations)
   kp_info_t second;
   const int st2 = solve_once(plan, b, lambda, tol, maxit,
-                             (mode & (KP_SOLVER_MASK | KP_NO_FALLBACK)) | KP_P32 | KP_WARM, x,
+                             (mode & (KP_SOLVER_MASK | KP_NO_FALLBACK | KP_EXACT_DIAG)) | KP_P32 |
+                                 KP_WARM,
+                             x,
                              &second, stream);
   if (st2 < 0) return st2;
   if (info) {
@@ -467,7 +471,8 @@ int pcg_solve_batched(const kp_plan_t* plans, int nplans, const float* const* b,
   if (!plans || nplans < 1 || !b || !lambdas || !plan_of_item || nitems < 1 || !x || !infos)
     return KP_ERR_ARG;
   if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 1) return KP_ERR_ARG;
-  if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM | KP_BATCH_EAGER)) != 0) return KP_ERR_ARG;
+  if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM | KP_BATCH_EAGER | KP_EXACT_DIAG)) != 0)
+    return KP_ERR_ARG;
   if ((mode & KP_SOLVER_MASK) == 3 || (mode & KP_PREC_MASK) == KP_PREC_MASK) return KP_ERR_ARG;
   if ((mode & KP_WARM) || (mode & KP_PREC_MASK) == KP_P8) return KP_ERR_UNSUPPORTED;
   std::vector<Plan*> ps(nplans);
@@ -587,6 +592,7 @@ int kp_precond(kp_plan_t plan, const float* r, double lambda, int mode, float* z
   if (prec == KP_P8 && !fp8_supported_size(plan->P.n)) return KP_ERR_UNSUPPORTED;
   if (!aligned16(r) || !aligned16(z)) return KP_ERR_ARG;
   Plan& P = plan->P;
+  P.sprime_d0 = (mode & KP_EXACT_DIAG) ? P.d0 : nullptr;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Ctrl c;
   std::memset(&c, 0, sizeof(c));
@@ -630,6 +636,7 @@ int kp_time_precond(kp_plan_t plan, const float* r, double lambda, int mode, flo
   if (prec == KP_PREC_MASK) return KP_ERR_ARG;
   if (prec == KP_P8 && !fp8_supported_size(plan->P.n)) return KP_ERR_UNSUPPORTED;
   Plan& P = plan->P;
+  P.sprime_d0 = (mode & KP_EXACT_DIAG) ? P.d0 : nullptr;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Ctrl c;
   std::memset(&c, 0, sizeof(c));
@@ -660,6 +667,14 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int* prev) {
   if (!plan || cfg < 0 || cfg > BLUR_CFG_MFMA) return KP_ERR_ARG;
   if (prev) *prev = plan->P.blur_cfg;
   plan->P.blur_cfg = cfg;
+  return KP_OK;
+}
+
+int kp_get_diag(kp_plan_t plan, float* d0) {
+  if (!plan || !d0) return KP_ERR_ARG;
+  Plan& P = plan->P;
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(d0, P.d0, sizeof(float) * P.n * P.n, hipMemcpyDeviceToHost));
   return KP_OK;
 }
 

@@ -163,6 +163,9 @@ struct Plan {
   double* sr = nullptr;
   float* sc2 = nullptr;          // squares in FP32
   float* sr2 = nullptr;
+  float* d0 = nullptr;           // exact KP-basis diagonal diag(V^T A^T A V), [n][n]
+  const float* sprime_d0 = nullptr;  // the current solve's S' table: d0 with
+                                     // KP_EXACT_DIAG, else nullptr (s_c^2 s_r^2)
   float* Vc32 = nullptr;         // row-major Vc[i][a]
   float* VcT32 = nullptr;        // row-major Vc^T
   float* Vr32 = nullptr;

@@ -172,10 +172,13 @@ struct GEpiStore {                       // row-major store
 
 template <typename T>
 struct GEpiSPrimeT {                     // T2^T[j][i] = S'[i][j] * T[i][j]
-  T* C; const float* sc2; const float* sr2; float lam2; int n;
+  // S' = lam2 / (s_c[i]^2 s_r[j]^2 + lam2), or lam2 / (d0[i][j] + lam2) with
+  // the exact KP-basis diagonal d0
+  T* C; const float* sc2; const float* sr2; float lam2; int n; const float* d0;
   static constexpr bool kReduce = false;
   __device__ void apply(int i, int j, float v, double&, double&) const {
-    const float sp = lam2 / fmaf(sc2[i], sr2[j], lam2);
+    const float den = d0 ? d0[(size_t)i * n + j] + lam2 : fmaf(sc2[i], sr2[j], lam2);
+    const float sp = lam2 / den;
     C[(size_t)j * n + i] = (T)(sp * v);
   }
 };

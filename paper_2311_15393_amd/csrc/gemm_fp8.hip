@@ -75,6 +75,7 @@ struct Gemm8Args {
   uint8_t* C; uint8_t* Cs;                  // quantised output (E8_ROWS / E8_SPRIME_T)
   float* z; const float* r; const float* w; // final stage
   const float* sc2; const float* sr2; float lam2;
+  const float* d0;                          // exact KP-basis diagonal, or nullptr
   int n;
 };
 
@@ -235,7 +236,9 @@ __global__ __launch_bounds__(G8T) void gemm8_kernel(Gemm8Args g, Ctrl* ctrl, int
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = m0 + wm * 32 + mi * 16 + 4 * g4 + v;
-          const float sp = g.lam2 / fmaf(g.sc2[i], g.sr2[j], g.lam2);
+          const float den = g.d0 ? g.d0[(size_t)i * n + j] + g.lam2
+                                 : fmaf(g.sc2[i], g.sr2[j], g.lam2);
+          const float sp = g.lam2 / den;
           t[mi][ni][v] = sp * acc[mi][ni][v];
         }
       }
@@ -312,6 +315,7 @@ hipError_t launch_precond_fp8(const Plan& P, const float* r, float* z, const flo
   a.n = n;
   a.sc2 = P.sc2;
   a.sr2 = P.sr2;
+  a.d0 = P.sprime_d0;
   a.lam2 = lam2;
   // 1. T1 = Vc^T R (R quantised per (column, 32 rows) while staged)
   a.A = P.VcT8; a.As = P.VcT8s; a.Bf32 = r; a.C = t1; a.Cs = P.t1s;

@@ -62,6 +62,101 @@ __global__ void profiles_kernel(const double* __restrict__ S, const double* __re
   }
 }
 
+// All t terms of the Kronecker sum (Section 5, eq. (KronSumDecomp)) from the
+// weighted PSF SVD: prof[k][d] = sqrt(s_k) U(d,k) / sqrt(w_d) (column
+// profiles) and prof[t + k][d] = sqrt(s_k) V(d,k) / sqrt(w_d) (row profiles),
+// so that P = sum_k c_k a_k^T.  The sign of a pair (c_k, a_k) is immaterial
+// for the diagonal built from them.
+__global__ void all_profiles_kernel(const double* __restrict__ S, const double* __restrict__ U,
+                                    const double* __restrict__ Vt, int K, int n, int t,
+                                    double* __restrict__ prof) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= t * K) return;
+  const int k = idx / K, d = idx - k * K, h = (K - 1) / 2;
+  const double g = sqrt(S[k]) / sqrt((double)(n - abs(d - h)));
+  prof[idx] = g * U[d + (size_t)k * K];                  // U(d, k)
+  prof[t * K + idx] = g * Vt[k + (size_t)d * K];         // Vt(k, d) = V(d, k)
+}
+
+// Per column a of one factor's V (row-major n x n, FP64): the Gram matrix of
+// y_k = T(f_k) V(:, a) over the t profiles f_k of that factor,
+//     G[k * t + l][a] = sum_i y_k[i] y_l[i],
+// with (T(f) v)[i] = sum_d f[d] v[i + h - d] (zero outside [0, n)).  One
+// block per column; the column (zero padded by h on both sides) and the
+// profiles sit in LDS, y is formed GRAM_CH rows at a time, and each thread
+// accumulates up to GRAM_PAIRS of the t (t + 1) / 2 pairs k <= l in FP64.
+constexpr int GRAM_NT = 256;
+constexpr int GRAM_CH = 64;
+constexpr int GRAM_PAIRS = 8;              // 63 * 64 / 2 = 2016 <= 256 * 8
+
+size_t gram_lds_bytes(int t, int K, int n) {
+  return sizeof(double) * ((size_t)t * K + (size_t)n + K - 1 + (size_t)t * (GRAM_CH + 1));
+}
+
+__global__ __launch_bounds__(GRAM_NT) void gram_kernel(const double* __restrict__ V,
+                                                       const double* __restrict__ prof, int t,
+                                                       int K, int n, double* __restrict__ G) {
+  extern __shared__ double gsm[];
+  double* sp = gsm;                               // [t][K]
+  double* sv = sp + t * K;                        // [n + K - 1]: sv[m] = v[m - h]
+  double* sy = sv + n + K - 1;                    // [t][GRAM_CH + 1]
+  const int a = blockIdx.x, tid = threadIdx.x, h = (K - 1) / 2;
+  for (int i = tid; i < t * K; i += GRAM_NT) sp[i] = prof[i];
+  for (int m = tid; m < n + K - 1; m += GRAM_NT) {
+    const int i = m - h;
+    sv[m] = (i >= 0 && i < n) ? V[(size_t)i * n + a] : 0.0;
+  }
+  // this thread's pairs p = tid + GRAM_NT q in the order (0,0), (0,1), ...
+  int pk[GRAM_PAIRS], pl[GRAM_PAIRS];
+  double acc[GRAM_PAIRS];
+#pragma unroll
+  for (int q = 0; q < GRAM_PAIRS; ++q) { pk[q] = -1; pl[q] = 0; acc[q] = 0.0; }
+  {
+    int p = 0;
+    for (int k = 0; k < t; ++k)
+      for (int l = k; l < t; ++l, ++p) {
+        const int q = (p - tid) / GRAM_NT;
+        if (p >= tid && (p - tid) % GRAM_NT == 0 && q < GRAM_PAIRS) { pk[q] = k; pl[q] = l; }
+      }
+  }
+  __syncthreads();
+  constexpr int LD = GRAM_CH + 1;
+  for (int i0 = 0; i0 < n; i0 += GRAM_CH) {
+    for (int idx = tid; idx < t * GRAM_CH; idx += GRAM_NT) {
+      const int k = idx / GRAM_CH, r = idx - k * GRAM_CH, i = i0 + r;
+      double y = 0.0;
+      if (i < n) {
+        const double* f = sp + k * K;
+        const double* v = sv + i + 2 * h;         // v[i + h - d] = sv[i + 2h - d]
+        for (int d = 0; d < K; ++d) y = fma(f[d], v[-d], y);
+      }
+      sy[k * LD + r] = y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < GRAM_PAIRS; ++q) {
+      if (pk[q] < 0) continue;
+      const double* yk = sy + pk[q] * LD;
+      const double* yl = sy + pl[q] * LD;
+      double sum = 0.0;
+      for (int r = 0; r < GRAM_CH; ++r) sum = fma(yk[r], yl[r], sum);
+      acc[q] += sum;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < GRAM_PAIRS; ++q) {
+    if (pk[q] < 0) continue;
+    G[((size_t)pk[q] * t + pl[q]) * n + a] = acc[q];
+    G[((size_t)pl[q] * t + pk[q]) * n + a] = acc[q];
+  }
+}
+
+__global__ void to_f32_kernel(const double* __restrict__ src, size_t cnt, float* __restrict__ dst) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < cnt) dst[idx] = (float)src[idx];
+}
+
 // Column-major banded Toeplitz T(f)[i][i'] = f[h + i - i'].
 __global__ void toeplitz_kernel(const double* __restrict__ f, int K, int n,
                                 double* __restrict__ t) {
@@ -213,6 +308,9 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
   rocblas_int* info = nullptr;
   double* wv = nullptr;
   int* perm = nullptr;
+  double *pall = nullptr, *G2 = nullptr, *D64 = nullptr;   // exact KP-basis diagonal
+  int tall = 0;
+  size_t glds = 0;
   bool symmetric[2] = {false, false};
   std::vector<double> hs(K);
   rocblas_int hinfo = 0;
@@ -286,6 +384,21 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
     for (int i = 0; i < K; ++i)
       if (hs[i] > 1e-12 * hs[0]) ++t;
     P.terms = t;
+    tall = t;
+  }
+  // every term's profiles, and room for the per-factor Gram matrices of the
+  // exact diagonal D0 = diag(V^T A^T A V) (built below)
+  if (tall > 0) {
+    HCHK(hipMalloc(&pall, sizeof(double) * 2 * tall * K));
+    HCHK(hipMalloc(&G2, sizeof(double) * 2 * (size_t)tall * tall * n));
+    HCHK(hipMalloc(&D64, sizeof(double) * nn));
+    hipLaunchKernelGGL(all_profiles_kernel, dim3((tall * K + 255) / 256), dim3(256), 0, s, spsf,
+                       upsf, vpsf, K, n, tall, pall);
+    HCHK(hipGetLastError());
+    glds = gram_lds_bytes(tall, K, n);
+    if (glds > 65536)
+      HCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(gram_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds));
   }
 
   // the two factors: c -> A_c (column factor), a -> A_r (row factor)
@@ -308,6 +421,13 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
     HCHK(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
     HCHK(hipStreamSynchronize(s));
     if (hinfo != 0) { rc = KP_ERR_SOLVER; goto done; }
+    if (tall > 0) {
+      // Gram matrices of T(f_k) V(:, a) over this factor's profiles (Vt holds
+      // V row-major here)
+      hipLaunchKernelGGL(gram_kernel, dim3(n), dim3(GRAM_NT), glds, s, Vt, pall + f * tall * K,
+                         tall, K, n, G2 + (size_t)f * tall * tall * n);
+      HCHK(hipGetLastError());
+    }
     if (f == 0) {
       hipLaunchKernelGGL(factors_kernel, dim3(gnn), dim3(nthr), 0, s, Vt, U, n, P.Vc32, P.VcT32,
                          reinterpret_cast<_Float16*>(P.Vc16),
@@ -320,6 +440,19 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
       hipLaunchKernelGGL(sigma_kernel, dim3((n + 255) / 256), dim3(256), 0, s, P.sr, n, P.sr2);
     }
     HCHK(hipGetLastError());
+  }
+
+  // D0[i][j] = sum_p Gc[p][i] Gr[p][j] (p over term pairs): as column-major
+  // BLAS, D0^T (n x n) = Gr^T-layout (n x t^2) times Gc^T-layout^T
+  if (tall > 0) {
+    const double one = 1.0, zero = 0.0;
+    const size_t tt = (size_t)tall * tall;
+    SCHK(rocblas_dgemm(handle, rocblas_operation_none, rocblas_operation_transpose, n, n,
+                       (rocblas_int)tt, &one, G2 + tt * n, n, G2, n, &zero, D64, n));
+    hipLaunchKernelGGL(to_f32_kernel, dim3(gnn), dim3(nthr), 0, s, D64, nn, P.d0);
+    HCHK(hipGetLastError());
+  } else {
+    HCHK(hipMemsetAsync(P.d0, 0, sizeof(float) * nn, s));
   }
 
   // FP8 copies with 32-entry block exponents along each row
@@ -352,7 +485,7 @@ done:
   if (handle) rocblas_destroy_handle(handle);
   hipFree(dpsf); hipFree(pw); hipFree(spsf); hipFree(upsf); hipFree(vpsf); hipFree(e);
   hipFree(prof); hipFree(T); hipFree(U); hipFree(Vt); hipFree(info); hipFree(wv);
-  hipFree(perm);
+  hipFree(perm); hipFree(pall); hipFree(G2); hipFree(D64);
   return rc;
 }
 

@@ -24,6 +24,7 @@ KP_P32, KP_P16, KP_P8 = 0x000, 0x010, 0x020
 KP_WARM = 0x100
 KP_BATCH_EAGER = 0x200
 KP_NO_FALLBACK = 0x400
+KP_EXACT_DIAG = 0x800
 KP_MAX_PSF = 63
 KP_BLUR_MFMA = 6
 KP_MLP_NFEAT, KP_MLP_HIDDEN, KP_MLP_NPARAM = 128, 256, 164865
@@ -82,6 +83,7 @@ _SIGS = {
     "kp_normal_fp64": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP]),
     "kp_precond": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP, _VP]),
     "kp_get_factors": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "kp_get_diag": (ctypes.c_int, [_VP, _VP]),
     "kp_time_blur": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_float), _VP]),
     "kp_time_precond": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP,
@@ -223,6 +225,12 @@ class Plan:
         p = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
         _check(load().kp_get_factors(self._h, p(sc), p(sr), p(vc), p(vr)), "kp_get_factors")
         return sc, sr, vc, vr
+
+    def exact_diag(self):
+        """kp_get_diag: D0[i, j] = ||A (v_c,i v_r,j^T)||_F^2 (n x n float32)."""
+        d0 = np.empty((self.n, self.n), dtype=np.float32)
+        _check(load().kp_get_diag(self._h, d0.ctypes.data_as(ctypes.c_void_p)), "kp_get_diag")
+        return d0
 
     # -- the hot path -----------------------------------------------------
     def solve(self, b, lam: float, tol: float = 1e-6, maxit: int = 1000,

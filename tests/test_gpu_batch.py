@@ -207,3 +207,26 @@ def test_batched_true_residual_matches_oracle(tol):
     finally:
         for p in plans:
             p.close()
+
+
+def test_batched_exact_diag_items_match_oracle():
+    """pcg_solve_batched with KP_EXACT_DIAG: every item reaches the oracle's
+    x_lambda, with no more iterations than with the one-term diagonal."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_EXACT_DIAG, KP_FPCG, KP_OK, KP_P16, Plan
+    probs, items = _small_batch()
+    plans = [Plan(p.psf, p.n) for p in probs]
+    try:
+        say(f"batched exact diagonal: {len(items)} items")
+        xs, infos, st = _run(plans, probs, items, KP_FPCG | KP_P16 | KP_EXACT_DIAG, 1e-8, 400)
+        _, infos1, _ = _run(plans, probs, items, KP_FPCG | KP_P16, 1e-8, 400)
+        assert st == KP_OK
+        for (pi, lam), x, info, info1 in zip(items, xs, infos, infos1):
+            err = rel(x, _xlam(probs, pi, lam))
+            say(f"  n={probs[pi].n} k={probs[pi].k} lam={lam} iters={info.iters} "
+                f"(one-term {info1.iters}) err={err:.2e}")
+            assert info.status == KP_OK and err <= 1e-4
+            assert info.iters <= info1.iters + 1
+    finally:
+        for p in plans:
+            p.close()

@@ -276,3 +276,51 @@ def test_symmetric_and_general_factor_paths_agree(monkeypatch):
             plan.precond(r, lam, KP_P32, z)
             outs.append(to_host(z))
     assert rel(outs[0], outs[1]) < 1e-5
+
+
+@pytest.mark.parametrize("n,k,kind", [(64, 15, "moffat"), (100, 9, "rand"), (256, 31, "moffat"),
+                                      (128, 63, "moffat"), (64, 15, "gauss")])
+def test_exact_diag_matches_oracle(n, k, kind):
+    """kp_setup's exact KP-basis diagonal D0 = diag(V^T A^T A V) (all terms of
+    eq. (KronSumDecomp), FP64 Gram sums on the device, stored FP32) against
+    the oracle's, elementwise: FP32 rounding of each entry plus an absolute
+    1e-9 max(D0) for the entries far below the largest (FP64 cancellation
+    in the sum over term pairs, and the device's own FP64 V)."""
+    require_gpu()
+    from paper_2311_15393_amd import Plan
+    say(f"exact diagonal n={n} k={k} {kind}")
+    psf = _psf(kind, k, 21)
+    kp = KP.kp_svd(psf, n)
+    ref = KP.exact_diag(kp, psf)
+    with Plan(psf, n) as plan:
+        got = plan.exact_diag().astype(np.float64)
+    err = np.abs(got - ref)
+    say(f"  max rel (entries > 1e-3 max) "
+        f"{(err / ref)[ref > 1e-3 * ref.max()].max():.2e}, max abs / max {err.max() / ref.max():.2e}")
+    assert np.all(err <= 2.0 ** -23 * np.abs(ref) + 1e-9 * ref.max())
+
+
+@pytest.mark.parametrize("n,k,lam", [(64, 15, 0.02), (256, 31, 0.01)])
+def test_precond_exact_diag_matches_oracle(n, k, lam):
+    """z = V (S .* V^T r V) V^T with S = 1 / (D0 + lambda^2) on the device's
+    FP32 and FP16 chains vs the oracle's FP64 application with its own D0."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_EXACT_DIAG, KP_P16, KP_P32, Plan
+    say(f"precond exact diagonal n={n} k={k}")
+    psf = _psf("moffat", k, 23)
+    r = S.random_image(np.random.default_rng(29), n)
+    kp = KP.kp_svd(psf, n)
+    ref = KP.precond_solve(kp, lam, r.astype(np.float64), KP.exact_diag(kp, psf))
+    one = KP.precond_solve(kp, lam, r.astype(np.float64))
+    with Plan(psf, n) as plan:
+        z = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        plan.precond(to_dev(r), lam, KP_P32 | KP_EXACT_DIAG, z)
+        e32 = rel(to_host(z), ref)
+        plan.precond(to_dev(r), lam, KP_P16 | KP_EXACT_DIAG, z)
+        e16 = rel(to_host(z), ref)
+        plan.precond(to_dev(r), lam, KP_P32, z)
+        e_one = rel(to_host(z), one)
+    say(f"  fp32 {e32:.2e} fp16 {e16:.2e} (one-term fp32 {e_one:.2e}; "
+        f"the two S differ by {rel(one, ref):.2e})")
+    assert e32 < 1e-4 and e16 < 2e-2 and e_one < 1e-4
+    assert rel(one, ref) > 10 * e32        # the test can tell the two tables apart
