@@ -145,8 +145,8 @@ hipError_t autotune_blur(Plan& P, hipStream_t s, float* times_ms) {
   return err;
 }
 
-hipError_t launch_rhs(const Plan& P, const float* b, hipStream_t s) {
-  EpiRhs e{P.r, P.n};
+hipError_t launch_rhs(const Plan& P, const float* b, bool zero_x, hipStream_t s) {
+  EpiRhs e{P.r, P.n, P.p, P.w, zero_x ? P.x64 : nullptr};
   int nb;
   hipError_t err = blur_dispatch(P.blur_cfg, P, b, P.taps32, e, P.ctrl, 0, s, &nb);
   if (err != hipSuccess) return err;
@@ -154,11 +154,21 @@ hipError_t launch_rhs(const Plan& P, const float* b, hipStream_t s) {
 }
 
 hipError_t launch_true_residual(const Plan& P, const float* b, const double* x, double lam2,
-                                bool fin, bool fast, hipStream_t s) {
-  // u = b - A x (FP64 accumulation) into q (FP32) or y64 (FP64)
-  EpiResid e1{b, fast ? P.q : nullptr, fast ? nullptr : P.y64, P.n};
-  hipError_t err =
-      run_blur<KP_F64IN_CFG, double, double, double>(P, x, P.taps64_flip, e1, P.ctrl, 0, s);
+                                bool fin, int trmode, hipStream_t s) {
+  const bool fast = trmode != TR_FP64;
+  hipError_t err;
+  if (trmode == TR_FAST_ALL) {
+    // u = b - A fp32(x) on the plan's blur, into q (z holds fp32(x))
+    err = launch_convert_x(P, P.z, true, s);
+    if (err != hipSuccess) return err;
+    EpiResid e1{b, P.q, nullptr, P.n};
+    int nb1;
+    err = blur_dispatch(P.blur_cfg, P, P.z, P.taps32_flip, e1, P.ctrl, 0, s, &nb1);
+  } else {
+    // u = b - A x (FP64 accumulation) into q (FP32) or y64 (FP64)
+    EpiResid e1{b, fast ? P.q : nullptr, fast ? nullptr : P.y64, P.n};
+    err = run_blur<KP_F64IN_CFG, double, double, double>(P, x, P.taps64_flip, e1, P.ctrl, 0, s);
+  }
   if (err != hipSuccess) return err;
   EpiTrueRes e2{x, P.r, lam2, P.n, P.xa64, P.ra64};
   int nb;

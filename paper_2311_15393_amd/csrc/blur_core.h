@@ -83,8 +83,11 @@ struct EpiNormalW {
 // r_0 = c = A^T b and ||c||^2.  c only seeds the recursion: every true
 // residual is formed from b directly (EpiResid, EpiTrueRes), so an FP32-class
 // blur suffices here.
+// Optionally it also clears the solver's p, w and x (x_0 = 0) at the same
+// positions, saving separate fills.
 struct EpiRhs {
   float* r; int n;
+  float* p0 = nullptr; float* w0 = nullptr; double* x0 = nullptr;
   static constexpr bool kReduce = true;
   static constexpr int kSlot = SLOT_RHS;
   template <typename Acc>
@@ -94,6 +97,11 @@ struct EpiRhs {
       const double cv = (double)v[c];
       r[o + c] = (float)cv;
       d += cv * cv;
+      if (p0) {
+        p0[o + c] = 0.0f;
+        w0[o + c] = 0.0f;
+      }
+      if (x0) x0[o + c] = 0.0;
     }
   }
 };

@@ -131,5 +131,7 @@ template hipError_t launch_blur_mfma<EpiRhs>(const Plan&, const float*, bool, Ep
                                              int, hipStream_t);
 template hipError_t launch_blur_mfma<EpiTrueRes>(const Plan&, const float*, bool, EpiTrueRes,
                                                  Ctrl*, int, hipStream_t);
+template hipError_t launch_blur_mfma<EpiResid>(const Plan&, const float*, bool, EpiResid, Ctrl*,
+                                               int, hipStream_t);
 
 }  // namespace kpcg

@@ -110,11 +110,7 @@ int read_ctrl(Plan& P, hipStream_t s, Ctrl& out) {
 }
 
 int write_ctrl(Plan& P, hipStream_t s, const Ctrl& c) {
-  // the pinned buffer's second half stages host -> device writes
-  Ctrl* stage = P.host_ctrl + 1;
-  HIPCHK(hipStreamSynchronize(s));
-  std::memcpy(stage, &c, sizeof(Ctrl));
-  HIPCHK(hipMemcpyAsync(P.ctrl, stage, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_init_ctrl(P, c, s));
   return KP_OK;
 }
 
@@ -127,15 +123,58 @@ hipError_t enqueue_tail(Plan& P, int solver, int prec, float lam2, hipStream_t s
   return launch_pupdate_from(P, P.z, s);
 }
 
-hipError_t enqueue_iteration(Plan& P, int solver, int prec, float lam2, hipStream_t s) {
+// the first half of an iteration: matvecs, step length, update, ||r||
+hipError_t enqueue_matvec_half(Plan& P, float lam2, hipStream_t s) {
   hipError_t e;
   e = launch_blur_f32(P, P.p, P.q, false, s, P.ctrl);           // q = A p
   if (e != hipSuccess) return e;
   e = launch_blur_normal(P, P.q, P.p, P.w, lam2, s);            // w = A^T q + l^2 p, alpha
   if (e != hipSuccess) return e;
-  e = launch_update(P, s);                                      // x, r, ||r||
+  return launch_update(P, s);                                   // x, r, ||r||
+}
+
+hipError_t enqueue_iteration(Plan& P, int solver, int prec, float lam2, hipStream_t s) {
+  hipError_t e = enqueue_matvec_half(P, lam2, s);
   if (e != hipSuccess) return e;
   return enqueue_tail(P, solver, prec, lam2, s);
+}
+
+// The host mirror's latest publication, unpacked.
+struct Snap {
+  unsigned pub;
+  int iter, done, repl;
+  bool tol_hit, anchor_ok;
+};
+
+Snap read_mirror(const CtrlMirror* mirror) {
+  const unsigned long long w = *reinterpret_cast<const volatile unsigned long long*>(&mirror->word);
+  Snap out;
+  out.pub = (unsigned)(w & MIRROR_PUB_MASK);
+  out.iter = (int)((w >> 24) & 0xffffff);
+  out.done = (int)((w >> 48) & 0xf);
+  out.tol_hit = ((w >> 52) & 1) != 0;
+  out.anchor_ok = ((w >> 53) & 1) != 0;
+  out.repl = (int)((w >> 54) & 0x3ff);
+  return out;
+}
+
+// Wait for a publication other than `after` (numbers wrap at 2^24, far more
+// than one solve publishes between two reads).  Every few hundred polls the
+// stream is queried: an error ends the wait, and so does a drained stream
+// with nothing new published (nothing more can come).
+int wait_mirror(const Plan& P, hipStream_t s, unsigned after, Snap& out) {
+  for (unsigned spins = 1;; ++spins) {
+    out = read_mirror(P.mirror);
+    if (out.pub != after) return KP_OK;
+    if ((spins & 255u) == 0u) {
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipSuccess) {
+        out = read_mirror(P.mirror);
+        return out.pub != after ? KP_OK : KP_ERR_HIP;
+      }
+      if (q != hipErrorNotReady) return KP_ERR_HIP;
+    }
+  }
 }
 
 }  // namespace
@@ -194,12 +233,24 @@ int kp_setup(const double* psf, int k, int n, int bc, void* workspace, size_t ws
     return KP_ERR_HIP;
   }
   std::memset(P.host_ctrl, 0, 2 * sizeof(Ctrl));
+  if (hipHostMalloc(reinterpret_cast<void**>(&P.mirror), sizeof(CtrlMirror),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&P.mirror_dev), P.mirror, 0) !=
+          hipSuccess) {
+    if (P.mirror) hipHostFree(P.mirror);
+    hipHostFree(P.host_ctrl);
+    if (P.owns) hipFree(base);
+    delete h;
+    return KP_ERR_HIP;
+  }
+  std::memset(P.mirror, 0, sizeof(CtrlMirror));
   int rc = KP_OK;
   if (hipMemsetAsync(P.ctrl, 0, sizeof(Ctrl), s) != hipSuccess) rc = KP_ERR_HIP;
   if (rc == KP_OK) rc = build_factors(P, psf, s);
   if (rc == KP_OK && autotune_blur(P, s, P.blur_times) != hipSuccess) rc = KP_ERR_HIP;
   if (rc != KP_OK) {
     hipStreamSynchronize(s);
+    hipHostFree(P.mirror);
     hipHostFree(P.host_ctrl);
     if (P.owns) hipFree(base);
     delete h;
@@ -230,6 +281,8 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t* out) {
 int kp_destroy(kp_plan_t plan) {
   if (!plan) return KP_ERR_ARG;
   Plan& P = plan->P;
+  hipDeviceSynchronize();
+  if (P.mirror) hipHostFree(P.mirror);
   if (P.host_ctrl) hipHostFree(P.host_ctrl);
   if (P.owns && P.base) hipFree(P.base);
   delete plan;
@@ -270,7 +323,6 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   P.sprime_d0 = (mode & KP_EXACT_DIAG) ? P.d0 : nullptr;
   const double lam2d = lambda * lambda;
   const float lam2 = (float)lam2d;
-  double hc_gamma0sq = 0.0;
 
   Ctrl c;
   std::memset(&c, 0, sizeof(c));
@@ -283,46 +335,121 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   c.done = RUNNING;
   c.pscale = 1.0f;
   c.zscale = (float)(1.0 / lam2d);
+  // nothing of this plan may still be publishing when the mirror is reset
+  // (a no-op wait when the stream is idle, as after the previous solve)
+  HIPCHK(hipStreamSynchronize(s));
+  std::memset(P.mirror, 0, sizeof(CtrlMirror));
   int rc = write_ctrl(P, s, c);
   if (rc != KP_OK) return rc;
-  HIPCHK(hipMemsetAsync(P.p, 0, N * sizeof(float), s));
-  HIPCHK(hipMemsetAsync(P.w, 0, N * sizeof(float), s));
   if (mode & KP_WARM) HIPCHK(launch_convert_x(P, x, false, s));
-  else HIPCHK(hipMemsetAsync(P.x64, 0, N * sizeof(double), s));
 
   int replacements = 0;
-  // A true residual is A^T (b - A x) - lambda^2 x with b - A x in FP64 and
-  // A^T of it on the fast blur when the tolerance allows (TR_FAST_TOL).
+  // A true residual is A^T (b - A x) - lambda^2 x.  u = b - A x is formed on
+  // the fast blur for loose tolerances (TR_FASTU_TOL_*), else in FP64; A^T u
+  // on the fast blur from TR_FAST_TOL on, else in FP64.
   // After one at x_a (residual r_a), later ones are computed as
   // r_a - H (x - x_a) with FP32 matvecs on the small step x - x_a: exact in
   // exact arithmetic, with an error of ~1e-6 ||r_a||.  Used once
   // ||r_a|| <= ANCHOR_REL ||A^T b||, so the error stays ~1e-9 ||A^T b||.
-  const bool fast_tr = tol >= TR_FAST_TOL;
-  double anchor_rr = -1.0;                                       // none yet
+  const int trmode =
+      tol >= (P.blur_cfg == BLUR_CFG_MFMA ? TR_FASTU_TOL_MFMA : TR_FASTU_TOL_VALU) ? TR_FAST_ALL
+      : tol >= TR_FAST_TOL                                                        ? TR_FAST_AT
+                                                                                  : TR_FP64;
+  bool anchor_ok = false;        // the last true residual may anchor the next
   auto true_residual = [&](bool fin) -> hipError_t {
-    if (anchor_rr >= 0.0 && anchor_rr <= ANCHOR_REL * ANCHOR_REL * hc_gamma0sq)
-      return launch_anchor_residual(P, lam2d, fin, s);
-    return launch_true_residual(P, b, P.x64, lam2d, fin, fast_tr, s);
+    if (anchor_ok) return launch_anchor_residual(P, lam2d, fin, s);
+    return launch_true_residual(P, b, P.x64, lam2d, fin, trmode, s);
   };
-  HIPCHK(launch_rhs(P, b, s));                                  // r = c = A^T b, ||c||
+
+  // The host follows the device through the word the scalar steps publish,
+  // and keeps at most LOOKAHEAD publishing units enqueued beyond the last
+  // publication it has read.  A unit is half an iteration (A p, A^T q, step,
+  // update: publishes ||r||; preconditioner, direction: publishes r.z), or a
+  // whole iteration for CG.  Kernels enqueued after the device has marked
+  // the solve PENDING or finished exit at once and publish nothing.
+  constexpr unsigned LOOKAHEAD = 2;
+  Snap m{};
+  unsigned seen = 0;             // the last publication read (mod 2^24)
+  unsigned enq = 0;              // publications enqueued, if every unit runs
+  auto inflight = [&]() { return (enq - seen) & MIRROR_PUB_MASK; };
+  auto bump = [&]() { enq = (enq + 1u) & MIRROR_PUB_MASK; };
+  int its = 0;                   // iterations enqueued (matvec halves)
+  bool mv_next = true;           // the next unit is a matvec half
+  HIPCHK(launch_rhs(P, b, !(mode & KP_WARM), s));   // r = c = A^T b, ||c||; p = w (= x) = 0
+  bump();
   if (mode & KP_WARM) {
-    HIPCHK(launch_true_residual(P, b, P.x64, lam2d, true, fast_tr, s));   // r = c - H x0
+    HIPCHK(launch_true_residual(P, b, P.x64, lam2d, true, trmode, s));    // r = c - H x0
+    bump();
     ++replacements;
   }
-  // first direction p = z_0 (CG: p = r_0) and a first block of iterations,
-  // enqueued without reading the state back: zero or non-finite data marks
-  // the solve finished on the device and the kernels then exit at once
-  int block = 4;
+  // first direction p = z_0 (CG: p = r_0)
   HIPCHK(enqueue_tail(P, solver, prec, lam2, s));
-  {
-    const int m = block < maxit ? block : maxit;
-    for (int it = 0; it < m; ++it) HIPCHK(enqueue_iteration(P, solver, prec, lam2, s));
+  if (solver != KP_CG) bump();
+  auto top_up = [&]() -> hipError_t {
+    while (inflight() < LOOKAHEAD && its < maxit) {
+      hipError_t e;
+      if (solver == KP_CG) {
+        e = enqueue_iteration(P, solver, prec, lam2, s);
+        ++its;
+      } else if (mv_next) {
+        e = enqueue_matvec_half(P, lam2, s);
+        ++its;
+        mv_next = false;
+      } else {
+        e = enqueue_tail(P, solver, prec, lam2, s);
+        mv_next = true;
+      }
+      if (e != hipSuccess) return e;
+      bump();
+    }
+    return hipSuccess;
+  };
+  auto next = [&]() -> int {
+    const int rc2 = wait_mirror(P, s, seen, m);
+    if (rc2 != KP_OK) return rc2;
+    seen = m.pub;
+    anchor_ok = m.anchor_ok;
+    return KP_OK;
+  };
+
+  int state = RUNNING;
+  HIPCHK(top_up());
+  if ((rc = next()) != KP_OK) return rc;
+  for (;;) {
+    if (m.done == PENDING) {
+      // the recurrence residual met the tolerance or fell 1/REPLACE_DROP:
+      // recompute it from b and x and continue from the true residual.
+      // Everything enqueued after that publication was skipped.
+      its = m.iter;
+      HIPCHK(true_residual(true));
+      ++replacements;
+      enq = seen;
+      bump();
+      if (m.tol_hit || its >= maxit) {
+        // may have converged (or no budget left): see the outcome first
+        if ((rc = next()) != KP_OK) return rc;
+        if (m.done != RUNNING) { state = m.done; break; }
+        if (its >= maxit) { state = MAXIT; break; }
+      }
+      // then the direction from the new residual: CG's p = r + beta p
+      // (publishes nothing), else the preconditioner half as the next unit
+      if (solver == KP_CG) HIPCHK(enqueue_tail(P, solver, prec, lam2, s));
+      else mv_next = false;
+    } else if (m.done != RUNNING) {
+      state = m.done;
+      break;
+    } else if (m.iter >= maxit && inflight() == 0) {
+      state = MAXIT;
+      break;
+    }
+    HIPCHK(top_up());
+    if ((rc = next()) != KP_OK) return rc;
   }
+
   Ctrl hc;
-  if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
-  hc_gamma0sq = hc.gamma0sq;
-  if (mode & KP_WARM) anchor_rr = hc.true_rr;
+  if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;          // also drains the stream
   if (!(hc.gamma0sq > 0.0) || !std::isfinite(hc.gamma0sq)) {
+    // zero data: x = 0 is the solution; non-finite data: nothing to do
     const bool zero = hc.gamma0sq == 0.0;
     HIPCHK(hipMemsetAsync(x, 0, N * sizeof(float), s));
     HIPCHK(hipStreamSynchronize(s));
@@ -333,70 +460,8 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
     }
     return zero ? KP_OK : KP_BREAKDOWN;
   }
-
-  // Iterations are enqueued in blocks; kernels enqueued after the device has
-  // marked the solve finished exit at once but still cost a launch each.
-  // Once a contraction rate of ||r||^2 has been observed, a block is sized
-  // to reach the next stopping point (tolerance or replacement threshold).
-  double rate = 0.0;                   // mean per-iteration factor of ||r||^2
-  double rr_mark = (mode & KP_WARM) ? hc.true_rr : hc.gamma0sq;
-  int it_mark = 0;
-  if (hc.iter > 0 && hc.rr > 0.0 && hc.rr < rr_mark)
-    rate = std::pow(hc.rr / rr_mark, 1.0 / hc.iter);
-  if (block < 32) block *= 2;
-  if (hc.done == RUNNING && hc.iter >= maxit) hc.done = MAXIT;
-  bool anchor_pending = false;         // true residual run since the last read
-  while (hc.done == RUNNING || hc.done == PENDING) {
-    if (hc.done == PENDING) {
-      // the recurrence residual met the tolerance or fell 1/REPLACE_DROP:
-      // recompute it from b and x and continue from the true residual
-      HIPCHK(true_residual(true));
-      ++replacements;
-      const int todo = maxit - hc.iter;
-      if (hc.rr <= hc.tol2 || todo <= 0) {
-        // may have converged (or no budget left): read before going on
-        if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
-        anchor_rr = hc.true_rr;
-        anchor_pending = false;
-        if (hc.done != RUNNING) break;
-        if (hc.iter >= maxit) {
-          hc.done = MAXIT;
-          break;
-        }
-      } else {
-        // re-anchoring away from the tolerance: continue without a round trip
-        anchor_pending = true;
-      }
-      HIPCHK(enqueue_tail(P, solver, prec, lam2, s));
-      rr_mark = hc.rr;                 // restart the rate estimate from here
-      it_mark = hc.iter;
-    }
-    const int todo = maxit - hc.iter;
-    int m = block;
-    if (rate > 0.0 && rate < 1.0 && hc.rr > 0.0) {
-      // after an unread re-anchoring the device's threshold is
-      // REPLACE_DROP^2 times the new residual, which the recurrence value
-      // at the replacement approximates
-      const double repl2 = anchor_pending ? REPLACE_DROP * REPLACE_DROP * hc.rr : hc.repl2;
-      const double target = hc.tol2 > repl2 ? hc.tol2 : repl2;
-      const double need = std::ceil(std::log(target / hc.rr) / std::log(rate));
-      m = need < 1.0 ? 1 : (need > 32.0 ? 32 : (int)need);
-    }
-    m = m < todo ? m : todo;
-    for (int it = 0; it < m; ++it) HIPCHK(enqueue_iteration(P, solver, prec, lam2, s));
-    if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;
-    if (anchor_pending) {
-      anchor_rr = hc.true_rr;
-      anchor_pending = false;
-    }
-    if (hc.iter > it_mark && hc.rr > 0.0 && rr_mark > 0.0 && hc.rr < rr_mark)
-      rate = std::pow(hc.rr / rr_mark, 1.0 / (hc.iter - it_mark));
-    if (block < 32) block *= 2;
-    if (hc.done == RUNNING && hc.iter >= maxit) hc.done = MAXIT;
-  }
-
   double true_rr = hc.true_rr;
-  if (hc.done != CONVERGED) {
+  if (state != CONVERGED) {
     HIPCHK(true_residual(false));
     Ctrl t;
     if ((rc = read_ctrl(P, s, t)) != KP_OK) return rc;
@@ -405,8 +470,8 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   HIPCHK(launch_convert_x(P, x, true, s));
   HIPCHK(hipStreamSynchronize(s));
   int status;
-  if (hc.done == CONVERGED) status = KP_OK;
-  else if (hc.done == BREAKDOWN) status = KP_BREAKDOWN;
+  if (state == CONVERGED) status = KP_OK;
+  else if (state == BREAKDOWN) status = KP_BREAKDOWN;
   else status = (true_rr <= hc.tol2) ? KP_OK : KP_MAXIT;
   if (info) {
     info->iters = hc.iter;

@@ -69,8 +69,24 @@ struct Ctrl {
   double misfit2;   // ||A x - b||^2 (batched solves)
   int anchor;       // batched solves: (x_a, r_a) holds a true residual small
                     // enough (<= ANCHOR_REL ||A^T b||) to anchor the next one
-  int pad_;
+  int pub;          // publications to the host mirror so far (CtrlMirror)
 };
+
+// The convergence state as the scalar steps publish it to coherent pinned
+// host memory, so that the host follows a solve without stream round trips:
+// one naturally aligned 64-bit word, written with a single store (so the
+// host never sees a torn state, and no fence is needed: the store lands at
+// the latest when the kernel ends).
+//   bits  0-23  publication number p = 1, 2, ... (mod 2^24)
+//   bits 24-47  iterations done
+//   bits 48-51  state (RUNNING, CONVERGED, MAXIT, BREAKDOWN, PENDING)
+//   bit  52     the residual norm met the tolerance (PENDING for a check)
+//   bit  53     the last true residual may anchor the next one
+//   bits 54-63  true-residual replacements (mod 2^10)
+struct CtrlMirror {
+  unsigned long long word;
+};
+constexpr unsigned MIRROR_PUB_MASK = (1u << 24) - 1u;
 
 // A true residual r_a at x_a anchors later ones, r = r_a - H (x - x_a) with
 // FP32 matvecs on the step, once ||r_a|| <= ANCHOR_REL ||A^T b||.
@@ -82,6 +98,17 @@ constexpr double ANCHOR_REL = 1e-2;
 // residuals ||u|| of a few per cent of ||b|| and below TR_FAST_TOL / 5 even
 // at ||u|| = ||b||; tighter tolerances use the FP64 blur for it.
 constexpr double TR_FAST_TOL = 1e-7;
+// From these tolerances on, u = b - A x is formed on the fast blur as well
+// (x rounded to FP32).  Its error reaches the residual as A^T du, smoothed by
+// the blur, and x only through the Tikhonov filter (A^T A + lambda^2 I)^-1
+// A^T, whose norm is at most 1 / (2 lambda) (the form c - H x would amplify
+// by 1 / lambda^2).  Measured at 1024^2, K = 63: ||dr|| <= 6.5e-8 ||A^T b||
+// on the MFMA blur, <= 1.4e-7 on the FP32 VALU blur; x moves by <= 1.7e-6
+// and 5e-6 of its norm.
+constexpr double TR_FASTU_TOL_MFMA = 1e-6;
+constexpr double TR_FASTU_TOL_VALU = 1e-5;
+// how a true residual forms u = b - A x and A^T u
+enum TrMode : int { TR_FP64 = 0, TR_FAST_AT = 1, TR_FAST_ALL = 2 };
 
 // ---------------------------------------------------------------------------
 // reductions: deterministic two-stage sums (per-block FP64 partials, summed
@@ -199,6 +226,8 @@ struct Plan {
   Ctrl* ctrl = nullptr;
   double* partials = nullptr;
   Ctrl* host_ctrl = nullptr;     // pinned
+  CtrlMirror* mirror = nullptr;  // coherent pinned host memory (host address)
+  CtrlMirror* mirror_dev = nullptr;  // its device address
 
   int blur_cfg = 0;              // blur kernel (autotuned; BLUR_CFG_MFMA = MFMA)
   int blur_cfg_valu = 0;         // fastest FP32-VALU tile shape (batched path)
@@ -217,18 +246,21 @@ hipError_t launch_blur_f32(const Plan& P, const float* src, float* dst, bool tra
                            hipStream_t s, const Ctrl* ctrl);
 hipError_t launch_blur_normal(const Plan& P, const float* q, const float* p, float* w,
                               float lam2, hipStream_t s);
-// r = c = A^T b on the plan's blur, ||c||^2 (the SC_RHS scalar step)
-hipError_t launch_rhs(const Plan& P, const float* b, hipStream_t s);
+// r = c = A^T b on the plan's blur, ||c||^2 (the SC_RHS scalar step); also
+// p = w = 0 and, with zero_x, x = 0
+hipError_t launch_rhs(const Plan& P, const float* b, bool zero_x, hipStream_t s);
+// the control block set to `c` by a kernel (stream-ordered, no host sync)
+hipError_t launch_init_ctrl(const Plan& P, const Ctrl& c, hipStream_t s);
 hipError_t autotune_blur(Plan& P, hipStream_t s, float* times_ms);
 // r = r_a - H (x - x_a) from the anchor (x_a, r_a) of the last true residual,
 // with the FP32 blur kernels on the difference and FP64 epilogue arithmetic;
 // moves the anchor to x
 hipError_t launch_anchor_residual(const Plan& P, double lam2, bool fin, hipStream_t s);
 hipError_t launch_diff32(const Plan& P, float* d, hipStream_t s);
-// r = A^T (b - A x) - lam2 x: b - A x in FP64, A^T of it on the plan's blur
-// (fast) or in FP64; records the anchor (x, r)
+// r = A^T (b - A x) - lam2 x with u = b - A x and A^T u on the FP64 blur or
+// the plan's fast blur as TrMode says; records the anchor (x, r)
 hipError_t launch_true_residual(const Plan& P, const float* b, const double* x64, double lam2,
-                                bool fin, bool fast, hipStream_t s);
+                                bool fin, int trmode, hipStream_t s);
 hipError_t launch_normal_fp64(const Plan& P, const float* x, double lam2, double* y,
                               hipStream_t s);
 

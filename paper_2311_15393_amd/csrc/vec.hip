@@ -117,6 +117,15 @@ hipError_t launch_convert_x(const Plan& P, float* x, bool to_f32, hipStream_t s)
   return hipGetLastError();
 }
 
+__global__ void init_ctrl_kernel(Ctrl* __restrict__ c, Ctrl v) {
+  if (threadIdx.x == 0) *c = v;
+}
+
+hipError_t launch_init_ctrl(const Plan& P, const Ctrl& c, hipStream_t s) {
+  hipLaunchKernelGGL(init_ctrl_kernel, dim3(1), dim3(64), 0, s, P.ctrl, c);
+  return hipGetLastError();
+}
+
 // d = fp32(x - x_a): the step since the anchor
 __global__ __launch_bounds__(VT) void diff32_kernel(const double* __restrict__ x64,
                                                     const double* __restrict__ xa64,
@@ -164,9 +173,13 @@ __device__ inline double sum_slot(const double* partials, int slot, int nb, doub
   return block_sum<ST>(s, sh);
 }
 
+// Every step that the host follows (the residual norm after an update, the
+// direction step, the right-hand side, true residuals, and a breakdown found
+// by the step length) publishes the new state to the host mirror.
 __global__ __launch_bounds__(ST) void scalar_kernel(Ctrl* __restrict__ c,
                                                     const double* __restrict__ partials,
-                                                    int kind, int nb) {
+                                                    int kind, int nb,
+                                                    CtrlMirror* __restrict__ mirror) {
   __shared__ double sh[ST / 64];
   const int done = c->done;
   if ((kind == SC_ALPHA || kind == SC_RR || kind == SC_BETA) && done != RUNNING) return;
@@ -238,6 +251,7 @@ __global__ __launch_bounds__(ST) void scalar_kernel(Ctrl* __restrict__ c,
       if (!isfinite(S)) c->done = BREAKDOWN;
       else if (S <= c->tol2) c->done = CONVERGED;
       else if (done == PENDING) c->done = RUNNING;
+      c->repl += 1;
       break;
     case SC_TRUE_INFO:
       c->true_rr = S;
@@ -247,11 +261,25 @@ __global__ __launch_bounds__(ST) void scalar_kernel(Ctrl* __restrict__ c,
       set_scales(c, S);
       break;
   }
+  const bool publish = kind == SC_RR || kind == SC_BETA || kind == SC_RHS || kind == SC_TRUE ||
+                       kind == SC_TRUE_INFO || (kind == SC_ALPHA && c->done != RUNNING);
+  if (mirror != nullptr && publish) {
+    const unsigned p = ((unsigned)c->pub + 1u) & MIRROR_PUB_MASK;
+    c->pub = (int)p;
+    const bool tol_hit = c->rr <= c->tol2;
+    const bool anchor_ok = c->repl > 0 && c->true_rr <= ANCHOR_REL * ANCHOR_REL * c->gamma0sq;
+    const unsigned long long w =
+        (unsigned long long)p | ((unsigned long long)(c->iter & 0xffffff) << 24) |
+        ((unsigned long long)(c->done & 0xf) << 48) | ((unsigned long long)tol_hit << 52) |
+        ((unsigned long long)anchor_ok << 53) | ((unsigned long long)(c->repl & 0x3ff) << 54);
+    *reinterpret_cast<volatile unsigned long long*>(&mirror->word) = w;
+  }
 }
 
 hipError_t launch_scalar(const Plan& P, int kind, int nb, hipStream_t s) {
   if (nb > MAX_PARTIALS) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(ST), 0, s, P.ctrl, P.partials, kind, nb);
+  hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(ST), 0, s, P.ctrl, P.partials, kind, nb,
+                     P.mirror_dev);
   return hipGetLastError();
 }
 
