@@ -53,6 +53,7 @@ size_t layout(int n, int k, char* base, Plan* P) {
   Q.sc2 = b.take<float>(n);
   Q.sr2 = b.take<float>(n);
   Q.d0 = b.take<float>(nn);
+  Q.d0t = b.take<float>(nn);
   Q.Vc32 = b.take<float>(nn);
   Q.VcT32 = b.take<float>(nn);
   Q.Vr32 = b.take<float>(nn);
@@ -446,13 +447,17 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
     if ((rc = next()) != KP_OK) return rc;
   }
 
-  Ctrl hc;
-  if ((rc = read_ctrl(P, s, hc)) != KP_OK) return rc;          // also drains the stream
-  if (!(hc.gamma0sq > 0.0) || !std::isfinite(hc.gamma0sq)) {
+  // an unconverged solve reports its true residual; then x in FP32 (x_0 = 0
+  // stays 0 for zero or non-finite data)
+  if (state != CONVERGED) HIPCHK(true_residual(false));
+  HIPCHK(launch_convert_x(P, x, true, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const volatile CtrlMirror* fm = P.mirror;       // complete: the stream has drained
+  const double gamma0sq = fm->gamma0sq, true_rr = fm->true_rr, rr = fm->rr, tol2 = fm->tol2;
+  const int iters = fm->iter;
+  if (!(gamma0sq > 0.0) || !std::isfinite(gamma0sq)) {
     // zero data: x = 0 is the solution; non-finite data: nothing to do
-    const bool zero = hc.gamma0sq == 0.0;
-    HIPCHK(hipMemsetAsync(x, 0, N * sizeof(float), s));
-    HIPCHK(hipStreamSynchronize(s));
+    const bool zero = gamma0sq == 0.0;
     if (info) {
       std::memset(info, 0, sizeof(*info));
       info->status = zero ? KP_OK : KP_BREAKDOWN;
@@ -460,28 +465,19 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
     }
     return zero ? KP_OK : KP_BREAKDOWN;
   }
-  double true_rr = hc.true_rr;
-  if (state != CONVERGED) {
-    HIPCHK(true_residual(false));
-    Ctrl t;
-    if ((rc = read_ctrl(P, s, t)) != KP_OK) return rc;
-    true_rr = t.true_rr;
-  }
-  HIPCHK(launch_convert_x(P, x, true, s));
-  HIPCHK(hipStreamSynchronize(s));
   int status;
   if (state == CONVERGED) status = KP_OK;
   else if (state == BREAKDOWN) status = KP_BREAKDOWN;
-  else status = (true_rr <= hc.tol2) ? KP_OK : KP_MAXIT;
+  else status = (true_rr <= tol2) ? KP_OK : KP_MAXIT;
   if (info) {
-    info->iters = hc.iter;
+    info->iters = iters;
     info->status = status;
     info->replacements = replacements;
     info->fallback = 0;
-    info->relres_rec = std::sqrt(hc.rr / hc.gamma0sq);
-    info->relres_true = std::sqrt(true_rr / hc.gamma0sq);
+    info->relres_rec = std::sqrt(rr / gamma0sq);
+    info->relres_true = std::sqrt(true_rr / gamma0sq);
     info->lambda = lambda;
-    info->rhs_norm = std::sqrt(hc.gamma0sq);
+    info->rhs_norm = std::sqrt(gamma0sq);
     info->misfit = 0.0;
   }
   return status;

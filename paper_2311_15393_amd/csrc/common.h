@@ -83,8 +83,12 @@ struct Ctrl {
 //   bit  52     the residual norm met the tolerance (PENDING for a check)
 //   bit  53     the last true residual may anchor the next one
 //   bits 54-63  true-residual replacements (mod 2^10)
+// The values the host reports at the end of a solve are written beside it;
+// they are read only after the stream has drained.
 struct CtrlMirror {
   unsigned long long word;
+  double rr, true_rr, gamma0sq, tol2;
+  int iter, pad_;
 };
 constexpr unsigned MIRROR_PUB_MASK = (1u << 24) - 1u;
 
@@ -191,6 +195,7 @@ struct Plan {
   float* sc2 = nullptr;          // squares in FP32
   float* sr2 = nullptr;
   float* d0 = nullptr;           // exact KP-basis diagonal diag(V^T A^T A V), [n][n]
+  float* d0t = nullptr;          // the same transposed, [j][i]
   const float* sprime_d0 = nullptr;  // the current solve's S' table: d0 with
                                      // KP_EXACT_DIAG, else nullptr (s_c^2 s_r^2)
   float* Vc32 = nullptr;         // row-major Vc[i][a]

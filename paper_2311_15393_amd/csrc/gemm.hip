@@ -82,7 +82,7 @@ static hipError_t precond_chain(const Plan& P, const T* VcT, const T* Vc, const 
   hipError_t e;
   e = run_gemm<T, true>(P, VcT, r, GEpiStore<T>{t1, n}, skip, 1, s);
   if (e != hipSuccess) return e;
-  e = run_gemm<T, false>(P, t1, VrT, GEpiSPrimeT<T>{t2, P.sc2, P.sr2, lam2, n, P.sprime_d0}, skip, 0, s);
+  e = run_gemm<T, false>(P, t1, VrT, GEpiSPrimeT<T>{t2, P.sc2, P.sr2, lam2, n, nullptr, P.sprime_d0 ? P.d0t : nullptr}, skip, 0, s);
   if (e != hipSuccess) return e;
   e = run_gemm<T, false>(P, Vc, t2, GEpiStore<T>{t3, n}, skip, 0, s);
   if (e != hipSuccess) return e;

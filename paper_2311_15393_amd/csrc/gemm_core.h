@@ -159,8 +159,15 @@ __device__ inline void mma_stage(const Tile<T>& sA, const Tile<T>& sB, float4_t 
 }
 
 // ---------------------------------------------------------------------------
-// epilogues: lane holds C[i0 + 4*(lane>>4) + v][j0 + (lane&15)], v = 0..3
+// epilogues: apply(i, j, v) for C[i][j] = v.  kColMajor asks the split-K
+// kernel to hand consecutive threads consecutive i (for stores along i).
 // ---------------------------------------------------------------------------
+template <class Epi, class = void>
+struct ColMajorEpi : std::false_type {};
+template <class Epi>
+struct ColMajorEpi<Epi, std::void_t<decltype(Epi::kColMajor)>>
+    : std::integral_constant<bool, Epi::kColMajor> {};
+
 template <typename T>
 struct GEpiStore {                       // row-major store
   T* C; int n;
@@ -174,10 +181,16 @@ template <typename T>
 struct GEpiSPrimeT {                     // T2^T[j][i] = S'[i][j] * T[i][j]
   // S' = lam2 / (s_c[i]^2 s_r[j]^2 + lam2), or lam2 / (d0[i][j] + lam2) with
   // the exact KP-basis diagonal d0
+  // the exact KP-basis diagonal d0 ([i][j]), or its transpose d0t ([j][i],
+  // read along i like the stores)
   T* C; const float* sc2; const float* sr2; float lam2; int n; const float* d0;
+  const float* d0t = nullptr;
   static constexpr bool kReduce = false;
+  static constexpr bool kColMajor = true;
   __device__ void apply(int i, int j, float v, double&, double&) const {
-    const float den = d0 ? d0[(size_t)i * n + j] + lam2 : fmaf(sc2[i], sr2[j], lam2);
+    const float den = d0t  ? d0t[(size_t)j * n + i] + lam2
+                      : d0 ? d0[(size_t)i * n + j] + lam2
+                           : fmaf(sc2[i], sr2[j], lam2);
     const float sp = lam2 / den;
     C[(size_t)j * n + i] = (T)(sp * v);
   }
@@ -283,6 +296,7 @@ template <typename T>
 constexpr size_t gemm_splitk_lds(int ks) {
   return (size_t)4 * ks * sizeof(Tile<T>);
 }
+constexpr int RED_LD = BN + 1;           // row pitch of the reduction tiles (floats)
 
 template <typename T, bool B_FROM_F32, class Epi, int KS>
 __device__ inline void gemm_tile_splitk(const T* __restrict__ A, const void* __restrict__ Bsrc,
@@ -290,8 +304,9 @@ __device__ inline void gemm_tile_splitk(const T* __restrict__ A, const void* __r
                                         float oscale, double* partial_out, int slot_stride,
                                         char* lds) {
   constexpr int BK = MT<T>::BK;
-  static_assert((KS - 1) * 4 * 16 * 64 * sizeof(float) <= gemm_splitk_lds<T>(KS),
-                "reduction buffer must fit in the stage buffers");
+  static_assert((size_t)KS * BM * RED_LD * sizeof(float) <= gemm_splitk_lds<T>(KS),
+                "reduction tiles must fit in the stage buffers");
+  static_assert((BM * BN) % (GT * KS) == 0, "outputs must split evenly over the threads");
   Tile<T>* sA = reinterpret_cast<Tile<T>*>(lds);     // [KS][2]
   Tile<T>* sB = sA + 2 * KS;                          // [KS][2]
   const int kg = threadIdx.x / GT, tid = threadIdx.x % GT;
@@ -341,40 +356,35 @@ __device__ inline void gemm_tile_splitk(const T* __restrict__ A, const void* __r
     __syncthreads();
   }
 
-  // cross-group reduction (the stage buffers are free after the last barrier)
-  float* red = reinterpret_cast<float*>(lds);
-  if (kg > 0) {
+  // cross-group reduction (the stage buffers are free after the last barrier):
+  // every group leaves its 64 x 64 partial tile in LDS, then all GT * KS
+  // threads add the KS partials of their outputs in group order and run the
+  // epilogue, consecutive threads on consecutive j (or i for kColMajor) so
+  // that global accesses coalesce
+  float* red = reinterpret_cast<float*>(lds);        // [KS][BM][RED_LD]
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
+    for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          red[(((kg - 1) * 4 + wv) * 16 + (mi * 2 + ni) * 4 + v) * 64 + lane] = acc[mi][ni][v];
-  }
+      for (int v = 0; v < 4; ++v) {
+        const int il = wm * 32 + mi * 16 + 4 * (lane >> 4) + v;
+        const int jl = wn * 32 + ni * 16 + (lane & 15);
+        red[((size_t)kg * BM + il) * RED_LD + jl] = acc[mi][ni][v];
+      }
   __syncthreads();
   double d0 = 0.0, d1 = 0.0;
-  if (kg == 0) {
+  constexpr bool kCol = ColMajorEpi<Epi>::value;
 #pragma unroll
-    for (int g = 1; g < KS; ++g)
+  for (int q = 0; q < BM * BN / (GT * KS); ++q) {
+    const int idx = threadIdx.x + q * GT * KS;
+    const int il = kCol ? idx % BM : idx / BN;
+    const int jl = kCol ? idx / BM : idx % BN;
+    float v = red[(size_t)il * RED_LD + jl];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            acc[mi][ni][v] += red[(((g - 1) * 4 + wv) * 16 + (mi * 2 + ni) * 4 + v) * 64 + lane];
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni) {
-        const int j = n0 + wn * 32 + ni * 16 + (lane & 15);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = m0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + v;
-          if (i < n && j < n) epi.apply(i, j, acc[mi][ni][v] * oscale, d0, d1);
-        }
-      }
+    for (int g = 1; g < KS; ++g) v += red[((size_t)g * BM + il) * RED_LD + jl];
+    const int i = m0 + il, j = n0 + jl;
+    if (i < n && j < n) epi.apply(i, j, v * oscale, d0, d1);
   }
   if constexpr (Epi::kReduce) {
     __shared__ double sh[GT * KS / 64];

@@ -152,9 +152,15 @@ __global__ __launch_bounds__(GRAM_NT) void gram_kernel(const double* __restrict_
   }
 }
 
-__global__ void to_f32_kernel(const double* __restrict__ src, size_t cnt, float* __restrict__ dst) {
+// FP32 copies of a row-major n x n FP64 matrix, as is and transposed
+__global__ void to_f32_kernel(const double* __restrict__ src, int n, float* __restrict__ dst,
+                              float* __restrict__ dst_t) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < cnt) dst[idx] = (float)src[idx];
+  if (idx >= (size_t)n * n) return;
+  const float v = (float)src[idx];
+  const size_t i = idx / n, j = idx - i * n;
+  dst[idx] = v;
+  dst_t[j * n + i] = v;
 }
 
 // Column-major banded Toeplitz T(f)[i][i'] = f[h + i - i'].
@@ -449,10 +455,11 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
     const size_t tt = (size_t)tall * tall;
     SCHK(rocblas_dgemm(handle, rocblas_operation_none, rocblas_operation_transpose, n, n,
                        (rocblas_int)tt, &one, G2 + tt * n, n, G2, n, &zero, D64, n));
-    hipLaunchKernelGGL(to_f32_kernel, dim3(gnn), dim3(nthr), 0, s, D64, nn, P.d0);
+    hipLaunchKernelGGL(to_f32_kernel, dim3(gnn), dim3(nthr), 0, s, D64, n, P.d0, P.d0t);
     HCHK(hipGetLastError());
   } else {
     HCHK(hipMemsetAsync(P.d0, 0, sizeof(float) * nn, s));
+    HCHK(hipMemsetAsync(P.d0t, 0, sizeof(float) * nn, s));
   }
 
   // FP8 copies with 32-entry block exponents along each row

@@ -272,7 +272,13 @@ __global__ __launch_bounds__(ST) void scalar_kernel(Ctrl* __restrict__ c,
         (unsigned long long)p | ((unsigned long long)(c->iter & 0xffffff) << 24) |
         ((unsigned long long)(c->done & 0xf) << 48) | ((unsigned long long)tol_hit << 52) |
         ((unsigned long long)anchor_ok << 53) | ((unsigned long long)(c->repl & 0x3ff) << 54);
-    *reinterpret_cast<volatile unsigned long long*>(&mirror->word) = w;
+    volatile CtrlMirror* m = mirror;
+    m->rr = c->rr;
+    m->true_rr = c->true_rr;
+    m->gamma0sq = c->gamma0sq;
+    m->tol2 = c->tol2;
+    m->iter = c->iter;
+    m->word = w;
   }
 }
 
