@@ -38,7 +38,14 @@ def spectrum(kp: kpmod.KPSVD, b: np.ndarray):
 
 
 def gcv(s2, bhat2, lams, omega: float = 1.0):
-    """G_w on each grid lambda (G for omega = 1), eq. (wGCVTikSVD)."""
+    """G_w on each grid lambda (G for omega = 1), eq. (wGCVTikSVD).
+
+    For omega > 1 the trace term T(lambda) = sum((1 - omega) s^2 + lambda^2)
+    / (s^2 + lambda^2) increases with lambda and is negative below some
+    lambda_0, where G_w falls back towards 0 as lambda -> 0.  The paper
+    minimises G_w on a bracket (Section 2.2) without naming the branch; the
+    reading taken: only the branch T > 0, continuous with large lambda, is
+    admissible, and G_w is +inf elsewhere (never for omega <= 1)."""
     s2 = np.asarray(s2, dtype=np.float64)
     bhat2 = np.asarray(bhat2, dtype=np.float64)
     N = s2.size
@@ -48,7 +55,7 @@ def gcv(s2, bhat2, lams, omega: float = 1.0):
         den = s2 + l2
         num = N * np.sum(l2 * l2 * bhat2 / (den * den))
         tr = np.sum(((1.0 - omega) * s2 + l2) / den)
-        out.append(num / (tr * tr))
+        out.append(num / (tr * tr) if tr > 0.0 else np.inf)
     return np.asarray(out)
 
 
@@ -119,7 +126,8 @@ def discrepancy_root(s2, bhat2, eps: float, lo: float = 1e-8, hi: float = 1e2,
 
 def gcv_trace_form(psf: np.ndarray, b: np.ndarray, lam: float, omega: float = 1.0) -> float:
     """Eq. (GCVTik)/(wGCVTik) with the dense influence matrix
-    A A_lambda^+ = A (A^T A + lambda^2 I)^{-1} A^T."""
+    A A_lambda^+ = A (A^T A + lambda^2 I)^{-1} A^T; +inf where the trace of
+    I - omega A A_lambda^+ is not positive (the branch rule of gcv)."""
     n = b.shape[0]
     N = n * n
     a = dense_matrix(psf, n)
@@ -127,7 +135,7 @@ def gcv_trace_form(psf: np.ndarray, b: np.ndarray, lam: float, omega: float = 1.
     bv = vec(np.asarray(b, dtype=np.float64))
     res = bv - infl @ bv
     tr = np.trace(np.eye(N) - omega * infl)
-    return float(N * (res @ res) / tr ** 2)
+    return float(N * (res @ res) / tr ** 2) if tr > 0.0 else float("inf")
 
 
 def dense_spectrum(psf: np.ndarray, b: np.ndarray):

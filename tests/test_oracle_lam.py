@@ -33,12 +33,22 @@ def test_gcv_svd_form_equals_trace_form(omega):
     s2, bh2 = L.dense_spectrum(psf, b)
     kp = KP.kp_svd(psf, n)
     ks2, kbh2 = L.spectrum(kp, b)
+    inadmissible = 0
     for lam in LAMS:
         tr = L.gcv_trace_form(psf, b, lam, omega)
         sv = L.gcv(s2, bh2, [lam], omega)[0]
         kb = L.gcv(ks2, kbh2, [lam], omega)[0]
+        if np.isinf(tr):
+            # the dense trace of I - omega A A^+ is not positive: the spectral
+            # forms must exclude the same lambda
+            inadmissible += 1
+            assert np.isinf(sv) and np.isinf(kb)
+            continue
         assert abs(sv - tr) <= 1e-8 * tr
         assert abs(kb - tr) <= 1e-8 * tr
+    assert inadmissible == 0 or omega > 1.0
+    if omega > 1.0:
+        assert 0 < inadmissible < len(LAMS)     # both branches are exercised
 
 
 def test_gcv_printed_form_equals_weighted_form_at_omega_one():
@@ -95,3 +105,19 @@ def test_grid_rules_tie_breaking():
     assert L.grid_argmin([3.0, 1.0, 1.0, 2.0]) == 1
     assert L.grid_discrepancy([-2.0, -1.0, 0.0, 1.0]) == 2
     assert L.grid_discrepancy([1.0, 2.0]) == 0
+
+
+def test_discrepancy_choice_grows_with_eta():
+    """D(lambda) = sum (lambda^2 b_hat / (s^2 + lambda^2))^2 - (eta ||eps||)^2
+    increases with lambda, so a larger eta can only move the discrepancy
+    choice to a larger (or the same) lambda (eq. (DSCTikSVD) with the modified
+    epsilon of Section 5.1); the bisection root grows strictly."""
+    psf, x, b, nn = _separable(24, 7, 3)
+    kp = KP.kp_svd(psf, 24)
+    s2, bh2 = L.spectrum(kp, b)
+    grid = np.logspace(-4, 0, 48)
+    idx = [L.grid_discrepancy(L.discrepancy(s2, bh2, grid, eta * nn)) for eta in
+           (1.0, 2.0, 3.0, 5.0, 10.0, 15.0)]
+    assert idx == sorted(idx) and idx[-1] > idx[0]
+    roots = [L.discrepancy_root(s2, bh2, eta * nn) for eta in (1.0, 2.0, 3.0)]
+    assert roots[0] < roots[1] < roots[2]
