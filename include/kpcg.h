@@ -188,9 +188,13 @@ int pcg_solve(kp_plan_t plan, const float *b, double lambda, double tol,
  * Kronecker approximation's SVD as in Section 5.1):
  *   b_hat = U_c^T B U_r,  s_ij = s_c[i] s_r[j],
  *   G_w(l) = N sum (l^2 b_hat/(s^2+l^2))^2 / (sum ((1-w) s^2 + l^2)/(s^2+l^2))^2
- * omega = 1 gives GCV.  lambda_out = the grid value with the smallest score
- * (ties: smallest index).  scores_out: ngrid FP64 scores (host, may be
- * NULL).  grid: host array of ngrid > 0 positive values.  Synchronises.
+ * omega = 1 gives GCV.  For omega > 1 the trace term (the denominator
+ * before squaring) increases with l and is negative for small l, where G_w
+ * would fall back towards 0: those grid points score +inf, so the choice is
+ * made on the branch continuous with large l (the paper minimises on a
+ * bracket).  lambda_out = the grid value with the smallest score (ties:
+ * smallest index).  scores_out: ngrid FP64 scores (host, may be NULL).
+ * grid: host array of ngrid > 0 positive values.  Synchronises.
  */
 int gcv_lambda(kp_plan_t plan, const float *b, const double *grid, int ngrid,
                double omega, double *lambda_out, double *scores_out,

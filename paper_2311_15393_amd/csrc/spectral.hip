@@ -58,7 +58,10 @@ __global__ __launch_bounds__(ST) void spectral_partials_kernel(
 }
 
 // kind 0: (weighted) GCV score; kind 1: discrepancy value (noise2 = eps^2);
-// kind 2: optimal error
+// kind 2: optimal error.  The weighted GCV trace term increases with lambda;
+// for omega > 1 it is negative below some lambda_0, where the score would
+// fall back towards 0: only the branch with a positive trace (continuous
+// with large lambda) is admissible, the others score +inf.
 __global__ __launch_bounds__(64) void spectral_final_kernel(const double* __restrict__ part,
                                                             int nb, int ngrid, int kind, double N,
                                                             double noise2,
@@ -70,7 +73,8 @@ __global__ __launch_bounds__(64) void spectral_final_kernel(const double* __rest
     num += part[(size_t)(2 * g) * nb + b];
     tr += part[(size_t)(2 * g + 1) * nb + b];
   }
-  scores[g] = kind == 0 ? N * num / (tr * tr) : (kind == 1 ? num - noise2 : num);
+  scores[g] = kind == 0 ? (tr > 0.0 ? N * num / (tr * tr) : INFINITY)
+                       : (kind == 1 ? num - noise2 : num);
 }
 
 hipError_t launch_spectrum(const Plan& P, const float* b, hipStream_t s) {

@@ -145,6 +145,21 @@ def psf_moffat_motion(k: int, alpha: float, beta: float, length: float,
     return _finish(np.maximum(p, 0.0))
 
 
+def psf_defocus(k: int, radius: float) -> np.ndarray:
+    """Out-of-focus blur: a uniform disk of the given radius (pixels) centred
+    on the k x k support, each pixel weighted by the fraction of its area
+    inside the disk (8 x 8 sub-samples), unit sum."""
+    if k % 2 != 1:
+        raise ValueError("PSF support must be odd")
+    y, x = _offsets(k)
+    sub = (np.arange(8) + 0.5) / 8 - 0.5
+    cover = np.zeros((k, k))
+    for dy in sub:
+        for dx in sub:
+            cover += ((x + dx) ** 2 + (y + dy) ** 2 <= radius * radius)
+    return _finish(cover / 64.0)
+
+
 # --------------------------------------------------------------------------
 # data
 # --------------------------------------------------------------------------
@@ -247,6 +262,34 @@ def training_group(group: int, per_psf: int = 8, n: int = 256, seed0: int = TRAI
         nu = rng.uniform(0.005, 0.03)
         out.append(make_problem(n, psf, rng, nu, None, seed, kind))
     return out
+
+
+STUDY_SEED0 = 130000       # problems of the parameter-choice study
+
+
+def study_problem(kind: str, n: int, noise_level: float, index: int,
+                  seed0: int = STUDY_SEED0) -> Problem:
+    """A problem of the parameter-choice study: the paper's blur families at
+    its noise levels (Section 5: 1% and 10%), drawn like the other workloads.
+    kind: "gauss" (rotated anisotropic Gaussian, sigma ~ U[1.5, 4]),
+    "defocus" (disk radius ~ U[3, 6]), "motion" (Moffat alpha = 1.5 with a
+    motion segment of length ~ U[6, 14]) or "moffat" (the large workload's
+    Moffat + motion mix); support 31 for n <= 256, else 63."""
+    key = {"gauss": 0, "defocus": 1, "motion": 2, "moffat": 3}[kind]
+    seed = seed0 + 1000 * key + 10 * index + (0 if noise_level < 0.05 else 5)
+    rng = np.random.default_rng(seed)
+    k = 31 if n <= 256 else 63
+    if kind == "gauss":
+        sx, sy = rng.uniform(1.5, 4.0, size=2)
+        psf = psf_gaussian(k, sx, sy, rng.uniform(0.0, math.pi))
+    elif kind == "defocus":
+        psf = psf_defocus(k, rng.uniform(3.0, 6.0))
+    elif kind == "motion":
+        psf = psf_moffat_motion(k, 1.5, 2.5, rng.uniform(6.0, 14.0), rng.uniform(0.0, math.pi))
+    else:
+        psf = psf_moffat_motion(k, rng.uniform(3.0, 8.0), 2.5, rng.uniform(3.0, 9.0),
+                                rng.uniform(0.0, math.pi))
+    return make_problem(n, psf, rng, noise_level, None, seed, f"{kind}{k}")
 
 
 def lambda_grid(count: int = 32, lo: float = 1e-4, hi: float = 1.0) -> np.ndarray:

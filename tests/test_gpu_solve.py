@@ -224,6 +224,55 @@ def test_gcv_and_discrepancy_match_oracle():
     assert lam_d == grid[L.grid_discrepancy(d_ref)]
 
 
+@pytest.mark.parametrize("kind", ["defocus", "motion"])
+def test_weighted_gcv_and_modified_discrepancy_match_oracle(kind):
+    """wGCV at omega = 2, 5, 8 (eq. (wGCVTikSVD)) and the discrepancy
+    principle with epsilon = eta ||eps||, eta = 2, 5, 15 (Section 5.1) on
+    non-separable blurs: the GPU's grid choice equals the oracle's, and the
+    discrepancy choice never decreases with eta."""
+    require_gpu()
+    from paper_2311_15393_amd import Plan
+    prob = S.study_problem(kind, 128, 0.01, 0)
+    grid = S.lambda_grid(48)
+    kp = KP.kp_svd(prob.psf, prob.n)
+    s2, bh2 = L.spectrum(kp, prob.b.astype(np.float64))
+    say(f"wgcv / modified dp on {prob.kind}")
+    with Plan(prob.psf, prob.n) as plan:
+        b = to_dev(prob.b)
+        for omega in (2.0, 5.0, 8.0):
+            lam, sc = plan.gcv(b, grid, omega=omega)
+            ref = L.gcv(s2, bh2, grid, omega)
+            assert np.allclose(sc, ref, rtol=1e-5)
+            assert lam == grid[L.grid_argmin(ref)]
+        prev = 0.0
+        for eta in (2.0, 5.0, 15.0):
+            lam, d = plan.discrepancy(b, grid, prob.noise_norm, eta=eta)
+            ref = L.discrepancy(s2, bh2, grid, eta * prob.noise_norm)
+            assert np.allclose(d, ref, rtol=1e-5, atol=1e-6 * (eta * prob.noise_norm) ** 2)
+            assert lam == grid[L.grid_discrepancy(ref)]
+            assert lam >= prev
+            prev = lam
+
+
+def test_lambda_study_runs():
+    """The parameter study end to end on four small problems: every rule has
+    a lambda on the grid and a finite error no smaller than the grid's best,
+    and the optimal-error choice in the KP basis stays within 1.5x of it."""
+    require_gpu()
+    from paper_2311_15393_amd import lambda_study as LS
+    probs = [S.study_problem(kind, 64, 0.01, 0) for kind in LS.KINDS]
+    grid = S.lambda_grid(32)
+    rows = LS.study(probs, grid, tol=1e-6)
+    summary = LS.summarize(rows)
+    say(LS.table(summary))
+    for r in rows:
+        assert set(r["lam"]) == set(LS.rule_names())
+        assert all(lam in grid for lam in r["lam"].values())
+        assert all(0.0 < e < 1.0 for e in r["err"].values())
+        assert min(r["err"].values()) == r["err"]["best"]
+        assert r["err"]["opt"] <= 1.5 * r["err"]["best"]
+
+
 @pytest.mark.parametrize("mode", ["fpcg16", "fpcg8", "pcg32"])
 def test_large_moffat_full_size(mode):
     """1024 x 1024, Moffat + motion PSF (K = 63), lambda from the GPU's KP-GCV
