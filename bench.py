@@ -92,12 +92,16 @@ def blur_traffic(kernel: str):
     return BLUR_TRAFFIC["bytes_per_launch"]
 
 
-def mfma_blur_flops(n: int, k: int) -> float:
-    """FP16 MFMA flops the MFMA blur issues per launch: per 64 x 64 tile, 4
-    waves x K tap rows x NCH chunks x 4 blocks x 3 split products of
-    16x16x32 (16384 flop)."""
-    nch = (k + 15 + 31) // 32
+def mfma_blur_flops(n: int, k: int, cfg: int = 6) -> float:
+    """FP16 MFMA flops the MFMA blur issues per launch.  16x16x32 kernel
+    (cfg 6): per 64 x 64 tile, 4 row strips x K tap rows x NCH chunks x 4
+    blocks x 3 split products of 16384 flop.  32x32x16 kernel (cfg 7): 2 row
+    halves x K tap rows x NC chunks x 2 blocks x 3 products of 32768 flop."""
     tiles = ((n + 63) // 64) ** 2
+    if cfg == 7:
+        nc = (k + 31 + 15) // 16
+        return tiles * 2.0 * k * nc * 2 * 3 * 32768
+    nch = (k + 15 + 31) // 32
     return tiles * 4.0 * k * nch * 4 * 3 * 16384
 
 
@@ -269,9 +273,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    if pinfo["blur_config"] == 6:
-        kname = f"blur_mfma_kernel<{(k + 46) // 32}, EpiStoreF32>"
-        issued = mfma_blur_flops(n, k) / (blur_ms * 1e-3)
+    if pinfo["blur_config"] in (6, 7):
+        if pinfo["blur_config"] == 6:
+            kname = f"blur_mfma_kernel<{(k + 46) // 32}, EpiStoreF32>"
+        else:
+            kname = f"blur_mfma32_kernel<{(k + 46) // 16}, EpiStoreF32>"
+        issued = mfma_blur_flops(n, k, pinfo["blur_config"]) / (blur_ms * 1e-3)
         roofline = {
             "bound": "mfma", "achieved": achieved / 1e12, "peak": FP16_MFMA_PEAK / 1e12,
             "unit": "TFLOP/s", "frac": achieved / FP16_MFMA_PEAK,

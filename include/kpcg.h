@@ -393,10 +393,12 @@ int kp_time_precond(kp_plan_t plan, const float *r, double lambda, int mode,
                     float *z, int reps, float *avg_ms, void *stream);
 
 /* Blur kernel used by pcg_solve and kp_blur: 0..5 are FP32-VALU tile shapes,
-   6 the FP16-split MFMA kernel; kp_setup's autotuner picks the fastest.
-   kp_set_blur_config overrides the choice (cfg in 0..6; *prev, if not NULL,
+   6 the FP16-split MFMA kernel on 16x16x32 instructions, 7 the same on
+   32x32x16 instructions; kp_setup's autotuner picks the fastest.
+   kp_set_blur_config overrides the choice (cfg in 0..7; *prev, if not NULL,
    receives the previous one). */
 #define KP_BLUR_MFMA 6
+#define KP_BLUR_MFMA32 7
 int kp_set_blur_config(kp_plan_t plan, int cfg, int *prev);
 
 /* Copy the exact KP-basis diagonal D0[i][j] = ||A (v_c,i v_r,j^T)||_F^2

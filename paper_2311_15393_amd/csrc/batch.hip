@@ -709,7 +709,7 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
     d.nb_blur = d.ntx_blur * ((n + th - 1) / th);
     for (int t = 0; t < d.nb_blur; ++t) grp_tiles[cfg].push_back(TileRef{i, t});
     grp_lds[cfg] = grp_lds[cfg] > lds ? grp_lds[cfg] : lds;
-    d.use_mfma = P.blur_cfg == BLUR_CFG_MFMA ? 1 : 0;
+    d.use_mfma = blur_cfg_is_mfma(P.blur_cfg) ? 1 : 0;     // (16 x 16 x 32 form)
     d.nch = mfma_nch(P.k);
     d.exq = P.mfma_exq;
     d.mfma_taps = P.mfma_taps;

@@ -71,6 +71,8 @@ static hipError_t blur_dispatch(int cfg, const Plan& P, const float* src, const 
   switch (cfg) {
     case BLUR_CFG_MFMA: *nb = mfma_blocks(n);
       return launch_blur_mfma(P, src, taps == P.taps32, epi, ctrl, skip, s);
+    case BLUR_CFG_MFMA32: *nb = mfma_blocks(n);
+      return launch_blur_mfma32(P, src, taps == P.taps32, epi, ctrl, skip, s);
     case 1: *nb = blur_blocks<KP_CFG1>(n);
       return run_blur<KP_CFG1, float, float, float>(P, src, taps, epi, ctrl, skip, s);
     case 2: *nb = blur_blocks<KP_CFG2>(n);
@@ -115,7 +117,7 @@ hipError_t autotune_blur(Plan& P, hipStream_t s, float* times_ms) {
   err = hipMemsetAsync(P.p, 0, sizeof(float) * (size_t)P.n * P.n, s);
   int best = 0, best_valu = 0;
   float best_ms = 1e30f, best_valu_ms = 1e30f;
-  for (int c = 0; c <= BLUR_CFG_MFMA && err == hipSuccess; ++c) {
+  for (int c = 0; c <= BLUR_CFG_MFMA32 && err == hipSuccess; ++c) {
     EpiStoreF32 e{P.q, P.n};
     int nb;
     err = blur_dispatch(c, P, P.p, P.taps32_flip, e, nullptr, 0, s, &nb);

@@ -249,7 +249,9 @@ __device__ inline void blur_tile(const In* __restrict__ src, const Tap* __restri
 #define KP_CFG4 8, 64, 8, 1     // 64 x 64 tile, 512 threads
 #define KP_CFG5 16, 16, 4, 2    // 64 x 32 tile, 256 threads, 4 x 2 per thread
 constexpr int NUM_BLUR_CFG = 6;        // FP32-VALU tile shapes
-constexpr int BLUR_CFG_MFMA = 6;       // the MFMA kernel (blur_mfma.hip)
+constexpr int BLUR_CFG_MFMA = 6;       // the MFMA kernel (blur_mfma.hip), 16 x 16 x 32
+constexpr int BLUR_CFG_MFMA32 = 7;     // the MFMA kernel on 32 x 32 x 16
+__host__ __device__ constexpr bool blur_cfg_is_mfma(int cfg) { return cfg >= BLUR_CFG_MFMA; }
 constexpr int BC = 16;
 // FP32 input, FP64 accumulation (right-hand side)
 #define KP_F32_CFG KP_CFG0
@@ -270,5 +272,8 @@ __host__ __device__ inline int lds_width(int kq) {
 template <class Epi>
 hipError_t launch_blur_mfma(const Plan& P, const float* src, bool transpose, Epi epi,
                             Ctrl* ctrl, int skip, hipStream_t s);
+template <class Epi>
+hipError_t launch_blur_mfma32(const Plan& P, const float* src, bool transpose, Epi epi,
+                              Ctrl* ctrl, int skip, hipStream_t s);
 
 }  // namespace kpcg

@@ -171,4 +171,175 @@ __device__ inline void blur_mfma_tile(const float* __restrict__ src,
 }
 
 
+// ---------------------------------------------------------------------------
+// The same blur on v_mfma_f32_32x32x16_f16: one A fragment covers 32 output
+// rows, so a wave reads half the LDS bytes per flop of the 16 x 16 x 32 form.
+// For a 32-column output block and tap row a, the Toeplitz chunks are
+// T32_{a,t}[k][c] = Q[a][16 t + k - c] (k < 16, c < 32), t < NC = ceil((K +
+// 31) / 16); lane l of a fragment holds rows 8 (l / 32) .. + 7 of column
+// l % 32 (B), or row l % 32, entries 8 (l / 32) .. + 7 (A); the accumulator
+// holds C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32] in register r.
+// Workgroup: 64 x 64 outputs, 8 waves = 2 row halves (32 rows, both 32-column
+// blocks) x 4 groups that split the tap rows; the input tile, 64 + K - 1 rows
+// of 16 (NC + 2) columns, is staged once as hi / lo FP16 planes (pitch
+// 16 (NC + 2) + 8 halves: conflict-free 16-byte reads of 32 rows), and the
+// four groups' partial tiles are added in group order over the freed planes.
+// Measured at 1024^2, K = 63 it is slower than blur_mfma_tile (about 41 against
+// 34 us); the autotuner keeps whichever is faster for the plan.
+// ---------------------------------------------------------------------------
+typedef float mf16_t __attribute__((ext_vector_type(16)));
+
+__host__ __device__ constexpr int m32_nch(int K) { return (K + 31 + 15) / 16; }
+__host__ __device__ constexpr int m32_width(int nc) { return 16 * (nc + 2); }
+__host__ __device__ constexpr int m32_pitch(int nc) { return m32_width(nc) + 8; }
+inline size_t m32_lds_bytes(int nc, int K) {
+  const size_t planes = (size_t)2 * (MB_TM + K - 1) * m32_pitch(nc) * sizeof(_Float16);
+  const size_t partials = (size_t)4 * MB_TM * (MB_TN + 1) * sizeof(float);
+  return planes > partials ? planes : partials;
+}
+
+template <int NC, class Epi>
+__device__ inline void blur_mfma32_tile(const float* __restrict__ src,
+                                        const mh8_t* __restrict__ bfrag, int n, int K, int exq,
+                                        int i0, int j0, Epi epi, double* partial_out,
+                                        unsigned char* mb_lds) {
+  constexpr int W = m32_width(NC), PITCH = m32_pitch(NC), W2 = W / 2;
+  constexpr int NU = NC + 2;                  // A fragments: 16-column windows
+  constexpr int NVP = ((MB_TM + 62) * W2 + MB_NT - 1) / MB_NT;   // K <= 63
+  const int h = (K - 1) >> 1;
+  const int rows = MB_TM + K - 1;
+  const int cvalid = MB_TN + K - 1;
+  _Float16* shi = reinterpret_cast<_Float16*>(mb_lds);
+  _Float16* slo = shi + rows * PITCH;
+  __shared__ float red[MB_NT / 64];
+
+  // stage: as blur_mfma_tile (two columns per slot, tile max, 2^ex scale)
+  float v0[NVP], v1[NVP];
+  float mx = 0.0f;
+#pragma unroll
+  for (int q = 0; q < NVP; ++q) {
+    const int idx = threadIdx.x + q * MB_NT;
+    float a0 = 0.0f, a1 = 0.0f;
+    if (idx < rows * W2) {
+      const int r = idx / W2, c = 2 * (idx - r * W2);
+      const int gi = i0 - h + r, gj = j0 - h + c;
+      if ((unsigned)gi < (unsigned)n) {
+        if (c < cvalid && (unsigned)gj < (unsigned)n) a0 = src[(size_t)gi * n + gj];
+        if (c + 1 < cvalid && (unsigned)(gj + 1) < (unsigned)n) a1 = src[(size_t)gi * n + gj + 1];
+      }
+    }
+    v0[q] = a0;
+    v1[q] = a1;
+    mx = fmaxf(mx, fmaxf(fabsf(a0), fabsf(a1)));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  mx = red[0];
+#pragma unroll
+  for (int i = 1; i < MB_NT / 64; ++i) mx = fmaxf(mx, red[i]);
+  const int ex = (mx > 0.0f && mx <= 3.0e38f) ? 13 - ilogbf(mx) : 0;
+#pragma unroll
+  for (int q = 0; q < NVP; ++q) {
+    const int idx = threadIdx.x + q * MB_NT;
+    if (idx < rows * W2) {
+      const int r = idx / W2, c = 2 * (idx - r * W2);
+      const float a0 = ldexpf(v0[q], ex), a1 = ldexpf(v1[q], ex);
+      const _Float16 h0 = (_Float16)a0, h1 = (_Float16)a1;
+      const mh2_t hh = {h0, h1};
+      const mh2_t ll = {(_Float16)(a0 - (float)h0), (_Float16)(a1 - (float)h1)};
+      *reinterpret_cast<mh2_t*>(shi + r * PITCH + c) = hh;
+      *reinterpret_cast<mh2_t*>(slo + r * PITCH + c) = ll;
+    }
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int rw = wv & 1, grp = wv >> 1;       // row half, tap-row group
+  const int lr = lane & 31, lg = lane >> 5;
+  const int quarter = (K + 3) >> 2;
+  const int abeg = grp * quarter;
+  const int aend = abeg + quarter < K ? abeg + quarter : K;
+  mf16_t acc[2];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[cb][r] = 0.0f;
+
+  // tap fragments of the next row in flight while the current one is used
+  mh8_t bq[2][2 * NC];
+  if (abeg < aend) {
+#pragma unroll
+    for (int t = 0; t < 2 * NC; ++t) bq[0][t] = bfrag[(abeg * NC * 2 + t) * 64 + lane];
+  }
+  for (int a0 = abeg; a0 < aend; a0 += 2) {
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int a = a0 + sl;
+      if (a < aend) {
+        const int an = a + 1 < aend ? a + 1 : a;
+#pragma unroll
+        for (int t = 0; t < 2 * NC; ++t) bq[sl ^ 1][t] = bfrag[(an * NC * 2 + t) * 64 + lane];
+        const int off = (rw * 32 + a + lr) * PITCH + 8 * lg;
+        mh8_t ah[NU], al[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          ah[u] = *reinterpret_cast<const mh8_t*>(shi + off + 16 * u);
+          al[u] = *reinterpret_cast<const mh8_t*>(slo + off + 16 * u);
+        }
+#pragma unroll
+        for (int t = 0; t < NC; ++t) {
+          const mh8_t bh = bq[sl][2 * t], bl = bq[sl][2 * t + 1];
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb)
+            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[2 * cb + t], bh, acc[cb], 0, 0, 0);
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb)
+            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[2 * cb + t], bl, acc[cb], 0, 0, 0);
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb)
+            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[2 * cb + t], bh, acc[cb], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  // the four groups' partial tiles over the freed planes, then every thread
+  // adds them in group order for its outputs (consecutive threads on
+  // consecutive columns) and runs the epilogue
+  __syncthreads();
+  float* part = reinterpret_cast<float*>(mb_lds);       // [4][64][65]
+  constexpr int LD = MB_TN + 1;
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int il = rw * 32 + 8 * (r >> 2) + 4 * lg + (r & 3);
+      const int jl = 32 * cb + lr;
+      part[((size_t)grp * MB_TM + il) * LD + jl] = acc[cb][r];
+    }
+  __syncthreads();
+  const float oscale = ldexpf(1.0f, -(ex + exq));
+  double d = 0.0;
+#pragma unroll
+  for (int q = 0; q < MB_TM * MB_TN / MB_NT; ++q) {
+    const int idx = threadIdx.x + q * MB_NT;
+    const int il = idx / MB_TN, jl = idx % MB_TN;
+    float tot = part[(size_t)il * LD + jl];
+#pragma unroll
+    for (int g2 = 1; g2 < 4; ++g2) tot += part[((size_t)g2 * MB_TM + il) * LD + jl];
+    const int i = i0 + il, j = j0 + jl;
+    if (i < n && j < n) {
+      const float val = tot * oscale;
+      epi.row(i, j, 1, &val, d);
+    }
+  }
+  if constexpr (Epi::kReduce) {
+    __shared__ double sh[MB_NT / 64];
+    const double s = block_sum<MB_NT>(d, sh);
+    if (threadIdx.x == 0) *partial_out = s;
+  }
+}
+
 }  // namespace kpcg

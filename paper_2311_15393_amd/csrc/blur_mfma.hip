@@ -52,6 +52,48 @@ __global__ __launch_bounds__(256) void mfma_taps_kernel(const float* __restrict_
   out[idx] = v;
 }
 
+// 32 x 32 x 16 tap fragments: entry ((a * nc + t) * 2 + part) * 64 + lane
+// holds T32_{a,t}[8 g + e][c] = Q[a][16 t + 8 g + e - c] (c = lane mod 32,
+// g = lane div 32), part 0 = hi, 1 = lo of Q * 2^exq
+__global__ __launch_bounds__(256) void mfma32_taps_kernel(const float* __restrict__ taps, int K,
+                                                          int KQ, int nc, int exq,
+                                                          mh8_t* __restrict__ out) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= K * nc * 2 * 64) return;
+  const int lane = idx & 63;
+  int rest = idx >> 6;
+  const int part = rest & 1;
+  rest >>= 1;
+  const int t = rest % nc, a = rest / nc;
+  const int c = lane & 31, g = lane >> 5;
+  mh8_t v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int b = 16 * t + 8 * g + e - c;
+    const float q = (b >= 0 && b < K) ? taps[a * KQ + b] : 0.0f;
+    const float sc = ldexpf(q, exq);
+    const _Float16 hi = (_Float16)sc;
+    v[e] = part == 0 ? hi : (_Float16)(sc - (float)hi);
+  }
+  out[idx] = v;
+}
+
+template <int NC, class Epi>
+__global__ __launch_bounds__(MB_NT) void blur_mfma32_kernel(const float* __restrict__ src,
+                                                            const mh8_t* __restrict__ bfrag,
+                                                            int n, int K, int exq, Epi epi,
+                                                            Ctrl* ctrl, int skip_if_done,
+                                                            double* partials) {
+  extern __shared__ __align__(16) unsigned char mb_lds[];
+  if (skip_if_done && ctrl->done != RUNNING) return;
+  blur_mfma32_tile<NC, Epi>(src, bfrag, n, K, exq, blockIdx.y * MB_TM, blockIdx.x * MB_TN, epi,
+                            partials + Epi::kSlot * MAX_PARTIALS + blockIdx.y * gridDim.x +
+                                blockIdx.x,
+                            mb_lds);
+}
+
+size_t mfma32_taps_count(int K) { return (size_t)K * m32_nch(K) * 2 * 64; }
+
 template <int NCH, class Epi>
 __global__ __launch_bounds__(MB_NT) void blur_mfma_kernel(const float* __restrict__ src,
                                                           const mh8_t* __restrict__ bfrag,
@@ -81,8 +123,21 @@ hipError_t build_mfma_taps(const Plan& P, hipStream_t s) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(mfma_taps_kernel, dim3(blocks), dim3(256), 0, s, P.taps32_flip, K, P.kq,
                      nch, P.mfma_exq, tab + cnt);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nc = m32_nch(K);
+  const size_t cnt32 = mfma32_taps_count(K);
+  const unsigned blocks32 = (unsigned)((cnt32 + 255) / 256);
+  mh8_t* tab32 = reinterpret_cast<mh8_t*>(P.mfma32_taps);
+  hipLaunchKernelGGL(mfma32_taps_kernel, dim3(blocks32), dim3(256), 0, s, P.taps32, K, P.kq, nc,
+                     P.mfma_exq, tab32);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mfma32_taps_kernel, dim3(blocks32), dim3(256), 0, s, P.taps32_flip, K,
+                     P.kq, nc, P.mfma_exq, tab32 + cnt32);
   return hipGetLastError();
 }
+
 
 template <int NCH, class Epi>
 static hipError_t run_mfma(const Plan& P, const float* src, const mh8_t* tab, Epi epi,
@@ -121,6 +176,43 @@ hipError_t launch_blur_mfma(const Plan& P, const float* src, bool transpose, Epi
   }
 }
 
+template <int NC, class Epi>
+static hipError_t run_mfma32(const Plan& P, const float* src, const mh8_t* tab, Epi epi,
+                             Ctrl* ctrl, int skip, hipStream_t s) {
+  const int n = P.n;
+  dim3 grid((n + MB_TN - 1) / MB_TN, (n + MB_TM - 1) / MB_TM);
+  if ((long)grid.x * grid.y > MAX_PARTIALS) return hipErrorInvalidValue;
+  const size_t lds = m32_lds_bytes(NC, P.k);
+  auto kern = blur_mfma32_kernel<NC, Epi>;
+  if (lds > 65536) {
+    static size_t granted = 65536;      // once per instantiation, the largest K seen
+    if (lds > granted) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      granted = lds;
+    }
+  }
+  hipLaunchKernelGGL(kern, grid, dim3(MB_NT), lds, s, src, tab, n, P.k, P.mfma_exq, epi, ctrl,
+                     skip, P.partials);
+  return hipGetLastError();
+}
+
+// transpose: A^T (taps32, table 0), else A (taps32_flip, table 1)
+template <class Epi>
+hipError_t launch_blur_mfma32(const Plan& P, const float* src, bool transpose, Epi epi,
+                              Ctrl* ctrl, int skip, hipStream_t s) {
+  const mh8_t* tab = reinterpret_cast<const mh8_t*>(P.mfma32_taps) +
+                     (transpose ? 0 : mfma32_taps_count(P.k));
+  switch (m32_nch(P.k)) {
+    case 2: return run_mfma32<2>(P, src, tab, epi, ctrl, skip, s);
+    case 3: return run_mfma32<3>(P, src, tab, epi, ctrl, skip, s);
+    case 4: return run_mfma32<4>(P, src, tab, epi, ctrl, skip, s);
+    case 5: return run_mfma32<5>(P, src, tab, epi, ctrl, skip, s);
+    default: return run_mfma32<6>(P, src, tab, epi, ctrl, skip, s);
+  }
+}
+
 template hipError_t launch_blur_mfma<EpiStoreF32>(const Plan&, const float*, bool, EpiStoreF32,
                                                   Ctrl*, int, hipStream_t);
 template hipError_t launch_blur_mfma<EpiNormalW>(const Plan&, const float*, bool, EpiNormalW,
@@ -133,5 +225,18 @@ template hipError_t launch_blur_mfma<EpiTrueRes>(const Plan&, const float*, bool
                                                  Ctrl*, int, hipStream_t);
 template hipError_t launch_blur_mfma<EpiResid>(const Plan&, const float*, bool, EpiResid, Ctrl*,
                                                int, hipStream_t);
+
+template hipError_t launch_blur_mfma32<EpiStoreF32>(const Plan&, const float*, bool, EpiStoreF32,
+                                                    Ctrl*, int, hipStream_t);
+template hipError_t launch_blur_mfma32<EpiNormalW>(const Plan&, const float*, bool, EpiNormalW,
+                                                   Ctrl*, int, hipStream_t);
+template hipError_t launch_blur_mfma32<EpiAnchorRes>(const Plan&, const float*, bool,
+                                                     EpiAnchorRes, Ctrl*, int, hipStream_t);
+template hipError_t launch_blur_mfma32<EpiRhs>(const Plan&, const float*, bool, EpiRhs, Ctrl*,
+                                               int, hipStream_t);
+template hipError_t launch_blur_mfma32<EpiTrueRes>(const Plan&, const float*, bool, EpiTrueRes,
+                                                   Ctrl*, int, hipStream_t);
+template hipError_t launch_blur_mfma32<EpiResid>(const Plan&, const float*, bool, EpiResid,
+                                                 Ctrl*, int, hipStream_t);
 
 }  // namespace kpcg

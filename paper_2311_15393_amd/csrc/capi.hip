@@ -48,6 +48,7 @@ size_t layout(int n, int k, char* base, Plan* P) {
   Q.taps64 = b.take<double>((size_t)k * kq);
   Q.taps64_flip = b.take<double>((size_t)k * kq);
   Q.mfma_taps = b.take<uint8_t>(2 * mfma_taps_count(k) * 16);
+  Q.mfma32_taps = b.take<uint8_t>(2 * mfma32_taps_count(k) * 16);
   Q.sc = b.take<double>(n);
   Q.sr = b.take<double>(n);
   Q.sc2 = b.take<float>(n);
@@ -353,7 +354,7 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   // exact arithmetic, with an error of ~1e-6 ||r_a||.  Used once
   // ||r_a|| <= ANCHOR_REL ||A^T b||, so the error stays ~1e-9 ||A^T b||.
   const int trmode =
-      tol >= (P.blur_cfg == BLUR_CFG_MFMA ? TR_FASTU_TOL_MFMA : TR_FASTU_TOL_VALU) ? TR_FAST_ALL
+      tol >= (blur_cfg_is_mfma(P.blur_cfg) ? TR_FASTU_TOL_MFMA : TR_FASTU_TOL_VALU) ? TR_FAST_ALL
       : tol >= TR_FAST_TOL                                                        ? TR_FAST_AT
                                                                                   : TR_FP64;
   bool anchor_ok = false;        // the last true residual may anchor the next
@@ -725,7 +726,7 @@ int kp_time_precond(kp_plan_t plan, const float* r, double lambda, int mode, flo
 }
 
 int kp_set_blur_config(kp_plan_t plan, int cfg, int* prev) {
-  if (!plan || cfg < 0 || cfg > BLUR_CFG_MFMA) return KP_ERR_ARG;
+  if (!plan || cfg < 0 || cfg > BLUR_CFG_MFMA32) return KP_ERR_ARG;
   if (prev) *prev = plan->P.blur_cfg;
   plan->P.blur_cfg = cfg;
   return KP_OK;

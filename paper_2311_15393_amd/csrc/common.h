@@ -187,6 +187,7 @@ struct Plan {
   // MFMA fragments of the banded Toeplitz tap blocks (blur_mfma.hip): the
   // table for taps32, then the one for taps32_flip; taps scaled by 2^mfma_exq
   void* mfma_taps = nullptr;
+  void* mfma32_taps = nullptr;   // tap fragments of the 32 x 32 x 16 MFMA blur
   int mfma_exq = 0;
 
   // KP-SVD factors
@@ -303,6 +304,7 @@ hipError_t launch_spectral_gemms(const Plan& P, const float* b, float* out, hipS
 // orientation (16 bytes each), workgroups per launch, table construction
 int mfma_nch(int K);
 size_t mfma_taps_count(int K);
+size_t mfma32_taps_count(int K);      // the same for the 32 x 32 x 16 kernel
 int mfma_blocks(int n);
 hipError_t build_mfma_taps(const Plan& P, hipStream_t s);
 

@@ -27,6 +27,7 @@ KP_NO_FALLBACK = 0x400
 KP_EXACT_DIAG = 0x800
 KP_MAX_PSF = 63
 KP_BLUR_MFMA = 6
+KP_BLUR_MFMA32 = 7
 KP_MLP_NFEAT, KP_MLP_HIDDEN, KP_MLP_NPARAM = 128, 256, 164865
 
 

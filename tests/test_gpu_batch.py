@@ -159,8 +159,9 @@ def test_batch_mixes_valu_and_mfma_items():
     probs, _ = _small_batch()
     plans = [Plan(p.psf, p.n) for p in probs]
     # K = 15, 9, 31, 21, 31: chunk counts 1, 1, 2, 2, 2; alternate the kernels
+    # (a plan on the 32x32x16 blur runs the 16x16x32 one in batched solves)
     for i, pl in enumerate(plans):
-        pl.set_blur_config(KP_BLUR_MFMA if i % 2 == 0 else 0)
+        pl.set_blur_config((KP_BLUR_MFMA if i % 4 == 0 else 7) if i % 2 == 0 else 0)
     big = S.batch_problem(7)                       # n = 128, K = 55: three chunks
     extra = Plan(big.psf, big.n)
     extra.set_blur_config(KP_BLUR_MFMA)

@@ -31,12 +31,13 @@ BLUR_CASES = [(64, 15, "gauss"), (100, 15, "rand"), (256, 31, "gauss"), (131, 63
 
 
 @pytest.mark.parametrize("n,k,kind", BLUR_CASES)
-@pytest.mark.parametrize("cfg", [0, 6])
+@pytest.mark.parametrize("cfg", [0, 6, 7])
 def test_blur_matches_oracle(n, k, kind, cfg):
     """Blur vs FP64, elementwise.
     VALU shapes (cfg 0..5), FP32 products and sums in any order:
         |y - y64| <= gamma_{K^2+1} (|P| * |x|) + u |y|.
-    MFMA kernel (cfg 6): x and P are split into FP16 hi + lo (scaled by
+    MFMA kernels (cfg 6: 16x16x32, cfg 7: 32x32x16 instructions): x and P
+    are split into FP16 hi + lo (scaled by
     powers of two), the hi*hi, hi*lo, lo*hi products are exact in FP32 and
     summed in FP32 (3 K^2 terms); the representation error and the dropped
     lo*lo term are each at most 2^-22 relative per product, and FP16
@@ -49,8 +50,8 @@ def test_blur_matches_oracle(n, k, kind, cfg):
     psf = _psf(kind, k, n)
     x = S.random_image(np.random.default_rng(n + k), n)
     xd = to_dev(x)
-    if cfg == 6:
-        t = 3 * k * k + 1
+    if cfg in (6, 7):
+        t = 3 * k * k + 4
         g = t * U32 / (1 - t * U32) + 2.0 ** -20
     else:
         g = (k * k + 1) * U32 / (1 - (k * k + 1) * U32)
@@ -64,25 +65,26 @@ def test_blur_matches_oracle(n, k, kind, cfg):
             ref = O.blur_t(psf, x64) if tr else O.blur(psf, x64)
             absref = O.blur_t(np.abs(psf), np.abs(x64)) if tr else O.blur(np.abs(psf), np.abs(x64))
             bound = g * absref + U32 * np.abs(ref)
-            if cfg == 6:
+            if cfg in (6, 7):
                 bound = bound + 2.0 ** -30 * np.abs(x64).max() * np.abs(psf).sum()
             assert np.all(np.abs(got - ref) <= bound), (tr, np.max(np.abs(got - ref) / bound))
 
 
-def test_blur_mfma_high_dynamic_range():
-    """MFMA blur on an image whose tiles mix values of 1 and 1e-6 (worst case
+@pytest.mark.parametrize("cfg", [6, 7])
+def test_blur_mfma_high_dynamic_range(cfg):
+    """MFMA blurs on an image whose tiles mix values of 1 and 1e-6 (worst case
     for a per-tile scale): the error stays within the MFMA bound above."""
     torch = require_gpu()
-    from paper_2311_15393_amd import KP_BLUR_MFMA, Plan
+    from paper_2311_15393_amd import Plan
     n, k = 200, 31
     psf = _psf("moffat", k, 4)
     rng = np.random.default_rng(3)
     x = (rng.uniform(0, 1, (n, n)) * np.where(rng.uniform(size=(n, n)) < 0.5, 1.0, 1e-6))
     x = x.astype(np.float32)
-    t = 3 * k * k + 1
+    t = 3 * k * k + 4
     g = t * U32 / (1 - t * U32) + 2.0 ** -20
     with Plan(psf, n) as plan:
-        plan.set_blur_config(KP_BLUR_MFMA)
+        plan.set_blur_config(cfg)
         y = torch.empty_like(to_dev(x))
         plan.blur(to_dev(x), y)
         x64 = x.astype(np.float64)
@@ -94,7 +96,7 @@ def test_blur_mfma_high_dynamic_range():
         assert np.all(err <= bound)
 
 
-@pytest.mark.parametrize("cfg", [0, 6])
+@pytest.mark.parametrize("cfg", [0, 6, 7])
 def test_solve_with_each_blur_kernel(cfg):
     """The FP16-KP FPCG solve at 256^2 reaches the same x_lambda with the VALU
     and the MFMA blur."""

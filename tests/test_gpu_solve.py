@@ -130,7 +130,7 @@ def test_edge_cases():
         assert ei.value.status == KP_BREAKDOWN
 
 
-@pytest.mark.parametrize("tol,cfg", [(1e-6, 6), (1e-6, 0), (5e-8, 6)])
+@pytest.mark.parametrize("tol,cfg", [(1e-6, 6), (1e-6, 7), (1e-6, 0), (5e-8, 6)])
 def test_reported_true_residual_matches_oracle(tol, cfg):
     """The certificate: relres_true, formed on the device as
     A^T (b - A x) - lambda^2 x with b - A x in FP64 and A^T on the MFMA blur
