@@ -95,6 +95,49 @@ def test_ragged_sizes(n, k):
             assert info.status == KP_OK and err <= bar
 
 
+@pytest.mark.parametrize("n,k", [(1, 1), (2, 3), (3, 5), (5, 9), (16, 31)])
+def test_smallest_sizes(n, k):
+    """Degenerate sizes: one pixel (A = P[0,0] I, so x = P b / (P^2 + lambda^2)
+    in closed form), and PSF supports larger than the image (K up to 2n - 1),
+    against the oracle's dense Cholesky solve; FP32 PCG and FP16 FPCG."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, KP_P32, KP_PCG, Plan
+    rng = np.random.default_rng(70 + n)
+    psf = rng.uniform(0.2, 1.0, (k, k))
+    psf = (psf / psf.sum()).astype(np.float32).astype(np.float64)
+    b = rng.uniform(0.0, 1.0, (n, n)).astype(np.float32)
+    lam = 0.05
+    ref = SV.x_lambda_dense(psf, b.astype(np.float64), lam)
+    if n == 1:
+        p0 = psf[0, 0]
+        assert abs(ref[0, 0] - p0 * b[0, 0] / (p0 * p0 + lam * lam)) <= 1e-12
+    say(f"smallest n={n} k={k}")
+    with Plan(psf, n) as plan:
+        for mode, bar in ((KP_PCG | KP_P32, 1e-5), (KP_FPCG | KP_P16, 1e-4)):
+            x, info = plan.solve(to_dev(b), lam, tol=1e-9, maxit=100, mode=mode)
+            err = rel(to_host(x), ref)
+            say(f"  mode={mode:#x} iters={info.iters} err={err:.2e}")
+            assert info.status == KP_OK and err <= bar
+
+
+def test_maximum_size():
+    """The largest image the library accepts (2048 x 2048) with the largest
+    PSF support (K = 63): the FP16-KP FPCG solve reaches the oracle's
+    x_lambda."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, Plan
+    prob = S.large_moffat(3, n=2048, k=63)
+    lam = 0.03
+    say("maximum size 2048^2, K = 63")
+    ref = SV.x_lambda(prob.psf, prob.b.astype(np.float64), lam)
+    with Plan(prob.psf, prob.n) as plan:
+        x, info = plan.solve(to_dev(prob.b), lam, tol=1e-6, maxit=100, mode=KP_FPCG | KP_P16)
+        got = to_host(x)
+    err = rel(got, ref)
+    say(f"  iters={info.iters} relres_true={info.relres_true:.2e} err={err:.2e}")
+    assert info.status == KP_OK and err <= 1e-4
+
+
 def test_edge_cases():
     torch = require_gpu()
     from paper_2311_15393_amd import (KP_BREAKDOWN, KP_ERR_ARG, KP_FPCG, KP_MAXIT, KP_OK, KP_P16,
