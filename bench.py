@@ -408,7 +408,7 @@ def run_batch(nprob: int, dev):
     on the solves' actual misfits."""
     import torch
     import synthetic as S
-    from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, Plan, solve_batched
+    from paper_2311_15393_amd import KP_EXACT_DIAG, KP_FPCG, KP_OK, KP_P16, Plan, solve_batched
 
     t0 = time.time()
     probs = [S.batch_problem(i) for i in range(nprob)]
@@ -455,6 +455,18 @@ def run_batch(nprob: int, dev):
         for kk, store in ((k_gcv, errs_gcv), (k_dp, errs_dp)):
             x = xs[idx[kk]].cpu().numpy().astype(np.float64)
             store.append(float(np.linalg.norm(x - xt) / np.linalg.norm(xt)))
+    # the same batch with the exact KP-basis diagonal in the preconditioner
+    xs2 = [torch.empty_like(b) for b in bs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, infos2, _ = solve_batched(plans, bs, lams, poi, tol=1e-6, maxit=1000,
+                                 mode=KP_FPCG | KP_P16 | KP_EXACT_DIAG, xs=xs2)
+    torch.cuda.synchronize()
+    wall2 = time.perf_counter() - t0
+    iters2 = np.array([i.iters for i in infos2])
+    ok2 = sum(i.status == KP_OK for i in infos2)
+    log(f"[bench] batch, exact diagonal: {wall2:.3f}s ({len(items) / wall2:.1f}/s), converged "
+        f"{ok2}, iters mean {iters2.mean():.1f} max {iters2.max()}")
     out = {
         "problems": nprob, "solves": len(items), "wall_s": wall,
         "solves_per_s": len(items) / wall, "converged": ok,
@@ -462,6 +474,8 @@ def run_batch(nprob: int, dev):
         "setup_s_total": setup_s, "tol": 1e-6, "mode": "fp16_kp_fpcg",
         "err_vs_true_gcv_pick_mean": float(np.mean(errs_gcv)),
         "err_vs_true_dp_pick_mean": float(np.mean(errs_dp)),
+        "exact_diag": {"wall_s": wall2, "solves_per_s": len(items) / wall2, "converged": ok2,
+                       "iters_mean": float(iters2.mean()), "iters_max": int(iters2.max())},
     }
     log(f"[bench] batch: {wall:.3f}s for {len(items)} solves ({len(items) / wall:.1f}/s), "
         f"converged {ok}, iters mean {iters.mean():.1f} max {iters.max()}; "

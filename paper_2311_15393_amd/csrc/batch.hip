@@ -59,7 +59,8 @@ struct TileRef {
 };
 
 enum RunMode : int { RM_RUNNING = 0, RM_PENDING = 1, RM_ALL = 2, RM_RESUME = 3, RM_FINISHED = 4,
-                     RM_PEND_FULL = 5, RM_PEND_ANCH = 6 };
+                     RM_PEND_FULL = 5, RM_PEND_ANCH = 6, RM_PEND_FULL_FASTU = 7,
+                     RM_PEND_FULL_F64U = 8 };
 
 // batched scalar kind: a true residual whose last blur ran on the fast blur
 // (anchored, or A^T (b - A x) on it), partials per fast-blur tile
@@ -72,6 +73,8 @@ __device__ inline bool item_active(const Ctrl* c, int mode) {
     case RM_PENDING: return d == PENDING;
     case RM_PEND_FULL: return d == PENDING && !c->anchor;
     case RM_PEND_ANCH: return d == PENDING && c->anchor;
+    case RM_PEND_FULL_FASTU: return d == PENDING && !c->anchor && c->fastu;
+    case RM_PEND_FULL_F64U: return d == PENDING && !c->anchor && !c->fastu;
     case RM_RESUME: return d == RUNNING && c->resume;
     case RM_FINISHED: return d == MAXIT || d == BREAKDOWN;
     default: return true;
@@ -82,9 +85,10 @@ __device__ inline bool item_active(const Ctrl* c, int mode) {
 // batched blur
 // ---------------------------------------------------------------------------
 // BK_TRUE1: u = b - A x (FP64); BK_TRUE2: r = A^T u - lambda^2 x with A^T in
-// FP64, BK_TRUE2F: the same on the fast blur
+// FP64, BK_TRUE2F: the same on the fast blur; BK_TRUE1F: u = b - A z on the
+// fast blur, z = fp32(x)
 enum BlurKind : int { BK_A = 0, BK_AT_NORMAL = 1, BK_RHS = 2, BK_TRUE1 = 3, BK_TRUE2 = 4,
-                      BK_MISFIT = 5, BK_ANC1 = 6, BK_ANC2 = 7, BK_TRUE2F = 8 };
+                      BK_MISFIT = 5, BK_ANC1 = 6, BK_ANC2 = 7, BK_TRUE2F = 8, BK_TRUE1F = 9 };
 
 // ||A x - b||^2 for the data-misfit report
 struct EpiMisfit {
@@ -144,6 +148,10 @@ __global__ __launch_bounds__(TX* TY) void blur_batched_kernel(const ItemDesc* __
       blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiAnchorRes>(
           it.z, it.taps32, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
           it.partials + SLOT_TRUE * MAXP_ITEM + tr.t);
+    } else if constexpr (KIND == BK_TRUE1F) {
+      EpiResid e{it.b, it.q, nullptr, n};
+      blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiResid>(
+          it.z, it.taps32_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, nullptr);
     } else if constexpr (KIND == BK_TRUE2F) {
       EpiTrueRes e{it.x64, it.r, it.lam2, n, it.xa64, it.ra64};
       blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiTrueRes>(
@@ -186,6 +194,9 @@ __global__ __launch_bounds__(MB_NT) void blur_mfma_batched_kernel(
   } else if constexpr (KIND == BK_ANC1) {
     blur_mfma_tile<NCH>(it.q, tabA, n, it.k, it.exq, i0, j0, EpiStoreF32{it.z, n}, nullptr,
                         mb_lds);
+  } else if constexpr (KIND == BK_TRUE1F) {
+    blur_mfma_tile<NCH>(it.z, tabA, n, it.k, it.exq, i0, j0, EpiResid{it.b, it.q, nullptr, n},
+                        nullptr, mb_lds);
   } else if constexpr (KIND == BK_TRUE2F) {
     blur_mfma_tile<NCH>(it.q, tabT, n, it.k, it.exq, i0, j0,
                         EpiTrueRes{it.x64, it.r, it.lam2, n, it.xa64, it.ra64},
@@ -239,7 +250,7 @@ __global__ __launch_bounds__(GT) void gemm_batched_kernel(const ItemDesc* __rest
 // batched vector kernels (one block per VCH floats of an item)
 // ---------------------------------------------------------------------------
 enum VecKind : int { VK_UPDATE = 0, VK_PUPDATE_Z = 1, VK_PUPDATE_R = 2, VK_INIT = 3,
-                     VK_TO_F32 = 4, VK_FROM_F32 = 5, VK_DIFF = 6 };
+                     VK_TO_F32 = 4, VK_FROM_F32 = 5, VK_DIFF = 6, VK_X_TO_Z = 7 };
 
 template <int KIND>
 __global__ __launch_bounds__(256) void vec_batched_kernel(const ItemDesc* __restrict__ items,
@@ -274,6 +285,8 @@ __global__ __launch_bounds__(256) void vec_batched_kernel(const ItemDesc* __rest
     for (int i = e0 + threadIdx.x; i < e1; i += 256) it.x[i] = (float)it.x64[i];
   } else if constexpr (KIND == VK_DIFF) {         // q = fp32(x - x_a)
     for (int i = e0 + threadIdx.x; i < e1; i += 256) it.q[i] = (float)(it.x64[i] - it.xa64[i]);
+  } else if constexpr (KIND == VK_X_TO_Z) {       // z = fp32(x)
+    for (int i = e0 + threadIdx.x; i < e1; i += 256) it.z[i] = (float)it.x64[i];
   } else {
     for (int i = e0 + threadIdx.x; i < e1; i += 256) it.x64[i] = (double)it.x[i];
   }
@@ -617,13 +630,16 @@ static hipError_t true_residual_b(const Batch& B, int mode, int kind) {
 }
 
 // true residuals of the items that asked for one: A^T (b - A x) - lambda^2 x
-// for items without a usable anchor (b - A x in FP64, A^T of it on the fast
-// blur when the tolerance allows, else in FP64), r_a - H (x - x_a) on the
-// fast blur for the others
+// for items without a usable anchor (u = b - A x on the item's fast blur or
+// in FP64 as its tolerance allows, A^T of it on the fast blur when the
+// tolerance allows, else in FP64), r_a - H (x - x_a) on the fast blur for
+// the others
 static hipError_t pending_residuals_b(const Batch& B) {
   hipError_t e;
   if (B.fast_tr) {
-    if ((e = blur64_b<BK_TRUE1>(B, RM_PEND_FULL)) != hipSuccess) return e;
+    if ((e = vec_launch<VK_X_TO_Z>(B, RM_PEND_FULL_FASTU)) != hipSuccess) return e;
+    if ((e = fast_launch<BK_TRUE1F>(B, RM_PEND_FULL_FASTU)) != hipSuccess) return e;
+    if ((e = blur64_b<BK_TRUE1>(B, RM_PEND_FULL_F64U)) != hipSuccess) return e;
     if ((e = fast_launch<BK_TRUE2F>(B, RM_PEND_FULL)) != hipSuccess) return e;
   } else {
     if ((e = true_residual_b(B, RM_PEND_FULL, SC_TRUE)) != hipSuccess) return e;
@@ -794,6 +810,7 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
     c.done = RUNNING;
     c.pscale = 1.0f;
     c.zscale = (float)(1.0 / d.lam2);
+    c.fastu = B.fast_tr && tol >= (d.use_mfma ? TR_FASTU_TOL_MFMA : TR_FASTU_TOL_VALU) ? 1 : 0;
   }
   // tables
   std::vector<TileRef> all;

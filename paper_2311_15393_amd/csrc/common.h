@@ -70,6 +70,9 @@ struct Ctrl {
   int anchor;       // batched solves: (x_a, r_a) holds a true residual small
                     // enough (<= ANCHOR_REL ||A^T b||) to anchor the next one
   int pub;          // publications to the host mirror so far (CtrlMirror)
+  int fastu;        // batched solves: u = b - A x of a full true residual is
+                    // formed on the item's fast blur (TR_FASTU_TOL_*)
+  int pad_;
 };
 
 // The convergence state as the scalar steps publish it to coherent pinned
