@@ -43,21 +43,32 @@ using Tile = T[BM][MT<T>::BK + MT<T>::PAD];
 // operand staging: global -> registers (issued one stage ahead) -> LDS
 // (s[row][k], k contiguous).  Each thread moves two 16-byte vectors per
 // K-contiguous operand and BK*BN/(4*GT) float4 of an FP32 row-major source.
+//
+// VK (n % 8 == 0): every 16-byte vector lies wholly inside or wholly outside
+// the matrix, so each load is one unconditional vector read of a clamped,
+// in-range address and the out-of-range vectors are zeroed only when staged
+// into LDS.  No register written by a load is touched before the staging
+// step, so the loads of a stage stay in flight together across the MFMAs
+// (a bounds branch around each load would make the compiler wait for every
+// load as soon as it is issued).  Otherwise every element is read on its own.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool VK>
 struct KContig {
   static constexpr int BK = MT<T>::BK, VEC = MT<T>::VEC, PER_ROW = BK / VEC;
   static constexpr int NV = BM * BK / VEC / GT;      // = 2
   float4 reg[NV];
-  __device__ void load(const T* __restrict__ g, int row0, int k0, int n, bool vec_ok,
+  bool in[NV];
+  __device__ void load(const T* __restrict__ g, int row0, int k0, int n,
                        int tid = threadIdx.x) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int id = tid + GT * v;
       const int row = id / PER_ROW, kc = (id % PER_ROW) * VEC;
       const int gr = row0 + row, gk = k0 + kc;
-      if (vec_ok && gr < n && gk + VEC <= n) {
-        reg[v] = *reinterpret_cast<const float4*>(g + (size_t)gr * n + gk);
+      if constexpr (VK) {
+        in[v] = gr < n && gk < n;
+        const int cr = gr < n ? gr : n - 1, ck = gk < n ? gk : n - VEC;
+        reg[v] = *reinterpret_cast<const float4*>(g + (size_t)cr * n + ck);
       } else {
         T tmp[VEC];
 #pragma unroll
@@ -72,47 +83,69 @@ struct KContig {
     for (int v = 0; v < NV; ++v) {
       const int id = tid + GT * v;
       const int row = id / PER_ROW, kc = (id % PER_ROW) * VEC;
-      *reinterpret_cast<float4*>(&s[row][kc]) = reg[v];
+      float4 val = reg[v];
+      if constexpr (VK)
+        if (!in[v]) val = make_float4(0.f, 0.f, 0.f, 0.f);
+      *reinterpret_cast<float4*>(&s[row][kc]) = val;
     }
   }
 };
 
 // B tile from a row-major FP32 matrix src[k][j] (contraction over its rows):
-// scaled and rounded to T, transposed into s[j][k].
-template <typename T>
+// scaled and rounded to T, transposed into s[j][k].  Lane j of a wave reads
+// column j0 + j of NG groups of 8 consecutive rows (each read of the wave is
+// one contiguous 256-byte row segment), and writes each group as one 16-byte
+// (T = FP16) or two (T = FP32) vectors along k of s[j][.], so the staging
+// stores are vector writes without bank conflicts.
+template <typename T, bool VK>
 struct FromF32Rows {
   static constexpr int BK = MT<T>::BK;
-  static constexpr int NV = BK * BN / 4 / GT;        // float4 per thread
-  static constexpr int TPR = BN / 4;                 // threads per k row
-  float4 reg[NV];
-  __device__ void load(const float* __restrict__ src, int j0, int k0, int n, bool vec_ok,
+  static constexpr int KQ = GT / BN;                  // row groups in flight at once (4)
+  static constexpr int NG = BK / 8 / KQ;              // groups of 8 rows per thread
+  static_assert(NG >= 1 && NG * 8 * KQ == BK, "k tile must split into groups of 8 rows");
+  float reg[NG][8];
+  bool in[NG];
+  __device__ void load(const float* __restrict__ src, int j0, int k0, int n,
                        int tid = threadIdx.x) {
+    const int j = tid % BN, kq = tid / BN;
+    const int gj = j0 + j;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int id = tid + GT * v;
-      const int k = id / TPR, jc = (id % TPR) * 4;
-      const int gk = k0 + k, gj = j0 + jc;
-      if (vec_ok && gk < n && gj + 4 <= n) {
-        reg[v] = *reinterpret_cast<const float4*>(src + (size_t)gk * n + gj);
+    for (int g = 0; g < NG; ++g) {
+      const int gk0 = k0 + (kq + g * KQ) * 8;
+      if constexpr (VK) {
+        // n % 8 == 0: the 8 rows lie wholly inside or wholly outside
+        in[g] = gk0 < n && gj < n;
+        const int cj = gj < n ? gj : n - 1, ck = gk0 < n ? gk0 : n - 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) reg[g][e] = src[(size_t)(ck + e) * n + cj];
       } else {
-        float4 t;
-        t.x = (gk < n && gj + 0 < n) ? src[(size_t)gk * n + gj + 0] : 0.f;
-        t.y = (gk < n && gj + 1 < n) ? src[(size_t)gk * n + gj + 1] : 0.f;
-        t.z = (gk < n && gj + 2 < n) ? src[(size_t)gk * n + gj + 2] : 0.f;
-        t.w = (gk < n && gj + 3 < n) ? src[(size_t)gk * n + gj + 3] : 0.f;
-        reg[v] = t;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          reg[g][e] = (gk0 + e < n && gj < n) ? src[(size_t)(gk0 + e) * n + gj] : 0.f;
       }
     }
   }
   __device__ void store(Tile<T>& s, float scale, int tid = threadIdx.x) const {
+    const int j = tid % BN, kq = tid / BN;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int id = tid + GT * v;
-      const int k = id / TPR, jc = (id % TPR) * 4;
-      s[jc + 0][k] = (T)(reg[v].x * scale);
-      s[jc + 1][k] = (T)(reg[v].y * scale);
-      s[jc + 2][k] = (T)(reg[v].z * scale);
-      s[jc + 3][k] = (T)(reg[v].w * scale);
+    for (int g = 0; g < NG; ++g) {
+      const int kl = (kq + g * KQ) * 8;
+      bool ok = true;
+      if constexpr (VK) ok = in[g];
+      if constexpr (sizeof(T) == 2) {
+        half8_t h;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) h[e] = ok ? (T)(reg[g][e] * scale) : T(0);
+        *reinterpret_cast<half8_t*>(&s[j][kl]) = h;
+      } else {
+        float4 lo, hi;
+        lo.x = ok ? reg[g][0] * scale : 0.f; lo.y = ok ? reg[g][1] * scale : 0.f;
+        lo.z = ok ? reg[g][2] * scale : 0.f; lo.w = ok ? reg[g][3] * scale : 0.f;
+        hi.x = ok ? reg[g][4] * scale : 0.f; hi.y = ok ? reg[g][5] * scale : 0.f;
+        hi.z = ok ? reg[g][6] * scale : 0.f; hi.w = ok ? reg[g][7] * scale : 0.f;
+        *reinterpret_cast<float4*>(&s[j][kl]) = lo;
+        *reinterpret_cast<float4*>(&s[j][kl + 4]) = hi;
+      }
     }
   }
 };
@@ -214,16 +247,15 @@ struct GEpiFinal {                       // z (already scaled) ; r.z ; z.w
 // ---------------------------------------------------------------------------
 // the GEMM kernel: C[n x n] = A[n x n] * Bt^T (or * B from FP32 rows)
 // ---------------------------------------------------------------------------
-template <typename T, bool B_FROM_F32, class Epi>
-__device__ inline void gemm_tile(const T* __restrict__ A, const void* __restrict__ Bsrc,
-                                 int n, int m0, int n0, Epi epi, float bscale, float oscale,
-                                 double* partial_out, int slot_stride) {
+template <typename T, bool B_FROM_F32, class Epi, bool VK>
+__device__ inline void gemm_tile_vk(const T* __restrict__ A, const void* __restrict__ Bsrc,
+                                    int n, int m0, int n0, Epi epi, float bscale, float oscale,
+                                    double* partial_out, int slot_stride) {
   constexpr int BK = MT<T>::BK;
   __shared__ __align__(16) Tile<T> sA[2];
   __shared__ __align__(16) Tile<T> sB[2];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wm = wv >> 1, wn = wv & 1;
-  const bool vec_ok = (n % 8) == 0;
 
   float4_t acc[2][2];
 #pragma unroll
@@ -231,15 +263,15 @@ __device__ inline void gemm_tile(const T* __restrict__ A, const void* __restrict
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = float4_t{0.f, 0.f, 0.f, 0.f};
 
-  KContig<T> la;
-  using BL = typename std::conditional<B_FROM_F32, FromF32Rows<T>, KContig<T>>::type;
+  KContig<T, VK> la;
+  using BL = typename std::conditional<B_FROM_F32, FromF32Rows<T, VK>, KContig<T, VK>>::type;
   BL lb;
   auto load = [&](int k0) {
-    la.load(A, m0, k0, n, vec_ok);
+    la.load(A, m0, k0, n);
     if constexpr (B_FROM_F32)
-      lb.load(reinterpret_cast<const float*>(Bsrc), n0, k0, n, vec_ok);
+      lb.load(reinterpret_cast<const float*>(Bsrc), n0, k0, n);
     else
-      lb.load(reinterpret_cast<const T*>(Bsrc), n0, k0, n, vec_ok);
+      lb.load(reinterpret_cast<const T*>(Bsrc), n0, k0, n);
   };
   auto store = [&](int buf) {
     la.store(sA[buf]);
@@ -298,11 +330,11 @@ constexpr size_t gemm_splitk_lds(int ks) {
 }
 constexpr int RED_LD = BN + 1;           // row pitch of the reduction tiles (floats)
 
-template <typename T, bool B_FROM_F32, class Epi, int KS>
-__device__ inline void gemm_tile_splitk(const T* __restrict__ A, const void* __restrict__ Bsrc,
-                                        int n, int m0, int n0, Epi epi, float bscale,
-                                        float oscale, double* partial_out, int slot_stride,
-                                        char* lds) {
+template <typename T, bool B_FROM_F32, class Epi, int KS, bool VK>
+__device__ inline void gemm_tile_splitk_vk(const T* __restrict__ A,
+                                           const void* __restrict__ Bsrc, int n, int m0, int n0,
+                                           Epi epi, float bscale, float oscale,
+                                           double* partial_out, int slot_stride, char* lds) {
   constexpr int BK = MT<T>::BK;
   static_assert((size_t)KS * BM * RED_LD * sizeof(float) <= gemm_splitk_lds<T>(KS),
                 "reduction tiles must fit in the stage buffers");
@@ -312,7 +344,6 @@ __device__ inline void gemm_tile_splitk(const T* __restrict__ A, const void* __r
   const int kg = threadIdx.x / GT, tid = threadIdx.x % GT;
   const int lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
-  const bool vec_ok = (n % 8) == 0;
 
   float4_t acc[2][2];
 #pragma unroll
@@ -320,17 +351,17 @@ __device__ inline void gemm_tile_splitk(const T* __restrict__ A, const void* __r
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = float4_t{0.f, 0.f, 0.f, 0.f};
 
-  KContig<T> la;
-  using BL = typename std::conditional<B_FROM_F32, FromF32Rows<T>, KContig<T>>::type;
+  KContig<T, VK> la;
+  using BL = typename std::conditional<B_FROM_F32, FromF32Rows<T, VK>, KContig<T, VK>>::type;
   BL lb;
   Tile<T>* myA = sA + 2 * kg;
   Tile<T>* myB = sB + 2 * kg;
   auto load = [&](int k0) {
-    la.load(A, m0, k0, n, vec_ok, tid);
+    la.load(A, m0, k0, n, tid);
     if constexpr (B_FROM_F32)
-      lb.load(reinterpret_cast<const float*>(Bsrc), n0, k0, n, vec_ok, tid);
+      lb.load(reinterpret_cast<const float*>(Bsrc), n0, k0, n, tid);
     else
-      lb.load(reinterpret_cast<const T*>(Bsrc), n0, k0, n, vec_ok, tid);
+      lb.load(reinterpret_cast<const T*>(Bsrc), n0, k0, n, tid);
   };
   auto store = [&](int buf) {
     la.store(myA[buf], tid);
@@ -395,6 +426,33 @@ __device__ inline void gemm_tile_splitk(const T* __restrict__ A, const void* __r
       partial_out[slot_stride] = s1;
     }
   }
+}
+
+// the kernels' entry points: the vector-load body when n % 8 == 0 (a uniform
+// branch), else the element-wise one
+template <typename T, bool B_FROM_F32, class Epi>
+__device__ inline void gemm_tile(const T* __restrict__ A, const void* __restrict__ Bsrc,
+                                 int n, int m0, int n0, Epi epi, float bscale, float oscale,
+                                 double* partial_out, int slot_stride) {
+  if ((n % 8) == 0)
+    gemm_tile_vk<T, B_FROM_F32, Epi, true>(A, Bsrc, n, m0, n0, epi, bscale, oscale,
+                                           partial_out, slot_stride);
+  else
+    gemm_tile_vk<T, B_FROM_F32, Epi, false>(A, Bsrc, n, m0, n0, epi, bscale, oscale,
+                                            partial_out, slot_stride);
+}
+
+template <typename T, bool B_FROM_F32, class Epi, int KS>
+__device__ inline void gemm_tile_splitk(const T* __restrict__ A, const void* __restrict__ Bsrc,
+                                        int n, int m0, int n0, Epi epi, float bscale,
+                                        float oscale, double* partial_out, int slot_stride,
+                                        char* lds) {
+  if ((n % 8) == 0)
+    gemm_tile_splitk_vk<T, B_FROM_F32, Epi, KS, true>(A, Bsrc, n, m0, n0, epi, bscale, oscale,
+                                                      partial_out, slot_stride, lds);
+  else
+    gemm_tile_splitk_vk<T, B_FROM_F32, Epi, KS, false>(A, Bsrc, n, m0, n0, epi, bscale,
+                                                       oscale, partial_out, slot_stride, lds);
 }
 
 }  // namespace kpcg
