@@ -2,6 +2,8 @@
 // the single-problem kernel and the batched tile-table kernel.
 #pragma once
 
+#include <type_traits>
+
 #include "blur_core.h"
 
 namespace kpcg {
@@ -13,7 +15,12 @@ typedef _Float16 mh2_t __attribute__((ext_vector_type(2)));
 constexpr int MB_TM = 64, MB_TN = 64, MB_NT = 512;   // 2 groups of 4 waves
 
 __host__ __device__ constexpr int mb_width(int nch) { return MB_TN - 16 + 32 * nch; }
-__host__ __device__ constexpr int mb_pitch(int nch) { return mb_width(nch) + 8; }
+// Row pitch of the LDS planes.  The A-fragment reads (lane l: 16 bytes at
+// row l % 16, column 8 (l / 16)) measured free of bank conflicts on gfx950
+// when the pitch is 8 mod 16 dwords, and 2-way conflicted at the other
+// multiples of 4 dwords tried; the width, 24 + 16 nch dwords, is such a
+// pitch, so the rows are not padded.
+__host__ __device__ constexpr int mb_pitch(int nch) { return mb_width(nch); }
 // hi and lo planes, then the second wave group's partial accumulators
 inline size_t mb_lds_bytes(int nch, int K) {
   return (size_t)2 * (MB_TM + K - 1) * mb_pitch(nch) * sizeof(_Float16) +
@@ -105,38 +112,54 @@ __device__ inline void blur_mfma_tile(const float* __restrict__ src,
 #pragma unroll
     for (int t = 0; t < 2 * NCH; ++t) bq[p][t] = bfrag[(ap * NCH * 2 + t) * 64 + lane];
   }
-  for (int a0 = abeg; a0 < aend; a0 += PF + 1) {
+  // tap row a in ring slot SL (= (a - abeg) mod (PF + 1)): prefetch row
+  // a + PF into the slot row a - 1 used, read the row-shifted input
+  // windows, and issue the MFMAs
+  auto row = [&](auto slc, int a) {
+    constexpr int SL = decltype(slc)::value;
+    const int an = a + PF < aend ? a + PF : aend - 1;
 #pragma unroll
-    for (int sl = 0; sl <= PF; ++sl) {
-      const int a = a0 + sl;
-      if (a < aend) {
-        const int an = a + PF < aend ? a + PF : aend - 1;
+    for (int t = 0; t < 2 * NCH; ++t)
+      bq[(SL + PF) % (PF + 1)][t] = bfrag[(an * NCH * 2 + t) * 64 + lane];
+    // keep the prefetch at the head of its row (the scheduler would sink it
+    // below the MFMAs, next to its first use)
+    __builtin_amdgcn_sched_barrier(0);
+    const int off = (w * 16 + a + m) * PITCH + 8 * g;
+    mh8_t ah[NU], al[NU];
 #pragma unroll
-        for (int t = 0; t < 2 * NCH; ++t)
-          bq[(sl + PF) % (PF + 1)][t] = bfrag[(an * NCH * 2 + t) * 64 + lane];
-        const int off = (w * 16 + a + m) * PITCH + 8 * g;
-        mh8_t ah[NU], al[NU];
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          ah[u] = *reinterpret_cast<const mh8_t*>(shi + off + 16 * u);
-          al[u] = *reinterpret_cast<const mh8_t*>(slo + off + 16 * u);
-        }
-#pragma unroll
-        for (int t = 0; t < NCH; ++t) {
-          const mh8_t bh = bq[sl][2 * t], bl = bq[sl][2 * t + 1];
-#pragma unroll
-          for (int jb = 0; jb < 4; ++jb)
-            acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bh, acc[jb], 0, 0, 0);
-#pragma unroll
-          for (int jb = 0; jb < 4; ++jb)
-            acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bl, acc[jb], 0, 0, 0);
-#pragma unroll
-          for (int jb = 0; jb < 4; ++jb)
-            acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[jb + 2 * t], bh, acc[jb], 0, 0, 0);
-        }
-      }
+    for (int u = 0; u < NU; ++u) {
+      ah[u] = *reinterpret_cast<const mh8_t*>(shi + off + 16 * u);
+      al[u] = *reinterpret_cast<const mh8_t*>(slo + off + 16 * u);
     }
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+      const mh8_t bh = bq[SL][2 * t], bl = bq[SL][2 * t + 1];
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bh, acc[jb], 0, 0, 0);
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bl, acc[jb], 0, 0, 0);
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[jb + 2 * t], bh, acc[jb], 0, 0, 0);
+    }
+  };
+  // whole rounds of PF + 1 rows run without a per-row branch, so the
+  // compiler's wait counts keep the prefetched rows in flight (a branch per
+  // row made it wait for every outstanding load); then the 0 .. PF rows left
+  static_assert(PF == 2, "the unrolled round below holds PF + 1 = 3 rows");
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  using S2 = std::integral_constant<int, 2>;
+  int a0 = abeg;
+  for (; a0 + PF + 1 <= aend; a0 += PF + 1) {
+    row(S0{}, a0);
+    row(S1{}, a0 + 1);
+    row(S2{}, a0 + 2);
   }
+  if (a0 < aend) row(S0{}, a0);
+  if (a0 + 1 < aend) row(S1{}, a0 + 1);
 
   float* redacc = reinterpret_cast<float*>(slo + rows * PITCH);
   if (grp == 1) {

@@ -26,10 +26,15 @@ template <> struct MT<float> {
   static constexpr int PAD = 4;
   static constexpr int KM = 4;      // k per MFMA
 };
+// FP16 stage rows are padded to 40 dwords: the MFMA operand reads (lane l:
+// 16 bytes at row l % 16, column 8 (l / 16)) measured free of LDS bank
+// conflicts on gfx950 at row pitches of 8 mod 16 dwords, and 2-way
+// conflicted at the other multiples of 4 dwords tried.  (The FP32 stages are
+// read 4 bytes per lane and keep the 36-dword pitch, measured faster.)
 template <> struct MT<_Float16> {
   static constexpr int BK = 64;
   static constexpr int VEC = 8;
-  static constexpr int PAD = 8;
+  static constexpr int PAD = 16;
   static constexpr int KM = 32;
 };
 
@@ -336,8 +341,9 @@ __device__ inline void gemm_tile_splitk_vk(const T* __restrict__ A,
                                            Epi epi, float bscale, float oscale,
                                            double* partial_out, int slot_stride, char* lds) {
   constexpr int BK = MT<T>::BK;
-  static_assert((size_t)KS * BM * RED_LD * sizeof(float) <= gemm_splitk_lds<T>(KS),
-                "reduction tiles must fit in the stage buffers");
+  static_assert((size_t)KS * BM * RED_LD * sizeof(float) + GT * KS / 64 * sizeof(double) <=
+                    gemm_splitk_lds<T>(KS),
+                "reduction tiles and the block-sum scratch must fit in the stage buffers");
   static_assert((BM * BN) % (GT * KS) == 0, "outputs must split evenly over the threads");
   Tile<T>* sA = reinterpret_cast<Tile<T>*>(lds);     // [KS][2]
   Tile<T>* sB = sA + 2 * KS;                          // [KS][2]
@@ -418,7 +424,9 @@ __device__ inline void gemm_tile_splitk_vk(const T* __restrict__ A,
     if (i < n && j < n) epi.apply(i, j, v * oscale, d0, d1);
   }
   if constexpr (Epi::kReduce) {
-    __shared__ double sh[GT * KS / 64];
+    // block-sum scratch after the reduction tiles (the stage buffers take
+    // all of the LDS a workgroup may have, so it cannot be static)
+    double* sh = reinterpret_cast<double*>(lds + (size_t)KS * BM * RED_LD * sizeof(float));
     const double s0 = block_sum<GT * KS>(d0, sh);
     const double s1 = block_sum<GT * KS>(d1, sh);
     if (threadIdx.x == 0) {
