@@ -14,13 +14,24 @@ typedef _Float16 mh2_t __attribute__((ext_vector_type(2)));
 
 constexpr int MB_TM = 64, MB_TN = 64, MB_NT = 512;   // 2 groups of 4 waves
 
-__host__ __device__ constexpr int mb_width(int nch) { return MB_TN - 16 + 32 * nch; }
+// NCH = 3 (K = 51 .. 63) pairs tap rows: two full 32-column chunks per row,
+// and one MFMA whose k = 32 holds the last 16 columns of two rows (the band
+// needs K + 15 - 64 <= 14 of them), so a row pair takes 5 chunk MFMAs
+// where unpaired rows take 6.
+__host__ __device__ constexpr bool mb_pair(int nch) { return nch == 3; }
+// staged input columns: the windows of the full chunks reach column
+// 48 + 32 nch (unpaired), the paired remainder column 32 (nch - 1) + 64
+__host__ __device__ constexpr int mb_width(int nch) {
+  return mb_pair(nch) ? 32 * nch + 32 : MB_TN - 16 + 32 * nch;
+}
 // Row pitch of the LDS planes.  The A-fragment reads (lane l: 16 bytes at
 // row l % 16, column 8 (l / 16)) measured free of bank conflicts on gfx950
 // when the pitch is 8 mod 16 dwords, and 2-way conflicted at the other
-// multiples of 4 dwords tried; the width, 24 + 16 nch dwords, is such a
-// pitch, so the rows are not padded.
-__host__ __device__ constexpr int mb_pitch(int nch) { return mb_width(nch); }
+// multiples of 4 dwords tried.  The unpaired width, 24 + 16 nch dwords, is
+// such a pitch; the paired one, 16 nch + 16 dwords, is padded by 8.
+__host__ __device__ constexpr int mb_pitch(int nch) {
+  return mb_pair(nch) ? mb_width(nch) + 16 : mb_width(nch);
+}
 // hi and lo planes, then the second wave group's partial accumulators
 inline size_t mb_lds_bytes(int nch, int K) {
   return (size_t)2 * (MB_TM + K - 1) * mb_pitch(nch) * sizeof(_Float16) +
@@ -97,69 +108,162 @@ __device__ inline void blur_mfma_tile(const float* __restrict__ src,
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int w = wv & 3, grp = wv >> 2;
   const int m = lane & 15, g = lane >> 4;
-  const int half = (K + 1) >> 1;
+  // (paired: group 0 takes an even number of rows, so only the last row,
+  // K - 1, can be left without a partner)
+  const int half = mb_pair(NCH) ? ((((K + 1) >> 1) + 1) & ~1) : (K + 1) >> 1;
   const int abeg = grp * half, aend = grp ? K : half;
   mf4_t acc[4];
 #pragma unroll
   for (int jb = 0; jb < 4; ++jb) acc[jb] = mf4_t{0.f, 0.f, 0.f, 0.f};
 
-  // tap fragments of rows a .. a + PF in a ring of PF + 1 register slots;
-  // slot entries 2t / 2t+1 are the hi / lo fragments of chunk t
-  mh8_t bq[PF + 1][2 * NCH];
+  if constexpr (mb_pair(NCH)) {
+    constexpr int F = NCH - 1;             // full 32-column chunks per row
+    constexpr int NF = 2 * F;              // their hi / lo fragments
+    constexpr int NUF = 2 * F + 2;         // 16-column windows they read
+    // a ring of two pair slots: fragments [0, NF) of row a, [NF, 2 NF) of
+    // row a + 1, then the hi / lo remainder fragment of the pair
+    mh8_t bp[2][2 * NF + 2];
+    auto fetch = [&](mh8_t (&dst)[2 * NF + 2], int ap) {
+      const int a1 = ap + 1 < K ? ap + 1 : ap;       // (row K - 1 has no partner)
 #pragma unroll
-  for (int p = 0; p < PF; ++p) {
-    const int ap = abeg + p < aend ? abeg + p : aend - 1;
+      for (int t = 0; t < NF; ++t) dst[t] = bfrag[(ap * NCH * 2 + t) * 64 + lane];
 #pragma unroll
-    for (int t = 0; t < 2 * NCH; ++t) bq[p][t] = bfrag[(ap * NCH * 2 + t) * 64 + lane];
-  }
-  // tap row a in ring slot SL (= (a - abeg) mod (PF + 1)): prefetch row
-  // a + PF into the slot row a - 1 used, read the row-shifted input
-  // windows, and issue the MFMAs
-  auto row = [&](auto slc, int a) {
-    constexpr int SL = decltype(slc)::value;
-    const int an = a + PF < aend ? a + PF : aend - 1;
+      for (int t = 0; t < NF; ++t) dst[NF + t] = bfrag[(a1 * NCH * 2 + t) * 64 + lane];
+      dst[2 * NF] = bfrag[(ap * NCH * 2 + NF) * 64 + lane];
+      dst[2 * NF + 1] = bfrag[(ap * NCH * 2 + NF + 1) * 64 + lane];
+    };
+    // the full chunks of tap row a (fragments bfr[0 .. NF))
+    auto full_row = [&](const mh8_t* bfr, int a) {
+      const int off = (w * 16 + a + m) * PITCH + 8 * g;
+      mh8_t ah[NUF], al[NUF];
 #pragma unroll
-    for (int t = 0; t < 2 * NCH; ++t)
-      bq[(SL + PF) % (PF + 1)][t] = bfrag[(an * NCH * 2 + t) * 64 + lane];
-    // keep the prefetch at the head of its row (the scheduler would sink it
-    // below the MFMAs, next to its first use)
-    __builtin_amdgcn_sched_barrier(0);
-    const int off = (w * 16 + a + m) * PITCH + 8 * g;
-    mh8_t ah[NU], al[NU];
+      for (int u = 0; u < NUF; ++u) {
+        ah[u] = *reinterpret_cast<const mh8_t*>(shi + off + 16 * u);
+        al[u] = *reinterpret_cast<const mh8_t*>(slo + off + 16 * u);
+      }
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-      ah[u] = *reinterpret_cast<const mh8_t*>(shi + off + 16 * u);
-      al[u] = *reinterpret_cast<const mh8_t*>(slo + off + 16 * u);
+      for (int t = 0; t < F; ++t) {
+        const mh8_t bh = bfr[2 * t], bl = bfr[2 * t + 1];
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+          acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bh, acc[jb], 0, 0, 0);
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+          acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bl, acc[jb], 0, 0, 0);
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+          acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[jb + 2 * t], bh, acc[jb], 0, 0, 0);
+      }
+    };
+    // the remainder of rows a and a + 1: lanes g < 2 read row a, g >= 2 row
+    // a + 1, each at window columns 32 F + 8 (g mod 2); a row without a
+    // partner reads itself twice against zero taps
+    auto remainder = [&](const mh8_t* bfr, int a, bool partner) {
+      const int r = w * 16 + a + m + (partner && g >= 2 ? 1 : 0);
+      const int off = r * PITCH + 32 * F + 8 * (g & 1);
+      mh8_t ah[4], al[4];
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) {
+        ah[jb] = *reinterpret_cast<const mh8_t*>(shi + off + 16 * jb);
+        al[jb] = *reinterpret_cast<const mh8_t*>(slo + off + 16 * jb);
+      }
+      const mh8_t bh = bfr[0], bl = bfr[1];
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb], bh, acc[jb], 0, 0, 0);
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb], bl, acc[jb], 0, 0, 0);
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[jb], bh, acc[jb], 0, 0, 0);
+    };
+    // rows a, a + 1 from ring slot SL, prefetching the next pair into the
+    // other slot (pinned at the head of the step, as in the unpaired loop)
+    auto pair = [&](auto slc, int a, auto lonec) {
+      constexpr int SL = decltype(slc)::value;
+      constexpr bool LONE = decltype(lonec)::value;
+      if constexpr (!LONE) fetch(bp[SL ^ 1], a + 2 < aend ? a + 2 : a);
+      __builtin_amdgcn_sched_barrier(0);
+      full_row(&bp[SL][0], a);
+      if constexpr (!LONE) full_row(&bp[SL][NF], a + 1);
+      remainder(&bp[SL][2 * NF], a, !LONE);
+    };
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    using Two = std::false_type;
+    using One = std::true_type;
+    fetch(bp[0], abeg);
+    int a0 = abeg;
+    for (; a0 + 4 <= aend; a0 += 4) {
+      pair(S0{}, a0, Two{});
+      pair(S1{}, a0 + 2, Two{});
     }
-#pragma unroll
-    for (int t = 0; t < NCH; ++t) {
-      const mh8_t bh = bq[SL][2 * t], bl = bq[SL][2 * t + 1];
-#pragma unroll
-      for (int jb = 0; jb < 4; ++jb)
-        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bh, acc[jb], 0, 0, 0);
-#pragma unroll
-      for (int jb = 0; jb < 4; ++jb)
-        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bl, acc[jb], 0, 0, 0);
-#pragma unroll
-      for (int jb = 0; jb < 4; ++jb)
-        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[jb + 2 * t], bh, acc[jb], 0, 0, 0);
+    if (a0 + 2 <= aend) {
+      pair(S0{}, a0, Two{});
+      if (a0 + 2 < aend) pair(S1{}, a0 + 2, One{});
+    } else if (a0 < aend) {
+      pair(S0{}, a0, One{});
     }
-  };
-  // whole rounds of PF + 1 rows run without a per-row branch, so the
-  // compiler's wait counts keep the prefetched rows in flight (a branch per
-  // row made it wait for every outstanding load); then the 0 .. PF rows left
-  static_assert(PF == 2, "the unrolled round below holds PF + 1 = 3 rows");
-  using S0 = std::integral_constant<int, 0>;
-  using S1 = std::integral_constant<int, 1>;
-  using S2 = std::integral_constant<int, 2>;
-  int a0 = abeg;
-  for (; a0 + PF + 1 <= aend; a0 += PF + 1) {
-    row(S0{}, a0);
-    row(S1{}, a0 + 1);
-    row(S2{}, a0 + 2);
+  } else {
+    // tap fragments of rows a .. a + PF in a ring of PF + 1 register slots;
+    // slot entries 2t / 2t+1 are the hi / lo fragments of chunk t
+    mh8_t bq[PF + 1][2 * NCH];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int ap = abeg + p < aend ? abeg + p : aend - 1;
+#pragma unroll
+      for (int t = 0; t < 2 * NCH; ++t) bq[p][t] = bfrag[(ap * NCH * 2 + t) * 64 + lane];
+    }
+    // tap row a in ring slot SL (= (a - abeg) mod (PF + 1)): prefetch row
+    // a + PF into the slot row a - 1 used, read the row-shifted input
+    // windows, and issue the MFMAs
+    auto row = [&](auto slc, int a) {
+      constexpr int SL = decltype(slc)::value;
+      const int an = a + PF < aend ? a + PF : aend - 1;
+#pragma unroll
+      for (int t = 0; t < 2 * NCH; ++t)
+        bq[(SL + PF) % (PF + 1)][t] = bfrag[(an * NCH * 2 + t) * 64 + lane];
+      // keep the prefetch at the head of its row (the scheduler would sink it
+      // below the MFMAs, next to its first use)
+      __builtin_amdgcn_sched_barrier(0);
+      const int off = (w * 16 + a + m) * PITCH + 8 * g;
+      mh8_t ah[NU], al[NU];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        ah[u] = *reinterpret_cast<const mh8_t*>(shi + off + 16 * u);
+        al[u] = *reinterpret_cast<const mh8_t*>(slo + off + 16 * u);
+      }
+#pragma unroll
+      for (int t = 0; t < NCH; ++t) {
+        const mh8_t bh = bq[SL][2 * t], bl = bq[SL][2 * t + 1];
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+          acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bh, acc[jb], 0, 0, 0);
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+          acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[jb + 2 * t], bl, acc[jb], 0, 0, 0);
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+          acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[jb + 2 * t], bh, acc[jb], 0, 0, 0);
+      }
+    };
+    // whole rounds of PF + 1 rows run without a per-row branch, so the
+    // compiler's wait counts keep the prefetched rows in flight (a branch per
+    // row made it wait for every outstanding load); then the 0 .. PF rows left
+    static_assert(PF == 2, "the unrolled round below holds PF + 1 = 3 rows");
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    using S2 = std::integral_constant<int, 2>;
+    int a0 = abeg;
+    for (; a0 + PF + 1 <= aend; a0 += PF + 1) {
+      row(S0{}, a0);
+      row(S1{}, a0 + 1);
+      row(S2{}, a0 + 2);
+    }
+    if (a0 < aend) row(S0{}, a0);
+    if (a0 + 1 < aend) row(S1{}, a0 + 1);
   }
-  if (a0 < aend) row(S0{}, a0);
-  if (a0 + 1 < aend) row(S1{}, a0 + 1);
 
   float* redacc = reinterpret_cast<float*>(slo + rows * PITCH);
   if (grp == 1) {

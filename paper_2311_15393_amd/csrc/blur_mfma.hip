@@ -7,7 +7,13 @@
 // input windows (row-shifted by a) with the banded Toeplitz 32 x 16 matrices
 // T_{a,t}[k][c] = Q[a][32 t + k - c], t = 0 .. NCH-1, NCH = ceil((K+15)/32);
 // T_{a,t} does not depend on where the block sits, so its MFMA fragments are
-// built once per plan (mfma_taps_kernel).  v_mfma_f32_16x16x32_f16 takes the
+// built once per plan (mfma_taps_kernel).  The band of one block and tap row
+// is 16 + K - 1 columns wide; for NCH = 3 (K = 51 .. 63) its last K - 49
+// <= 14 columns are shorter than a chunk, so tap rows go in pairs: each row
+// takes NCH - 1 full chunks, and one MFMA takes the last 16 columns of both
+// rows (k < 16 from row a, k >= 16 from row a + 1, taps R_a[k][c] = Q[a +
+// k div 16][64 + k mod 16 - c]), 5 chunk MFMAs per pair instead of 6.
+// v_mfma_f32_16x16x32_f16 takes the
 // inputs and taps as hi + lo FP16 pairs (power-of-two scaled: per tile for the
 // input, per plan for the taps, so the hi parts sit in [2^13, 2^14)), and the
 // three products hi*hi, hi*lo, lo*hi accumulate in FP32.  FP16 x FP16
@@ -17,11 +23,13 @@
 //
 // Workgroup: 64 x 64 outputs, two groups of 4 waves of 16 rows x 64 columns,
 // each group taking half of the tap rows (sums added in LDS).  The
-// (64+K-1) x (48+32 NCH) input tile is read once from global memory into
+// (64+K-1) x mb_width(NCH) input tile is read once from global memory into
 // registers, scaled, and written to LDS as hi and lo planes; per tap row a
 // wave reads NU = 2 NCH + 2 A-fragment pairs from LDS and 2 NCH tap fragments
 // from the L2-resident table (prefetched two rows ahead), and issues 12 NCH
-// MFMAs.
+// MFMAs (paired rows: 4 NCH + 4 A-fragment pairs, 4 NCH - 2 tap
+// fragments and 24 NCH - 12 MFMAs per pair, the next pair's fragments
+// prefetched).
 #include "blur_mfma.h"
 
 namespace kpcg {
@@ -40,11 +48,16 @@ __global__ __launch_bounds__(256) void mfma_taps_kernel(const float* __restrict_
   rest >>= 1;
   const int t = rest % nch, a = rest / nch;
   const int c = lane & 15, g = lane >> 4;
+  // paired rows (mb_pair): the last chunk of row a is the remainder of rows
+  // a (k < 16) and a + 1 (k >= 16), both at window columns 32 t + (k mod 16)
+  const bool rem = mb_pair(nch) && t == nch - 1;
+  const int arow = rem && g >= 2 ? a + 1 : a;
+  const int kk = rem ? 8 * (g & 1) : 8 * g;
   mh8_t v;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    const int b = 32 * t + 8 * g + e - c;
-    const float q = (b >= 0 && b < K) ? taps[a * KQ + b] : 0.0f;
+    const int b = 32 * t + kk + e - c;
+    const float q = (b >= 0 && b < K && arow < K) ? taps[arow * KQ + b] : 0.0f;
     const float s = ldexpf(q, exq);
     const _Float16 hi = (_Float16)s;
     v[e] = part == 0 ? hi : (_Float16)(s - (float)hi);
