@@ -53,10 +53,10 @@ COPY_CALIB_FLOATS = 64 * 1024 * 1024
 # is reported as null.
 BLUR_TRAFFIC = {
     "kernel": "blur_mfma_kernel<3, EpiStoreF32>",
-    "fetch_kib_raw": 5594.5, "write_kib_raw": 4096.0,       # per launch, as counted
+    "fetch_kib_raw": 5350.3, "write_kib_raw": 4096.0,       # per launch, as counted
     "fetch_scale": 1.99980, "write_scale": 1.0,              # copy bytes / counter
-    "bytes_per_launch": 15650687,
-    "sources_sha256": "919a344cf0d7474af82f62d0d6018617972bae25533562f59ebc2b9dbe8ee483",
+    "bytes_per_launch": 15150538,
+    "sources_sha256": "58bf650fdcce1ea93786d955106bdaf2f5f2d2d802f2045d26cf7b03886e9857",
 }
 
 
@@ -94,15 +94,24 @@ def blur_traffic(kernel: str):
 
 def mfma_blur_flops(n: int, k: int, cfg: int = 6) -> float:
     """FP16 MFMA flops the MFMA blur issues per launch.  16x16x32 kernel
-    (cfg 6): per 64 x 64 tile, 4 row strips x K tap rows x NCH chunks x 4
-    blocks x 3 split products of 16384 flop.  32x32x16 kernel (cfg 7): 2 row
-    halves x K tap rows x NC chunks x 2 blocks x 3 products of 32768 flop."""
+    (cfg 6): per 64 x 64 tile, 4 row strips x (chunk MFMAs of the K tap
+    rows) x 4 blocks x 3 split products of 16384 flop, where the chunks are
+    K x NCH, or with paired rows (NCH = 3) 2 NCH - 1 per pair and NCH for a
+    row left without a partner (the second wave group's last row).
+    32x32x16 kernel (cfg 7): 2 row halves x K tap rows x NC chunks x 2
+    blocks x 3 products of 32768 flop."""
     tiles = ((n + 63) // 64) ** 2
     if cfg == 7:
         nc = (k + 31 + 15) // 16
         return tiles * 2.0 * k * nc * 2 * 3 * 32768
     nch = (k + 15 + 31) // 32
-    return tiles * 4.0 * k * nch * 4 * 3 * 16384
+    if nch == 3:
+        half = (((k + 1) >> 1) + 1) & ~1
+        rows1 = k - half
+        chunks = (half // 2 + rows1 // 2) * (2 * nch - 1) + (rows1 % 2) * nch
+    else:
+        chunks = k * nch
+    return tiles * 4.0 * chunks * 4 * 3 * 16384
 
 
 def cpu_threads() -> int:

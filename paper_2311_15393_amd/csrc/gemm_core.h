@@ -255,10 +255,9 @@ struct GEpiFinal {                       // z (already scaled) ; r.z ; z.w
 template <typename T, bool B_FROM_F32, class Epi, bool VK>
 __device__ inline void gemm_tile_vk(const T* __restrict__ A, const void* __restrict__ Bsrc,
                                     int n, int m0, int n0, Epi epi, float bscale, float oscale,
-                                    double* partial_out, int slot_stride) {
+                                    double* partial_out, int slot_stride, Tile<T>* sA,
+                                    Tile<T>* sB) {
   constexpr int BK = MT<T>::BK;
-  __shared__ __align__(16) Tile<T> sA[2];
-  __shared__ __align__(16) Tile<T> sB[2];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wm = wv >> 1, wn = wv & 1;
 
@@ -309,7 +308,10 @@ __device__ inline void gemm_tile_vk(const T* __restrict__ A, const void* __restr
       }
     }
   if constexpr (Epi::kReduce) {
-    __shared__ double sh[GT / 64];
+    // block-sum scratch in the stage buffers, free after the k-loop's last
+    // barrier: a static array beside them would push four workgroups' LDS
+    // just past the 160 KiB of a CU and cost one of them
+    double* sh = reinterpret_cast<double*>(&sA[0][0][0]);
     const double s0 = block_sum<GT>(d0, sh);
     const double s1 = block_sum<GT>(d1, sh);
     if (threadIdx.x == 0) {
@@ -442,12 +444,16 @@ template <typename T, bool B_FROM_F32, class Epi>
 __device__ inline void gemm_tile(const T* __restrict__ A, const void* __restrict__ Bsrc,
                                  int n, int m0, int n0, Epi epi, float bscale, float oscale,
                                  double* partial_out, int slot_stride) {
+  // one set of stage buffers for both bodies (each declaring its own would
+  // double the workgroup's LDS and halve the workgroups per CU)
+  __shared__ __align__(16) Tile<T> sA[2];
+  __shared__ __align__(16) Tile<T> sB[2];
   if ((n % 8) == 0)
     gemm_tile_vk<T, B_FROM_F32, Epi, true>(A, Bsrc, n, m0, n0, epi, bscale, oscale,
-                                           partial_out, slot_stride);
+                                           partial_out, slot_stride, sA, sB);
   else
     gemm_tile_vk<T, B_FROM_F32, Epi, false>(A, Bsrc, n, m0, n0, epi, bscale, oscale,
-                                            partial_out, slot_stride);
+                                            partial_out, slot_stride, sA, sB);
 }
 
 template <typename T, bool B_FROM_F32, class Epi, int KS>
