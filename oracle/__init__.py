@@ -19,6 +19,9 @@ Preconditioner for Structured Inverse Problems" (arXiv:2311.15393):
   lam.py       lambda_opt, GCV, weighted GCV and the discrepancy principle in
                a spectral basis (eqs. (OptTikSVD), (GCVTikSVD), (wGCVTikSVD),
                (DSCTikSVD)), and the trace form of GCV (eq. (GCVTik))
+  periodic.py  the periodic boundary: block-circulant A and A^T, the
+               circulant one-term Kronecker approximation, and the exact
+               Tikhonov minimiser through the 2-D DFT
   quant.py     FP16 and FP8-e4m3 rounding and the emulated reduced-precision
                preconditioner chain
   mlp.py       FP64 reference of the small lambda-predicting network
