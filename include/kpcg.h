@@ -46,14 +46,19 @@ extern "C" {
 #define KP_ERR_ARG         -1   /* null pointer, n < 1, K even, K > 2n-1,
                                    lambda <= 0, tol <= 0, maxit < 1, a
                                    non-finite argument, bad mode bits      */
-#define KP_ERR_UNSUPPORTED -2   /* boundary condition other than zero, or
-                                   K above KP_MAX_PSF                      */
+#define KP_ERR_UNSUPPORTED -2   /* unknown boundary condition, K above
+                                   KP_MAX_PSF, or a mode the plan's
+                                   boundary does not support              */
 #define KP_ERR_HIP         -3   /* a HIP runtime call failed               */
 #define KP_ERR_SOLVER      -4   /* the FP64 factor SVD (rocSOLVER) failed  */
 #define KP_ERR_WORKSPACE   -5   /* caller workspace smaller than required  */
 
 #define KP_MAX_PSF 63           /* largest supported PSF support K          */
-#define KP_BC_ZERO  0           /* the only boundary condition supported   */
+#define KP_BC_ZERO      0       /* image zero outside [0, n)^2 (BTTB A)     */
+#define KP_BC_PERIODIC  1       /* image extended periodically (BCCB A,
+                                   K <= n); one-term KP with circulant
+                                   factors; no KP_EXACT_DIAG, no batched
+                                   solves                                  */
 
 /* ---- mode bits for pcg_solve / pcg_solve_batched --------------------- */
 #define KP_CG        0x000      /* no preconditioner                        */
@@ -126,13 +131,18 @@ size_t kp_workspace_size(int n, int k, int modes);
  * Section 3, eq. (AKronSVD) and Section 5, eq. (KronSumDecomp): A is
  * approximated by the Frobenius-optimal Kronecker product A_r (x) A_c
  * (built from the leading singular triple of the PSF weighted by
- * sqrt(n - |k - h|) on both sides), and A_r, A_c are factorised by FP64
- * SVDs on the device.  V_r, V_c are stored in FP32, FP16 and FP8 (with
+ * sqrt(n - |k - h|) on both sides: banded Toeplitz factors for the zero
+ * boundary; for the periodic boundary every weight is n, i.e. the plain
+ * PSF SVD, and the factors are circulant), and A_r, A_c are factorised by
+ * FP64 SVDs on the device.  The paper states no boundary condition; both
+ * keep its PSF centre (h, h) and true convolution for A.  V_r, V_c are stored in FP32, FP16 and FP8 (with
  * block scales), U_r, U_c in FP32, singular values in FP64 and FP32.
  *
  *   psf        host, K*K float64, row-major
- *   k, n       PSF support (odd, <= KP_MAX_PSF, <= 2n-1), image size
- *   bc         KP_BC_ZERO
+ *   k, n       PSF support (odd, <= KP_MAX_PSF, <= 2n-1; <= n for the
+ *              periodic boundary), image size
+ *   bc         KP_BC_ZERO or KP_BC_PERIODIC (other values:
+ *              KP_ERR_UNSUPPORTED)
  *   workspace  device buffer of >= kp_workspace_size(n, k, 0) bytes that
  *              the plan uses for all its device data (caller keeps
  *              ownership and must keep it alive until kp_destroy), or
@@ -221,7 +231,8 @@ int discrepancy_lambda(kp_plan_t plan, const float *b, const double *grid,
  * image sizes and PSF supports are allowed.  Each phase of an iteration is
  * one launch over the tiles of all items still iterating; each item stops
  * on its own (converged, maxit, breakdown).  infos[i] receives item i's
- * outcome, including its data misfit ||A x - b||.
+ * outcome, including its data misfit ||A x - b||.  Every plan must have
+ * the zero boundary (a KP_BC_PERIODIC plan: KP_ERR_UNSUPPORTED).
  *
  *   plans, nplans   array of plan handles and its length
  *   b, x            arrays of nitems device pointers (FP32 n_i x n_i, 16-byte
@@ -405,7 +416,8 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int *prev);
    (the table KP_EXACT_DIAG uses; built by kp_setup from all Kronecker terms
    with FP64 arithmetic, stored FP32) to the host array d0 (n*n, row-major:
    i indexes the column factor's singular vectors, j the row factor's).
-   Synchronises the device. */
+   Synchronises the device.  KP_ERR_UNSUPPORTED for a KP_BC_PERIODIC plan,
+   which has no D0; so is KP_EXACT_DIAG in pcg_solve and kp_precond. */
 int kp_get_diag(kp_plan_t plan, float *d0);
 
 /* Copy the FP64 singular values s_c, s_r (host arrays of n) and, if not

@@ -2,9 +2,11 @@
 //
 // The paper applies A and A^T through structured matvecs and names them the
 // most expensive part of an iteration (Section 5.2, work-unit model).  Here
-// they are zero-boundary 2-D correlations computed directly:
+// they are 2-D correlations computed directly:
 //     out[i][j] = sum_{a,b < K} Q[a][b] in[i + a - h][j + b - h]
-// with Q = P for A^T and Q = P rotated by 180 degrees for A.
+// with Q = P for A^T and Q = P rotated by 180 degrees for A, and the input
+// zero outside the image (KP_BC_ZERO) or extended periodically
+// (KP_BC_PERIODIC, indices taken mod n).
 //
 // Design (gfx950): one workgroup per TH x TW output tile stages the
 // (TH+K-1) x (TW+KQ) input halo tile in LDS with coalesced global loads and
@@ -22,12 +24,12 @@ template <int TX, int TY, int RX, int RY, int BC, typename In, typename Acc, typ
           class Epi>
 __global__ __launch_bounds__(TX* TY) void blur_kernel(
     const In* __restrict__ src, const Tap* __restrict__ taps, int n, int K, int KQ, int LDW,
-    Epi epi, Ctrl* ctrl, int skip_if_done, double* partials) {
+    Epi epi, Ctrl* ctrl, int skip_if_done, double* partials, int bc) {
   if (skip_if_done && ctrl->done != RUNNING) return;
   const int bid = blockIdx.y * gridDim.x + blockIdx.x;
   blur_tile<TX, TY, RX, RY, BC, In, Acc, Tap, Epi>(
       src, taps, n, K, KQ, LDW, blockIdx.y * (TY * RY), blockIdx.x * (TX * RX), epi,
-      partials + Epi::kSlot * MAX_PARTIALS + bid);
+      partials + Epi::kSlot * MAX_PARTIALS + bid, bc);
 }
 
 // ---------------------------------------------------------------------------
@@ -55,7 +57,7 @@ static hipError_t run_blur(const Plan& P, const In* src, const Tap* taps, Epi ep
     }
   }
   hipLaunchKernelGGL(kern, grid, dim3(TX * TY), lds, s, src, taps, n, K, KQ, ldw, epi, ctrl,
-                     skip, P.partials);
+                     skip, P.partials, P.bc);
   return hipGetLastError();
 }
 

@@ -171,6 +171,17 @@ struct EpiAnchorRes {
   }
 };
 
+// Source row or column of a staged tile entry.  The zero boundary keeps the
+// index (out-of-range entries are zero-filled by the caller); the periodic
+// boundary (KP_BC_PERIODIC) wraps it by one period, which covers every entry
+// that feeds an output inside the image (|index - [0, n)| <= h < n); entries
+// further out only feed the discarded outputs of edge tiles and are clamped.
+__device__ inline int bc_index(int g, int n, int bc) {
+  if (bc == 0) return g;
+  g = g < 0 ? g + n : (g >= n ? g - n : g);
+  return g < 0 ? 0 : (g >= n ? n - 1 : g);
+}
+
 // ---------------------------------------------------------------------------
 // the kernel
 // ---------------------------------------------------------------------------
@@ -178,7 +189,7 @@ template <int TX, int TY, int RX, int RY, int BC, typename In, typename Acc, typ
           class Epi>
 __device__ inline void blur_tile(const In* __restrict__ src, const Tap* __restrict__ taps,
                                  int n, int K, int KQ, int LDW, int ti0, int tj0, Epi epi,
-                                 double* partial_out) {
+                                 double* partial_out, int bc = 0) {
   constexpr int NT = TX * TY;
   constexpr int TW = TX * RX, TH = TY * RY;
   constexpr int WIN = RX + BC;   // RX + BC - 1 inputs used, one pad entry
@@ -190,7 +201,7 @@ __device__ inline void blur_tile(const In* __restrict__ src, const Tap* __restri
 
   for (int idx = threadIdx.x; idx < rows * LDW; idx += NT) {
     const int r = idx / LDW, c = idx - r * LDW;
-    const int gi = ti0 - h + r, gj = tj0 - h + c;
+    const int gi = bc_index(ti0 - h + r, n, bc), gj = bc_index(tj0 - h + c, n, bc);
     In v = In(0);
     if (c < cvalid && (unsigned)gi < (unsigned)n && (unsigned)gj < (unsigned)n)
       v = src[(size_t)gi * n + gj];

@@ -46,7 +46,7 @@ template <int NCH, class Epi>
 __device__ inline void blur_mfma_tile(const float* __restrict__ src,
                                       const mh8_t* __restrict__ bfrag, int n, int K, int exq,
                                       int i0, int j0, Epi epi, double* partial_out,
-                                      unsigned char* mb_lds) {
+                                      unsigned char* mb_lds, int bc = 0) {
   constexpr int W = mb_width(NCH), PITCH = mb_pitch(NCH), W2 = W / 2;
   constexpr int NU = 4 + 2 * (NCH - 1);       // distinct 16-column window offsets
   constexpr int PF = 2;                       // tap rows of fragments in flight
@@ -70,10 +70,11 @@ __device__ inline void blur_mfma_tile(const float* __restrict__ src,
     float a0 = 0.0f, a1 = 0.0f;
     if (idx < rows * W2) {
       const int r = idx / W2, c = 2 * (idx - r * W2);
-      const int gi = i0 - h + r, gj = j0 - h + c;
+      const int gi = bc_index(i0 - h + r, n, bc);
+      const int gj = bc_index(j0 - h + c, n, bc), gj1 = bc_index(j0 - h + c + 1, n, bc);
       if ((unsigned)gi < (unsigned)n) {
         if (c < cvalid && (unsigned)gj < (unsigned)n) a0 = src[(size_t)gi * n + gj];
-        if (c + 1 < cvalid && (unsigned)(gj + 1) < (unsigned)n) a1 = src[(size_t)gi * n + gj + 1];
+        if (c + 1 < cvalid && (unsigned)gj1 < (unsigned)n) a1 = src[(size_t)gi * n + gj1];
       }
     }
     v0[q] = a0;
@@ -329,7 +330,7 @@ template <int NC, class Epi>
 __device__ inline void blur_mfma32_tile(const float* __restrict__ src,
                                         const mh8_t* __restrict__ bfrag, int n, int K, int exq,
                                         int i0, int j0, Epi epi, double* partial_out,
-                                        unsigned char* mb_lds) {
+                                        unsigned char* mb_lds, int bc = 0) {
   constexpr int W = m32_width(NC), PITCH = m32_pitch(NC), W2 = W / 2;
   constexpr int NU = NC + 2;                  // A fragments: 16-column windows
   constexpr int NVP = ((MB_TM + 62) * W2 + MB_NT - 1) / MB_NT;   // K <= 63
@@ -349,10 +350,11 @@ __device__ inline void blur_mfma32_tile(const float* __restrict__ src,
     float a0 = 0.0f, a1 = 0.0f;
     if (idx < rows * W2) {
       const int r = idx / W2, c = 2 * (idx - r * W2);
-      const int gi = i0 - h + r, gj = j0 - h + c;
+      const int gi = bc_index(i0 - h + r, n, bc);
+      const int gj = bc_index(j0 - h + c, n, bc), gj1 = bc_index(j0 - h + c + 1, n, bc);
       if ((unsigned)gi < (unsigned)n) {
         if (c < cvalid && (unsigned)gj < (unsigned)n) a0 = src[(size_t)gi * n + gj];
-        if (c + 1 < cvalid && (unsigned)(gj + 1) < (unsigned)n) a1 = src[(size_t)gi * n + gj + 1];
+        if (c + 1 < cvalid && (unsigned)gj1 < (unsigned)n) a1 = src[(size_t)gi * n + gj1];
       }
     }
     v0[q] = a0;

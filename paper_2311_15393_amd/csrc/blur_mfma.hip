@@ -96,13 +96,13 @@ __global__ __launch_bounds__(MB_NT) void blur_mfma32_kernel(const float* __restr
                                                             const mh8_t* __restrict__ bfrag,
                                                             int n, int K, int exq, Epi epi,
                                                             Ctrl* ctrl, int skip_if_done,
-                                                            double* partials) {
+                                                            double* partials, int bc) {
   extern __shared__ __align__(16) unsigned char mb_lds[];
   if (skip_if_done && ctrl->done != RUNNING) return;
   blur_mfma32_tile<NC, Epi>(src, bfrag, n, K, exq, blockIdx.y * MB_TM, blockIdx.x * MB_TN, epi,
                             partials + Epi::kSlot * MAX_PARTIALS + blockIdx.y * gridDim.x +
                                 blockIdx.x,
-                            mb_lds);
+                            mb_lds, bc);
 }
 
 size_t mfma32_taps_count(int K) { return (size_t)K * m32_nch(K) * 2 * 64; }
@@ -112,13 +112,13 @@ __global__ __launch_bounds__(MB_NT) void blur_mfma_kernel(const float* __restric
                                                           const mh8_t* __restrict__ bfrag,
                                                           int n, int K, int exq, Epi epi,
                                                           Ctrl* ctrl, int skip_if_done,
-                                                          double* partials) {
+                                                          double* partials, int bc) {
   extern __shared__ __align__(16) unsigned char mb_lds[];
   if (skip_if_done && ctrl->done != RUNNING) return;
   blur_mfma_tile<NCH, Epi>(src, bfrag, n, K, exq, blockIdx.y * MB_TM, blockIdx.x * MB_TN, epi,
                            partials + Epi::kSlot * MAX_PARTIALS + blockIdx.y * gridDim.x +
                                blockIdx.x,
-                           mb_lds);
+                           mb_lds, bc);
 }
 
 int mfma_nch(int K) { return (K + 15 + 31) / 32; }
@@ -170,7 +170,7 @@ static hipError_t run_mfma(const Plan& P, const float* src, const mh8_t* tab, Ep
     }
   }
   hipLaunchKernelGGL(kern, grid, dim3(MB_NT), lds, s, src, tab, n, P.k, P.mfma_exq, epi, ctrl,
-                     skip, P.partials);
+                     skip, P.partials, P.bc);
   return hipGetLastError();
 }
 
@@ -207,7 +207,7 @@ static hipError_t run_mfma32(const Plan& P, const float* src, const mh8_t* tab, 
     }
   }
   hipLaunchKernelGGL(kern, grid, dim3(MB_NT), lds, s, src, tab, n, P.k, P.mfma_exq, epi, ctrl,
-                     skip, P.partials);
+                     skip, P.partials, P.bc);
   return hipGetLastError();
 }
 

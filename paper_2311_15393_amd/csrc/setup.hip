@@ -25,21 +25,28 @@
 
 namespace kpcg {
 
+// Frobenius weight of PSF offset k - h in one factor: ||Z_d||_F^2 = n - |d|
+// for the zero boundary's shift matrices, ||C_d||_F^2 = n for the periodic
+// boundary's cyclic shifts (so its optimal term is the plain PSF SVD).
+__device__ inline double psf_weight(int k, int h, int n, int bc) {
+  return bc == KP_BC_PERIODIC ? (double)n : (double)(n - abs(k - h));
+}
+
 // Weighted PSF, column-major K x K for the solver.
-__global__ void weighted_psf_kernel(const double* __restrict__ psf, int K, int n,
+__global__ void weighted_psf_kernel(const double* __restrict__ psf, int K, int n, int bc,
                                     double* __restrict__ pw) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= K * K) return;
   const int k = idx / K, l = idx - k * K;          // psf[k][l] row-major
   const int h = (K - 1) / 2;
-  const double wk = (double)(n - abs(k - h)), wl = (double)(n - abs(l - h));
+  const double wk = psf_weight(k, h, n, bc), wl = psf_weight(l, h, n, bc);
   pw[k + (size_t)l * K] = sqrt(wk * wl) * psf[idx];
 }
 
 // Profiles c (column factor) and a (row factor) from the leading singular
 // triple; sign fixed so that sum(c) > 0.  One block.
 __global__ void profiles_kernel(const double* __restrict__ S, const double* __restrict__ U,
-                                const double* __restrict__ Vt, int K, int n,
+                                const double* __restrict__ Vt, int K, int n, int bc,
                                 double* __restrict__ c, double* __restrict__ a) {
   __shared__ double red[64];
   const int h = (K - 1) / 2;
@@ -56,7 +63,7 @@ __global__ void profiles_kernel(const double* __restrict__ S, const double* __re
   __syncthreads();
   const double sg = red[0] < 0.0 ? -1.0 : 1.0;
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    const double w = sqrt((double)(n - abs(k - h)));
+    const double w = sqrt(psf_weight(k, h, n, bc));
     c[k] = sg * s1 * U[k] / w;                      // U(k, 0)
     a[k] = sg * s1 * Vt[(size_t)k * K] / w;         // Vt(0, k)
   }
@@ -163,13 +170,20 @@ __global__ void to_f32_kernel(const double* __restrict__ src, int n, float* __re
   dst_t[j * n + i] = v;
 }
 
-// Column-major banded Toeplitz T(f)[i][i'] = f[h + i - i'].
-__global__ void toeplitz_kernel(const double* __restrict__ f, int K, int n,
+// Column-major factor from a profile: the banded Toeplitz T(f)[i][i'] =
+// f[h + i - i'] (zero boundary), or the circulant C(f)[i][i'] = f[h + d]
+// with d = i - i' mod n taken in [-h, h] (periodic boundary, K <= n).
+__global__ void toeplitz_kernel(const double* __restrict__ f, int K, int n, int bc,
                                 double* __restrict__ t) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)n * n) return;
   const int i = (int)(idx % n), ip = (int)(idx / n);   // t[i + ip*n]
-  const int h = (K - 1) / 2, d = i - ip;
+  const int h = (K - 1) / 2;
+  int d = i - ip;
+  if (bc == KP_BC_PERIODIC) {
+    if (d > h) d -= n;
+    else if (d < -h) d += n;
+  }
   t[idx] = (d >= -h && d <= h) ? f[h + d] : 0.0;
 }
 
@@ -355,7 +369,7 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
 
   // weighted PSF SVD
   hipLaunchKernelGGL(weighted_psf_kernel, dim3((K * K + 255) / 256), dim3(256), 0, s, dpsf, K,
-                     n, pw);
+                     n, P.bc, pw);
   HCHK(hipGetLastError());
   SCHK(rocsolver_dgesvd(handle, rocblas_svect_all, rocblas_svect_all, K, K, pw, K, spsf, upsf,
                         K, vpsf, K, e, rocblas_outofplace, info));
@@ -363,8 +377,8 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
   HCHK(hipMemcpyAsync(hs.data(), spsf, sizeof(double) * K, hipMemcpyDeviceToHost, s));
   HCHK(hipStreamSynchronize(s));
   if (hinfo != 0) { rc = KP_ERR_SOLVER; goto done; }
-  hipLaunchKernelGGL(profiles_kernel, dim3(1), dim3(64), 0, s, spsf, upsf, vpsf, K, n, prof,
-                     prof + K);
+  hipLaunchKernelGGL(profiles_kernel, dim3(1), dim3(64), 0, s, spsf, upsf, vpsf, K, n, P.bc,
+                     prof, prof + K);
   HCHK(hipGetLastError());
 
   {
@@ -390,7 +404,8 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
     for (int i = 0; i < K; ++i)
       if (hs[i] > 1e-12 * hs[0]) ++t;
     P.terms = t;
-    tall = t;
+    // the exact diagonal D0 is built for the zero boundary only
+    tall = P.bc == KP_BC_ZERO ? t : 0;
   }
   // every term's profiles, and room for the per-factor Gram matrices of the
   // exact diagonal D0 = diag(V^T A^T A V) (built below)
@@ -411,7 +426,7 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
   for (int f = 0; f < 2; ++f) {
     const double* prof_f = prof + f * K;
     double* sig = f == 0 ? P.sc : P.sr;
-    hipLaunchKernelGGL(toeplitz_kernel, dim3(gnn), dim3(nthr), 0, s, prof_f, K, n, T);
+    hipLaunchKernelGGL(toeplitz_kernel, dim3(gnn), dim3(nthr), 0, s, prof_f, K, n, P.bc, T);
     HCHK(hipGetLastError());
     if (symmetric[f]) {
       SCHK(rocsolver_dsyevd(handle, rocblas_evect_original, rocblas_fill_upper, n, T, n, wv, e,

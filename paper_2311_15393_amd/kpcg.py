@@ -26,6 +26,8 @@ KP_BATCH_EAGER = 0x200
 KP_NO_FALLBACK = 0x400
 KP_EXACT_DIAG = 0x800
 KP_MAX_PSF = 63
+KP_BC_ZERO = 0
+KP_BC_PERIODIC = 1
 KP_BLUR_MFMA = 6
 KP_BLUR_MFMA32 = 7
 KP_MLP_NFEAT, KP_MLP_HIDDEN, KP_MLP_NPARAM = 128, 256, 164865
@@ -183,6 +185,7 @@ class Plan:
         if psf.ndim != 2 or psf.shape[0] != psf.shape[1]:
             raise ValueError("psf must be a square 2-D array")
         self.n, self.k = int(n), int(psf.shape[0])
+        self.bc = int(bc)
         self._ws = workspace
         wptr, wbytes = None, 0
         if workspace is not None:

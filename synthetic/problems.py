@@ -170,12 +170,20 @@ def _blur_for_data(psf: np.ndarray, x: np.ndarray) -> np.ndarray:
     return scipy.signal.fftconvolve(x, psf, mode="same")
 
 
+def _blur_for_data_periodic(psf: np.ndarray, x: np.ndarray) -> np.ndarray:
+    # the image extended periodically by h on every side, then the 'valid'
+    # part of the linear convolution: the periodic convolution centred at
+    # (h, h)
+    h = (psf.shape[0] - 1) // 2
+    return scipy.signal.fftconvolve(np.pad(x, h, mode="wrap"), psf, mode="valid")
+
+
 def make_problem(n: int, psf: np.ndarray, rng: np.random.Generator,
                  noise_level: float, lam: float | None, seed: int, kind: str,
-                 x_true: np.ndarray | None = None) -> Problem:
+                 x_true: np.ndarray | None = None, periodic: bool = False) -> Problem:
     if x_true is None:
         x_true = true_image(rng, n)
-    b_true = _blur_for_data(psf, x_true)
+    b_true = (_blur_for_data_periodic if periodic else _blur_for_data)(psf, x_true)
     g = rng.standard_normal((n, n))
     eps = noise_level * np.linalg.norm(b_true) * g / np.linalg.norm(g)
     b32 = (b_true + eps).astype(np.float32)
@@ -213,6 +221,20 @@ def large_moffat(seed: int = 0, n: int = 1024, k: int = 63) -> Problem:
     angle = rng.uniform(0.0, math.pi)
     psf = psf_moffat_motion(k, alpha, 2.5, length, angle)
     return make_problem(n, psf, rng, 0.02, None, seed, "moffat63", x_true=x)
+
+
+def large_moffat_periodic(seed: int = 0, n: int = 1024, k: int = 63) -> Problem:
+    """The large Moffat + motion workload of large_moffat (same seed, image
+    and PSF draws) with periodic data: b = A x_true + e where A extends the
+    image periodically (K <= n)."""
+    rng = np.random.default_rng(seed)
+    x = true_image(rng, n)
+    alpha = rng.uniform(3.0, 8.0)
+    length = rng.uniform(3.0, 9.0)
+    angle = rng.uniform(0.0, math.pi)
+    psf = psf_moffat_motion(k, alpha, 2.5, length, angle)
+    return make_problem(n, psf, rng, 0.02, None, seed, "moffat63-periodic", x_true=x,
+                        periodic=True)
 
 
 BATCH_SIZES = (128, 256, 384, 512, 768, 1024)

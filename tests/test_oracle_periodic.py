@@ -139,3 +139,18 @@ def test_oracle_pcg_converges_to_closed_form():
 def test_large_psf_rejected():
     with pytest.raises(ValueError):
         PB.blur(np.ones((9, 9)), np.zeros((8, 8)))
+
+
+def test_periodic_data_generator_matches_oracle_blur():
+    """The synthetic periodic workload's data model (wrap padding + the
+    'valid' linear convolution) is the oracle's periodic A."""
+    import synthetic as S
+    from synthetic.problems import _blur_for_data_periodic
+    rng = np.random.default_rng(11)
+    for n, k in ((40, 9), (33, 15), (15, 15)):
+        psf = rng.standard_normal((k, k))
+        x = rng.standard_normal((n, n))
+        assert np.abs(_blur_for_data_periodic(psf, x) - PB.blur(psf, x)).max() < 1e-10
+    p = S.large_moffat_periodic(0, n=96, k=15)
+    noise = p.b.astype(np.float64) - PB.blur(p.psf, p.x_true)
+    assert abs(np.linalg.norm(noise) - p.noise_norm) < 1e-9 * p.noise_norm
