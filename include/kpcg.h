@@ -46,9 +46,8 @@ extern "C" {
 #define KP_ERR_ARG         -1   /* null pointer, n < 1, K even, K > 2n-1,
                                    lambda <= 0, tol <= 0, maxit < 1, a
                                    non-finite argument, bad mode bits      */
-#define KP_ERR_UNSUPPORTED -2   /* unknown boundary condition, K above
-                                   KP_MAX_PSF, or a mode the plan's
-                                   boundary does not support              */
+#define KP_ERR_UNSUPPORTED -2   /* unknown boundary condition, or K above
+                                   KP_MAX_PSF                              */
 #define KP_ERR_HIP         -3   /* a HIP runtime call failed               */
 #define KP_ERR_SOLVER      -4   /* the FP64 factor SVD (rocSOLVER) failed  */
 #define KP_ERR_WORKSPACE   -5   /* caller workspace smaller than required  */
@@ -57,8 +56,7 @@ extern "C" {
 #define KP_BC_ZERO      0       /* image zero outside [0, n)^2 (BTTB A)     */
 #define KP_BC_PERIODIC  1       /* image extended periodically (BCCB A,
                                    K <= n); one-term KP with circulant
-                                   factors; no KP_EXACT_DIAG, no batched
-                                   solves                                  */
+                                   factors                                 */
 
 /* ---- mode bits for pcg_solve / pcg_solve_batched --------------------- */
 #define KP_CG        0x000      /* no preconditioner                        */
@@ -231,8 +229,8 @@ int discrepancy_lambda(kp_plan_t plan, const float *b, const double *grid,
  * image sizes and PSF supports are allowed.  Each phase of an iteration is
  * one launch over the tiles of all items still iterating; each item stops
  * on its own (converged, maxit, breakdown).  infos[i] receives item i's
- * outcome, including its data misfit ||A x - b||.  Every plan must have
- * the zero boundary (a KP_BC_PERIODIC plan: KP_ERR_UNSUPPORTED).
+ * outcome, including its data misfit ||A x - b||.  Plans of both
+ * boundary conditions may be mixed.
  *
  *   plans, nplans   array of plan handles and its length
  *   b, x            arrays of nitems device pointers (FP32 n_i x n_i, 16-byte
@@ -416,8 +414,9 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int *prev);
    (the table KP_EXACT_DIAG uses; built by kp_setup from all Kronecker terms
    with FP64 arithmetic, stored FP32) to the host array d0 (n*n, row-major:
    i indexes the column factor's singular vectors, j the row factor's).
-   Synchronises the device.  KP_ERR_UNSUPPORTED for a KP_BC_PERIODIC plan,
-   which has no D0; so is KP_EXACT_DIAG in pcg_solve and kp_precond. */
+   Synchronises the device.  For a KP_BC_PERIODIC plan D0 comes from the
+   circulant terms; its singular vectors are unique only up to rotations
+   within pairs of equal singular values, and D0 is that of the stored V. */
 int kp_get_diag(kp_plan_t plan, float *d0);
 
 /* Copy the FP64 singular values s_c, s_r (host arrays of n) and, if not

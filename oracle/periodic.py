@@ -50,7 +50,10 @@ exact for separable PSFs, equals the brute-force Van Loan-Pitsianis nearest
 Kronecker product on tiny images, and its error matches the singular-value
 formula; the circulant factors' singular values are |DFT| of their columns;
 the closed-form x_lambda equals a dense Cholesky solve; the oracle's PCG
-converges to it.
+converges to it; the exact KP-basis diagonal (exact_diag, the circulant
+form of kp.exact_diag) equals ||A (v_c,i v_r,j^T)||_F^2 from blurring every
+basis image, reduces to s_c^2 s_r^2 for separable PSFs and sums to
+||A||_F^2 = n^2 ||P||_F^2.
 """
 from __future__ import annotations
 
@@ -167,6 +170,29 @@ def kp_svd(psf: np.ndarray, n: int) -> kpmod.KPSVD:
     ur, sr, vrt = np.linalg.svd(ar)
     return kpmod.KPSVD(n=n, Ac=ac, Ar=ar, Uc=uc, sc=sc, Vc=vct.T, Ur=ur, sr=sr,
                        Vr=vrt.T, s_psf=s)
+
+
+def kp_all_terms(psf: np.ndarray, rel: float = 1e-12):
+    """All terms of the exact expansion A = sum_k C(a_k) (x) C(c_k) from the
+    plain SVD of P (c_k = sqrt(s_k) u_k, a_k = sqrt(s_k) v_k, s_k > rel s_1)."""
+    u, s, vt = np.linalg.svd(np.asarray(psf, dtype=np.float64))
+    t = kpmod.kp_terms(s, rel)
+    return ([np.sqrt(s[i]) * u[:, i] for i in range(t)],
+            [np.sqrt(s[i]) * vt[i, :] for i in range(t)])
+
+
+def exact_diag(kp: kpmod.KPSVD, psf: np.ndarray, rel: float = 1e-12) -> np.ndarray:
+    """D0[i, j] = ||A (v_c,i v_r,j^T)||_F^2 for the periodic A, through its
+    Kronecker sum as in kp.exact_diag with circulant factors."""
+    n = kp.n
+    cs, as_ = kp_all_terms(psf, rel)
+    B = [circulant_band(c, n) @ kp.Vc for c in cs]
+    C = [circulant_band(a, n) @ kp.Vr for a in as_]
+    d0 = np.zeros((n, n))
+    for k in range(len(cs)):
+        for l in range(len(cs)):
+            d0 += np.outer(np.sum(B[k] * B[l], axis=0), np.sum(C[k] * C[l], axis=0))
+    return d0
 
 
 class NormalOperator:

@@ -51,6 +51,7 @@ struct ItemDesc {
   int use_mfma, nch, exq, ntx_mfma, nb_fast;
   const void* mfma_taps;                     // table for taps32, then for taps32_flip
   size_t mfma_count;                         // entries per orientation
+  int bc;                                    // the plan's boundary (KP_BC_ZERO / KP_BC_PERIODIC)
 };
 
 struct TileRef {
@@ -121,11 +122,11 @@ __global__ __launch_bounds__(TX* TY) void blur_batched_kernel(const ItemDesc* __
     if constexpr (KIND == BK_TRUE1) {
       EpiResid e{it.b, it.q, it.y64, n};
       blur_tile<TX, TY, RX, RY, BC, double, double, double, EpiResid>(
-          it.x64, it.taps64_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, out);
+          it.x64, it.taps64_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, out, it.bc);
     } else {
       EpiTrueRes e{it.x64, it.r, it.lam2, n, it.xa64, it.ra64};
       blur_tile<TX, TY, RX, RY, BC, double, double, double, EpiTrueRes>(
-          it.y64, it.taps64, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, out);
+          it.y64, it.taps64, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, out, it.bc);
     }
   } else {
     const int ty = tr.t / it.ntx_blur, tx = tr.t - ty * it.ntx_blur;
@@ -133,40 +134,40 @@ __global__ __launch_bounds__(TX* TY) void blur_batched_kernel(const ItemDesc* __
     if constexpr (KIND == BK_A) {
       EpiStoreF32 e{it.q, n};
       blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiStoreF32>(
-          it.p, it.taps32_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, nullptr);
+          it.p, it.taps32_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, nullptr, it.bc);
     } else if constexpr (KIND == BK_AT_NORMAL) {
       EpiNormalW e{it.p, it.w, it.lam2f, n};
       blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiNormalW>(
           it.q, it.taps32, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
-          it.partials + SLOT_DELTA * MAXP_ITEM + tr.t);
+          it.partials + SLOT_DELTA * MAXP_ITEM + tr.t, it.bc);
     } else if constexpr (KIND == BK_ANC1) {
       EpiStoreF32 e{it.z, n};
       blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiStoreF32>(
-          it.q, it.taps32_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, nullptr);
+          it.q, it.taps32_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, nullptr, it.bc);
     } else if constexpr (KIND == BK_ANC2) {
       EpiAnchorRes e{it.x64, it.xa64, it.ra64, it.r, it.lam2, n};
       blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiAnchorRes>(
           it.z, it.taps32, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
-          it.partials + SLOT_TRUE * MAXP_ITEM + tr.t);
+          it.partials + SLOT_TRUE * MAXP_ITEM + tr.t, it.bc);
     } else if constexpr (KIND == BK_TRUE1F) {
       EpiResid e{it.b, it.q, nullptr, n};
       blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiResid>(
-          it.z, it.taps32_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, nullptr);
+          it.z, it.taps32_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e, nullptr, it.bc);
     } else if constexpr (KIND == BK_TRUE2F) {
       EpiTrueRes e{it.x64, it.r, it.lam2, n, it.xa64, it.ra64};
       blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiTrueRes>(
           it.q, it.taps32, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
-          it.partials + SLOT_TRUE * MAXP_ITEM + tr.t);
+          it.partials + SLOT_TRUE * MAXP_ITEM + tr.t, it.bc);
     } else if constexpr (KIND == BK_RHS) {
       EpiRhs e{it.r, n};
       blur_tile<TX, TY, RX, RY, BC, float, float, float, EpiRhs>(
           it.b, it.taps32, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
-          it.partials + SLOT_RHS * MAXP_ITEM + tr.t);
+          it.partials + SLOT_RHS * MAXP_ITEM + tr.t, it.bc);
     } else {
       EpiMisfit e{it.b, n};
       blur_tile<TX, TY, RX, RY, BC, float, double, double, EpiMisfit>(
           it.x, it.taps64_flip, n, it.k, it.kq, ldw, ty * TH, tx * TW, e,
-          it.partials + SLOT_NORM * MAXP_ITEM + tr.t);
+          it.partials + SLOT_NORM * MAXP_ITEM + tr.t, it.bc);
     }
   }
 }
@@ -186,25 +187,25 @@ __global__ __launch_bounds__(MB_NT) void blur_mfma_batched_kernel(
   const int i0 = ty * MB_TM, j0 = tx * MB_TN;
   if constexpr (KIND == BK_A) {
     blur_mfma_tile<NCH>(it.p, tabA, n, it.k, it.exq, i0, j0, EpiStoreF32{it.q, n}, nullptr,
-                        mb_lds);
+                        mb_lds, it.bc);
   } else if constexpr (KIND == BK_AT_NORMAL) {
     blur_mfma_tile<NCH>(it.q, tabT, n, it.k, it.exq, i0, j0,
                         EpiNormalW{it.p, it.w, it.lam2f, n},
-                        it.partials + SLOT_DELTA * MAXP_ITEM + tr.t, mb_lds);
+                        it.partials + SLOT_DELTA * MAXP_ITEM + tr.t, mb_lds, it.bc);
   } else if constexpr (KIND == BK_ANC1) {
     blur_mfma_tile<NCH>(it.q, tabA, n, it.k, it.exq, i0, j0, EpiStoreF32{it.z, n}, nullptr,
-                        mb_lds);
+                        mb_lds, it.bc);
   } else if constexpr (KIND == BK_TRUE1F) {
     blur_mfma_tile<NCH>(it.z, tabA, n, it.k, it.exq, i0, j0, EpiResid{it.b, it.q, nullptr, n},
-                        nullptr, mb_lds);
+                        nullptr, mb_lds, it.bc);
   } else if constexpr (KIND == BK_TRUE2F) {
     blur_mfma_tile<NCH>(it.q, tabT, n, it.k, it.exq, i0, j0,
                         EpiTrueRes{it.x64, it.r, it.lam2, n, it.xa64, it.ra64},
-                        it.partials + SLOT_TRUE * MAXP_ITEM + tr.t, mb_lds);
+                        it.partials + SLOT_TRUE * MAXP_ITEM + tr.t, mb_lds, it.bc);
   } else {
     blur_mfma_tile<NCH>(it.z, tabT, n, it.k, it.exq, i0, j0,
                         EpiAnchorRes{it.x64, it.xa64, it.ra64, it.r, it.lam2, n},
-                        it.partials + SLOT_TRUE * MAXP_ITEM + tr.t, mb_lds);
+                        it.partials + SLOT_TRUE * MAXP_ITEM + tr.t, mb_lds, it.bc);
   }
 }
 
@@ -730,6 +731,7 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
     d.exq = P.mfma_exq;
     d.mfma_taps = P.mfma_taps;
     d.mfma_count = mfma_taps_count(P.k);
+    d.bc = P.bc;
     d.ntx_mfma = (n + MB_TN - 1) / MB_TN;
     if (d.use_mfma) {
       const int fg = NUM_BLUR_CFG + d.nch - 1;

@@ -331,7 +331,6 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   if (!aligned16(b) || !aligned16(x)) return KP_ERR_ARG;
   if (solver != KP_CG && prec == KP_P8 && !fp8_supported_size(plan->P.n))
     return KP_ERR_UNSUPPORTED;
-  if ((mode & KP_EXACT_DIAG) && plan->P.bc != KP_BC_ZERO) return KP_ERR_UNSUPPORTED;
   Plan& P = plan->P;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t N = (size_t)P.n * P.n;
@@ -554,7 +553,6 @@ int pcg_solve_batched(const kp_plan_t* plans, int nplans, const float* const* b,
   for (int i = 0; i < nplans; ++i) {
     if (!plans[i]) return KP_ERR_ARG;
     ps[i] = &plans[i]->P;
-    if (ps[i]->bc != KP_BC_ZERO) return KP_ERR_UNSUPPORTED;
   }
   for (int i = 0; i < nitems; ++i) {
     if (plan_of_item[i] < 0 || plan_of_item[i] >= nplans) return KP_ERR_ARG;
@@ -666,7 +664,6 @@ int kp_precond(kp_plan_t plan, const float* r, double lambda, int mode, float* z
   const int prec = mode & KP_PREC_MASK;
   if (prec == KP_PREC_MASK) return KP_ERR_ARG;
   if (prec == KP_P8 && !fp8_supported_size(plan->P.n)) return KP_ERR_UNSUPPORTED;
-  if ((mode & KP_EXACT_DIAG) && plan->P.bc != KP_BC_ZERO) return KP_ERR_UNSUPPORTED;
   if (!aligned16(r) || !aligned16(z)) return KP_ERR_ARG;
   Plan& P = plan->P;
   P.sprime_d0 = (mode & KP_EXACT_DIAG) ? P.d0 : nullptr;
@@ -712,7 +709,6 @@ int kp_time_precond(kp_plan_t plan, const float* r, double lambda, int mode, flo
   const int prec = mode & KP_PREC_MASK;
   if (prec == KP_PREC_MASK) return KP_ERR_ARG;
   if (prec == KP_P8 && !fp8_supported_size(plan->P.n)) return KP_ERR_UNSUPPORTED;
-  if ((mode & KP_EXACT_DIAG) && plan->P.bc != KP_BC_ZERO) return KP_ERR_UNSUPPORTED;
   Plan& P = plan->P;
   P.sprime_d0 = (mode & KP_EXACT_DIAG) ? P.d0 : nullptr;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -751,7 +747,6 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int* prev) {
 int kp_get_diag(kp_plan_t plan, float* d0) {
   if (!plan || !d0) return KP_ERR_ARG;
   Plan& P = plan->P;
-  if (P.bc != KP_BC_ZERO) return KP_ERR_UNSUPPORTED;
   HIPCHK(hipDeviceSynchronize());
   HIPCHK(hipMemcpy(d0, P.d0, sizeof(float) * P.n * P.n, hipMemcpyDeviceToHost));
   return KP_OK;

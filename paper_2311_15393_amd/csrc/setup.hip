@@ -75,12 +75,12 @@ __global__ void profiles_kernel(const double* __restrict__ S, const double* __re
 // so that P = sum_k c_k a_k^T.  The sign of a pair (c_k, a_k) is immaterial
 // for the diagonal built from them.
 __global__ void all_profiles_kernel(const double* __restrict__ S, const double* __restrict__ U,
-                                    const double* __restrict__ Vt, int K, int n, int t,
+                                    const double* __restrict__ Vt, int K, int n, int bc, int t,
                                     double* __restrict__ prof) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= t * K) return;
   const int k = idx / K, d = idx - k * K, h = (K - 1) / 2;
-  const double g = sqrt(S[k]) / sqrt((double)(n - abs(d - h)));
+  const double g = sqrt(S[k]) / sqrt(psf_weight(d, h, n, bc));
   prof[idx] = g * U[d + (size_t)k * K];                  // U(d, k)
   prof[t * K + idx] = g * Vt[k + (size_t)d * K];         // Vt(k, d) = V(d, k)
 }
@@ -88,7 +88,8 @@ __global__ void all_profiles_kernel(const double* __restrict__ S, const double* 
 // Per column a of one factor's V (row-major n x n, FP64): the Gram matrix of
 // y_k = T(f_k) V(:, a) over the t profiles f_k of that factor,
 //     G[k * t + l][a] = sum_i y_k[i] y_l[i],
-// with (T(f) v)[i] = sum_d f[d] v[i + h - d] (zero outside [0, n)).  One
+// with (T(f) v)[i] = sum_d f[d] v[i + h - d] (zero outside [0, n); for the
+// periodic boundary the circulant C(f), v indexed mod n).  One
 // block per column; the column (zero padded by h on both sides) and the
 // profiles sit in LDS, y is formed GRAM_CH rows at a time, and each thread
 // accumulates up to GRAM_PAIRS of the t (t + 1) / 2 pairs k <= l in FP64.
@@ -102,7 +103,8 @@ size_t gram_lds_bytes(int t, int K, int n) {
 
 __global__ __launch_bounds__(GRAM_NT) void gram_kernel(const double* __restrict__ V,
                                                        const double* __restrict__ prof, int t,
-                                                       int K, int n, double* __restrict__ G) {
+                                                       int K, int n, int bc,
+                                                       double* __restrict__ G) {
   extern __shared__ double gsm[];
   double* sp = gsm;                               // [t][K]
   double* sv = sp + t * K;                        // [n + K - 1]: sv[m] = v[m - h]
@@ -110,7 +112,8 @@ __global__ __launch_bounds__(GRAM_NT) void gram_kernel(const double* __restrict_
   const int a = blockIdx.x, tid = threadIdx.x, h = (K - 1) / 2;
   for (int i = tid; i < t * K; i += GRAM_NT) sp[i] = prof[i];
   for (int m = tid; m < n + K - 1; m += GRAM_NT) {
-    const int i = m - h;
+    int i = m - h;
+    if (bc == KP_BC_PERIODIC) i = i < 0 ? i + n : (i >= n ? i - n : i);   // h < n
     sv[m] = (i >= 0 && i < n) ? V[(size_t)i * n + a] : 0.0;
   }
   // this thread's pairs p = tid + GRAM_NT q in the order (0,0), (0,1), ...
@@ -404,8 +407,7 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
     for (int i = 0; i < K; ++i)
       if (hs[i] > 1e-12 * hs[0]) ++t;
     P.terms = t;
-    // the exact diagonal D0 is built for the zero boundary only
-    tall = P.bc == KP_BC_ZERO ? t : 0;
+    tall = t;
   }
   // every term's profiles, and room for the per-factor Gram matrices of the
   // exact diagonal D0 = diag(V^T A^T A V) (built below)
@@ -414,7 +416,7 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
     HCHK(hipMalloc(&G2, sizeof(double) * 2 * (size_t)tall * tall * n));
     HCHK(hipMalloc(&D64, sizeof(double) * nn));
     hipLaunchKernelGGL(all_profiles_kernel, dim3((tall * K + 255) / 256), dim3(256), 0, s, spsf,
-                       upsf, vpsf, K, n, tall, pall);
+                       upsf, vpsf, K, n, P.bc, tall, pall);
     HCHK(hipGetLastError());
     glds = gram_lds_bytes(tall, K, n);
     if (glds > 65536)
@@ -446,7 +448,7 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
       // Gram matrices of T(f_k) V(:, a) over this factor's profiles (Vt holds
       // V row-major here)
       hipLaunchKernelGGL(gram_kernel, dim3(n), dim3(GRAM_NT), glds, s, Vt, pall + f * tall * K,
-                         tall, K, n, G2 + (size_t)f * tall * tall * n);
+                         tall, K, n, P.bc, G2 + (size_t)f * tall * tall * n);
       HCHK(hipGetLastError());
     }
     if (f == 0) {

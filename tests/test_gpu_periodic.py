@@ -165,28 +165,72 @@ def test_periodic_full_size_fp16():
     assert info.status == KP_OK and err <= 1e-4
 
 
+def test_periodic_exact_diag_matches_oracle():
+    """kp_setup's exact KP-basis diagonal for a periodic plan against the
+    oracle's circulant form.  A real circulant's singular vectors are not
+    unique within its pairs of equal singular values, so the oracle's D0 is
+    formed in the device's own basis (its FP32 V): FP32 rounding of V and of
+    D0 bound the difference by 1e-6 relative plus 1e-9 max(D0)."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_BC_PERIODIC, Plan
+    for n, k, kind in ((64, 15, "moffat"), (100, 9, "rand"), (128, 63, "moffat")):
+        psf = _psf(kind, k, 21)
+        kp = PB.kp_svd(psf, n)
+        with Plan(psf, n, bc=KP_BC_PERIODIC) as plan:
+            got = plan.exact_diag().astype(np.float64)
+            sc, sr, vc, vr = plan.factors()
+        kp.Vc, kp.Vr = vc.astype(np.float64), vr.astype(np.float64)
+        ref = PB.exact_diag(kp, psf)
+        err = np.abs(got - ref)
+        say(f"periodic exact diagonal n={n} k={k}: max err / max {err.max() / ref.max():.2e}")
+        assert np.all(err <= 1e-6 * np.abs(ref) + 1e-9 * ref.max())
+
+
+def test_periodic_exact_diag_solve_and_batch():
+    """A periodic solve with KP_EXACT_DIAG reaches the DFT closed form, and a
+    batch mixing periodic and zero-boundary plans (FP16-KP FPCG, one-term
+    and exact-diagonal S) reaches every item's own x_lambda to 1e-4."""
+    require_gpu()
+    from paper_2311_15393_amd import (KP_BC_PERIODIC, KP_EXACT_DIAG, KP_FPCG, KP_OK, KP_P16, Plan,
+                                      solve_batched)
+    from oracle import solvers as SV
+    pa, _, ba = _problem(128, 15, "moffat", 4)
+    pb, _, bb = _problem(200, 31, "gauss", 5)
+    pz = S.mid_anisotropic(1, n=128)
+    plans = [Plan(pa, 128, bc=KP_BC_PERIODIC), Plan(pb, 200, bc=KP_BC_PERIODIC),
+             Plan(pz.psf, 128)]
+    x, info = plans[0].solve(to_dev(ba), 0.01, tol=1e-7, maxit=500,
+                             mode=KP_FPCG | KP_P16 | KP_EXACT_DIAG)
+    err = rel(to_host(x), PB.x_lambda(pa, ba.astype(np.float64), 0.01))
+    say(f"periodic exact-diag solve: iters={info.iters} err={err:.2e}")
+    assert info.status == KP_OK and err <= 1e-4
+    items = [(0, 0.01), (0, 0.003), (1, 0.02), (2, 0.01)]
+    bs = [to_dev([ba, bb, pz.b][p]) for p, _ in items]
+    refs = [PB.x_lambda(pa, ba.astype(np.float64), lam) if p == 0 else
+            PB.x_lambda(pb, bb.astype(np.float64), lam) if p == 1 else
+            SV.x_lambda(pz.psf, pz.b.astype(np.float64), lam) for p, lam in items]
+    for extra in (0, KP_EXACT_DIAG):
+        xs, infos, st = solve_batched(plans, bs, [l for _, l in items], [p for p, _ in items],
+                                      tol=1e-8, maxit=2000, mode=KP_FPCG | KP_P16 | extra)
+        for (p, lam), xd, inf, ref in zip(items, xs, infos, refs):
+            e = rel(to_host(xd), ref)
+            say(f"  batch{'+diag' if extra else ''} plan {p} lam={lam}: iters={inf.iters} "
+                f"err={e:.2e}")
+            assert inf.status == KP_OK and e <= 1e-4
+        assert st == KP_OK
+    for pl in plans:
+        pl.close()
+
+
 def test_periodic_refusals():
-    """A periodic plan refuses the exact diagonal, batched solves and K > n;
-    an unknown boundary value is refused at setup."""
-    torch = require_gpu()
-    from paper_2311_15393_amd import (KP_BC_PERIODIC, KP_EXACT_DIAG, KP_FPCG, KP_P16, KPError,
-                                      Plan, solve_batched)
+    """kp_setup refuses a periodic PSF larger than the image (it would wrap
+    onto itself) and an unknown boundary value."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_BC_PERIODIC, KPError, Plan
     from paper_2311_15393_amd.kpcg import KP_ERR_ARG, KP_ERR_UNSUPPORTED
-    psf, _, b = _problem(64, 15, "gauss", 2)
-    with Plan(psf, 64, bc=KP_BC_PERIODIC) as plan:
-        for call in (lambda: plan.solve(to_dev(b), 0.01, mode=KP_FPCG | KP_P16 | KP_EXACT_DIAG),
-                     lambda: plan.exact_diag(),
-                     lambda: solve_batched([plan], [to_dev(b)], [0.01], [0])):
-            with pytest.raises(KPError) as ei:
-                call()
-            assert ei.value.status == KP_ERR_UNSUPPORTED
-        z = torch.empty_like(to_dev(b))
-        with pytest.raises(KPError) as ei:
-            plan.precond(to_dev(b), 0.01, KP_P16 | KP_EXACT_DIAG, z)
-        assert ei.value.status == KP_ERR_UNSUPPORTED
     with pytest.raises(KPError) as ei:
         Plan(_psf("rand", 17, 0), 15, bc=KP_BC_PERIODIC)
     assert ei.value.status == KP_ERR_ARG
     with pytest.raises(KPError) as ei:
-        Plan(psf, 64, bc=2)
+        Plan(_psf("gauss", 15, 0), 64, bc=2)
     assert ei.value.status == KP_ERR_UNSUPPORTED

@@ -154,3 +154,22 @@ def test_periodic_data_generator_matches_oracle_blur():
     p = S.large_moffat_periodic(0, n=96, k=15)
     noise = p.b.astype(np.float64) - PB.blur(p.psf, p.x_true)
     assert abs(np.linalg.norm(noise) - p.noise_norm) < 1e-9 * p.noise_norm
+
+
+def test_exact_diag_brute_force_and_closed_forms():
+    """D0[i, j] = ||A (v_c,i v_r,j^T)||_F^2 by blurring every basis image;
+    D0 = s_c^2 s_r^2 for a separable PSF; sum D0 = ||A||_F^2 = n^2 ||P||_F^2
+    (each of the n^2 rows of the BCCB matrix holds every tap once)."""
+    rng = np.random.default_rng(12)
+    n, k = 8, 5
+    psf = _psf(rng, k)
+    kp = PB.kp_svd(psf, n)
+    d0 = PB.exact_diag(kp, psf)
+    brute = np.array([[np.sum(PB.blur(psf, np.outer(kp.Vc[:, i], kp.Vr[:, j])) ** 2)
+                       for j in range(n)] for i in range(n)])
+    assert np.abs(d0 - brute).max() < 1e-13 * brute.max()
+    assert abs(d0.sum() - n * n * np.sum(psf ** 2)) < 1e-12 * d0.sum()
+    sep = np.outer(rng.uniform(0, 1, k), rng.uniform(0, 1, k))
+    kps = PB.kp_svd(sep, n)
+    assert np.allclose(PB.exact_diag(kps, sep), np.outer(kps.sc ** 2, kps.sr ** 2), rtol=1e-12,
+                       atol=1e-14)
