@@ -331,6 +331,9 @@ def main():
         log(f"[bench] cpu oracle solve {cpu_s:.2f}s iters={out.iters}")
 
     batch = run_batch(args.batch, dev) if args.batch else None
+    lowp = None
+    if not args.profile_only:
+        lowp = run_lowp_setup(prob, b, lam, results["fp16_kp_fpcg"]["tol"], xlam, setup_s)
     periodic = None
     if not args.profile_only and not args.no_periodic:
         periodic = run_periodic(args.seed, grid, ladder, dev)
@@ -362,6 +365,7 @@ def main():
             "learned_lambda": learned,
             "batched": batch,
             "periodic": periodic,
+            "lowp_setup": lowp,
         },
         "roofline": roofline,
         "cpu_baseline": cpu_baseline,
@@ -413,6 +417,40 @@ def time_learned_lambda(plan, b, grid, dev) -> dict:
     return {"lambda_learned_ms": ll_ms, "predict_rows": 4096, "predict_ms": pred_ms,
             "predict_samples_per_s": 4096 / (pred_ms * 1e-3),
             "train_step_ms": step_ms, "train_samples_per_s": 256 / (step_ms * 1e-3)}
+
+
+def run_lowp_setup(prob, b, lam: float, tol: float, xlam, setup64_s: float):
+    """The reduced-precision construction (KP_SETUP_LOWP: factors rounded to
+    FP16, FP32 SVDs) on the large workload: kp_setup time against the FP64
+    construction's, and the FP16-KP FPCG solve at the headline tolerance
+    with it (iterations, error against x_lambda, 5 timed solves)."""
+    import torch
+    from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, KP_SETUP_LOWP, Plan
+    torch.cuda.synchronize()
+    t0 = time.time()
+    plan = Plan(prob.psf, prob.n, bc=KP_SETUP_LOWP)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+
+    def run():
+        x = torch.empty_like(b)
+        return plan.solve(b, lam, tol=tol, maxit=200, mode=KP_FPCG | KP_P16, x=x,
+                          raise_on_fail=False)
+
+    x, info = run()
+    err = float(np.linalg.norm(x.cpu().numpy().astype(np.float64) - xlam) / np.linalg.norm(xlam))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / 5 * 1e3
+    plan.close()
+    log(f"[bench] lowp setup: {setup_s:.3f}s (FP64 construction {setup64_s:.3f}s); FP16 solve "
+        f"iters={info.iters} err={err:.2e} {ms:.3f} ms/solve")
+    return {"setup_s": setup_s, "setup_fp64_s": setup64_s, "tol": tol, "iters": info.iters,
+            "rel_err": err, "ok": bool(info.status == KP_OK and err <= 1e-4),
+            "ms_per_solve": ms}
 
 
 def run_periodic(seed: int, grid, ladder, dev):

@@ -57,6 +57,12 @@ extern "C" {
 #define KP_BC_PERIODIC  1       /* image extended periodically (BCCB A,
                                    K <= n); one-term KP with circulant
                                    factors                                 */
+#define KP_SETUP_LOWP   0x100   /* flag OR-ed into kp_setup's bc: reduced-
+                                   precision construction of S, V_r, V_c
+                                   (Section 3 leaves computing them in half
+                                   precision to future work): each factor
+                                   is scaled by a power of two, rounded to
+                                   FP16, and factorised by FP32 rocSOLVER */
 
 /* ---- mode bits for pcg_solve / pcg_solve_batched --------------------- */
 #define KP_CG        0x000      /* no preconditioner                        */
@@ -139,8 +145,8 @@ size_t kp_workspace_size(int n, int k, int modes);
  *   psf        host, K*K float64, row-major
  *   k, n       PSF support (odd, <= KP_MAX_PSF, <= 2n-1; <= n for the
  *              periodic boundary), image size
- *   bc         KP_BC_ZERO or KP_BC_PERIODIC (other values:
- *              KP_ERR_UNSUPPORTED)
+ *   bc         KP_BC_ZERO or KP_BC_PERIODIC, optionally | KP_SETUP_LOWP
+ *              (other values: KP_ERR_UNSUPPORTED)
  *   workspace  device buffer of >= kp_workspace_size(n, k, 0) bytes that
  *              the plan uses for all its device data (caller keeps
  *              ownership and must keep it alive until kp_destroy), or

@@ -133,6 +133,28 @@ def kp_svd(psf: np.ndarray, n: int) -> KPSVD:
                  Vr=vrt.T, s_psf=s)
 
 
+def fp16_factor(t: np.ndarray) -> np.ndarray:
+    """A factor as the reduced-precision construction sees it: scaled by the
+    power of two 2^e that puts its largest |entry| in [2^13, 2^14), rounded
+    to FP16 (round to nearest even), scaled back (exactly)."""
+    mx = float(np.abs(t).max())
+    if mx == 0.0:
+        return np.zeros_like(t)
+    e = 13 - int(np.floor(np.log2(mx)))
+    return np.ldexp(np.ldexp(t, e).astype(np.float16).astype(np.float64), -e)
+
+
+def kp_svd_fp16_factors(kp: KPSVD) -> KPSVD:
+    """The exact (FP64) SVDs of the FP16-rounded factors of `kp`: what a
+    half-precision construction of S, V_r and V_c (left to future work in
+    Section 3) computes up to the rounding of its own SVD."""
+    ac, ar = fp16_factor(kp.Ac), fp16_factor(kp.Ar)
+    uc, sc, vct = np.linalg.svd(ac)
+    ur, sr, vrt = np.linalg.svd(ar)
+    return KPSVD(n=kp.n, Ac=ac, Ar=ar, Uc=uc, sc=sc, Vc=vct.T, Ur=ur, sr=sr,
+                 Vr=vrt.T, s_psf=kp.s_psf)
+
+
 def kp_apply(kp: KPSVD, x: np.ndarray) -> np.ndarray:
     """A_hat X = A_c X A_r^T."""
     return kp.Ac @ x @ kp.Ar.T

@@ -199,8 +199,9 @@ size_t kp_workspace_size(int n, int k, int modes) {
   return layout(n, k, nullptr, nullptr);
 }
 
-int kp_setup(const double* psf, int k, int n, int bc, void* workspace, size_t ws_bytes,
+int kp_setup(const double* psf, int k, int n, int bc_flags, void* workspace, size_t ws_bytes,
              void* stream, kp_plan_t* plan) {
+  const int bc = bc_flags & ~KP_SETUP_LOWP;
   if (plan == nullptr) return KP_ERR_ARG;
   *plan = nullptr;
   if (psf == nullptr || !valid_sizes(n, k)) {
@@ -221,6 +222,7 @@ int kp_setup(const double* psf, int k, int n, int bc, void* workspace, size_t ws
   P.n = n;
   P.k = k;
   P.bc = bc;
+  P.lowp = (bc_flags & KP_SETUP_LOWP) != 0;
   P.kq = (k + TAP_CHUNK - 1) / TAP_CHUNK * TAP_CHUNK;
   const size_t need = layout(n, k, nullptr, nullptr);
   char* base = nullptr;

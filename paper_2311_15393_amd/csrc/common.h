@@ -179,6 +179,7 @@ __device__ inline void set_scales(Ctrl* c, double rr) {
 struct Plan {
   int n = 0, k = 0, kq = 0;       // kq: PSF row length padded to the tap chunk
   int bc = KP_BC_ZERO;            // boundary condition of A (KP_BC_ZERO / KP_BC_PERIODIC)
+  bool lowp = false;              // KP_SETUP_LOWP: factors rounded to FP16, FP32 SVDs
   bool owns = false;
   void* base = nullptr;
   size_t bytes = 0;

@@ -190,6 +190,21 @@ __global__ void toeplitz_kernel(const double* __restrict__ f, int K, int n, int 
   t[idx] = (d >= -h && d <= h) ? f[h + d] : 0.0;
 }
 
+// Reduced-precision construction (KP_SETUP_LOWP): the factor scaled by 2^e
+// (its largest |entry| in [2^13, 2^14)) and rounded to FP16, held in FP32
+// for the FP32 factorisation; and the widening of its FP32 results.
+__global__ void fp16_factor_kernel(const double* __restrict__ t, size_t count, int e,
+                                   float* __restrict__ out) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count) out[idx] = (float)(_Float16)ldexp(t[idx], e);
+}
+
+__global__ void widen_kernel(const float* __restrict__ src, size_t count, double scale,
+                             double* __restrict__ dst) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count) dst[idx] = scale * (double)src[idx];
+}
+
 // From the column-major gesvd outputs: Vt (n x n, Vt(a,i) = V(i,a)) and U.
 //   Vrm[i*n+a]  = V(i,a)   = Vt[a + i*n]   (same memory order)
 //   VTrm[a*n+i] = V(i,a)                   (transpose)
@@ -332,6 +347,8 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
   double* wv = nullptr;
   int* perm = nullptr;
   double *pall = nullptr, *G2 = nullptr, *D64 = nullptr;   // exact KP-basis diagonal
+  float *T32 = nullptr, *U32 = nullptr, *Vt32 = nullptr, *s32 = nullptr, *e32 = nullptr;
+  int lexp[2] = {0, 0};                                     // KP_SETUP_LOWP factor scales
   int tall = 0;
   size_t glds = 0;
   bool symmetric[2] = {false, false};
@@ -353,6 +370,13 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
   HCHK(hipMalloc(&info, sizeof(rocblas_int)));
   HCHK(hipMalloc(&wv, sizeof(double) * n));
   HCHK(hipMalloc(&perm, sizeof(int) * n));
+  if (P.lowp) {
+    HCHK(hipMalloc(&T32, sizeof(float) * nn));
+    HCHK(hipMalloc(&U32, sizeof(float) * nn));
+    HCHK(hipMalloc(&Vt32, sizeof(float) * nn));
+    HCHK(hipMalloc(&s32, sizeof(float) * n));
+    HCHK(hipMalloc(&e32, sizeof(float) * n));
+  }
   HCHK(hipMemcpyAsync(dpsf, psf_host, sizeof(double) * K * K, hipMemcpyHostToDevice, s));
 
   SCHK(rocblas_create_handle(&handle));
@@ -396,6 +420,11 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
       for (int k = 0; k < K; ++k)
         asym = std::fmax(asym, std::fabs(hp[f * K + k] - hp[f * K + K - 1 - k]));
       symmetric[f] = asym <= 1e-13 * mx && !force_general_svd();
+      // the factor's entries are the profile's values at offsets |k - h| < n
+      double fmx = 0.0;
+      for (int k = 0; k < K; ++k)
+        if (std::abs(k - (K - 1) / 2) < n) fmx = std::fmax(fmx, std::fabs(hp[f * K + k]));
+      lexp[f] = fmx > 0.0 ? 13 - std::ilogb(fmx) : 0;
     }
   }
   {
@@ -430,7 +459,31 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
     double* sig = f == 0 ? P.sc : P.sr;
     hipLaunchKernelGGL(toeplitz_kernel, dim3(gnn), dim3(nthr), 0, s, prof_f, K, n, P.bc, T);
     HCHK(hipGetLastError());
-    if (symmetric[f]) {
+    if (P.lowp) {
+      // FP16 factor, FP32 factorisation, results widened (the scale undone
+      // on the singular values / eigenvalues)
+      const double unscale = std::ldexp(1.0, -lexp[f]);
+      hipLaunchKernelGGL(fp16_factor_kernel, dim3(gnn), dim3(nthr), 0, s, T, nn, lexp[f], T32);
+      HCHK(hipGetLastError());
+      if (symmetric[f]) {
+        SCHK(rocsolver_ssyevd(handle, rocblas_evect_original, rocblas_fill_upper, n, T32, n, s32,
+                              e32, info));
+        hipLaunchKernelGGL(widen_kernel, dim3(gnn), dim3(nthr), 0, s, T32, nn, 1.0, T);
+        hipLaunchKernelGGL(widen_kernel, dim3((n + 255) / 256), dim3(256), 0, s, s32,
+                           (size_t)n, unscale, wv);
+        hipLaunchKernelGGL(rank_kernel, dim3((n + 255) / 256), dim3(256), 0, s, wv, n, perm);
+        hipLaunchKernelGGL(gather_eig_kernel, dim3(gnn), dim3(nthr), 0, s, T, wv, perm, n, sig,
+                           Vt, U);
+      } else {
+        SCHK(rocsolver_sgesvd(handle, rocblas_svect_all, rocblas_svect_all, n, n, T32, n, s32,
+                              U32, n, Vt32, n, e32, rocblas_outofplace, info));
+        hipLaunchKernelGGL(widen_kernel, dim3((n + 255) / 256), dim3(256), 0, s, s32,
+                           (size_t)n, unscale, sig);
+        hipLaunchKernelGGL(widen_kernel, dim3(gnn), dim3(nthr), 0, s, U32, nn, 1.0, U);
+        hipLaunchKernelGGL(widen_kernel, dim3(gnn), dim3(nthr), 0, s, Vt32, nn, 1.0, Vt);
+      }
+      HCHK(hipGetLastError());
+    } else if (symmetric[f]) {
       SCHK(rocsolver_dsyevd(handle, rocblas_evect_original, rocblas_fill_upper, n, T, n, wv, e,
                             info));
       hipLaunchKernelGGL(rank_kernel, dim3((n + 255) / 256), dim3(256), 0, s, wv, n, perm);
@@ -510,6 +563,7 @@ done:
   hipFree(dpsf); hipFree(pw); hipFree(spsf); hipFree(upsf); hipFree(vpsf); hipFree(e);
   hipFree(prof); hipFree(T); hipFree(U); hipFree(Vt); hipFree(info); hipFree(wv);
   hipFree(perm); hipFree(pall); hipFree(G2); hipFree(D64);
+  hipFree(T32); hipFree(U32); hipFree(Vt32); hipFree(s32); hipFree(e32);
   return rc;
 }
 

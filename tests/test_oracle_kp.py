@@ -222,3 +222,24 @@ def test_exact_diag_preconditioner_same_solution_fewer_iterations():
     assert ex.status == "converged" and one.status == "converged"
     assert np.linalg.norm(ex.x - ref) <= 1e-8 * np.linalg.norm(ref)
     assert ex.iters < one.iters
+
+
+def test_fp16_factor_construction():
+    """The FP16-rounded factors: the power-of-two scale puts the largest
+    entry in [2^13, 2^14) and unscales exactly; entries that are FP16 values
+    at that scale survive unchanged; every singular value moves by at most
+    ||A16 - A||_2 (Weyl), and the rounding is at most 2^-11 relative to the
+    largest entry per entry."""
+    rng = np.random.default_rng(31)
+    n, k = 48, 15
+    psf = S.psf_moffat_motion(k, 5.0, 2.5, 6.0, 0.7)
+    kp = KP.kp_svd(psf, n)
+    lo = KP.kp_svd_fp16_factors(kp)
+    for a, a16, s, s16 in ((kp.Ac, lo.Ac, kp.sc, lo.sc), (kp.Ar, lo.Ar, kp.sr, lo.sr)):
+        mx = np.abs(a).max()
+        e = 13 - int(np.floor(np.log2(mx)))
+        assert 2.0 ** 13 <= mx * 2.0 ** e < 2.0 ** 14
+        assert np.all(np.abs(a16 - a) <= 2.0 ** -11 * 2.0 ** 14 * 2.0 ** -e)
+        assert np.all(np.abs(s16 - s) <= np.linalg.norm(a16 - a, 2) * (1 + 1e-12) + 1e-15)
+    q = rng.integers(-2048, 2048, (n, n)) / 2048.0          # FP16 values already
+    assert np.array_equal(KP.fp16_factor(q), q)
