@@ -22,6 +22,9 @@ Preconditioner for Structured Inverse Problems" (arXiv:2311.15393):
   periodic.py  the periodic boundary: block-circulant A and A^T, the
                circulant one-term Kronecker approximation, and the exact
                Tikhonov minimiser through the 2-D DFT
+  reflexive.py the reflexive boundary for PSFs symmetric in both axes
+               (A = A^T, Toeplitz-plus-Hankel factors) and the exact
+               Tikhonov minimiser through the 2-D DCT
   quant.py     FP16 and FP8-e4m3 rounding and the emulated reduced-precision
                preconditioner chain
   mlp.py       FP64 reference of the small lambda-predicting network
