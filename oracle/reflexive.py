@@ -37,7 +37,8 @@ and the exact KP-basis diagonal follow kp.py with reflexive factors.
 Pins (tests/test_oracle_reflexive.py): scipy.ndimage.convolve with
 mode='reflect'; A is symmetric for symmetric PSFs and preserves constant
 images; the dense matrix equals the reflexive Kronecker-sum expansion; the
-DCT form equals the definition; x_lambda equals a dense solve; the one-term
+DCT form (with the closed-form corner response A E_00, itself pinned against
+the definition) equals the definition; x_lambda equals a dense solve; the one-term
 KP is exact for separable symmetric PSFs; the exact diagonal equals
 ||A (v_c,i v_r,j^T)||_F^2 by brute force; the oracle's PCG converges to
 x_lambda.
@@ -104,11 +105,26 @@ def dense_matrix(psf: np.ndarray, n: int) -> np.ndarray:
     return a
 
 
+def corner_response(psf: np.ndarray, n: int) -> np.ndarray:
+    """A E_00 (E_00 the unit image at (0, 0)) in closed form: refl(i - u) = 0
+    for u in {i, i + 1} only, so (A E_00)[i, j] is the sum of P[h+u, h+v]
+    over u in {i, i+1}, v in {j, j+1} with |u|, |v| <= h."""
+    k, h = _check(psf, n)
+    r = np.zeros((n, n))
+    for i in range(min(n, h + 1)):
+        for j in range(min(n, h + 1)):
+            for u in (i, i + 1):
+                for v in (j, j + 1):
+                    if u <= h and v <= h:
+                        r[i, j] += psf[h + u, h + v]
+    return r
+
+
 def eigenvalues(psf: np.ndarray, n: int) -> np.ndarray:
     """L with A X = idct2(L .* dct2(X)) (orthonormal DCT-II)."""
     e = np.zeros((n, n))
     e[0, 0] = 1.0
-    return (scipy.fft.dctn(blur(psf, e), type=2, norm="ortho")
+    return (scipy.fft.dctn(corner_response(psf, n), type=2, norm="ortho")
             / scipy.fft.dctn(e, type=2, norm="ortho"))
 
 

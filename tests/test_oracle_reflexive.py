@@ -105,3 +105,12 @@ def test_rejects_asymmetric_or_large_psf():
         RB.blur(np.arange(9.0).reshape(3, 3), np.zeros((8, 8)))
     with pytest.raises(ValueError):
         RB.blur(np.ones((9, 9)), np.zeros((8, 8)))
+
+
+def test_corner_response_closed_form():
+    rng = np.random.default_rng(8)
+    for n, k in ((8, 5), (16, 15), (9, 9)):
+        psf = _sym_psf(rng, k)
+        e = np.zeros((n, n))
+        e[0, 0] = 1.0
+        assert np.abs(RB.corner_response(psf, n) - RB.blur(psf, e)).max() < 1e-15
