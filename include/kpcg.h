@@ -57,6 +57,11 @@ extern "C" {
 #define KP_BC_PERIODIC  1       /* image extended periodically (BCCB A,
                                    K <= n); one-term KP with circulant
                                    factors                                 */
+#define KP_BC_REFLEXIVE 2       /* image extended by half-sample
+                                   reflection, K <= n, for PSFs symmetric
+                                   in both axes (then A = A^T; other PSFs:
+                                   KP_ERR_UNSUPPORTED); reflexive
+                                   (Toeplitz-plus-Hankel) factors          */
 #define KP_SETUP_LOWP   0x100   /* flag OR-ed into kp_setup's bc: reduced-
                                    precision construction of S, V_r, V_c
                                    (Section 3 leaves computing them in half
@@ -136,8 +141,9 @@ size_t kp_workspace_size(int n, int k, int modes);
  * approximated by the Frobenius-optimal Kronecker product A_r (x) A_c
  * (built from the leading singular triple of the PSF weighted by
  * sqrt(n - |k - h|) on both sides: banded Toeplitz factors for the zero
- * boundary; for the periodic boundary every weight is n, i.e. the plain
- * PSF SVD, and the factors are circulant), and A_r, A_c are factorised by
+ * boundary; for the periodic and reflexive boundaries every weight is n,
+ * i.e. the plain PSF SVD, and the factors are circulant or reflexive
+ * Toeplitz-plus-Hankel), and A_r, A_c are factorised by
  * FP64 SVDs on the device.  The paper states no boundary condition; both
  * keep its PSF centre (h, h) and true convolution for A.  V_r, V_c are stored in FP32, FP16 and FP8 (with
  * block scales), U_r, U_c in FP32, singular values in FP64 and FP32.
@@ -145,7 +151,8 @@ size_t kp_workspace_size(int n, int k, int modes);
  *   psf        host, K*K float64, row-major
  *   k, n       PSF support (odd, <= KP_MAX_PSF, <= 2n-1; <= n for the
  *              periodic boundary), image size
- *   bc         KP_BC_ZERO or KP_BC_PERIODIC, optionally | KP_SETUP_LOWP
+ *   bc         KP_BC_ZERO, KP_BC_PERIODIC or KP_BC_REFLEXIVE, optionally
+ *              | KP_SETUP_LOWP
  *              (other values: KP_ERR_UNSUPPORTED)
  *   workspace  device buffer of >= kp_workspace_size(n, k, 0) bytes that
  *              the plan uses for all its device data (caller keeps

@@ -173,12 +173,15 @@ struct EpiAnchorRes {
 
 // Source row or column of a staged tile entry.  The zero boundary keeps the
 // index (out-of-range entries are zero-filled by the caller); the periodic
-// boundary (KP_BC_PERIODIC) wraps it by one period, which covers every entry
-// that feeds an output inside the image (|index - [0, n)| <= h < n); entries
-// further out only feed the discarded outputs of edge tiles and are clamped.
+// boundary (KP_BC_PERIODIC) wraps it by one period and the reflexive one
+// (KP_BC_REFLEXIVE) reflects it once about the half-sample edge (-1 -> 0,
+// n -> n - 1), which covers every entry that feeds an output inside the
+// image (|index - [0, n)| <= h < n); entries further out only feed the
+// discarded outputs of edge tiles and are clamped.
 __device__ inline int bc_index(int g, int n, int bc) {
-  if (bc == 0) return g;
-  g = g < 0 ? g + n : (g >= n ? g - n : g);
+  if (bc == KP_BC_ZERO) return g;
+  if (bc == KP_BC_PERIODIC) g = g < 0 ? g + n : (g >= n ? g - n : g);
+  else g = g < 0 ? -g - 1 : (g >= n ? 2 * n - 1 - g : g);
   return g < 0 ? 0 : (g >= n ? n - 1 : g);
 }
 

@@ -209,9 +209,24 @@ int kp_setup(const double* psf, int k, int n, int bc_flags, void* workspace, siz
       return KP_ERR_UNSUPPORTED;
     return KP_ERR_ARG;
   }
-  if (bc != KP_BC_ZERO && bc != KP_BC_PERIODIC) return KP_ERR_UNSUPPORTED;
+  if (bc != KP_BC_ZERO && bc != KP_BC_PERIODIC && bc != KP_BC_REFLEXIVE)
+    return KP_ERR_UNSUPPORTED;
   if (k > KP_MAX_PSF) return KP_ERR_UNSUPPORTED;
-  if (bc == KP_BC_PERIODIC && k > n) return KP_ERR_ARG;     // the PSF would wrap onto itself
+  // periodic: the PSF would wrap onto itself; reflexive: one reflection
+  // must cover every index
+  if (bc != KP_BC_ZERO && k > n) return KP_ERR_ARG;
+  if (bc == KP_BC_REFLEXIVE) {
+    // A^T = A (and the blur of A^T equals that of A) needs a PSF symmetric
+    // in both axes
+    double mx = 0.0, asym = 0.0;
+    for (int i = 0; i < k * k; ++i) mx = std::fmax(mx, std::fabs(psf[i]));
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < k; ++b) {
+        asym = std::fmax(asym, std::fabs(psf[a * k + b] - psf[(k - 1 - a) * k + b]));
+        asym = std::fmax(asym, std::fabs(psf[a * k + b] - psf[a * k + (k - 1 - b)]));
+      }
+    if (asym > 1e-12 * mx) return KP_ERR_UNSUPPORTED;
+  }
   for (int i = 0; i < k * k; ++i)
     if (!std::isfinite(psf[i])) return KP_ERR_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);

@@ -27,9 +27,11 @@ namespace kpcg {
 
 // Frobenius weight of PSF offset k - h in one factor: ||Z_d||_F^2 = n - |d|
 // for the zero boundary's shift matrices, ||C_d||_F^2 = n for the periodic
-// boundary's cyclic shifts (so its optimal term is the plain PSF SVD).
+// boundary's cyclic shifts (so its optimal term is the plain PSF SVD); the
+// reflexive boundary takes the plain PSF SVD too (its reflected shifts have
+// n entries each but overlap, so no weighting makes it exactly optimal).
 __device__ inline double psf_weight(int k, int h, int n, int bc) {
-  return bc == KP_BC_PERIODIC ? (double)n : (double)(n - abs(k - h));
+  return bc != KP_BC_ZERO ? (double)n : (double)(n - abs(k - h));
 }
 
 // Weighted PSF, column-major K x K for the solver.
@@ -114,6 +116,7 @@ __global__ __launch_bounds__(GRAM_NT) void gram_kernel(const double* __restrict_
   for (int m = tid; m < n + K - 1; m += GRAM_NT) {
     int i = m - h;
     if (bc == KP_BC_PERIODIC) i = i < 0 ? i + n : (i >= n ? i - n : i);   // h < n
+    else if (bc == KP_BC_REFLEXIVE) i = i < 0 ? -i - 1 : (i >= n ? 2 * n - 1 - i : i);
     sv[m] = (i >= 0 && i < n) ? V[(size_t)i * n + a] : 0.0;
   }
   // this thread's pairs p = tid + GRAM_NT q in the order (0,0), (0,1), ...
@@ -174,8 +177,11 @@ __global__ void to_f32_kernel(const double* __restrict__ src, int n, float* __re
 }
 
 // Column-major factor from a profile: the banded Toeplitz T(f)[i][i'] =
-// f[h + i - i'] (zero boundary), or the circulant C(f)[i][i'] = f[h + d]
-// with d = i - i' mod n taken in [-h, h] (periodic boundary, K <= n).
+// f[h + i - i'] (zero boundary), the circulant C(f)[i][i'] = f[h + d] with
+// d = i - i' mod n taken in [-h, h] (periodic boundary, K <= n), or the
+// reflexive R(f)[i][i'] = sum of f[h + d] over the d with refl(i - d) = i':
+// d = i - i' (direct), i + i' + 1 (reflected at the top) and i + i' + 1 - 2n
+// (at the bottom), each if |d| <= h (reflexive boundary, K <= n).
 __global__ void toeplitz_kernel(const double* __restrict__ f, int K, int n, int bc,
                                 double* __restrict__ t) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -183,6 +189,14 @@ __global__ void toeplitz_kernel(const double* __restrict__ f, int K, int n, int 
   const int i = (int)(idx % n), ip = (int)(idx / n);   // t[i + ip*n]
   const int h = (K - 1) / 2;
   int d = i - ip;
+  if (bc == KP_BC_REFLEXIVE) {
+    const int d2 = i + ip + 1, d3 = i + ip + 1 - 2 * n;
+    double v = (d >= -h && d <= h) ? f[h + d] : 0.0;
+    if (d2 >= -h && d2 <= h) v += f[h + d2];
+    if (d3 >= -h && d3 <= h) v += f[h + d3];
+    t[idx] = v;
+    return;
+  }
   if (bc == KP_BC_PERIODIC) {
     if (d > h) d -= n;
     else if (d < -h) d += n;

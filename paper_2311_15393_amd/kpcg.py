@@ -28,6 +28,7 @@ KP_EXACT_DIAG = 0x800
 KP_MAX_PSF = 63
 KP_BC_ZERO = 0
 KP_BC_PERIODIC = 1
+KP_BC_REFLEXIVE = 2
 KP_SETUP_LOWP = 0x100
 KP_BLUR_MFMA = 6
 KP_BLUR_MFMA32 = 7

@@ -232,5 +232,5 @@ def test_periodic_refusals():
         Plan(_psf("rand", 17, 0), 15, bc=KP_BC_PERIODIC)
     assert ei.value.status == KP_ERR_ARG
     with pytest.raises(KPError) as ei:
-        Plan(_psf("gauss", 15, 0), 64, bc=2)
+        Plan(_psf("gauss", 15, 0), 64, bc=3)
     assert ei.value.status == KP_ERR_UNSUPPORTED

@@ -60,7 +60,8 @@ def test_strerror_and_workspace_size():
     (4, 16, 0, -1),       # even K
     (15, 4, 0, -1),       # K > 2n - 1
     (15, 0, 0, -1),       # n < 1
-    (15, 64, 2, -2),      # unknown boundary condition
+    (15, 64, 3, -2),      # unknown boundary condition
+    (15, 9, 2, -1),       # reflexive boundary with K > n
     (15, 9, 1, -1),       # periodic boundary with K > n
     (65, 64, 0, -2),      # K above the supported maximum
 ])
