@@ -178,11 +178,17 @@ struct EpiAnchorRes {
 // n -> n - 1), which covers every entry that feeds an output inside the
 // image (|index - [0, n)| <= h < n); entries further out only feed the
 // discarded outputs of edge tiles and are clamped.
-__device__ inline int bc_index(int g, int n, int bc) {
-  if (bc == KP_BC_ZERO) return g;
-  if (bc == KP_BC_PERIODIC) g = g < 0 ? g + n : (g >= n ? g - n : g);
+template <int BCV>
+__device__ inline int bc_index_c(int g, int n) {
+  if constexpr (BCV == KP_BC_ZERO) return g;
+  if constexpr (BCV == KP_BC_PERIODIC) g = g < 0 ? g + n : (g >= n ? g - n : g);
   else g = g < 0 ? -g - 1 : (g >= n ? 2 * n - 1 - g : g);
   return g < 0 ? 0 : (g >= n ? n - 1 : g);
+}
+__device__ inline int bc_index(int g, int n, int bc) {
+  if (bc == KP_BC_ZERO) return bc_index_c<KP_BC_ZERO>(g, n);
+  if (bc == KP_BC_PERIODIC) return bc_index_c<KP_BC_PERIODIC>(g, n);
+  return bc_index_c<KP_BC_REFLEXIVE>(g, n);
 }
 
 // ---------------------------------------------------------------------------

@@ -38,6 +38,48 @@ inline size_t mb_lds_bytes(int nch, int K) {
          (size_t)4 * 16 * 64 * sizeof(float);
 }
 
+// Register staging of a tile whose top-left input is (r0, c0): slot q of
+// each thread holds the column pair (c, c + 1) of row r at
+// idx = threadIdx.x + q MB_NT, idx = r W2 + c / 2, with boundary indices
+// mapped by bc_index_c; entries outside the image (zero boundary) or past
+// cvalid read as 0.  Returns the thread's largest |value|.
+template <int BCV, int NVP, int W2>
+__device__ inline float mb_stage_load_c(const float* __restrict__ src, int n, int r0, int c0,
+                                        int rows, int cvalid, float (&v0)[NVP],
+                                        float (&v1)[NVP]) {
+  float mx = 0.0f;
+#pragma unroll
+  for (int q = 0; q < NVP; ++q) {
+    const int idx = threadIdx.x + q * MB_NT;
+    float a0 = 0.0f, a1 = 0.0f;
+    if (idx < rows * W2) {
+      const int r = idx / W2, c = 2 * (idx - r * W2);
+      const int gi = bc_index_c<BCV>(r0 + r, n);
+      const int gj = bc_index_c<BCV>(c0 + c, n), gj1 = bc_index_c<BCV>(c0 + c + 1, n);
+      if ((unsigned)gi < (unsigned)n) {
+        if (c < cvalid && (unsigned)gj < (unsigned)n) a0 = src[(size_t)gi * n + gj];
+        if (c + 1 < cvalid && (unsigned)gj1 < (unsigned)n) a1 = src[(size_t)gi * n + gj1];
+      }
+    }
+    v0[q] = a0;
+    v1[q] = a1;
+    mx = fmaxf(mx, fmaxf(fabsf(a0), fabsf(a1)));
+  }
+  return mx;
+}
+// The boundary is uniform over the launch: branch on it once, outside the
+// unrolled slots.
+template <int NVP, int W2>
+__device__ inline float mb_stage_load(const float* __restrict__ src, int n, int r0, int c0,
+                                      int rows, int cvalid, int bc, float (&v0)[NVP],
+                                      float (&v1)[NVP]) {
+  if (bc == KP_BC_ZERO)
+    return mb_stage_load_c<KP_BC_ZERO, NVP, W2>(src, n, r0, c0, rows, cvalid, v0, v1);
+  if (bc == KP_BC_PERIODIC)
+    return mb_stage_load_c<KP_BC_PERIODIC, NVP, W2>(src, n, r0, c0, rows, cvalid, v0, v1);
+  return mb_stage_load_c<KP_BC_REFLEXIVE, NVP, W2>(src, n, r0, c0, rows, cvalid, v0, v1);
+}
+
 // One 64 x 64 output tile at (i0, j0): src is the n x n FP32 input, bfrag
 // the plan's tap-fragment table for this orientation, mb_lds dynamic LDS of
 // mb_lds_bytes(NCH, K) bytes; partial_out receives the tile's FP64 epilogue
@@ -63,24 +105,7 @@ __device__ inline void blur_mfma_tile(const float* __restrict__ src,
   // largest |x|, then write the scaled hi / lo planes: the scale 2^ex puts
   // that largest value in [2^13, 2^14)
   float v0[NVP], v1[NVP];
-  float mx = 0.0f;
-#pragma unroll
-  for (int q = 0; q < NVP; ++q) {
-    const int idx = threadIdx.x + q * MB_NT;
-    float a0 = 0.0f, a1 = 0.0f;
-    if (idx < rows * W2) {
-      const int r = idx / W2, c = 2 * (idx - r * W2);
-      const int gi = bc_index(i0 - h + r, n, bc);
-      const int gj = bc_index(j0 - h + c, n, bc), gj1 = bc_index(j0 - h + c + 1, n, bc);
-      if ((unsigned)gi < (unsigned)n) {
-        if (c < cvalid && (unsigned)gj < (unsigned)n) a0 = src[(size_t)gi * n + gj];
-        if (c + 1 < cvalid && (unsigned)gj1 < (unsigned)n) a1 = src[(size_t)gi * n + gj1];
-      }
-    }
-    v0[q] = a0;
-    v1[q] = a1;
-    mx = fmaxf(mx, fmaxf(fabsf(a0), fabsf(a1)));
-  }
+  float mx = mb_stage_load<NVP, W2>(src, n, i0 - h, j0 - h, rows, cvalid, bc, v0, v1);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
@@ -343,24 +368,7 @@ __device__ inline void blur_mfma32_tile(const float* __restrict__ src,
 
   // stage: as blur_mfma_tile (two columns per slot, tile max, 2^ex scale)
   float v0[NVP], v1[NVP];
-  float mx = 0.0f;
-#pragma unroll
-  for (int q = 0; q < NVP; ++q) {
-    const int idx = threadIdx.x + q * MB_NT;
-    float a0 = 0.0f, a1 = 0.0f;
-    if (idx < rows * W2) {
-      const int r = idx / W2, c = 2 * (idx - r * W2);
-      const int gi = bc_index(i0 - h + r, n, bc);
-      const int gj = bc_index(j0 - h + c, n, bc), gj1 = bc_index(j0 - h + c + 1, n, bc);
-      if ((unsigned)gi < (unsigned)n) {
-        if (c < cvalid && (unsigned)gj < (unsigned)n) a0 = src[(size_t)gi * n + gj];
-        if (c + 1 < cvalid && (unsigned)gj1 < (unsigned)n) a1 = src[(size_t)gi * n + gj1];
-      }
-    }
-    v0[q] = a0;
-    v1[q] = a1;
-    mx = fmaxf(mx, fmaxf(fabsf(a0), fabsf(a1)));
-  }
+  float mx = mb_stage_load<NVP, W2>(src, n, i0 - h, j0 - h, rows, cvalid, bc, v0, v1);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
