@@ -135,6 +135,9 @@ def main():
                     help="skip the periodic-boundary solve (also skipped with --profile-only)")
     ap.add_argument("--batch", type=int, default=0, metavar="P",
                     help="also run the uneven batched workload with P problems x 16 lambda")
+    ap.add_argument("--matvec-sweep", action="store_true",
+                    help="only compare the direct blurs with a zero-padded rocFFT H p over K "
+                         "(prints its own JSON line)")
     ap.add_argument("--modes", default=",".join(MODES),
                     help="comma list of solver modes to run (the first FP16 one is the headline)")
     args = ap.parse_args()
@@ -151,6 +154,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     nthreads = cpu_threads()
+    if args.matvec_sweep:
+        print(json.dumps(run_matvec_sweep(dev)), flush=True)
+        return
 
     t0 = time.time()
     prob = S.large_moffat(args.seed)
@@ -508,6 +514,87 @@ def run_periodic(seed: int, grid, ladder, dev):
             "ms_per_solve": ms, "solves_per_s": 1e3 / ms, "setup_s": setup_s,
             "kp_rel_error": info0["kp_rel_error"], "blur_config": info0["blur_config"],
             "blur_us": blur_us}
+
+
+def smooth_size(m: int) -> int:
+    """Smallest L >= m whose prime factors are all 2, 3, 5 or 7."""
+    L = m
+    while True:
+        r = L
+        for f in (2, 3, 5, 7):
+            while r % f == 0:
+                r //= f
+        if r == 1:
+            return L
+        L += 1
+
+
+def run_matvec_sweep(dev, n: int = 1024, ks=(15, 23, 31, 47, 63), reps: int = 50):
+    """The matvec's two forms at n^2 over the PSF width K (zero boundary):
+    the direct blurs the solver runs (A p and A^T y, each on the plan's
+    autotuned kernel) against H p = A^T A p by zero-padded FFTs (torch.fft,
+    i.e. rocFFT, FP32): p -> A p needs one forward and one inverse
+    transform, the crop to n x n, and A^T y two more.  With circular
+    indices every wrapped tap lands in the zero pad once L >= n + h, so L is
+    the smallest 7-smooth size at or above n + h (a power of two is also
+    timed).  The FFT result is checked against the library's FP64 normal
+    operator."""
+    import torch
+    import synthetic as S
+    from paper_2311_15393_amd import Plan
+
+    def ev_time(fn, reps):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+
+    p = torch.randn((n, n), device=dev, dtype=torch.float32)
+    q = torch.empty_like(p)
+    out = []
+    for k in ks:
+        h = (k - 1) // 2
+        psf = S.psf_moffat_motion(k, 5.5, 2.5, 6.0, 0.7)
+        plan = Plan(psf, n)
+        plan.time_blur(p, q, reps=3)
+        fwd_us = plan.time_blur(p, q, reps=reps) * 1e3
+        plan.time_blur(p, q, transpose=True, reps=3)
+        adj_us = plan.time_blur(p, q, transpose=True, reps=reps) * 1e3
+        ref = torch.empty((n, n), device=dev, dtype=torch.float64)
+        plan.normal_fp64(p, 0.0, ref)
+        torch.cuda.synchronize()
+        cfg = plan.query()["blur_config"]
+        plan.close()
+        row = {"k": k, "blur_config": cfg, "direct_fwd_us": fwd_us, "direct_adj_us": adj_us,
+               "direct_hp_us": fwd_us + adj_us}
+        for tag, L in (("smooth", smooth_size(n + h)), ("pow2", 1 << (n + h - 1).bit_length())):
+            pt = torch.zeros((L, L), device=dev, dtype=torch.float32)
+            pt[:k, :k] = torch.from_numpy(psf.astype(np.float32)).to(dev)
+            pf = torch.fft.rfft2(pt)
+            pfc = pf.conj()
+
+            def hp():
+                y = torch.fft.irfft2(torch.fft.rfft2(p, s=(L, L)) * pf, s=(L, L))[h:h + n, h:h + n]
+                c = torch.fft.irfft2(torch.fft.rfft2(y, s=(L, L)) * pfc, s=(L, L))
+                return torch.roll(c, shifts=(h, h), dims=(0, 1))[:n, :n]
+
+            got = hp().double()
+            err = float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
+            hp_us = ev_time(hp, reps)
+            x = torch.randn((n, n), device=dev)
+            rfft_us = ev_time(lambda: torch.fft.rfft2(x, s=(L, L)), reps)
+            row[f"fft_{tag}"] = {"L": L, "hp_us": hp_us, "rfft2_us": rfft_us, "rel_err": err}
+        log(f"[sweep] K={k}: direct A p {fwd_us:.1f} + A^T y {adj_us:.1f} us (cfg {cfg}); "
+            f"FFT H p L={row['fft_smooth']['L']} {row['fft_smooth']['hp_us']:.1f} us "
+            f"(rfft2 {row['fft_smooth']['rfft2_us']:.1f}, err {row['fft_smooth']['rel_err']:.1e}), "
+            f"L={row['fft_pow2']['L']} {row['fft_pow2']['hp_us']:.1f} us")
+        out.append(row)
+    return {"matvec_sweep": {"n": n, "boundary": "zero", "rows": out}}
 
 
 def run_batch(nprob: int, dev):
