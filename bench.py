@@ -53,10 +53,10 @@ COPY_CALIB_FLOATS = 64 * 1024 * 1024
 # is reported as null.
 BLUR_TRAFFIC = {
     "kernel": "blur_mfma_kernel<3, EpiStoreF32>",
-    "fetch_kib_raw": 5366.3, "write_kib_raw": 4096.0,       # per launch, as counted
+    "fetch_kib_raw": 5367.0, "write_kib_raw": 4096.0,       # per launch, as counted
     "fetch_scale": 1.99979, "write_scale": 1.0,              # copy bytes / counter
-    "bytes_per_launch": 15183297,
-    "sources_sha256": "c73b6fa356c23f26e36dbad44bcf97948bc9f8c1c8fff4b480dbe36d91eb87b3",
+    "bytes_per_launch": 15184812,
+    "sources_sha256": "4ffeead0c3a59a727fac05e52b7aac61c7e1735f28b633607da9bda1729ab4ed",
 }
 
 
@@ -132,7 +132,8 @@ def main():
     ap.add_argument("--profile-only", action="store_true",
                     help="skip the oracle parts (for profiler runs)")
     ap.add_argument("--no-periodic", action="store_true",
-                    help="skip the periodic-boundary solve (also skipped with --profile-only)")
+                    help="skip the periodic- and reflexive-boundary solves (also skipped with "
+                         "--profile-only)")
     ap.add_argument("--batch", type=int, default=0, metavar="P",
                     help="also run the uneven batched workload with P problems x 16 lambda")
     ap.add_argument("--matvec-sweep", action="store_true",
@@ -340,9 +341,10 @@ def main():
     lowp = None
     if not args.profile_only:
         lowp = run_lowp_setup(prob, b, lam, results["fp16_kp_fpcg"]["tol"], xlam, setup_s)
-    periodic = None
+    periodic = reflexive = None
     if not args.profile_only and not args.no_periodic:
-        periodic = run_periodic(args.seed, grid, ladder, dev)
+        periodic = run_boundary("periodic", args.seed, grid, ladder, dev)
+        reflexive = run_boundary("reflexive", args.seed, grid, ladder, dev)
 
     head = results["fp16_kp_fpcg"]
     line = {
@@ -371,6 +373,7 @@ def main():
             "learned_lambda": learned,
             "batched": batch,
             "periodic": periodic,
+            "reflexive": reflexive,
             "lowp_setup": lowp,
         },
         "roofline": roofline,
@@ -459,28 +462,36 @@ def run_lowp_setup(prob, b, lam: float, tol: float, xlam, setup64_s: float):
             "ms_per_solve": ms}
 
 
-def run_periodic(seed: int, grid, ladder, dev):
-    """The large workload with the periodic boundary (KP_BC_PERIODIC): the
-    same image and PSF draws with periodic data, lambda by the device's
-    KP-GCV, FP16-KP flexible PCG at the loosest ladder tolerance whose x
-    meets 1e-4 against the FP64 closed-form x_lambda (2-D DFT), then 5 timed
-    solves and the periodic blur's launch time."""
+def run_boundary(kind: str, seed: int, grid, ladder, dev):
+    """The large workload under another boundary: periodic (KP_BC_PERIODIC,
+    the same image and PSF draws with periodic data, x_lambda by the 2-D DFT)
+    or reflexive (KP_BC_REFLEXIVE, the radial Moffat of the same draw, which
+    is symmetric in both axes, with reflexive data, x_lambda by the 2-D DCT).
+    Lambda by the device's KP-GCV, FP16-KP flexible PCG at the loosest
+    ladder tolerance whose x meets 1e-4 against the FP64 closed form, then 5
+    timed solves and the blur's launch time."""
     import torch
     import synthetic as S
-    from paper_2311_15393_amd import KP_BC_PERIODIC, KP_FPCG, KP_OK, KP_P16, Plan
-    from oracle import periodic as PB
-    prob = S.large_moffat_periodic(seed)
+    from paper_2311_15393_amd import KP_BC_PERIODIC, KP_BC_REFLEXIVE, KP_FPCG, KP_OK, KP_P16, Plan
+    if kind == "periodic":
+        from oracle import periodic as ref
+        prob, bc = S.large_moffat_periodic(seed), KP_BC_PERIODIC
+        what = "Moffat(beta=2.5)+motion PSF 63x63, periodic BC"
+    else:
+        from oracle import reflexive as ref
+        prob, bc = S.large_moffat_reflexive(seed), KP_BC_REFLEXIVE
+        what = "radial Moffat(beta=2.5) PSF 63x63, reflexive BC"
     n = prob.n
     b = torch.from_numpy(prob.b).to(dev)
     torch.cuda.synchronize()
     t0 = time.time()
-    plan = Plan(prob.psf, n, bc=KP_BC_PERIODIC)
+    plan = Plan(prob.psf, n, bc=bc)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     info0 = plan.query()
     lam, _ = plan.gcv(b, grid)
     gidx = int(np.argmin(np.abs(grid - lam)))
-    xlam = PB.x_lambda(prob.psf, prob.b.astype(np.float64), lam)
+    xlam = ref.x_lambda(prob.psf, prob.b.astype(np.float64), lam)
     mode = KP_FPCG | KP_P16
 
     def run(tol):
@@ -505,10 +516,10 @@ def run_periodic(seed: int, grid, ladder, dev):
     plan.time_blur(p, q, reps=3)
     blur_us = plan.time_blur(p, q, reps=20) * 1e3
     plan.close()
-    log(f"[bench] periodic: lambda={lam:.4g} tol={tol:.0e} iters={info.iters} err={err:.2e} "
+    log(f"[bench] {kind}: lambda={lam:.4g} tol={tol:.0e} iters={info.iters} err={err:.2e} "
         f"{ms:.3f} ms/solve; blur {blur_us:.1f} us; setup {setup_s:.2f}s")
-    return {"workload": ("deblur 1024x1024, Moffat(beta=2.5)+motion PSF 63x63, periodic BC, "
-                         "2% noise, lambda by KP-GCV (32-pt grid), FP16-KP flexible PCG"),
+    return {"workload": (f"deblur 1024x1024, {what}, 2% noise, lambda by KP-GCV (32-pt grid), "
+                         "FP16-KP flexible PCG"),
             "lambda": lam, "gcv_grid_index": gidx, "tol": tol, "iters": info.iters,
             "rel_err": err, "ok": bool(info.status == KP_OK and err <= 1e-4),
             "ms_per_solve": ms, "solves_per_s": 1e3 / ms, "setup_s": setup_s,

@@ -132,6 +132,15 @@ def _motion_line(length: float, angle: float, size: int) -> np.ndarray:
     return img / img.sum()
 
 
+def psf_moffat(k: int, alpha: float, beta: float) -> np.ndarray:
+    """Radial Moffat turbulence profile (1 + r^2/alpha^2)^(-beta) on a k x k
+    support, unit sum; symmetric in both axes."""
+    if k % 2 != 1:
+        raise ValueError("PSF support must be odd")
+    y, x = _offsets(k)
+    return _finish((1.0 + (x * x + y * y) / (alpha * alpha)) ** (-beta))
+
+
 def psf_moffat_motion(k: int, alpha: float, beta: float, length: float,
                       angle: float) -> np.ndarray:
     """Moffat turbulence profile (1 + r^2/alpha^2)^(-beta) convolved with a
@@ -178,12 +187,23 @@ def _blur_for_data_periodic(psf: np.ndarray, x: np.ndarray) -> np.ndarray:
     return scipy.signal.fftconvolve(np.pad(x, h, mode="wrap"), psf, mode="valid")
 
 
+def _blur_for_data_reflexive(psf: np.ndarray, x: np.ndarray) -> np.ndarray:
+    # the image extended by h on every side by half-sample reflection
+    # (numpy's 'symmetric' padding repeats the edge sample), then the 'valid'
+    # part of the linear convolution
+    h = (psf.shape[0] - 1) // 2
+    return scipy.signal.fftconvolve(np.pad(x, h, mode="symmetric"), psf, mode="valid")
+
+
 def make_problem(n: int, psf: np.ndarray, rng: np.random.Generator,
                  noise_level: float, lam: float | None, seed: int, kind: str,
-                 x_true: np.ndarray | None = None, periodic: bool = False) -> Problem:
+                 x_true: np.ndarray | None = None, periodic: bool = False,
+                 reflexive: bool = False) -> Problem:
     if x_true is None:
         x_true = true_image(rng, n)
-    b_true = (_blur_for_data_periodic if periodic else _blur_for_data)(psf, x_true)
+    blur = (_blur_for_data_periodic if periodic else
+            _blur_for_data_reflexive if reflexive else _blur_for_data)
+    b_true = blur(psf, x_true)
     g = rng.standard_normal((n, n))
     eps = noise_level * np.linalg.norm(b_true) * g / np.linalg.norm(g)
     b32 = (b_true + eps).astype(np.float32)
@@ -235,6 +255,21 @@ def large_moffat_periodic(seed: int = 0, n: int = 1024, k: int = 63) -> Problem:
     psf = psf_moffat_motion(k, alpha, 2.5, length, angle)
     return make_problem(n, psf, rng, 0.02, None, seed, "moffat63-periodic", x_true=x,
                         periodic=True)
+
+
+def large_moffat_reflexive(seed: int = 0, n: int = 1024, k: int = 63) -> Problem:
+    """1024 x 1024, radial Moffat turbulence (beta = 2.5, alpha ~ U[3,8],
+    the draw of large_moffat without its motion segment, so the PSF is
+    symmetric in both axes) on a 63 x 63 support, reflexive data (the image
+    extended by half-sample reflection, K <= n), 2% noise."""
+    rng = np.random.default_rng(seed)
+    x = true_image(rng, n)
+    alpha = rng.uniform(3.0, 8.0)
+    rng.uniform(3.0, 9.0)          # the motion draws of large_moffat, unused
+    rng.uniform(0.0, math.pi)
+    psf = psf_moffat(k, alpha, 2.5)
+    return make_problem(n, psf, rng, 0.02, None, seed, "moffat63-reflexive", x_true=x,
+                        reflexive=True)
 
 
 BATCH_SIZES = (128, 256, 384, 512, 768, 1024)

@@ -114,3 +114,20 @@ def test_corner_response_closed_form():
         e = np.zeros((n, n))
         e[0, 0] = 1.0
         assert np.abs(RB.corner_response(psf, n) - RB.blur(psf, e)).max() < 1e-15
+
+
+def test_reflexive_data_generator_matches_oracle_blur():
+    """The synthetic reflexive workload's data model (numpy 'symmetric'
+    padding, i.e. half-sample reflection, then the 'valid' linear
+    convolution) is the oracle's reflexive A, and its PSF is symmetric."""
+    import synthetic as S
+    from synthetic.problems import _blur_for_data_reflexive
+    rng = np.random.default_rng(12)
+    for n, k in ((40, 9), (33, 15), (15, 15)):
+        psf = _sym_psf(rng, k)
+        x = rng.standard_normal((n, n))
+        assert np.abs(_blur_for_data_reflexive(psf, x) - RB.blur(psf, x)).max() < 1e-10
+    p = S.large_moffat_reflexive(0, n=96, k=15)
+    assert RB.is_symmetric_psf(p.psf, rel=0.0)
+    noise = p.b.astype(np.float64) - RB.blur(p.psf, p.x_true)
+    assert abs(np.linalg.norm(noise) - p.noise_norm) < 1e-9 * p.noise_norm
