@@ -93,6 +93,10 @@ extern "C" {
                                    cost per iteration; equal to the default
                                    for separable PSFs.  An extension of the
                                    paper's preconditioner.                 */
+#define KP_HIST 0x1000          /* pcg_solve: record the residual history
+                                   of the solve in the plan (kp_get_history) */
+#define KP_HIST_MAX 16384       /* history entries kept: iterations 0 ..
+                                   KP_HIST_MAX - 1                         */
 
 typedef struct kp_plan_s *kp_plan_t;   /* opaque */
 
@@ -195,7 +199,9 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t *out);
  * KP_BREAKDOWN (with a finite iterate), it is restarted from its last
  * iterate with the FP32 preconditioner and its own budget of maxit
  * iterations (info->iters counts both runs, info->fallback = 1); mode bit
- * KP_NO_FALLBACK turns this off (the restart keeps KP_EXACT_DIAG).
+ * KP_NO_FALLBACK turns this off (the restart keeps KP_EXACT_DIAG and
+ * KP_HIST).  With KP_HIST the residual after every iteration is recorded
+ * in the plan for kp_get_history (one FP64 store per scalar step).
  * Returns KP_OK (true relative residual <= tol), KP_OK_FALLBACK, KP_MAXIT,
  * KP_BREAKDOWN or an error.  Synchronises `stream` (it reads back the
  * convergence state).
@@ -436,6 +442,27 @@ int kp_get_diag(kp_plan_t plan, float *d0);
    NULL, V_c, V_r as FP64 row-major n x n host arrays (V[i*n + a] = V(i,a)). */
 int kp_get_factors(kp_plan_t plan, double *sc, double *sr, double *vc,
                    double *vr);
+
+/*
+ * kp_get_history -- the residual history of the plan's last pcg_solve run
+ * with mode bit KP_HIST: the convergence curve of the iteration (the
+ * quantity behind the relative-error-per-iteration figures of Section 5),
+ * relative to ||A^T b||.
+ *   relres_rec   host, cap doubles (or NULL): entry k is ||r_k|| / ||A^T b||
+ *                of the recurrence residual after iteration k (k = 0: r_0 =
+ *                A^T b, so 1.0), before any true-residual replacement at k
+ *   relres_true  host, cap doubles (or NULL): entry k is ||c - H x_k|| /
+ *                ||A^T b|| where a true residual was formed at iteration k
+ *                (replacement, warm start, final check), else NaN
+ *   cap          >= 0 entries to copy; count (out) receives the number
+ *                recorded, min(iterations + 1, KP_HIST_MAX) (0 if the last
+ *                solve ran without KP_HIST or had zero or non-finite data)
+ * After the automatic FP32 restart the history is that of the restart.
+ * Synchronises `stream`.  Returns KP_OK or KP_ERR_ARG (null plan or count,
+ * cap < 0) / KP_ERR_HIP.
+ */
+int kp_get_history(kp_plan_t plan, double *relres_rec, double *relres_true,
+                   int cap, int *count, void *stream);
 
 #ifdef __cplusplus
 }

@@ -352,9 +352,10 @@ __global__ __launch_bounds__(256) void scalar_batched_kernel(const ItemDesc* __r
         c->done = BREAKDOWN;
       } else {
         if (c->first) { c->beta = 0.0; c->first = 0; }
-        else if (c->solver == KP_PCG) c->beta = S / c->rho;
+        else if (c->solver == KP_PCG || c->fr_next) c->beta = S / c->rho;
         else c->beta = -S2 / c->delta;
         c->rho = S;
+        c->fr_next = 0;
       }
       break;
     case SC_RHS:
@@ -376,6 +377,8 @@ __global__ __launch_bounds__(256) void scalar_batched_kernel(const ItemDesc* __r
       if (c->solver == KP_CG) {
         if (done == PENDING) c->beta = S / c->rho_prev;
         c->rho = S;
+      } else {
+        c->fr_next = 1;
       }
       if (!isfinite(S)) c->done = BREAKDOWN;
       else if (S <= c->tol2) c->done = CONVERGED;

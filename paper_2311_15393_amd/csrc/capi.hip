@@ -95,6 +95,7 @@ size_t layout(int n, int k, char* base, Plan* P) {
                           128 + 2 * 64 * 256);
   Q.ctrl = b.take<Ctrl>(1);
   Q.partials = b.take<double>((size_t)NSLOTS * MAX_PARTIALS);
+  Q.hist = b.take<double>(2 * (size_t)KP_HIST_MAX);
   (void)Q;
   return (b.cur + ALIGN - 1) / ALIGN * ALIGN;
 }
@@ -366,10 +367,14 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   c.done = RUNNING;
   c.pscale = 1.0f;
   c.zscale = (float)(1.0 / lam2d);
+  const bool hist = (mode & KP_HIST) != 0;
+  c.hist = hist ? P.hist : nullptr;
+  P.hist_count = 0;
   // nothing of this plan may still be publishing when the mirror is reset
   // (a no-op wait when the stream is idle, as after the previous solve)
   HIPCHK(hipStreamSynchronize(s));
   std::memset(P.mirror, 0, sizeof(CtrlMirror));
+  if (hist) HIPCHK(launch_fill_f64(P.hist, 2 * KP_HIST_MAX, std::nan(""), s));
   int rc = write_ctrl(P, s, c);
   if (rc != KP_OK) return rc;
   if (mode & KP_WARM) HIPCHK(launch_convert_x(P, x, false, s));
@@ -485,6 +490,10 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   const volatile CtrlMirror* fm = P.mirror;       // complete: the stream has drained
   const double gamma0sq = fm->gamma0sq, true_rr = fm->true_rr, rr = fm->rr, tol2 = fm->tol2;
   const int iters = fm->iter;
+  if (hist && gamma0sq > 0.0 && std::isfinite(gamma0sq)) {
+    P.hist_count = iters + 1 < KP_HIST_MAX ? iters + 1 : KP_HIST_MAX;
+    P.hist_gamma0sq = gamma0sq;
+  }
   if (!(gamma0sq > 0.0) || !std::isfinite(gamma0sq)) {
     // zero data: x = 0 is the solution; non-finite data: nothing to do
     const bool zero = gamma0sq == 0.0;
@@ -523,7 +532,8 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
   if (!(lambda > 0.0) || !std::isfinite(lambda) || !(tol > 0.0) || !std::isfinite(tol) ||
       maxit < 1)
     return KP_ERR_ARG;
-  if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM | KP_NO_FALLBACK | KP_EXACT_DIAG)) != 0)
+  if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM | KP_NO_FALLBACK | KP_EXACT_DIAG |
+                KP_HIST)) != 0)
     return KP_ERR_ARG;
   kp_info_t first;
   const int st = solve_once(plan, b, lambda, tol, maxit, mode & ~KP_NO_FALLBACK, x, &first,
@@ -541,8 +551,8 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
   // iterate with the FP32 preconditioner (its own budget of maxit iterations)
   kp_info_t second;
   const int st2 = solve_once(plan, b, lambda, tol, maxit,
-                             (mode & (KP_SOLVER_MASK | KP_NO_FALLBACK | KP_EXACT_DIAG)) | KP_P32 |
-                                 KP_WARM,
+                             (mode & (KP_SOLVER_MASK | KP_NO_FALLBACK | KP_EXACT_DIAG | KP_HIST)) |
+                                 KP_P32 | KP_WARM,
                              x,
                              &second, stream);
   if (st2 < 0) return st2;
@@ -554,6 +564,26 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
     info->status = st2 == KP_OK ? KP_OK_FALLBACK : st2;
   }
   return st2 == KP_OK ? KP_OK_FALLBACK : st2;
+}
+
+int kp_get_history(kp_plan_t plan, double* relres_rec, double* relres_true, int cap, int* count,
+                   void* stream) {
+  if (!plan || !count || cap < 0) return KP_ERR_ARG;
+  Plan& P = plan->P;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  *count = P.hist_count;
+  const int m = cap < P.hist_count ? cap : P.hist_count;
+  if (m == 0 || (!relres_rec && !relres_true)) return KP_OK;
+  std::vector<double> h(2 * (size_t)m);
+  HIPCHK(hipMemcpyAsync(h.data(), P.hist, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(h.data() + m, P.hist + KP_HIST_MAX, sizeof(double) * m,
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int k = 0; k < m; ++k) {
+    if (relres_rec) relres_rec[k] = std::sqrt(h[k] / P.hist_gamma0sq);
+    if (relres_true) relres_true[k] = std::sqrt(h[m + k] / P.hist_gamma0sq);
+  }
+  return KP_OK;
 }
 
 int pcg_solve_batched(const kp_plan_t* plans, int nplans, const float* const* b,

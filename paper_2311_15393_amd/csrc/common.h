@@ -72,7 +72,12 @@ struct Ctrl {
   int pub;          // publications to the host mirror so far (CtrlMirror)
   int fastu;        // batched solves: u = b - A x of a full true residual is
                     // formed on the item's fast blur (TR_FASTU_TOL_*)
-  int pad_;
+  int fr_next;      // a true residual replaced r: the next beta is
+                    // Fletcher-Reeves (the Polak-Ribiere form -z.Hp / delta
+                    // assumes r_new = r_old - alpha Hp, which the
+                    // replacement breaks; with one unknown it cancels p)
+  double* hist;     // KP_HIST: ||r_k||^2 at [k], true residuals at
+                    // [KP_HIST_MAX + k]; null when not recording
 };
 
 // The convergence state as the scalar steps publish it to coherent pinned
@@ -236,6 +241,9 @@ struct Plan {
   double* spec = nullptr;        // spectral scratch (GCV)
   Ctrl* ctrl = nullptr;
   double* partials = nullptr;
+  double* hist = nullptr;        // residual history (2 KP_HIST_MAX FP64)
+  int hist_count = 0;            // entries recorded by the last solve
+  double hist_gamma0sq = 0.0;    // its ||A^T b||^2
   Ctrl* host_ctrl = nullptr;     // pinned
   CtrlMirror* mirror = nullptr;  // coherent pinned host memory (host address)
   CtrlMirror* mirror_dev = nullptr;  // its device address
@@ -292,6 +300,7 @@ enum ScalarKind : int {
   SC_NORM = 6,     // ||r||^2 -> preconditioner scales only
 };
 hipError_t launch_scalar(const Plan& P, int kind, int nb, hipStream_t s);
+hipError_t launch_fill_f64(double* a, int count, double v, hipStream_t s);
 hipError_t launch_init_ctrl(const Plan& P, const Ctrl& host, hipStream_t s);
 
 hipError_t launch_precond(const Plan& P, const float* r, float* z, const float* w,

@@ -219,12 +219,13 @@ __global__ __launch_bounds__(ST) void scalar_kernel(Ctrl* __restrict__ c,
         if (c->first) {
           c->beta = 0.0;
           c->first = 0;
-        } else if (c->solver == KP_PCG) {
+        } else if (c->solver == KP_PCG || c->fr_next) {
           c->beta = rz / c->rho;            // Fletcher-Reeves
         } else {
           c->beta = -zw / c->delta;         // Polak-Ribiere = -alpha (z.Hp) / rho
         }
         c->rho = rz;
+        c->fr_next = 0;
       }
       break;
     }
@@ -247,6 +248,8 @@ __global__ __launch_bounds__(ST) void scalar_kernel(Ctrl* __restrict__ c,
       if (c->solver == KP_CG) {
         if (done == PENDING) c->beta = S / c->rho_prev;
         c->rho = S;
+      } else {
+        c->fr_next = 1;
       }
       if (!isfinite(S)) c->done = BREAKDOWN;
       else if (S <= c->tol2) c->done = CONVERGED;
@@ -260,6 +263,14 @@ __global__ __launch_bounds__(ST) void scalar_kernel(Ctrl* __restrict__ c,
       c->rr = S;
       set_scales(c, S);
       break;
+  }
+  // KP_HIST: the recurrence norm after each iteration (and r_0 = c), and
+  // every true residual at the iteration it was formed
+  double* hist = c->hist;
+  const int it = c->iter;
+  if (hist != nullptr && it >= 0 && it < KP_HIST_MAX) {
+    if (kind == SC_RR || kind == SC_RHS) hist[it] = S;
+    else if (kind == SC_TRUE || kind == SC_TRUE_INFO) hist[KP_HIST_MAX + it] = S;
   }
   const bool publish = kind == SC_RR || kind == SC_BETA || kind == SC_RHS || kind == SC_TRUE ||
                        kind == SC_TRUE_INFO || (kind == SC_ALPHA && c->done != RUNNING);
@@ -280,6 +291,17 @@ __global__ __launch_bounds__(ST) void scalar_kernel(Ctrl* __restrict__ c,
     m->iter = c->iter;
     m->word = w;
   }
+}
+
+__global__ __launch_bounds__(VT) void fill_f64_kernel(double* __restrict__ a, int count,
+                                                      double v) {
+  for (int i = blockIdx.x * VT + threadIdx.x; i < count; i += gridDim.x * VT) a[i] = v;
+}
+
+hipError_t launch_fill_f64(double* a, int count, double v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3(vec_blocks(count)), dim3(VT), 0, s, a, count, v);
+  return hipGetLastError();
 }
 
 hipError_t launch_scalar(const Plan& P, int kind, int nb, hipStream_t s) {

@@ -25,6 +25,8 @@ KP_WARM = 0x100
 KP_BATCH_EAGER = 0x200
 KP_NO_FALLBACK = 0x400
 KP_EXACT_DIAG = 0x800
+KP_HIST = 0x1000
+KP_HIST_MAX = 16384
 KP_MAX_PSF = 63
 KP_BC_ZERO = 0
 KP_BC_PERIODIC = 1
@@ -89,6 +91,8 @@ _SIGS = {
     "kp_precond": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP, _VP]),
     "kp_get_factors": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "kp_get_diag": (ctypes.c_int, [_VP, _VP]),
+    "kp_get_history": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                      _VP]),
     "kp_time_blur": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_float), _VP]),
     "kp_time_precond": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP,
@@ -172,6 +176,10 @@ class SolveInfo:
     rhs_norm: float
     misfit: float = 0.0
     fallback: int = 0
+    # with history=True: ||r_k|| / ||A^T b|| of the recurrence after
+    # iteration k, and of the true residual where one was formed (else NaN)
+    history_rec: np.ndarray | None = None
+    history_true: np.ndarray | None = None
 
 
 def workspace_size(n: int, k: int) -> int:
@@ -240,20 +248,40 @@ class Plan:
 
     # -- the hot path -----------------------------------------------------
     def solve(self, b, lam: float, tol: float = 1e-6, maxit: int = 1000,
-              mode: int = KP_FPCG | KP_P16, x=None, stream=None, raise_on_fail=True):
+              mode: int = KP_FPCG | KP_P16, x=None, stream=None, raise_on_fail=True,
+              history: bool = False):
         import torch
         bp = _dev_image(b, self.n, "b")
         if x is None:
             x = torch.empty_like(b)
         xp = _dev_image(x, self.n, "x")
         info = _Info()
+        if history:
+            mode |= KP_HIST
         st = load().pcg_solve(self._h, bp, float(lam), float(tol), int(maxit), int(mode), xp,
                               ctypes.byref(info), _stream(stream))
         if st < 0 or (raise_on_fail and st not in (KP_OK, KP_OK_FALLBACK, KP_MAXIT)):
             raise KPError(st, "pcg_solve")
-        return x, SolveInfo(info.iters, st, info.replacements, info.relres_rec,
-                            info.relres_true, info.lambda_, info.rhs_norm, info.misfit,
-                            info.fallback)
+        out = SolveInfo(info.iters, st, info.replacements, info.relres_rec, info.relres_true,
+                        info.lambda_, info.rhs_norm, info.misfit, info.fallback)
+        if mode & KP_HIST:
+            out.history_rec, out.history_true = self.history(stream=stream)
+        return x, out
+
+    def history(self, stream=None):
+        """kp_get_history: (relres_rec, relres_true) of the last solve run
+        with KP_HIST (empty arrays if it ran without)."""
+        count = ctypes.c_int()
+        _check(load().kp_get_history(self._h, None, None, 0, ctypes.byref(count),
+                                     _stream(stream)), "kp_get_history")
+        m = count.value
+        rec, tru = np.empty(m), np.empty(m)
+        if m:
+            _check(load().kp_get_history(self._h, rec.ctypes.data_as(ctypes.c_void_p),
+                                         tru.ctypes.data_as(ctypes.c_void_p), m,
+                                         ctypes.byref(count), _stream(stream)),
+                   "kp_get_history")
+        return rec, tru
 
     def gcv(self, b, grid, omega: float = 1.0, stream=None):
         bp = _dev_image(b, self.n, "b")

@@ -184,8 +184,12 @@ def test_batch_mixes_valu_and_mfma_items():
 def test_batched_true_residual_matches_oracle(tol):
     """relres_true of every batched item (A^T of the FP64 data residual on
     each item's fast blur for tol >= 1e-7, in FP64 below) equals the oracle's
-    FP64 ||c - H x|| / ||c|| at the returned x, to within a tenth of tol.
-    Plans alternate between the MFMA and the VALU blur."""
+    FP64 ||c - H x|| / ||c|| at the returned x, to within a tenth of tol plus
+    the effect of returning x in FP32: the device certifies its FP64
+    iterate, and rounding it to FP32 (|dx_i| <= 2^-24 |x_i|) moves the
+    residual by at most ||H||_2 2^-24 ||x|| / ||c||, with ||H||_2 <=
+    (sum |P|)^2 + lambda^2 (zero-boundary convolution).  Plans alternate
+    between the MFMA and the VALU blur."""
     require_gpu()
     from paper_2311_15393_amd import KP_BLUR_MFMA, KP_FPCG, KP_OK, KP_P16, Plan
     probs, items = _small_batch()
@@ -203,8 +207,11 @@ def test_batched_true_residual_matches_oracle(tol):
             ref = float(np.linalg.norm(r) / np.linalg.norm(c))
             say(f"  n={pr.n} k={pr.k} lam={lam:.3g} iters={info.iters} "
                 f"relres_true={info.relres_true:.4e} oracle={ref:.4e}")
+            x64 = x.astype(np.float64)
+            rounding = ((np.abs(pr.psf).sum() ** 2 + lam * lam) * 2.0 ** -24
+                        * np.linalg.norm(x64) / np.linalg.norm(c))
             assert info.status == KP_OK and info.relres_true <= tol
-            assert abs(info.relres_true - ref) <= 0.1 * tol
+            assert abs(info.relres_true - ref) <= 0.1 * tol + rounding
     finally:
         for p in plans:
             p.close()

@@ -158,7 +158,7 @@ def test_edge_cases():
         assert info2.status == KP_OK and info2.iters == 0
         say("edge: invalid arguments")
         for kw in ({"lam": -1.0}, {"lam": 0.0}, {"lam": float("nan")}, {"tol": 0.0},
-                   {"maxit": 0}, {"mode": 3}, {"mode": 0x30}, {"mode": 0x1000}):
+                   {"maxit": 0}, {"mode": 3}, {"mode": 0x30}, {"mode": 0x2000}):
             args = {"lam": 0.02, "tol": 1e-6, "maxit": 10, "mode": KP_PCG}
             args.update(kw)
             with pytest.raises(KPError) as ei:

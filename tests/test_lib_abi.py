@@ -89,6 +89,10 @@ def test_null_plan_arguments():
     assert lib.kp_destroy(None) == -1
     assert lib.pcg_solve(None, None, 0.1, 1e-6, 10, 0, None, None, None) == -1
     assert lib.gcv_lambda(None, None, None, 0, 1.0, None, None, None) == -1
+    import ctypes
+    count = ctypes.c_int(7)
+    assert lib.kp_get_history(None, None, None, 4, ctypes.byref(count), None) == -1
+    assert count.value == 7
 
 
 def test_binding_constants_match_header():
