@@ -115,6 +115,11 @@ typedef struct kp_info_s {
     double  rhs_norm;       /* ||A^T b||_2                                 */
     double  misfit;         /* ||A x - b||_2 (pcg_solve_batched only; 0 for
                                pcg_solve)                                 */
+    float   ms;             /* pcg_solve: device time in milliseconds
+                               between HIP events recorded on `stream`
+                               around all the work it enqueued (the FP32
+                               restart included); 0 for pcg_solve_batched */
+    int32_t reserved;
 } kp_info_t;
 
 /* Properties of a plan (the Kronecker approximation it holds). */

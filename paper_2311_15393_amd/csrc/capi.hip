@@ -316,6 +316,8 @@ int kp_destroy(kp_plan_t plan) {
   hipDeviceSynchronize();
   if (P.mirror) hipHostFree(P.mirror);
   if (P.host_ctrl) hipHostFree(P.host_ctrl);
+  if (P.ev_start) hipEventDestroy(P.ev_start);
+  if (P.ev_end) hipEventDestroy(P.ev_end);
   if (P.owns && P.base) hipFree(P.base);
   delete plan;
   return KP_OK;
@@ -486,6 +488,7 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   // stays 0 for zero or non-finite data)
   if (state != CONVERGED) HIPCHK(true_residual(false));
   HIPCHK(launch_convert_x(P, x, true, s));
+  HIPCHK(hipEventRecord(P.ev_end, s));
   HIPCHK(hipStreamSynchronize(s));
   const volatile CtrlMirror* fm = P.mirror;       // complete: the stream has drained
   const double gamma0sq = fm->gamma0sq, true_rr = fm->true_rr, rr = fm->rr, tol2 = fm->tol2;
@@ -535,10 +538,30 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
   if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM | KP_NO_FALLBACK | KP_EXACT_DIAG |
                 KP_HIST)) != 0)
     return KP_ERR_ARG;
-  kp_info_t first;
+  Plan& P = plan->P;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (!P.ev_start) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return KP_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+      hipEventDestroy(e0);
+      return KP_ERR_HIP;
+    }
+    P.ev_start = e0;
+    P.ev_end = e1;
+  }
+  HIPCHK(hipEventRecord(P.ev_start, s));
+  // device time from the start event to the end event of the last run
+  // (solve_once records the end event before its closing synchronisation)
+  auto elapsed = [&]() -> float {
+    float ms = 0.0f;
+    return hipEventElapsedTime(&ms, P.ev_start, P.ev_end) == hipSuccess ? ms : 0.0f;
+  };
+  kp_info_t first{};
   const int st = solve_once(plan, b, lambda, tol, maxit, mode & ~KP_NO_FALLBACK, x, &first,
                             stream);
   if (st < 0) return st;
+  first.ms = elapsed();
   const int solver = mode & KP_SOLVER_MASK, prec = mode & KP_PREC_MASK;
   const bool retry = (st == KP_MAXIT || st == KP_BREAKDOWN) && solver != KP_CG &&
                      prec != KP_P32 && !(mode & KP_NO_FALLBACK) &&
@@ -549,7 +572,7 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
   }
   // reduced-precision preconditioner did not reach tol: restart from the last
   // iterate with the FP32 preconditioner (its own budget of maxit iterations)
-  kp_info_t second;
+  kp_info_t second{};
   const int st2 = solve_once(plan, b, lambda, tol, maxit,
                              (mode & (KP_SOLVER_MASK | KP_NO_FALLBACK | KP_EXACT_DIAG | KP_HIST)) |
                                  KP_P32 | KP_WARM,
@@ -562,6 +585,7 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
     info->replacements = first.replacements + second.replacements;
     info->fallback = 1;
     info->status = st2 == KP_OK ? KP_OK_FALLBACK : st2;
+    info->ms = elapsed();
   }
   return st2 == KP_OK ? KP_OK_FALLBACK : st2;
 }

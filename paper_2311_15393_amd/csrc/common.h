@@ -244,6 +244,8 @@ struct Plan {
   double* hist = nullptr;        // residual history (2 KP_HIST_MAX FP64)
   int hist_count = 0;            // entries recorded by the last solve
   double hist_gamma0sq = 0.0;    // its ||A^T b||^2
+  hipEvent_t ev_start = nullptr;  // pcg_solve timing (created on first use)
+  hipEvent_t ev_end = nullptr;
   Ctrl* host_ctrl = nullptr;     // pinned
   CtrlMirror* mirror = nullptr;  // coherent pinned host memory (host address)
   CtrlMirror* mirror_dev = nullptr;  // its device address

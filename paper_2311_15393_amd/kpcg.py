@@ -48,7 +48,8 @@ class _Info(ctypes.Structure):
                 ("replacements", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("relres_rec", ctypes.c_double), ("relres_true", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("rhs_norm", ctypes.c_double),
-                ("misfit", ctypes.c_double)]
+                ("misfit", ctypes.c_double), ("ms", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -176,6 +177,7 @@ class SolveInfo:
     rhs_norm: float
     misfit: float = 0.0
     fallback: int = 0
+    ms: float = 0.0             # device time of the solve (pcg_solve)
     # with history=True: ||r_k|| / ||A^T b|| of the recurrence after
     # iteration k, and of the true residual where one was formed (else NaN)
     history_rec: np.ndarray | None = None
@@ -263,7 +265,7 @@ class Plan:
         if st < 0 or (raise_on_fail and st not in (KP_OK, KP_OK_FALLBACK, KP_MAXIT)):
             raise KPError(st, "pcg_solve")
         out = SolveInfo(info.iters, st, info.replacements, info.relres_rec, info.relres_true,
-                        info.lambda_, info.rhs_norm, info.misfit, info.fallback)
+                        info.lambda_, info.rhs_norm, info.misfit, info.fallback, info.ms)
         if mode & KP_HIST:
             out.history_rec, out.history_true = self.history(stream=stream)
         return x, out

@@ -11,6 +11,8 @@ which CG's loss of orthogonality takes over).  The device also replaces its
 recurrence residual by the true residual every 1000x drop, which moves later
 entries by ~1e-7 ||A^T b||.  The comparison below is at 1e-3 relative, over
 the first 40 (PCG) and 25 (CG) iterations."""
+import time
+
 import numpy as np
 import pytest
 
@@ -65,8 +67,8 @@ def test_history_follows_oracle_iteration(case):
 def test_history_fp16_structure_warm_start_and_off():
     """FP16-KP FPCG: one entry per iteration, a true residual formed at the
     first iteration whose recurrence residual meets the tolerance, a warm
-    start's true residual at entry 0, and no history for a solve without
-    the bit."""
+    start's true residual at entry 0, no history for a solve without the
+    bit, and the solve's device time in info.ms."""
     torch = require_gpu()
     from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, KP_WARM, Plan
     p = S.mid_anisotropic(1)
@@ -90,8 +92,15 @@ def test_history_fp16_structure_warm_start_and_off():
         assert info2.status == KP_OK
         assert info2.history_rec[0] == 1.0
         assert np.isfinite(info2.history_true[0]) and info2.history_true[0] < 1e-3
-        # a solve without KP_HIST leaves no history
+        # a solve without KP_HIST leaves no history; its device time (HIP
+        # events on the stream around the call's work) lies within the
+        # call's wall time
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         _, info3 = plan.solve(b, p.lam, tol=tol, maxit=300, mode=KP_FPCG | KP_P16, x=x2)
+        wall_ms = (time.perf_counter() - t0) * 1e3
+        say(f"  solve device time {info3.ms:.3f} ms, wall {wall_ms:.3f} ms")
+        assert 0.0 < info3.ms <= wall_ms + 0.05
         assert info3.history_rec is None
         r3, t3 = plan.history()
         assert r3.size == 0 and t3.size == 0
