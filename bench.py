@@ -136,6 +136,9 @@ def main():
                          "--profile-only)")
     ap.add_argument("--batch", type=int, default=0, metavar="P",
                     help="also run the uneven batched workload with P problems x 16 lambda")
+    ap.add_argument("--instances", type=int, default=0, metavar="S",
+                    help="also run the FP16 headline on seeds 0 .. S-1 of the large workload "
+                         "(GCV index and 1e-4 parity against the oracle per seed)")
     ap.add_argument("--matvec-sweep", action="store_true",
                     help="only compare the direct blurs with a zero-padded rocFFT H p over K "
                          "(prints its own JSON line)")
@@ -341,6 +344,10 @@ def main():
     lowp = None
     if not args.profile_only:
         lowp = run_lowp_setup(prob, b, lam, results["fp16_kp_fpcg"]["tol"], xlam, setup_s)
+    instances = None
+    if args.instances and not args.profile_only:
+        instances = run_instances(args.instances, grid, ladder, args.steps, args.warmup, dev,
+                                  nthreads)
     periodic = reflexive = None
     if not args.profile_only and not args.no_periodic:
         periodic = run_boundary("periodic", args.seed, grid, ladder, dev)
@@ -374,6 +381,7 @@ def main():
             "batched": batch,
             "periodic": periodic,
             "reflexive": reflexive,
+            "instances": instances,
             "lowp_setup": lowp,
         },
         "roofline": roofline,
@@ -525,6 +533,63 @@ def run_boundary(kind: str, seed: int, grid, ladder, dev):
             "ms_per_solve": ms, "solves_per_s": 1e3 / ms, "setup_s": setup_s,
             "kp_rel_error": info0["kp_rel_error"], "blur_config": info0["blur_config"],
             "blur_us": blur_us}
+
+
+def run_instances(count: int, grid, ladder, steps: int, warmup: int, dev, nthreads: int):
+    """The headline FP16-KP FPCG solve on seeds 0 .. count-1 of the large
+    workload, each with its own image, Moffat + motion PSF and noise: the
+    device's KP-GCV grid index must equal the oracle's, the tolerance is the
+    loosest ladder value whose x meets 1e-4 against the oracle's x_lambda,
+    then `warmup` untimed and `steps` timed solves."""
+    import torch
+    from threadpoolctl import threadpool_limits
+    import synthetic as S
+    from oracle import kp as KP
+    from oracle import lam as L
+    from oracle import solvers as SV
+    from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, Plan
+    rows = []
+    for seed in range(count):
+        prob = S.large_moffat(seed)
+        n = prob.n
+        b = torch.from_numpy(prob.b).to(dev)
+        plan = Plan(prob.psf, n)
+        lam, _ = plan.gcv(b, grid)
+        gidx = int(np.argmin(np.abs(grid - lam)))
+        with threadpool_limits(limits=nthreads):
+            kp = KP.kp_svd(prob.psf, n)
+            s2, bh2 = L.spectrum(kp, prob.b.astype(np.float64))
+            ref_idx = L.grid_argmin(L.gcv(s2, bh2, grid))
+            xlam, _ = SV.x_lambda_iterative(prob.psf, prob.b.astype(np.float64), lam, kp=kp,
+                                            workers=nthreads, check=False)
+        x = torch.empty_like(b)
+        for tol in ladder:
+            _, info = plan.solve(b, lam, tol=tol, maxit=200, mode=KP_FPCG | KP_P16, x=x,
+                                 raise_on_fail=False)
+            err = float(np.linalg.norm(x.cpu().numpy().astype(np.float64) - xlam)
+                        / np.linalg.norm(xlam))
+            if info.status == KP_OK and err <= 1e-4:
+                break
+        for _ in range(warmup):
+            plan.solve(b, lam, tol=tol, maxit=200, mode=KP_FPCG | KP_P16, x=x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.solve(b, lam, tol=tol, maxit=200, mode=KP_FPCG | KP_P16, x=x)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        plan.close()
+        row = {"seed": seed, "lambda": lam, "gcv_grid_index": gidx,
+               "oracle_gcv_grid_index": ref_idx, "tol": tol, "iters": info.iters,
+               "rel_err": err, "ok": bool(info.status == KP_OK and err <= 1e-4
+                                          and gidx == ref_idx),
+               "ms_per_solve": ms, "solves_per_s": 1e3 / ms}
+        log(f"[bench] instance seed {seed}: lambda={lam:.4g} (index {gidx}, oracle {ref_idx}) "
+            f"tol={tol:.0e} iters={info.iters} err={err:.2e} {ms:.3f} ms/solve")
+        rows.append(row)
+    sps = [r["solves_per_s"] for r in rows]
+    return {"rows": rows, "median_solves_per_s": float(np.median(sps)),
+            "all_ok": all(r["ok"] for r in rows)}
 
 
 def smooth_size(m: int) -> int:
