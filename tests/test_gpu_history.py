@@ -105,3 +105,16 @@ def test_history_fp16_structure_warm_start_and_off():
         r3, t3 = plan.history()
         assert r3.size == 0 and t3.size == 0
     torch.cuda.synchronize()
+
+
+def test_batched_refuses_history():
+    """The batched path keeps no history: KP_HIST there is an argument error."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_FPCG, KP_HIST, KP_P16, KPError, Plan, solve_batched
+    from paper_2311_15393_amd.kpcg import KP_ERR_ARG
+    p = S.small_gaussian(0)
+    with Plan(p.psf, p.n) as plan:
+        with pytest.raises(KPError) as ei:
+            solve_batched([plan], [to_dev(p.b)], [p.lam], [0], tol=1e-6, maxit=50,
+                          mode=KP_FPCG | KP_P16 | KP_HIST)
+        assert ei.value.status == KP_ERR_ARG
