@@ -99,12 +99,9 @@ hipError_t launch_blur_f32(const Plan& P, const float* src, float* dst, bool tra
 }
 
 hipError_t launch_blur_normal(const Plan& P, const float* q, const float* p, float* w,
-                              float lam2, hipStream_t s) {
+                              float lam2, hipStream_t s, int* nb) {
   EpiNormalW e{p, w, lam2, P.n};
-  int nb;
-  hipError_t err = blur_dispatch(P.blur_cfg, P, q, P.taps32, e, P.ctrl, 1, s, &nb);
-  if (err != hipSuccess) return err;
-  return launch_scalar(P, SC_ALPHA, nb, s);
+  return blur_dispatch(P.blur_cfg, P, q, P.taps32, e, P.ctrl, 1, s, nb);
 }
 
 // Autotuner: time every FP32-VALU tile shape and the MFMA kernel on this

@@ -132,9 +132,10 @@ hipError_t enqueue_matvec_half(Plan& P, float lam2, hipStream_t s) {
   hipError_t e;
   e = launch_blur_f32(P, P.p, P.q, false, s, P.ctrl);           // q = A p
   if (e != hipSuccess) return e;
-  e = launch_blur_normal(P, P.q, P.p, P.w, lam2, s);            // w = A^T q + l^2 p, alpha
+  int nbd = 0;
+  e = launch_blur_normal(P, P.q, P.p, P.w, lam2, s, &nbd);      // w = A^T q + l^2 p, p.w
   if (e != hipSuccess) return e;
-  return launch_update(P, s);                                   // x, r, ||r||
+  return launch_update_alpha(P, nbd, s);                        // alpha; x, r, ||r||
 }
 
 hipError_t enqueue_iteration(Plan& P, int solver, int prec, float lam2, hipStream_t s) {

@@ -265,8 +265,9 @@ struct Plan {
 // ---------------------------------------------------------------------------
 hipError_t launch_blur_f32(const Plan& P, const float* src, float* dst, bool transpose,
                            hipStream_t s, const Ctrl* ctrl);
+// w = A^T q + lambda^2 p with the partials of p.w; *nb receives their count
 hipError_t launch_blur_normal(const Plan& P, const float* q, const float* p, float* w,
-                              float lam2, hipStream_t s);
+                              float lam2, hipStream_t s, int* nb);
 // r = c = A^T b on the plan's blur, ||c||^2 (the SC_RHS scalar step); also
 // p = w = 0 and, with zero_x, x = 0
 hipError_t launch_rhs(const Plan& P, const float* b, bool zero_x, hipStream_t s);
@@ -286,6 +287,8 @@ hipError_t launch_normal_fp64(const Plan& P, const float* x, double lam2, double
                               hipStream_t s);
 
 hipError_t launch_update(const Plan& P, hipStream_t s);
+// alpha = rho / p.Hp from the normal blur's nbd partials, then the update
+hipError_t launch_update_alpha(const Plan& P, int nbd, hipStream_t s);
 hipError_t launch_convert_x(const Plan& P, float* x, bool to_f32, hipStream_t s);
 hipError_t launch_pupdate(const Plan& P, hipStream_t s);
 hipError_t launch_norm_scale(const Plan& P, const float* v, hipStream_t s);

@@ -18,14 +18,10 @@ static inline int vec_blocks(int n4) {
   return b < 1 ? 1 : (b > VMAXB ? VMAXB : b);
 }
 
-// x += alpha p (FP64 accumulator) ; r -= alpha w ; ||r||^2
-__global__ __launch_bounds__(VT) void update_kernel(double* __restrict__ x,
-                                                    float* __restrict__ r,
-                                                    const float* __restrict__ p,
-                                                    const float* __restrict__ w, int N,
-                                                    Ctrl* ctrl, double* partials) {
-  if (ctrl->done != RUNNING) return;
-  const double ad = ctrl->alpha;
+// x += alpha p (FP64 accumulator) ; r -= alpha w ; ||r||^2 (partials)
+__device__ inline void update_body(double* __restrict__ x, float* __restrict__ r,
+                                   const float* __restrict__ p, const float* __restrict__ w,
+                                   int N, double ad, double* partials) {
   const float a = (float)ad;
   const int n4 = N >> 2;
   double d = 0.0;
@@ -58,6 +54,15 @@ __global__ __launch_bounds__(VT) void update_kernel(double* __restrict__ x,
   __shared__ double sh[VT / 64];
   const double v1[1] = {block_sum<VT>(d, sh)};
   write_partials<1>(v1, partials, SLOT_RR, blockIdx.x);
+}
+
+__global__ __launch_bounds__(VT) void update_kernel(double* __restrict__ x,
+                                                    float* __restrict__ r,
+                                                    const float* __restrict__ p,
+                                                    const float* __restrict__ w, int N,
+                                                    Ctrl* ctrl, double* partials) {
+  if (ctrl->done != RUNNING) return;
+  update_body(x, r, p, w, N, ctrl->alpha, partials);
 }
 
 // p = z + beta p
@@ -173,6 +178,8 @@ __device__ inline double sum_slot(const double* partials, int slot, int nb, doub
   return block_sum<ST>(s, sh);
 }
 
+__device__ inline void publish_mirror(Ctrl* __restrict__ c, CtrlMirror* __restrict__ mirror);
+
 // Every step that the host follows (the residual norm after an update, the
 // direction step, the right-hand side, true residuals, and a breakdown found
 // by the step length) publishes the new state to the host mirror.
@@ -274,23 +281,26 @@ __global__ __launch_bounds__(ST) void scalar_kernel(Ctrl* __restrict__ c,
   }
   const bool publish = kind == SC_RR || kind == SC_BETA || kind == SC_RHS || kind == SC_TRUE ||
                        kind == SC_TRUE_INFO || (kind == SC_ALPHA && c->done != RUNNING);
-  if (mirror != nullptr && publish) {
-    const unsigned p = ((unsigned)c->pub + 1u) & MIRROR_PUB_MASK;
-    c->pub = (int)p;
-    const bool tol_hit = c->rr <= c->tol2;
-    const bool anchor_ok = c->repl > 0 && c->true_rr <= ANCHOR_REL * ANCHOR_REL * c->gamma0sq;
-    const unsigned long long w =
-        (unsigned long long)p | ((unsigned long long)(c->iter & 0xffffff) << 24) |
-        ((unsigned long long)(c->done & 0xf) << 48) | ((unsigned long long)tol_hit << 52) |
-        ((unsigned long long)anchor_ok << 53) | ((unsigned long long)(c->repl & 0x3ff) << 54);
-    volatile CtrlMirror* m = mirror;
-    m->rr = c->rr;
-    m->true_rr = c->true_rr;
-    m->gamma0sq = c->gamma0sq;
-    m->tol2 = c->tol2;
-    m->iter = c->iter;
-    m->word = w;
-  }
+  if (mirror != nullptr && publish) publish_mirror(c, mirror);
+}
+
+// The new state to the host mirror (one thread).
+__device__ inline void publish_mirror(Ctrl* __restrict__ c, CtrlMirror* __restrict__ mirror) {
+  const unsigned p = ((unsigned)c->pub + 1u) & MIRROR_PUB_MASK;
+  c->pub = (int)p;
+  const bool tol_hit = c->rr <= c->tol2;
+  const bool anchor_ok = c->repl > 0 && c->true_rr <= ANCHOR_REL * ANCHOR_REL * c->gamma0sq;
+  const unsigned long long w =
+      (unsigned long long)p | ((unsigned long long)(c->iter & 0xffffff) << 24) |
+      ((unsigned long long)(c->done & 0xf) << 48) | ((unsigned long long)tol_hit << 52) |
+      ((unsigned long long)anchor_ok << 53) | ((unsigned long long)(c->repl & 0x3ff) << 54);
+  volatile CtrlMirror* m = mirror;
+  m->rr = c->rr;
+  m->true_rr = c->true_rr;
+  m->gamma0sq = c->gamma0sq;
+  m->tol2 = c->tol2;
+  m->iter = c->iter;
+  m->word = w;
 }
 
 __global__ __launch_bounds__(VT) void fill_f64_kernel(double* __restrict__ a, int count,
@@ -302,6 +312,62 @@ hipError_t launch_fill_f64(double* a, int count, double v, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_f64_kernel, dim3(vec_blocks(count)), dim3(VT), 0, s, a, count, v);
   return hipGetLastError();
+}
+
+// The step length fused into the update: every block sums the nbd
+// partials of p.Hp in the scalar step's order (ST == VT threads, the same
+// block_sum), so all blocks hold the same delta and alpha = rho / delta;
+// block 0 stores them (and a breakdown, which it publishes).  No block
+// reads a control-block field that block 0 writes here.
+static_assert(ST == VT, "the fused step must reduce in the scalar step's order");
+__global__ __launch_bounds__(VT) void update_alpha_kernel(double* __restrict__ x,
+                                                          float* __restrict__ r,
+                                                          const float* __restrict__ p,
+                                                          const float* __restrict__ w, int N,
+                                                          Ctrl* ctrl, double* partials, int nbd,
+                                                          CtrlMirror* __restrict__ mirror) {
+  if (ctrl->done != RUNNING) return;
+  __shared__ double shd[VT / 64];
+  __shared__ double s_delta;
+  const double S0 = sum_slot(partials, SLOT_DELTA, nbd, shd);     // valid in thread 0
+  if (threadIdx.x == 0) s_delta = S0;
+  __syncthreads();
+  const double S = s_delta;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (!(S > 0.0) || !isfinite(S)) {
+    if (lead) {
+      ctrl->delta = S;
+      ctrl->done = BREAKDOWN;
+      if (mirror != nullptr) publish_mirror(ctrl, mirror);
+    }
+    return;
+  }
+  const double ad = ctrl->rho / S;
+  if (lead) {
+    ctrl->delta = S;
+    ctrl->alpha = ad;
+  }
+  update_body(x, r, p, w, N, ad, partials);
+}
+
+// alpha from the nbd partials of the normal-equations blur, then the update
+// and ||r||^2; one launch when the partials are few enough for every block
+// to sum them
+constexpr int FUSED_ALPHA_MAX = 1024;
+
+hipError_t launch_update_alpha(const Plan& P, int nbd, hipStream_t s) {
+  if (nbd > FUSED_ALPHA_MAX) {
+    hipError_t e = launch_scalar(P, SC_ALPHA, nbd, s);
+    if (e != hipSuccess) return e;
+    return launch_update(P, s);
+  }
+  const int N = P.n * P.n;
+  const int nb = vec_blocks(N >> 2);
+  hipLaunchKernelGGL(update_alpha_kernel, dim3(nb), dim3(VT), 0, s, P.x64, P.r, P.p, P.w, N,
+                     P.ctrl, P.partials, nbd, P.mirror_dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_scalar(P, SC_RR, nb, s);
 }
 
 hipError_t launch_scalar(const Plan& P, int kind, int nb, hipStream_t s) {
