@@ -180,3 +180,37 @@ def test_work_unit_break_even_fixture():
                 vals[key] = float(v)
     mv, pc = vals["matvecs_per_iteration"], vals["preconditioner_cost_in_matvecs"]
     assert math.isclose(mv / (mv + pc), vals["break_even_ratio"], rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("mode", [SV.CG, SV.PCG])
+def test_residual_history_equals_krylov_galerkin_iterates(mode):
+    """The recurrence norms resnorms[k] are ||c - H x_k|| of the k-th
+    (P)CG iterate, which for SPD H and M is the Galerkin solution on the
+    Krylov space K_k(M^-1 H, M^-1 c): x_k = Q (Q^T H Q)^-1 Q^T c with Q an
+    orthonormal basis of that space (textbook characterisation, here formed
+    densely with scipy-built H, independent of the solver's recurrences)."""
+    n, k, lam = 8, 5, 0.1
+    psf, _, b = _small_problem(n, k, 21)
+    N = n * n
+    a = _library_dense_a(psf, n)
+    h = a.T @ a + lam * lam * np.eye(N)
+    c = a.T @ b.reshape(-1, order="F")
+    op = SV.NormalOperator(psf, n, lam)
+    if mode == SV.CG:
+        minv = np.eye(N)
+        pre = None
+    else:
+        kp = KP.kp_svd(psf, n)
+        pre = SV.kp_preconditioner(psf, n, lam, kp)
+        minv = np.column_stack([pre(np.eye(N)[:, q].reshape((n, n), order="F"))
+                                .reshape(-1, order="F") for q in range(N)])
+    out = SV.solve(op, b, mode=mode, tol=1e-14, maxit=8, precond=pre)
+    g = minv @ h
+    v = minv @ c
+    for it in range(1, min(7, out.iters + 1)):
+        kry = np.column_stack([np.linalg.matrix_power(g, j) @ v for j in range(it)])
+        q, _ = np.linalg.qr(kry)
+        xk = q @ np.linalg.solve(q.T @ h @ q, q.T @ c)
+        ref = np.linalg.norm(c - h @ xk)
+        assert abs(out.resnorms[it] - ref) <= 1e-7 * out.resnorms[0], (it, out.resnorms[it], ref)
+    assert out.resnorms[0] == pytest.approx(np.linalg.norm(c), rel=1e-12)
