@@ -183,7 +183,10 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t *out);
  *
  * Solver (mode & KP_SOLVER_MASK): CG, PCG with M = A_hat^T A_hat +
  * lambda^2 I applied as Z = V_c (S .* (V_c^T R V_r)) V_r^T (eq.
- * (PreconSolve)), or flexible PCG.  The same lambda is used in M and in the
+ * (PreconSolve)), or flexible PCG (Polak-Ribiere beta, Section 3; the one
+ * direction update after a true-residual replacement takes the
+ * Fletcher-Reeves beta, since the replacement breaks the recurrence the
+ * Polak-Ribiere form relies on).  The same lambda is used in M and in the
  * problem (Section 5.3).  Preconditioner precision: mode & KP_PREC_MASK.
  * Vectors are FP32, matvecs FP32; the solution is accumulated in FP64 on
  * the device and the scalars alpha, beta, ||r|| are accumulated and kept in
