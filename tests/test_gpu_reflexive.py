@@ -2,7 +2,7 @@
 the C ABI, against the FP64 reflexive oracle (oracle/reflexive.py): blur
 kernels elementwise (A and A^T, equal here), reflexive factor SVDs, solves
 against the DCT closed-form x_lambda, the exact diagonal, a mixed batch,
-and the refusals."""
+the refusals, and the largest image size under both non-zero boundaries."""
 import numpy as np
 import pytest
 
@@ -194,3 +194,26 @@ def test_reflexive_refusals():
     with pytest.raises(KPError) as ei:
         Plan(_psf("sym", 17, 0), 15, bc=KP_BC_REFLEXIVE)
     assert ei.value.status == KP_ERR_ARG
+
+
+@pytest.mark.parametrize("bc_name", ["periodic", "reflexive"])
+def test_maximum_size_other_boundaries(bc_name):
+    """The largest image (2048 x 2048) with the largest PSF (K = 63) under
+    the periodic and the reflexive boundary: FP16-KP FPCG reaches the
+    closed-form x_lambda (2-D DFT or DCT) to 1e-4."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_BC_PERIODIC, KP_BC_REFLEXIVE, KP_FPCG, KP_OK, KP_P16, Plan
+    from oracle import periodic as PB
+    if bc_name == "periodic":
+        prob, bc, ref_mod = S.large_moffat_periodic(3, n=2048, k=63), KP_BC_PERIODIC, PB
+    else:
+        prob, bc, ref_mod = S.large_moffat_reflexive(3, n=2048, k=63), KP_BC_REFLEXIVE, RB
+    lam = 0.03
+    say(f"maximum size 2048^2, K = 63, {bc_name}")
+    ref = ref_mod.x_lambda(prob.psf, prob.b.astype(np.float64), lam)
+    with Plan(prob.psf, prob.n, bc=bc) as plan:
+        x, info = plan.solve(to_dev(prob.b), lam, tol=1e-6, maxit=200, mode=KP_FPCG | KP_P16)
+        got = to_host(x)
+    err = rel(got, ref)
+    say(f"  iters={info.iters} relres_true={info.relres_true:.2e} err={err:.2e}")
+    assert info.status == KP_OK and err <= 1e-4
