@@ -8,6 +8,7 @@ import pytest
 import synthetic as S
 from oracle import kp as KP
 from oracle import periodic as PB
+from oracle import reflexive as RB
 from tests.gpu_util import rel, require_gpu, say, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
@@ -28,7 +29,7 @@ def _psf(kind, k, seed=0):
 
 @pytest.mark.parametrize("n,k,kind,bc", [(64, 15, "moffat", 0), (100, 31, "rand", 0),
                                          (256, 31, "moffat", 0), (128, 63, "gauss", 0),
-                                         (96, 15, "moffat", 1)])
+                                         (96, 15, "moffat", 1), (112, 31, "gauss", 2)])
 def test_lowp_factors_match_fp16_oracle(n, k, kind, bc):
     """FP32 SVD (general path) or FP32 symmetric eigensolver (symmetric
     profiles) of the FP16 factor: a backward-stable factorisation in FP32
@@ -41,7 +42,8 @@ def test_lowp_factors_match_fp16_oracle(n, k, kind, bc):
     from paper_2311_15393_amd import KP_SETUP_LOWP, Plan
     say(f"lowp factors n={n} k={k} {kind} bc={bc}")
     psf = _psf(kind, k, 7)
-    kp = PB.kp_svd(psf, n) if bc else KP.kp_svd(psf, n)
+    kp = (PB.kp_svd(psf, n) if bc == 1 else RB.kp_svd(psf, n) if bc == 2
+          else KP.kp_svd(psf, n))
     ref = KP.kp_svd_fp16_factors(kp)
     with Plan(psf, n, bc=bc | KP_SETUP_LOWP) as plan:
         sc, sr, vc, vr = plan.factors()
