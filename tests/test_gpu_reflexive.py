@@ -86,20 +86,23 @@ def test_reflexive_factors_match_oracle(n, k, kind):
     assert np.allclose((vr * sr ** 2) @ vr.T, kp.Ar.T @ kp.Ar, atol=1e-5 * sr[0] ** 2)
 
 
-@pytest.mark.parametrize("mode", ["fpcg16", "pcg32", "cg"])
+@pytest.mark.parametrize("mode", ["fpcg16", "pcg32", "cg", "fpcg8", "fpcg16diag"])
 def test_reflexive_solve_matches_closed_form(mode):
     """Solves at 256^2 (K = 31, random doubly symmetric PSF) reach the DCT
     closed-form x_lambda to 1e-4, and the reported true residual agrees with
-    the oracle's ||c - H x|| / ||c|| to a tenth of the tolerance.  The broad
+    the oracle's ||c - H x|| / ||c|| to a tenth of the tolerance plus twice
+    the residual that rounding x_lambda to FP32 causes (the returned x is
+    FP32, the certificate is for the FP64 iterate).  The broad
     random PSF at lambda = 0.01 is worse conditioned than the Moffat case of
     the other boundaries: tol 1e-7 left x at 1.04e-4, so tol is 2e-8."""
     require_gpu()
     from paper_2311_15393_amd import (KP_BC_REFLEXIVE, KP_CG, KP_FPCG, KP_OK, KP_P16, KP_P32,
-                                      KP_PCG, Plan)
+                                      KP_PCG, KP_P8, KP_EXACT_DIAG, Plan)
     n, k, lam, tol = 256, 31, 0.01, 2e-8
     psf, b = _problem(n, k, "sym", 1)
     b64 = b.astype(np.float64)
-    m = {"fpcg16": KP_FPCG | KP_P16, "pcg32": KP_PCG | KP_P32, "cg": KP_CG}[mode]
+    m = {"fpcg16": KP_FPCG | KP_P16, "pcg32": KP_PCG | KP_P32, "cg": KP_CG,
+         "fpcg8": KP_FPCG | KP_P8, "fpcg16diag": KP_FPCG | KP_P16 | KP_EXACT_DIAG}[mode]
     with Plan(psf, n, bc=KP_BC_REFLEXIVE) as plan:
         x, info = plan.solve(to_dev(b), lam, tol=tol, maxit=3000, mode=m)
         got = to_host(x)
@@ -107,11 +110,15 @@ def test_reflexive_solve_matches_closed_form(mode):
     op = RB.NormalOperator(psf, n, lam)
     c = op.At(b64)
     rr = float(np.linalg.norm(c - op.H(got)) / np.linalg.norm(c))
+    # the device certifies its FP64 iterate and returns it in FP32: the
+    # residual of fl32(x_lambda) measures what that rounding alone adds
+    floor = float(np.linalg.norm(c - op.H(ref.astype(np.float32).astype(np.float64)))
+                  / np.linalg.norm(c))
     err = rel(got, ref)
     say(f"reflexive {mode}: iters={info.iters} err={err:.2e} relres_true={info.relres_true:.3e} "
-        f"oracle={rr:.3e}")
+        f"oracle={rr:.3e} fp32 floor={floor:.1e}")
     assert info.status == KP_OK and err <= 1e-4
-    assert abs(info.relres_true - rr) <= 0.1 * tol
+    assert abs(info.relres_true - rr) <= 0.1 * tol + 2 * floor
 
 
 def test_reflexive_full_size_fp16():
