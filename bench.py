@@ -592,6 +592,28 @@ def run_instances(count: int, grid, ladder, steps: int, warmup: int, dev, nthrea
             "all_ok": all(r["ok"] for r in rows)}
 
 
+def psf_spectrum(psf: np.ndarray, L: int, dev):
+    """rfft2 of the PSF zero-padded to L x L (FP32, on dev)."""
+    import torch
+    k = psf.shape[0]
+    pt = torch.zeros((L, L), device=dev, dtype=torch.float32)
+    pt[:k, :k] = torch.from_numpy(np.ascontiguousarray(psf, dtype=np.float32)).to(dev)
+    return torch.fft.rfft2(pt)
+
+
+def fft_normal(p, pf, pfc, L: int, h: int):
+    """A^T A p (zero boundary, centre (h, h)) by zero-padded FFTs of size L:
+    entries h .. h + n - 1 of the linear convolution are A p, and the
+    circular correlation with the PSF, shifted by h, is A^T y.  Wrapped taps
+    land in the zero pad once L >= n + h.  pf, pfc: psf_spectrum and its
+    conjugate."""
+    import torch
+    n = p.shape[0]
+    y = torch.fft.irfft2(torch.fft.rfft2(p, s=(L, L)) * pf, s=(L, L))[h:h + n, h:h + n]
+    c = torch.fft.irfft2(torch.fft.rfft2(y, s=(L, L)) * pfc, s=(L, L))
+    return torch.roll(c, shifts=(h, h), dims=(0, 1))[:n, :n]
+
+
 def smooth_size(m: int) -> int:
     """Smallest L >= m whose prime factors are all 2, 3, 5 or 7."""
     L = m
@@ -649,15 +671,11 @@ def run_matvec_sweep(dev, n: int = 1024, ks=(15, 23, 31, 47, 63), reps: int = 50
         row = {"k": k, "blur_config": cfg, "direct_fwd_us": fwd_us, "direct_adj_us": adj_us,
                "direct_hp_us": fwd_us + adj_us}
         for tag, L in (("smooth", smooth_size(n + h)), ("pow2", 1 << (n + h - 1).bit_length())):
-            pt = torch.zeros((L, L), device=dev, dtype=torch.float32)
-            pt[:k, :k] = torch.from_numpy(psf.astype(np.float32)).to(dev)
-            pf = torch.fft.rfft2(pt)
+            pf = psf_spectrum(psf, L, dev)
             pfc = pf.conj()
 
             def hp():
-                y = torch.fft.irfft2(torch.fft.rfft2(p, s=(L, L)) * pf, s=(L, L))[h:h + n, h:h + n]
-                c = torch.fft.irfft2(torch.fft.rfft2(y, s=(L, L)) * pfc, s=(L, L))
-                return torch.roll(c, shifts=(h, h), dims=(0, 1))[:n, :n]
+                return fft_normal(p, pf, pfc, L, h)
 
             got = hp().double()
             err = float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
