@@ -118,3 +118,22 @@ def test_batched_refuses_history():
             solve_batched([plan], [to_dev(p.b)], [p.lam], [0], tol=1e-6, maxit=50,
                           mode=KP_FPCG | KP_P16 | KP_HIST)
         assert ei.value.status == KP_ERR_ARG
+
+
+def test_history_after_fp32_restart():
+    """An FP16 solve that runs out of iterations restarts with the FP32
+    preconditioner from its last iterate; the history is the restart's: its
+    entry 0 is the warm start's true residual, and it holds the restart's
+    iterations only (maxit = 2 for each run)."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_FPCG, KP_MAXIT, KP_P16, Plan
+    p = S.mid_anisotropic(2)
+    with Plan(p.psf, p.n) as plan:
+        _, info = plan.solve(to_dev(p.b), p.lam, tol=1e-10, maxit=2, mode=KP_FPCG | KP_P16,
+                             history=True, raise_on_fail=False)
+    say(f"restart history: status {info.status} fallback {info.fallback} iters {info.iters} "
+        f"entries {info.history_rec.size}")
+    assert info.fallback == 1 and info.status == KP_MAXIT
+    assert info.iters == 4 and info.history_rec.size == 3
+    assert info.history_rec[0] == 1.0 and np.isfinite(info.history_true[0])
+    assert info.history_true[-1] == info.relres_true
