@@ -8,7 +8,9 @@ more systematic way to choose these parameters (Section 5.1, last paragraph;
 Section 6).  The network here is this library's own answer to that, not a
 method from the paper: it maps spectral features of the data in the KP-SVD
 basis to log10(lambda).  Parity status: pinned by central finite differences
-(tests/test_oracle_mlp.py); the features are pinned by brute-force binning.
+(tests/test_oracle_mlp.py); the FP16 forward by torch's own layers with an
+explicit binary16 cast of each hidden layer's operands; the features by
+brute-force binning.
 
 Features (128 per problem), from the coefficients c = V_c^T B V_r and the
 singular values s_ij = s_c[i] s_r[j] of the Kronecker approximation:

@@ -190,27 +190,40 @@ def test_precond_fp32_within_accumulation_bound(n, k, lam):
 def test_precond_fp16_matches_emulated_chain(n, k, lam):
     """FP16 chain on MFMA vs the oracle's emulation of the same rounding
     points (FP16 storage of V, of the power-of-two-scaled residual and of
-    each intermediate; exact products).  The GPU accumulates in FP32, so a
-    small fraction of the FP16 roundings land on the neighbouring value; its
-    error against exact arithmetic must therefore be of the emulation's size
-    (within 0.5x-1.5x), and its distance to the emulation at most half that
-    size.  A wrong operand, transposition or scale gives O(1) errors."""
+    each intermediate; exact products).
+    Elementwise: |z_gpu - z_emul| <= Q.fp16_chain_bound, the worst-case bound
+    for FP32 accumulation in any order plus, at each stored intermediate, the
+    neighbouring FP16 value wherever the accumulated value may lie on the
+    other side of a rounding boundary, propagated through |V|.
+    Normwise (sharper, since the worst case is loose at large n): the GPU's
+    error against exact arithmetic is of the emulation's size (0.5x-1.5x)
+    and its distance to the emulation at most half that size.  A wrong
+    operand, transposition or scale gives O(1) errors."""
     torch = require_gpu()
     from paper_2311_15393_amd import KP_P16, Plan
     say(f"precond16 n={n} k={k}")
     psf = _psf("moffat", k, 13)
     r = S.random_image(np.random.default_rng(17), n) * 1e-3
+    r64 = r.astype(np.float64)
+    # the device picks its scale from its own FP64 ||r||: keep clear of a
+    # power-of-two boundary so both sides take the same one
+    m = np.frexp(np.linalg.norm(r64))[0]
+    assert 0.5 + 1e-9 < m < 1.0 - 1e-9
     with Plan(psf, n) as plan:
         sc, sr, vc, vr = _gpu_factors(plan)
         z = torch.empty((n, n), dtype=torch.float32, device="cuda")
         plan.precond(to_dev(r), lam, KP_P16, z)
         got = to_host(z)
-    emul = Q.precond_fp16(vc, vr, sc, sr, lam, r.astype(np.float64))
+    emul = Q.precond_fp16(vc, vr, sc, sr, lam, r64)
+    bound = Q.fp16_chain_bound(vc, vr, sc, sr, lam, r64)
     exact = Q.precond_fp32(vc, vr, sc, sr, lam, r)
     e_emul = rel(emul, exact)
     e_gpu = rel(got, exact)
     d = rel(got, emul)
-    say(f"  |gpu-exact|={e_gpu:.3e} |emul-exact|={e_emul:.3e} |gpu-emul|={d:.3e}")
+    worst = float(np.max(np.abs(got - emul) / bound))
+    say(f"  |gpu-exact|={e_gpu:.3e} |emul-exact|={e_emul:.3e} |gpu-emul|={d:.3e} "
+        f"max |gpu-emul|/bound={worst:.3e}")
+    assert np.all(np.abs(got - emul) <= bound)
     assert 0.5 * e_emul <= e_gpu <= 1.5 * e_emul
     assert d <= 0.5 * e_emul
     assert 1e-5 < e_emul < 2e-2
@@ -221,29 +234,87 @@ def test_precond_fp8_matches_emulated_chain(n, k, lam):
     """FP8 e4m3 chain with 32-entry block exponents on the block-scaled MFMA,
     vs the oracle's emulation with the same block structure (exponent from
     the block's largest magnitude, e4m3 round-to-nearest-even, exact
-    products).  As for FP16, the GPU's FP32 accumulation moves a few
-    roundings to the neighbouring code: its error against exact arithmetic
-    must be of the emulation's size and its distance to the emulation at
-    most half of that."""
+    products), quantising the same FP32 copies of V the device quantises.
+    Elementwise: |z_gpu - z_emul| <= Q.fp8_chain_bound (FP32 accumulation
+    in any order; at each stored intermediate the neighbouring e4m3 value,
+    or a neighbouring block exponent, wherever the accumulated values allow
+    it).  Normwise as for FP16."""
     torch = require_gpu()
     from paper_2311_15393_amd import KP_P8, Plan
     say(f"precond8 n={n} k={k}")
     psf = _psf("moffat", k, 21)
     r = S.random_image(np.random.default_rng(23), n) * 1e-3
+    r64 = r.astype(np.float64)
     with Plan(psf, n) as plan:
         sc, sr, vc, vr = _gpu_factors(plan)
         z = torch.empty((n, n), dtype=torch.float32, device="cuda")
         plan.precond(to_dev(r), lam, KP_P8, z)
         got = to_host(z)
-    emul = Q.precond_fp8(vc, vr, sc, sr, lam, r.astype(np.float64))
+    vc32, vr32 = Q.round_fp32(vc), Q.round_fp32(vr)
+    emul = Q.precond_fp8(vc32, vr32, sc, sr, lam, r64)
+    bound = Q.fp8_chain_bound(vc32, vr32, sc, sr, lam, r64)
     exact = Q.precond_fp32(vc, vr, sc, sr, lam, r)
     e_emul = rel(emul, exact)
     e_gpu = rel(got, exact)
     d = rel(got, emul)
-    say(f"  |gpu-exact|={e_gpu:.3e} |emul-exact|={e_emul:.3e} |gpu-emul|={d:.3e}")
+    worst = float(np.max(np.abs(got - emul) / bound))
+    say(f"  |gpu-exact|={e_gpu:.3e} |emul-exact|={e_emul:.3e} |gpu-emul|={d:.3e} "
+        f"max |gpu-emul|/bound={worst:.3e}")
+    assert np.all(np.abs(got - emul) <= bound)
     assert 0.5 * e_emul <= e_gpu <= 1.5 * e_emul
     assert d <= 0.5 * e_emul
     assert 1e-3 < e_emul < 0.2
+
+
+@pytest.mark.parametrize("lam", [1.0, 0.5])
+def test_precond_lowp_exact_products_bit_for_bit(lam):
+    """An identity PSF (K = 1) gives A = I: both Kronecker factors are the
+    identity, their singular values 1 and V = I.  Every product of the
+    chain then has one nonzero term and is exact in FP32, so the device
+    must reproduce the rounding points of the emulation bit for bit: the
+    power-of-two residual scale and its FP16 (or block-scaled e4m3)
+    rounding, the stored intermediates, S' = lambda^2 / (1 + lambda^2)
+    in FP32 and the final 1 / (scale lambda^2).  lambda = 1 makes S' = 1/2
+    (exact); lambda = 1/2 makes S' = 0.2 (rounded to FP32 first, then the
+    FP16 product is rounded from its FP32 value, as on the device)."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_P8, KP_P16, KP_P32, Plan
+    n = 256
+    say(f"precond exact products lambda={lam}")
+    r = S.random_image(np.random.default_rng(41), n).astype(np.float64) - 0.5
+    r[5, :40] *= 2.0 ** -20                              # some subnormal FP16 entries
+    r = r.astype(np.float32)
+    r64 = r.astype(np.float64)
+    with Plan(np.array([[1.0]]), n) as plan:
+        sc, sr, vc, vr = _gpu_factors(plan)
+        if not (np.array_equal(np.abs(vc), np.eye(n)) and np.array_equal(np.abs(vr), np.eye(n))
+                and np.all(sc == 1.0) and np.all(sr == 1.0)):
+            pytest.skip("device SVD of the identity factor is not a signed identity")
+        outs = {}
+        for prec in (KP_P32, KP_P16, KP_P8):
+            z = torch.empty((n, n), dtype=torch.float32, device="cuda")
+            plan.precond(to_dev(r), lam, prec, z)
+            outs[prec] = to_host(z).astype(np.float64)
+    f32 = np.float32
+    sp = f32(lam * lam) / (f32(1.0) + f32(lam * lam))     # S' in FP32
+    # FP32: each product is one exact term; S' applied in FP32
+    t = vc.T @ r64 @ vr
+    t2 = Q.round_fp32(np.float64(sp) * t)
+    want32 = Q.round_fp32((vc @ t2 @ vr.T) * np.float64(f32(1.0 / (lam * lam))))
+    assert np.array_equal(outs[KP_P32], want32)
+    if lam == 1.0:
+        emul16 = Q.precond_fp16(vc, vr, sc, sr, lam, r64)
+        emul8 = Q.precond_fp8(vc, vr, sc, sr, lam, r64)
+        assert np.array_equal(outs[KP_P16], Q.round_fp32(emul16))
+        assert np.array_equal(outs[KP_P8], Q.round_fp32(emul8))
+    else:
+        tr = {}
+        Q.precond_fp16(vc, vr, sc, sr, lam, r64, trace=tr)
+        t1 = vc.T @ tr["rt"] @ vr                         # exact: one term each
+        t2 = Q.round_fp16(Q.round_fp32(np.float64(sp) * t1))
+        zs = np.float64(f32(1.0 / (tr["scale"] * lam * lam)))
+        want16 = Q.round_fp32((vc @ t2 @ vr.T) * zs)
+        assert np.array_equal(outs[KP_P16], want16)
 
 
 def test_fp8_rejects_unsupported_size():

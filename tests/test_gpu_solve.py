@@ -316,8 +316,32 @@ def test_lambda_study_runs():
         assert r["err"]["opt"] <= 1.5 * r["err"]["best"]
 
 
-@pytest.mark.parametrize("mode", ["fpcg16", "fpcg8", "pcg32"])
-def test_large_moffat_full_size(mode):
+def _xlam_large(prob, lam, kp):
+    """The oracle's settled x_lambda for a large problem: FP64 KP-PCG to a
+    true residual of 1e-13, accepted only if a run at a 100x looser
+    tolerance agrees with it (check=True), converged, with its true
+    residual at or below 1e-12."""
+    key = ("large", prob.seed, lam)
+    if key not in _XLAM:
+        x, info = SV.x_lambda_iterative(prob.psf, prob.b.astype(np.float64), lam, kp=kp,
+                                        check=True)
+        say(f"  oracle x_lambda: iters={info['iters']} status={info['status']} "
+            f"true relres={info['true_relres']:.1e} loose agreement "
+            f"{info['loose_agreement']:.1e}")
+        assert info["status"] == "converged" and info["true_relres"] <= 1e-12
+        _XLAM[key] = x
+    return _XLAM[key]
+
+
+# (mode, tol, bar): the FP32 modes are held to 1e-5 at a tolerance whose
+# true residuals use the FP64 data misfit b - A x; the reduced-precision
+# preconditioners to 1e-4
+LARGE_CASES = [("fpcg16", 1e-6, 1e-4), ("fpcg8", 1e-6, 1e-4), ("pcg32", 1e-7, 1e-5),
+               ("fpcg32", 1e-7, 1e-5)]
+
+
+@pytest.mark.parametrize("mode,tol,bar", LARGE_CASES)
+def test_large_moffat_full_size(mode, tol, bar):
     """1024 x 1024, Moffat + motion PSF (K = 63), lambda from the GPU's KP-GCV
     (same grid index as the oracle): the benchmark's configuration, checked
     against the oracle's x_lambda at full size."""
@@ -325,22 +349,18 @@ def test_large_moffat_full_size(mode):
     from paper_2311_15393_amd import KP_OK, Plan
     prob = S.large_moffat(0)
     grid = S.lambda_grid()
-    say(f"large moffat {mode}")
+    say(f"large moffat {mode} tol={tol:g}")
     with Plan(prob.psf, prob.n) as plan:
         b = to_dev(prob.b)
         lam, _ = plan.gcv(b, grid)
         kp = KP.kp_svd(prob.psf, prob.n)
         s2, bh2 = L.spectrum(kp, prob.b.astype(np.float64))
         assert lam == grid[L.grid_argmin(L.gcv(s2, bh2, grid))]
-        key = ("large", prob.seed, lam)
-        if key not in _XLAM:
-            _XLAM[key] = SV.x_lambda_iterative(prob.psf, prob.b.astype(np.float64), lam, kp=kp,
-                                               check=False)[0]
-        ref = _XLAM[key]
-        x, info = plan.solve(b, lam, tol=1e-6, maxit=300, mode=_modes()[mode])
+        ref = _xlam_large(prob, lam, kp)
+        x, info = plan.solve(b, lam, tol=tol, maxit=300, mode=_modes()[mode])
         err = rel(to_host(x), ref)
     say(f"  lam={lam:.4g} iters={info.iters} repl={info.replacements} err={err:.2e}")
-    assert info.status == KP_OK and err <= 1e-4
+    assert info.status == KP_OK and err <= bar
 
 
 def test_fp32_fallback_after_reduced_precision_failure():
@@ -366,9 +386,5 @@ def test_fp32_fallback_after_reduced_precision_failure():
             f"relres={info.relres_true:.2e}")
         assert info.status == KP_OK_FALLBACK and info.fallback == 1
         assert 10 < info.iters <= 20 and info.relres_true <= 1e-6
-        key = ("large", prob.seed, lam)
-        if key not in _XLAM:
-            kp = KP.kp_svd(prob.psf, prob.n)
-            _XLAM[key] = SV.x_lambda_iterative(prob.psf, prob.b.astype(np.float64), lam, kp=kp,
-                                               check=False)[0]
-        assert rel(to_host(x), _XLAM[key]) <= 1e-4
+        ref = _xlam_large(prob, lam, KP.kp_svd(prob.psf, prob.n))
+        assert rel(to_host(x), ref) <= 1e-4

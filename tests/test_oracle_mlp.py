@@ -83,3 +83,41 @@ def test_features_by_brute_force():
         mean = np.mean(acc[k]) if acc[k] else 0.0
         assert np.isclose(f[k], np.log10(max(mean, 1e-30)))
         assert np.isclose(f[64 + k], np.log10(len(acc[k]) / n / n + 1e-12))
+
+
+def test_fp16_forward_matches_per_layer_half_casts():
+    """forward(..., fp16=True) against torch's own layers in float64 with an
+    explicit half-precision cast of each hidden layer's input and weight
+    (the cast rounds the double straight to binary16; torch's own float64 ->
+    float16 conversion goes through float32 and can double-round, so the
+    cast is numpy's).  The output layer stays unrounded, as on the device.
+    The check also shows the rounding is visible (differs from the FP64
+    forward) and that rounding the output layer too would differ."""
+    import torch
+
+    rng = np.random.default_rng(4)
+    params = M.init_params(rng)
+    X = rng.standard_normal((9, M.NFEAT)) * 3.0
+    mu = rng.standard_normal(M.NFEAT)
+    scale = rng.uniform(0.5, 2.0, M.NFEAT)
+
+    def half(t):
+        return torch.from_numpy(t.numpy().astype(np.float16).astype(np.float64))
+
+    def reference(round_last):
+        h = (torch.from_numpy(X) - torch.from_numpy(mu)) / torch.from_numpy(scale)
+        for li, (W, b) in enumerate(params):
+            last = li == len(params) - 1
+            Wt, bt = torch.from_numpy(W), torch.from_numpy(b)
+            if not last or round_last:
+                h, Wt = half(h), half(Wt)
+            z = torch.nn.functional.linear(h, Wt, bt)
+            h = z if last else torch.nn.functional.gelu(z, approximate="none")
+        return h[:, 0].numpy()
+
+    y16, _ = M.forward(params, X, mu, scale, fp16=True)
+    y64, _ = M.forward(params, X, mu, scale, fp16=False)
+    ref = reference(False)
+    assert np.allclose(y16, ref, rtol=1e-12, atol=1e-12)
+    assert not np.allclose(y64, ref, rtol=1e-7, atol=0)
+    assert not np.allclose(reference(True), ref, rtol=1e-9, atol=0)
