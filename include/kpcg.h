@@ -49,8 +49,10 @@ extern "C" {
 #define KP_ERR_UNSUPPORTED -2   /* unknown boundary condition, or K above
                                    KP_MAX_PSF                              */
 #define KP_ERR_HIP         -3   /* a HIP runtime call failed               */
-#define KP_ERR_SOLVER      -4   /* the FP64 factor SVD (rocSOLVER) failed  */
-#define KP_ERR_WORKSPACE   -5   /* caller workspace smaller than required  */
+#define KP_ERR_WORKSPACE   -4   /* caller workspace smaller than required,
+                                   or misaligned                           */
+#define KP_ERR_SOLVER      -5   /* the FP64 factor SVD (rocSOLVER) failed,
+                                   or its workspace size query did         */
 
 #define KP_MAX_PSF 63           /* largest supported PSF support K          */
 #define KP_BC_ZERO      0       /* image zero outside [0, n)^2 (BTTB A)     */
@@ -139,7 +141,13 @@ typedef struct kp_plan_info_s {
 
 /*
  * kp_workspace_size -- device bytes a plan for an n x n image and a K x K
- * PSF needs.  `modes` is reserved (pass 0).  Returns 0 for invalid sizes.
+ * PSF needs on the current device: the plan's data (factors, taps, tables,
+ * the solver's vectors and control block) and, overlapping the solver's
+ * vectors, the scratch of the construction in kp_setup, rocSOLVER's own
+ * workspace included (found by rocBLAS's device-memory size query; the
+ * first call on a device creates the library's rocBLAS handle for it, which
+ * is kept for the process).  `modes` is reserved (pass 0).  Returns 0 for
+ * invalid sizes or when the query fails (no device).
  */
 size_t kp_workspace_size(int n, int k, int modes);
 
@@ -163,14 +171,19 @@ size_t kp_workspace_size(int n, int k, int modes);
  *   bc         KP_BC_ZERO, KP_BC_PERIODIC or KP_BC_REFLEXIVE, optionally
  *              | KP_SETUP_LOWP
  *              (other values: KP_ERR_UNSUPPORTED)
- *   workspace  device buffer of >= kp_workspace_size(n, k, 0) bytes that
- *              the plan uses for all its device data (caller keeps
- *              ownership and must keep it alive until kp_destroy), or
- *              NULL to let the plan allocate and own its memory
+ *   workspace  device buffer of >= kp_workspace_size(n, k, 0) bytes,
+ *              16-byte aligned, that holds all of the plan's device data
+ *              and the construction's scratch (rocSOLVER's workspace is
+ *              handed to rocBLAS from it): with a workspace kp_setup and
+ *              every later call on the plan allocate no device memory.  The
+ *              caller keeps ownership and keeps it alive until kp_destroy.
+ *              NULL lets the plan allocate (hipMalloc) and own its memory.
  *   ws_bytes   size of `workspace` (ignored if workspace is NULL)
  *   plan       out: the new plan (NULL on error)
- * Errors: KP_ERR_ARG, KP_ERR_UNSUPPORTED, KP_ERR_WORKSPACE, KP_ERR_HIP,
- * KP_ERR_SOLVER.  Synchronises `stream`.
+ * Errors: KP_ERR_ARG, KP_ERR_UNSUPPORTED, KP_ERR_WORKSPACE (too small or
+ * misaligned), KP_ERR_HIP, KP_ERR_SOLVER.  Constructions on one device are
+ * serialised (they share the device's rocBLAS handle).  Synchronises
+ * `stream`.
  */
 int kp_setup(const double *psf, int k, int n, int bc, void *workspace,
              size_t ws_bytes, void *stream, kp_plan_t *plan);
@@ -256,22 +269,34 @@ int discrepancy_lambda(kp_plan_t plan, const float *b, const double *grid,
  * image sizes and PSF supports are allowed.  Each phase of an iteration is
  * one launch over the tiles of all items still iterating; each item stops
  * on its own (converged, maxit, breakdown).  infos[i] receives item i's
- * outcome, including its data misfit ||A x - b||.  Plans of both
- * boundary conditions may be mixed.
+ * outcome, including its data misfit ||A x - b||.  Plans of every boundary
+ * condition may be mixed.
  *
  *   plans, nplans   array of plan handles and its length
  *   b, x            arrays of nitems device pointers (FP32 n_i x n_i, 16-byte
  *                   aligned); lambdas: host array of nitems values > 0
  *   plan_of_item    host array of nitems indices into plans
- * Device memory for the items' vectors is allocated for the duration of
- * the call (about 56 n_i^2 bytes per item).  Synchronises `stream`.
- * Returns KP_OK if every item converged, KP_MAXIT / KP_BREAKDOWN if some
- * did not (see infos), or an error.
+ *   workspace       device buffer of >= pcg_solve_batched_workspace_size
+ *                   bytes, 256-byte aligned, owned by the caller: the items'
+ *                   vectors (about 56 n_i^2 bytes each), control blocks and
+ *                   tile tables.  The library allocates no device memory.
+ * The iterations run on a non-blocking stream of the library's (one per
+ * device, created on first use), ordered after `stream` by an event and
+ * before the return; batched calls are serialised per process.
+ * Synchronises `stream`.  Returns KP_OK if every item converged, KP_MAXIT /
+ * KP_BREAKDOWN if some did not (see infos), KP_ERR_WORKSPACE, or an error.
  */
 int pcg_solve_batched(const kp_plan_t *plans, int nplans, const float *const *b,
                       const double *lambdas, const int *plan_of_item, int nitems,
                       double tol, int maxit, int mode, float *const *x,
-                      kp_info_t *infos, void *stream);
+                      kp_info_t *infos, void *workspace, size_t ws_bytes,
+                      void *stream);
+
+/* pcg_solve_batched_workspace_size -- device bytes pcg_solve_batched needs
+   for these plans, items and mode (0 for invalid arguments). */
+size_t pcg_solve_batched_workspace_size(const kp_plan_t *plans, int nplans,
+                                        const int *plan_of_item, int nitems,
+                                        int mode);
 
 /*
  * opt_lambda -- the optimal-error rule in the KP-SVD basis, eq. (OptTikSVD):
@@ -285,7 +310,9 @@ int opt_lambda(kp_plan_t plan, const float *b, const float *x_true,
                const double *grid, int ngrid, double *lambda_out,
                double *scores_out, void *stream);
 
-/* kp_destroy -- release the plan (and its memory if it allocated it). */
+/* kp_destroy -- release the plan (and its memory if it allocated it).
+   Waits for the plan's last enqueued work (an event recorded on the stream
+   of the last call that used it), not for other streams or the device. */
 int kp_destroy(kp_plan_t plan);
 
 /* ---- learned choice of lambda ------------------------------------------
@@ -441,13 +468,15 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int *prev);
    (the table KP_EXACT_DIAG uses; built by kp_setup from all Kronecker terms
    with FP64 arithmetic, stored FP32) to the host array d0 (n*n, row-major:
    i indexes the column factor's singular vectors, j the row factor's).
-   Synchronises the device.  For a KP_BC_PERIODIC plan D0 comes from the
+   The copy runs on a non-blocking stream of the library's and waits for
+   nothing else (the table is final once kp_setup returns).  For a KP_BC_PERIODIC plan D0 comes from the
    circulant terms; its singular vectors are unique only up to rotations
    within pairs of equal singular values, and D0 is that of the stored V. */
 int kp_get_diag(kp_plan_t plan, float *d0);
 
 /* Copy the FP64 singular values s_c, s_r (host arrays of n) and, if not
-   NULL, V_c, V_r as FP64 row-major n x n host arrays (V[i*n + a] = V(i,a)). */
+   NULL, the stored FP32 copies of V_c, V_r widened to FP64 row-major n x n
+   host arrays (V[i*n + a] = V(i,a)).  Copies as kp_get_diag does. */
 int kp_get_factors(kp_plan_t plan, double *sc, double *sr, double *vc,
                    double *vr);
 

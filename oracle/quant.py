@@ -274,7 +274,8 @@ def _flip_gap(acc, e, rnd):
 
 def fp16_chain_bound(Vc, Vr, sc, sr, lam, r, rnorm=None):
     """Elementwise bound on |z_impl - precond_fp16(...)| for an FP16 chain
-    that stores fp16(V) (possibly rounded through FP32 first), fp16(scale r)
+    that stores FP16 V rounded from any value within half an FP32 unit of
+    the given V (so V may be the FP32 copy of the factor), fp16(scale r)
     and fp16 of its own FP32 intermediates, accumulates in FP32, forms S' in
     FP32 (to within 4 u32 relative of s_prime) and scales the output by the
     FP32 value of 1 / (scale lambda^2)."""
@@ -285,8 +286,10 @@ def fp16_chain_bound(Vc, Vr, sc, sr, lam, r, rnorm=None):
     s = pow2_scale_for_norm(rnorm)
     g = gamma(n + 8, U32)
     vc, vr = round_fp16(Vc), round_fp16(Vr)
-    dvc = np.abs(vc - round_fp16(round_fp32(Vc)))
-    dvr = np.abs(vr - round_fp16(round_fp32(Vr)))
+    # the implementation may round V to FP16 from any value within half an
+    # FP32 unit of the V given here (its FP64 or its FP32 copy)
+    dvc = _flip_gap(np.asarray(Vc, dtype=np.float64), U32 * np.abs(Vc), round_fp16)
+    dvr = _flip_gap(np.asarray(Vr, dtype=np.float64), U32 * np.abs(Vr), round_fp16)
     avc, avr = np.abs(vc) + dvc, np.abs(vr) + dvr
     rt = round_fp16(s * r)
     art = np.abs(rt)

@@ -13,6 +13,7 @@
 // run the FP64 true-residual recomputations the items ask for.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -663,19 +664,23 @@ static int read_ctrls(Batch& B) {
   return KP_OK;
 }
 
+// The batch's device memory is the caller's workspace and its stream the
+// device's AUX_BATCH stream: neither is released here.
 static void destroy_batch(Batch& B) {
   if (B.s) hipStreamSynchronize(B.s);
-  if (B.mem) hipFree(B.mem);
   if (B.h_ctrl) hipHostFree(B.h_ctrl);
-  if (B.s) hipStreamDestroy(B.s);
   B.mem = nullptr;
   B.h_ctrl = nullptr;
   B.s = nullptr;
 }
 
-int batched_solve(Plan* const* plans, const float* const* b, const double* lambdas,
-                  const int* plan_of_item, int nitems, double tol, int maxit, int mode,
-                  float* const* x, kp_info_t* infos, hipStream_t user_stream) {
+// one batched solve at a time per process: they share the AUX_BATCH streams
+static std::mutex g_batch_mu;
+
+int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int mode,
+                  double tol, int maxit, const float* const* b, const double* lambdas,
+                  float* const* x, kp_info_t* infos, void* ws, size_t ws_bytes,
+                  size_t* need_out, hipStream_t user_stream) {
   Batch B;
   B.nitems = nitems;
   B.mode = mode;
@@ -767,11 +772,15 @@ int batched_solve(Plan* const* plans, const float* const* b, const double* lambd
   const size_t off_tab = total;
   total += align(sizeof(TileRef) * ntab);
 
-  if (hipStreamCreateWithFlags(&B.s, hipStreamNonBlocking) != hipSuccess) return KP_ERR_HIP;
-  if (hipMalloc(&B.mem, total) != hipSuccess) {
-    destroy_batch(B);
-    return KP_ERR_HIP;
+  if (need_out) {
+    *need_out = total;
+    if (!ws) return KP_OK;
   }
+  if (!ws || ws_bytes < total) return KP_ERR_WORKSPACE;
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  B.s = aux_stream(AUX_BATCH);
+  if (!B.s) return KP_ERR_HIP;
+  B.mem = ws;
   if (hipHostMalloc(reinterpret_cast<void**>(&B.h_ctrl), sizeof(Ctrl) * nitems) != hipSuccess) {
     destroy_batch(B);
     return KP_ERR_HIP;

@@ -7,6 +7,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -16,7 +18,8 @@
 using namespace kpcg;
 
 namespace kpcg {
-int build_factors(Plan& P, const double* psf_host, hipStream_t s);
+int build_factors(Plan& P, const double* psf_host, char* scratch, hipStream_t s);
+size_t setup_scratch_bytes(int n, int k);
 hipError_t launch_pupdate_from(const Plan& P, const float* z, hipStream_t s);
 }
 
@@ -37,7 +40,12 @@ struct Bump {
   }
 };
 
-size_t layout(int n, int k, char* base, Plan* P) {
+// The plan's workspace: the persistent part (taps, factors, control block,
+// partial sums, history), then one transient region shared by the solver's
+// vectors and, during kp_setup only, the construction's scratch (its size is
+// the larger of the two).  Returns the total bytes, 0 if the construction's
+// scratch size cannot be determined; *scratch receives the region's start.
+size_t layout(int n, int k, char* base, Plan* P, char** scratch = nullptr) {
   Bump b{base};
   const size_t nn = (size_t)n * n;
   const int kq = (k + TAP_CHUNK - 1) / TAP_CHUNK * TAP_CHUNK;
@@ -74,6 +82,15 @@ size_t layout(int n, int k, char* base, Plan* P) {
   Q.VrT8s = b.take<uint8_t>(nsc);
   Q.UcT32 = b.take<float>(nn);
   Q.UrT32 = b.take<float>(nn);
+  Q.spec = b.take<double>((((nn * sizeof(float)) + ALIGN - 1) / ALIGN * ALIGN) / sizeof(double) +
+                          128 + 2 * 64 * 256);
+  Q.ctrl = b.take<Ctrl>(1);
+  Q.partials = b.take<double>((size_t)NSLOTS * MAX_PARTIALS);
+  Q.hist = b.take<double>(2 * (size_t)KP_HIST_MAX);
+  // transient region
+  b.cur = (b.cur + ALIGN - 1) / ALIGN * ALIGN;
+  const size_t region = b.cur;
+  if (scratch) *scratch = base ? base + region : nullptr;
   Q.r = b.take<float>(nn);
   Q.p = b.take<float>(nn);
   Q.q = b.take<float>(nn);
@@ -91,13 +108,12 @@ size_t layout(int n, int k, char* base, Plan* P) {
   Q.t3s = b.take<uint8_t>(nsc);
   Q.rs = b.take<uint8_t>(nsc);
   Q.r8 = b.take<uint8_t>(nn);
-  Q.spec = b.take<double>((((nn * sizeof(float)) + ALIGN - 1) / ALIGN * ALIGN) / sizeof(double) +
-                          128 + 2 * 64 * 256);
-  Q.ctrl = b.take<Ctrl>(1);
-  Q.partials = b.take<double>((size_t)NSLOTS * MAX_PARTIALS);
-  Q.hist = b.take<double>(2 * (size_t)KP_HIST_MAX);
   (void)Q;
-  return (b.cur + ALIGN - 1) / ALIGN * ALIGN;
+  const size_t vec_end = (b.cur + ALIGN - 1) / ALIGN * ALIGN;
+  const size_t scr = setup_scratch_bytes(n, k);
+  if (scr == 0) return 0;
+  const size_t scr_end = region + scr;
+  return vec_end > scr_end ? vec_end : scr_end;
 }
 
 bool valid_sizes(int n, int k) {
@@ -242,6 +258,10 @@ int kp_setup(const double* psf, int k, int n, int bc_flags, void* workspace, siz
   P.lowp = (bc_flags & KP_SETUP_LOWP) != 0;
   P.kq = (k + TAP_CHUNK - 1) / TAP_CHUNK * TAP_CHUNK;
   const size_t need = layout(n, k, nullptr, nullptr);
+  if (need == 0) {
+    delete h;
+    return KP_ERR_SOLVER;
+  }
   char* base = nullptr;
   if (workspace != nullptr) {
     if (ws_bytes < need || !aligned16(workspace)) {
@@ -259,7 +279,8 @@ int kp_setup(const double* psf, int k, int n, int bc_flags, void* workspace, siz
   }
   P.base = base;
   P.bytes = need;
-  layout(n, k, base, &P);
+  char* scratch = nullptr;
+  layout(n, k, base, &P, &scratch);
   if (hipHostMalloc(reinterpret_cast<void**>(&P.host_ctrl), 2 * sizeof(Ctrl)) != hipSuccess) {
     if (P.owns) hipFree(base);
     delete h;
@@ -279,10 +300,15 @@ int kp_setup(const double* psf, int k, int n, int bc_flags, void* workspace, siz
   std::memset(P.mirror, 0, sizeof(CtrlMirror));
   int rc = KP_OK;
   if (hipMemsetAsync(P.ctrl, 0, sizeof(Ctrl), s) != hipSuccess) rc = KP_ERR_HIP;
-  if (rc == KP_OK) rc = build_factors(P, psf, s);
+  if (rc == KP_OK && hipEventCreateWithFlags(&P.ev_last, hipEventDisableTiming) != hipSuccess)
+    rc = KP_ERR_HIP;
+  if (rc == KP_OK) rc = build_factors(P, psf, scratch, s);
   if (rc == KP_OK && autotune_blur(P, s, P.blur_times) != hipSuccess) rc = KP_ERR_HIP;
+  if (rc == KP_OK && hipEventRecord(P.ev_last, s) != hipSuccess) rc = KP_ERR_HIP;
+  if (rc == KP_OK && hipStreamSynchronize(s) != hipSuccess) rc = KP_ERR_HIP;
   if (rc != KP_OK) {
     hipStreamSynchronize(s);
+    if (P.ev_last) hipEventDestroy(P.ev_last);
     hipHostFree(P.mirror);
     hipHostFree(P.host_ctrl);
     if (P.owns) hipFree(base);
@@ -314,7 +340,10 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t* out) {
 int kp_destroy(kp_plan_t plan) {
   if (!plan) return KP_ERR_ARG;
   Plan& P = plan->P;
-  hipDeviceSynchronize();
+  // the plan's last enqueued work (recorded on the stream it ran on) must
+  // finish before its memory goes; other streams are left alone
+  if (P.ev_last) hipEventSynchronize(P.ev_last);
+  if (P.ev_last) hipEventDestroy(P.ev_last);
   if (P.mirror) hipHostFree(P.mirror);
   if (P.host_ctrl) hipHostFree(P.host_ctrl);
   if (P.ev_start) hipEventDestroy(P.ev_start);
@@ -561,6 +590,7 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
   kp_info_t first{};
   const int st = solve_once(plan, b, lambda, tol, maxit, mode & ~KP_NO_FALLBACK, x, &first,
                             stream);
+  HIPCHK(hipEventRecord(P.ev_last, s));
   if (st < 0) return st;
   first.ms = elapsed();
   const int solver = mode & KP_SOLVER_MASK, prec = mode & KP_PREC_MASK;
@@ -579,6 +609,7 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
                                  KP_P32 | KP_WARM,
                              x,
                              &second, stream);
+  HIPCHK(hipEventRecord(P.ev_last, s));
   if (st2 < 0) return st2;
   if (info) {
     *info = second;
@@ -611,29 +642,52 @@ int kp_get_history(kp_plan_t plan, double* relres_rec, double* relres_true, int 
   return KP_OK;
 }
 
-int pcg_solve_batched(const kp_plan_t* plans, int nplans, const float* const* b,
-                      const double* lambdas, const int* plan_of_item, int nitems, double tol,
-                      int maxit, int mode, float* const* x, kp_info_t* infos, void* stream) {
-  if (!plans || nplans < 1 || !b || !lambdas || !plan_of_item || nitems < 1 || !x || !infos)
-    return KP_ERR_ARG;
-  if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 1) return KP_ERR_ARG;
+// argument checks shared by pcg_solve_batched and its workspace query
+static int batched_args(const kp_plan_t* plans, int nplans, const int* plan_of_item, int nitems,
+                        int mode, std::vector<Plan*>& ps) {
+  if (!plans || nplans < 1 || !plan_of_item || nitems < 1) return KP_ERR_ARG;
   if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM | KP_BATCH_EAGER | KP_EXACT_DIAG)) != 0)
     return KP_ERR_ARG;
   if ((mode & KP_SOLVER_MASK) == 3 || (mode & KP_PREC_MASK) == KP_PREC_MASK) return KP_ERR_ARG;
   if ((mode & KP_WARM) || (mode & KP_PREC_MASK) == KP_P8) return KP_ERR_UNSUPPORTED;
-  std::vector<Plan*> ps(nplans);
+  ps.resize(nplans);
   for (int i = 0; i < nplans; ++i) {
     if (!plans[i]) return KP_ERR_ARG;
     ps[i] = &plans[i]->P;
   }
-  for (int i = 0; i < nitems; ++i) {
+  for (int i = 0; i < nitems; ++i)
     if (plan_of_item[i] < 0 || plan_of_item[i] >= nplans) return KP_ERR_ARG;
+  return KP_OK;
+}
+
+size_t pcg_solve_batched_workspace_size(const kp_plan_t* plans, int nplans,
+                                        const int* plan_of_item, int nitems, int mode) {
+  std::vector<Plan*> ps;
+  if (batched_args(plans, nplans, plan_of_item, nitems, mode, ps) != KP_OK) return 0;
+  size_t need = 0;
+  if (batched_solve(ps.data(), plan_of_item, nitems, mode, 0.0, 0, nullptr, nullptr, nullptr,
+                    nullptr, nullptr, 0, &need, nullptr) != KP_OK)
+    return 0;
+  return need;
+}
+
+int pcg_solve_batched(const kp_plan_t* plans, int nplans, const float* const* b,
+                      const double* lambdas, const int* plan_of_item, int nitems, double tol,
+                      int maxit, int mode, float* const* x, kp_info_t* infos, void* workspace,
+                      size_t ws_bytes, void* stream) {
+  std::vector<Plan*> ps;
+  int rc = batched_args(plans, nplans, plan_of_item, nitems, mode, ps);
+  if (rc != KP_OK) return rc;
+  if (!b || !lambdas || !x || !infos || !workspace) return KP_ERR_ARG;
+  if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 1) return KP_ERR_ARG;
+  for (int i = 0; i < nitems; ++i) {
     if (!b[i] || !x[i] || !aligned16(b[i]) || !aligned16(x[i])) return KP_ERR_ARG;
     if (!(lambdas[i] > 0.0) || !std::isfinite(lambdas[i])) return KP_ERR_ARG;
   }
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return KP_ERR_WORKSPACE;
   // every plan's own solve state must be idle: the batch only reads factors
-  const int rc = batched_solve(ps.data(), b, lambdas, plan_of_item, nitems, tol, maxit, mode, x,
-                               infos, reinterpret_cast<hipStream_t>(stream));
+  rc = batched_solve(ps.data(), plan_of_item, nitems, mode, tol, maxit, b, lambdas, x, infos,
+                     workspace, ws_bytes, nullptr, reinterpret_cast<hipStream_t>(stream));
   if (rc != KP_OK) return rc;
   int worst = KP_OK;
   for (int i = 0; i < nitems; ++i)
@@ -644,6 +698,21 @@ int pcg_solve_batched(const kp_plan_t* plans, int nplans, const float* const* b,
 }  // extern "C"
 
 namespace kpcg {
+
+hipStream_t aux_stream(int slot) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, hipStream_t> streams;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_pair(dev, slot);
+  auto it = streams.find(key);
+  if (it != streams.end()) return it->second;
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  streams[key] = st;
+  return st;
+}
 
 int spectral_call(kp_plan_t plan, const float* b, const double* grid, int ngrid, double omega,
                   double noise2, int kind, double* scores_host, void* stream,
@@ -717,6 +786,7 @@ int kp_blur(kp_plan_t plan, const float* x, float* y, int transpose, void* strea
   if (!plan || !x || !y || x == y) return KP_ERR_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIPCHK(launch_blur_f32(plan->P, x, y, transpose != 0, s, nullptr));
+  HIPCHK(hipEventRecord(plan->P.ev_last, s));
   HIPCHK(hipStreamSynchronize(s));
   return KP_OK;
 }
@@ -725,6 +795,7 @@ int kp_normal_fp64(kp_plan_t plan, const float* x, double lambda, double* y, voi
   if (!plan || !x || !y || !(lambda >= 0.0) || !std::isfinite(lambda)) return KP_ERR_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIPCHK(launch_normal_fp64(plan->P, x, lambda * lambda, y, s));
+  HIPCHK(hipEventRecord(plan->P.ev_last, s));
   HIPCHK(hipStreamSynchronize(s));
   return KP_OK;
 }
@@ -816,11 +887,17 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int* prev) {
   return KP_OK;
 }
 
+// The factors and D0 are final once kp_setup has returned (it synchronises
+// its stream), so the getters wait for nothing else: they copy on the
+// device's auxiliary stream (non-blocking, so the copies neither wait for
+// nor hold up other streams) and wait for those copies only.
 int kp_get_diag(kp_plan_t plan, float* d0) {
   if (!plan || !d0) return KP_ERR_ARG;
   Plan& P = plan->P;
-  HIPCHK(hipDeviceSynchronize());
-  HIPCHK(hipMemcpy(d0, P.d0, sizeof(float) * P.n * P.n, hipMemcpyDeviceToHost));
+  hipStream_t a = aux_stream(AUX_COPY);
+  if (!a) return KP_ERR_HIP;
+  HIPCHK(hipMemcpyAsync(d0, P.d0, sizeof(float) * P.n * P.n, hipMemcpyDeviceToHost, a));
+  HIPCHK(hipStreamSynchronize(a));
   return KP_OK;
 }
 
@@ -828,22 +905,26 @@ int kp_get_factors(kp_plan_t plan, double* sc, double* sr, double* vc, double* v
   if (!plan || !sc || !sr) return KP_ERR_ARG;
   Plan& P = plan->P;
   const int n = P.n;
-  HIPCHK(hipDeviceSynchronize());
-  HIPCHK(hipMemcpy(sc, P.sc, sizeof(double) * n, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(sr, P.sr, sizeof(double) * n, hipMemcpyDeviceToHost));
+  hipStream_t a = aux_stream(AUX_COPY);
+  if (!a) return KP_ERR_HIP;
+  HIPCHK(hipMemcpyAsync(sc, P.sc, sizeof(double) * n, hipMemcpyDeviceToHost, a));
+  HIPCHK(hipMemcpyAsync(sr, P.sr, sizeof(double) * n, hipMemcpyDeviceToHost, a));
+  HIPCHK(hipStreamSynchronize(a));
   if (vc || vr) {
     const size_t nn = (size_t)n * n;
     float* tmp = new (std::nothrow) float[nn];
     if (!tmp) return KP_ERR_ARG;
     int rc = KP_OK;
     if (vc) {
-      if (hipMemcpy(tmp, P.Vc32, sizeof(float) * nn, hipMemcpyDeviceToHost) != hipSuccess)
+      if (hipMemcpyAsync(tmp, P.Vc32, sizeof(float) * nn, hipMemcpyDeviceToHost, a) !=
+              hipSuccess || hipStreamSynchronize(a) != hipSuccess)
         rc = KP_ERR_HIP;
       else
         for (size_t i = 0; i < nn; ++i) vc[i] = tmp[i];
     }
     if (vr && rc == KP_OK) {
-      if (hipMemcpy(tmp, P.Vr32, sizeof(float) * nn, hipMemcpyDeviceToHost) != hipSuccess)
+      if (hipMemcpyAsync(tmp, P.Vr32, sizeof(float) * nn, hipMemcpyDeviceToHost, a) !=
+              hipSuccess || hipStreamSynchronize(a) != hipSuccess)
         rc = KP_ERR_HIP;
       else
         for (size_t i = 0; i < nn; ++i) vr[i] = tmp[i];

@@ -19,6 +19,7 @@ namespace kpcg {
 
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+
 // grid of ngrid in [1, max_points] finite positive values
 bool valid_grid(const double* grid, int ngrid, int max_points = 64);
 

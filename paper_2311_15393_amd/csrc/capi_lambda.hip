@@ -41,6 +41,7 @@ extern "C" {
 int kp_features(kp_plan_t plan, const float* b, float* features_out, void* stream) {
   if (!plan || !b || !features_out || !aligned16(b)) return KP_ERR_ARG;
   HIPCHK(launch_features(plan->P, b, features_out, reinterpret_cast<hipStream_t>(stream)));
+  HIPCHK(hipEventRecord(plan->P.ev_last, reinterpret_cast<hipStream_t>(stream)));
   return KP_OK;
 }
 

@@ -244,6 +244,7 @@ struct Plan {
   double* hist = nullptr;        // residual history (2 KP_HIST_MAX FP64)
   int hist_count = 0;            // entries recorded by the last solve
   double hist_gamma0sq = 0.0;    // its ||A^T b||^2
+  hipEvent_t ev_last = nullptr;   // recorded after the plan's last enqueued work
   hipEvent_t ev_start = nullptr;  // pcg_solve timing (created on first use)
   hipEvent_t ev_end = nullptr;
   Ctrl* host_ctrl = nullptr;     // pinned
@@ -314,9 +315,20 @@ hipError_t launch_precond_fp8(const Plan& P, const float* r, float* z, const flo
                               bool finalize, float lam2, hipStream_t s);
 bool fp8_supported_size(int n);   // the FP8 chain needs n to be a multiple of 128
 
-int batched_solve(Plan* const* plans, const float* const* b, const double* lambdas,
-                  const int* plan_of_item, int nitems, double tol, int maxit, int mode,
-                  float* const* x, kp_info_t* infos, hipStream_t user_stream);
+// Non-blocking streams of the current device, created once per device and
+// slot and kept for the process: the getters' copies run on AUX_COPY, the
+// batched solver (whose iterations are captured into a graph; the caller's
+// stream may be the legacy default stream, which cannot be captured) on
+// AUX_BATCH.  NULL on error.
+enum AuxSlot : int { AUX_COPY = 0, AUX_BATCH = 1 };
+hipStream_t aux_stream(int slot);
+
+// The batched solve.  With need_out set, stores the workspace bytes the
+// batch needs there and, if ws is NULL, returns without launching anything.
+int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int mode,
+                  double tol, int maxit, const float* const* b, const double* lambdas,
+                  float* const* x, kp_info_t* infos, void* ws, size_t ws_bytes,
+                  size_t* need_out, hipStream_t user_stream);
 hipError_t launch_spectral_gemms(const Plan& P, const float* b, float* out, hipStream_t s);
 
 // MFMA blur (blur_mfma.hip): chunks per tap row, table entries per

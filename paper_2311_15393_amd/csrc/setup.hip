@@ -18,7 +18,11 @@
 #include <rocsolver/rocsolver.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -350,18 +354,151 @@ static bool force_general_svd() {
   return v != nullptr && v[0] == '1';
 }
 
-int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
+// ---------------------------------------------------------------------------
+// Device memory of the construction.  Nothing here is allocated: every
+// buffer, rocSOLVER's own workspace included, is a view into the plan's
+// workspace (the region the solver's vectors use later), and rocBLAS is
+// handed that workspace with rocblas_set_workspace.  One rocBLAS handle per
+// device serves every construction in the process, under a lock.
+// ---------------------------------------------------------------------------
+namespace {
+
+std::mutex g_setup_mu;
+std::map<int, rocblas_handle> g_handles;                      // device -> handle
+std::map<std::pair<int, std::pair<int, int>>, size_t> g_ws;   // (device, (n, k)) -> bytes
+
+// the current device's handle (caller holds g_setup_mu)
+rocblas_handle device_handle() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  auto it = g_handles.find(dev);
+  if (it != g_handles.end()) return it->second;
+  rocblas_handle h = nullptr;
+  if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
+  g_handles[dev] = h;
+  return h;
+}
+
+// rocSOLVER / rocBLAS device workspace the construction's calls need, by
+// rocBLAS's size query (no call computes anything in query mode; the
+// pointers only have to be non-null).  Caller holds g_setup_mu.  0 on error.
+size_t solver_ws_bytes_locked(int n, int K) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  const auto key = std::make_pair(dev, std::make_pair(n, K));
+  auto it = g_ws.find(key);
+  if (it != g_ws.end()) return it->second;
+  rocblas_handle h = device_handle();
+  if (!h) return 0;
+  double* dp = reinterpret_cast<double*>(static_cast<uintptr_t>(256));
+  float* fp = reinterpret_cast<float*>(static_cast<uintptr_t>(256));
+  rocblas_int* ip = reinterpret_cast<rocblas_int*>(static_cast<uintptr_t>(256));
+  size_t bytes = 0;
+  bool ok = rocblas_start_device_memory_size_query(h) == rocblas_status_success;
+  if (ok) {
+    const double one = 1.0, zero = 0.0;
+    // every call the construction can make (the symmetric and general
+    // paths, FP64 and the reduced-precision FP32 variants, the D0 product
+    // with up to K^2 term pairs); statuses other than success are expected
+    // in query mode and ignored
+    rocsolver_dgesvd(h, rocblas_svect_all, rocblas_svect_all, K, K, dp, K, dp, dp, K, dp, K,
+                     dp, rocblas_outofplace, ip);
+    rocsolver_dgesvd(h, rocblas_svect_all, rocblas_svect_all, n, n, dp, n, dp, dp, n, dp, n, dp,
+                     rocblas_outofplace, ip);
+    rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, dp, n, dp, dp, ip);
+    rocsolver_sgesvd(h, rocblas_svect_all, rocblas_svect_all, n, n, fp, n, fp, fp, n, fp, n, fp,
+                     rocblas_outofplace, ip);
+    rocsolver_ssyevd(h, rocblas_evect_original, rocblas_fill_upper, n, fp, n, fp, fp, ip);
+    rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, n, n,
+                  (rocblas_int)((size_t)K * K), &one, dp, n, dp, n, &zero, dp, n);
+    ok = rocblas_stop_device_memory_size_query(h, &bytes) == rocblas_status_success;
+  }
+  if (!ok) return 0;
+  bytes = bytes < 256 ? 256 : bytes;
+  g_ws[key] = bytes;
+  return bytes;
+}
+
+}  // namespace
+
+// Views of the construction's buffers; see scratch_layout.
+struct SetupScratch {
+  double *dpsf, *pw, *spsf, *upsf, *vpsf, *e, *prof, *T, *U, *Vt, *wv, *pall, *G2, *D64;
+  rocblas_int* info;
+  int* perm;
+  float *T32, *U32, *Vt32, *s32, *e32;
+  void* rocws;
+  size_t rocws_bytes;
+};
+
+// Lay the construction's buffers out from `base` (NULL: sizes only), with
+// rocws bytes of solver workspace first, and return the bytes they take.  The term count t is at most K, so the Gram matrices of the
+// exact diagonal are sized for t = K.
+static size_t scratch_layout(int n, int K, size_t rocws, char* base, SetupScratch* S) {
+  const size_t nn = (size_t)n * n, KK = (size_t)K * K;
+  size_t cur = 0;
+  auto take = [&](size_t bytes) -> char* {
+    cur = (cur + 255) / 256 * 256;
+    char* p = base ? base + cur : nullptr;
+    cur += bytes;
+    return p;
+  };
+  SetupScratch tmp;
+  SetupScratch& Q = S ? *S : tmp;
+  Q.rocws = take(rocws);
+  Q.rocws_bytes = rocws;
+  Q.dpsf = (double*)take(8 * KK);
+  Q.pw = (double*)take(8 * KK);
+  Q.spsf = (double*)take(8 * (size_t)K);
+  Q.upsf = (double*)take(8 * KK);
+  Q.vpsf = (double*)take(8 * KK);
+  Q.e = (double*)take(8 * (size_t)(n > K ? n : K));
+  Q.prof = (double*)take(8 * 2 * (size_t)K);
+  Q.T = (double*)take(8 * nn);
+  Q.U = (double*)take(8 * nn);
+  Q.Vt = (double*)take(8 * nn);
+  Q.info = (rocblas_int*)take(sizeof(rocblas_int));
+  Q.wv = (double*)take(8 * (size_t)n);
+  Q.perm = (int*)take(sizeof(int) * (size_t)n);
+  Q.T32 = (float*)take(4 * nn);
+  Q.U32 = (float*)take(4 * nn);
+  Q.Vt32 = (float*)take(4 * nn);
+  Q.s32 = (float*)take(4 * (size_t)n);
+  Q.e32 = (float*)take(4 * (size_t)n);
+  Q.pall = (double*)take(8 * 2 * KK);
+  Q.G2 = (double*)take(8 * 2 * KK * (size_t)n);
+  Q.D64 = (double*)take(8 * nn);
+  return (cur + 255) / 256 * 256;
+}
+
+size_t setup_scratch_bytes(int n, int K) {
+  size_t rocws;
+  {
+    std::lock_guard<std::mutex> lk(g_setup_mu);
+    rocws = solver_ws_bytes_locked(n, K);
+  }
+  if (rocws == 0) return 0;
+  return scratch_layout(n, K, rocws, nullptr, nullptr);
+}
+
+int build_factors(Plan& P, const double* psf_host, char* scratch, hipStream_t s) {
   const int n = P.n, K = P.k;
   const size_t nn = (size_t)n * n;
   int rc = KP_OK;
-  rocblas_handle handle = nullptr;
-  double *dpsf = nullptr, *pw = nullptr, *spsf = nullptr, *upsf = nullptr, *vpsf = nullptr,
-         *e = nullptr, *prof = nullptr, *T = nullptr, *U = nullptr, *Vt = nullptr;
-  rocblas_int* info = nullptr;
-  double* wv = nullptr;
-  int* perm = nullptr;
-  double *pall = nullptr, *G2 = nullptr, *D64 = nullptr;   // exact KP-basis diagonal
-  float *T32 = nullptr, *U32 = nullptr, *Vt32 = nullptr, *s32 = nullptr, *e32 = nullptr;
+  std::lock_guard<std::mutex> lk(g_setup_mu);
+  rocblas_handle handle = device_handle();
+  if (!handle) return KP_ERR_SOLVER;
+  SetupScratch S;
+  const size_t rocws = solver_ws_bytes_locked(n, K);
+  if (rocws == 0) return KP_ERR_SOLVER;
+  scratch_layout(n, K, rocws, scratch, &S);
+  double *dpsf = S.dpsf, *pw = S.pw, *spsf = S.spsf, *upsf = S.upsf, *vpsf = S.vpsf, *e = S.e,
+         *prof = S.prof, *T = S.T, *U = S.U, *Vt = S.Vt;
+  rocblas_int* info = S.info;
+  double* wv = S.wv;
+  int* perm = S.perm;
+  double *pall = S.pall, *G2 = S.G2, *D64 = S.D64;          // exact KP-basis diagonal
+  float *T32 = S.T32, *U32 = S.U32, *Vt32 = S.Vt32, *s32 = S.s32, *e32 = S.e32;
   int lexp[2] = {0, 0};                                     // KP_SETUP_LOWP factor scales
   int tall = 0;
   size_t glds = 0;
@@ -371,30 +508,9 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
   const int nthr = 256;
   const unsigned gnn = (unsigned)((nn + nthr - 1) / nthr);
 
-  HCHK(hipMalloc(&dpsf, sizeof(double) * K * K));
-  HCHK(hipMalloc(&pw, sizeof(double) * K * K));
-  HCHK(hipMalloc(&spsf, sizeof(double) * K));
-  HCHK(hipMalloc(&upsf, sizeof(double) * K * K));
-  HCHK(hipMalloc(&vpsf, sizeof(double) * K * K));
-  HCHK(hipMalloc(&e, sizeof(double) * (n > K ? n : K)));
-  HCHK(hipMalloc(&prof, sizeof(double) * 2 * K));
-  HCHK(hipMalloc(&T, sizeof(double) * nn));
-  HCHK(hipMalloc(&U, sizeof(double) * nn));
-  HCHK(hipMalloc(&Vt, sizeof(double) * nn));
-  HCHK(hipMalloc(&info, sizeof(rocblas_int)));
-  HCHK(hipMalloc(&wv, sizeof(double) * n));
-  HCHK(hipMalloc(&perm, sizeof(int) * n));
-  if (P.lowp) {
-    HCHK(hipMalloc(&T32, sizeof(float) * nn));
-    HCHK(hipMalloc(&U32, sizeof(float) * nn));
-    HCHK(hipMalloc(&Vt32, sizeof(float) * nn));
-    HCHK(hipMalloc(&s32, sizeof(float) * n));
-    HCHK(hipMalloc(&e32, sizeof(float) * n));
-  }
-  HCHK(hipMemcpyAsync(dpsf, psf_host, sizeof(double) * K * K, hipMemcpyHostToDevice, s));
-
-  SCHK(rocblas_create_handle(&handle));
   SCHK(rocblas_set_stream(handle, s));
+  SCHK(rocblas_set_workspace(handle, S.rocws, S.rocws_bytes));
+  HCHK(hipMemcpyAsync(dpsf, psf_host, sizeof(double) * K * K, hipMemcpyHostToDevice, s));
 
   // blur taps
   hipLaunchKernelGGL(taps_kernel, dim3((K * P.kq + 255) / 256), dim3(256), 0, s, dpsf, K, P.kq,
@@ -455,9 +571,6 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
   // every term's profiles, and room for the per-factor Gram matrices of the
   // exact diagonal D0 = diag(V^T A^T A V) (built below)
   if (tall > 0) {
-    HCHK(hipMalloc(&pall, sizeof(double) * 2 * tall * K));
-    HCHK(hipMalloc(&G2, sizeof(double) * 2 * (size_t)tall * tall * n));
-    HCHK(hipMalloc(&D64, sizeof(double) * nn));
     hipLaunchKernelGGL(all_profiles_kernel, dim3((tall * K + 255) / 256), dim3(256), 0, s, spsf,
                        upsf, vpsf, K, n, P.bc, tall, pall);
     HCHK(hipGetLastError());
@@ -573,12 +686,10 @@ int build_factors(Plan& P, const double* psf_host, hipStream_t s) {
 
 done:
   hipStreamSynchronize(s);
-  if (handle) rocblas_destroy_handle(handle);
-  hipFree(dpsf); hipFree(pw); hipFree(spsf); hipFree(upsf); hipFree(vpsf); hipFree(e);
-  hipFree(prof); hipFree(T); hipFree(U); hipFree(Vt); hipFree(info); hipFree(wv);
-  hipFree(perm); hipFree(pall); hipFree(G2); hipFree(D64);
-  hipFree(T32); hipFree(U32); hipFree(Vt32); hipFree(s32); hipFree(e32);
+  // the workspace belongs to this plan: leave the handle without it
+  rocblas_set_workspace(handle, nullptr, 0);
   return rc;
 }
+
 
 }  // namespace kpcg

@@ -2,8 +2,9 @@
 
 Argument marshalling only: every step of the computation runs in the HIP
 library.  Device buffers are torch CUDA tensors (float32, contiguous, n x n);
-torch supplies device memory and the stream.  The binding fails loudly if the
-shared library has not been built.
+torch supplies all device memory (the plan, model and batch workspaces are
+torch uint8 tensors the library only takes views into) and the stream.  The
+binding fails loudly if the shared library has not been built.
 """
 from __future__ import annotations
 
@@ -18,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libkpcg.so")
 
 # status codes and mode bits (mirror include/kpcg.h)
 KP_OK, KP_MAXIT, KP_BREAKDOWN, KP_OK_FALLBACK = 0, 1, 2, 3
-KP_ERR_ARG, KP_ERR_UNSUPPORTED, KP_ERR_HIP, KP_ERR_SOLVER, KP_ERR_WORKSPACE = -1, -2, -3, -4, -5
+KP_ERR_ARG, KP_ERR_UNSUPPORTED, KP_ERR_HIP, KP_ERR_WORKSPACE, KP_ERR_SOLVER = -1, -2, -3, -4, -5
 KP_CG, KP_PCG, KP_FPCG = 0x000, 0x001, 0x002
 KP_P32, KP_P16, KP_P8 = 0x000, 0x010, 0x020
 KP_WARM = 0x100
@@ -85,7 +86,9 @@ _SIGS = {
     "kp_destroy": (ctypes.c_int, [_VP]),
     "pcg_solve_batched": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP, ctypes.c_int,
                                          ctypes.c_double, ctypes.c_int, ctypes.c_int, _VP,
-                                         _VP, _VP]),
+                                         _VP, _VP, ctypes.c_size_t, _VP]),
+    "pcg_solve_batched_workspace_size": (ctypes.c_size_t, [_VP, ctypes.c_int, _VP, ctypes.c_int,
+                                                           ctypes.c_int]),
     "kp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "kp_blur": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
     "kp_normal_fp64": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP]),
@@ -185,11 +188,30 @@ class SolveInfo:
 
 
 def workspace_size(n: int, k: int) -> int:
+    """kp_workspace_size: device bytes of a plan (0 for invalid sizes)."""
     return int(load().kp_workspace_size(n, k, 0))
 
 
+def _workspace(nbytes: int, what: str):
+    """A torch-owned device buffer of nbytes (uint8, 256-byte aligned by the
+    caching allocator) for the library to take views into."""
+    import torch
+    if nbytes <= 0:
+        raise KPError(KP_ERR_ARG, what)
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=torch.cuda.current_device())
+
+
+def _ws_ptr(workspace):
+    if workspace is None:
+        return None, 0
+    return (ctypes.c_void_p(workspace.data_ptr()),
+            workspace.numel() * workspace.element_size())
+
+
 class Plan:
-    """kp_setup / kp_destroy around one PSF and image size."""
+    """kp_setup / kp_destroy around one PSF and image size.  The plan lives
+    in `workspace` (a CUDA tensor of at least workspace_size(n, k) bytes);
+    by default the binding allocates one with torch."""
 
     def __init__(self, psf: np.ndarray, n: int, bc: int = 0, stream=None, workspace=None):
         lib = load()
@@ -198,10 +220,12 @@ class Plan:
             raise ValueError("psf must be a square 2-D array")
         self.n, self.k = int(n), int(psf.shape[0])
         self.bc = int(bc)
+        if workspace is None and 1 <= self.k <= 2 * self.n - 1 and self.k % 2 == 1:
+            nbytes = lib.kp_workspace_size(self.n, self.k, 0)
+            if nbytes:
+                workspace = _workspace(nbytes, "kp_workspace_size")
         self._ws = workspace
-        wptr, wbytes = None, 0
-        if workspace is not None:
-            wptr, wbytes = ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+        wptr, wbytes = _ws_ptr(workspace)
         h = ctypes.c_void_p()
         st = lib.kp_setup(psf.ctypes.data_as(ctypes.c_void_p), self.k, self.n, int(bc), wptr,
                           wbytes, _stream(stream), ctypes.byref(h))
@@ -400,11 +424,12 @@ class Mlp:
     def __init__(self, max_batch: int = 1024, stream=None, workspace=None):
         lib = load()
         self.max_batch = int(max_batch)
+        if workspace is None:
+            nbytes = lib.mlp_workspace_size(self.max_batch)
+            if nbytes:
+                workspace = _workspace(nbytes, "mlp_workspace_size")
         self._ws = workspace
-        wptr, wbytes = None, 0
-        if workspace is not None:
-            wptr = ctypes.c_void_p(workspace.data_ptr())
-            wbytes = workspace.numel() * workspace.element_size()
+        wptr, wbytes = _ws_ptr(workspace)
         h = ctypes.c_void_p()
         _check(lib.mlp_create(self.max_batch, wptr, wbytes, _stream(stream), ctypes.byref(h)),
                "mlp_create")
@@ -508,10 +533,21 @@ def _feature_rows(features) -> int:
     return int(features.shape[0])
 
 
+def batched_workspace_size(plans, plan_of_item, mode: int = KP_FPCG | KP_P16) -> int:
+    """pcg_solve_batched_workspace_size: device bytes of one batched call."""
+    hp = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    poi = np.ascontiguousarray(plan_of_item, dtype=np.int32)
+    return int(load().pcg_solve_batched_workspace_size(hp, len(plans),
+                                                       poi.ctypes.data_as(ctypes.c_void_p),
+                                                       poi.size, int(mode)))
+
+
 def solve_batched(plans, bs, lambdas, plan_of_item, tol: float = 1e-6, maxit: int = 1000,
-                  mode: int = KP_FPCG | KP_P16, xs=None, stream=None):
+                  mode: int = KP_FPCG | KP_P16, xs=None, stream=None, workspace=None):
     """pcg_solve_batched: item i solves with plans[plan_of_item[i]], data bs[i]
-    (CUDA float32 n_i x n_i), parameter lambdas[i].  Returns (xs, infos, status)."""
+    (CUDA float32 n_i x n_i), parameter lambdas[i].  The batch runs in
+    `workspace` (CUDA tensor of at least batched_workspace_size bytes; by
+    default allocated with torch for the call).  Returns (xs, infos, status)."""
     import torch
     lib = load()
     nitems = len(bs)
@@ -519,6 +555,12 @@ def solve_batched(plans, bs, lambdas, plan_of_item, tol: float = 1e-6, maxit: in
         raise ValueError("bs, lambdas and plan_of_item must have the same length")
     if xs is None:
         xs = [torch.empty_like(b) for b in bs]
+    if workspace is None:
+        nbytes = batched_workspace_size(plans, plan_of_item, mode)
+        if nbytes == 0:
+            raise KPError(KP_ERR_ARG, "pcg_solve_batched_workspace_size")
+        workspace = _workspace(nbytes, "pcg_solve_batched_workspace_size")
+    wptr, wbytes = _ws_ptr(workspace)
     hp = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
     bp = (ctypes.c_void_p * nitems)(*[_dev_image(b, plans[plan_of_item[i]].n, "b").value
                                       for i, b in enumerate(bs)])
@@ -529,7 +571,7 @@ def solve_batched(plans, bs, lambdas, plan_of_item, tol: float = 1e-6, maxit: in
     infos = (_Info * nitems)()
     st = lib.pcg_solve_batched(hp, len(plans), bp, lam.ctypes.data_as(ctypes.c_void_p),
                                poi.ctypes.data_as(ctypes.c_void_p), nitems, float(tol),
-                               int(maxit), int(mode), xp, infos, _stream(stream))
+                               int(maxit), int(mode), xp, infos, wptr, wbytes, _stream(stream))
     if st < 0:
         raise KPError(st, "pcg_solve_batched")
     out = [SolveInfo(i.iters, i.status, i.replacements, i.relres_rec, i.relres_true, i.lambda_,
