@@ -130,13 +130,16 @@ typedef struct kp_plan_info_s {
     int32_t kron_terms;     /* numerical rank of the weighted PSF: the
                                number of Kronecker terms needed to
                                represent A exactly (Table 1's k)          */
-    int32_t reserved;
+    int32_t normal_op;      /* form of H p the solver uses: KP_NORMAL_DIRECT
+                               or KP_NORMAL_FFT (autotuned at setup)      */
     double  kp_rel_error;   /* ||A - A_r (x) A_c||_F / ||A||_F (Table 1)   */
     double  sigma_c_max, sigma_c_min, sigma_r_max, sigma_r_min;
     size_t  device_bytes;   /* device memory held by the plan              */
     int32_t blur_config;    /* blur tile shape picked by the setup-time
                                autotuner (index into its candidate list)  */
     float   blur_config_ms[8]; /* autotuner time per candidate (ms)       */
+    int32_t fft_length;     /* L of the FFT form (zero-padded L x L grid)   */
+    float   normal_op_ms[2];   /* autotuner time of H p: direct, FFT (ms)  */
 } kp_plan_info_t;
 
 /*
@@ -463,6 +466,37 @@ int kp_time_precond(kp_plan_t plan, const float *r, double lambda, int mode,
 #define KP_BLUR_MFMA 6
 #define KP_BLUR_MFMA32 7
 int kp_set_blur_config(kp_plan_t plan, int cfg, int *prev);
+
+/*
+ * The normal operator H p = A^T A p + lambda^2 p in two forms, both FP32:
+ *  - KP_NORMAL_DIRECT: A p then A^T (A p) on the plan's direct blur (the
+ *    kernel kp_set_blur_config selects);
+ *  - KP_NORMAL_FFT: zero-padded FFTs (Section 2.3 names FFTs for
+ *    structured A; Section 5.2's cost model assumes cheap matvecs): with L
+ *    the smallest even 2,3,5,7-smooth size >= n + (K-1)/2 and Hc the L x L
+ *    DFT of the PSF wrapped around the origin, A p = crop(IDFT(Hc .*
+ *    DFT(pad p))) and A^T q = crop(IDFT(conj(Hc) .* DFT(pad q))) on the
+ *    n x n window (exact: every wrapped tap lands in the zero pad).  Five
+ *    passes of one-workgroup-per-line Stockham FFTs in LDS; FP32 with the
+ *    PSF spectrum and twiddles computed in FP64.
+ * kp_setup times both on the plan and the solver uses the faster.  The FFT
+ * form applies the zero boundary's operator: it is offered for KP_BC_ZERO
+ * plans only (others: direct; forcing FFT gives KP_ERR_UNSUPPORTED).
+ * kp_set_normal_op forces a form for pcg_solve's iterations (true residuals
+ * stay on the blurs); kp_normal computes y = H x with the plan's form
+ * (KP_NORMAL_PLAN) or a given one, into the FP32 device image y (x and y
+ * must differ; the direct form uses the plan's scratch vector); it
+ * synchronises.  kp_time_normal: mean time of `reps` back-to-back
+ * applications between HIP events (synchronises).
+ */
+#define KP_NORMAL_PLAN   -1
+#define KP_NORMAL_DIRECT  0
+#define KP_NORMAL_FFT     1
+int kp_set_normal_op(kp_plan_t plan, int op, int *prev);
+int kp_normal(kp_plan_t plan, const float *x, double lambda, float *y, int op,
+              void *stream);
+int kp_time_normal(kp_plan_t plan, const float *x, float *y, int op, int reps,
+                   float *avg_ms, void *stream);
 
 /* Copy the exact KP-basis diagonal D0[i][j] = ||A (v_c,i v_r,j^T)||_F^2
    (the table KP_EXACT_DIAG uses; built by kp_setup from all Kronecker terms

@@ -146,6 +146,52 @@ hipError_t autotune_blur(Plan& P, hipStream_t s, float* times_ms) {
   return err;
 }
 
+// The two forms of w = A^T A p + lam2 p (p . w partials included): the
+// direct blurs (A p into q, then the normal epilogue) and the FFT passes.
+// Each is timed over 3 launches after one warm-up on the scratch vector p
+// (zeros) and the faster is kept; kp_set_normal_op overrides the choice.
+hipError_t launch_normal_direct(const Plan& P, const float* p, float* w, float lam2,
+                                hipStream_t s, int* nb) {
+  hipError_t e = launch_blur_f32(P, p, P.q, false, s, nullptr);
+  if (e != hipSuccess) return e;
+  EpiNormalW en{p, w, lam2, P.n};
+  return blur_dispatch(P.blur_cfg, P, P.q, P.taps32, en, nullptr, 0, s, nb);
+}
+
+hipError_t autotune_normal(Plan& P, hipStream_t s) {
+  hipEvent_t e0, e1;
+  hipError_t err = hipEventCreate(&e0);
+  if (err != hipSuccess) return err;
+  err = hipEventCreate(&e1);
+  if (err != hipSuccess) {
+    hipEventDestroy(e0);
+    return err;
+  }
+  const float lam2 = 1e-4f;
+  // the FFT form applies the zero boundary's operator only
+  const int nops = P.bc == KP_BC_ZERO ? 2 : 1;
+  P.normal_times[1] = 0.f;
+  for (int op = 0; op < nops && err == hipSuccess; ++op) {
+    auto run = [&]() {
+      int nb;
+      return op == 0 ? launch_normal_direct(P, P.p, P.w, lam2, s, &nb)
+                     : launch_fft_normal(P, P.p, P.w, lam2, s, &nb, nullptr);
+    };
+    err = run();
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    for (int it = 0; it < 3 && err == hipSuccess; ++it) err = run();
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    P.normal_times[op] = ms / 3.f;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  P.normal_op = (err == hipSuccess && nops == 2 && P.normal_times[1] < P.normal_times[0]) ? 1 : 0;
+  return err;
+}
+
 hipError_t launch_rhs(const Plan& P, const float* b, bool zero_x, hipStream_t s) {
   EpiRhs e{P.r, P.n, P.p, P.w, zero_x ? P.x64 : nullptr};
   int nb;

@@ -82,6 +82,11 @@ size_t layout(int n, int k, char* base, Plan* P, char** scratch = nullptr) {
   Q.VrT8s = b.take<uint8_t>(nsc);
   Q.UcT32 = b.take<float>(nn);
   Q.UrT32 = b.take<float>(nn);
+  const int fL = fft_length(n, k), fF = fL / 2 + 1;
+  Q.fft_L = fL;
+  Q.fft_nrad = fft_radices(fL, Q.fft_rad);
+  Q.fft_tw = b.take<float2>((size_t)fL);
+  Q.fft_Ht = b.take<float2>((size_t)fF * fL);
   Q.spec = b.take<double>((((nn * sizeof(float)) + ALIGN - 1) / ALIGN * ALIGN) / sizeof(double) +
                           128 + 2 * 64 * 256);
   Q.ctrl = b.take<Ctrl>(1);
@@ -108,6 +113,8 @@ size_t layout(int n, int k, char* base, Plan* P, char** scratch = nullptr) {
   Q.t3s = b.take<uint8_t>(nsc);
   Q.rs = b.take<uint8_t>(nsc);
   Q.r8 = b.take<uint8_t>(nn);
+  Q.fft_S = b.take<float2>((size_t)n * fF);
+  Q.fft_T = b.take<float2>((size_t)n * fF);
   (void)Q;
   const size_t vec_end = (b.cur + ALIGN - 1) / ALIGN * ALIGN;
   const size_t scr = setup_scratch_bytes(n, k);
@@ -146,11 +153,16 @@ hipError_t enqueue_tail(Plan& P, int solver, int prec, float lam2, hipStream_t s
 // the first half of an iteration: matvecs, step length, update, ||r||
 hipError_t enqueue_matvec_half(Plan& P, float lam2, hipStream_t s) {
   hipError_t e;
-  e = launch_blur_f32(P, P.p, P.q, false, s, P.ctrl);           // q = A p
-  if (e != hipSuccess) return e;
   int nbd = 0;
-  e = launch_blur_normal(P, P.q, P.p, P.w, lam2, s, &nbd);      // w = A^T q + l^2 p, p.w
-  if (e != hipSuccess) return e;
+  if (P.normal_op == KP_NORMAL_FFT) {
+    e = launch_fft_normal(P, P.p, P.w, lam2, s, &nbd, P.ctrl);  // w = H p, p.w (FFTs)
+    if (e != hipSuccess) return e;
+  } else {
+    e = launch_blur_f32(P, P.p, P.q, false, s, P.ctrl);         // q = A p
+    if (e != hipSuccess) return e;
+    e = launch_blur_normal(P, P.q, P.p, P.w, lam2, s, &nbd);    // w = A^T q + l^2 p, p.w
+    if (e != hipSuccess) return e;
+  }
   return launch_update_alpha(P, nbd, s);                        // alpha; x, r, ||r||
 }
 
@@ -304,6 +316,7 @@ int kp_setup(const double* psf, int k, int n, int bc_flags, void* workspace, siz
     rc = KP_ERR_HIP;
   if (rc == KP_OK) rc = build_factors(P, psf, scratch, s);
   if (rc == KP_OK && autotune_blur(P, s, P.blur_times) != hipSuccess) rc = KP_ERR_HIP;
+  if (rc == KP_OK && autotune_normal(P, s) != hipSuccess) rc = KP_ERR_HIP;
   if (rc == KP_OK && hipEventRecord(P.ev_last, s) != hipSuccess) rc = KP_ERR_HIP;
   if (rc == KP_OK && hipStreamSynchronize(s) != hipSuccess) rc = KP_ERR_HIP;
   if (rc != KP_OK) {
@@ -325,7 +338,7 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t* out) {
   out->n = P.n;
   out->k = P.k;
   out->kron_terms = P.terms;
-  out->reserved = 0;
+  out->normal_op = P.normal_op;
   out->kp_rel_error = P.kp_err;
   out->sigma_c_max = P.sc_max;
   out->sigma_c_min = P.sc_min;
@@ -334,6 +347,9 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t* out) {
   out->device_bytes = P.bytes;
   out->blur_config = P.blur_cfg;
   for (int i = 0; i < 8; ++i) out->blur_config_ms[i] = P.blur_times[i];
+  out->fft_length = P.fft_L;
+  out->normal_op_ms[0] = P.normal_times[0];
+  out->normal_op_ms[1] = P.normal_times[1];
   return KP_OK;
 }
 
@@ -891,6 +907,68 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int* prev) {
 // its stream), so the getters wait for nothing else: they copy on the
 // device's auxiliary stream (non-blocking, so the copies neither wait for
 // nor hold up other streams) and wait for those copies only.
+int kp_set_normal_op(kp_plan_t plan, int op, int* prev) {
+  if (!plan || (op != KP_NORMAL_DIRECT && op != KP_NORMAL_FFT)) return KP_ERR_ARG;
+  if (op == KP_NORMAL_FFT && plan->P.bc != KP_BC_ZERO) return KP_ERR_UNSUPPORTED;
+  if (prev) *prev = plan->P.normal_op;
+  plan->P.normal_op = op;
+  return KP_OK;
+}
+
+static hipError_t normal_op_launch(Plan& P, const float* x, float* y, float lam2, int op,
+                                   hipStream_t s) {
+  int nb;
+  return op == KP_NORMAL_FFT ? launch_fft_normal(P, x, y, lam2, s, &nb, nullptr)
+                             : launch_normal_direct(P, x, y, lam2, s, &nb);
+}
+
+static bool valid_normal_op(int op) {
+  return op == KP_NORMAL_PLAN || op == KP_NORMAL_DIRECT || op == KP_NORMAL_FFT;
+}
+
+int kp_normal(kp_plan_t plan, const float* x, double lambda, float* y, int op, void* stream) {
+  if (!plan || !x || !y || x == y || !(lambda >= 0.0) || !std::isfinite(lambda) ||
+      !valid_normal_op(op))
+    return KP_ERR_ARG;
+  Plan& P = plan->P;
+  if (x == P.q || y == P.q) return KP_ERR_ARG;
+  if (op == KP_NORMAL_FFT && P.bc != KP_BC_ZERO) return KP_ERR_UNSUPPORTED;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(normal_op_launch(P, x, y, (float)(lambda * lambda),
+                          op == KP_NORMAL_PLAN ? P.normal_op : op, s));
+  HIPCHK(hipEventRecord(P.ev_last, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return KP_OK;
+}
+
+int kp_time_normal(kp_plan_t plan, const float* x, float* y, int op, int reps, float* avg_ms,
+                   void* stream) {
+  if (!plan || !x || !y || x == y || reps < 1 || !avg_ms || !valid_normal_op(op))
+    return KP_ERR_ARG;
+  Plan& P = plan->P;
+  const int which = op == KP_NORMAL_PLAN ? P.normal_op : op;
+  if (which == KP_NORMAL_FFT && P.bc != KP_BC_ZERO) return KP_ERR_UNSUPPORTED;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return KP_ERR_HIP;
+  }
+  int rc = KP_OK;
+  if (hipEventRecord(e0, s) != hipSuccess) rc = KP_ERR_HIP;
+  for (int i = 0; i < reps && rc == KP_OK; ++i)
+    if (normal_op_launch(P, x, y, 1e-4f, which, s) != hipSuccess) rc = KP_ERR_HIP;
+  if (rc == KP_OK && hipEventRecord(e1, s) != hipSuccess) rc = KP_ERR_HIP;
+  if (rc == KP_OK && hipEventSynchronize(e1) != hipSuccess) rc = KP_ERR_HIP;
+  float ms = 0.f;
+  if (rc == KP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = KP_ERR_HIP;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *avg_ms = ms / reps;
+  return rc;
+}
+
 int kp_get_diag(kp_plan_t plan, float* d0) {
   if (!plan || !d0) return KP_ERR_ARG;
   Plan& P = plan->P;

@@ -178,6 +178,10 @@ __device__ inline void set_scales(Ctrl* c, double rr) {
   c->zscale = (float)(1.0 / ((double)s * c->lam2));
 }
 
+// FFT normal operator limits: L <= 2100 for n <= 2048, K <= 63
+constexpr int FFT_MAX_RADICES = 12;
+constexpr int FFT_MAX_L = 2100;
+
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
@@ -250,6 +254,18 @@ struct Plan {
   Ctrl* host_ctrl = nullptr;     // pinned
   CtrlMirror* mirror = nullptr;  // coherent pinned host memory (host address)
   CtrlMirror* mirror_dev = nullptr;  // its device address
+
+  // FFT form of the normal operator (fft.hip): length L, its radices, the
+  // twiddle table, the PSF spectrum (transposed, scaled by 1/L^2) and two
+  // n x (L/2 + 1) complex work arrays
+  int fft_L = 0, fft_nrad = 0;
+  int fft_rad[FFT_MAX_RADICES] = {};
+  void* fft_tw = nullptr;
+  void* fft_Ht = nullptr;
+  void* fft_S = nullptr;
+  void* fft_T = nullptr;
+  int normal_op = 0;             // H p by the direct blurs (0) or the FFTs (1)
+  float normal_times[2] = {};    // autotuner time of each form (ms)
 
   int blur_cfg = 0;              // blur kernel (autotuned; BLUR_CFG_MFMA = MFMA)
   int blur_cfg_valu = 0;         // fastest FP32-VALU tile shape (batched path)
@@ -339,6 +355,20 @@ size_t mfma32_taps_count(int K);      // the same for the 32 x 32 x 16 kernel
 int mfma_blocks(int n);
 hipError_t build_mfma_taps(const Plan& P, hipStream_t s);
 
+// FFT form of w = A^T A p + lam2 p with the partials of p.w (fft.hip); the
+// plan's FFT length and radices, and the twiddle / PSF-spectrum tables
+// (g_scratch: K (L/2 + 1) complex FP64)
+int fft_length(int n, int k);
+int fft_radices(int L, int* rad);
+hipError_t build_fft_tables(const Plan& P, const double* psf_dev, void* g_scratch,
+                            hipStream_t s);
+hipError_t launch_fft_normal(const Plan& P, const float* p, float* w, float lam2, hipStream_t s,
+                             int* nb, const Ctrl* ctrl);
+// w = A^T A p + lam2 p on the plan's direct blurs (A p into P.q)
+hipError_t launch_normal_direct(const Plan& P, const float* p, float* w, float lam2,
+                                hipStream_t s, int* nb);
+// time both forms of H p on this plan and keep the faster (P.normal_op)
+hipError_t autotune_normal(Plan& P, hipStream_t s);
 hipError_t launch_spectrum(const Plan& P, const float* b, hipStream_t s);
 hipError_t launch_spectral_scores(const Plan& P, const double* grid_dev, int ngrid,
                                   double omega, double noise2, int kind, double* out_dev,

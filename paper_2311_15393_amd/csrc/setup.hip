@@ -427,6 +427,7 @@ struct SetupScratch {
   rocblas_int* info;
   int* perm;
   float *T32, *U32, *Vt32, *s32, *e32;
+  void* fftG;                // PSF rows' spectra of the FFT normal operator
   void* rocws;
   size_t rocws_bytes;
 };
@@ -468,6 +469,7 @@ static size_t scratch_layout(int n, int K, size_t rocws, char* base, SetupScratc
   Q.pall = (double*)take(8 * 2 * KK);
   Q.G2 = (double*)take(8 * 2 * KK * (size_t)n);
   Q.D64 = (double*)take(8 * nn);
+  Q.fftG = take(16 * (size_t)K * (size_t)(fft_length(n, K) / 2 + 1));
   return (cur + 255) / 256 * 256;
 }
 
@@ -523,6 +525,8 @@ int build_factors(Plan& P, const double* psf_host, char* scratch, hipStream_t s)
     HCHK(build_mfma_taps(P, s));
   }
   HCHK(hipGetLastError());
+  // tables of the FFT form of the normal operator
+  HCHK(build_fft_tables(P, dpsf, S.fftG, s));
 
   // weighted PSF SVD
   hipLaunchKernelGGL(weighted_psf_kernel, dim3((K * K + 255) / 256), dim3(256), 0, s, dpsf, K,

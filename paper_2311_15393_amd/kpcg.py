@@ -35,6 +35,7 @@ KP_BC_REFLEXIVE = 2
 KP_SETUP_LOWP = 0x100
 KP_BLUR_MFMA = 6
 KP_BLUR_MFMA32 = 7
+KP_NORMAL_PLAN, KP_NORMAL_DIRECT, KP_NORMAL_FFT = -1, 0, 1
 KP_MLP_NFEAT, KP_MLP_HIDDEN, KP_MLP_NPARAM = 128, 256, 164865
 
 
@@ -55,12 +56,13 @@ class _Info(ctypes.Structure):
 
 class _PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("k", ctypes.c_int32),
-                ("kron_terms", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("kron_terms", ctypes.c_int32), ("normal_op", ctypes.c_int32),
                 ("kp_rel_error", ctypes.c_double),
                 ("sigma_c_max", ctypes.c_double), ("sigma_c_min", ctypes.c_double),
                 ("sigma_r_max", ctypes.c_double), ("sigma_r_min", ctypes.c_double),
                 ("device_bytes", ctypes.c_size_t), ("blur_config", ctypes.c_int32),
-                ("blur_config_ms", ctypes.c_float * 8)]
+                ("blur_config_ms", ctypes.c_float * 8), ("fft_length", ctypes.c_int32),
+                ("normal_op_ms", ctypes.c_float * 2)]
 
 
 class _LambdaInfo(ctypes.Structure):
@@ -102,6 +104,10 @@ _SIGS = {
     "kp_time_precond": (ctypes.c_int, [_VP, _VP, ctypes.c_double, ctypes.c_int, _VP,
                                        ctypes.c_int, ctypes.POINTER(ctypes.c_float), _VP]),
     "kp_set_blur_config": (ctypes.c_int, [_VP, ctypes.c_int, _VP]),
+    "kp_set_normal_op": (ctypes.c_int, [_VP, ctypes.c_int, _VP]),
+    "kp_normal": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, ctypes.c_int, _VP]),
+    "kp_time_normal": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_float), _VP]),
     "opt_lambda": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP, _VP]),
     "kp_features": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "mlp_workspace_size": (ctypes.c_size_t, [ctypes.c_int]),
@@ -253,8 +259,9 @@ class Plan:
     def query(self) -> dict:
         pi = _PlanInfo()
         _check(load().kp_plan_query(self._h, ctypes.byref(pi)), "kp_plan_query")
-        out = {f: getattr(pi, f) for f, _ in _PlanInfo._fields_ if f != "reserved"}
+        out = {f: getattr(pi, f) for f, _ in _PlanInfo._fields_}
         out["blur_config_ms"] = list(out["blur_config_ms"])
+        out["normal_op_ms"] = list(out["normal_op_ms"])
         return out
 
     def factors(self, with_v: bool = True):
@@ -392,6 +399,28 @@ class Plan:
         _check(load().kp_time_precond(self._h, _dev_image(r, self.n, "r"), float(lam), int(mode),
                                       _dev_image(z, self.n, "z"), int(reps), ctypes.byref(ms),
                                       _stream(stream)), "kp_time_precond")
+        return float(ms.value)
+
+    def set_normal_op(self, op: int) -> int:
+        """kp_set_normal_op: H p for the solver's iterations by the direct
+        blurs (KP_NORMAL_DIRECT) or the FFTs (KP_NORMAL_FFT); returns the
+        previous choice."""
+        prev = ctypes.c_int()
+        _check(load().kp_set_normal_op(self._h, int(op), ctypes.byref(prev)), "kp_set_normal_op")
+        return prev.value
+
+    def normal(self, x, lam: float, y, op: int = KP_NORMAL_PLAN, stream=None):
+        """kp_normal: y = (A^T A + lam^2 I) x in FP32 by the given form."""
+        _check(load().kp_normal(self._h, _dev_image(x, self.n, "x"), float(lam),
+                                _dev_image(y, self.n, "y"), int(op), _stream(stream)),
+               "kp_normal")
+        return y
+
+    def time_normal(self, x, y, op: int = KP_NORMAL_PLAN, reps: int = 20, stream=None) -> float:
+        ms = ctypes.c_float()
+        _check(load().kp_time_normal(self._h, _dev_image(x, self.n, "x"),
+                                     _dev_image(y, self.n, "y"), int(op), int(reps),
+                                     ctypes.byref(ms), _stream(stream)), "kp_time_normal")
         return float(ms.value)
 
     def set_blur_config(self, cfg: int) -> int:

@@ -1,0 +1,96 @@
+"""The FFT form of the normal operator (KP_NORMAL_FFT) against the FP64
+oracle operator, and solves that use it.
+
+FP32 FFT error analysis (Higham, Accuracy and Stability of Numerical
+Algorithms, ch. 24): a radix-based FFT of length L computed in precision u
+has normwise relative error at most about log2(L) (u + gamma_4 (sqrt 2 + mu))
+with mu the twiddle error (here one FP32 rounding of FP64 values), about
+1e-6 for L ~ 2100.  H p applies four transforms of that length and two
+pointwise products: the bar is 1e-5 normwise (relative to ||H p||), which a
+wrong twiddle, radix butterfly, packing or crop misses by orders of
+magnitude."""
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import operator as O
+from oracle import solvers as SV
+from tests.gpu_util import rel, require_gpu, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(37, 9), (64, 15), (100, 31), (129, 23), (256, 63), (1024, 15), (1024, 63),
+         (2048, 63)]
+
+
+def _psf(k, seed):
+    rng = np.random.default_rng(seed)
+    return S.psf_moffat_motion(k, rng.uniform(3, 8), 2.5, rng.uniform(3, 9),
+                               rng.uniform(0, np.pi))
+
+
+@pytest.mark.parametrize("n,k", CASES)
+def test_fft_normal_matches_oracle(n, k):
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_NORMAL_DIRECT, KP_NORMAL_FFT, Plan
+    psf = _psf(k, n + k)
+    x = S.random_image(np.random.default_rng(n), n) - 0.5
+    lam = 0.01
+    with Plan(psf, n) as plan:
+        info = plan.query()
+        y = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        plan.normal(to_dev(x), lam, y, op=KP_NORMAL_FFT)
+        got_fft = to_host(y)
+        plan.normal(to_dev(x), lam, y, op=KP_NORMAL_DIRECT)
+        got_dir = to_host(y)
+    x64 = x.astype(np.float64)
+    fft = O.FFTBlur(psf, n) if n > 256 else None
+    ref = O.normal_op(psf, lam, x64, fft)
+    e_fft, e_dir = rel(got_fft, ref), rel(got_dir, ref)
+    say(f"n={n} K={k} L={info['fft_length']}: |fft - ref| {e_fft:.2e}, |direct - ref| "
+        f"{e_dir:.2e}; autotuned form {info['normal_op']} (direct {info['normal_op_ms'][0]:.4f} "
+        f"ms, fft {info['normal_op_ms'][1]:.4f} ms)")
+    assert e_fft <= 1e-5
+    assert e_dir <= 1e-5
+
+
+@pytest.mark.parametrize("n,k,mode_name", [(256, 31, "fpcg16"), (1024, 63, "fpcg16"),
+                                           (200, 15, "pcg32"), (64, 15, "cg")])
+def test_solve_with_fft_normal(n, k, mode_name):
+    """Solves whose iterations use the FFT form reach x_lambda (1e-4 for the
+    FP16 preconditioner and CG, 1e-5 for FP32), certified by true
+    residuals on the blurs.  CG runs to a tighter tolerance: without a
+    preconditioner the error is up to cond(H) times the relative residual
+    (about 2.5e3 here)."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_CG, KP_FPCG, KP_NORMAL_FFT, KP_OK, KP_P16, KP_P32, KP_PCG
+    from paper_2311_15393_amd import Plan
+    mode = {"fpcg16": KP_FPCG | KP_P16, "pcg32": KP_PCG | KP_P32, "cg": KP_CG}[mode_name]
+    bar = 1e-5 if mode_name == "pcg32" else 1e-4
+    tol = {"pcg32": 1e-7, "cg": 1e-9}.get(mode_name, 1e-6)
+    psf = _psf(k, 7 * n + k)
+    prob = S.make_problem(n, psf, np.random.default_rng(n + 1), 0.01, None, n + 1, "fft")
+    lam = 0.02
+    with Plan(psf, n) as plan:
+        plan.set_normal_op(KP_NORMAL_FFT)
+        x, info = plan.solve(to_dev(prob.b), lam, tol=tol, maxit=3000, mode=mode)
+        got = to_host(x)
+    if n >= 1024:
+        ref = SV.x_lambda_iterative(psf, prob.b.astype(np.float64), lam, check=True)[0]
+    else:
+        ref = SV.x_lambda(psf, prob.b.astype(np.float64), lam)
+    err = rel(got, ref)
+    say(f"{mode_name} n={n} K={k} via FFT: iters={info.iters} status={info.status} err={err:.2e}")
+    assert info.status == KP_OK and err <= bar
+
+
+def test_fft_form_refused_off_the_zero_boundary():
+    torch = require_gpu()
+    from paper_2311_15393_amd import (KP_BC_PERIODIC, KP_ERR_UNSUPPORTED, KP_NORMAL_FFT, KPError,
+                                      Plan)
+    n, k = 64, 9
+    with Plan(_psf(k, 1), n, bc=KP_BC_PERIODIC) as plan:
+        assert plan.query()["normal_op"] == 0
+        with pytest.raises(KPError) as ei:
+            plan.set_normal_op(KP_NORMAL_FFT)
+        assert ei.value.status == KP_ERR_UNSUPPORTED
