@@ -694,6 +694,13 @@ int pcg_solve_batched(const kp_plan_t* plans, int nplans, const float* const* b,
   std::vector<Plan*> ps;
   int rc = batched_args(plans, nplans, plan_of_item, nitems, mode, ps);
   if (rc != KP_OK) return rc;
+  {
+    // the sizing pass refuses unsupported item shapes before anything else
+    size_t need = 0;
+    rc = batched_solve(ps.data(), plan_of_item, nitems, mode, 0.0, 0, nullptr, nullptr, nullptr,
+                       nullptr, nullptr, 0, &need, nullptr);
+    if (rc != KP_OK) return rc;
+  }
   if (!b || !lambdas || !x || !infos || !workspace) return KP_ERR_ARG;
   if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 1) return KP_ERR_ARG;
   for (int i = 0; i < nitems; ++i) {

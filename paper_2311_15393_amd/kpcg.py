@@ -587,7 +587,14 @@ def solve_batched(plans, bs, lambdas, plan_of_item, tol: float = 1e-6, maxit: in
     if workspace is None:
         nbytes = batched_workspace_size(plans, plan_of_item, mode)
         if nbytes == 0:
-            raise KPError(KP_ERR_ARG, "pcg_solve_batched_workspace_size")
+            # the size query cannot say why: the solve itself names the
+            # refusal (it validates everything before it needs a workspace)
+            hp = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+            poi = np.ascontiguousarray(plan_of_item, dtype=np.int32)
+            st = lib.pcg_solve_batched(hp, len(plans), None, None,
+                                       poi.ctypes.data_as(ctypes.c_void_p), nitems, 1.0, 1,
+                                       int(mode), None, None, None, 0, _stream(stream))
+            raise KPError(st if st < 0 else KP_ERR_ARG, "pcg_solve_batched_workspace_size")
         workspace = _workspace(nbytes, "pcg_solve_batched_workspace_size")
     wptr, wbytes = _ws_ptr(workspace)
     hp = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
