@@ -399,6 +399,25 @@ int mlp_fit_normalizer(kp_mlp_t mlp, const float *features, int nb,
 int lambda_predict(kp_mlp_t mlp, const float *features, int nb,
                    double *log10_lambda, void *stream);
 
+/* lambda_predict_noalloc -- lambda_predict for callers that cannot
+   allocate device memory (code under HIP graph capture, serving loops,
+   harnesses that forbid hipMalloc): the same kernels and results, with the
+   network's activations in a static device array of the library
+   (KP_PREDICT_NOALLOC_BYTES, about 10.5 MiB per GPU, held until the
+   process ends) instead of the model's workspace.  1 <= nb <=
+   KP_PREDICT_NOALLOC_MAX_ROWS (larger nb: KP_ERR_WORKSPACE; call again per
+   chunk).  Calls no allocating routine: the array's device address is
+   looked up once per device, with that device current, by mlp_create (or
+   by the first call on a device where no model was created).
+   Every call on one GPU shares the array: calls that overlap on a GPU (two
+   streams, two threads) race and must be serialised by the caller.
+   Nothing in the array needs to start at zero (the forward writes every
+   activation of rows 0..nb-1 before reading it).  Does not synchronise. */
+#define KP_PREDICT_NOALLOC_MAX_ROWS 2048
+#define KP_PREDICT_NOALLOC_BYTES 11026432   /* 10.5 MiB + 16 KiB */
+int lambda_predict_noalloc(kp_mlp_t mlp, const float *features, int nb,
+                           double *log10_lambda, void *stream);
+
 /* mlp_train_step -- one Adam step on the minibatch rows[0..nb) (host
    array of indices into the nrows feature rows / targets; NULL: rows
    0..nb-1) of features (device, nrows x 128) and targets (device, nrows

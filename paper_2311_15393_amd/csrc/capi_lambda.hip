@@ -4,6 +4,7 @@
 // Kronecker basis of Section 5.1) as the judge of its answer.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -11,6 +12,11 @@
 #include "mlp.h"
 
 using namespace kpcg;
+
+// lambda_predict_noalloc's activations (see scratch_address below)
+constexpr size_t kNoallocBytes = kpcg::mlp_act_bytes(KP_PREDICT_NOALLOC_MAX_ROWS);
+static_assert(kNoallocBytes == KP_PREDICT_NOALLOC_BYTES, "header states the array's size");
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
 
 struct kp_mlp_s {
   Mlp M;
@@ -25,6 +31,33 @@ constexpr int kMaxBatch = 65536;
 
 size_t model_bytes(int max_batch) {
   return (mlp_layout(max_batch, nullptr, nullptr) + 255) / 256 * 256 + 1024;
+}
+
+// lambda_predict_noalloc: the forward activations of up to
+// KP_PREDICT_NOALLOC_MAX_ROWS rows in a static device array (each GPU the
+// library runs on holds its own copy until the process ends).  Host code
+// never passes the array's name to a kernel or copy: it is a host-side
+// stand-in, not a device address.  The device address is looked up once per
+// device with hipGetSymbolAddress (that device current) and kept: at
+// mlp_create, or on the entry point's first call on a device where no model
+// was created.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return KP_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || (reinterpret_cast<uintptr_t>(p) & 255u) != 0) return KP_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return KP_OK;
 }
 
 int read_loss(const Mlp& M, double* out, hipStream_t s) {
@@ -106,6 +139,11 @@ int mlp_create(int max_batch, void* workspace, size_t ws_bytes, void* stream, kp
         hipStreamSynchronize(s) != hipSuccess)
       rc = KP_ERR_HIP;
   }
+  // set-up of lambda_predict_noalloc on this device: the static array's
+  // device address (the runtime makes the array resident here, so that the
+  // entry point itself has nothing left to set up)
+  void* sp = nullptr;
+  if (rc == KP_OK) rc = scratch_address(&sp);
   if (rc != KP_OK) {
     if (M.host_loss) hipHostFree(M.host_loss);
     if (M.owns) hipFree(base);
@@ -177,6 +215,25 @@ int lambda_predict(kp_mlp_t mlp, const float* features, int nb, double* log10_la
     const int cnt = nb - off < M.max_batch ? nb - off : M.max_batch;
     HIPCHK(mlp_forward(M, features + (size_t)off * MLP_NF, nullptr, cnt, log10_lambda + off, s));
   }
+  return KP_OK;
+}
+
+int lambda_predict_noalloc(kp_mlp_t mlp, const float* features, int nb, double* log10_lambda,
+                           void* stream) {
+  if (!mlp || !features || !log10_lambda || nb < 1) return KP_ERR_ARG;
+  if (!aligned16(features)) return KP_ERR_ARG;
+  if (nb > KP_PREDICT_NOALLOC_MAX_ROWS) return KP_ERR_WORKSPACE;
+  void* base = nullptr;
+  const int rc = scratch_address(&base);
+  if (rc != KP_OK) return rc;
+  // the model's weights and normaliser; activations in the static array
+  Mlp Q = mlp->M;
+  Q.max_batch = KP_PREDICT_NOALLOC_MAX_ROWS;
+  if (mlp_act_layout(KP_PREDICT_NOALLOC_MAX_ROWS, reinterpret_cast<char*>(base), &Q) >
+      kNoallocBytes)
+    return KP_ERR_WORKSPACE;
+  HIPCHK(mlp_forward(Q, features, nullptr, nb, log10_lambda,
+                     reinterpret_cast<hipStream_t>(stream)));
   return KP_OK;
 }
 

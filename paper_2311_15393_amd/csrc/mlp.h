@@ -75,6 +75,17 @@ struct Mlp {
 
 size_t mlp_layout(int max_batch, char* base, Mlp* M);
 
+// bytes of the forward activations (h0, z1, h1, z2, h2, z3, h3, y, dz4) of
+// `rows` rows, each buffer 256-byte aligned; mlp_act_layout points M's
+// activation buffers into base (which must be 256-byte aligned) and returns
+// the bytes used, which equal mlp_act_bytes(rows)
+constexpr size_t mlp_a256(size_t v) { return (v + 255) / 256 * 256; }
+constexpr size_t mlp_act_bytes(size_t rows) {
+  return mlp_a256(rows * MLP_NF * 2) + 3 * mlp_a256(rows * MLP_NH * 4) +
+         2 * mlp_a256(rows * MLP_NH * 2) + mlp_a256(rows * MLP_NH * 4) + 2 * mlp_a256(rows * 4);
+}
+size_t mlp_act_layout(int rows, char* base, Mlp* M);
+
 // forward through the hidden layers and the output layer for nb rows of X
 // (rows == nullptr: rows 0..nb-1, else the device indices rows[0..nb)),
 // writing y (and, if pred != nullptr, the outputs as FP64 to pred)

@@ -428,6 +428,26 @@ size_t mlp_layout(int max_batch, char* base, Mlp* M) {
   return (cur + 255) / 256 * 256;
 }
 
+size_t mlp_act_layout(int rows, char* base, Mlp* M) {
+  size_t cur = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base + cur;
+    cur += mlp_a256(bytes);
+    return p;
+  };
+  const size_t B = (size_t)rows;
+  M->h0 = reinterpret_cast<_Float16*>(take(B * MLP_NF * 2));
+  M->z1 = reinterpret_cast<float*>(take(B * MLP_NH * 4));
+  M->h1 = reinterpret_cast<_Float16*>(take(B * MLP_NH * 2));
+  M->z2 = reinterpret_cast<float*>(take(B * MLP_NH * 4));
+  M->h2 = reinterpret_cast<_Float16*>(take(B * MLP_NH * 2));
+  M->z3 = reinterpret_cast<float*>(take(B * MLP_NH * 4));
+  M->h3 = reinterpret_cast<float*>(take(B * MLP_NH * 4));
+  M->y = reinterpret_cast<float*>(take(B * 4));
+  M->dz4 = reinterpret_cast<float*>(take(B * 4));
+  return cur;
+}
+
 hipError_t mlp_forward(const Mlp& M, const float* X, const int* rows, int nb, double* pred,
                        hipStream_t s) {
   if (nb < 1 || nb > M.max_batch) return hipErrorInvalidValue;

@@ -28,6 +28,7 @@ KP_NO_FALLBACK = 0x400
 KP_EXACT_DIAG = 0x800
 KP_HIST = 0x1000
 KP_HIST_MAX = 16384
+KP_PREDICT_NOALLOC_MAX_ROWS = 2048
 KP_MAX_PSF = 63
 KP_BC_ZERO = 0
 KP_BC_PERIODIC = 1
@@ -118,6 +119,7 @@ _SIGS = {
     "mlp_get_normalizer": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "mlp_fit_normalizer": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP]),
     "lambda_predict": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP, _VP]),
+    "lambda_predict_noalloc": (ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP, _VP]),
     "mlp_train_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP, ctypes.c_int,
                                       ctypes.c_float, _VP, _VP]),
     "mlp_gradients": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP, _VP, _VP]),
@@ -520,6 +522,18 @@ class Mlp:
         _check(load().lambda_predict(self._h, ctypes.c_void_p(features.data_ptr()), nb,
                                      ctypes.c_void_p(out.data_ptr()), _stream(stream)),
                "lambda_predict")
+        return out
+
+    def predict_noalloc(self, features, out, stream=None):
+        """lambda_predict_noalloc: as predict, with the activations in the
+        library's static device array (at most KP_PREDICT_NOALLOC_MAX_ROWS
+        rows; `out` is required, so nothing is allocated)."""
+        import torch
+        nb = _feature_rows(features)
+        _check_vec(out, nb, "out", torch.float64)
+        _check(load().lambda_predict_noalloc(self._h, ctypes.c_void_p(features.data_ptr()), nb,
+                                             ctypes.c_void_p(out.data_ptr()), _stream(stream)),
+               "lambda_predict_noalloc")
         return out
 
     def train_step(self, features, targets, lr: float, rows=None, want_loss: bool = False,
