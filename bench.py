@@ -137,23 +137,173 @@ def cpu_threads() -> int:
     return max(1, min(c, 16))
 
 
+MODE_LABELS = {"fp16_kp_fpcg": "FP16-KP flexible PCG", "fp32_kp_pcg": "FP32-KP PCG",
+               "fp8_kp_fpcg": "FP8-KP flexible PCG", "none_cg": "CG (no preconditioner)",
+               "fp16_kpdiag_fpcg": "FP16-KP flexible PCG, exact KP-basis diagonal",
+               "fp32_kpdiag_pcg": "FP32-KP PCG, exact KP-basis diagonal"}
+
+
+def mode_bits_table():
+    from paper_2311_15393_amd import KP_CG, KP_EXACT_DIAG, KP_FPCG, KP_P8, KP_P16, KP_P32, KP_PCG
+    return {"fp16_kp_fpcg": KP_FPCG | KP_P16, "fp32_kp_pcg": KP_PCG | KP_P32,
+            "fp8_kp_fpcg": KP_FPCG | KP_P8, "none_cg": KP_CG,
+            "fp16_kpdiag_fpcg": KP_FPCG | KP_P16 | KP_EXACT_DIAG,
+            "fp32_kpdiag_pcg": KP_PCG | KP_P32 | KP_EXACT_DIAG}
+
+
+# tolerance ladder: 1e-5, 5e-6, 2e-6, 1e-6, 5e-7, ... down to 1e-9
+LADDER = [m * 10.0 ** e for e in range(-5, -10, -1) for m in (1.0, 0.5, 0.2)] + [1e-9]
+
+
+def time_solves(run, steps: int, warmup: int):
+    """`warmup` untimed solves, then exactly `steps` timed ones, each from b
+    resident in HBM to x resident in HBM (pcg_solve returns after its stream
+    has drained); the device is synchronised on both sides of the timed
+    region.  Returns the per-solve wall times (ms) and the last info."""
+    import torch
+    info = None
+    for _ in range(warmup):
+        _, info = run()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        _, info = run()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    torch.cuda.synchronize()
+    return ts, info
+
+
+def run_instance(seed: int, modes, args, grid, dev, nthreads: int, keep: bool):
+    """One instance of the large workload (its own image, Moffat + motion
+    PSF and noise): lambda by the device's KP-GCV (its grid index must equal
+    the oracle's), the oracle's settled x_lambda, then per mode the loosest
+    ladder tolerance whose x is within 1e-4 of x_lambda and `steps` timed
+    solves (per-solve median)."""
+    import torch
+    import synthetic as S
+    from paper_2311_15393_amd import KP_OK, Plan
+    t0 = time.time()
+    prob = S.large_moffat(seed)
+    n = prob.n
+    b = torch.from_numpy(prob.b).to(dev)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    plan = Plan(prob.psf, n)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t1
+    pinfo = plan.query()
+    lam, _ = plan.gcv(b, grid)
+    gidx = int(np.argmin(np.abs(grid - lam)))
+    out = {"seed": seed, "lambda": lam, "gcv_grid_index": gidx, "setup_s": setup_s,
+           "kp_rel_error": pinfo["kp_rel_error"], "blur_config": pinfo["blur_config"],
+           "normal_op": pinfo["normal_op"], "modes": {}}
+    xlam = kp = None
+    if not args.profile_only:
+        from threadpoolctl import threadpool_limits
+        from oracle import kp as KP
+        from oracle import lam as L
+        from oracle import solvers as SV
+        with threadpool_limits(limits=nthreads):
+            kp = KP.kp_svd(prob.psf, n)
+            s2, bh2 = L.spectrum(kp, prob.b.astype(np.float64))
+            ref_idx = L.grid_argmin(L.gcv(s2, bh2, grid))
+            xlam, xinfo = settled_x_lambda(SV, prob, lam, kp, nthreads)
+        out["oracle_gcv_grid_index"] = ref_idx
+        out["x_lambda_oracle"] = {"iters": xinfo["iters"], "true_relres": xinfo["true_relres"],
+                                  "loose_agreement": xinfo["loose_agreement"]}
+    log(f"[bench] seed {seed}: setup {setup_s:.2f}s lambda={lam:.4g} (index {gidx}, oracle "
+        f"{out.get('oracle_gcv_grid_index')}) normal op {pinfo['normal_op']} "
+        f"({time.time() - t0:.1f}s with the oracle)")
+    bits = mode_bits_table()
+
+    def run(mode, tol, maxit):
+        x = torch.empty_like(b)
+        return plan.solve(b, lam, tol=tol, maxit=maxit, mode=mode, x=x, raise_on_fail=False)
+
+    for name in modes:
+        mode, maxit = bits[name], MODES[name]
+        if args.profile_only:
+            tol = PROFILE_TOLS[name]
+            _, info = run(mode, tol, maxit)
+            err = float("nan")
+        else:
+            for tol in LADDER:
+                x, info = run(mode, tol, maxit)
+                err = float(np.linalg.norm(x.cpu().numpy().astype(np.float64) - xlam)
+                            / np.linalg.norm(xlam))
+                if info.status == KP_OK and err <= 1e-4:
+                    break
+        steps = args.steps if name == "fp16_kp_fpcg" else max(1, min(args.steps, 5))
+        warm = args.warmup if name == "fp16_kp_fpcg" else 1
+        ts, info2 = time_solves(lambda: run(mode, tol, maxit), steps, warm)
+        ok = bool(info.status == KP_OK and (args.profile_only or err <= 1e-4)
+                  and (args.profile_only or gidx == out["oracle_gcv_grid_index"]))
+        out["modes"][name] = {"tol": tol, "iters": info.iters, "rel_err": err,
+                              "ms_median": float(np.median(ts)), "ms_mean": float(np.mean(ts)),
+                              "ms_min": float(np.min(ts)), "ok": ok}
+        log(f"[bench]   {name}: tol={tol:.0e} iters={info.iters} err={err:.2e} "
+            f"median {np.median(ts):.3f} ms/solve (min {np.min(ts):.3f})")
+    if keep:
+        return out, {"prob": prob, "b": b, "plan": plan, "lam": lam, "xlam": xlam, "kp": kp,
+                     "pinfo": pinfo, "gidx": gidx, "setup_s": setup_s}
+    plan.close()
+    return out, None
+
+
+def cpu_description() -> dict:
+    """The host the CPU baseline ran on: core counts, CPU model, the BLAS
+    numpy uses (threadpoolctl) and the thread variables."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        info["blas"] = [{k: d.get(k) for k in ("internal_api", "version", "num_threads",
+                                                 "threading_layer")}
+                        for d in threadpool_info() if d.get("user_api") == "blas"]
+    except Exception:
+        pass
+    info["thread_env"] = {k: os.environ[k] for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                                      "MKL_NUM_THREADS") if k in os.environ}
+    return info
+
+
+def matvec_label(pinfo) -> str:
+    if pinfo.get("normal_op") == 1:
+        return "A^T A p by FP32 zero-padded FFTs"
+    if pinfo["blur_config"] in (6, 7):
+        return "A p and A^T q on MFMA, FP16 hi/lo split (3 products, ~22-bit)"
+    return "A p and A^T q on FP32 VALU"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=0, help="first seed of the instances")
+    ap.add_argument("--instances", type=int, default=8, metavar="S",
+                    help="seeds seed .. seed+S-1 of the large workload; the headline is the "
+                         "median over them")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="skip the oracle parts (for profiler runs)")
     ap.add_argument("--no-periodic", action="store_true",
                     help="skip the periodic- and reflexive-boundary solves (also skipped with "
                          "--profile-only)")
-    ap.add_argument("--batch", type=int, default=0, metavar="P",
-                    help="also run the uneven batched workload with P problems x 16 lambda")
-    ap.add_argument("--instances", type=int, default=0, metavar="S",
-                    help="also run the FP16 headline on seeds 0 .. S-1 of the large workload "
-                         "(GCV index and 1e-4 parity against the oracle per seed)")
+    ap.add_argument("--batch", type=int, default=64, metavar="P",
+                    help="the uneven batched workload with P problems x 16 lambda (0: skip)")
     ap.add_argument("--matvec-sweep", action="store_true",
                     help="only compare the direct blurs with a zero-padded rocFFT H p over K "
                          "(prints its own JSON line)")
@@ -167,8 +317,7 @@ def main():
 
     import torch
     import synthetic as S
-    from paper_2311_15393_amd import (KP_CG, KP_EXACT_DIAG, KP_FPCG, KP_OK, KP_P8, KP_P16, KP_P32,
-                                      KP_PCG, Plan)
+    from paper_2311_15393_amd import KP_P16
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -176,116 +325,66 @@ def main():
     if args.matvec_sweep:
         print(json.dumps(run_matvec_sweep(dev)), flush=True)
         return
-
-    t0 = time.time()
-    prob = S.large_moffat(args.seed)
-    n, k = prob.n, prob.k
     grid = S.lambda_grid()
-    log(f"[bench] problem n={n} k={k} generated in {time.time() - t0:.1f}s")
+    chosen = [m for m in args.modes.split(",") if m]
+    assert "fp16_kp_fpcg" in chosen and all(m in MODES for m in chosen), args.modes
 
-    b = torch.from_numpy(prob.b).to(dev)
-    torch.cuda.synchronize()
-    t0 = time.time()
-    plan = Plan(prob.psf, n)
-    torch.cuda.synchronize()
-    setup_s = time.time() - t0
-    pinfo = plan.query()
-    log(f"[bench] kp_setup {setup_s:.2f}s kp_err={pinfo['kp_rel_error']:.3e} "
-        f"blur config {pinfo['blur_config']} times(ms) "
-        f"{[round(t, 4) for t in pinfo['blur_config_ms'][:6]]}")
+    # ---- the headline: every mode on each instance, median over instances
+    rows, first = [], None
+    for i in range(max(1, args.instances)):
+        row, kept = run_instance(args.seed + i, chosen, args, grid, dev, nthreads, keep=(i == 0))
+        rows.append(row)
+        if kept is not None:
+            first = kept
+    summary = {}
+    for name in chosen:
+        ms = [r["modes"][name]["ms_median"] for r in rows]
+        summary[name] = {
+            "label": MODE_LABELS[name],
+            "ms_median_over_instances": float(np.median(ms)),
+            "solves_per_s": 1e3 / float(np.median(ms)),
+            "ms_per_instance": ms,
+            "iters_per_instance": [r["modes"][name]["iters"] for r in rows],
+            "tol_per_instance": [r["modes"][name]["tol"] for r in rows],
+            "rel_err_per_instance": [r["modes"][name]["rel_err"] for r in rows],
+            "all_ok": all(r["modes"][name]["ok"] for r in rows),
+        }
+        log(f"[bench] {name}: median {np.median(ms):.3f} ms over {len(rows)} instances "
+            f"({1e3 / np.median(ms):.1f} solves/s), all ok {summary[name]['all_ok']}")
+    head = summary["fp16_kp_fpcg"]
 
-    # lambda by KP-GCV on the GPU
-    lam, scores = plan.gcv(b, grid)
+    # ---- the paper's break-even (Section 5.2): preconditioning pays iff
+    # m_P t_P < m_N t_N, i.e. m_P / m_N < t_N / t_P with t the time of one
+    # iteration of each method, here measured per instance
+    break_even = None
+    if "none_cg" in chosen:
+        per = []
+        for r in rows:
+            mp, mn = r["modes"]["fp16_kp_fpcg"]["iters"], r["modes"]["none_cg"]["iters"]
+            tp = r["modes"]["fp16_kp_fpcg"]["ms_median"] / max(mp, 1)
+            tn = r["modes"]["none_cg"]["ms_median"] / max(mn, 1)
+            per.append({"seed": r["seed"], "m_P": mp, "m_N": mn, "mP_over_mN": mp / max(mn, 1),
+                        "t_P_ms": tp, "t_N_ms": tn, "tN_over_tP": tn / tp,
+                        "pays": bool(mp * tp < mn * tn)})
+        break_even = {"preconditioner": "FP16-KP", "rows": per,
+                      "paper_model_bound": 8.0 / 9.0,
+                      "note": "m_P/m_N against the measured per-iteration cost ratio t_N/t_P "
+                              "(solve time / iterations, including true-residual work)"}
+
+    # ---- seed 0 extras: GCV timing, learned lambda, kernels, CPU baseline
+    prob, b, plan, lam = first["prob"], first["b"], first["plan"], first["lam"]
+    xlam, kp, pinfo = first["xlam"], first["kp"], first["pinfo"]
+    n, k = prob.n, prob.k
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(5):
         plan.gcv(b, grid)
     torch.cuda.synchronize()
     gcv_ms = (time.perf_counter() - t0) / 5 * 1e3
-    gidx = int(np.argmin(np.abs(grid - lam)))
-    log(f"[bench] gcv lambda={lam:.4g} (grid index {gidx}) {gcv_ms:.2f} ms")
-
     learned = time_learned_lambda(plan, b, grid, dev)
     log(f"[bench] learned lambda: kp_lambda_learned {learned['lambda_learned_ms']:.2f} ms at "
         f"{n}^2; lambda_predict {learned['predict_samples_per_s'] / 1e6:.2f} M rows/s; "
         f"train step (256 rows) {learned['train_step_ms']:.3f} ms")
-
-    oracle = {}
-    if not args.profile_only:
-        from threadpoolctl import threadpool_limits
-        from oracle import kp as KP
-        from oracle import lam as L
-        from oracle import solvers as SV
-        with threadpool_limits(limits=nthreads):
-            t0 = time.time()
-            kp = KP.kp_svd(prob.psf, n)
-            s2, bh2 = L.spectrum(kp, prob.b.astype(np.float64))
-            ref_idx = L.grid_argmin(L.gcv(s2, bh2, grid))
-            oracle["gcv_index"] = ref_idx
-            log(f"[bench] oracle KP-SVD + GCV {time.time() - t0:.1f}s index {ref_idx}")
-            assert ref_idx == gidx, f"GPU GCV picked grid index {gidx}, oracle {ref_idx}"
-            t0 = time.time()
-            xlam, xinfo = settled_x_lambda(SV, prob, lam, kp, nthreads)
-            log(f"[bench] oracle x_lambda {time.time() - t0:.1f}s iters={xinfo['iters']} "
-                f"relres={xinfo['true_relres']:.1e} loose agreement "
-                f"{xinfo['loose_agreement']:.1e}")
-
-    def run(mode, tol, maxit):
-        x = torch.empty_like(b)
-        x, info = plan.solve(b, lam, tol=tol, maxit=maxit, mode=mode, x=x, raise_on_fail=False)
-        return x, info
-
-    # tolerance ladder: 1e-5, 5e-6, 2e-6, 1e-6, 5e-7, ... down to 1e-9
-    ladder = [m * 10.0 ** e for e in range(-5, -10, -1) for m in (1.0, 0.5, 0.2)] + [1e-9]
-
-    def pick_tol(name, mode, maxit):
-        """Loosest tolerance on the ladder whose solution meets the 1e-4 bar."""
-        if args.profile_only:
-            tol = PROFILE_TOLS[name]
-            _, info = run(mode, tol, maxit)
-            return tol, info, float("nan")
-        for tol in ladder:
-            x, info = run(mode, tol, maxit)
-            got = x.cpu().numpy().astype(np.float64)
-            err = float(np.linalg.norm(got - xlam) / np.linalg.norm(xlam))
-            log(f"[bench]   mode={mode:#x} tol={tol:.0e} iters={info.iters} "
-                f"status={info.status} err={err:.2e}")
-            if info.status == KP_OK and err <= 1e-4:
-                return tol, info, err
-        return tol, info, err
-
-    def time_mode(mode, tol, maxit, steps, warmup):
-        for _ in range(warmup):
-            run(mode, tol, maxit)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        iters = []
-        for _ in range(steps):
-            _, info = run(mode, tol, maxit)
-            iters.append(info.iters)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        return dt / steps * 1e3, iters
-
-    # the paper's one-term S (kp) and the exact KP-basis diagonal (kpdiag)
-    mode_bits = {"fp16_kp_fpcg": KP_FPCG | KP_P16, "fp32_kp_pcg": KP_PCG | KP_P32,
-                 "fp8_kp_fpcg": KP_FPCG | KP_P8, "none_cg": KP_CG,
-                 "fp16_kpdiag_fpcg": KP_FPCG | KP_P16 | KP_EXACT_DIAG,
-                 "fp32_kpdiag_pcg": KP_PCG | KP_P32 | KP_EXACT_DIAG}
-    chosen = [m for m in args.modes.split(",") if m]
-    assert "fp16_kp_fpcg" in chosen and all(m in MODES for m in chosen), args.modes
-    modes = {m: (mode_bits[m], MODES[m]) for m in chosen}
-    results = {}
-    for name, (mode, maxit) in modes.items():
-        tol, info, err = pick_tol(name, mode, maxit)
-        steps = args.steps if name == "fp16_kp_fpcg" else max(1, min(args.steps, 5))
-        warm = args.warmup if name == "fp16_kp_fpcg" else 1
-        ms, iters = time_mode(mode, tol, maxit, steps, warm)
-        results[name] = {"tol": tol, "iters": info.iters, "rel_err": err,
-                         "ms_per_solve": ms, "solves_per_s": 1e3 / ms,
-                         "ok": bool(info.status == KP_OK and (err <= 1e-4 or args.profile_only))}
-        log(f"[bench] {name}: tol={tol:.0e} iters={info.iters} err={err:.2e} "
-            f"{ms:.3f} ms/solve")
 
     # dominant kernel: the blur matvec (two per iteration), as autotuned
     p = torch.randn((n, n), device=dev, dtype=torch.float32)
@@ -296,9 +395,11 @@ def main():
     achieved = flops / (blur_ms * 1e-3)
     prec_ms = plan.time_precond(p, lam, KP_P16, q, reps=20)
     prec_flops = 8.0 * n ** 3
+    normal_ms = {op: plan.time_normal(p, q, op, reps=20) for op in (0, 1)}
     log(f"[bench] blur kernel {blur_ms * 1e3:.1f} us ({achieved / 1e12:.2f} TFLOP/s); "
         f"FP16 preconditioner chain {prec_ms * 1e3:.1f} us "
-        f"({prec_flops / (prec_ms * 1e-3) / 1e12:.1f} TFLOP/s)")
+        f"({prec_flops / (prec_ms * 1e-3) / 1e12:.1f} TFLOP/s); H p direct "
+        f"{normal_ms[0] * 1e3:.1f} us, FFT {normal_ms[1] * 1e3:.1f} us")
 
     if args.profile_only:
         # plain copy of known size for the counter calibration
@@ -338,6 +439,7 @@ def main():
     if not args.profile_only and not args.no_cpu_baseline:
         from threadpoolctl import threadpool_limits
         from oracle import solvers as SV
+        tol0 = rows[0]["modes"]["fp16_kp_fpcg"]["tol"]
         with threadpool_limits(limits=nthreads):
             op = SV.NormalOperator(prob.psf, n, lam, workers=nthreads)
             pre = SV.kp_preconditioner(prob.psf, n, lam, kp)
@@ -345,8 +447,8 @@ def main():
             t0 = time.time()
             count = 0
             while True:
-                out = SV.solve(op, prob.b.astype(np.float64), mode=SV.FPCG,
-                               tol=results["fp16_kp_fpcg"]["tol"], maxit=1000, precond=pre)
+                out = SV.solve(op, prob.b.astype(np.float64), mode=SV.FPCG, tol=tol0,
+                               maxit=1000, precond=pre)
                 count += 1
                 cpu_s = time.time() - t0
                 if cpu_s >= CPU_SAMPLE_S or count >= CPU_SAMPLE_MAX:
@@ -354,27 +456,27 @@ def main():
         cpu_err = float(np.linalg.norm(out.x - xlam) / np.linalg.norm(xlam))
         cpu_baseline = {
             "value": count / cpu_s, "unit": "solves/s", "cores": nthreads, "kind": "oracle",
-            "sample": (f"{count} FP64 KP-preconditioned flexible-PCG solves of the same 1024^2 "
-                       f"problem (tol {results['fp16_kp_fpcg']['tol']:.0e}, {out.iters} "
-                       f"iterations each, rel err {cpu_err:.1e}; scipy.fft matvecs, numpy BLAS "
-                       f"GEMMs, {cpu_s:.1f} s)"),
+            "sample": (f"{count} FP64 KP-preconditioned flexible-PCG solves of the seed-{args.seed} "
+                       f"1024^2 problem (tol {tol0:.0e}, {out.iters} iterations each, rel err "
+                       f"{cpu_err:.1e}; scipy.fft matvecs with {nthreads} workers, numpy BLAS "
+                       f"GEMMs with {nthreads} threads, {cpu_s:.1f} s)"),
+            "host": cpu_description(),
         }
         log(f"[bench] cpu oracle: {count} solves in {cpu_s:.2f}s iters={out.iters}")
 
-    batch = run_batch(args.batch, dev) if args.batch else None
+    batch = run_batch(args.batch, dev, nthreads, parity=not args.profile_only) \
+        if args.batch else None
     lowp = None
     if not args.profile_only:
-        lowp = run_lowp_setup(prob, b, lam, results["fp16_kp_fpcg"]["tol"], xlam, setup_s)
-    instances = None
-    if args.instances and not args.profile_only:
-        instances = run_instances(args.instances, grid, ladder, args.steps, args.warmup, dev,
-                                  nthreads)
+        lowp = run_lowp_setup(prob, b, lam, rows[0]["modes"]["fp16_kp_fpcg"]["tol"], xlam,
+                              first["setup_s"])
     periodic = reflexive = None
     if not args.profile_only and not args.no_periodic:
-        periodic = run_boundary("periodic", args.seed, grid, ladder, dev)
-        reflexive = run_boundary("reflexive", args.seed, grid, ladder, dev)
+        periodic = run_boundary("periodic", args.seed, grid, LADDER, dev)
+        reflexive = run_boundary("reflexive", args.seed, grid, LADDER, dev)
 
-    head = results["fp16_kp_fpcg"]
+    seeds = f"seeds {args.seed}-{args.seed + len(rows) - 1}" if len(rows) > 1 \
+        else f"seed {args.seed}"
     line = {
         "metric": METRIC,
         "value": head["solves_per_s"],
@@ -382,27 +484,32 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": head["ms_per_solve"],
+        "ms_per_step": head["ms_median_over_instances"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 vectors+matvec, f16 MFMA preconditioner, f64 scalars",
+        "dtype": (f"FP32 vectors with x accumulated in FP64; {matvec_label(pinfo)}; "
+                  "FP16 MFMA preconditioner with FP32 accumulation; FP64 scalars"),
         "data": "synthetic",
         "config": {
-            "workload": ("deblur 1024x1024, Moffat(beta=2.5)+motion PSF 63x63, zero BC, "
-                         "2% noise, lambda by KP-GCV (32-pt grid), FP16-KP flexible PCG"),
-            "n": n, "k": k, "seed": args.seed, "lambda": lam, "gcv_grid_index": gidx,
+            "workload": (f"deblur 1024x1024, Moffat(beta=2.5)+motion PSF 63x63 ({seeds}), zero "
+                         "BC, 2% noise, lambda by KP-GCV (32-pt grid), FP16-KP flexible PCG; "
+                         "value = 1 / (median over the instances of each instance's median "
+                         "solve time)"),
+            "n": n, "k": k, "instances": len(rows),
             "parallelism": "single GPU",
-            "modes": results,
-            "setup_s": setup_s, "gcv_ms": gcv_ms,
-            "kp_rel_error": pinfo["kp_rel_error"],
+            "modes": summary,
+            "per_instance": rows,
+            "break_even": break_even,
+            "gcv_ms": gcv_ms,
             "blur_tile_config": pinfo["blur_config"],
+            "normal_op": pinfo["normal_op"],
+            "normal_op_us": {"direct": normal_ms[0] * 1e3, "fft": normal_ms[1] * 1e3},
             "precond_fp16_chain_us": prec_ms * 1e3,
             "learned_lambda": learned,
             "batched": batch,
             "periodic": periodic,
             "reflexive": reflexive,
-            "instances": instances,
             "lowp_setup": lowp,
         },
         "roofline": roofline,
@@ -556,62 +663,6 @@ def run_boundary(kind: str, seed: int, grid, ladder, dev):
             "blur_us": blur_us}
 
 
-def run_instances(count: int, grid, ladder, steps: int, warmup: int, dev, nthreads: int):
-    """The headline FP16-KP FPCG solve on seeds 0 .. count-1 of the large
-    workload, each with its own image, Moffat + motion PSF and noise: the
-    device's KP-GCV grid index must equal the oracle's, the tolerance is the
-    loosest ladder value whose x meets 1e-4 against the oracle's x_lambda,
-    then `warmup` untimed and `steps` timed solves."""
-    import torch
-    from threadpoolctl import threadpool_limits
-    import synthetic as S
-    from oracle import kp as KP
-    from oracle import lam as L
-    from oracle import solvers as SV
-    from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, Plan
-    rows = []
-    for seed in range(count):
-        prob = S.large_moffat(seed)
-        n = prob.n
-        b = torch.from_numpy(prob.b).to(dev)
-        plan = Plan(prob.psf, n)
-        lam, _ = plan.gcv(b, grid)
-        gidx = int(np.argmin(np.abs(grid - lam)))
-        with threadpool_limits(limits=nthreads):
-            kp = KP.kp_svd(prob.psf, n)
-            s2, bh2 = L.spectrum(kp, prob.b.astype(np.float64))
-            ref_idx = L.grid_argmin(L.gcv(s2, bh2, grid))
-            xlam, _ = settled_x_lambda(SV, prob, lam, kp, nthreads)
-        x = torch.empty_like(b)
-        for tol in ladder:
-            _, info = plan.solve(b, lam, tol=tol, maxit=200, mode=KP_FPCG | KP_P16, x=x,
-                                 raise_on_fail=False)
-            err = float(np.linalg.norm(x.cpu().numpy().astype(np.float64) - xlam)
-                        / np.linalg.norm(xlam))
-            if info.status == KP_OK and err <= 1e-4:
-                break
-        for _ in range(warmup):
-            plan.solve(b, lam, tol=tol, maxit=200, mode=KP_FPCG | KP_P16, x=x)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            plan.solve(b, lam, tol=tol, maxit=200, mode=KP_FPCG | KP_P16, x=x)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) / steps * 1e3
-        plan.close()
-        row = {"seed": seed, "lambda": lam, "gcv_grid_index": gidx,
-               "oracle_gcv_grid_index": ref_idx, "tol": tol, "iters": info.iters,
-               "rel_err": err, "ok": bool(info.status == KP_OK and err <= 1e-4
-                                          and gidx == ref_idx),
-               "ms_per_solve": ms, "solves_per_s": 1e3 / ms}
-        log(f"[bench] instance seed {seed}: lambda={lam:.4g} (index {gidx}, oracle {ref_idx}) "
-            f"tol={tol:.0e} iters={info.iters} err={err:.2e} {ms:.3f} ms/solve")
-        rows.append(row)
-    sps = [r["solves_per_s"] for r in rows]
-    return {"rows": rows, "median_solves_per_s": float(np.median(sps)),
-            "all_ok": all(r["ok"] for r in rows)}
-
-
 def psf_spectrum(psf: np.ndarray, L: int, dev):
     """rfft2 of the PSF zero-padded to L x L (FP32, on dev)."""
     import torch
@@ -711,12 +762,14 @@ def run_matvec_sweep(dev, n: int = 1024, ks=(15, 23, 31, 47, 63), reps: int = 50
     return {"matvec_sweep": {"n": n, "boundary": "zero", "rows": out}}
 
 
-def run_batch(nprob: int, dev):
+def run_batch(nprob: int, dev, nthreads: int = 16, parity: bool = True):
     """Uneven batch: problems of sizes {128,...,1024}, supports 15..63, each
     with 16 lambda values log-spaced over lambda_gcv * 10^[-1.5, 1.5] (KP-GCV
     on the 32-point grid picks lambda_gcv), all solved by one batched FP16
     FPCG call; the sweep is scored by KP-GCV and by the discrepancy principle
-    on the solves' actual misfits."""
+    on the solves' actual misfits.  With `parity`, one item for each of the
+    image sizes 128, 768 and 1024 (the first problem of that size, at the
+    middle of its sweep) is compared with the oracle's settled x_lambda."""
     import torch
     import synthetic as S
     from paper_2311_15393_amd import KP_EXACT_DIAG, KP_FPCG, KP_OK, KP_P16, Plan, solve_batched
@@ -766,6 +819,32 @@ def run_batch(nprob: int, dev):
         for kk, store in ((k_gcv, errs_gcv), (k_dp, errs_dp)):
             x = xs[idx[kk]].cpu().numpy().astype(np.float64)
             store.append(float(np.linalg.norm(x - xt) / np.linalg.norm(xt)))
+    # parity sample: one item per image size against the oracle's x_lambda
+    samples = []
+    if parity:
+        from threadpoolctl import threadpool_limits
+        from oracle import solvers as SV
+        seen = set()
+        for pi, p in enumerate(probs):
+            # the smallest and the two largest image sizes (the oracle's
+            # settled x_lambda at 1024^2 takes tens of seconds on the host)
+            if p.n in seen or p.n not in (128, 768, 1024):
+                continue
+            seen.add(p.n)
+            idx = [kk for kk, (q, _) in enumerate(items) if q == pi]
+            it = idx[len(idx) // 2]
+            lam_it = items[it][1]
+            with threadpool_limits(limits=nthreads):
+                xl, xi = SV.x_lambda_iterative(p.psf, p.b.astype(np.float64), lam_it,
+                                               workers=nthreads, check=True)
+            got = xs[it].cpu().numpy().astype(np.float64)
+            err = float(np.linalg.norm(got - xl) / np.linalg.norm(xl))
+            samples.append({"problem": pi, "n": p.n, "k": p.k, "lambda": lam_it,
+                            "status": int(infos[it].status), "iters": int(infos[it].iters),
+                            "rel_err": err, "ok": bool(infos[it].status == KP_OK and err <= 1e-4
+                                                       and xi["status"] == "converged")})
+            log(f"[bench] batch parity: problem {pi} n={p.n} K={p.k} lambda={lam_it:.3g} "
+                f"iters={infos[it].iters} err={err:.2e}")
     # the same batch with the exact KP-basis diagonal in the preconditioner
     xs2 = [torch.empty_like(b) for b in bs]
     torch.cuda.synchronize()
@@ -785,6 +864,8 @@ def run_batch(nprob: int, dev):
         "setup_s_total": setup_s, "tol": 1e-6, "mode": "fp16_kp_fpcg",
         "err_vs_true_gcv_pick_mean": float(np.mean(errs_gcv)),
         "err_vs_true_dp_pick_mean": float(np.mean(errs_dp)),
+        "parity_samples": samples,
+        "parity_ok": all(x["ok"] for x in samples) if samples else None,
         "exact_diag": {"wall_s": wall2, "solves_per_s": len(items) / wall2, "converged": ok2,
                        "iters_mean": float(iters2.mean()), "iters_max": int(iters2.max())},
     }

@@ -122,12 +122,14 @@ def test_batched_rejects_bad_arguments():
 
 
 def test_uneven_batch_sample_full_sizes():
-    """Four problems of the uneven-size workload (sizes from {128,...,1024},
-    supports 15..63, Gaussian or Moffat), four lambda around each problem's
-    KP-GCV choice: every item converges and meets the FP16 bar."""
+    """Five problems of the uneven-size workload (sizes 128, 384, 1024, 256
+    and 768, supports 15..63, Gaussian or Moffat), three lambda around each
+    problem's KP-GCV choice: every item converges, and the middle item of
+    every problem (the 768^2 and 1024^2 ones included) meets the FP16 bar
+    against the oracle's settled x_lambda."""
     require_gpu()
     from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, Plan
-    probs = [S.batch_problem(i) for i in range(4)]
+    probs = [S.batch_problem(i) for i in (0, 1, 2, 3, 9)]
     plans = [Plan(p.psf, p.n) for p in probs]
     grid = S.lambda_grid()
     items = []
@@ -140,12 +142,15 @@ def test_uneven_batch_sample_full_sizes():
     checked = 0
     for (p, lam), x, inf in zip(items, xs, infos):
         assert inf.status == KP_OK, (p, lam, inf)
-        if lam == items[3 * p + 1][1] and probs[p].n <= 512:
-            err = rel(x, SV.x_lambda(probs[p].psf, probs[p].b.astype(np.float64), lam))
+        if lam == items[3 * p + 1][1]:
+            ref, rinfo = SV.x_lambda_iterative(probs[p].psf, probs[p].b.astype(np.float64), lam,
+                                               check=True)
+            assert rinfo["status"] == "converged" and rinfo["true_relres"] <= 1e-12, rinfo
+            err = rel(x, ref)
             say(f"  n={probs[p].n} k={probs[p].k} lam={lam:.3g} iters={inf.iters} err={err:.2e}")
             assert err <= 1e-4
             checked += 1
-    assert checked >= 1
+    assert checked == len(probs)
     for pl in plans:
         pl.close()
 
