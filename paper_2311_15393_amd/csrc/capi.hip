@@ -141,17 +141,26 @@ int write_ctrl(Plan& P, hipStream_t s, const Ctrl& c) {
   return KP_OK;
 }
 
-// one iteration after the matvecs: update, preconditioner, direction
-hipError_t enqueue_tail(Plan& P, int solver, int prec, float lam2, hipStream_t s) {
+// The second half of an iteration: preconditioner and direction (CG: the
+// direction only).  With fold_rr the preconditioner's first GEMM also takes
+// the residual-norm step of the update before it (fold_rr > 0 partials);
+// without, that step ran already (the right-hand side, a true residual).
+// The direction step is folded into p = z + beta p.  Publishes twice with
+// fold_rr (||r||, then r.z), else once; CG publishes nothing here.
+hipError_t enqueue_tail(Plan& P, int solver, int prec, float lam2, hipStream_t s,
+                        int fold_rr = 0) {
   hipError_t e;
   if (solver == KP_CG) return launch_pupdate_from(P, P.r, s);
-  e = launch_precond(P, P.r, P.z, P.w, prec, true, lam2, s);
+  e = launch_precond(P, P.r, P.z, P.w, prec, true, lam2, s, fold_rr);
   if (e != hipSuccess) return e;
-  return launch_pupdate_from(P, P.z, s);
+  return launch_pupdate_fold(P, P.z, precond_partials(P, prec), s);
 }
 
-// the first half of an iteration: matvecs, step length, update, ||r||
-hipError_t enqueue_matvec_half(Plan& P, float lam2, hipStream_t s) {
+// The first half of an iteration: matvecs, step length, update.  With
+// rr_step the residual-norm step follows as a launch of its own (CG, and the
+// last iteration of a solve, where no preconditioner follows to fold it in)
+// and publishes; without, it publishes nothing.
+hipError_t enqueue_matvec_half(Plan& P, float lam2, hipStream_t s, bool rr_step = true) {
   hipError_t e;
   int nbd = 0;
   if (P.normal_op == KP_NORMAL_FFT) {
@@ -163,11 +172,11 @@ hipError_t enqueue_matvec_half(Plan& P, float lam2, hipStream_t s) {
     e = launch_blur_normal(P, P.q, P.p, P.w, lam2, s, &nbd);    // w = A^T q + l^2 p, p.w
     if (e != hipSuccess) return e;
   }
-  return launch_update_alpha(P, nbd, s);                        // alpha; x, r, ||r||
+  return launch_update_alpha(P, nbd, rr_step, s);               // alpha; x, r, ||r||
 }
 
 hipError_t enqueue_iteration(Plan& P, int solver, int prec, float lam2, hipStream_t s) {
-  hipError_t e = enqueue_matvec_half(P, lam2, s);
+  hipError_t e = enqueue_matvec_half(P, lam2, s, true);
   if (e != hipSuccess) return e;
   return enqueue_tail(P, solver, prec, lam2, s);
 }
@@ -446,11 +455,14 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   };
 
   // The host follows the device through the word the scalar steps publish,
-  // and keeps at most LOOKAHEAD publishing units enqueued beyond the last
-  // publication it has read.  A unit is half an iteration (A p, A^T q, step,
-  // update: publishes ||r||; preconditioner, direction: publishes r.z), or a
-  // whole iteration for CG.  Kernels enqueued after the device has marked
-  // the solve PENDING or finished exit at once and publish nothing.
+  // and keeps at most LOOKAHEAD publications enqueued beyond the last one it
+  // has read.  For PCG and FPCG an iteration is the matvec half (A p, A^T q,
+  // step, update) and the tail (preconditioner, whose first GEMM takes the
+  // update's residual-norm step and publishes ||r||; direction: publishes
+  // r.z); the matvec half of the last iteration, which no tail follows,
+  // launches its own residual-norm step.  For CG an iteration publishes
+  // once (||r||).  Kernels enqueued after the device has marked the solve
+  // PENDING or finished exit at once and publish nothing.
   constexpr unsigned LOOKAHEAD = 2;
   Snap m{};
   unsigned seen = 0;             // the last publication read (mod 2^24)
@@ -459,6 +471,7 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   auto bump = [&]() { enq = (enq + 1u) & MIRROR_PUB_MASK; };
   int its = 0;                   // iterations enqueued (matvec halves)
   bool mv_next = true;           // the next unit is a matvec half
+  bool fold_next = false;        // the next tail folds in the update's ||r|| step
   HIPCHK(launch_rhs(P, b, !(mode & KP_WARM), s));   // r = c = A^T b, ||c||; p = w (= x) = 0
   bump();
   if (mode & KP_WARM) {
@@ -475,16 +488,22 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
       if (solver == KP_CG) {
         e = enqueue_iteration(P, solver, prec, lam2, s);
         ++its;
+        bump();
       } else if (mv_next) {
-        e = enqueue_matvec_half(P, lam2, s);
+        const bool last = its + 1 >= maxit;      // no tail will follow
+        e = enqueue_matvec_half(P, lam2, s, last);
         ++its;
         mv_next = false;
+        fold_next = !last;
+        if (last) bump();
       } else {
-        e = enqueue_tail(P, solver, prec, lam2, s);
+        e = enqueue_tail(P, solver, prec, lam2, s, fold_next ? update_partials(P) : 0);
+        if (fold_next) bump();
+        bump();
         mv_next = true;
+        fold_next = false;
       }
       if (e != hipSuccess) return e;
-      bump();
     }
     return hipSuccess;
   };
@@ -519,6 +538,7 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
       // (publishes nothing), else the preconditioner half as the next unit
       if (solver == KP_CG) HIPCHK(enqueue_tail(P, solver, prec, lam2, s));
       else mv_next = false;
+      fold_next = false;                  // the true residual set ||r|| and the scales
     } else if (m.done != RUNNING) {
       state = m.done;
       break;

@@ -178,6 +178,103 @@ __device__ inline void set_scales(Ctrl* c, double rr) {
   c->zscale = (float)(1.0 / ((double)s * c->lam2));
 }
 
+// ---------------------------------------------------------------------------
+// The iteration's scalar logic, shared by the one-block scalar step and by
+// the kernels that fold a scalar step into their start: there every block
+// sums the partials of the kernel before it, in the scalar step's order (so
+// all blocks obtain the same value and take the same decision), and block 0
+// alone writes the control block.  A kernel that folds a step reads no
+// control-block field that its block 0 writes.  (A last-block reduction
+// would need device-scope release/acquire fences, whose L2 write-backs
+// measured far slower than a second launch.)
+// ---------------------------------------------------------------------------
+constexpr int FOLD_T = 256;            // threads that read partials, as the scalar step
+
+// Sum of the nb partials of `slot`: threads below FOLD_T stride over them
+// as the scalar step does, then the block sum (the other threads add exact
+// zeros).  Returned to every thread through sh[NT / 64 + 1].
+template <int NT>
+__device__ inline double fold_slot(const double* __restrict__ partials, int slot, int nb,
+                                   double* sh) {
+  double s = 0.0;
+  if (threadIdx.x < FOLD_T)
+    for (int i = threadIdx.x; i < nb; i += FOLD_T) s += partials[slot * MAX_PARTIALS + i];
+  const double t = block_sum<NT>(s, sh);
+  if (threadIdx.x == 0) sh[NT / 64] = t;
+  __syncthreads();
+  return sh[NT / 64];
+}
+
+// r.z of the current direction: the last direction step's (PCG, FPCG) or
+// ||r||^2 (CG)
+__device__ inline double step_rho(const Ctrl* c) { return c->solver == KP_CG ? c->rho : c->rz; }
+
+// After the step length (one thread): the direction step's r.z becomes the
+// previous one, and the first-step and Fletcher-Reeves flags are spent.
+// (The direction step itself writes none of these: its blocks read them.)
+__device__ inline void commit_direction(Ctrl* c) {
+  if (c->solver != KP_CG) {
+    c->rho = c->rz;
+    c->first = 0;
+    c->fr_next = 0;
+  }
+}
+
+// The state after an update with ||r||^2 = S (read-only: every block of a
+// folding kernel evaluates it).
+__device__ inline int rr_state(const Ctrl* c, double S) {
+  if (!isfinite(S)) return BREAKDOWN;
+  if (S <= c->tol2 || S <= c->repl2) return PENDING;
+  return RUNNING;
+}
+
+// The residual-norm step after x += alpha p, r -= alpha w (one thread).
+__device__ inline void apply_rr(Ctrl* c, double S) {
+  c->rr = S;
+  c->iter += 1;
+  if (c->solver == KP_CG) {
+    c->rho_prev = c->rho;
+    c->beta = S / c->rho;
+    c->rho = S;
+  }
+  set_scales(c, S);
+  const int st = rr_state(c, S);
+  if (st != RUNNING) c->done = st;
+  // KP_HIST: the recurrence norm after each iteration
+  if (c->hist != nullptr && c->iter >= 0 && c->iter < KP_HIST_MAX) c->hist[c->iter] = S;
+}
+
+// The new state to the host mirror (one thread).
+__device__ inline void publish_mirror(Ctrl* __restrict__ c, CtrlMirror* __restrict__ mirror) {
+  const unsigned p = ((unsigned)c->pub + 1u) & MIRROR_PUB_MASK;
+  c->pub = (int)p;
+  const bool tol_hit = c->rr <= c->tol2;
+  const bool anchor_ok = c->repl > 0 && c->true_rr <= ANCHOR_REL * ANCHOR_REL * c->gamma0sq;
+  const unsigned long long w =
+      (unsigned long long)p | ((unsigned long long)(c->iter & 0xffffff) << 24) |
+      ((unsigned long long)(c->done & 0xf) << 48) | ((unsigned long long)tol_hit << 52) |
+      ((unsigned long long)anchor_ok << 53) | ((unsigned long long)(c->repl & 0x3ff) << 54);
+  volatile CtrlMirror* m = mirror;
+  m->rr = c->rr;
+  m->true_rr = c->true_rr;
+  m->gamma0sq = c->gamma0sq;
+  m->tol2 = c->tol2;
+  m->iter = c->iter;
+  m->word = w;
+}
+
+// beta of the direction step from r.z and z.Hp: Fletcher-Reeves rz / rho
+// (PCG, and the step after a true-residual replacement), Polak-Ribiere
+// -zw / delta (FPCG: equals -alpha (z.Hp) / rho), 0 for the first
+// direction.  Read-only; *ok is false for a breakdown.
+__device__ inline double beta_of(const Ctrl* c, double rz, double zw, bool* ok) {
+  *ok = (rz > 0.0) && isfinite(rz) && isfinite(zw);
+  if (!*ok) return 0.0;
+  if (c->first) return 0.0;
+  if (c->solver == KP_PCG || c->fr_next) return rz / c->rho;
+  return -zw / c->delta;
+}
+
 // FFT normal operator limits: L <= 2100 for n <= 2048, K <= 63
 constexpr int FFT_MAX_RADICES = 12;
 constexpr int FFT_MAX_L = 2100;
@@ -303,9 +400,16 @@ hipError_t launch_true_residual(const Plan& P, const float* b, const double* x64
 hipError_t launch_normal_fp64(const Plan& P, const float* x, double lam2, double* y,
                               hipStream_t s);
 
-hipError_t launch_update(const Plan& P, hipStream_t s);
+// x += alpha p, r -= alpha w with the partials of ||r||^2; with rr_step the
+// residual-norm scalar step follows as a launch of its own, else the
+// preconditioner's first GEMM folds it in (launch_precond's fold_rr)
+hipError_t launch_update(const Plan& P, bool rr_step, hipStream_t s);
 // alpha = rho / p.Hp from the normal blur's nbd partials, then the update
-hipError_t launch_update_alpha(const Plan& P, int nbd, hipStream_t s);
+hipError_t launch_update_alpha(const Plan& P, int nbd, bool rr_step, hipStream_t s);
+int update_partials(const Plan& P);     // partials of ||r||^2 an update writes
+// p = z + beta p with beta from the nbz partials of r.z and z.Hp of the
+// preconditioner's last GEMM (the direction step folded in; publishes)
+hipError_t launch_pupdate_fold(const Plan& P, const float* z, int nbz, hipStream_t s);
 hipError_t launch_convert_x(const Plan& P, float* x, bool to_f32, hipStream_t s);
 hipError_t launch_pupdate(const Plan& P, hipStream_t s);
 hipError_t launch_norm_scale(const Plan& P, const float* v, hipStream_t s);
@@ -315,7 +419,8 @@ hipError_t launch_norm_scale(const Plan& P, const float* v, hipStream_t s);
 enum ScalarKind : int {
   SC_ALPHA = 0,    // delta = p.Hp -> alpha, breakdown test
   SC_RR = 1,       // ||r||^2 -> convergence / replacement test, FP16 scale, CG beta
-  SC_BETA = 2,     // r.z, z.Hp -> beta (Fletcher-Reeves or Polak-Ribiere)
+  SC_BETA = 2,     // r.z, z.Hp -> beta (batched solves; pcg_solve folds it into
+                   // the direction update, launch_pupdate_fold)
   SC_RHS = 3,      // ||A^T b||^2 -> tolerances
   SC_TRUE = 4,     // true residual ||c - Hx||^2 -> converged / continue
   SC_TRUE_INFO = 5,// true residual for reporting only
@@ -325,10 +430,18 @@ hipError_t launch_scalar(const Plan& P, int kind, int nb, hipStream_t s);
 hipError_t launch_fill_f64(double* a, int count, double v, hipStream_t s);
 hipError_t launch_init_ctrl(const Plan& P, const Ctrl& host, hipStream_t s);
 
+// z = M^{-1} r.  finalize: the solver's tail (kernels skip a finished
+// solve; the last GEMM writes the partials of r.z and z.w, which
+// launch_pupdate_fold consumes: precond_partials of them).  fold_rr > 0:
+// the first GEMM folds in the residual-norm step of the update before it,
+// summing that update's fold_rr partials of ||r||^2 (and publishes).
 hipError_t launch_precond(const Plan& P, const float* r, float* z, const float* w,
-                          int prec, bool finalize, float lam2, hipStream_t s);
+                          int prec, bool finalize, float lam2, hipStream_t s,
+                          int fold_rr = 0);
 hipError_t launch_precond_fp8(const Plan& P, const float* r, float* z, const float* w,
-                              bool finalize, float lam2, hipStream_t s);
+                              bool finalize, float lam2, hipStream_t s, int fold_rr = 0);
+int precond_partials(const Plan& P, int prec);
+int precond_partials_fp8(const Plan& P);
 bool fp8_supported_size(int n);   // the FP8 chain needs n to be a multiple of 128
 
 // Non-blocking streams of the current device, created once per device and

@@ -36,13 +36,28 @@ template <typename T, bool B_FROM_F32, class Epi>
 __global__ __launch_bounds__(GT * GEMM_KS) void gemm_kernel(const T* __restrict__ A,
                                                             const void* __restrict__ Bsrc, int n,
                                                             Epi epi, Ctrl* ctrl, int skip_if_done,
-                                                            int scale_mode, double* partials) {
+                                                            int scale_mode, double* partials,
+                                                            int fold_rr,
+                                                            CtrlMirror* __restrict__ mirror) {
   extern __shared__ __align__(16) char gemm_lds[];
   if (skip_if_done && ctrl->done != RUNNING) return;
   // scale_mode bit 0: scale the FP32 B source by pscale; bit 1: scale the
   // output by zscale (both set on the device from ||r||)
-  const float bscale = (scale_mode & 1) ? ctrl->pscale : 1.0f;
+  float bscale = (scale_mode & 1) ? ctrl->pscale : 1.0f;
   const float oscale = (scale_mode & 2) ? ctrl->zscale : 1.0f;
+  if (fold_rr > 0) {
+    // the residual-norm step of the update before, folded in (the LDS
+    // scratch is free: the stage buffers are first written after it)
+    double* sh = reinterpret_cast<double*>(gemm_lds);
+    const double S = fold_slot<GT * GEMM_KS>(partials, SLOT_RR, fold_rr, sh);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+      apply_rr(ctrl, S);
+      if (mirror != nullptr) publish_mirror(ctrl, mirror);
+    }
+    if (rr_state(ctrl, S) != RUNNING) return;          // the same decision in every block
+    if (scale_mode & 1) bscale = ctrl->prec == KP_P16 ? fp16_residual_scale(S) : 1.0f;
+    __syncthreads();
+  }
   const int bid = blockIdx.y * gridDim.x + blockIdx.x;
   gemm_tile_splitk<T, B_FROM_F32, Epi, GEMM_KS>(A, Bsrc, n, blockIdx.y * BM, blockIdx.x * BN,
                                                 epi, bscale, oscale,
@@ -52,7 +67,7 @@ __global__ __launch_bounds__(GT * GEMM_KS) void gemm_kernel(const T* __restrict_
 
 template <typename T, bool BF, class Epi>
 static hipError_t run_gemm(const Plan& P, const T* A, const void* B, Epi epi, int skip,
-                           int scale_mode, hipStream_t s) {
+                           int scale_mode, hipStream_t s, int fold_rr = 0) {
   const int n = P.n;
   dim3 grid((n + BN - 1) / BN, (n + BM - 1) / BM);
   if ((long)grid.x * grid.y > MAX_PARTIALS) return hipErrorInvalidValue;
@@ -66,45 +81,49 @@ static hipError_t run_gemm(const Plan& P, const T* A, const void* B, Epi epi, in
     granted = true;
   }
   hipLaunchKernelGGL(kern, grid, dim3(GT * GEMM_KS), lds, s, A, B, n, epi, P.ctrl, skip,
-                     scale_mode, P.partials);
+                     scale_mode, P.partials, fold_rr, P.mirror_dev);
   return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t precond_chain(const Plan& P, const T* VcT, const T* Vc, const T* Vr,
                                 const T* VrT, const float* r, float* z, const float* w,
-                                bool finalize, float lam2, hipStream_t s) {
+                                bool finalize, float lam2, hipStream_t s, int fold_rr) {
   const int n = P.n;
   const int skip = finalize ? 1 : 0;
   T* t1 = reinterpret_cast<T*>(P.t1);
   T* t2 = reinterpret_cast<T*>(P.t2);
   T* t3 = reinterpret_cast<T*>(P.t3);
   hipError_t e;
-  e = run_gemm<T, true>(P, VcT, r, GEpiStore<T>{t1, n}, skip, 1, s);
+  e = run_gemm<T, true>(P, VcT, r, GEpiStore<T>{t1, n}, skip, 1, s, fold_rr);
   if (e != hipSuccess) return e;
   e = run_gemm<T, false>(P, t1, VrT, GEpiSPrimeT<T>{t2, P.sc2, P.sr2, lam2, n, nullptr, P.sprime_d0 ? P.d0t : nullptr}, skip, 0, s);
   if (e != hipSuccess) return e;
   e = run_gemm<T, false>(P, Vc, t2, GEpiStore<T>{t3, n}, skip, 0, s);
   if (e != hipSuccess) return e;
   if (!finalize) return run_gemm<T, false>(P, t3, Vr, GEpiFinal<false>{z, r, w, n}, skip, 2, s);
-  e = run_gemm<T, false>(P, t3, Vr, GEpiFinal<true>{z, r, w, n}, skip, 2, s);
-  if (e != hipSuccess) return e;
-  const int nb = ((n + BN - 1) / BN) * ((n + BM - 1) / BM);
-  return launch_scalar(P, SC_BETA, nb, s);
+  // the partials of r.z and z.w go to the direction step (launch_pupdate_fold)
+  return run_gemm<T, false>(P, t3, Vr, GEpiFinal<true>{z, r, w, n}, skip, 2, s);
+}
+
+int precond_partials(const Plan& P, int prec) {
+  if (prec == KP_P8) return precond_partials_fp8(P);
+  return ((P.n + BN - 1) / BN) * ((P.n + BM - 1) / BM);
 }
 
 hipError_t launch_precond(const Plan& P, const float* r, float* z, const float* w, int prec,
-                          bool finalize, float lam2, hipStream_t s) {
+                          bool finalize, float lam2, hipStream_t s, int fold_rr) {
+  if (fold_rr > MAX_PARTIALS) return hipErrorInvalidValue;
   if (prec == KP_P16)
     return precond_chain<_Float16>(P, reinterpret_cast<const _Float16*>(P.VcT16),
                                    reinterpret_cast<const _Float16*>(P.Vc16),
                                    reinterpret_cast<const _Float16*>(P.Vr16),
                                    reinterpret_cast<const _Float16*>(P.VrT16), r, z, w,
-                                   finalize, lam2, s);
+                                   finalize, lam2, s, fold_rr);
   if (prec == KP_P32)
     return precond_chain<float>(P, P.VcT32, P.Vc32, P.Vr32, P.VrT32, r, z, w, finalize, lam2,
-                                s);
-  return launch_precond_fp8(P, r, z, w, finalize, lam2, s);
+                                s, fold_rr);
+  return launch_precond_fp8(P, r, z, w, finalize, lam2, s, fold_rr);
 }
 
 // plain FP32 GEMM C = A * B (B from FP32 rows) then C2 = C * Bt^T, used for the

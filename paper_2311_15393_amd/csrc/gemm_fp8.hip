@@ -81,8 +81,20 @@ struct Gemm8Args {
 
 template <bool B_F32, int EPI>
 __global__ __launch_bounds__(G8T) void gemm8_kernel(Gemm8Args g, Ctrl* ctrl, int skip,
-                                                    double* partials) {
+                                                    double* partials, int fold_rr,
+                                                    CtrlMirror* __restrict__ mirror) {
   if (skip && ctrl->done != RUNNING) return;
+  if (fold_rr > 0) {
+    // the residual-norm step of the update before, folded in (the FP8 chain
+    // does not scale the residual, so only the state is needed here)
+    __shared__ double fsh[G8T / 64 + 1];
+    const double S = fold_slot<G8T>(partials, SLOT_RR, fold_rr, fsh);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+      apply_rr(ctrl, S);
+      if (mirror != nullptr) publish_mirror(ctrl, mirror);
+    }
+    if (rr_state(ctrl, S) != RUNNING) return;          // the same decision in every block
+  }
   const int n = g.n, nb32 = n / 32;
   __shared__ __align__(16) uint8_t sA[2][B8M][LD8];
   __shared__ __align__(16) uint8_t sB[2][B8N][LD8];
@@ -294,17 +306,20 @@ __global__ __launch_bounds__(G8T) void gemm8_kernel(Gemm8Args g, Ctrl* ctrl, int
 }
 
 template <bool BF, int EPI>
-static hipError_t run8(const Plan& P, const Gemm8Args& a, int skip, hipStream_t s) {
+static hipError_t run8(const Plan& P, const Gemm8Args& a, int skip, hipStream_t s,
+                       int fold_rr = 0) {
   dim3 grid(P.n / B8N, P.n / B8M);
   hipLaunchKernelGGL((gemm8_kernel<BF, EPI>), grid, dim3(G8T), 0, s, a, P.ctrl, skip,
-                     P.partials);
+                     P.partials, fold_rr, P.mirror_dev);
   return hipGetLastError();
 }
 
 bool fp8_supported_size(int n) { return n % B8K == 0; }
 
+int precond_partials_fp8(const Plan& P) { return (P.n / B8N) * (P.n / B8M); }
+
 hipError_t launch_precond_fp8(const Plan& P, const float* r, float* z, const float* w,
-                              bool finalize, float lam2, hipStream_t s) {
+                              bool finalize, float lam2, hipStream_t s, int fold_rr) {
   if (r == nullptr) return hipSuccess;                 // capability probe
   if (!fp8_supported_size(P.n)) return hipErrorNotSupported;
   const int n = P.n, skip = finalize ? 1 : 0;
@@ -319,7 +334,7 @@ hipError_t launch_precond_fp8(const Plan& P, const float* r, float* z, const flo
   a.lam2 = lam2;
   // 1. T1 = Vc^T R (R quantised per (column, 32 rows) while staged)
   a.A = P.VcT8; a.As = P.VcT8s; a.Bf32 = r; a.C = t1; a.Cs = P.t1s;
-  hipError_t e = run8<true, E8_ROWS>(P, a, skip, s);
+  hipError_t e = run8<true, E8_ROWS>(P, a, skip, s, fold_rr);
   if (e != hipSuccess) return e;
   // 2. T2^T = (S' .* (T1 Vr))^T
   a.A = t1; a.As = P.t1s; a.B = P.VrT8; a.Bs = P.VrT8s; a.C = t2; a.Cs = P.t2s;
@@ -332,9 +347,8 @@ hipError_t launch_precond_fp8(const Plan& P, const float* r, float* z, const flo
   // 4. z = T3 Vr^T / lambda^2
   a.A = t3; a.As = P.t3s; a.B = P.Vr8; a.Bs = P.Vr8s; a.z = z; a.r = r; a.w = w;
   if (!finalize) return run8<false, E8_FINAL_NR>(P, a, skip, s);
-  e = run8<false, E8_FINAL>(P, a, skip, s);
-  if (e != hipSuccess) return e;
-  return launch_scalar(P, SC_BETA, (n / B8N) * (n / B8M), s);
+  // the partials of r.z and z.w go to the direction step (launch_pupdate_fold)
+  return run8<false, E8_FINAL>(P, a, skip, s);
 }
 
 }  // namespace kpcg

@@ -85,6 +85,46 @@ __global__ __launch_bounds__(VT) void pupdate_kernel(float* __restrict__ p,
     for (int i = 4 * n4 + threadIdx.x; i < N; i += VT) p[i] = fmaf(b, p[i], z[i]);
 }
 
+// The direction step folded into p = z + beta p: every block sums the nbz
+// partials of r.z and z.Hp of the preconditioner's last GEMM (in the scalar
+// step's order) and takes beta from them; block 0 stores r.z, z.Hp, beta
+// (or the breakdown) and publishes.  The fields beta_of reads (first,
+// fr_next, rho, delta) are written only by the step length that follows.
+__global__ __launch_bounds__(VT) void pupdate_fold_kernel(float* __restrict__ p,
+                                                          const float* __restrict__ z, int N,
+                                                          Ctrl* ctrl,
+                                                          const double* __restrict__ partials,
+                                                          int nbz,
+                                                          CtrlMirror* __restrict__ mirror) {
+  if (ctrl->done != RUNNING) return;
+  __shared__ double sh[VT / 64 + 1];
+  const double rz = fold_slot<VT>(partials, SLOT_RZ, nbz, sh);
+  const double zw = fold_slot<VT>(partials, SLOT_ZW, nbz, sh);
+  bool ok;
+  const double beta = beta_of(ctrl, rz, zw, &ok);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->rz = rz;
+    ctrl->zw = zw;
+    if (ok) ctrl->beta = beta;
+    else ctrl->done = BREAKDOWN;
+    if (mirror != nullptr) publish_mirror(ctrl, mirror);
+  }
+  if (!ok) return;
+  const float b = (float)beta;
+  const int n4 = N >> 2;
+  float4* p4 = reinterpret_cast<float4*>(p);
+  const float4* z4 = reinterpret_cast<const float4*>(z);
+  for (int i = blockIdx.x * VT + threadIdx.x; i < n4; i += gridDim.x * VT) {
+    float4 pv = p4[i];
+    const float4 zv = z4[i];
+    pv.x = fmaf(b, pv.x, zv.x); pv.y = fmaf(b, pv.y, zv.y);
+    pv.z = fmaf(b, pv.z, zv.z); pv.w = fmaf(b, pv.w, zv.w);
+    p4[i] = pv;
+  }
+  if (blockIdx.x == 0)
+    for (int i = 4 * n4 + threadIdx.x; i < N; i += VT) p[i] = fmaf(b, p[i], z[i]);
+}
+
 // ||v||^2 -> rr and the preconditioner scales (standalone preconditioner use)
 __global__ __launch_bounds__(VT) void norm_scale_kernel(const float* __restrict__ v, int N,
                                                         Ctrl* ctrl, double* partials) {
@@ -96,13 +136,13 @@ __global__ __launch_bounds__(VT) void norm_scale_kernel(const float* __restrict_
   write_partials<1>(v1, partials, SLOT_NORM, blockIdx.x);
 }
 
-hipError_t launch_update(const Plan& P, hipStream_t s) {
+hipError_t launch_update(const Plan& P, bool rr_step, hipStream_t s) {
   const int N = P.n * P.n;
   const int nb = vec_blocks(N >> 2);
   hipLaunchKernelGGL(update_kernel, dim3(nb), dim3(VT), 0, s, P.x64, P.r, P.p, P.w, N, P.ctrl,
                      P.partials);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !rr_step) return e;
   return launch_scalar(P, SC_RR, nb, s);
 }
 
@@ -153,6 +193,14 @@ hipError_t launch_pupdate_from(const Plan& P, const float* z, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_pupdate_fold(const Plan& P, const float* z, int nbz, hipStream_t s) {
+  if (nbz > MAX_PARTIALS) return hipErrorInvalidValue;
+  const int N = P.n * P.n;
+  hipLaunchKernelGGL(pupdate_fold_kernel, dim3(vec_blocks(N >> 2)), dim3(VT), 0, s, P.p, z, N,
+                     P.ctrl, P.partials, nbz, P.mirror_dev);
+  return hipGetLastError();
+}
+
 hipError_t launch_pupdate(const Plan& P, hipStream_t s) {
   return launch_pupdate_from(P, P.z, s);
 }
@@ -178,8 +226,6 @@ __device__ inline double sum_slot(const double* partials, int slot, int nb, doub
   return block_sum<ST>(s, sh);
 }
 
-__device__ inline void publish_mirror(Ctrl* __restrict__ c, CtrlMirror* __restrict__ mirror);
-
 // Every step that the host follows (the residual norm after an update, the
 // direction step, the right-hand side, true residuals, and a breakdown found
 // by the step length) publishes the new state to the host mirror.
@@ -189,53 +235,26 @@ __global__ __launch_bounds__(ST) void scalar_kernel(Ctrl* __restrict__ c,
                                                     CtrlMirror* __restrict__ mirror) {
   __shared__ double sh[ST / 64];
   const int done = c->done;
-  if ((kind == SC_ALPHA || kind == SC_RR || kind == SC_BETA) && done != RUNNING) return;
+  if ((kind == SC_ALPHA || kind == SC_RR) && done != RUNNING) return;
   const int slot = kind == SC_ALPHA ? SLOT_DELTA
                  : kind == SC_RR ? SLOT_RR
-                 : kind == SC_BETA ? SLOT_RZ
                  : kind == SC_RHS ? SLOT_RHS
                  : kind == SC_NORM ? SLOT_NORM : SLOT_TRUE;
   const double S = sum_slot(partials, slot, nb, sh);
-  const double S2 = kind == SC_BETA ? sum_slot(partials, SLOT_ZW, nb, sh) : 0.0;
   if (threadIdx.x != 0) return;
   switch (kind) {
     case SC_ALPHA:                          // delta = p . Hp
       c->delta = S;
-      if (!(S > 0.0) || !isfinite(S)) c->done = BREAKDOWN;
-      else c->alpha = c->rho / S;
-      break;
-    case SC_RR:                             // after x += alpha p, r -= alpha w
-      c->rr = S;
-      c->iter += 1;
-      if (c->solver == KP_CG) {
-        c->rho_prev = c->rho;
-        c->beta = S / c->rho;
-        c->rho = S;
-      }
-      set_scales(c, S);
-      if (!isfinite(S)) c->done = BREAKDOWN;
-      else if (S <= c->tol2 || S <= c->repl2) c->done = PENDING;
-      break;
-    case SC_BETA: {                         // r.z and z.Hp after z = M^{-1} r
-      const double rz = S, zw = S2;
-      c->rz = rz;
-      c->zw = zw;
-      if (!(rz > 0.0) || !isfinite(rz) || !isfinite(zw)) {
+      if (!(S > 0.0) || !isfinite(S)) {
         c->done = BREAKDOWN;
       } else {
-        if (c->first) {
-          c->beta = 0.0;
-          c->first = 0;
-        } else if (c->solver == KP_PCG || c->fr_next) {
-          c->beta = rz / c->rho;            // Fletcher-Reeves
-        } else {
-          c->beta = -zw / c->delta;         // Polak-Ribiere = -alpha (z.Hp) / rho
-        }
-        c->rho = rz;
-        c->fr_next = 0;
+        c->alpha = step_rho(c) / S;
+        commit_direction(c);
       }
       break;
-    }
+    case SC_RR:                             // after x += alpha p, r -= alpha w
+      apply_rr(c, S);                       // (records the history itself)
+      break;
     case SC_RHS:                            // c = A^T b
       c->gamma0sq = S;
       c->rr = S;
@@ -271,36 +290,18 @@ __global__ __launch_bounds__(ST) void scalar_kernel(Ctrl* __restrict__ c,
       set_scales(c, S);
       break;
   }
-  // KP_HIST: the recurrence norm after each iteration (and r_0 = c), and
-  // every true residual at the iteration it was formed
+  // KP_HIST: r_0 = c (the recurrence norms after each iteration are
+  // recorded by apply_rr), and every true residual at the iteration it was
+  // formed
   double* hist = c->hist;
   const int it = c->iter;
   if (hist != nullptr && it >= 0 && it < KP_HIST_MAX) {
-    if (kind == SC_RR || kind == SC_RHS) hist[it] = S;
+    if (kind == SC_RHS) hist[it] = S;
     else if (kind == SC_TRUE || kind == SC_TRUE_INFO) hist[KP_HIST_MAX + it] = S;
   }
-  const bool publish = kind == SC_RR || kind == SC_BETA || kind == SC_RHS || kind == SC_TRUE ||
+  const bool publish = kind == SC_RR || kind == SC_RHS || kind == SC_TRUE ||
                        kind == SC_TRUE_INFO || (kind == SC_ALPHA && c->done != RUNNING);
   if (mirror != nullptr && publish) publish_mirror(c, mirror);
-}
-
-// The new state to the host mirror (one thread).
-__device__ inline void publish_mirror(Ctrl* __restrict__ c, CtrlMirror* __restrict__ mirror) {
-  const unsigned p = ((unsigned)c->pub + 1u) & MIRROR_PUB_MASK;
-  c->pub = (int)p;
-  const bool tol_hit = c->rr <= c->tol2;
-  const bool anchor_ok = c->repl > 0 && c->true_rr <= ANCHOR_REL * ANCHOR_REL * c->gamma0sq;
-  const unsigned long long w =
-      (unsigned long long)p | ((unsigned long long)(c->iter & 0xffffff) << 24) |
-      ((unsigned long long)(c->done & 0xf) << 48) | ((unsigned long long)tol_hit << 52) |
-      ((unsigned long long)anchor_ok << 53) | ((unsigned long long)(c->repl & 0x3ff) << 54);
-  volatile CtrlMirror* m = mirror;
-  m->rr = c->rr;
-  m->true_rr = c->true_rr;
-  m->gamma0sq = c->gamma0sq;
-  m->tol2 = c->tol2;
-  m->iter = c->iter;
-  m->word = w;
 }
 
 __global__ __launch_bounds__(VT) void fill_f64_kernel(double* __restrict__ a, int count,
@@ -342,10 +343,11 @@ __global__ __launch_bounds__(VT) void update_alpha_kernel(double* __restrict__ x
     }
     return;
   }
-  const double ad = ctrl->rho / S;
+  const double ad = step_rho(ctrl) / S;
   if (lead) {
     ctrl->delta = S;
     ctrl->alpha = ad;
+    commit_direction(ctrl);                 // no block here reads rho, first, fr_next
   }
   update_body(x, r, p, w, N, ad, partials);
 }
@@ -355,18 +357,20 @@ __global__ __launch_bounds__(VT) void update_alpha_kernel(double* __restrict__ x
 // to sum them
 constexpr int FUSED_ALPHA_MAX = 1024;
 
-hipError_t launch_update_alpha(const Plan& P, int nbd, hipStream_t s) {
+int update_partials(const Plan& P) { return vec_blocks((P.n * P.n) >> 2); }
+
+hipError_t launch_update_alpha(const Plan& P, int nbd, bool rr_step, hipStream_t s) {
   if (nbd > FUSED_ALPHA_MAX) {
     hipError_t e = launch_scalar(P, SC_ALPHA, nbd, s);
     if (e != hipSuccess) return e;
-    return launch_update(P, s);
+    return launch_update(P, rr_step, s);
   }
   const int N = P.n * P.n;
   const int nb = vec_blocks(N >> 2);
   hipLaunchKernelGGL(update_alpha_kernel, dim3(nb), dim3(VT), 0, s, P.x64, P.r, P.p, P.w, N,
                      P.ctrl, P.partials, nbd, P.mirror_dev);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !rr_step) return e;
   return launch_scalar(P, SC_RR, nb, s);
 }
 
