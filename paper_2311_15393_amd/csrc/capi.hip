@@ -516,6 +516,7 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   };
 
   int state = RUNNING;
+  bool x_out = false;            // x holds the FP32 copy of the last true residual's x
   HIPCHK(top_up());
   if ((rc = next()) != KP_OK) return rc;
   for (;;) {
@@ -528,6 +529,11 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
       ++replacements;
       enq = seen;
       bump();
+      // a true residual that may end the solve: x in FP32 at once, so that
+      // a converged solve needs no further launch (a solve that goes on
+      // overwrites x later)
+      x_out = m.tol_hit || its >= maxit;
+      if (x_out) HIPCHK(launch_convert_x(P, x, true, s));
       if (m.tol_hit || its >= maxit) {
         // may have converged (or no budget left): see the outcome first
         if ((rc = next()) != KP_OK) return rc;
@@ -553,7 +559,7 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   // an unconverged solve reports its true residual; then x in FP32 (x_0 = 0
   // stays 0 for zero or non-finite data)
   if (state != CONVERGED) HIPCHK(true_residual(false));
-  HIPCHK(launch_convert_x(P, x, true, s));
+  if (state != CONVERGED || !x_out) HIPCHK(launch_convert_x(P, x, true, s));
   HIPCHK(hipEventRecord(P.ev_end, s));
   HIPCHK(hipStreamSynchronize(s));
   const volatile CtrlMirror* fm = P.mirror;       // complete: the stream has drained

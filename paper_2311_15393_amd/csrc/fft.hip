@@ -136,7 +136,8 @@ __constant__ float kS7[4][4] = {
     {0, 0.97492791218182361f, -0.43388373911755812f, -0.78183148246802981f},
     {0, 0.43388373911755812f, -0.78183148246802981f, 0.97492791218182361f}};
 
-// One radix-R Stockham stage over the whole line: in -> out.
+// One radix-R Stockham stage over the whole line: in -> out (tw: the
+// twiddle table in LDS).
 template <int R>
 __device__ inline void fft_stage(const float2* __restrict__ in, float2* __restrict__ out,
                                  const float2* __restrict__ tw, int L, int Ns) {
@@ -163,19 +164,20 @@ __device__ inline void fft_stage(const float2* __restrict__ in, float2* __restri
   }
 }
 
-// Forward DFT of the line in a (length g.L), b as the second buffer.
-// Returns the buffer holding the result.  Ends with a barrier.
-__device__ inline float2* fft_line(float2* a, float2* b, const FftGeom& g) {
+// Forward DFT of the line in a (length g.L), b as the second buffer, with
+// the twiddle table tw in LDS.  Returns the buffer holding the result.
+// Ends with a barrier.
+__device__ inline float2* fft_line(float2* a, float2* b, const float2* tw, const FftGeom& g) {
   int Ns = 1;
   for (int s = 0; s < g.nrad; ++s) {
     const int R = g.rad[s];
     switch (R) {
-      case 8: fft_stage<8>(a, b, g.tw, g.L, Ns); break;
-      case 4: fft_stage<4>(a, b, g.tw, g.L, Ns); break;
-      case 2: fft_stage<2>(a, b, g.tw, g.L, Ns); break;
-      case 3: fft_stage<3>(a, b, g.tw, g.L, Ns); break;
-      case 5: fft_stage<5>(a, b, g.tw, g.L, Ns); break;
-      default: fft_stage<7>(a, b, g.tw, g.L, Ns); break;
+      case 8: fft_stage<8>(a, b, tw, g.L, Ns); break;
+      case 4: fft_stage<4>(a, b, tw, g.L, Ns); break;
+      case 2: fft_stage<2>(a, b, tw, g.L, Ns); break;
+      case 3: fft_stage<3>(a, b, tw, g.L, Ns); break;
+      case 5: fft_stage<5>(a, b, tw, g.L, Ns); break;
+      default: fft_stage<7>(a, b, tw, g.L, Ns); break;
     }
     __syncthreads();
     float2* t = a; a = b; b = t;
@@ -197,22 +199,30 @@ __device__ inline void split_store(const float2* Z, int L, int F, float2* Sa, fl
   }
 }
 
-// conj of the full spectrum of x_a + i x_b from the half spectra Ta, Tb
-// (Hermitian extension), ready for IDFT(Z) = conj(DFT(conj Z)).
-__device__ inline void pack_conj(const float2* __restrict__ Ta, const float2* __restrict__ Tb,
-                                 int L, int F, float2* out) {
-  for (int k = threadIdx.x; k < L; k += FT) {
-    float2 z;
-    if (k < F) {
-      const float2 a = Ta[k], b = Tb ? Tb[k] : make_float2(0.f, 0.f);
-      z = make_float2(a.x - b.y, a.y + b.x);                 // a + i b
-    } else {
-      const float2 a = Ta[L - k], b = Tb ? Tb[L - k] : make_float2(0.f, 0.f);
-      z = make_float2(a.x + b.y, b.x - a.y);                 // conj a + i conj b
+// Every kernel issues all of its global loads (its line, the twiddle table,
+// and the PSF spectrum column or the p rows it needs at the end) before it
+// waits for any of them, then works in LDS: a line of L <= FFT_MAX_L points
+// is FE elements per thread.
+constexpr int FE = (FFT_MAX_L + FT - 1) / FT;
+
+// the twiddle table into registers (issued), then into LDS (tw_lds)
+struct TwStage {
+  float2 v[FE];
+  __device__ void load(const float2* __restrict__ tw, int L) {
+#pragma unroll
+    for (int e = 0; e < FE; ++e) {
+      const int t = threadIdx.x + e * FT;
+      if (t < L) v[e] = tw[t];
     }
-    out[k] = cconj(z);
   }
-}
+  __device__ void store(float2* tw_lds, int L) const {
+#pragma unroll
+    for (int e = 0; e < FE; ++e) {
+      const int t = threadIdx.x + e * FT;
+      if (t < L) tw_lds[t] = v[e];
+    }
+  }
+};
 
 __global__ __launch_bounds__(FT) void fft_rows_fwd_kernel(const float* __restrict__ p, FftGeom g,
                                                           float2* __restrict__ S,
@@ -221,18 +231,29 @@ __global__ __launch_bounds__(FT) void fft_rows_fwd_kernel(const float* __restric
   extern __shared__ float2 fft_lds[];
   float2* a = fft_lds;
   float2* b = fft_lds + g.L;
-  const int n = g.n, ra = 2 * blockIdx.x, rb = ra + 1;
-  for (int j = threadIdx.x; j < g.L; j += FT) {
-    float2 v = make_float2(0.f, 0.f);
+  float2* tw = fft_lds + 2 * g.L;
+  const int n = g.n, L = g.L, ra = 2 * blockIdx.x, rb = ra + 1;
+  TwStage ts;
+  ts.load(g.tw, L);
+  float2 v[FE];
+#pragma unroll
+  for (int e = 0; e < FE; ++e) {
+    const int j = threadIdx.x + e * FT;
+    v[e] = make_float2(0.f, 0.f);
     if (j < n) {
-      v.x = p[(size_t)ra * n + j];
-      if (rb < n) v.y = p[(size_t)rb * n + j];
+      v[e].x = p[(size_t)ra * n + j];
+      if (rb < n) v[e].y = p[(size_t)rb * n + j];
     }
-    a[j] = v;
+  }
+  ts.store(tw, L);
+#pragma unroll
+  for (int e = 0; e < FE; ++e) {
+    const int j = threadIdx.x + e * FT;
+    if (j < L) a[j] = v[e];
   }
   __syncthreads();
-  const float2* Z = fft_line(a, b, g);
-  split_store(Z, g.L, g.F, S + (size_t)ra * g.F, rb < n ? S + (size_t)rb * g.F : nullptr);
+  const float2* Z = fft_line(a, b, tw, g);
+  split_store(Z, L, g.F, S + (size_t)ra * g.F, rb < n ? S + (size_t)rb * g.F : nullptr);
 }
 
 // Columns: consecutive workgroups go to different XCDs (round robin), so the
@@ -251,23 +272,76 @@ __global__ __launch_bounds__(FT) void fft_cols_kernel(const float2* __restrict__
   const int k = xcd_column(blockIdx.x, g.F);
   if (k >= g.F) return;
   extern __shared__ float2 fft_lds[];
-  float2* a = fft_lds;
-  float2* b = fft_lds + g.L;
   const int n = g.n, L = g.L, F = g.F;
-  for (int i = threadIdx.x; i < L; i += FT)
-    a[i] = i < n ? S[(size_t)i * F + k] : make_float2(0.f, 0.f);
-  __syncthreads();
-  float2* Y = fft_line(a, b, g);
-  float2* other = Y == a ? b : a;
+  float2* a = fft_lds;
+  float2* b = fft_lds + L;
+  float2* tw = fft_lds + 2 * L;
+  TwStage ts;
+  ts.load(g.tw, L);
+  // the column (rows n .. L-1 are the zero pad) and the PSF spectrum column
   const float2* h = Ht + (size_t)k * L;
-  for (int m = threadIdx.x; m < L; m += FT) {
-    float2 hv = h[m];
-    if (conjH) hv.y = -hv.y;
-    Y[m] = cconj(cmul(Y[m], hv));
+  float2 v[FE], hv[FE];
+#pragma unroll
+  for (int e = 0; e < FE; ++e) {
+    const int i = threadIdx.x + e * FT;
+    v[e] = make_float2(0.f, 0.f);
+    if (i < n) v[e] = S[(size_t)i * F + k];
+    if (i < L) hv[e] = h[i];
+  }
+  ts.store(tw, L);
+#pragma unroll
+  for (int e = 0; e < FE; ++e) {
+    const int i = threadIdx.x + e * FT;
+    if (i < L) a[i] = v[e];
   }
   __syncthreads();
-  const float2* y = fft_line(Y, other, g);
+  float2* Y = fft_line(a, b, tw, g);
+  float2* other = Y == a ? b : a;
+  // the spectrum times Hc (or conj Hc), conjugated for the inverse transform;
+  // element m of Y belongs to the thread that loaded hv for m
+#pragma unroll
+  for (int e = 0; e < FE; ++e) {
+    const int m = threadIdx.x + e * FT;
+    if (m < L) {
+      float2 hm = hv[e];
+      if (conjH) hm.y = -hm.y;
+      Y[m] = cconj(cmul(Y[m], hm));
+    }
+  }
+  __syncthreads();
+  const float2* y = fft_line(Y, other, tw, g);
   for (int i = threadIdx.x; i < n; i += FT) T[(size_t)i * F + k] = cconj(y[i]);
+}
+
+// conj of the full spectrum of x_a + i x_b from the half spectra held in
+// registers (ta, tb: element j of thread t is k = t + j FT, k < F) into out
+// (Hermitian extension), ready for IDFT(Z) = conj(DFT(conj Z)): out[k] for
+// k < F and out[L - k] for 0 < k < L - F + 1... written by the owner of k.
+__device__ inline void pack_conj_regs(const float2 (&ta)[FE], const float2 (&tb)[FE], bool has_b,
+                                      int L, int F, float2* out) {
+#pragma unroll
+  for (int e = 0; e < FE; ++e) {
+    const int k = threadIdx.x + e * FT;
+    if (k < F) {
+      const float2 a = ta[e], bb = has_b ? tb[e] : make_float2(0.f, 0.f);
+      // Z_k = a + i b; conj(Z_k)
+      out[k] = cconj(make_float2(a.x - bb.y, a.y + bb.x));
+      // Z_{L-k} = conj a + i conj b (for 0 < k, L - k >= F)
+      if (k > 0 && L - k >= F) out[L - k] = cconj(make_float2(a.x + bb.y, bb.x - a.y));
+    }
+  }
+}
+
+__device__ inline void load_half_rows(const float2* __restrict__ T, int ra, int rb, int n, int F,
+                                      float2 (&ta)[FE], float2 (&tb)[FE]) {
+#pragma unroll
+  for (int e = 0; e < FE; ++e) {
+    const int k = threadIdx.x + e * FT;
+    if (k < F) {
+      ta[e] = T[(size_t)ra * F + k];
+      tb[e] = rb < n ? T[(size_t)rb * F + k] : make_float2(0.f, 0.f);
+    }
+  }
 }
 
 __global__ __launch_bounds__(FT) void fft_rows_mid_kernel(const float2* __restrict__ T,
@@ -275,12 +349,18 @@ __global__ __launch_bounds__(FT) void fft_rows_mid_kernel(const float2* __restri
                                                           const Ctrl* ctrl) {
   if (fft_skip(ctrl)) return;
   extern __shared__ float2 fft_lds[];
-  float2* a = fft_lds;
-  float2* b = fft_lds + g.L;
   const int n = g.n, L = g.L, F = g.F, ra = 2 * blockIdx.x, rb = ra + 1;
-  pack_conj(T + (size_t)ra * F, rb < n ? T + (size_t)rb * F : nullptr, L, F, a);
+  float2* a = fft_lds;
+  float2* b = fft_lds + L;
+  float2* tw = fft_lds + 2 * L;
+  TwStage ts;
+  ts.load(g.tw, L);
+  float2 ta[FE], tb[FE];
+  load_half_rows(T, ra, rb, n, F, ta, tb);
+  ts.store(tw, L);
+  pack_conj_regs(ta, tb, rb < n, L, F, a);
   __syncthreads();
-  float2* z = fft_line(a, b, g);
+  float2* z = fft_line(a, b, tw, g);
   // conj(z) = A p rows ra (real) and rb (imaginary); keep j < n, re-pad
   for (int j = threadIdx.x; j < L; j += FT) {
     float2 v = make_float2(0.f, 0.f);
@@ -292,7 +372,7 @@ __global__ __launch_bounds__(FT) void fft_rows_mid_kernel(const float2* __restri
   }
   __syncthreads();
   float2* other = z == a ? b : a;
-  const float2* Z = fft_line(z, other, g);
+  const float2* Z = fft_line(z, other, tw, g);
   split_store(Z, L, F, S + (size_t)ra * F, rb < n ? S + (size_t)rb * F : nullptr);
 }
 
@@ -304,26 +384,43 @@ __global__ __launch_bounds__(FT) void fft_rows_out_kernel(const float2* __restri
   if (fft_skip(ctrl)) return;
   extern __shared__ float2 fft_lds[];
   __shared__ double sh[FT / 64];
-  float2* a = fft_lds;
-  float2* b = fft_lds + g.L;
   const int n = g.n, L = g.L, F = g.F, ra = 2 * blockIdx.x, rb = ra + 1;
-  pack_conj(T + (size_t)ra * F, rb < n ? T + (size_t)rb * F : nullptr, L, F, a);
+  float2* a = fft_lds;
+  float2* b = fft_lds + L;
+  float2* tw = fft_lds + 2 * L;
+  TwStage ts;
+  ts.load(g.tw, L);
+  float2 ta[FE], tb[FE];
+  load_half_rows(T, ra, rb, n, F, ta, tb);
+  // the two rows of p for lambda^2 p and p . w
+  float pa[FE], pb[FE];
+#pragma unroll
+  for (int e = 0; e < FE; ++e) {
+    const int j = threadIdx.x + e * FT;
+    if (j < n) {
+      pa[e] = p[(size_t)ra * n + j];
+      pb[e] = rb < n ? p[(size_t)rb * n + j] : 0.f;
+    }
+  }
+  ts.store(tw, L);
+  pack_conj_regs(ta, tb, rb < n, L, F, a);
   __syncthreads();
-  const float2* z = fft_line(a, b, g);
+  const float2* z = fft_line(a, b, tw, g);
   double d = 0.0;
-  for (int j = threadIdx.x; j < n; j += FT) {
-    const float2 v = cconj(z[j]);
-    const size_t oa = (size_t)ra * n + j;
-    const float pa = p[oa];
-    const float wa = fmaf(lam2, pa, v.x);
-    w[oa] = wa;
-    d += (double)pa * (double)wa;
-    if (rb < n) {
-      const size_t ob = oa + n;
-      const float pb = p[ob];
-      const float wb = fmaf(lam2, pb, v.y);
-      w[ob] = wb;
-      d += (double)pb * (double)wb;
+#pragma unroll
+  for (int e = 0; e < FE; ++e) {
+    const int j = threadIdx.x + e * FT;
+    if (j < n) {
+      const float2 v = cconj(z[j]);
+      const size_t oa = (size_t)ra * n + j;
+      const float wa = fmaf(lam2, pa[e], v.x);
+      w[oa] = wa;
+      d += (double)pa[e] * (double)wa;
+      if (rb < n) {
+        const float wb = fmaf(lam2, pb[e], v.y);
+        w[oa + n] = wb;
+        d += (double)pb[e] * (double)wb;
+      }
     }
   }
   const double tot = block_sum<FT>(d, sh);
@@ -426,12 +523,12 @@ hipError_t build_fft_tables(const Plan& P, const double* psf_dev, void* g_scratc
   return hipGetLastError();
 }
 
-size_t fft_lds_bytes(int L) { return (size_t)2 * L * sizeof(float2); }
+size_t fft_lds_bytes(int L) { return (size_t)3 * L * sizeof(float2); }   // a, b, twiddles
 
 hipError_t launch_fft_normal(const Plan& P, const float* p, float* w, float lam2, hipStream_t s,
                              int* nb, const Ctrl* ctrl) {
   const FftGeom g = geom(P);
-  const size_t lds = fft_lds_bytes(g.L);        // <= 2 * FFT_MAX_L * 8 B = 33.6 KB
+  const size_t lds = fft_lds_bytes(g.L);        // <= 3 * FFT_MAX_L * 8 B = 50.4 KB
   float2* S = reinterpret_cast<float2*>(P.fft_S);
   float2* T = reinterpret_cast<float2*>(P.fft_T);
   const float2* Ht = reinterpret_cast<const float2*>(P.fft_Ht);

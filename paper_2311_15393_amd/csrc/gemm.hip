@@ -32,6 +32,31 @@ namespace kpcg {
 // workgroups, one per CU, so the k-loop's global latency is otherwise exposed
 constexpr int GEMM_KS = 4;
 
+// The residual-norm step of the update before the preconditioner, folded
+// into its first GEMM while the first operand loads are in flight: every
+// workgroup sums the update's partials of ||r||^2 (LDS scratch at the start
+// of the stage buffers, free until the first stage is staged), block 0
+// records the step and publishes, and the FP16 residual scale follows from
+// the sum.
+struct RrFold {
+  Ctrl* ctrl;
+  const double* partials;
+  int nb;
+  CtrlMirror* mirror;
+  bool scale;
+  __device__ bool operator()(float& bscale, char* lds) const {
+    double* sh = reinterpret_cast<double*>(lds);
+    const double S = fold_slot<GT * GEMM_KS>(partials, SLOT_RR, nb, sh);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+      apply_rr(ctrl, S);
+      if (mirror != nullptr) publish_mirror(ctrl, mirror);
+    }
+    if (rr_state(ctrl, S) != RUNNING) return false;    // the same decision in every block
+    if (scale) bscale = ctrl->prec == KP_P16 ? fp16_residual_scale(S) : 1.0f;
+    return true;
+  }
+};
+
 template <typename T, bool B_FROM_F32, class Epi>
 __global__ __launch_bounds__(GT * GEMM_KS) void gemm_kernel(const T* __restrict__ A,
                                                             const void* __restrict__ Bsrc, int n,
@@ -43,22 +68,16 @@ __global__ __launch_bounds__(GT * GEMM_KS) void gemm_kernel(const T* __restrict_
   if (skip_if_done && ctrl->done != RUNNING) return;
   // scale_mode bit 0: scale the FP32 B source by pscale; bit 1: scale the
   // output by zscale (both set on the device from ||r||)
-  float bscale = (scale_mode & 1) ? ctrl->pscale : 1.0f;
+  const float bscale = (scale_mode & 1) ? ctrl->pscale : 1.0f;
   const float oscale = (scale_mode & 2) ? ctrl->zscale : 1.0f;
-  if (fold_rr > 0) {
-    // the residual-norm step of the update before, folded in (the LDS
-    // scratch is free: the stage buffers are first written after it)
-    double* sh = reinterpret_cast<double*>(gemm_lds);
-    const double S = fold_slot<GT * GEMM_KS>(partials, SLOT_RR, fold_rr, sh);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-      apply_rr(ctrl, S);
-      if (mirror != nullptr) publish_mirror(ctrl, mirror);
-    }
-    if (rr_state(ctrl, S) != RUNNING) return;          // the same decision in every block
-    if (scale_mode & 1) bscale = ctrl->prec == KP_P16 ? fp16_residual_scale(S) : 1.0f;
-    __syncthreads();
-  }
   const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  if (fold_rr > 0) {
+    RrFold f{ctrl, partials, fold_rr, mirror, (scale_mode & 1) != 0};
+    gemm_tile_splitk<T, B_FROM_F32, Epi, GEMM_KS, RrFold>(
+        A, Bsrc, n, blockIdx.y * BM, blockIdx.x * BN, epi, bscale, oscale,
+        partials + SLOT_RZ * MAX_PARTIALS + bid, MAX_PARTIALS, gemm_lds, f);
+    return;
+  }
   gemm_tile_splitk<T, B_FROM_F32, Epi, GEMM_KS>(A, Bsrc, n, blockIdx.y * BM, blockIdx.x * BN,
                                                 epi, bscale, oscale,
                                                 partials + SLOT_RZ * MAX_PARTIALS + bid,

@@ -337,11 +337,20 @@ constexpr size_t gemm_splitk_lds(int ks) {
 }
 constexpr int RED_LD = BN + 1;           // row pitch of the reduction tiles (floats)
 
-template <typename T, bool B_FROM_F32, class Epi, int KS, bool VK>
+// A fold runs once the first stage's operand loads are in flight and before
+// they are staged: it may change the B scale, and returns false when the
+// workgroup has nothing to do (the same answer in every thread).  It may use
+// the start of the LDS buffer; it ends with a barrier.
+struct NoFold {
+  __device__ bool operator()(float&, char*) const { return true; }
+};
+
+template <typename T, bool B_FROM_F32, class Epi, int KS, bool VK, class Fold = NoFold>
 __device__ inline void gemm_tile_splitk_vk(const T* __restrict__ A,
                                            const void* __restrict__ Bsrc, int n, int m0, int n0,
                                            Epi epi, float bscale, float oscale,
-                                           double* partial_out, int slot_stride, char* lds) {
+                                           double* partial_out, int slot_stride, char* lds,
+                                           Fold fold = Fold{}) {
   constexpr int BK = MT<T>::BK;
   static_assert((size_t)KS * BM * RED_LD * sizeof(float) + GT * KS / 64 * sizeof(double) <=
                     gemm_splitk_lds<T>(KS),
@@ -381,10 +390,9 @@ __device__ inline void gemm_tile_splitk_vk(const T* __restrict__ A,
   const int kb = kg * nk / KS, ke = (kg + 1) * nk / KS;
   const int cnt = ke - kb;
   const int steps = (nk + KS - 1) / KS;              // the same barrier count in every group
-  if (cnt > 0) {
-    load(kb * BK);
-    store(0);
-  }
+  if (cnt > 0) load(kb * BK);
+  if (!fold(bscale, lds)) return;
+  if (cnt > 0) store(0);
   __syncthreads();
   for (int st = 0; st < steps; ++st) {
     const int cur = st & 1;
@@ -456,17 +464,19 @@ __device__ inline void gemm_tile(const T* __restrict__ A, const void* __restrict
                                             partial_out, slot_stride, sA, sB);
 }
 
-template <typename T, bool B_FROM_F32, class Epi, int KS>
+template <typename T, bool B_FROM_F32, class Epi, int KS, class Fold = NoFold>
 __device__ inline void gemm_tile_splitk(const T* __restrict__ A, const void* __restrict__ Bsrc,
                                         int n, int m0, int n0, Epi epi, float bscale,
                                         float oscale, double* partial_out, int slot_stride,
-                                        char* lds) {
+                                        char* lds, Fold fold = Fold{}) {
   if ((n % 8) == 0)
-    gemm_tile_splitk_vk<T, B_FROM_F32, Epi, KS, true>(A, Bsrc, n, m0, n0, epi, bscale, oscale,
-                                                      partial_out, slot_stride, lds);
+    gemm_tile_splitk_vk<T, B_FROM_F32, Epi, KS, true, Fold>(A, Bsrc, n, m0, n0, epi, bscale,
+                                                            oscale, partial_out, slot_stride,
+                                                            lds, fold);
   else
-    gemm_tile_splitk_vk<T, B_FROM_F32, Epi, KS, false>(A, Bsrc, n, m0, n0, epi, bscale,
-                                                       oscale, partial_out, slot_stride, lds);
+    gemm_tile_splitk_vk<T, B_FROM_F32, Epi, KS, false, Fold>(A, Bsrc, n, m0, n0, epi, bscale,
+                                                             oscale, partial_out, slot_stride,
+                                                             lds, fold);
 }
 
 }  // namespace kpcg

@@ -84,17 +84,6 @@ __global__ __launch_bounds__(G8T) void gemm8_kernel(Gemm8Args g, Ctrl* ctrl, int
                                                     double* partials, int fold_rr,
                                                     CtrlMirror* __restrict__ mirror) {
   if (skip && ctrl->done != RUNNING) return;
-  if (fold_rr > 0) {
-    // the residual-norm step of the update before, folded in (the FP8 chain
-    // does not scale the residual, so only the state is needed here)
-    __shared__ double fsh[G8T / 64 + 1];
-    const double S = fold_slot<G8T>(partials, SLOT_RR, fold_rr, fsh);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-      apply_rr(ctrl, S);
-      if (mirror != nullptr) publish_mirror(ctrl, mirror);
-    }
-    if (rr_state(ctrl, S) != RUNNING) return;          // the same decision in every block
-  }
   const int n = g.n, nb32 = n / 32;
   __shared__ __align__(16) uint8_t sA[2][B8M][LD8];
   __shared__ __align__(16) uint8_t sB[2][B8N][LD8];
@@ -183,6 +172,18 @@ __global__ __launch_bounds__(G8T) void gemm8_kernel(Gemm8Args g, Ctrl* ctrl, int
 
   const int nk = n / B8K;
   load(0);
+  if (fold_rr > 0) {
+    // the residual-norm step of the update before, folded in while the first
+    // operand loads are in flight (the FP8 chain does not scale the
+    // residual, so only the state is needed here)
+    __shared__ double fsh[G8T / 64 + 1];
+    const double S = fold_slot<G8T>(partials, SLOT_RR, fold_rr, fsh);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+      apply_rr(ctrl, S);
+      if (mirror != nullptr) publish_mirror(ctrl, mirror);
+    }
+    if (rr_state(ctrl, S) != RUNNING) return;          // the same decision in every block
+  }
   store(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
