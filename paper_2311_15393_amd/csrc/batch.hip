@@ -303,8 +303,9 @@ __global__ __launch_bounds__(256) void vec_batched_kernel(const ItemDesc* __rest
 // batched scalar kernel: one block per item
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void scalar_batched_kernel(const ItemDesc* __restrict__ items,
+                                                             const TileRef* __restrict__ list,
                                                              int kind, int mode) {
-  const ItemDesc& it = items[blockIdx.x];
+  const ItemDesc& it = items[list[blockIdx.x].item];
   Ctrl* c = it.ctrl;
   if (!item_active(c, mode)) return;
   __shared__ double sh[4];
@@ -418,7 +419,14 @@ struct Batch {
   std::vector<Group> fast_groups;
   TileRef *t_blur64 = nullptr, *t_gemm = nullptr, *t_vec = nullptr;
   int n_blur64 = 0, n_gemm = 0, n_vec = 0;
+  TileRef* t_items = nullptr;                // the items in the tables (scalar steps)
+  int n_items = 0;
   size_t lds64 = 0;
+  // per item: its FP32-blur group (tile shape) and fast group, with their LDS
+  std::vector<int> blur_cfg, fast_gid;
+  std::vector<size_t> blur_lds, fast_lds;
+  TileRef* d_tab = nullptr;                  // device region of the tables
+  std::vector<TileRef> h_tab;                // their host staging
   void* mem = nullptr;                       // one allocation for everything
   Ctrl* h_ctrl = nullptr;                    // pinned mirror of the items' Ctrl
   Ctrl* d_ctrl = nullptr;
@@ -567,8 +575,9 @@ static hipError_t vec_launch(const Batch& B, int mode) {
 }
 
 static hipError_t scalar_launch(const Batch& B, int kind, int mode) {
-  hipLaunchKernelGGL(scalar_batched_kernel, dim3(B.nitems), dim3(256), 0, B.s, B.d_items, kind,
-                     mode);
+  if (B.n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(scalar_batched_kernel, dim3(B.n_items), dim3(256), 0, B.s, B.d_items,
+                     B.t_items, kind, mode);
   return hipGetLastError();
 }
 
@@ -664,6 +673,63 @@ static int read_ctrls(Batch& B) {
   return KP_OK;
 }
 
+// The tile tables of the items with live[i] set, in a fixed order (FP32
+// blur groups by tile shape, fast groups, FP64 blur, GEMM, vector, the item
+// list), copied to the device region on the batch stream.  The host staging
+// is reused only after a synchronisation of that stream (read_ctrls).
+static hipError_t build_tables(Batch& B, const std::vector<char>& live) {
+  const int ng = NUM_BLUR_CFG + 3;
+  B.h_tab.clear();
+  B.blur_groups.clear();
+  B.fast_groups.clear();
+  size_t cur = 0;
+  auto add_group = [&](std::vector<Batch::Group>& out, int gid, int which) {
+    const size_t start = cur;
+    size_t lds = 0;
+    for (int i = 0; i < B.nitems; ++i) {
+      if (!live[i]) continue;
+      const ItemDesc& d = B.h_items[i];
+      const bool in = which == 0 ? B.blur_cfg[i] == gid : B.fast_gid[i] == gid;
+      if (!in) continue;
+      const int cnt = which == 0 ? d.nb_blur : d.nb_fast;
+      for (int t = 0; t < cnt; ++t) B.h_tab.push_back(TileRef{i, t});
+      cur += cnt;
+      const size_t l = which == 0 ? B.blur_lds[i] : B.fast_lds[i];
+      lds = lds > l ? lds : l;
+    }
+    if (cur > start) {
+      const int cfg = which == 0 || gid < NUM_BLUR_CFG ? gid
+                                                       : BLUR_CFG_MFMA + (gid - NUM_BLUR_CFG + 1);
+      out.push_back(Batch::Group{cfg, B.d_tab + start, (int)(cur - start), lds});
+    }
+  };
+  for (int c = 0; c < NUM_BLUR_CFG; ++c) add_group(B.blur_groups, c, 0);
+  for (int c = 0; c < ng; ++c) add_group(B.fast_groups, c, 1);
+  auto add_plain = [&](TileRef*& ptr, int& count, int ItemDesc::*nb) {
+    const size_t start = cur;
+    for (int i = 0; i < B.nitems; ++i) {
+      if (!live[i]) continue;
+      const int cnt = B.h_items[i].*nb;
+      for (int t = 0; t < cnt; ++t) B.h_tab.push_back(TileRef{i, t});
+      cur += cnt;
+    }
+    ptr = B.d_tab + start;
+    count = (int)(cur - start);
+  };
+  add_plain(B.t_blur64, B.n_blur64, &ItemDesc::nb_blur64);
+  add_plain(B.t_gemm, B.n_gemm, &ItemDesc::nb_gemm);
+  add_plain(B.t_vec, B.n_vec, &ItemDesc::nb_vec);
+  const size_t start = cur;
+  for (int i = 0; i < B.nitems; ++i)
+    if (live[i]) B.h_tab.push_back(TileRef{i, 0});
+  cur = B.h_tab.size();
+  B.t_items = B.d_tab + start;
+  B.n_items = (int)(cur - start);
+  if (B.h_tab.empty()) return hipSuccess;
+  return hipMemcpyAsync(B.d_tab, B.h_tab.data(), sizeof(TileRef) * B.h_tab.size(),
+                        hipMemcpyHostToDevice, B.s);
+}
+
 // The batch's device memory is the caller's workspace and its stream the
 // device's AUX_BATCH stream: neither is released here.
 static void destroy_batch(Batch& B) {
@@ -706,14 +772,15 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
   const size_t off_desc = total;
   total += align(sizeof(ItemDesc) * nitems);
 
-  // ---- tile tables (host)
-  std::vector<std::vector<TileRef>> grp_tiles(NUM_BLUR_CFG);
-  std::vector<size_t> grp_lds(NUM_BLUR_CFG, 0);
-  // fast groups: VALU shapes 0..5, then MFMA with nch = 1, 2, 3 (index 6 + nch - 1)
-  std::vector<std::vector<TileRef>> fast_tiles(NUM_BLUR_CFG + 3);
-  std::vector<size_t> fast_lds(NUM_BLUR_CFG + 3, 0);
-  std::vector<TileRef> t64, tg, tv;
+  // ---- per-item tile counts and groups (the tables are built by build_tables):
+  // FP32 blur groups by VALU tile shape 0..5; fast groups: VALU shapes 0..5,
+  // then MFMA with nch = 1, 2, 3 (group 6 + nch - 1)
+  size_t ntab = 0;
   B.h_items.resize(nitems);
+  B.blur_cfg.assign(nitems, 0);
+  B.fast_gid.assign(nitems, 0);
+  B.blur_lds.assign(nitems, 0);
+  B.fast_lds.assign(nitems, 0);
   for (int i = 0; i < nitems; ++i) {
     const Plan& P = *plans[plan_of_item[i]];
     ItemDesc& d = B.h_items[i];
@@ -732,8 +799,8 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
     }
     d.ntx_blur = (n + tw - 1) / tw;
     d.nb_blur = d.ntx_blur * ((n + th - 1) / th);
-    for (int t = 0; t < d.nb_blur; ++t) grp_tiles[cfg].push_back(TileRef{i, t});
-    grp_lds[cfg] = grp_lds[cfg] > lds ? grp_lds[cfg] : lds;
+    B.blur_cfg[i] = cfg;
+    B.blur_lds[i] = lds;
     d.use_mfma = blur_cfg_is_mfma(P.blur_cfg) ? 1 : 0;     // (16 x 16 x 32 form)
     d.nch = mfma_nch(P.k);
     d.exq = P.mfma_exq;
@@ -742,33 +809,26 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
     d.bc = P.bc;
     d.ntx_mfma = (n + MB_TN - 1) / MB_TN;
     if (d.use_mfma) {
-      const int fg = NUM_BLUR_CFG + d.nch - 1;
       d.nb_fast = d.ntx_mfma * ((n + MB_TM - 1) / MB_TM);
-      for (int t = 0; t < d.nb_fast; ++t) fast_tiles[fg].push_back(TileRef{i, t});
-      const size_t ml = mb_lds_bytes(d.nch, P.k);
-      fast_lds[fg] = fast_lds[fg] > ml ? fast_lds[fg] : ml;
+      B.fast_gid[i] = NUM_BLUR_CFG + d.nch - 1;
+      B.fast_lds[i] = mb_lds_bytes(d.nch, P.k);
     } else {
       d.nb_fast = d.nb_blur;
-      for (int t = 0; t < d.nb_blur; ++t) fast_tiles[cfg].push_back(TileRef{i, t});
-      fast_lds[cfg] = fast_lds[cfg] > lds ? fast_lds[cfg] : lds;
+      B.fast_gid[i] = cfg;
+      B.fast_lds[i] = lds;
     }
     d.ntx_blur64 = (n + 63) / 64;
     d.nb_blur64 = d.ntx_blur64 * d.ntx_blur64;
-    for (int t = 0; t < d.nb_blur64; ++t) t64.push_back(TileRef{i, t});
     const size_t l64 = (size_t)(64 + P.k - 1) * lds_width<KP_F64IN_CFG, double>(P.kq) * 8;
     B.lds64 = B.lds64 > l64 ? B.lds64 : l64;
     d.ntx_gemm = (n + BN - 1) / BN;
     d.nb_gemm = d.ntx_gemm * ((n + BM - 1) / BM);
-    for (int t = 0; t < d.nb_gemm; ++t) tg.push_back(TileRef{i, t});
     d.nb_vec = (n * n + VCH - 1) / VCH;
-    for (int t = 0; t < d.nb_vec; ++t) tv.push_back(TileRef{i, t});
+    ntab += (size_t)d.nb_blur + d.nb_fast + d.nb_blur64 + d.nb_gemm + d.nb_vec + 1;
     if (d.nb_blur > MAXP_ITEM || d.nb_blur64 > MAXP_ITEM || d.nb_gemm > MAXP_ITEM ||
         d.nb_vec > MAXP_ITEM || d.nb_fast > MAXP_ITEM)
       return KP_ERR_UNSUPPORTED;
   }
-  size_t ntab = t64.size() + tg.size() + tv.size();
-  for (auto& g : grp_tiles) ntab += g.size();
-  for (auto& g : fast_tiles) ntab += g.size();
   const size_t off_tab = total;
   total += align(sizeof(TileRef) * ntab);
 
@@ -826,30 +886,8 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
     c.zscale = (float)(1.0 / d.lam2);
     c.fastu = B.fast_tr && tol >= (d.use_mfma ? TR_FASTU_TOL_MFMA : TR_FASTU_TOL_VALU) ? 1 : 0;
   }
-  // tables
-  std::vector<TileRef> all;
-  all.reserve(ntab);
-  size_t cur = 0;
-  TileRef* dtab = reinterpret_cast<TileRef*>(base + off_tab);
-  for (int c = 0; c < NUM_BLUR_CFG; ++c) {
-    if (grp_tiles[c].empty()) continue;
-    B.blur_groups.push_back(Batch::Group{c, dtab + cur, (int)grp_tiles[c].size(), grp_lds[c]});
-    all.insert(all.end(), grp_tiles[c].begin(), grp_tiles[c].end());
-    cur += grp_tiles[c].size();
-  }
-  for (int c = 0; c < NUM_BLUR_CFG + 3; ++c) {
-    if (fast_tiles[c].empty()) continue;
-    const int gid = c < NUM_BLUR_CFG ? c : BLUR_CFG_MFMA + (c - NUM_BLUR_CFG + 1);
-    B.fast_groups.push_back(Batch::Group{gid, dtab + cur, (int)fast_tiles[c].size(), fast_lds[c]});
-    all.insert(all.end(), fast_tiles[c].begin(), fast_tiles[c].end());
-    cur += fast_tiles[c].size();
-  }
-  B.t_blur64 = dtab + cur; B.n_blur64 = (int)t64.size();
-  all.insert(all.end(), t64.begin(), t64.end()); cur += t64.size();
-  B.t_gemm = dtab + cur; B.n_gemm = (int)tg.size();
-  all.insert(all.end(), tg.begin(), tg.end()); cur += tg.size();
-  B.t_vec = dtab + cur; B.n_vec = (int)tv.size();
-  all.insert(all.end(), tv.begin(), tv.end()); cur += tv.size();
+  B.d_tab = reinterpret_cast<TileRef*>(base + off_tab);
+  B.h_tab.reserve(ntab);
 
   int rc = KP_OK;
   hipGraph_t graph = nullptr;
@@ -865,7 +903,10 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
   BCHK(hipStreamWaitEvent(B.s, ev, 0));
   BCHK(hipMemcpyAsync(B.d_items, B.h_items.data(), sizeof(ItemDesc) * nitems,
                       hipMemcpyHostToDevice, B.s));
-  BCHK(hipMemcpyAsync(dtab, all.data(), sizeof(TileRef) * ntab, hipMemcpyHostToDevice, B.s));
+  {
+    const std::vector<char> every(nitems, 1);
+    BCHK(build_tables(B, every));
+  }
   BCHK(hipMemcpyAsync(B.d_ctrl, B.h_ctrl, sizeof(Ctrl) * nitems, hipMemcpyHostToDevice, B.s));
   BCHK(hipStreamSynchronize(B.s));
 
@@ -880,25 +921,39 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
     const int block = 8;
     BCHK(ensure_fast<BK_A>(B));
     BCHK(ensure_fast<BK_AT_NORMAL>(B));
-    if (!eager) {
-      BCHK(hipStreamBeginCapture(B.s, hipStreamCaptureModeThreadLocal));
-      for (int it = 0; it < block; ++it) {
-        if (iteration_b(B) != hipSuccess) {
-          hipStreamEndCapture(B.s, &graph);
-          rc = KP_ERR_HIP;
-          goto out;
-        }
-      }
-      BCHK(hipStreamEndCapture(B.s, &graph));
-      BCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    }
+    // the block of iterations as a graph of the current tables
+    auto capture = [&]() -> hipError_t {
+      if (exec) hipGraphExecDestroy(exec);
+      if (graph) hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
+      hipError_t e = hipStreamBeginCapture(B.s, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return e;
+      for (int it = 0; it < block && e == hipSuccess; ++it) e = iteration_b(B);
+      hipError_t e2 = hipStreamEndCapture(B.s, &graph);
+      if (e != hipSuccess) return e;
+      if (e2 != hipSuccess) return e2;
+      return hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    };
+    if (!eager) BCHK(capture());
+    int in_tables = nitems;                    // items the tables cover
+    std::vector<char> live(nitems, 0);
     for (int guard = 0; guard < 1000000; ++guard) {
       int running = 0, pending = 0;
       for (int i = 0; i < nitems; ++i) {
         running += B.h_ctrl[i].done == RUNNING;
         pending += B.h_ctrl[i].done == PENDING;
+        live[i] = B.h_ctrl[i].done == RUNNING || B.h_ctrl[i].done == PENDING;
       }
       if (!running && !pending) break;
+      // once half of the items in the tables have finished, rebuild them for
+      // the live items only (finished items' blocks would otherwise still be
+      // launched, only to return at once) and capture the graph anew
+      if (2 * (running + pending) <= in_tables) {
+        BCHK(build_tables(B, live));
+        in_tables = running + pending;
+        if (!eager) BCHK(capture());
+      }
       if (pending) {
         BCHK(pending_residuals_b(B));
         BCHK(tail_b(B, RM_RESUME));
@@ -916,7 +971,12 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
       if ((rc = read_ctrls(B)) != KP_OK) goto out;
     }
   }
-  // report: true residual of unconverged items, x in FP32, data misfit
+  // report: true residual of unconverged items, x in FP32, data misfit (the
+  // tables cover every item again)
+  {
+    const std::vector<char> every(nitems, 1);
+    BCHK(build_tables(B, every));
+  }
   BCHK(true_residual_b(B, RM_FINISHED, SC_TRUE_INFO));
   BCHK(vec_launch<VK_TO_F32>(B, RM_ALL));
   BCHK(blur_groups_launch<BK_MISFIT>(B, RM_ALL));
