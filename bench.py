@@ -842,9 +842,49 @@ def run_batch(nprob: int, dev, nthreads: int = 16, parity: bool = True):
             samples.append({"problem": pi, "n": p.n, "k": p.k, "lambda": lam_it,
                             "status": int(infos[it].status), "iters": int(infos[it].iters),
                             "rel_err": err, "ok": bool(infos[it].status == KP_OK and err <= 1e-4
-                                                       and xi["status"] == "converged")})
+                                                       and xi["status"] == "converged"),
+                            "_xl": xl})
             log(f"[bench] batch parity: problem {pi} n={p.n} K={p.k} lambda={lam_it:.3g} "
                 f"iters={infos[it].iters} err={err:.2e}")
+    # the same sweep by continuation: 16 batched calls, largest lambda first,
+    # each item warm-started (KP_WARM) from its problem's solution at the
+    # previous lambda of the sweep
+    from paper_2311_15393_amd import KP_WARM
+    order = [[k for k, (q, _) in enumerate(items) if q == pi] for pi in range(nprob)]
+    nl = len(order[0])
+    xs_c = [torch.empty_like(b) for b in bs]
+    infos_c = [None] * len(items)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for stage in range(nl):
+        sel = [order[pi][nl - 1 - stage] for pi in range(nprob)]
+        if stage > 0:
+            prev = [order[pi][nl - stage] for pi in range(nprob)]
+            for k, kp_ in zip(sel, prev):
+                xs_c[k].copy_(xs_c[kp_])
+        out_x, out_i, _ = solve_batched(plans, [bs[k] for k in sel], [lams[k] for k in sel],
+                                        [poi[k] for k in sel], tol=1e-6, maxit=1000,
+                                        mode=KP_FPCG | KP_P16 | (KP_WARM if stage else 0),
+                                        xs=[xs_c[k] for k in sel])
+        for k, inf in zip(sel, out_i):
+            infos_c[k] = inf
+    torch.cuda.synchronize()
+    wall_c = time.perf_counter() - t0
+    iters_c = np.array([i.iters for i in infos_c])
+    ok_c = sum(i.status == KP_OK for i in infos_c)
+    cont_samples = []
+    for smp in samples:
+        k = next(kk for kk, (q, lam_k) in enumerate(items)
+                 if q == smp["problem"] and lam_k == smp["lambda"])
+        got = xs_c[k].cpu().numpy().astype(np.float64)
+        err = float(np.linalg.norm(got - smp["_xl"]) / np.linalg.norm(smp["_xl"]))
+        cont_samples.append({"problem": smp["problem"], "n": smp["n"], "rel_err": err,
+                             "iters": int(infos_c[k].iters),
+                             "ok": bool(infos_c[k].status == KP_OK and err <= 1e-4)})
+    log(f"[bench] batch by continuation: {wall_c:.3f}s ({len(items) / wall_c:.1f}/s), converged "
+        f"{ok_c}, iters mean {iters_c.mean():.1f} max {iters_c.max()}")
+    for smp in samples:
+        smp.pop("_xl", None)
     # the same batch with the exact KP-basis diagonal in the preconditioner
     xs2 = [torch.empty_like(b) for b in bs]
     torch.cuda.synchronize()
@@ -868,6 +908,11 @@ def run_batch(nprob: int, dev, nthreads: int = 16, parity: bool = True):
         "parity_ok": all(x["ok"] for x in samples) if samples else None,
         "exact_diag": {"wall_s": wall2, "solves_per_s": len(items) / wall2, "converged": ok2,
                        "iters_mean": float(iters2.mean()), "iters_max": int(iters2.max())},
+        "continuation": {"what": "16 batched calls over the sweep, largest lambda first, each "
+                                 "item warm-started from its problem's previous solution",
+                         "wall_s": wall_c, "solves_per_s": len(items) / wall_c,
+                         "converged": ok_c, "iters_mean": float(iters_c.mean()),
+                         "iters_max": int(iters_c.max()), "parity_samples": cont_samples},
     }
     log(f"[bench] batch: {wall:.3f}s for {len(items)} solves ({len(items) / wall:.1f}/s), "
         f"converged {ok}, iters mean {iters.mean():.1f} max {iters.max()}; "

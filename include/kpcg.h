@@ -266,7 +266,9 @@ int discrepancy_lambda(kp_plan_t plan, const float *b, const double *grid,
  * launches: item i solves with plan plans[plan_of_item[i]] (its PSF and
  * image size), data b[i], parameter lambdas[i], writing x[i].  All items
  * share tol, maxit and mode (solver and preconditioner bits and
- * KP_EXACT_DIAG as pcg_solve; KP_P8 and KP_WARM are not supported here;
+ * KP_EXACT_DIAG as pcg_solve; KP_P8 is not supported here; with KP_WARM
+ * every x[i] holds its item's initial guess, whose residual is a full FP64
+ * true residual, e.g. the solution at the neighbouring lambda of a sweep;
  * KP_BATCH_EAGER launches the
  * iterations eagerly instead of replaying a captured hipGraph).  Uneven
  * image sizes and PSF supports are allowed.  Each phase of an iteration is

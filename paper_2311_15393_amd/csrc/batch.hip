@@ -53,6 +53,7 @@ struct ItemDesc {
   const void* mfma_taps;                     // table for taps32, then for taps32_flip
   size_t mfma_count;                         // entries per orientation
   int bc;                                    // the plan's boundary (KP_BC_ZERO / KP_BC_PERIODIC)
+  int warm;                                  // x holds the initial guess (KP_WARM)
 };
 
 struct TileRef {
@@ -278,10 +279,12 @@ __global__ __launch_bounds__(256) void vec_batched_kernel(const ItemDesc* __rest
     const float* z = KIND == VK_PUPDATE_Z ? it.z : it.r;
     for (int i = e0 + threadIdx.x; i < e1; i += 256) it.p[i] = fmaf(bt, it.p[i], z[i]);
   } else if constexpr (KIND == VK_INIT) {
+    // x_0 = 0, or the caller's x for a warm start (KP_WARM)
+    const bool warm = it.warm != 0;
     for (int i = e0 + threadIdx.x; i < e1; i += 256) {
       it.p[i] = 0.0f;
       it.w[i] = 0.0f;
-      it.x64[i] = 0.0;
+      it.x64[i] = warm ? (double)it.x[i] : 0.0;
     }
   } else if constexpr (KIND == VK_TO_F32) {
     for (int i = e0 + threadIdx.x; i < e1; i += 256) it.x[i] = (float)it.x64[i];
@@ -873,6 +876,7 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
     d.d0 = (mode & KP_EXACT_DIAG) ? P.d0 : nullptr;
     d.b = b[i];
     d.x = x[i];
+    d.warm = (mode & KP_WARM) ? 1 : 0;
     Ctrl& c = B.h_ctrl[i];
     std::memset(&c, 0, sizeof(c));
     c.tol_rel2 = tol * tol;
@@ -910,11 +914,21 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
   BCHK(hipMemcpyAsync(B.d_ctrl, B.h_ctrl, sizeof(Ctrl) * nitems, hipMemcpyHostToDevice, B.s));
   BCHK(hipStreamSynchronize(B.s));
 
-  // x_0 = 0, r = c = A^T b, ||c||, then the first direction
+  // x_0 = 0 (or the caller's x), r = c = A^T b, ||c||; for a warm start
+  // the residual r = c - H x_0 is a full FP64 true residual (which may find
+  // the item converged already); then the first direction
   BCHK(vec_launch<VK_INIT>(B, RM_ALL));
   BCHK(blur_groups_launch<BK_RHS>(B, RM_ALL));          // r = c = A^T b (FP32 blur)
   BCHK(scalar_launch(B, SC_RHS, RM_ALL));
-  BCHK(tail_b(B, RM_RUNNING));
+  if (mode & KP_WARM) {
+    BCHK(true_residual_b(B, RM_RUNNING, SC_TRUE));
+    BCHK(tail_b(B, RM_RUNNING));
+    hipLaunchKernelGGL(clear_resume_kernel, dim3((nitems + 255) / 256), dim3(256), 0, B.s,
+                       B.d_items, nitems);
+    BCHK(hipGetLastError());
+  } else {
+    BCHK(tail_b(B, RM_RUNNING));
+  }
   if ((rc = read_ctrls(B)) != KP_OK) goto out;
 
   {

@@ -691,7 +691,7 @@ static int batched_args(const kp_plan_t* plans, int nplans, const int* plan_of_i
   if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM | KP_BATCH_EAGER | KP_EXACT_DIAG)) != 0)
     return KP_ERR_ARG;
   if ((mode & KP_SOLVER_MASK) == 3 || (mode & KP_PREC_MASK) == KP_PREC_MASK) return KP_ERR_ARG;
-  if ((mode & KP_WARM) || (mode & KP_PREC_MASK) == KP_P8) return KP_ERR_UNSUPPORTED;
+  if ((mode & KP_PREC_MASK) == KP_P8) return KP_ERR_UNSUPPORTED;
   ps.resize(nplans);
   for (int i = 0; i < nplans; ++i) {
     if (!plans[i]) return KP_ERR_ARG;

@@ -243,3 +243,46 @@ def test_batched_exact_diag_items_match_oracle():
     finally:
         for p in plans:
             p.close()
+
+
+def test_batched_warm_start_continuation():
+    """KP_WARM in pcg_solve_batched: each item of a lambda = 0.01 batch starts
+    from the item's own solution at lambda = 0.05 (continuation along a
+    sweep).  Every item reaches the oracle's x_lambda at 0.01 in no more
+    iterations than from x_0 = 0; an item started from its own converged
+    solution is certified by its first true residual (no iteration)."""
+    require_gpu()
+    import torch
+    from paper_2311_15393_amd import KP_FPCG, KP_OK, KP_P16, KP_WARM, Plan, solve_batched
+    probs, _ = _small_batch()
+    plans = [Plan(p.psf, p.n) for p in probs]
+    try:
+        bs = [to_dev(p.b) for p in probs]
+        poi = list(range(len(probs)))
+        mode = KP_FPCG | KP_P16
+        say("batched warm start: cold solves at 0.05, then 0.01 from them")
+        x05, inf05, st = solve_batched(plans, bs, [0.05] * len(probs), poi, tol=1e-8, maxit=500,
+                                       mode=mode)
+        assert st == KP_OK
+        _, cold, _ = solve_batched(plans, bs, [0.01] * len(probs), poi, tol=1e-8, maxit=500,
+                                   mode=mode)
+        xw = [x.clone() for x in x05]
+        xw, warm, st = solve_batched(plans, bs, [0.01] * len(probs), poi, tol=1e-8, maxit=500,
+                                     mode=mode | KP_WARM, xs=xw)
+        assert st == KP_OK
+        for i, (x, c, w) in enumerate(zip(xw, cold, warm)):
+            err = rel(to_host(x), _xlam(probs, i, 0.01))
+            say(f"  n={probs[i].n} k={probs[i].k}: cold {c.iters} warm {w.iters} err={err:.2e}")
+            assert w.status == KP_OK and err <= 1e-4
+            assert w.iters <= c.iters
+        # restart from the converged solutions themselves: nothing left to do
+        # (at a tolerance above the effect of their rounding to FP32)
+        xr = [x.clone() for x in xw]
+        xr, again, st = solve_batched(plans, bs, [0.01] * len(probs), poi, tol=1e-6, maxit=500,
+                                      mode=mode | KP_WARM, xs=xr)
+        for x0, x1, a in zip(xw, xr, again):
+            assert a.status == KP_OK and a.iters == 0, a
+            assert torch.equal(x0, x1)
+    finally:
+        for p in plans:
+            p.close()
