@@ -60,6 +60,28 @@ BLUR_TRAFFIC = {
 }
 
 
+# HBM bandwidth of the two vector steps of an iteration on a working set far
+# above the 256 MB Infinity Cache: the batched update (x += alpha p in FP64,
+# r -= alpha w, ||r||^2 partials: 32 B per element) and direction update
+# (p = z + beta p: 12 B per element) over 16 items of 1024^2 (one lambda sweep
+# of the large workload; ~1 GiB of item vectors), from
+# `rocprofv3 --kernel-trace --stats -- python3 bench.py --vector-batch` (mean
+# duration of the launches over all 16 items) and two --pmc runs of the same
+# command (FETCH_SIZE, WRITE_SIZE, scaled by the calibration copy it
+# launches).  Null when the batched kernels' source differs from the one
+# measured (sha256 of batch.hip).
+VECTOR_KERNELS = {
+    "workload": "16 items of 1024^2 (~1 GiB of item vectors), profiles/vector_kernels_batch16_1024_hbm.md",
+    "update": {"kernel": "vec_batched_kernel<0>", "avg_us": 83.89, "bytes_per_launch": 536870912,
+               "achieved_TBps": 6.400, "frac_of_8TBps": 0.800,
+               "traffic": {"fetch_bytes": 336250368, "write_bytes": 202136269}},
+    "pupdate": {"kernel": "vec_batched_kernel<1>", "avg_us": 34.43, "bytes_per_launch": 201326592,
+                "achieved_TBps": 5.848, "frac_of_8TBps": 0.731,
+                "traffic": {"fetch_bytes": 134860800, "write_bytes": 67108864}},
+    "sources_sha256": "6be39aeb601c4ef8cc814655e97845f5f147644b9c802ab7624f7c48723099a5",
+}
+
+
 CPU_SAMPLE_S = 10.0       # the CPU oracle leg times at least this long ...
 CPU_SAMPLE_MAX = 60       # ... or this many solves
 
@@ -85,6 +107,20 @@ def blur_sources_sha256() -> str:
         with open(os.path.join(ROOT, "paper_2311_15393_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def batch_sources_sha256() -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2311_15393_amd", "csrc", "batch.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def vector_kernels():
+    """The recorded bandwidth of the batched vector steps, or None when the
+    batched kernels' source has changed since it was measured."""
+    if VECTOR_KERNELS is None or VECTOR_KERNELS["sources_sha256"] != batch_sources_sha256():
+        return None
+    return {k: v for k, v in VECTOR_KERNELS.items() if k != "sources_sha256"}
 
 
 def blur_traffic(kernel: str):
@@ -304,6 +340,10 @@ def main():
                          "--profile-only)")
     ap.add_argument("--batch", type=int, default=64, metavar="P",
                     help="the uneven batched workload with P problems x 16 lambda (0: skip)")
+    ap.add_argument("--vector-batch", action="store_true",
+                    help="only run one 16-lambda batch of the 1024^2 workload for 40 iterations "
+                         "(and the counter calibration copy), for profiling the batched vector "
+                         "kernels on a working set above the Infinity Cache")
     ap.add_argument("--matvec-sweep", action="store_true",
                     help="only compare the direct blurs with a zero-padded rocFFT H p over K "
                          "(prints its own JSON line)")
@@ -324,6 +364,9 @@ def main():
     nthreads = cpu_threads()
     if args.matvec_sweep:
         print(json.dumps(run_matvec_sweep(dev)), flush=True)
+        return
+    if args.vector_batch:
+        print(json.dumps(run_vector_batch(dev)), flush=True)
         return
     grid = S.lambda_grid()
     chosen = [m for m in args.modes.split(",") if m]
@@ -513,6 +556,7 @@ def main():
             "lowp_setup": lowp,
         },
         "roofline": roofline,
+        "vector_kernels": vector_kernels(),
         "cpu_baseline": cpu_baseline,
     }
     print(json.dumps(line), flush=True)
@@ -760,6 +804,44 @@ def run_matvec_sweep(dev, n: int = 1024, ks=(15, 23, 31, 47, 63), reps: int = 50
             f"L={row['fft_pow2']['L']} {row['fft_pow2']['hp_us']:.1f} us")
         out.append(row)
     return {"matvec_sweep": {"n": n, "boundary": "zero", "rows": out}}
+
+
+def run_vector_batch(dev, items: int = 16, iters: int = 40) -> dict:
+    """One lambda sweep of the seed-0 1024^2 problem as a batch of `items`
+    FP16-KP FPCG solves, run for `iters` iterations (a tolerance no item
+    reaches), after one warm-up batch; then the plain copy that calibrates
+    the HBM counters.  The item vectors (r, p, q, w, z in FP32; x, y and the
+    anchor in FP64; the GEMM intermediates) take ~64 MiB per item."""
+    import torch
+    import synthetic as S
+    from paper_2311_15393_amd import KP_FPCG, KP_P16, Plan, solve_batched
+    prob = S.large_moffat(0)
+    b = torch.from_numpy(prob.b).to(dev)
+    plan = Plan(prob.psf, prob.n)
+    lam_g, _ = plan.gcv(b, S.lambda_grid())
+    lams = [float(v) for v in np.clip(lam_g * 10.0 ** np.linspace(-1.5, 1.5, items), 1e-4, 1.0)]
+    xs = [torch.empty_like(b) for _ in range(items)]
+
+    def run():
+        return solve_batched([plan], [b] * items, lams, [0] * items, tol=1e-12, maxit=iters,
+                             mode=KP_FPCG | KP_P16, xs=xs)
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, infos, _ = run()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    src = torch.ones(COPY_CALIB_FLOATS, device=dev, dtype=torch.float32)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    plan.close()
+    n2 = prob.n * prob.n
+    return {"vector_batch": {"items": items, "n": prob.n, "iterations": [i.iters for i in infos],
+                             "wall_s": wall,
+                             "update_bytes_per_launch": 32 * n2 * items,
+                             "pupdate_bytes_per_launch": 12 * n2 * items}}
 
 
 def run_batch(nprob: int, dev, nthreads: int = 16, parity: bool = True):

@@ -265,10 +265,32 @@ __global__ __launch_bounds__(256) void vec_batched_kernel(const ItemDesc* __rest
   const int N = it.n * it.n;
   const int e0 = tr.t * VCH, e1 = min(N, e0 + VCH);
   double d = 0.0;
+  // the two HBM-bound steps of every iteration move 16 bytes per lane and
+  // access (e0 is a multiple of VCH; vectors are 256-byte aligned); an
+  // item's last block finishes a ragged n^2 element by element
+  const int v0 = e0 >> 2, v1 = e1 >> 2;
   if constexpr (KIND == VK_UPDATE) {
     const double ad = it.ctrl->alpha;
     const float a = (float)ad;
-    for (int i = e0 + threadIdx.x; i < e1; i += 256) {
+    double2* x2 = reinterpret_cast<double2*>(it.x64);
+    float4* r4 = reinterpret_cast<float4*>(it.r);
+    const float4* p4 = reinterpret_cast<const float4*>(it.p);
+    const float4* w4 = reinterpret_cast<const float4*>(it.w);
+    for (int i = v0 + threadIdx.x; i < v1; i += 256) {
+      double2 xa = x2[2 * i], xb = x2[2 * i + 1];
+      float4 rv = r4[i];
+      const float4 pv = p4[i], wv = w4[i];
+      xa.x = fma(ad, (double)pv.x, xa.x); xa.y = fma(ad, (double)pv.y, xa.y);
+      xb.x = fma(ad, (double)pv.z, xb.x); xb.y = fma(ad, (double)pv.w, xb.y);
+      rv.x = fmaf(-a, wv.x, rv.x); rv.y = fmaf(-a, wv.y, rv.y);
+      rv.z = fmaf(-a, wv.z, rv.z); rv.w = fmaf(-a, wv.w, rv.w);
+      x2[2 * i] = xa;
+      x2[2 * i + 1] = xb;
+      r4[i] = rv;
+      d += (double)rv.x * rv.x + (double)rv.y * rv.y + (double)rv.z * rv.z +
+           (double)rv.w * rv.w;
+    }
+    for (int i = 4 * v1 + threadIdx.x; i < e1; i += 256) {
       it.x64[i] = fma(ad, (double)it.p[i], it.x64[i]);
       const float rv = fmaf(-a, it.w[i], it.r[i]);
       it.r[i] = rv;
@@ -277,7 +299,16 @@ __global__ __launch_bounds__(256) void vec_batched_kernel(const ItemDesc* __rest
   } else if constexpr (KIND == VK_PUPDATE_Z || KIND == VK_PUPDATE_R) {
     const float bt = (float)it.ctrl->beta;
     const float* z = KIND == VK_PUPDATE_Z ? it.z : it.r;
-    for (int i = e0 + threadIdx.x; i < e1; i += 256) it.p[i] = fmaf(bt, it.p[i], z[i]);
+    float4* p4 = reinterpret_cast<float4*>(it.p);
+    const float4* z4 = reinterpret_cast<const float4*>(z);
+    for (int i = v0 + threadIdx.x; i < v1; i += 256) {
+      float4 pv = p4[i];
+      const float4 zv = z4[i];
+      pv.x = fmaf(bt, pv.x, zv.x); pv.y = fmaf(bt, pv.y, zv.y);
+      pv.z = fmaf(bt, pv.z, zv.z); pv.w = fmaf(bt, pv.w, zv.w);
+      p4[i] = pv;
+    }
+    for (int i = 4 * v1 + threadIdx.x; i < e1; i += 256) it.p[i] = fmaf(bt, it.p[i], z[i]);
   } else if constexpr (KIND == VK_INIT) {
     // x_0 = 0, or the caller's x for a warm start (KP_WARM)
     const bool warm = it.warm != 0;
