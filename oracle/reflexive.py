@@ -34,6 +34,18 @@ construction as the periodic boundary; it is exact for separable PSFs.  The
 factor SVDs (eq. (AKronSVD)), the preconditioner solve (eq. (PreconSolve))
 and the exact KP-basis diagonal follow kp.py with reflexive factors.
 
+PSFs not symmetric in both axes (the `*_general` functions below): A is the
+same convolution of the reflected image, but no longer symmetric.  A^T
+follows from the definition by scattering: A X gathers X[refl(i-u),
+refl(j-v)] with weight P[h+u, h+v] into (i, j), so A^T Y adds
+P[h+u, h+v] Y[i, j] into (refl(i-u), refl(j-v)) -- the correlation of Y
+(zero outside the image) evaluated on the positions [-h, n+h) and folded
+back onto the image by the reflection.  The DCT no longer diagonalises A;
+x_lambda comes from a dense solve (tiny n) or FP64 PCG run to a true
+relative residual of 1e-13 with the one-term reflexive KP preconditioner
+(the leading term of the same plain-SVD expansion, which holds for any PSF
+because the reflection acts on rows and columns separately).
+
 Pins (tests/test_oracle_reflexive.py): scipy.ndimage.convolve with
 mode='reflect'; A is symmetric for symmetric PSFs and preserves constant
 images; the dense matrix equals the reflexive Kronecker-sum expansion; the
@@ -57,13 +69,13 @@ def is_symmetric_psf(psf: np.ndarray, rel: float = 1e-12) -> bool:
     return (np.abs(p - p[::-1, :]).max() <= tol) and (np.abs(p - p[:, ::-1]).max() <= tol)
 
 
-def _check(psf: np.ndarray, n: int):
+def _check(psf: np.ndarray, n: int, symmetric: bool = True):
     k = psf.shape[0]
     if psf.shape != (k, k) or k % 2 != 1:
         raise ValueError("PSF must be K x K with K odd")
     if k > n:
         raise ValueError("reflexive boundary needs K <= n")
-    if not is_symmetric_psf(psf):
+    if symmetric and not is_symmetric_psf(psf):
         raise ValueError("reflexive boundary needs a PSF symmetric in both axes")
     return k, (k - 1) // 2
 
@@ -75,9 +87,16 @@ def refl(j: np.ndarray, n: int) -> np.ndarray:
 
 def blur(psf: np.ndarray, x: np.ndarray) -> np.ndarray:
     """A X by the definition (A^T = A for the PSFs accepted here)."""
+    _check(psf, np.asarray(x).shape[0])
+    return blur_general(psf, x)
+
+
+def blur_general(psf: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """A X by the definition for any K x K PSF with K <= n:
+    (A X)[i, j] = sum_{u,v} P[h+u, h+v] X[refl(i-u), refl(j-v)]."""
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
-    k, h = _check(psf, n)
+    k, h = _check(psf, n, symmetric=False)
     idx = np.arange(n)
     y = np.zeros_like(x)
     for u in range(-h, h + 1):
@@ -85,6 +104,55 @@ def blur(psf: np.ndarray, x: np.ndarray) -> np.ndarray:
         for v in range(-h, h + 1):
             y += psf[h + u, h + v] * x[np.ix_(ri, refl(idx - v, n))]
     return y
+
+
+def blur_t_general(psf: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """A^T Y by the definition: every term of blur_general scattered back,
+    (A^T Y)[refl(i-u), refl(j-v)] += P[h+u, h+v] Y[i, j]."""
+    y = np.asarray(y, dtype=np.float64)
+    n = y.shape[0]
+    k, h = _check(psf, n, symmetric=False)
+    idx = np.arange(n)
+    out = np.zeros_like(y)
+    for u in range(-h, h + 1):
+        ri = refl(idx - u, n)
+        for v in range(-h, h + 1):
+            np.add.at(out, (ri[:, None], refl(idx - v, n)[None, :]), psf[h + u, h + v] * y)
+    return out
+
+
+def blur_fft_general(psf: np.ndarray, x: np.ndarray, workers: int | None = None) -> np.ndarray:
+    """A X through the image extended by half-sample reflection (numpy's
+    'symmetric' padding by h) and the 'valid' part of the linear convolution
+    by zero-padded FFTs (the same operator as blur_general)."""
+    import scipy.signal
+    x = np.asarray(x, dtype=np.float64)
+    k, h = _check(psf, x.shape[0], symmetric=False)
+    return scipy.signal.fftconvolve(np.pad(x, h, mode="symmetric"), psf, mode="valid")
+
+
+def fold(z: np.ndarray, h: int) -> np.ndarray:
+    """The (n + 2h)^2 array z on the positions [-h, n+h)^2 folded onto the
+    n x n image: entry (q1, q2) is added into (refl(q1), refl(q2))."""
+    m = z.shape[0]
+    n = m - 2 * h
+    q = refl(np.arange(-h, n + h), n)
+    out = np.zeros((n, n))
+    np.add.at(out, (q[:, None], q[None, :]), z)
+    return out
+
+
+def blur_t_fft_general(psf: np.ndarray, y: np.ndarray,
+                       workers: int | None = None) -> np.ndarray:
+    """A^T Y as the correlation of Y (zero outside the image) on the
+    positions [-h, n+h) -- the 'full' convolution with the flipped PSF, by
+    zero-padded FFTs -- folded back by fold (the same operator as
+    blur_t_general)."""
+    import scipy.signal
+    y = np.asarray(y, dtype=np.float64)
+    k, h = _check(psf, y.shape[0], symmetric=False)
+    z = scipy.signal.fftconvolve(y, psf[::-1, ::-1], mode="full")
+    return fold(z, h)
 
 
 def shift(d: int, n: int) -> np.ndarray:
@@ -95,13 +163,14 @@ def shift(d: int, n: int) -> np.ndarray:
 
 
 def dense_matrix(psf: np.ndarray, n: int) -> np.ndarray:
-    """The N x N matrix of A in the column-major vec ordering (tiny n)."""
+    """The N x N matrix of A in the column-major vec ordering (tiny n); any
+    PSF with K <= n."""
     N = n * n
     a = np.zeros((N, N))
     for q in range(N):
         e = np.zeros(N)
         e[q] = 1.0
-        a[:, q] = blur(psf, e.reshape((n, n), order="F")).reshape(N, order="F")
+        a[:, q] = blur_general(psf, e.reshape((n, n), order="F")).reshape(N, order="F")
     return a
 
 
@@ -164,8 +233,9 @@ def kp_profiles(psf: np.ndarray):
 
 def kp_svd(psf: np.ndarray, n: int) -> kpmod.KPSVD:
     """Reflexive factors A_c = R(c), A_r = R(a) and their FP64 SVDs;
-    A_hat X = A_c X A_r^T as for the zero boundary."""
-    _check(psf, n)
+    A_hat X = A_c X A_r^T as for the zero boundary.  Any PSF with K <= n
+    (the factors are non-symmetric when the profiles are not even)."""
+    _check(psf, n, symmetric=False)
     c, a, s = kp_profiles(psf)
     ac = reflexive_band(c, n)
     ar = reflexive_band(a, n)
@@ -211,3 +281,62 @@ class NormalOperator:
 
     def H(self, x):
         return self.At(self.A(x)) + self.lam * self.lam * x
+
+
+class NormalOperatorGeneral:
+    """H_lambda = A^T A + lambda^2 I for the reflexive boundary and any PSF
+    (K <= n), interface of solvers.NormalOperator: the definitions for
+    n <= 64, their FFT forms above."""
+
+    def __init__(self, psf: np.ndarray, n: int, lam: float, use_fft: bool | None = None):
+        _check(psf, n, symmetric=False)
+        self.psf, self.n, self.lam = psf, n, float(lam)
+        self.use_fft = n > 64 if use_fft is None else use_fft
+
+    def A(self, x):
+        return blur_fft_general(self.psf, x) if self.use_fft else blur_general(self.psf, x)
+
+    def At(self, y):
+        return blur_t_fft_general(self.psf, y) if self.use_fft else blur_t_general(self.psf, y)
+
+    def H(self, x):
+        return self.At(self.A(x)) + self.lam * self.lam * x
+
+
+def x_lambda_dense_general(psf: np.ndarray, b: np.ndarray, lam: float) -> np.ndarray:
+    """The Tikhonov minimiser by a dense Cholesky solve of eq. (tik:normal2)
+    (tiny n)."""
+    import scipy.linalg
+    b = np.asarray(b, dtype=np.float64)
+    n = b.shape[0]
+    a = dense_matrix(psf, n)
+    h = a.T @ a + lam * lam * np.eye(n * n)
+    rhs = a.T @ b.reshape(-1, order="F")
+    return scipy.linalg.cho_solve(scipy.linalg.cho_factor(h), rhs).reshape((n, n), order="F")
+
+
+def x_lambda_general(psf: np.ndarray, b: np.ndarray, lam: float, tol: float = 1e-13,
+                     maxit: int = 20000, check: bool = True):
+    """x_lambda for any PSF under the reflexive boundary: FP64 PCG with the
+    one-term reflexive KP preconditioner to a true relative residual of
+    `tol`; with `check`, a run at a 100x looser tolerance must agree to
+    1e-7 relative (else ValueError).  Returns (x, info dict)."""
+    from . import solvers as sv
+    b = np.asarray(b, dtype=np.float64)
+    n = b.shape[0]
+    op = NormalOperatorGeneral(psf, n, lam)
+    kp = kp_svd(psf, n)
+
+    def pre(r):
+        return kpmod.precond_solve(kp, lam, r)
+    out = sv.solve(op, b, mode=sv.PCG, tol=tol, maxit=maxit, precond=pre)
+    c = op.At(b)
+    info = {"iters": out.iters, "status": out.status,
+            "true_relres": float(np.linalg.norm(c - op.H(out.x)) / np.linalg.norm(c))}
+    if check:
+        loose = sv.solve(op, b, mode=sv.PCG, tol=tol * 100, maxit=maxit, precond=pre)
+        agree = float(np.linalg.norm(loose.x - out.x) / np.linalg.norm(out.x))
+        info["loose_agreement"] = agree
+        if agree > 1e-7:
+            raise ValueError(f"x_lambda not settled: loose vs tight differ by {agree:.2e}")
+    return out.x, info

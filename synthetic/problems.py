@@ -272,6 +272,20 @@ def large_moffat_reflexive(seed: int = 0, n: int = 1024, k: int = 63) -> Problem
                         reflexive=True)
 
 
+def large_moffat_motion_reflexive(seed: int = 0, n: int = 1024, k: int = 63) -> Problem:
+    """The large Moffat + motion workload of large_moffat (same seed, image
+    and PSF draws; the PSF is not symmetric) with reflexive data: the image
+    extended by half-sample reflection (K <= n), 2% noise."""
+    rng = np.random.default_rng(seed)
+    x = true_image(rng, n)
+    alpha = rng.uniform(3.0, 8.0)
+    length = rng.uniform(3.0, 9.0)
+    angle = rng.uniform(0.0, math.pi)
+    psf = psf_moffat_motion(k, alpha, 2.5, length, angle)
+    return make_problem(n, psf, rng, 0.02, None, seed, "moffat63-motion-reflexive", x_true=x,
+                        reflexive=True)
+
+
 BATCH_SIZES = (128, 256, 384, 512, 768, 1024)
 
 

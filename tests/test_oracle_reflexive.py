@@ -131,3 +131,98 @@ def test_reflexive_data_generator_matches_oracle_blur():
     assert RB.is_symmetric_psf(p.psf, rel=0.0)
     noise = p.b.astype(np.float64) - RB.blur(p.psf, p.x_true)
     assert abs(np.linalg.norm(noise) - p.noise_norm) < 1e-9 * p.noise_norm
+
+
+# ---- PSFs that are not symmetric: A by the definition, A^T by scattering
+
+
+def _asym_psf(rng, k):
+    p = rng.uniform(0, 1, (k, k))
+    return p / p.sum()
+
+
+@pytest.mark.parametrize("n,k", [(8, 3), (9, 5), (16, 15), (12, 11), (7, 7)])
+def test_general_blur_equals_scipy_reflect(n, k):
+    rng = np.random.default_rng(n * 31 + k)
+    psf = _asym_psf(rng, k)
+    x = rng.standard_normal((n, n))
+    ref = scipy.ndimage.convolve(x, psf, mode="reflect")
+    assert np.abs(RB.blur_general(psf, x) - ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("n,k", [(6, 5), (7, 3), (9, 9), (10, 7)])
+def test_general_adjoint_is_dense_transpose(n, k):
+    """A^T by scattering equals the transpose of the dense A built column by
+    column from the definition, and A is not symmetric for these PSFs."""
+    rng = np.random.default_rng(n * 7 + k)
+    psf = _asym_psf(rng, k)
+    a = RB.dense_matrix(psf, n)
+    assert np.abs(a - a.T).max() > 1e-3
+    y = rng.standard_normal((n, n))
+    want = (a.T @ y.reshape(-1, order="F")).reshape((n, n), order="F")
+    assert np.abs(RB.blur_t_general(psf, y) - want).max() < 1e-13
+    # and for the symmetric PSFs A^T = A
+    sym = _sym_psf(rng, k)
+    assert np.abs(RB.blur_t_general(sym, y) - RB.blur(sym, y)).max() < 1e-13
+
+
+@pytest.mark.parametrize("n,k", [(16, 15), (40, 9), (33, 31), (64, 63)])
+def test_general_fft_forms_equal_definitions(n, k):
+    rng = np.random.default_rng(n + 3 * k)
+    psf = _asym_psf(rng, k)
+    x = rng.standard_normal((n, n))
+    y = rng.standard_normal((n, n))
+    ax = RB.blur_general(psf, x)
+    aty = RB.blur_t_general(psf, y)
+    assert np.abs(RB.blur_fft_general(psf, x) - ax).max() < 1e-12 * np.abs(ax).max()
+    assert np.abs(RB.blur_t_fft_general(psf, y) - aty).max() < 1e-12 * np.abs(aty).max()
+    # adjointness at this size
+    assert abs(np.sum(ax * y) - np.sum(x * aty)) < 1e-11 * np.abs(ax).sum()
+
+
+def test_general_kp_expansion_and_separable_exactness():
+    """Every term of the plain PSF SVD gives A exactly for an asymmetric
+    PSF, and the one-term reflexive KP is exact for a separable one."""
+    rng = np.random.default_rng(21)
+    n, k = 12, 7
+    psf = _asym_psf(rng, k)
+    x = rng.standard_normal((n, n))
+    u, s, vt = np.linalg.svd(psf)
+    full = sum(RB.reflexive_band(np.sqrt(s[i]) * u[:, i], n) @ x
+               @ RB.reflexive_band(np.sqrt(s[i]) * vt[i, :], n).T for i in range(k))
+    assert np.abs(full - RB.blur_general(psf, x)).max() < 1e-12
+    sep = np.outer(rng.uniform(0, 1, k), rng.uniform(0, 1, k))
+    kp = RB.kp_svd(sep, n)
+    assert np.abs(KP.kp_apply(kp, x) - RB.blur_general(sep, x)).max() < 1e-12
+
+
+def test_general_x_lambda_equals_dense_solve():
+    """The settled FP64 PCG minimiser equals a dense Cholesky solve, and
+    the one-term KP preconditioner is exact (one iteration) for a separable
+    asymmetric PSF."""
+    rng = np.random.default_rng(22)
+    n, k, lam = 12, 5, 0.05
+    psf = _asym_psf(rng, k)
+    b = rng.standard_normal((n, n))
+    xd = RB.x_lambda_dense_general(psf, b, lam)
+    x, info = RB.x_lambda_general(psf, b, lam)
+    assert info["status"] == "converged" and info["true_relres"] < 1e-12
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-11
+    sep = np.outer(rng.uniform(0, 1, k), rng.uniform(0, 1, k))
+    sep /= sep.sum()
+    _, info = RB.x_lambda_general(sep, b, lam, tol=1e-10, check=False)
+    assert info["iters"] == 1
+
+
+def test_general_reflexive_data_generator_matches_oracle_blur():
+    import synthetic as S
+    from synthetic.problems import _blur_for_data_reflexive
+    rng = np.random.default_rng(23)
+    for n, k in ((40, 9), (33, 15)):
+        psf = _asym_psf(rng, k)
+        x = rng.standard_normal((n, n))
+        assert np.abs(_blur_for_data_reflexive(psf, x) - RB.blur_general(psf, x)).max() < 1e-10
+    p = S.large_moffat_motion_reflexive(0, n=96, k=15)
+    assert not RB.is_symmetric_psf(p.psf)
+    noise = p.b.astype(np.float64) - RB.blur_general(p.psf, p.x_true)
+    assert abs(np.linalg.norm(noise) - p.noise_norm) < 1e-9 * p.noise_norm
