@@ -46,8 +46,10 @@ extern "C" {
 #define KP_ERR_ARG         -1   /* null pointer, n < 1, K even, K > 2n-1,
                                    lambda <= 0, tol <= 0, maxit < 1, a
                                    non-finite argument, bad mode bits      */
-#define KP_ERR_UNSUPPORTED -2   /* unknown boundary condition, or K above
-                                   KP_MAX_PSF                              */
+#define KP_ERR_UNSUPPORTED -2   /* unknown boundary condition, K above
+                                   KP_MAX_PSF, or a call the plan's
+                                   operator cannot serve (see
+                                   KP_BC_REFLEXIVE)                        */
 #define KP_ERR_HIP         -3   /* a HIP runtime call failed               */
 #define KP_ERR_WORKSPACE   -4   /* caller workspace smaller than required,
                                    or misaligned                           */
@@ -60,10 +62,16 @@ extern "C" {
                                    K <= n); one-term KP with circulant
                                    factors                                 */
 #define KP_BC_REFLEXIVE 2       /* image extended by half-sample
-                                   reflection, K <= n, for PSFs symmetric
-                                   in both axes (then A = A^T; other PSFs:
-                                   KP_ERR_UNSUPPORTED); reflexive
-                                   (Toeplitz-plus-Hankel) factors          */
+                                   reflection, K <= n; reflexive
+                                   (Toeplitz-plus-Hankel) factors.  For a
+                                   PSF symmetric in both axes A^T = A is the
+                                   same blur; for any other A^T is the
+                                   correlation over [-h, n+h) folded back
+                                   onto the image, applied by FFTs only:
+                                   such a plan's solves use KP_NORMAL_FFT
+                                   and tol >= 1e-7, and the FP64 normal
+                                   operator, the direct normal form and
+                                   batched solves give KP_ERR_UNSUPPORTED  */
 #define KP_SETUP_LOWP   0x100   /* flag OR-ed into kp_setup's bc: reduced-
                                    precision construction of S, V_r, V_c
                                    (Section 3 leaves computing them in half
@@ -210,7 +218,9 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t *out);
  * recomputed whenever the recurrence residual has fallen 1000x since the
  * last recomputation and before convergence is declared, and replaces the
  * recurrence residual: b - A x is accumulated in FP64, A^T of it on the
- * FP32-class blur for tol >= 1e-7 and in FP64 below.  Later recomputations
+ * FP32-class blur for tol >= 1e-7 and in FP64 below (a reflexive plan whose
+ * PSF is not symmetric: by FFTs, tol < 1e-7 gives KP_ERR_UNSUPPORTED).
+ * Later recomputations
  * add H (x - x_a) to the last true residual at x_a (FP32 matvecs on the step,
  * FP64 sums) once that residual is below 1e-2 ||A^T b||.
  *
@@ -275,7 +285,8 @@ int discrepancy_lambda(kp_plan_t plan, const float *b, const double *grid,
  * one launch over the tiles of all items still iterating; each item stops
  * on its own (converged, maxit, breakdown).  infos[i] receives item i's
  * outcome, including its data misfit ||A x - b||.  Plans of every boundary
- * condition may be mixed.
+ * condition may be mixed; a reflexive plan whose PSF is not symmetric gives
+ * KP_ERR_UNSUPPORTED (the batched matvecs are direct blurs).
  *
  *   plans, nplans   array of plan handles and its length
  *   b, x            arrays of nitems device pointers (FP32 n_i x n_i, 16-byte
@@ -456,11 +467,14 @@ const char *kp_strerror(int status);
 /* ---- operator-level entry points (used by the parity tests) ---------- */
 
 /* y = A x (transpose = 0) or y = A^T x (transpose = 1); FP32 in and out,
-   FP32 accumulation.  x and y must not alias. */
+   FP32 accumulation (A^T of a reflexive plan whose PSF is not symmetric:
+   the folded correlation by FFTs, as KP_NORMAL_FFT's last passes).  x and y
+   must not alias. */
 int kp_blur(kp_plan_t plan, const float *x, float *y, int transpose,
             void *stream);
 
-/* y = (A^T A + lambda^2 I) x with FP64 accumulation; y is FP64 (device). */
+/* y = (A^T A + lambda^2 I) x with FP64 accumulation; y is FP64 (device).
+   KP_ERR_UNSUPPORTED for a reflexive plan whose PSF is not symmetric. */
 int kp_normal_fp64(kp_plan_t plan, const float *x, double lambda, double *y,
                    void *stream);
 
@@ -497,14 +511,21 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int *prev);
  *    the smallest even 2,3,5,7-smooth size >= n + (K-1)/2 and Hc the L x L
  *    DFT of the PSF wrapped around the origin, A p = crop(IDFT(Hc .*
  *    DFT(pad p))) and A^T q = crop(IDFT(conj(Hc) .* DFT(pad q))) on the
- *    n x n window (exact: every wrapped tap lands in the zero pad).  Five
- *    passes of one-workgroup-per-line Stockham FFTs in LDS; FP32 with the
- *    PSF spectrum and twiddles computed in FP64.
+ *    n x n window (exact: every wrapped tap lands in the zero pad).  For
+ *    the reflexive boundary p is first extended by h = (K-1)/2 reflected
+ *    rows and columns per side (L >= n + K - 1), and A^T q is the
+ *    correlation over [-h, n+h)^2 with the outer h-wide frame folded back
+ *    onto its mirror images.  Five passes of one-workgroup-per-line
+ *    Stockham FFTs in LDS; FP32 with the PSF spectrum and twiddles
+ *    computed in FP64.
  * kp_setup times both on the plan and the solver uses the faster.  The FFT
- * form applies the zero boundary's operator: it is offered for KP_BC_ZERO
- * plans only (others: direct; forcing FFT gives KP_ERR_UNSUPPORTED).
+ * form is offered for KP_BC_ZERO and KP_BC_REFLEXIVE plans (periodic:
+ * direct; forcing FFT gives KP_ERR_UNSUPPORTED); a reflexive plan whose
+ * PSF is not symmetric has the FFT form only (forcing direct gives
+ * KP_ERR_UNSUPPORTED).
  * kp_set_normal_op forces a form for pcg_solve's iterations (true residuals
- * stay on the blurs); kp_normal computes y = H x with the plan's form
+ * stay on the blurs, but for the FFT A^T of a reflexive plan whose PSF is
+ * not symmetric); kp_normal computes y = H x with the plan's form
  * (KP_NORMAL_PLAN) or a given one, into the FP32 device image y (x and y
  * must differ; the direct form uses the plan's scratch vector); it
  * synchronises.  kp_time_normal: mean time of `reps` back-to-back

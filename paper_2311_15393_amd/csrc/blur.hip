@@ -92,6 +92,12 @@ static hipError_t blur_dispatch(int cfg, const Plan& P, const float* src, const 
 
 hipError_t launch_blur_f32(const Plan& P, const float* src, float* dst, bool transpose,
                            hipStream_t s, const Ctrl* ctrl) {
+  if (transpose && P.refl_general) {
+    // the reflexive A^T of a PSF that is not symmetric is no blur: the
+    // folded correlation by FFTs (no control-block test)
+    if (ctrl) return hipErrorInvalidValue;
+    return launch_fft_at(P, src, dst, s);
+  }
   EpiStoreF32 e{dst, P.n};
   int nb;
   return blur_dispatch(P.blur_cfg, P, src, transpose ? P.taps32 : P.taps32_flip, e,
@@ -168,10 +174,13 @@ hipError_t autotune_normal(Plan& P, hipStream_t s) {
     return err;
   }
   const float lam2 = 1e-4f;
-  // the FFT form applies the zero boundary's operator only
-  const int nops = P.bc == KP_BC_ZERO ? 2 : 1;
-  P.normal_times[1] = 0.f;
-  for (int op = 0; op < nops && err == hipSuccess; ++op) {
+  // the FFT form covers the zero and reflexive boundaries; with a PSF that
+  // is not symmetric the reflexive A^T is no blur and the FFT form is the
+  // only one
+  const int op0 = P.refl_general ? 1 : 0;
+  const int nops = (P.bc == KP_BC_ZERO || P.bc == KP_BC_REFLEXIVE) ? 2 : 1;
+  P.normal_times[0] = P.normal_times[1] = 0.f;
+  for (int op = op0; op < nops && err == hipSuccess; ++op) {
     auto run = [&]() {
       int nb;
       return op == 0 ? launch_normal_direct(P, P.p, P.w, lam2, s, &nb)
@@ -188,11 +197,14 @@ hipError_t autotune_normal(Plan& P, hipStream_t s) {
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  P.normal_op = (err == hipSuccess && nops == 2 && P.normal_times[1] < P.normal_times[0]) ? 1 : 0;
+  P.normal_op = P.refl_general ? 1
+                : (err == hipSuccess && nops == 2 && P.normal_times[1] < P.normal_times[0]) ? 1
+                                                                                          : 0;
   return err;
 }
 
 hipError_t launch_rhs(const Plan& P, const float* b, bool zero_x, hipStream_t s) {
+  if (P.refl_general) return launch_fft_rhs(P, b, zero_x, s);
   EpiRhs e{P.r, P.n, P.p, P.w, zero_x ? P.x64 : nullptr};
   int nb;
   hipError_t err = blur_dispatch(P.blur_cfg, P, b, P.taps32, e, P.ctrl, 0, s, &nb);
@@ -217,6 +229,12 @@ hipError_t launch_true_residual(const Plan& P, const float* b, const double* x, 
     err = run_blur<KP_F64IN_CFG, double, double, double>(P, x, P.taps64_flip, e1, P.ctrl, 0, s);
   }
   if (err != hipSuccess) return err;
+  if (P.refl_general) {
+    // A^T of the reflexive boundary with a PSF that is not symmetric: the
+    // folded correlation by FFTs, on u in q (the solver refuses TR_FP64)
+    if (!fast) return hipErrorInvalidValue;
+    return launch_fft_true_res(P, lam2, fin, s);
+  }
   EpiTrueRes e2{x, P.r, lam2, P.n, P.xa64, P.ra64};
   int nb;
   if (fast) {
@@ -230,6 +248,7 @@ hipError_t launch_true_residual(const Plan& P, const float* b, const double* x, 
 }
 
 hipError_t launch_anchor_residual(const Plan& P, double lam2, bool fin, hipStream_t s) {
+  if (P.refl_general) return launch_fft_anchor_residual(P, lam2, fin, s);
   // q = fp32(x - x_a), z = A q, r = r_a - A^T z - lam2 (x - x_a)
   hipError_t err = launch_diff32(P, P.q, s);
   if (err != hipSuccess) return err;

@@ -82,11 +82,15 @@ size_t layout(int n, int k, char* base, Plan* P, char** scratch = nullptr) {
   Q.VrT8s = b.take<uint8_t>(nsc);
   Q.UcT32 = b.take<float>(nn);
   Q.UrT32 = b.take<float>(nn);
-  const int fL = fft_length(n, k), fF = fL / 2 + 1;
+  // FFT tables and work arrays sized for the longer (reflexive) length; the
+  // zero boundary's length is the default, kp_setup sets the plan's own
+  const int fL = fft_length(n, k);
+  const int fLm = fft_length_reflexive(n, k), fFm = fLm / 2 + 1;
+  const int hh = (k - 1) / 2;
   Q.fft_L = fL;
   Q.fft_nrad = fft_radices(fL, Q.fft_rad);
-  Q.fft_tw = b.take<float2>((size_t)fL);
-  Q.fft_Ht = b.take<float2>((size_t)fF * fL);
+  Q.fft_tw = b.take<float2>((size_t)fLm);
+  Q.fft_Ht = b.take<float2>((size_t)fFm * fLm);
   Q.spec = b.take<double>((((nn * sizeof(float)) + ALIGN - 1) / ALIGN * ALIGN) / sizeof(double) +
                           128 + 2 * 64 * 256);
   Q.ctrl = b.take<Ctrl>(1);
@@ -113,8 +117,8 @@ size_t layout(int n, int k, char* base, Plan* P, char** scratch = nullptr) {
   Q.t3s = b.take<uint8_t>(nsc);
   Q.rs = b.take<uint8_t>(nsc);
   Q.r8 = b.take<uint8_t>(nn);
-  Q.fft_S = b.take<float2>((size_t)n * fF);
-  Q.fft_T = b.take<float2>((size_t)n * fF);
+  Q.fft_S = b.take<float2>((size_t)(n + 2 * hh) * fFm);   // n + 2h row slots (reflexive)
+  Q.fft_T = b.take<float2>((size_t)n * fFm);
   (void)Q;
   const size_t vec_end = (b.cur + ALIGN - 1) / ALIGN * ALIGN;
   const size_t scr = setup_scratch_bytes(n, k);
@@ -254,9 +258,10 @@ int kp_setup(const double* psf, int k, int n, int bc_flags, void* workspace, siz
   // periodic: the PSF would wrap onto itself; reflexive: one reflection
   // must cover every index
   if (bc != KP_BC_ZERO && k > n) return KP_ERR_ARG;
+  bool refl_general = false;
   if (bc == KP_BC_REFLEXIVE) {
-    // A^T = A (and the blur of A^T equals that of A) needs a PSF symmetric
-    // in both axes
+    // A^T = A (and the blur of A^T equals that of A) for PSFs symmetric in
+    // both axes; for the others A^T is applied by the FFT form
     double mx = 0.0, asym = 0.0;
     for (int i = 0; i < k * k; ++i) mx = std::fmax(mx, std::fabs(psf[i]));
     for (int a = 0; a < k; ++a)
@@ -264,7 +269,7 @@ int kp_setup(const double* psf, int k, int n, int bc_flags, void* workspace, siz
         asym = std::fmax(asym, std::fabs(psf[a * k + b] - psf[(k - 1 - a) * k + b]));
         asym = std::fmax(asym, std::fabs(psf[a * k + b] - psf[a * k + (k - 1 - b)]));
       }
-    if (asym > 1e-12 * mx) return KP_ERR_UNSUPPORTED;
+    refl_general = asym > 1e-12 * mx;
   }
   for (int i = 0; i < k * k; ++i)
     if (!std::isfinite(psf[i])) return KP_ERR_ARG;
@@ -277,6 +282,7 @@ int kp_setup(const double* psf, int k, int n, int bc_flags, void* workspace, siz
   P.k = k;
   P.bc = bc;
   P.lowp = (bc_flags & KP_SETUP_LOWP) != 0;
+  P.refl_general = refl_general;
   P.kq = (k + TAP_CHUNK - 1) / TAP_CHUNK * TAP_CHUNK;
   const size_t need = layout(n, k, nullptr, nullptr);
   if (need == 0) {
@@ -302,6 +308,11 @@ int kp_setup(const double* psf, int k, int n, int bc_flags, void* workspace, siz
   P.bytes = need;
   char* scratch = nullptr;
   layout(n, k, base, &P, &scratch);
+  if (bc == KP_BC_REFLEXIVE) {
+    // the reflexive FFT form transforms the image extended by h per side
+    P.fft_L = fft_length_reflexive(n, k);
+    P.fft_nrad = fft_radices(P.fft_L, P.fft_rad);
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&P.host_ctrl), 2 * sizeof(Ctrl)) != hipSuccess) {
     if (P.owns) hipFree(base);
     delete h;
@@ -611,6 +622,9 @@ int pcg_solve(kp_plan_t plan, const float* b, double lambda, double tol, int max
                 KP_HIST)) != 0)
     return KP_ERR_ARG;
   Plan& P = plan->P;
+  // with a PSF that is not symmetric under the reflexive boundary, A^T runs
+  // by FFTs in FP32 only: no FP64 true residual for the tightest tolerances
+  if (P.refl_general && tol < TR_FAST_TOL) return KP_ERR_UNSUPPORTED;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (!P.ev_start) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -697,6 +711,9 @@ static int batched_args(const kp_plan_t* plans, int nplans, const int* plan_of_i
     if (!plans[i]) return KP_ERR_ARG;
     ps[i] = &plans[i]->P;
   }
+  // the batched matvecs are direct blurs: A^T must be one
+  for (int i = 0; i < nplans; ++i)
+    if (ps[i]->refl_general) return KP_ERR_UNSUPPORTED;
   for (int i = 0; i < nitems; ++i)
     if (plan_of_item[i] < 0 || plan_of_item[i] >= nplans) return KP_ERR_ARG;
   return KP_OK;
@@ -842,6 +859,7 @@ int kp_blur(kp_plan_t plan, const float* x, float* y, int transpose, void* strea
 
 int kp_normal_fp64(kp_plan_t plan, const float* x, double lambda, double* y, void* stream) {
   if (!plan || !x || !y || !(lambda >= 0.0) || !std::isfinite(lambda)) return KP_ERR_ARG;
+  if (plan->P.refl_general) return KP_ERR_UNSUPPORTED;     // its A^T is no FP64 blur
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIPCHK(launch_normal_fp64(plan->P, x, lambda * lambda, y, s));
   HIPCHK(hipEventRecord(plan->P.ev_last, s));
@@ -940,9 +958,16 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int* prev) {
 // its stream), so the getters wait for nothing else: they copy on the
 // device's auxiliary stream (non-blocking, so the copies neither wait for
 // nor hold up other streams) and wait for those copies only.
+// The forms of H p a plan can use: the FFT form for the zero and reflexive
+// boundaries; the direct blurs unless A^T is not a blur (refl_general).
+static bool normal_op_valid(const Plan& P, int op) {
+  if (op == KP_NORMAL_FFT) return P.bc == KP_BC_ZERO || P.bc == KP_BC_REFLEXIVE;
+  return !P.refl_general;
+}
+
 int kp_set_normal_op(kp_plan_t plan, int op, int* prev) {
   if (!plan || (op != KP_NORMAL_DIRECT && op != KP_NORMAL_FFT)) return KP_ERR_ARG;
-  if (op == KP_NORMAL_FFT && plan->P.bc != KP_BC_ZERO) return KP_ERR_UNSUPPORTED;
+  if (!normal_op_valid(plan->P, op)) return KP_ERR_UNSUPPORTED;
   if (prev) *prev = plan->P.normal_op;
   plan->P.normal_op = op;
   return KP_OK;
@@ -965,7 +990,7 @@ int kp_normal(kp_plan_t plan, const float* x, double lambda, float* y, int op, v
     return KP_ERR_ARG;
   Plan& P = plan->P;
   if (x == P.q || y == P.q) return KP_ERR_ARG;
-  if (op == KP_NORMAL_FFT && P.bc != KP_BC_ZERO) return KP_ERR_UNSUPPORTED;
+  if (!normal_op_valid(P, op == KP_NORMAL_PLAN ? P.normal_op : op)) return KP_ERR_UNSUPPORTED;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIPCHK(normal_op_launch(P, x, y, (float)(lambda * lambda),
                           op == KP_NORMAL_PLAN ? P.normal_op : op, s));
@@ -980,7 +1005,7 @@ int kp_time_normal(kp_plan_t plan, const float* x, float* y, int op, int reps, f
     return KP_ERR_ARG;
   Plan& P = plan->P;
   const int which = op == KP_NORMAL_PLAN ? P.normal_op : op;
-  if (which == KP_NORMAL_FFT && P.bc != KP_BC_ZERO) return KP_ERR_UNSUPPORTED;
+  if (!normal_op_valid(P, which)) return KP_ERR_UNSUPPORTED;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));

@@ -275,9 +275,10 @@ __device__ inline double beta_of(const Ctrl* c, double rz, double zw, bool* ok) 
   return -zw / c->delta;
 }
 
-// FFT normal operator limits: L <= 2100 for n <= 2048, K <= 63
+// FFT normal operator limits: L <= 2304 for n <= 2048, K <= 63 (zero
+// boundary n + h, reflexive n + 2h, rounded up to a 7-smooth length)
 constexpr int FFT_MAX_RADICES = 12;
-constexpr int FFT_MAX_L = 2100;
+constexpr int FFT_MAX_L = 2304;
 
 // ---------------------------------------------------------------------------
 // plan
@@ -285,6 +286,9 @@ constexpr int FFT_MAX_L = 2100;
 struct Plan {
   int n = 0, k = 0, kq = 0;       // kq: PSF row length padded to the tap chunk
   int bc = KP_BC_ZERO;            // boundary condition of A (KP_BC_ZERO / KP_BC_PERIODIC)
+  bool refl_general = false;      // reflexive boundary with a PSF not symmetric in both
+                                  // axes: A^T is not the blur, so H p, A^T b and the
+                                  // true residuals' A^T go through the FFT form
   bool lowp = false;              // KP_SETUP_LOWP: factors rounded to FP16, FP32 SVDs
   bool owns = false;
   void* base = nullptr;
@@ -476,7 +480,16 @@ int fft_radices(int L, int* rad);
 hipError_t build_fft_tables(const Plan& P, const double* psf_dev, void* g_scratch,
                             hipStream_t s);
 hipError_t launch_fft_normal(const Plan& P, const float* p, float* w, float lam2, hipStream_t s,
-                             int* nb, const Ctrl* ctrl);
+                             int* nb, const Ctrl* ctrl, bool with_partials = true);
+// A^T u alone by FFTs into out (the reflexive boundary's A^T for any PSF)
+hipError_t launch_fft_at(const Plan& P, const float* u, float* out, hipStream_t s);
+// the right-hand side, the true residual from u = b - A x in P.q, and the
+// anchored true residual with their A^T (or A^T A) by FFTs (plans whose A^T
+// is not a blur: refl_general)
+hipError_t launch_fft_rhs(const Plan& P, const float* b, bool zero_x, hipStream_t s);
+hipError_t launch_fft_true_res(const Plan& P, double lam2, bool fin, hipStream_t s);
+hipError_t launch_fft_anchor_residual(const Plan& P, double lam2, bool fin, hipStream_t s);
+int fft_length_reflexive(int n, int k);
 // w = A^T A p + lam2 p on the plan's direct blurs (A p into P.q)
 hipError_t launch_normal_direct(const Plan& P, const float* p, float* w, float lam2,
                                 hipStream_t s, int* nb);

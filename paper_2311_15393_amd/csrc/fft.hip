@@ -30,7 +30,7 @@
 // twiddles from an FP32 table of exp(-2 pi i t / L) built in FP64.
 #include <cmath>
 
-#include "common.h"
+#include "blur_core.h"
 
 namespace kpcg {
 
@@ -40,7 +40,11 @@ struct FftGeom {
   int n, L, F, nrad;
   int rad[FFT_MAX_RADICES];
   const float2* tw;                     // exp(-2 pi i t / L), t < L
+  int refl, h;                          // reflexive boundary; PSF half-width
 };
+
+// half-sample reflection of an index in [-n, 2n)
+__device__ inline int refl_index(int q, int n) { return q < 0 ? -q - 1 : (q >= n ? 2 * n - 1 - q : q); }
 
 __device__ inline float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -224,25 +228,35 @@ struct TwStage {
   }
 };
 
+// Row pass of the forward transform.  Plain (ext = 0): rows 0 .. n-1 of p,
+// zero-padded to L.  Extended (ext = 1, reflexive boundary): the image
+// extended by half-sample reflection over the rows and columns [-h, n+h):
+// row slot s of S holds image row refl(s - h), and a column index j in
+// [-h, 0) sits at the circular position L + j.
 __global__ __launch_bounds__(FT) void fft_rows_fwd_kernel(const float* __restrict__ p, FftGeom g,
-                                                          float2* __restrict__ S,
+                                                          int ext, float2* __restrict__ S,
                                                           const Ctrl* ctrl) {
   if (fft_skip(ctrl)) return;
   extern __shared__ float2 fft_lds[];
   float2* a = fft_lds;
   float2* b = fft_lds + g.L;
   float2* tw = fft_lds + 2 * g.L;
-  const int n = g.n, L = g.L, ra = 2 * blockIdx.x, rb = ra + 1;
+  const int n = g.n, L = g.L, h = ext ? g.h : 0;
+  const int rows = n + 2 * h, ra = 2 * blockIdx.x, rb = ra + 1;
+  const int sa = ext ? refl_index(ra - h, n) : ra;
+  const int sb = rb < rows ? (ext ? refl_index(rb - h, n) : rb) : -1;
   TwStage ts;
   ts.load(g.tw, L);
   float2 v[FE];
 #pragma unroll
   for (int e = 0; e < FE; ++e) {
-    const int j = threadIdx.x + e * FT;
+    const int c = threadIdx.x + e * FT;
     v[e] = make_float2(0.f, 0.f);
-    if (j < n) {
-      v[e].x = p[(size_t)ra * n + j];
-      if (rb < n) v[e].y = p[(size_t)rb * n + j];
+    const int j = c >= L - h ? c - L : c;          // column of circular position c
+    if (c < L && j >= -h && j < n + h) {
+      const int jj = ext ? refl_index(j, n) : j;
+      v[e].x = p[(size_t)sa * n + jj];
+      if (sb >= 0) v[e].y = p[(size_t)sb * n + jj];
     }
   }
   ts.store(tw, L);
@@ -253,7 +267,7 @@ __global__ __launch_bounds__(FT) void fft_rows_fwd_kernel(const float* __restric
   }
   __syncthreads();
   const float2* Z = fft_line(a, b, tw, g);
-  split_store(Z, L, g.F, S + (size_t)ra * g.F, rb < n ? S + (size_t)rb * g.F : nullptr);
+  split_store(Z, L, g.F, S + (size_t)ra * g.F, sb >= 0 ? S + (size_t)rb * g.F : nullptr);
 }
 
 // Columns: consecutive workgroups go to different XCDs (round robin), so the
@@ -265,9 +279,17 @@ __device__ inline int xcd_column(int bid, int F) {
   return k;
 }
 
+// Column pass: the column k of S (its in_rows row slots, slot s at the
+// circular row position s - in_off, the rest zero), its transform times the
+// PSF spectrum (or its conjugate), the inverse; rows 0 .. n-1 kept, or with
+// fold (the correlation of the reflexive boundary's A^T) the rows [-h, n+h)
+// folded onto the image by the reflection: row a gains rows -1-a (circular
+// L-1-a, for a < h) and 2n-1-a (for a >= n-h).
 __global__ __launch_bounds__(FT) void fft_cols_kernel(const float2* __restrict__ S, FftGeom g,
+                                                      int in_rows, int in_off,
                                                       const float2* __restrict__ Ht, int conjH,
-                                                      float2* __restrict__ T, const Ctrl* ctrl) {
+                                                      int fold, float2* __restrict__ T,
+                                                      const Ctrl* ctrl) {
   if (fft_skip(ctrl)) return;
   const int k = xcd_column(blockIdx.x, g.F);
   if (k >= g.F) return;
@@ -278,15 +300,16 @@ __global__ __launch_bounds__(FT) void fft_cols_kernel(const float2* __restrict__
   float2* tw = fft_lds + 2 * L;
   TwStage ts;
   ts.load(g.tw, L);
-  // the column (rows n .. L-1 are the zero pad) and the PSF spectrum column
+  // the column and the PSF spectrum column
   const float2* h = Ht + (size_t)k * L;
   float2 v[FE], hv[FE];
 #pragma unroll
   for (int e = 0; e < FE; ++e) {
-    const int i = threadIdx.x + e * FT;
+    const int c = threadIdx.x + e * FT;
     v[e] = make_float2(0.f, 0.f);
-    if (i < n) v[e] = S[(size_t)i * F + k];
-    if (i < L) hv[e] = h[i];
+    const int sl = (c >= L - in_off ? c - L : c) + in_off;   // row slot of circular row c
+    if (c < L && sl >= 0 && sl < in_rows) v[e] = S[(size_t)sl * F + k];
+    if (c < L) hv[e] = h[c];
   }
   ts.store(tw, L);
 #pragma unroll
@@ -310,7 +333,13 @@ __global__ __launch_bounds__(FT) void fft_cols_kernel(const float2* __restrict__
   }
   __syncthreads();
   const float2* y = fft_line(Y, other, tw, g);
-  for (int i = threadIdx.x; i < n; i += FT) T[(size_t)i * F + k] = cconj(y[i]);
+  const int hf = fold ? g.h : 0;
+  for (int i = threadIdx.x; i < n; i += FT) {
+    float2 t = y[i];
+    if (i < hf) t = cadd(t, y[L - 1 - i]);
+    if (i >= n - hf) t = cadd(t, y[2 * n - 1 - i]);
+    T[(size_t)i * F + k] = cconj(t);
+  }
 }
 
 // conj of the full spectrum of x_a + i x_b from the half spectra held in
@@ -376,8 +405,11 @@ __global__ __launch_bounds__(FT) void fft_rows_mid_kernel(const float2* __restri
   split_store(Z, L, F, S + (size_t)ra * F, rb < n ? S + (size_t)rb * F : nullptr);
 }
 
+// Last row pass: the inverse transform of two rows, rows 0 .. n-1 of the
+// result (with fold, the columns [-h, n+h) folded onto the image as in the
+// column pass), plus lambda^2 p and the partials of p . w when p is given.
 __global__ __launch_bounds__(FT) void fft_rows_out_kernel(const float2* __restrict__ T, FftGeom g,
-                                                          const float* __restrict__ p,
+                                                          int fold, const float* __restrict__ p,
                                                           float* __restrict__ w, float lam2,
                                                           double* __restrict__ partials,
                                                           const Ctrl* ctrl) {
@@ -397,7 +429,9 @@ __global__ __launch_bounds__(FT) void fft_rows_out_kernel(const float2* __restri
 #pragma unroll
   for (int e = 0; e < FE; ++e) {
     const int j = threadIdx.x + e * FT;
-    if (j < n) {
+    pa[e] = 0.f;
+    pb[e] = 0.f;
+    if (p != nullptr && j < n) {
       pa[e] = p[(size_t)ra * n + j];
       pb[e] = rb < n ? p[(size_t)rb * n + j] : 0.f;
     }
@@ -406,12 +440,16 @@ __global__ __launch_bounds__(FT) void fft_rows_out_kernel(const float2* __restri
   pack_conj_regs(ta, tb, rb < n, L, F, a);
   __syncthreads();
   const float2* z = fft_line(a, b, tw, g);
+  const int hf = fold ? g.h : 0;
   double d = 0.0;
 #pragma unroll
   for (int e = 0; e < FE; ++e) {
     const int j = threadIdx.x + e * FT;
     if (j < n) {
-      const float2 v = cconj(z[j]);
+      float2 zt = z[j];
+      if (j < hf) zt = cadd(zt, z[L - 1 - j]);
+      if (j >= n - hf) zt = cadd(zt, z[2 * n - 1 - j]);
+      const float2 v = cconj(zt);
       const size_t oa = (size_t)ra * n + j;
       const float wa = fmaf(lam2, pa[e], v.x);
       w[oa] = wa;
@@ -488,6 +526,10 @@ int fft_length(int n, int k) {
   }
 }
 
+// the reflexive boundary's length: the image extended by h on each side
+// convolved with the PSF must not wrap onto the image, L >= n + 2h
+int fft_length_reflexive(int n, int k) { return fft_length(n + (k - 1) / 2, k); }
+
 int fft_radices(int L, int* rad) {
   int m = L, c = 0;
   while (m % 8 == 0) { rad[c++] = 8; m /= 8; }
@@ -506,6 +548,8 @@ static FftGeom geom(const Plan& P) {
   g.nrad = P.fft_nrad;
   for (int i = 0; i < FFT_MAX_RADICES; ++i) g.rad[i] = i < P.fft_nrad ? P.fft_rad[i] : 1;
   g.tw = reinterpret_cast<const float2*>(P.fft_tw);
+  g.refl = P.bc == KP_BC_REFLEXIVE ? 1 : 0;
+  g.h = (P.k - 1) / 2;
   return g;
 }
 
@@ -525,23 +569,118 @@ hipError_t build_fft_tables(const Plan& P, const double* psf_dev, void* g_scratc
 
 size_t fft_lds_bytes(int L) { return (size_t)3 * L * sizeof(float2); }   // a, b, twiddles
 
+// w = A^T A p + lam2 p with the partials of p . w (with_partials).  Zero
+// boundary: the plain passes.  Reflexive boundary: the first row pass
+// extends p by reflection (n + 2h row slots), the first column pass reads
+// them, and the passes of A^T fold the correlation back onto the image.
 hipError_t launch_fft_normal(const Plan& P, const float* p, float* w, float lam2, hipStream_t s,
-                             int* nb, const Ctrl* ctrl) {
+                             int* nb, const Ctrl* ctrl, bool with_partials) {
   const FftGeom g = geom(P);
-  const size_t lds = fft_lds_bytes(g.L);        // <= 3 * FFT_MAX_L * 8 B = 50.4 KB
+  const size_t lds = fft_lds_bytes(g.L);        // <= 3 * FFT_MAX_L * 8 B = 55.3 KB
+  float2* S = reinterpret_cast<float2*>(P.fft_S);
+  float2* T = reinterpret_cast<float2*>(P.fft_T);
+  const float2* Ht = reinterpret_cast<const float2*>(P.fft_Ht);
+  const int ext_rows = g.refl ? g.n + 2 * g.h : g.n;
+  const int rows = (g.n + 1) / 2;
+  const int cols = ((g.F + 7) / 8) * 8;
+  hipLaunchKernelGGL(fft_rows_fwd_kernel, dim3((ext_rows + 1) / 2), dim3(FT), lds, s, p, g,
+                     g.refl, S, ctrl);
+  hipLaunchKernelGGL(fft_cols_kernel, dim3(cols), dim3(FT), lds, s, S, g, ext_rows,
+                     g.refl ? g.h : 0, Ht, 0, 0, T, ctrl);
+  hipLaunchKernelGGL(fft_rows_mid_kernel, dim3(rows), dim3(FT), lds, s, T, g, S, ctrl);
+  hipLaunchKernelGGL(fft_cols_kernel, dim3(cols), dim3(FT), lds, s, S, g, g.n, 0, Ht, 1, g.refl,
+                     T, ctrl);
+  hipLaunchKernelGGL(fft_rows_out_kernel, dim3(rows), dim3(FT), lds, s, T, g, g.refl, p, w, lam2,
+                     with_partials ? P.partials : nullptr, ctrl);
+  if (nb) *nb = rows;
+  return hipGetLastError();
+}
+
+// out = A^T u alone (the last three passes of the normal operator, the row
+// pass on u zero-padded); no control-block test, no partials.
+hipError_t launch_fft_at(const Plan& P, const float* u, float* out, hipStream_t s) {
+  const FftGeom g = geom(P);
+  const size_t lds = fft_lds_bytes(g.L);
   float2* S = reinterpret_cast<float2*>(P.fft_S);
   float2* T = reinterpret_cast<float2*>(P.fft_T);
   const float2* Ht = reinterpret_cast<const float2*>(P.fft_Ht);
   const int rows = (g.n + 1) / 2;
   const int cols = ((g.F + 7) / 8) * 8;
-  hipLaunchKernelGGL(fft_rows_fwd_kernel, dim3(rows), dim3(FT), lds, s, p, g, S, ctrl);
-  hipLaunchKernelGGL(fft_cols_kernel, dim3(cols), dim3(FT), lds, s, S, g, Ht, 0, T, ctrl);
-  hipLaunchKernelGGL(fft_rows_mid_kernel, dim3(rows), dim3(FT), lds, s, T, g, S, ctrl);
-  hipLaunchKernelGGL(fft_cols_kernel, dim3(cols), dim3(FT), lds, s, S, g, Ht, 1, T, ctrl);
-  hipLaunchKernelGGL(fft_rows_out_kernel, dim3(rows), dim3(FT), lds, s, T, g, p, w, lam2,
-                     P.partials, ctrl);
-  if (nb) *nb = rows;
+  hipLaunchKernelGGL(fft_rows_fwd_kernel, dim3(rows), dim3(FT), lds, s, u, g, 0, S,
+                     (const Ctrl*)nullptr);
+  hipLaunchKernelGGL(fft_cols_kernel, dim3(cols), dim3(FT), lds, s, S, g, g.n, 0, Ht, 1, g.refl,
+                     T, (const Ctrl*)nullptr);
+  hipLaunchKernelGGL(fft_rows_out_kernel, dim3(rows), dim3(FT), lds, s, T, g, g.refl,
+                     (const float*)nullptr, out, 0.0f, (double*)nullptr, (const Ctrl*)nullptr);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// A blur epilogue (blur_core.h) applied to a dense n x n result v, element
+// by element, with the per-block partial sums of its reduction: the FFT
+// forms of the right-hand side and of the true residuals use the blurs'
+// epilogues unchanged.
+// ---------------------------------------------------------------------------
+constexpr int EPI_T = 256, EPI_MAXB = 1024;
+
+template <class Epi>
+__global__ __launch_bounds__(EPI_T) void epi_dense_kernel(const float* __restrict__ v, int n,
+                                                          Epi epi, double* __restrict__ partials) {
+  const int N = n * n;
+  double d = 0.0;
+  for (int o = blockIdx.x * EPI_T + threadIdx.x; o < N; o += gridDim.x * EPI_T) {
+    const int i = o / n, j = o - i * n;
+    const float val = v[o];
+    epi.row(i, j, 1, &val, d);
+  }
+  if constexpr (Epi::kReduce) {
+    __shared__ double sh[EPI_T / 64];
+    const double t = block_sum<EPI_T>(d, sh);
+    if (threadIdx.x == 0) partials[Epi::kSlot * MAX_PARTIALS + blockIdx.x] = t;
+  }
+}
+
+template <class Epi>
+static hipError_t epi_dense(const Plan& P, const float* v, Epi epi, hipStream_t s, int* nb) {
+  const int N = P.n * P.n;
+  int b = (N + EPI_T - 1) / EPI_T;
+  b = b > EPI_MAXB ? EPI_MAXB : b;
+  hipLaunchKernelGGL(epi_dense_kernel<Epi>, dim3(b), dim3(EPI_T), 0, s, v, P.n, epi, P.partials);
+  *nb = b;
+  return hipGetLastError();
+}
+
+// r = c = A^T b, ||c||^2 (the SC_RHS step); p = w (= x) = 0: launch_rhs by FFTs
+hipError_t launch_fft_rhs(const Plan& P, const float* b, bool zero_x, hipStream_t s) {
+  hipError_t e = launch_fft_at(P, b, P.q, s);
+  if (e != hipSuccess) return e;
+  int nb;
+  e = epi_dense(P, P.q, EpiRhs{P.r, P.n, P.p, P.w, zero_x ? P.x64 : nullptr}, s, &nb);
+  if (e != hipSuccess) return e;
+  return launch_scalar(P, SC_RHS, nb, s);
+}
+
+// r = A^T u - lam2 x from u = b - A x already in P.q (FP32), with the anchor
+// recorded; A^T u by FFTs into P.z
+hipError_t launch_fft_true_res(const Plan& P, double lam2, bool fin, hipStream_t s) {
+  hipError_t e = launch_fft_at(P, P.q, P.z, s);
+  if (e != hipSuccess) return e;
+  int nb;
+  e = epi_dense(P, P.z, EpiTrueRes{P.x64, P.r, lam2, P.n, P.xa64, P.ra64}, s, &nb);
+  if (e != hipSuccess) return e;
+  return launch_scalar(P, fin ? SC_TRUE : SC_TRUE_INFO, nb, s);
+}
+
+// r = r_a - H (x - x_a) from the anchor, A^T A of fp32(x - x_a) by FFTs
+hipError_t launch_fft_anchor_residual(const Plan& P, double lam2, bool fin, hipStream_t s) {
+  hipError_t e = launch_diff32(P, P.q, s);
+  if (e != hipSuccess) return e;
+  e = launch_fft_normal(P, P.q, P.z, 0.0f, s, nullptr, nullptr, false);
+  if (e != hipSuccess) return e;
+  int nb;
+  e = epi_dense(P, P.z, EpiAnchorRes{P.x64, P.xa64, P.ra64, P.r, lam2, P.n}, s, &nb);
+  if (e != hipSuccess) return e;
+  return launch_scalar(P, fin ? SC_TRUE : SC_TRUE_INFO, nb, s);
 }
 
 }  // namespace kpcg

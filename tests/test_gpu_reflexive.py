@@ -190,14 +190,14 @@ def test_reflexive_exact_diag_and_batch():
 
 
 def test_reflexive_refusals():
-    """A PSF not symmetric in both axes and K > n are refused."""
+    """K > n is refused; a PSF not symmetric in both axes is accepted and
+    takes the FFT form of the normal operator (its A^T is no blur)."""
     require_gpu()
-    from paper_2311_15393_amd import KP_BC_REFLEXIVE, KPError, Plan
-    from paper_2311_15393_amd.kpcg import KP_ERR_ARG, KP_ERR_UNSUPPORTED
+    from paper_2311_15393_amd import KP_BC_REFLEXIVE, KP_NORMAL_FFT, KPError, Plan
+    from paper_2311_15393_amd.kpcg import KP_ERR_ARG
     asym = S.psf_moffat_motion(15, 4.0, 2.5, 6.0, 0.7)
-    with pytest.raises(KPError) as ei:
-        Plan(asym, 64, bc=KP_BC_REFLEXIVE)
-    assert ei.value.status == KP_ERR_UNSUPPORTED
+    with Plan(asym, 64, bc=KP_BC_REFLEXIVE) as plan:
+        assert plan.query()["normal_op"] == KP_NORMAL_FFT
     with pytest.raises(KPError) as ei:
         Plan(_psf("sym", 17, 0), 15, bc=KP_BC_REFLEXIVE)
     assert ei.value.status == KP_ERR_ARG
