@@ -513,10 +513,11 @@ def main():
     if not args.profile_only:
         lowp = run_lowp_setup(prob, b, lam, rows[0]["modes"]["fp16_kp_fpcg"]["tol"], xlam,
                               first["setup_s"])
-    periodic = reflexive = None
+    periodic = reflexive = reflexive_motion = None
     if not args.profile_only and not args.no_periodic:
         periodic = run_boundary("periodic", args.seed, grid, LADDER, dev)
         reflexive = run_boundary("reflexive", args.seed, grid, LADDER, dev)
+        reflexive_motion = run_boundary("reflexive-motion", args.seed, grid, LADDER, dev)
 
     seeds = f"seeds {args.seed}-{args.seed + len(rows) - 1}" if len(rows) > 1 \
         else f"seed {args.seed}"
@@ -553,6 +554,7 @@ def main():
             "batched": batch,
             "periodic": periodic,
             "reflexive": reflexive,
+            "reflexive_motion": reflexive_motion,
             "lowp_setup": lowp,
         },
         "roofline": roofline,
@@ -644,23 +646,33 @@ def run_lowp_setup(prob, b, lam: float, tol: float, xlam, setup64_s: float):
 
 def run_boundary(kind: str, seed: int, grid, ladder, dev):
     """The large workload under another boundary: periodic (KP_BC_PERIODIC,
-    the same image and PSF draws with periodic data, x_lambda by the 2-D DFT)
-    or reflexive (KP_BC_REFLEXIVE, the radial Moffat of the same draw, which
-    is symmetric in both axes, with reflexive data, x_lambda by the 2-D DCT).
+    the same image and PSF draws with periodic data, x_lambda by the 2-D DFT),
+    reflexive (KP_BC_REFLEXIVE, the radial Moffat of the same draw, which
+    is symmetric in both axes, with reflexive data, x_lambda by the 2-D DCT)
+    or reflexive-motion (the Moffat + motion PSF itself, not symmetric, with
+    reflexive data: A^T and H p by the folded FFT passes, x_lambda by the
+    oracle's settled FP64 PCG, tolerances from 1e-7 up).
     Lambda by the device's KP-GCV, FP16-KP flexible PCG at the loosest
-    ladder tolerance whose x meets 1e-4 against the FP64 closed form, then 5
+    ladder tolerance whose x meets 1e-4 against the FP64 x_lambda, then 5
     timed solves and the blur's launch time."""
     import torch
     import synthetic as S
     from paper_2311_15393_amd import KP_BC_PERIODIC, KP_BC_REFLEXIVE, KP_FPCG, KP_OK, KP_P16, Plan
+    from oracle import reflexive as RB
     if kind == "periodic":
         from oracle import periodic as ref
         prob, bc = S.large_moffat_periodic(seed), KP_BC_PERIODIC
         what = "Moffat(beta=2.5)+motion PSF 63x63, periodic BC"
-    else:
-        from oracle import reflexive as ref
+        x_lambda = ref.x_lambda
+    elif kind == "reflexive":
         prob, bc = S.large_moffat_reflexive(seed), KP_BC_REFLEXIVE
         what = "radial Moffat(beta=2.5) PSF 63x63, reflexive BC"
+        x_lambda = RB.x_lambda
+    else:
+        prob, bc = S.large_moffat_motion_reflexive(seed), KP_BC_REFLEXIVE
+        what = "Moffat(beta=2.5)+motion PSF 63x63 (not symmetric), reflexive BC"
+        x_lambda = lambda psf, b64, lam: RB.x_lambda_general(psf, b64, lam, tol=1e-12)[0]
+        ladder = [t for t in ladder if t >= 1e-7]
     n = prob.n
     b = torch.from_numpy(prob.b).to(dev)
     torch.cuda.synchronize()
@@ -671,7 +683,7 @@ def run_boundary(kind: str, seed: int, grid, ladder, dev):
     info0 = plan.query()
     lam, _ = plan.gcv(b, grid)
     gidx = int(np.argmin(np.abs(grid - lam)))
-    xlam = ref.x_lambda(prob.psf, prob.b.astype(np.float64), lam)
+    xlam = x_lambda(prob.psf, prob.b.astype(np.float64), lam)
     mode = KP_FPCG | KP_P16
 
     def run(tol):
@@ -695,16 +707,19 @@ def run_boundary(kind: str, seed: int, grid, ladder, dev):
     q = torch.empty_like(p)
     plan.time_blur(p, q, reps=3)
     blur_us = plan.time_blur(p, q, reps=20) * 1e3
+    plan.time_normal(p, q, reps=3)
+    normal_us = plan.time_normal(p, q, reps=20) * 1e3
     plan.close()
     log(f"[bench] {kind}: lambda={lam:.4g} tol={tol:.0e} iters={info.iters} err={err:.2e} "
-        f"{ms:.3f} ms/solve; blur {blur_us:.1f} us; setup {setup_s:.2f}s")
+        f"{ms:.3f} ms/solve; blur {blur_us:.1f} us; H p ({info0['normal_op']}) "
+        f"{normal_us:.1f} us; setup {setup_s:.2f}s")
     return {"workload": (f"deblur 1024x1024, {what}, 2% noise, lambda by KP-GCV (32-pt grid), "
                          "FP16-KP flexible PCG"),
             "lambda": lam, "gcv_grid_index": gidx, "tol": tol, "iters": info.iters,
             "rel_err": err, "ok": bool(info.status == KP_OK and err <= 1e-4),
             "ms_per_solve": ms, "solves_per_s": 1e3 / ms, "setup_s": setup_s,
             "kp_rel_error": info0["kp_rel_error"], "blur_config": info0["blur_config"],
-            "blur_us": blur_us}
+            "blur_us": blur_us, "normal_op": info0["normal_op"], "normal_op_us": normal_us}
 
 
 def psf_spectrum(psf: np.ndarray, L: int, dev):
