@@ -9,38 +9,50 @@
 // correlation for A^T q.  So, with Hc the 2-D DFT of the wrapped PSF,
 //     A p   = crop(IDFT(Hc .* DFT(pad(p)))),
 //     A^T q = crop(IDFT(conj(Hc) .* DFT(pad(q)))).
-// L is the smallest even size >= n + h whose prime factors are 2, 3, 5, 7.
+// The reflexive boundary extends p by h reflected rows and columns per side
+// first (L >= n + 2h), and its A^T folds the correlation over [-h, n+h) back
+// onto the image.
 //
-// Five passes, each one workgroup per line with the line in LDS:
-//   rows_fwd  two real rows of p packed as one complex row (x_a + i x_b),
+// Five passes:
+//   rows_fwd  two real rows of p packed as one complex line (x_a + i x_b),
 //             one length-L transform, split into the two half spectra
-//             (k = 0 .. L/2) -> S [n][F], F = L/2 + 1
-//   cols      one column k of S: transform, times Hc[:, k] / L^2, inverse
-//             transform, rows 0 .. n-1 kept -> T
+//             (k = 0 .. L/2) -> S
+//   cols      one column k of S: transform, times Hc[:, k] (1/L^2 folded
+//             in), inverse transform, rows 0 .. n-1 kept -> T
 //   rows_mid  two rows of T: Hermitian extension packed as one complex
 //             spectrum, inverse transform (real part row a, imaginary part
 //             row b: A p), columns 0 .. n-1 kept and re-padded, forward
 //             transform, split -> S (the half spectra of A p)
 //   cols      with conj(Hc) -> T
 //   rows_out  inverse as rows_mid, w = result + lambda^2 p on the n x n
-//             window, and the per-workgroup partial sum of p . w.
-// The inverse transforms use IDFT(Y) = conj(DFT(conj(Y))) / L with the 1/L^2
-// folded into the stored Hc.  Each 1-D transform is a Stockham autosort FFT
-// in LDS (ping-pong buffers) over the radices 8, 4, 2, 3, 5, 7, with
-// twiddles from an FP32 table of exp(-2 pi i t / L) built in FP64.
+//             window, and the per-workgroup partial sums of p . w.
+// S and T are stored by frequency: S[k][row], T[k][row] (row pitch spitch,
+// tpitch), so the column passes read and write whole contiguous lines and
+// a row pass's workgroup, which owns 2B consecutive rows, reads and writes
+// 2B consecutive elements per frequency.
+//
+// Each length-L transform is a Stockham autosort FFT of three stages,
+// L = R1 R2 R3 (radices from a fixed menu of lengths, all compile-time):
+// stage s of radix R with Ns = the product of the earlier radices reads
+// x[j + r L/R] (r < R) for each j < L/R, twiddles by W_{Ns R}^{(j mod Ns) r},
+// transforms the R values in registers and writes them to
+// (j / Ns) Ns R + (j mod Ns) + r Ns.  The in-register transforms are
+// mixed-radix (8, 4, 2, 3, 5, 7) with the roots of unity as compile-time
+// constants; W_L comes from an FP32 table built in FP64 and kept in LDS.  The
+// first stage reads global memory and the last may write it; the others
+// exchange through LDS.  A workgroup transforms B lines at once.
 #include <cmath>
+#include <type_traits>
 
 #include "blur_core.h"
 
 namespace kpcg {
 
-constexpr int FT = 256;                 // threads per FFT workgroup
-
 struct FftGeom {
-  int n, L, F, nrad;
-  int rad[FFT_MAX_RADICES];
+  int n, L, F;
   const float2* tw;                     // exp(-2 pi i t / L), t < L
   int refl, h;                          // reflexive boundary; PSF half-width
+  int spitch, tpitch;                   // row pitch of S and T (elements)
 };
 
 // half-sample reflection of an index in [-n, 2n)
@@ -55,414 +67,497 @@ __device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 __device__ inline float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }   // -i a
 __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
-// forward DFTs of length R (W = exp(-2 pi i / R)) in place
-__device__ inline void dft2(float2* v) {
+// ---------------------------------------------------------------------------
+// compile-time roots of unity: W<N, M> = exp(-2 pi i M / N)
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+__host__ __device__ constexpr double ce_sin(double x) {      // |x| <= pi
+  double t = x, s = x;
+  for (int i = 1; i < 26; ++i) {
+    t *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+    s += t;
+  }
+  return s;
+}
+__host__ __device__ constexpr double ce_cos(double x) {      // |x| <= pi
+  double t = 1.0, s = 1.0;
+  for (int i = 1; i < 26; ++i) {
+    t *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+    s += t;
+  }
+  return s;
+}
+// the angle -2 pi M / N reduced to (-pi, pi]
+__host__ __device__ constexpr double root_angle(int N, int M) {
+  const int m = ((M % N) + N) % N;
+  const int mm = 2 * m > N ? m - N : m;
+  return -2.0 * kPi * (double)mm / (double)N;
+}
+template <int N, int M>
+struct W {
+  static constexpr float re = (float)ce_cos(root_angle(N, M));
+  static constexpr float im = (float)ce_sin(root_angle(N, M));
+};
+
+template <int I, int E, class Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (I < E) {
+    fn(std::integral_constant<int, I>{});
+    static_for<I + 1, E>(fn);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward DFTs of compile-time length in registers (W = exp(-2 pi i / N))
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void dft2(float2* v) {
   const float2 a = v[0], b = v[1];
   v[0] = cadd(a, b);
   v[1] = csub(a, b);
 }
-__device__ inline void dft4(float2& v0, float2& v1, float2& v2, float2& v3) {
-  const float2 a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3),
-               a3 = mul_mi(csub(v1, v3));
-  v0 = cadd(a0, a2);
-  v1 = cadd(a1, a3);
-  v2 = csub(a0, a2);
-  v3 = csub(a1, a3);
+__device__ __forceinline__ void dft4(float2* v) {
+  const float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]), a2 = cadd(v[1], v[3]),
+               a3 = mul_mi(csub(v[1], v[3]));
+  v[0] = cadd(a0, a2);
+  v[1] = cadd(a1, a3);
+  v[2] = csub(a0, a2);
+  v[3] = csub(a1, a3);
 }
-__device__ inline void dft8(float2* v) {
-  float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
-  float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
-  dft4(e0, e1, e2, e3);
-  dft4(o0, o1, o2, o3);
+__device__ __forceinline__ void dft8(float2* v) {
+  float2 e[4] = {v[0], v[2], v[4], v[6]};
+  float2 o[4] = {v[1], v[3], v[5], v[7]};
+  dft4(e);
+  dft4(o);
   constexpr float r = 0.70710678118654752f;
   // o_k *= exp(-i pi k / 4)
-  o1 = make_float2(r * (o1.x + o1.y), r * (o1.y - o1.x));
-  o2 = mul_mi(o2);
-  o3 = make_float2(r * (o3.y - o3.x), -r * (o3.x + o3.y));
-  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
-  v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
-  v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
-  v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+  o[1] = make_float2(r * (o[1].x + o[1].y), r * (o[1].y - o[1].x));
+  o[2] = mul_mi(o[2]);
+  o[3] = make_float2(r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = cadd(e[k], o[k]);
+    v[k + 4] = csub(e[k], o[k]);
+  }
 }
 // odd R: with A_k = v_k + v_{R-k}, B_k = v_k - v_{R-k} (k = 1 .. (R-1)/2),
 // X_m = v_0 + sum_k cos(2 pi m k / R) A_k -/+ i sum_k sin(2 pi m k / R) B_k
 // for m and R - m
 template <int R>
-__device__ inline void dft_odd(float2* v, const float (*C)[4], const float (*S)[4]) {
+__device__ __forceinline__ void dft_odd(float2* v) {
   constexpr int H = (R - 1) / 2;
   float2 A[H], B[H];
-#pragma unroll
-  for (int k = 1; k <= H; ++k) {
+  static_for<1, H + 1>([&](auto k) {
     A[k - 1] = cadd(v[k], v[R - k]);
     B[k - 1] = csub(v[k], v[R - k]);
-  }
-  float2 x0 = v[0];
-#pragma unroll
-  for (int k = 0; k < H; ++k) x0 = cadd(x0, A[k]);
+  });
   float2 out[R];
+  float2 x0 = v[0];
+  static_for<0, H>([&](auto k) { x0 = cadd(x0, A[k]); });
   out[0] = x0;
-#pragma unroll
-  for (int m = 1; m <= H; ++m) {
+  static_for<1, H + 1>([&](auto m) {
     float2 re = v[0], im = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int k = 1; k <= H; ++k) {
-      re.x = fmaf(C[m][k], A[k - 1].x, re.x);
-      re.y = fmaf(C[m][k], A[k - 1].y, re.y);
-      im.x = fmaf(S[m][k], B[k - 1].x, im.x);
-      im.y = fmaf(S[m][k], B[k - 1].y, im.y);
-    }
+    static_for<1, H + 1>([&](auto k) {
+      constexpr int e = (decltype(m)::value * decltype(k)::value) % R;
+      constexpr float c = W<R, e>::re;     // cos(2 pi e / R)
+      constexpr float s = -W<R, e>::im;    // sin(2 pi e / R)
+      re.x = fmaf(c, A[k - 1].x, re.x);
+      re.y = fmaf(c, A[k - 1].y, re.y);
+      im.x = fmaf(s, B[k - 1].x, im.x);
+      im.y = fmaf(s, B[k - 1].y, im.y);
+    });
     out[m] = cadd(re, mul_mi(im));          // re - i im
     out[R - m] = csub(re, mul_mi(im));      // re + i im
-  }
-#pragma unroll
-  for (int m = 0; m < R; ++m) v[m] = out[m];
+  });
+  static_for<0, R>([&](auto m) { v[m] = out[m]; });
 }
-// cos / sin (2 pi m k / R), indices [m][k], m, k <= 3
-__constant__ float kC3[4][4] = {{1, 1, 1, 1}, {1, -0.5f, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-__constant__ float kS3[4][4] = {{0, 0, 0, 0}, {0, 0.86602540378443865f, 0, 0}, {0, 0, 0, 0},
-                                {0, 0, 0, 0}};
-__constant__ float kC5[4][4] = {{1, 1, 1, 1},
-                                {1, 0.30901699437494742f, -0.80901699437494742f, 0},
-                                {1, -0.80901699437494742f, 0.30901699437494742f, 0},
-                                {0, 0, 0, 0}};
-__constant__ float kS5[4][4] = {{0, 0, 0, 0},
-                                {0, 0.95105651629515357f, 0.58778525229247313f, 0},
-                                {0, 0.58778525229247313f, -0.95105651629515357f, 0},
-                                {0, 0, 0, 0}};
-__constant__ float kC7[4][4] = {
-    {1, 1, 1, 1},
-    {1, 0.62348980185873353f, -0.22252093395631440f, -0.90096886790241913f},
-    {1, -0.22252093395631440f, -0.90096886790241913f, 0.62348980185873353f},
-    {1, -0.90096886790241913f, 0.62348980185873353f, -0.22252093395631440f}};
-__constant__ float kS7[4][4] = {
-    {0, 0, 0, 0},
-    {0, 0.78183148246802981f, 0.97492791218182361f, 0.43388373911755812f},
-    {0, 0.97492791218182361f, -0.43388373911755812f, -0.78183148246802981f},
-    {0, 0.43388373911755812f, -0.78183148246802981f, 0.97492791218182361f}};
 
-// One radix-R Stockham stage over the whole line: in -> out (tw: the
-// twiddle table in LDS).
-template <int R>
-__device__ inline void fft_stage(const float2* __restrict__ in, float2* __restrict__ out,
-                                 const float2* __restrict__ tw, int L, int Ns) {
-  const int Ls = L / R;
-  const int step = L / (Ns * R);
-  for (int j = threadIdx.x; j < Ls; j += FT) {
-    const int k = j % Ns;
-    float2 v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = in[j + r * Ls];
-    if (Ns > 1) {
-#pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[k * r * step]);
-    }
-    if constexpr (R == 2) dft2(v);
-    else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3]);
-    else if constexpr (R == 8) dft8(v);
-    else if constexpr (R == 3) dft_odd<3>(v, kC3, kS3);
-    else if constexpr (R == 5) dft_odd<5>(v, kC5, kS5);
-    else dft_odd<7>(v, kC7, kS7);
-    const int base = (j / Ns) * Ns * R + k;
-#pragma unroll
-    for (int r = 0; r < R; ++r) out[base + r * Ns] = v[r];
+template <int N>
+constexpr int first_radix() {
+  return (N % 8 == 0) ? 8 : (N % 4 == 0) ? 4 : (N % 2 == 0) ? 2 : (N % 3 == 0) ? 3
+         : (N % 5 == 0) ? 5 : 7;
+}
+
+// v <- DFT_N(v); N a product of 2, 3, 5, 7 (decimation in time: N = R M,
+// X[k + M q] = sum_r W_R^{rq} W_N^{rk} DFT_M(v[r + R m])[k])
+template <int N>
+__device__ __forceinline__ void dftr(float2 (&v)[N]) {
+  if constexpr (N == 1) {
+  } else if constexpr (N == 2) {
+    dft2(v);
+  } else if constexpr (N == 4) {
+    dft4(v);
+  } else if constexpr (N == 8) {
+    dft8(v);
+  } else if constexpr (N == 3 || N == 5 || N == 7) {
+    dft_odd<N>(v);
+  } else {
+    constexpr int R = first_radix<N>(), M = N / R;
+    static_assert(R * M == N && M > 1, "N must be 7-smooth");
+    float2 d[R][M];
+    static_for<0, R>([&](auto r) {
+      static_for<0, M>([&](auto m) { d[r][m] = v[r + R * m]; });
+      dftr<M>(d[r]);
+    });
+    static_for<1, R>([&](auto r) {
+      static_for<1, M>([&](auto k) {
+        constexpr int e = decltype(r)::value * decltype(k)::value;
+        d[r][k] = cmul(d[r][k], make_float2(W<N, e>::re, W<N, e>::im));
+      });
+    });
+    static_for<0, M>([&](auto k) {
+      float2 t[R];
+      static_for<0, R>([&](auto r) { t[r] = d[r][k]; });
+      dftr<R>(t);
+      static_for<0, R>([&](auto q) { v[k + M * q] = t[q]; });
+    });
   }
 }
 
-// Forward DFT of the line in a (length g.L), b as the second buffer, with
-// the twiddle table tw in LDS.  Returns the buffer holding the result.
-// Ends with a barrier.
-__device__ inline float2* fft_line(float2* a, float2* b, const float2* tw, const FftGeom& g) {
-  int Ns = 1;
-  for (int s = 0; s < g.nrad; ++s) {
-    const int R = g.rad[s];
-    switch (R) {
-      case 8: fft_stage<8>(a, b, tw, g.L, Ns); break;
-      case 4: fft_stage<4>(a, b, tw, g.L, Ns); break;
-      case 2: fft_stage<2>(a, b, tw, g.L, Ns); break;
-      case 3: fft_stage<3>(a, b, tw, g.L, Ns); break;
-      case 5: fft_stage<5>(a, b, tw, g.L, Ns); break;
-      default: fft_stage<7>(a, b, tw, g.L, Ns); break;
-    }
-    __syncthreads();
-    float2* t = a; a = b; b = t;
-    Ns *= R;
-  }
-  return a;
+// sum_t x[t] W^{-tk}: conj(DFT(conj x))
+template <int N, bool INV>
+__device__ __forceinline__ void dft_dir(float2 (&v)[N]) {
+  if constexpr (INV) static_for<0, N>([&](auto i) { v[i].y = -v[i].y; });
+  dftr<N>(v);
+  if constexpr (INV) static_for<0, N>([&](auto i) { v[i].y = -v[i].y; });
 }
+
+// ---------------------------------------------------------------------------
+// Stockham transforms of length L = R1 R2 R3 over B lines per workgroup
+// ---------------------------------------------------------------------------
+template <int A1, int A2, int A3>
+struct Sh3 {
+  static constexpr int R1 = A1, R2 = A2, R3 = A3;
+  static constexpr int L = R1 * R2 * R3;
+  static constexpr int F = L / 2 + 1;
+#ifndef KPCG_FFT_B1_MIN
+#define KPCG_FFT_B1_MIN 1536
+#endif
+  static constexpr int B = L >= KPCG_FFT_B1_MIN ? 1 : L >= 512 ? 2 : (L >= 192 ? 4 : 8);   // lines per workgroup
+  static constexpr int RMIN = R1 < R2 ? (R1 < R3 ? R1 : R3) : (R2 < R3 ? R2 : R3);
+  static constexpr int NTASK = B * (L / RMIN);                    // most tasks of a stage
+  // one task per thread in every stage (a second round would double it)
+  static constexpr int NT = ((NTASK + 63) / 64) * 64;
+  static_assert(NT <= 1024, "too many tasks per stage");
+  static constexpr int LP = L + 1;                                // line pitch in LDS
+  static constexpr size_t LDS = (size_t)(L + 2 * B * LP) * sizeof(float2);
+  static constexpr int TWN = (L + NT - 1) / NT;                  // twiddle loads per thread
+  static constexpr int EPT = (B * L + NT - 1) / NT;              // elements per thread
+};
 
 __device__ inline bool fft_skip(const Ctrl* ctrl) { return ctrl != nullptr && ctrl->done != RUNNING; }
 
-// Split the transform Z of x_a + i x_b into the half spectra of the two real
-// rows: X_a = (Z_k + conj Z_{L-k}) / 2, X_b = (Z_k - conj Z_{L-k}) / (2 i).
-__device__ inline void split_store(const float2* Z, int L, int F, float2* Sa, float2* Sb) {
-  for (int k = threadIdx.x; k < F; k += FT) {
-    const float2 z = Z[k];
-    const float2 zr = cconj(Z[k == 0 ? 0 : L - k]);
-    Sa[k] = cscale(cadd(z, zr), 0.5f);
-    if (Sb) Sb[k] = cscale(mul_mi(csub(z, zr)), 0.5f);
-  }
+// Row passes: workgroup b runs on XCD b % 8 (the grid is a multiple of 8),
+// and each XCD takes a contiguous range of the G line groups, so that the
+// groups sharing cache lines of S and T (consecutive rows of one frequency)
+// share one L2.  -1: no group (padding of the grid).
+__device__ inline int xcd_line_group(int G) {
+  const int per = gridDim.x / 8;
+  const int g = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  return g < G ? g : -1;
 }
 
-// Every kernel issues all of its global loads (its line, the twiddle table,
-// and the PSF spectrum column or the p rows it needs at the end) before it
-// waits for any of them, then works in LDS: a line of L <= FFT_MAX_L points
-// is FE elements per thread.
-constexpr int FE = (FFT_MAX_L + FT - 1) / FT;
-
-// the twiddle table into registers (issued), then into LDS (tw_lds)
-struct TwStage {
-  float2 v[FE];
+// the twiddle table through registers (loads issued first) into LDS
+template <int NT, int TWN>
+struct TwLoad {
+  float2 v[TWN];
   __device__ void load(const float2* __restrict__ tw, int L) {
 #pragma unroll
-    for (int e = 0; e < FE; ++e) {
-      const int t = threadIdx.x + e * FT;
+    for (int e = 0; e < TWN; ++e) {
+      const int t = threadIdx.x + e * NT;
       if (t < L) v[e] = tw[t];
     }
   }
-  __device__ void store(float2* tw_lds, int L) const {
+  __device__ void store(float2* lds, int L) const {
 #pragma unroll
-    for (int e = 0; e < FE; ++e) {
-      const int t = threadIdx.x + e * FT;
-      if (t < L) tw_lds[t] = v[e];
+    for (int e = 0; e < TWN; ++e) {
+      const int t = threadIdx.x + e * NT;
+      if (t < L) lds[t] = v[e];
     }
   }
 };
 
+// One radix-R stage over the workgroup's B lines: task (b, j), j < L/R,
+// b fastest, reads src(b, j + r L/R) (r < R), multiplies by
+// W_{Ns R}^{(j mod Ns) r}, transforms (INV: exponents negated) and writes
+// dst(b, (j / Ns) Ns R + (j mod Ns) + r Ns).  After the stages with
+// Ns = 1, R1, R1 R2 the lines hold their DFTs in natural order.
+template <class C, int R, int Ns, bool INV, class Src, class Dst>
+__device__ __forceinline__ void sh_stage(Src&& src, Dst&& dst, const float2* tw) {
+  constexpr int J = C::L / R, TWS = C::L / (Ns * R);
+  for (int q = threadIdx.x; q < C::B * J; q += C::NT) {
+    const int b = q % C::B, j = q / C::B;
+    const int k = j % Ns;
+    float2 v[R];
+    static_for<0, R>([&](auto r) { v[r] = src(b, j + decltype(r)::value * J); });
+    if constexpr (Ns > 1) {
+      static_for<1, R>([&](auto r) {
+        float2 w = tw[k * decltype(r)::value * TWS];
+        if constexpr (INV) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+      });
+    }
+    dft_dir<R, INV>(v);
+    const int base = (j / Ns) * Ns * R + k;
+    static_for<0, R>([&](auto r) { dst(b, base + decltype(r)::value * Ns, v[r]); });
+  }
+}
+
+// A whole transform: stage 1 from src into X, stage 2 from X into Y, stage
+// 3 from Y into dst, with barriers between them.  src must not read X.
+template <class C, bool INV, class Src, class Dst>
+__device__ __forceinline__ void sh_transform(Src&& src, float2* X, float2* Y, Dst&& dst,
+                                             const float2* tw) {
+  sh_stage<C, C::R1, 1, INV>(src, [&](int b, int t, float2 v) { X[b * C::LP + t] = v; }, tw);
+  __syncthreads();
+  sh_stage<C, C::R2, C::R1, INV>([&](int b, int t) { return X[b * C::LP + t]; },
+                                 [&](int b, int t, float2 v) { Y[b * C::LP + t] = v; }, tw);
+  __syncthreads();
+  sh_stage<C, C::R3, C::R1 * C::R2, INV>([&](int b, int t) { return Y[b * C::LP + t]; }, dst, tw);
+}
+
+// Split the transforms Z (line b at Z + b LP) of x_a + i x_b into the half
+// spectra of the two real rows, X_a = (Z_k + conj Z_{L-k}) / 2,
+// X_b = (Z_k - conj Z_{L-k}) / (2 i), stored at S[k][sa], S[k][sb]; lines b
+// fastest, so that the workgroup writes its 2B rows of one k together.
+template <class C>
+__device__ inline void split_store(const float2* Z, int line0, int nl, int rows,
+                                   float2* __restrict__ S, int spitch) {
+  for (int q = threadIdx.x; q < C::B * C::F; q += C::NT) {
+    const int b = q % C::B, k = q / C::B, line = line0 + b;
+    if (line >= nl) continue;
+    const float2* zb = Z + b * C::LP;
+    const float2 z = zb[k];
+    const float2 zr = cconj(zb[k == 0 ? 0 : C::L - k]);
+    const int sa = 2 * line, sb = sa + 1;
+    S[(size_t)k * spitch + sa] = cscale(cadd(z, zr), 0.5f);
+    if (sb < rows) S[(size_t)k * spitch + sb] = cscale(mul_mi(csub(z, zr)), 0.5f);
+  }
+}
+
+// The Hermitian-extended spectrum of rows ra (real part) and rb (imaginary
+// part, rb < 0: zero) at frequency kap: Z = A + i B from the half spectra
+// stored in T[k][row].
+template <class C>
+__device__ inline float2 row_spectrum(const float2* __restrict__ T, int tpitch, int ra, int rb,
+                                      int kap) {
+  const bool low = kap < C::F;
+  const int kk = low ? kap : C::L - kap;
+  float2 A = T[(size_t)kk * tpitch + ra];
+  float2 Bv = rb >= 0 ? T[(size_t)kk * tpitch + rb] : make_float2(0.f, 0.f);
+  if (!low) {
+    A.y = -A.y;
+    Bv.y = -Bv.y;
+  }
+  return make_float2(A.x - Bv.y, A.y + Bv.x);
+}
+
+// ---------------------------------------------------------------------------
+// pass kernels (LDS: the twiddle table, then line buffers A and Bf)
+// ---------------------------------------------------------------------------
+
 // Row pass of the forward transform.  Plain (ext = 0): rows 0 .. n-1 of p,
 // zero-padded to L.  Extended (ext = 1, reflexive boundary): the image
 // extended by half-sample reflection over the rows and columns [-h, n+h):
-// row slot s of S holds image row refl(s - h), and a column index j in
-// [-h, 0) sits at the circular position L + j.
-__global__ __launch_bounds__(FT) void fft_rows_fwd_kernel(const float* __restrict__ p, FftGeom g,
-                                                          int ext, float2* __restrict__ S,
-                                                          const Ctrl* ctrl) {
+// row slot s holds image row refl(s - h), and a column index j in [-h, 0)
+// sits at the circular position L + j.
+template <class C>
+__global__ __launch_bounds__(C::NT) void fft_rows_fwd_kernel(const float* __restrict__ p, FftGeom g,
+                                                           int ext, float2* __restrict__ S,
+                                                           const Ctrl* ctrl) {
   if (fft_skip(ctrl)) return;
   extern __shared__ float2 fft_lds[];
-  float2* a = fft_lds;
-  float2* b = fft_lds + g.L;
-  float2* tw = fft_lds + 2 * g.L;
-  const int n = g.n, L = g.L, h = ext ? g.h : 0;
-  const int rows = n + 2 * h, ra = 2 * blockIdx.x, rb = ra + 1;
-  const int sa = ext ? refl_index(ra - h, n) : ra;
-  const int sb = rb < rows ? (ext ? refl_index(rb - h, n) : rb) : -1;
-  TwStage ts;
-  ts.load(g.tw, L);
-  float2 v[FE];
-#pragma unroll
-  for (int e = 0; e < FE; ++e) {
-    const int c = threadIdx.x + e * FT;
-    v[e] = make_float2(0.f, 0.f);
-    const int j = c >= L - h ? c - L : c;          // column of circular position c
-    if (c < L && j >= -h && j < n + h) {
-      const int jj = ext ? refl_index(j, n) : j;
-      v[e].x = p[(size_t)sa * n + jj];
-      if (sb >= 0) v[e].y = p[(size_t)sb * n + jj];
-    }
-  }
-  ts.store(tw, L);
-#pragma unroll
-  for (int e = 0; e < FE; ++e) {
-    const int j = threadIdx.x + e * FT;
-    if (j < L) a[j] = v[e];
-  }
+  float2* tw = fft_lds;
+  float2* A = tw + C::L;
+  float2* Bf = A + C::B * C::LP;
+  const int n = g.n, h = ext ? g.h : 0;
+  const int rows = n + 2 * h, nl = (rows + 1) / 2;
+  const int grp = xcd_line_group((nl + C::B - 1) / C::B);
+  if (grp < 0) return;
+  const int line0 = grp * C::B;
+  TwLoad<C::NT, C::TWN> ts;
+  ts.load(g.tw, C::L);
+  auto src = [&](int b, int t) -> float2 {
+    float2 x = make_float2(0.f, 0.f);
+    const int line = line0 + b;
+    const int j = t >= C::L - h ? t - C::L : t;          // column of circular position t
+    if (line >= nl || j < -h || j >= n + h) return x;
+    const int jj = ext ? refl_index(j, n) : j;
+    const int sa = 2 * line, sb = sa + 1;
+    x.x = p[(size_t)(ext ? refl_index(sa - h, n) : sa) * n + jj];
+    if (sb < rows) x.y = p[(size_t)(ext ? refl_index(sb - h, n) : sb) * n + jj];
+    return x;
+  };
+  ts.store(tw, C::L);          // first read in stage 2, after a barrier
+  sh_transform<C, false>(src, A, Bf, [&](int b, int t, float2 v) { A[b * C::LP + t] = v; }, tw);
   __syncthreads();
-  const float2* Z = fft_line(a, b, tw, g);
-  split_store(Z, L, g.F, S + (size_t)ra * g.F, sb >= 0 ? S + (size_t)rb * g.F : nullptr);
+  split_store<C>(A, line0, nl, rows, S, g.spitch);
 }
 
-// Columns: consecutive workgroups go to different XCDs (round robin), so the
-// column index is chosen to give each XCD a contiguous range of columns:
-// neighbouring columns share cache lines of S and T.
-__device__ inline int xcd_column(int bid, int F) {
-  const int per = (F + 7) / 8;
-  const int k = (bid & 7) * per + (bid >> 3);
-  return k;
-}
-
-// Column pass: the column k of S (its in_rows row slots, slot s at the
-// circular row position s - in_off, the rest zero), its transform times the
-// PSF spectrum (or its conjugate), the inverse; rows 0 .. n-1 kept, or with
-// fold (the correlation of the reflexive boundary's A^T) the rows [-h, n+h)
+// Column pass: column k of S (its in_rows row slots, slot s at the circular
+// row position s - in_off, the rest zero), its transform times the PSF
+// spectrum (or its conjugate), the inverse; rows 0 .. n-1 kept, or with fold
+// (the correlation of the reflexive boundary's A^T) the rows [-h, n+h)
 // folded onto the image by the reflection: row a gains rows -1-a (circular
 // L-1-a, for a < h) and 2n-1-a (for a >= n-h).
-__global__ __launch_bounds__(FT) void fft_cols_kernel(const float2* __restrict__ S, FftGeom g,
-                                                      int in_rows, int in_off,
-                                                      const float2* __restrict__ Ht, int conjH,
-                                                      int fold, float2* __restrict__ T,
-                                                      const Ctrl* ctrl) {
-  if (fft_skip(ctrl)) return;
-  const int k = xcd_column(blockIdx.x, g.F);
-  if (k >= g.F) return;
-  extern __shared__ float2 fft_lds[];
-  const int n = g.n, L = g.L, F = g.F;
-  float2* a = fft_lds;
-  float2* b = fft_lds + L;
-  float2* tw = fft_lds + 2 * L;
-  TwStage ts;
-  ts.load(g.tw, L);
-  // the column and the PSF spectrum column
-  const float2* h = Ht + (size_t)k * L;
-  float2 v[FE], hv[FE];
-#pragma unroll
-  for (int e = 0; e < FE; ++e) {
-    const int c = threadIdx.x + e * FT;
-    v[e] = make_float2(0.f, 0.f);
-    const int sl = (c >= L - in_off ? c - L : c) + in_off;   // row slot of circular row c
-    if (c < L && sl >= 0 && sl < in_rows) v[e] = S[(size_t)sl * F + k];
-    if (c < L) hv[e] = h[c];
-  }
-  ts.store(tw, L);
-#pragma unroll
-  for (int e = 0; e < FE; ++e) {
-    const int i = threadIdx.x + e * FT;
-    if (i < L) a[i] = v[e];
-  }
-  __syncthreads();
-  float2* Y = fft_line(a, b, tw, g);
-  float2* other = Y == a ? b : a;
-  // the spectrum times Hc (or conj Hc), conjugated for the inverse transform;
-  // element m of Y belongs to the thread that loaded hv for m
-#pragma unroll
-  for (int e = 0; e < FE; ++e) {
-    const int m = threadIdx.x + e * FT;
-    if (m < L) {
-      float2 hm = hv[e];
-      if (conjH) hm.y = -hm.y;
-      Y[m] = cconj(cmul(Y[m], hm));
-    }
-  }
-  __syncthreads();
-  const float2* y = fft_line(Y, other, tw, g);
-  const int hf = fold ? g.h : 0;
-  for (int i = threadIdx.x; i < n; i += FT) {
-    float2 t = y[i];
-    if (i < hf) t = cadd(t, y[L - 1 - i]);
-    if (i >= n - hf) t = cadd(t, y[2 * n - 1 - i]);
-    T[(size_t)i * F + k] = cconj(t);
-  }
-}
-
-// conj of the full spectrum of x_a + i x_b from the half spectra held in
-// registers (ta, tb: element j of thread t is k = t + j FT, k < F) into out
-// (Hermitian extension), ready for IDFT(Z) = conj(DFT(conj Z)): out[k] for
-// k < F and out[L - k] for 0 < k < L - F + 1... written by the owner of k.
-__device__ inline void pack_conj_regs(const float2 (&ta)[FE], const float2 (&tb)[FE], bool has_b,
-                                      int L, int F, float2* out) {
-#pragma unroll
-  for (int e = 0; e < FE; ++e) {
-    const int k = threadIdx.x + e * FT;
-    if (k < F) {
-      const float2 a = ta[e], bb = has_b ? tb[e] : make_float2(0.f, 0.f);
-      // Z_k = a + i b; conj(Z_k)
-      out[k] = cconj(make_float2(a.x - bb.y, a.y + bb.x));
-      // Z_{L-k} = conj a + i conj b (for 0 < k, L - k >= F)
-      if (k > 0 && L - k >= F) out[L - k] = cconj(make_float2(a.x + bb.y, bb.x - a.y));
-    }
-  }
-}
-
-__device__ inline void load_half_rows(const float2* __restrict__ T, int ra, int rb, int n, int F,
-                                      float2 (&ta)[FE], float2 (&tb)[FE]) {
-#pragma unroll
-  for (int e = 0; e < FE; ++e) {
-    const int k = threadIdx.x + e * FT;
-    if (k < F) {
-      ta[e] = T[(size_t)ra * F + k];
-      tb[e] = rb < n ? T[(size_t)rb * F + k] : make_float2(0.f, 0.f);
-    }
-  }
-}
-
-__global__ __launch_bounds__(FT) void fft_rows_mid_kernel(const float2* __restrict__ T,
-                                                          FftGeom g, float2* __restrict__ S,
-                                                          const Ctrl* ctrl) {
+template <class C>
+__global__ __launch_bounds__(C::NT) void fft_cols_kernel(const float2* __restrict__ S, FftGeom g,
+                                                       int in_rows, int in_off,
+                                                       const float2* __restrict__ Ht, int conjH,
+                                                       int fold, float2* __restrict__ T,
+                                                       const Ctrl* ctrl) {
   if (fft_skip(ctrl)) return;
   extern __shared__ float2 fft_lds[];
-  const int n = g.n, L = g.L, F = g.F, ra = 2 * blockIdx.x, rb = ra + 1;
-  float2* a = fft_lds;
-  float2* b = fft_lds + L;
-  float2* tw = fft_lds + 2 * L;
-  TwStage ts;
-  ts.load(g.tw, L);
-  float2 ta[FE], tb[FE];
-  load_half_rows(T, ra, rb, n, F, ta, tb);
-  ts.store(tw, L);
-  pack_conj_regs(ta, tb, rb < n, L, F, a);
-  __syncthreads();
-  float2* z = fft_line(a, b, tw, g);
-  // conj(z) = A p rows ra (real) and rb (imaginary); keep j < n, re-pad
-  for (int j = threadIdx.x; j < L; j += FT) {
-    float2 v = make_float2(0.f, 0.f);
-    if (j < n) {
-      v = cconj(z[j]);
-      if (rb >= n) v.y = 0.f;
+  float2* tw = fft_lds;
+  float2* A = tw + C::L;
+  float2* Bf = A + C::B * C::LP;
+  const int n = g.n, k0 = blockIdx.x * C::B;
+  TwLoad<C::NT, C::TWN> ts;
+  ts.load(g.tw, C::L);
+  // the PSF spectrum of this thread's elements of the product below
+  float2 hv[C::EPT];
+#pragma unroll
+  for (int i = 0; i < C::EPT; ++i) {
+    const int q = threadIdx.x + i * C::NT, b = q % C::B, t = q / C::B, k = k0 + b;
+    hv[i] = make_float2(0.f, 0.f);
+    if (q < C::B * C::L && k < C::F) {
+      hv[i] = Ht[(size_t)k * C::L + t];
+      if (conjH) hv[i].y = -hv[i].y;
     }
-    z[j] = v;
+  }
+  auto src = [&](int b, int t) -> float2 {
+    const int k = k0 + b;
+    const int sl = (t >= C::L - in_off ? t - C::L : t) + in_off;   // row slot of row t
+    return (k < C::F && sl >= 0 && sl < in_rows) ? S[(size_t)k * g.spitch + sl]
+                                                 : make_float2(0.f, 0.f);
+  };
+  ts.store(tw, C::L);
+  sh_transform<C, false>(src, A, Bf, [&](int b, int t, float2 v) { A[b * C::LP + t] = v; }, tw);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < C::EPT; ++i) {
+    const int q = threadIdx.x + i * C::NT, b = q % C::B, t = q / C::B;
+    if (q < C::B * C::L) A[b * C::LP + t] = cmul(A[b * C::LP + t], hv[i]);
   }
   __syncthreads();
-  float2* other = z == a ? b : a;
-  const float2* Z = fft_line(z, other, tw, g);
-  split_store(Z, L, F, S + (size_t)ra * F, rb < n ? S + (size_t)rb * F : nullptr);
+  auto srcA = [&](int b, int t) { return A[b * C::LP + t]; };
+  if (!fold) {
+    sh_transform<C, true>(srcA, Bf, A, [&](int b, int t, float2 v) {
+      const int k = k0 + b;
+      if (k < C::F && t < n) T[(size_t)k * g.tpitch + t] = v;
+    }, tw);
+    return;
+  }
+  sh_transform<C, true>(srcA, Bf, A, [&](int b, int t, float2 v) { Bf[b * C::LP + t] = v; }, tw);
+  __syncthreads();
+  const int hf = g.h;
+  for (int q = threadIdx.x; q < C::B * n; q += C::NT) {
+    const int b = q % C::B, i = q / C::B, k = k0 + b;
+    if (k >= C::F) continue;
+    const float2* zb = Bf + b * C::LP;
+    float2 t = zb[i];
+    if (i < hf) t = cadd(t, zb[C::L - 1 - i]);
+    if (i >= n - hf) t = cadd(t, zb[2 * n - 1 - i]);
+    T[(size_t)k * g.tpitch + i] = t;
+  }
+}
+
+template <class C>
+__global__ __launch_bounds__(C::NT) void fft_rows_mid_kernel(const float2* __restrict__ T,
+                                                           FftGeom g, float2* __restrict__ S,
+                                                           const Ctrl* ctrl) {
+  if (fft_skip(ctrl)) return;
+  extern __shared__ float2 fft_lds[];
+  float2* tw = fft_lds;
+  float2* A = tw + C::L;
+  float2* Bf = A + C::B * C::LP;
+  const int n = g.n, nl = (n + 1) / 2;
+  const int grp = xcd_line_group((nl + C::B - 1) / C::B);
+  if (grp < 0) return;
+  const int line0 = grp * C::B;
+  TwLoad<C::NT, C::TWN> ts;
+  ts.load(g.tw, C::L);
+  auto src = [&](int b, int kap) -> float2 {
+    const int line = line0 + b, ra = 2 * line, rb = ra + 1 < n ? ra + 1 : -1;
+    if (line >= nl) return make_float2(0.f, 0.f);
+    return row_spectrum<C>(T, g.tpitch, ra, rb, kap);
+  };
+  ts.store(tw, C::L);
+  // A p of the line's two rows (real, imaginary part) into A
+  sh_transform<C, true>(src, A, Bf, [&](int b, int t, float2 v) { A[b * C::LP + t] = v; }, tw);
+  __syncthreads();
+  // columns >= n cut, re-padded; forward transform into Bf
+  auto srcc = [&](int b, int t) -> float2 {
+    const int line = line0 + b;
+    float2 v = t < n ? A[b * C::LP + t] : make_float2(0.f, 0.f);
+    if (2 * line + 1 >= n) v.y = 0.f;
+    return v;
+  };
+  sh_transform<C, false>(srcc, Bf, A, [&](int b, int t, float2 v) { Bf[b * C::LP + t] = v; }, tw);
+  __syncthreads();
+  split_store<C>(Bf, line0, nl, n, S, g.spitch);
 }
 
 // Last row pass: the inverse transform of two rows, rows 0 .. n-1 of the
 // result (with fold, the columns [-h, n+h) folded onto the image as in the
 // column pass), plus lambda^2 p and the partials of p . w when p is given.
-__global__ __launch_bounds__(FT) void fft_rows_out_kernel(const float2* __restrict__ T, FftGeom g,
-                                                          int fold, const float* __restrict__ p,
-                                                          float* __restrict__ w, float lam2,
-                                                          double* __restrict__ partials,
-                                                          const Ctrl* ctrl) {
+template <class C>
+__global__ __launch_bounds__(C::NT) void fft_rows_out_kernel(
+    const float2* __restrict__ T, FftGeom g, int fold, const float* __restrict__ p,
+    float* __restrict__ w, float lam2, double* __restrict__ partials, const Ctrl* ctrl) {
   if (fft_skip(ctrl)) return;
   extern __shared__ float2 fft_lds[];
-  __shared__ double sh[FT / 64];
-  const int n = g.n, L = g.L, F = g.F, ra = 2 * blockIdx.x, rb = ra + 1;
-  float2* a = fft_lds;
-  float2* b = fft_lds + L;
-  float2* tw = fft_lds + 2 * L;
-  TwStage ts;
-  ts.load(g.tw, L);
-  float2 ta[FE], tb[FE];
-  load_half_rows(T, ra, rb, n, F, ta, tb);
-  // the two rows of p for lambda^2 p and p . w
-  float pa[FE], pb[FE];
+  __shared__ double sh[C::NT / 64];
+  float2* tw = fft_lds;
+  float2* A = tw + C::L;
+  float2* Bf = A + C::B * C::LP;
+  const int n = g.n, nl = (n + 1) / 2;
+  const int grp = xcd_line_group((nl + C::B - 1) / C::B);
+  if (grp < 0) return;
+  const int line0 = grp * C::B;
+  TwLoad<C::NT, C::TWN> ts;
+  ts.load(g.tw, C::L);
+  // the rows of p at this thread's outputs (element q: line q % B, column q / B)
+  constexpr int OPT = (C::B * C::L + C::NT - 1) / C::NT;
+  float pa[OPT], pb[OPT];
 #pragma unroll
-  for (int e = 0; e < FE; ++e) {
-    const int j = threadIdx.x + e * FT;
-    pa[e] = 0.f;
-    pb[e] = 0.f;
-    if (p != nullptr && j < n) {
-      pa[e] = p[(size_t)ra * n + j];
-      pb[e] = rb < n ? p[(size_t)rb * n + j] : 0.f;
-    }
+  for (int i = 0; i < OPT; ++i) {
+    const int q = threadIdx.x + i * C::NT, b = q % C::B, j = q / C::B, line = line0 + b;
+    const int ra = 2 * line, rb = ra + 1;
+    const bool ok = p != nullptr && q < C::B * C::L && j < n && line < nl;
+    pa[i] = ok ? p[(size_t)ra * n + j] : 0.f;
+    pb[i] = (ok && rb < n) ? p[(size_t)rb * n + j] : 0.f;
   }
-  ts.store(tw, L);
-  pack_conj_regs(ta, tb, rb < n, L, F, a);
+  auto src = [&](int b, int kap) -> float2 {
+    const int line = line0 + b, ra = 2 * line, rb = ra + 1 < n ? ra + 1 : -1;
+    if (line >= nl) return make_float2(0.f, 0.f);
+    return row_spectrum<C>(T, g.tpitch, ra, rb, kap);
+  };
+  ts.store(tw, C::L);
+  sh_transform<C, true>(src, A, Bf, [&](int b, int t, float2 v) { A[b * C::LP + t] = v; }, tw);
   __syncthreads();
-  const float2* z = fft_line(a, b, tw, g);
   const int hf = fold ? g.h : 0;
-  double d = 0.0;
+  double dsum = 0.0;
 #pragma unroll
-  for (int e = 0; e < FE; ++e) {
-    const int j = threadIdx.x + e * FT;
-    if (j < n) {
-      float2 zt = z[j];
-      if (j < hf) zt = cadd(zt, z[L - 1 - j]);
-      if (j >= n - hf) zt = cadd(zt, z[2 * n - 1 - j]);
-      const float2 v = cconj(zt);
-      const size_t oa = (size_t)ra * n + j;
-      const float wa = fmaf(lam2, pa[e], v.x);
-      w[oa] = wa;
-      d += (double)pa[e] * (double)wa;
-      if (rb < n) {
-        const float wb = fmaf(lam2, pb[e], v.y);
-        w[oa + n] = wb;
-        d += (double)pb[e] * (double)wb;
-      }
+  for (int i = 0; i < OPT; ++i) {
+    const int q = threadIdx.x + i * C::NT, b = q % C::B, j = q / C::B, line = line0 + b;
+    if (q >= C::B * C::L || j >= n || line >= nl) continue;
+    const float2* zb = A + b * C::LP;
+    float2 t = zb[j];
+    if (j < hf) t = cadd(t, zb[C::L - 1 - j]);
+    if (j >= n - hf) t = cadd(t, zb[2 * n - 1 - j]);
+    const int ra = 2 * line, rb = ra + 1;
+    const float wa = fmaf(lam2, pa[i], t.x);
+    w[(size_t)ra * n + j] = wa;
+    dsum += (double)pa[i] * (double)wa;
+    if (rb < n) {
+      const float wb = fmaf(lam2, pb[i], t.y);
+      w[(size_t)rb * n + j] = wb;
+      dsum += (double)pb[i] * (double)wb;
     }
   }
-  const double tot = block_sum<FT>(d, sh);
-  if (threadIdx.x == 0 && partials) partials[SLOT_DELTA * MAX_PARTIALS + blockIdx.x] = tot;
+  const double tot = block_sum<C::NT>(dsum, sh);
+  if (threadIdx.x == 0 && partials) partials[SLOT_DELTA * MAX_PARTIALS + grp] = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -516,28 +611,48 @@ __global__ void fft_psf_cols_kernel(const double2* __restrict__ G, int K, int L,
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-int fft_length(int n, int k) {
-  const int h = (k - 1) / 2;
-  for (int L = n + h + ((n + h) & 1);; L += 2) {
-    int r = L;
-    for (int f : {2, 3, 5, 7})
-      while (r % f == 0) r /= f;
-    if (r == 1) return L;
-  }
+// the transform lengths L = R1 R2 R3 the kernels are built for (radices of
+// the three Stockham stages), in increasing order; L <= FFT_MAX_L
+#define KPCG_FFT_SIZES(X)                                                                      \
+  X(4, 4, 4) X(4, 4, 6) X(4, 4, 8) X(4, 6, 6) X(4, 6, 8) X(4, 8, 8) X(4, 8, 10) X(6, 8, 8)    \
+  X(6, 8, 10) X(6, 9, 10) X(7, 8, 10) X(8, 8, 9) X(7, 8, 12) X(8, 8, 12) X(7, 8, 16)          \
+  X(8, 8, 15) X(8, 8, 16) X(7, 10, 15) X(8, 9, 15) X(8, 12, 12) X(9, 12, 12) X(10, 12, 12)    \
+  X(10, 10, 16) X(12, 12, 12) X(10, 12, 16) X(12, 12, 14) X(10, 14, 15) X(12, 12, 15)         \
+  X(12, 12, 16)
+
+struct FftSize {
+  int r1, r2, r3;
+};
+static constexpr FftSize kFftSizes[] = {
+#define KPCG_FFT_ENTRY(a, b, c) {a, b, c},
+    KPCG_FFT_SIZES(KPCG_FFT_ENTRY)
+#undef KPCG_FFT_ENTRY
+};
+
+static int fft_menu_length(int need) {
+  for (const FftSize& z : kFftSizes)
+    if (z.r1 * z.r2 * z.r3 >= need) return z.r1 * z.r2 * z.r3;
+  return -1;
 }
+
+// the zero boundary's length: every wrapped tap must land in the zero pad,
+// L >= n + h
+int fft_length(int n, int k) { return fft_menu_length(n + (k - 1) / 2); }
 
 // the reflexive boundary's length: the image extended by h on each side
 // convolved with the PSF must not wrap onto the image, L >= n + 2h
-int fft_length_reflexive(int n, int k) { return fft_length(n + (k - 1) / 2, k); }
+int fft_length_reflexive(int n, int k) { return fft_menu_length(n + 2 * ((k - 1) / 2)); }
 
+// the radices of L's three stages, or -1
 int fft_radices(int L, int* rad) {
-  int m = L, c = 0;
-  while (m % 8 == 0) { rad[c++] = 8; m /= 8; }
-  while (m % 4 == 0) { rad[c++] = 4; m /= 4; }
-  while (m % 2 == 0) { rad[c++] = 2; m /= 2; }
-  for (int f : {3, 5, 7})
-    while (m % f == 0) { rad[c++] = f; m /= f; }
-  return m == 1 ? c : -1;
+  for (const FftSize& z : kFftSizes)
+    if (z.r1 * z.r2 * z.r3 == L) {
+      rad[0] = z.r1;
+      rad[1] = z.r2;
+      rad[2] = z.r3;
+      return 3;
+    }
+  return -1;
 }
 
 static FftGeom geom(const Plan& P) {
@@ -545,11 +660,12 @@ static FftGeom geom(const Plan& P) {
   g.n = P.n;
   g.L = P.fft_L;
   g.F = P.fft_L / 2 + 1;
-  g.nrad = P.fft_nrad;
-  for (int i = 0; i < FFT_MAX_RADICES; ++i) g.rad[i] = i < P.fft_nrad ? P.fft_rad[i] : 1;
   g.tw = reinterpret_cast<const float2*>(P.fft_tw);
   g.refl = P.bc == KP_BC_REFLEXIVE ? 1 : 0;
   g.h = (P.k - 1) / 2;
+  // S holds every row slot of the reflexive extension
+  g.spitch = P.n + 2 * g.h;
+  g.tpitch = P.n;
   return g;
 }
 
@@ -567,7 +683,64 @@ hipError_t build_fft_tables(const Plan& P, const double* psf_dev, void* g_scratc
   return hipGetLastError();
 }
 
-size_t fft_lds_bytes(int L) { return (size_t)3 * L * sizeof(float2); }   // a, b, twiddles
+// the dynamic LDS above 64 KB is granted once per kernel
+template <class Kern>
+static hipError_t grant_lds(Kern kern, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+// mode 0: w = A^T A p + lam2 p (all five passes); mode 1: w = A^T p (the
+// row pass of p, the column pass with conj Hc, the last row pass)
+template <class C>
+static hipError_t run_fft(const Plan& P, const FftGeom& g, int mode, const float* p, float* w,
+                          float lam2, double* partials, const Ctrl* ctrl, int* nb,
+                          hipStream_t s) {
+  static bool granted = false;
+  if (!granted) {
+    hipError_t e = grant_lds(fft_rows_fwd_kernel<C>, C::LDS);
+    if (e == hipSuccess) e = grant_lds(fft_cols_kernel<C>, C::LDS);
+    if (e == hipSuccess) e = grant_lds(fft_rows_mid_kernel<C>, C::LDS);
+    if (e == hipSuccess) e = grant_lds(fft_rows_out_kernel<C>, C::LDS);
+    if (e != hipSuccess) return e;
+    granted = true;
+  }
+  float2* S = reinterpret_cast<float2*>(P.fft_S);
+  float2* T = reinterpret_cast<float2*>(P.fft_T);
+  const float2* Ht = reinterpret_cast<const float2*>(P.fft_Ht);
+  const int n = g.n;
+  const int ext = (mode == 0 && g.refl) ? 1 : 0;
+  const int rows_in = ext ? n + 2 * g.h : n;
+  const int gr_in = ((rows_in + 1) / 2 + C::B - 1) / C::B;
+  const int gr = ((n + 1) / 2 + C::B - 1) / C::B;
+  auto pad8 = [](int v) { return (v + 7) / 8 * 8; };
+  const int gc = (C::F + C::B - 1) / C::B;
+  hipLaunchKernelGGL(fft_rows_fwd_kernel<C>, dim3(pad8(gr_in)), dim3(C::NT), C::LDS, s, p, g, ext, S,
+                     ctrl);
+  if (mode == 0) {
+    hipLaunchKernelGGL(fft_cols_kernel<C>, dim3(gc), dim3(C::NT), C::LDS, s, S, g, rows_in,
+                       ext ? g.h : 0, Ht, 0, 0, T, ctrl);
+    hipLaunchKernelGGL(fft_rows_mid_kernel<C>, dim3(pad8(gr)), dim3(C::NT), C::LDS, s, T, g, S, ctrl);
+  }
+  hipLaunchKernelGGL(fft_cols_kernel<C>, dim3(gc), dim3(C::NT), C::LDS, s, S, g, n, 0, Ht, 1,
+                     g.refl, T, ctrl);
+  hipLaunchKernelGGL(fft_rows_out_kernel<C>, dim3(pad8(gr)), dim3(C::NT), C::LDS, s, T, g, g.refl,
+                     mode == 0 ? p : nullptr, w, lam2, partials, ctrl);
+  if (nb) *nb = gr;
+  return hipGetLastError();
+}
+
+static hipError_t dispatch_fft(const Plan& P, int mode, const float* p, float* w, float lam2,
+                               double* partials, const Ctrl* ctrl, int* nb, hipStream_t s) {
+  const FftGeom g = geom(P);
+#define KPCG_FFT_CASE(a, b, c)                                                   \
+  if (P.fft_rad[0] == a && P.fft_rad[1] == b && P.fft_rad[2] == c && g.L == a * b * c) \
+    return run_fft<Sh3<a, b, c>>(P, g, mode, p, w, lam2, partials, ctrl, nb, s);
+  KPCG_FFT_SIZES(KPCG_FFT_CASE)
+#undef KPCG_FFT_CASE
+  return hipErrorInvalidValue;
+}
 
 // w = A^T A p + lam2 p with the partials of p . w (with_partials).  Zero
 // boundary: the plain passes.  Reflexive boundary: the first row pass
@@ -575,44 +748,12 @@ size_t fft_lds_bytes(int L) { return (size_t)3 * L * sizeof(float2); }   // a, b
 // them, and the passes of A^T fold the correlation back onto the image.
 hipError_t launch_fft_normal(const Plan& P, const float* p, float* w, float lam2, hipStream_t s,
                              int* nb, const Ctrl* ctrl, bool with_partials) {
-  const FftGeom g = geom(P);
-  const size_t lds = fft_lds_bytes(g.L);        // <= 3 * FFT_MAX_L * 8 B = 55.3 KB
-  float2* S = reinterpret_cast<float2*>(P.fft_S);
-  float2* T = reinterpret_cast<float2*>(P.fft_T);
-  const float2* Ht = reinterpret_cast<const float2*>(P.fft_Ht);
-  const int ext_rows = g.refl ? g.n + 2 * g.h : g.n;
-  const int rows = (g.n + 1) / 2;
-  const int cols = ((g.F + 7) / 8) * 8;
-  hipLaunchKernelGGL(fft_rows_fwd_kernel, dim3((ext_rows + 1) / 2), dim3(FT), lds, s, p, g,
-                     g.refl, S, ctrl);
-  hipLaunchKernelGGL(fft_cols_kernel, dim3(cols), dim3(FT), lds, s, S, g, ext_rows,
-                     g.refl ? g.h : 0, Ht, 0, 0, T, ctrl);
-  hipLaunchKernelGGL(fft_rows_mid_kernel, dim3(rows), dim3(FT), lds, s, T, g, S, ctrl);
-  hipLaunchKernelGGL(fft_cols_kernel, dim3(cols), dim3(FT), lds, s, S, g, g.n, 0, Ht, 1, g.refl,
-                     T, ctrl);
-  hipLaunchKernelGGL(fft_rows_out_kernel, dim3(rows), dim3(FT), lds, s, T, g, g.refl, p, w, lam2,
-                     with_partials ? P.partials : nullptr, ctrl);
-  if (nb) *nb = rows;
-  return hipGetLastError();
+  return dispatch_fft(P, 0, p, w, lam2, with_partials ? P.partials : nullptr, ctrl, nb, s);
 }
 
-// out = A^T u alone (the last three passes of the normal operator, the row
-// pass on u zero-padded); no control-block test, no partials.
+// out = A^T u alone; no control-block test, no partials.
 hipError_t launch_fft_at(const Plan& P, const float* u, float* out, hipStream_t s) {
-  const FftGeom g = geom(P);
-  const size_t lds = fft_lds_bytes(g.L);
-  float2* S = reinterpret_cast<float2*>(P.fft_S);
-  float2* T = reinterpret_cast<float2*>(P.fft_T);
-  const float2* Ht = reinterpret_cast<const float2*>(P.fft_Ht);
-  const int rows = (g.n + 1) / 2;
-  const int cols = ((g.F + 7) / 8) * 8;
-  hipLaunchKernelGGL(fft_rows_fwd_kernel, dim3(rows), dim3(FT), lds, s, u, g, 0, S,
-                     (const Ctrl*)nullptr);
-  hipLaunchKernelGGL(fft_cols_kernel, dim3(cols), dim3(FT), lds, s, S, g, g.n, 0, Ht, 1, g.refl,
-                     T, (const Ctrl*)nullptr);
-  hipLaunchKernelGGL(fft_rows_out_kernel, dim3(rows), dim3(FT), lds, s, T, g, g.refl,
-                     (const float*)nullptr, out, 0.0f, (double*)nullptr, (const Ctrl*)nullptr);
-  return hipGetLastError();
+  return dispatch_fft(P, 1, u, out, 0.0f, nullptr, nullptr, nullptr, s);
 }
 
 // ---------------------------------------------------------------------------
