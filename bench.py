@@ -82,6 +82,24 @@ VECTOR_KERNELS = {
 }
 
 
+# HBM traffic of one H p by FFTs (the five passes: rows_fwd, cols, rows_mid,
+# cols, rows_out) at the 1024^2, K=63 workload, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE) of `python bench.py --profile-only --modes
+# fp16_kp_fpcg --steps 2 --warmup 1`, the mean per launch of each pass scaled
+# by the calibration copy, summed over the passes of one H p.  Null when the
+# FFT source differs from the one measured (sha256 of fft.hip) or the plan's
+# transform length differs.
+FFT_TRAFFIC = {
+    "fft_length": 1080,
+    # per launch of each pass, as counted
+    "fetch_kib_raw": {"rows_fwd": 2147.5, "cols": 4609.4, "rows_mid": 2285.0, "rows_out": 4322.0},
+    "write_kib_raw": {"rows_fwd": 4395.5, "cols": 4328.0, "rows_mid": 4395.5, "rows_out": 4098.0},
+    "fetch_scale": 1.99978, "write_scale": 1.0,              # copy bytes / counter
+    "bytes_per_unit": 58867383,                               # one H p (two column passes)
+    "sources_sha256": "3198dbc3e091a224b9d8ef9e88b4f895ec0f40197654cd78155aa6c4840c99cb",
+}
+
+
 CPU_SAMPLE_S = 10.0       # the CPU oracle leg times at least this long ...
 CPU_SAMPLE_MAX = 60       # ... or this many solves
 
@@ -130,6 +148,29 @@ def blur_traffic(kernel: str):
             or BLUR_TRAFFIC["sources_sha256"] != blur_sources_sha256()):
         return None
     return BLUR_TRAFFIC["bytes_per_launch"]
+
+
+def fft_sources_sha256() -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2311_15393_amd", "csrc", "fft.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def fft_normal_bytes(n: int, L: int) -> int:
+    """Algorithmic HBM bytes of one H p by the five FFT passes: p read twice
+    and w written (FP32 n x n), the half spectra (F = L/2 + 1 frequencies of
+    n rows, FP32 complex) written by four passes and read by four, and the
+    PSF spectrum (F x L complex) read by both column passes."""
+    F = L // 2 + 1
+    return 3 * 4 * n * n + 8 * 8 * F * n + 2 * 8 * F * L
+
+
+def fft_traffic(L: int):
+    """Counter-measured HBM bytes per H p by FFTs at this length, or None."""
+    if (FFT_TRAFFIC is None or FFT_TRAFFIC["fft_length"] != L
+            or FFT_TRAFFIC["sources_sha256"] != fft_sources_sha256()):
+        return None
+    return FFT_TRAFFIC["bytes_per_unit"]
 
 
 def mfma_blur_flops(n: int, k: int, cfg: int = 6) -> float:
@@ -218,7 +259,7 @@ def run_instance(seed: int, modes, args, grid, dev, nthreads: int, keep: bool):
     solves (per-solve median)."""
     import torch
     import synthetic as S
-    from paper_2311_15393_amd import KP_OK, Plan
+    from paper_2311_15393_amd import KP_NORMAL_DIRECT, KP_NORMAL_FFT, KP_OK, Plan
     t0 = time.time()
     prob = S.large_moffat(seed)
     n = prob.n
@@ -228,6 +269,10 @@ def run_instance(seed: int, modes, args, grid, dev, nthreads: int, keep: bool):
     plan = Plan(prob.psf, n)
     torch.cuda.synchronize()
     setup_s = time.time() - t1
+    if args.normal_op != "auto":
+        # a profiler's per-launch overhead can tip the setup's choice between
+        # the two forms: profiling runs name the one the plain run picks
+        plan.set_normal_op(KP_NORMAL_FFT if args.normal_op == "fft" else KP_NORMAL_DIRECT)
     pinfo = plan.query()
     lam, _ = plan.gcv(b, grid)
     gidx = int(np.argmin(np.abs(grid - lam)))
@@ -317,7 +362,9 @@ def cpu_description() -> dict:
 
 def matvec_label(pinfo) -> str:
     if pinfo.get("normal_op") == 1:
-        return "A^T A p by FP32 zero-padded FFTs"
+        return ("A^T A p by FP32 zero-padded FFTs (A^T b and the true residuals on the "
+                + ("MFMA blur, FP16 hi/lo split" if pinfo["blur_config"] in (6, 7)
+                   else "FP32 VALU blur") + ")")
     if pinfo["blur_config"] in (6, 7):
         return "A p and A^T q on MFMA, FP16 hi/lo split (3 products, ~22-bit)"
     return "A p and A^T q on FP32 VALU"
@@ -333,6 +380,8 @@ def main():
                     help="seeds seed .. seed+S-1 of the large workload; the headline is the "
                          "median over them")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--normal-op", choices=("auto", "direct", "fft"), default="auto",
+                    help="form of H p in the solves (default: the setup's autotuned choice)")
     ap.add_argument("--profile-only", action="store_true",
                     help="skip the oracle parts (for profiler runs)")
     ap.add_argument("--no-periodic", action="store_true",
@@ -453,6 +502,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    blur_entry = None
     if pinfo["blur_config"] in (6, 7):
         if pinfo["blur_config"] == 6:
             kname = f"blur_mfma_kernel<{(k + 46) // 32}, EpiStoreF32>"
@@ -476,6 +526,24 @@ def main():
             "traffic": blur_traffic(kname),
             "kernel": kname + " (direct convolution A p, FP32 VALU)",
             "avg_us": blur_ms * 1e3,
+        }
+    if pinfo["normal_op"] == 1:
+        # the iterations' H p runs as the five FFT passes: that unit is the
+        # dominant work of an iteration; the blur (right-hand side and true
+        # residuals) is kept beside it
+        blur_entry = roofline
+        L = pinfo["fft_length"]
+        fft_s = normal_ms[1] * 1e-3
+        fbytes = fft_normal_bytes(n, L)
+        roofline = {
+            "bound": "hbm", "achieved": fbytes / fft_s / 1e9, "peak": HBM_PEAK / 1e9,
+            "unit": "GB/s", "frac": fbytes / fft_s / HBM_PEAK,
+            "traffic": fft_traffic(L),
+            "kernel": (f"H p by FFTs, L = {L}: fft_rows_fwd, fft_cols, fft_rows_mid, fft_cols, "
+                       "fft_rows_out (one unit of five launches; achieved = algorithmic bytes "
+                       f"{fbytes} / time)"),
+            "avg_us": normal_ms[1] * 1e3,
+            "blur": blur_entry,
         }
 
     cpu_baseline = None
