@@ -248,7 +248,10 @@ hipError_t launch_true_residual(const Plan& P, const float* b, const double* x, 
 }
 
 hipError_t launch_anchor_residual(const Plan& P, double lam2, bool fin, hipStream_t s) {
-  if (P.refl_general) return launch_fft_anchor_residual(P, lam2, fin, s);
+  // H (x - x_a) in the form the iterations use (the FFT passes: one H p
+  // instead of the two blurs)
+  if (P.refl_general || P.normal_op == KP_NORMAL_FFT)
+    return launch_fft_anchor_residual(P, lam2, fin, s);
   // q = fp32(x - x_a), z = A q, r = r_a - A^T z - lam2 (x - x_a)
   hipError_t err = launch_diff32(P, P.q, s);
   if (err != hipSuccess) return err;

@@ -612,13 +612,13 @@ __global__ void fft_psf_cols_kernel(const double2* __restrict__ G, int K, int L,
 // host side
 // ---------------------------------------------------------------------------
 // the transform lengths L = R1 R2 R3 the kernels are built for (radices of
-// the three Stockham stages), in increasing order; L <= FFT_MAX_L
+// the three Stockham stages), in increasing order; the largest covers the
+// reflexive boundary's n + 2h at n = 2048, K = 63 (L <= FFT_MAX_L)
 #define KPCG_FFT_SIZES(X)                                                                      \
   X(4, 4, 4) X(4, 4, 6) X(4, 4, 8) X(4, 6, 6) X(4, 6, 8) X(4, 8, 8) X(4, 8, 10) X(6, 8, 8)    \
   X(6, 8, 10) X(6, 9, 10) X(7, 8, 10) X(8, 8, 9) X(7, 8, 12) X(8, 8, 12) X(7, 8, 16)          \
   X(8, 8, 15) X(8, 8, 16) X(7, 10, 15) X(8, 9, 15) X(8, 12, 12) X(9, 12, 12) X(10, 12, 12)    \
-  X(10, 10, 16) X(12, 12, 12) X(10, 12, 16) X(12, 12, 14) X(10, 14, 15) X(12, 12, 15)         \
-  X(12, 12, 16)
+  X(10, 10, 16) X(12, 12, 12) X(10, 12, 16) X(12, 12, 14) X(10, 14, 15) X(12, 12, 15)
 
 struct FftSize {
   int r1, r2, r3;

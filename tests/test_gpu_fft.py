@@ -94,3 +94,43 @@ def test_fft_form_refused_off_the_zero_boundary():
         with pytest.raises(KPError) as ei:
             plan.set_normal_op(KP_NORMAL_FFT)
         assert ei.value.status == KP_ERR_UNSUPPORTED
+
+
+# every transform length the library's FFT menu holds (each is its own set of
+# kernels), with its three Stockham radices; the two largest are reached by
+# n = 2048 with K = 63 (zero boundary 2100, reflexive 2160)
+MENU = [64, 96, 128, 144, 192, 256, 320, 384, 480, 540, 560, 576, 672, 768, 896, 960, 1024,
+        1050, 1080, 1152, 1296, 1440, 1600, 1728, 1920, 2016, 2100, 2160]
+
+
+@pytest.mark.parametrize("L", MENU)
+def test_fft_normal_every_menu_length(L):
+    """H p by the FFT passes at n = L - h (so that L is the plan's length)
+    for every length of the menu against the oracle's operator (normwise
+    1e-5): n odd (K = 15; the last row pair has one row) below 2048, and the
+    two largest lengths at n = 2048, K = 63 (zero and reflexive boundary)."""
+    torch = require_gpu()
+    from paper_2311_15393_amd import KP_BC_REFLEXIVE, KP_NORMAL_FFT, Plan
+    from oracle import reflexive as RB
+    if L == 2100:
+        n, k, bc = 2048, 63, 0
+    elif L == 2160:
+        n, k, bc = 2048, 63, KP_BC_REFLEXIVE
+    else:
+        n, k, bc = L - 7, 15, 0
+    psf = _psf(k, L)
+    x = S.random_image(np.random.default_rng(L), n) - 0.5
+    lam = 0.02
+    with Plan(psf, n, bc=bc) as plan:
+        assert plan.query()["fft_length"] == L
+        y = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        plan.normal(to_dev(x), lam, y, op=KP_NORMAL_FFT)
+        got = to_host(y)
+    x64 = x.astype(np.float64)
+    if bc == KP_BC_REFLEXIVE:
+        ref = RB.NormalOperatorGeneral(psf, n, lam).H(x64)
+    else:
+        ref = O.normal_op(psf, lam, x64, O.FFTBlur(psf, n) if n > 256 else None)
+    e = rel(got, ref)
+    say(f"menu L={L} n={n} K={k} bc={bc}: |fft - ref| {e:.2e}")
+    assert e <= 1e-5
