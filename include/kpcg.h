@@ -71,7 +71,9 @@ extern "C" {
                                    such a plan's solves use KP_NORMAL_FFT
                                    and tol >= 1e-7, and the FP64 normal
                                    operator, the direct normal form and
-                                   batched solves give KP_ERR_UNSUPPORTED  */
+                                   batched solves give KP_ERR_UNSUPPORTED,
+                                   and so does kp_setup where n + K - 1
+                                   exceeds the FFT menu's 2160          */
 #define KP_SETUP_LOWP   0x100   /* flag OR-ed into kp_setup's bc: reduced-
                                    precision construction of S, V_r, V_c
                                    (Section 3 leaves computing them in half
@@ -146,7 +148,8 @@ typedef struct kp_plan_info_s {
     int32_t blur_config;    /* blur tile shape picked by the setup-time
                                autotuner (index into its candidate list)  */
     float   blur_config_ms[8]; /* autotuner time per candidate (ms)       */
-    int32_t fft_length;     /* L of the FFT form (zero-padded L x L grid)   */
+    int32_t fft_length;     /* L of the FFT form (zero-padded L x L grid),
+                               0: no FFT form at this size                 */
     float   normal_op_ms[2];   /* autotuner time of H p: direct, FFT (ms)  */
 } kp_plan_info_t;
 
@@ -508,7 +511,8 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int *prev);
  *    kernel kp_set_blur_config selects);
  *  - KP_NORMAL_FFT: zero-padded FFTs (Section 2.3 names FFTs for
  *    structured A; Section 5.2's cost model assumes cheap matvecs): with L
- *    the smallest even 2,3,5,7-smooth size >= n + (K-1)/2 and Hc the L x L
+ *    the smallest length >= n + (K-1)/2 in a fixed menu of 28 products of
+ *    three radices (64 .. 2160; none beyond: no FFT form) and Hc the L x L
  *    DFT of the PSF wrapped around the origin, A p = crop(IDFT(Hc .*
  *    DFT(pad p))) and A^T q = crop(IDFT(conj(Hc) .* DFT(pad q))) on the
  *    n x n window (exact: every wrapped tap lands in the zero pad).  For
@@ -519,8 +523,10 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int *prev);
  *    Stockham FFTs in LDS; FP32 with the PSF spectrum and twiddles
  *    computed in FP64.
  * kp_setup times both on the plan and the solver uses the faster.  The FFT
- * form is offered for KP_BC_ZERO and KP_BC_REFLEXIVE plans (periodic:
- * direct; forcing FFT gives KP_ERR_UNSUPPORTED); a reflexive plan whose
+ * form is offered for KP_BC_ZERO and KP_BC_REFLEXIVE plans whose length
+ * is on the menu (otherwise, and for periodic plans: direct; forcing FFT
+ * gives KP_ERR_UNSUPPORTED, kp_plan_info reports fft_length 0); a reflexive
+ * plan whose
  * PSF is not symmetric has the FFT form only (forcing direct gives
  * KP_ERR_UNSUPPORTED).
  * kp_set_normal_op forces a form for pcg_solve's iterations (true residuals

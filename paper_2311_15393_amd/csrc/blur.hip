@@ -178,7 +178,7 @@ hipError_t autotune_normal(Plan& P, hipStream_t s) {
   // is not symmetric the reflexive A^T is no blur and the FFT form is the
   // only one
   const int op0 = P.refl_general ? 1 : 0;
-  const int nops = (P.bc == KP_BC_ZERO || P.bc == KP_BC_REFLEXIVE) ? 2 : 1;
+  const int nops = (P.fft_L > 0 && (P.bc == KP_BC_ZERO || P.bc == KP_BC_REFLEXIVE)) ? 2 : 1;
   P.normal_times[0] = P.normal_times[1] = 0.f;
   for (int op = op0; op < nops && err == hipSuccess; ++op) {
     auto run = [&]() {

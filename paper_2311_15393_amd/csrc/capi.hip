@@ -82,13 +82,14 @@ size_t layout(int n, int k, char* base, Plan* P, char** scratch = nullptr) {
   Q.VrT8s = b.take<uint8_t>(nsc);
   Q.UcT32 = b.take<float>(nn);
   Q.UrT32 = b.take<float>(nn);
-  // FFT tables and work arrays sized for the longer (reflexive) length; the
-  // zero boundary's length is the default, kp_setup sets the plan's own
+  // FFT tables and work arrays sized for the longer of the two lengths (none
+  // where the menu has no length for either); the zero boundary's length is
+  // the default, kp_setup sets the plan's own
   const int fL = fft_length(n, k);
-  const int fLm = fft_length_reflexive(n, k), fFm = fLm / 2 + 1;
+  const int fLm = fft_table_length(n, k), fFm = fLm > 0 ? fLm / 2 + 1 : 0;
   const int hh = (k - 1) / 2;
   Q.fft_L = fL;
-  Q.fft_nrad = fft_radices(fL, Q.fft_rad);
+  Q.fft_nrad = fL > 0 ? fft_radices(fL, Q.fft_rad) : 0;
   Q.fft_tw = b.take<float2>((size_t)fLm);
   Q.fft_Ht = b.take<float2>((size_t)fFm * fLm);
   Q.spec = b.take<double>((((nn * sizeof(float)) + ALIGN - 1) / ALIGN * ALIGN) / sizeof(double) +
@@ -151,24 +152,35 @@ int write_ctrl(Plan& P, hipStream_t s, const Ctrl& c) {
 // without, that step ran already (the right-hand side, a true residual).
 // The direction step is folded into p = z + beta p.  Publishes twice with
 // fold_rr (||r||, then r.z), else once; CG publishes nothing here.
+// PCG and FPCG on the FFT form of a zero-boundary plan take the direction
+// step in the first pass of the next H p instead (enqueue_matvec_half); the
+// tail is then the preconditioner alone and publishes only with fold_rr.
+bool dir_in_matvec(const Plan& P, int solver) {
+  return solver != KP_CG && P.normal_op == KP_NORMAL_FFT && P.bc == KP_BC_ZERO;
+}
+
 hipError_t enqueue_tail(Plan& P, int solver, int prec, float lam2, hipStream_t s,
                         int fold_rr = 0) {
   hipError_t e;
   if (solver == KP_CG) return launch_pupdate_from(P, P.r, s);
   e = launch_precond(P, P.r, P.z, P.w, prec, true, lam2, s, fold_rr);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || dir_in_matvec(P, solver)) return e;
   return launch_pupdate_fold(P, P.z, precond_partials(P, prec), s);
 }
 
 // The first half of an iteration: matvecs, step length, update.  With
 // rr_step the residual-norm step follows as a launch of its own (CG, and the
 // last iteration of a solve, where no preconditioner follows to fold it in)
-// and publishes; without, it publishes nothing.
-hipError_t enqueue_matvec_half(Plan& P, float lam2, hipStream_t s, bool rr_step = true) {
+// and publishes.  With dir_in_matvec the first FFT pass takes the direction
+// step of the tail before it and publishes r.z.
+hipError_t enqueue_matvec_half(Plan& P, int solver, int prec, float lam2, hipStream_t s,
+                               bool rr_step = true) {
   hipError_t e;
   int nbd = 0;
   if (P.normal_op == KP_NORMAL_FFT) {
-    e = launch_fft_normal(P, P.p, P.w, lam2, s, &nbd, P.ctrl);  // w = H p, p.w (FFTs)
+    // w = H p, p.w (FFTs); first p = z + beta p
+    e = dir_in_matvec(P, solver) ? launch_fft_normal_dir(P, lam2, precond_partials(P, prec), s, &nbd)
+                                 : launch_fft_normal(P, P.p, P.w, lam2, s, &nbd, P.ctrl);
     if (e != hipSuccess) return e;
   } else {
     e = launch_blur_f32(P, P.p, P.q, false, s, P.ctrl);         // q = A p
@@ -180,7 +192,7 @@ hipError_t enqueue_matvec_half(Plan& P, float lam2, hipStream_t s, bool rr_step 
 }
 
 hipError_t enqueue_iteration(Plan& P, int solver, int prec, float lam2, hipStream_t s) {
-  hipError_t e = enqueue_matvec_half(P, lam2, s, true);
+  hipError_t e = enqueue_matvec_half(P, solver, prec, lam2, s, true);
   if (e != hipSuccess) return e;
   return enqueue_tail(P, solver, prec, lam2, s);
 }
@@ -270,6 +282,8 @@ int kp_setup(const double* psf, int k, int n, int bc_flags, void* workspace, siz
         asym = std::fmax(asym, std::fabs(psf[a * k + b] - psf[a * k + (k - 1 - b)]));
       }
     refl_general = asym > 1e-12 * mx;
+    // such a plan's A^T exists only in the FFT form
+    if (refl_general && fft_length_reflexive(n, k) <= 0) return KP_ERR_UNSUPPORTED;
   }
   for (int i = 0; i < k * k; ++i)
     if (!std::isfinite(psf[i])) return KP_ERR_ARG;
@@ -311,7 +325,7 @@ int kp_setup(const double* psf, int k, int n, int bc_flags, void* workspace, siz
   if (bc == KP_BC_REFLEXIVE) {
     // the reflexive FFT form transforms the image extended by h per side
     P.fft_L = fft_length_reflexive(n, k);
-    P.fft_nrad = fft_radices(P.fft_L, P.fft_rad);
+    P.fft_nrad = P.fft_L > 0 ? fft_radices(P.fft_L, P.fft_rad) : 0;
   }
   if (hipHostMalloc(reinterpret_cast<void**>(&P.host_ctrl), 2 * sizeof(Ctrl)) != hipSuccess) {
     if (P.owns) hipFree(base);
@@ -367,7 +381,7 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t* out) {
   out->device_bytes = P.bytes;
   out->blur_config = P.blur_cfg;
   for (int i = 0; i < 8; ++i) out->blur_config_ms[i] = P.blur_times[i];
-  out->fft_length = P.fft_L;
+  out->fft_length = P.fft_L > 0 ? P.fft_L : 0;
   out->normal_op_ms[0] = P.normal_times[0];
   out->normal_op_ms[1] = P.normal_times[1];
   return KP_OK;
@@ -471,9 +485,11 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   // step, update) and the tail (preconditioner, whose first GEMM takes the
   // update's residual-norm step and publishes ||r||; direction: publishes
   // r.z); the matvec half of the last iteration, which no tail follows,
-  // launches its own residual-norm step.  For CG an iteration publishes
-  // once (||r||).  Kernels enqueued after the device has marked the solve
-  // PENDING or finished exit at once and publish nothing.
+  // launches its own residual-norm step.  With dir_in_matvec the direction
+  // step (and its r.z) moves into the next matvec half: every matvec half
+  // follows a tail.  For CG an iteration publishes once (||r||).  Kernels
+  // enqueued after the device has marked the solve PENDING or finished exit
+  // at once and publish nothing.
   constexpr unsigned LOOKAHEAD = 2;
   Snap m{};
   unsigned seen = 0;             // the last publication read (mod 2^24)
@@ -490,9 +506,10 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
     bump();
     ++replacements;
   }
+  const bool dir = dir_in_matvec(P, solver);
   // first direction p = z_0 (CG: p = r_0)
   HIPCHK(enqueue_tail(P, solver, prec, lam2, s));
-  if (solver != KP_CG) bump();
+  if (solver != KP_CG && !dir) bump();
   auto top_up = [&]() -> hipError_t {
     while (inflight() < LOOKAHEAD && its < maxit) {
       hipError_t e;
@@ -502,15 +519,16 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
         bump();
       } else if (mv_next) {
         const bool last = its + 1 >= maxit;      // no tail will follow
-        e = enqueue_matvec_half(P, lam2, s, last);
+        e = enqueue_matvec_half(P, solver, prec, lam2, s, last);
         ++its;
         mv_next = false;
         fold_next = !last;
+        if (dir) bump();
         if (last) bump();
       } else {
         e = enqueue_tail(P, solver, prec, lam2, s, fold_next ? update_partials(P) : 0);
         if (fold_next) bump();
-        bump();
+        if (!dir) bump();
         mv_next = true;
         fold_next = false;
       }
@@ -961,7 +979,7 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int* prev) {
 // The forms of H p a plan can use: the FFT form for the zero and reflexive
 // boundaries; the direct blurs unless A^T is not a blur (refl_general).
 static bool normal_op_valid(const Plan& P, int op) {
-  if (op == KP_NORMAL_FFT) return P.bc == KP_BC_ZERO || P.bc == KP_BC_REFLEXIVE;
+  if (op == KP_NORMAL_FFT) return P.fft_L > 0 && (P.bc == KP_BC_ZERO || P.bc == KP_BC_REFLEXIVE);
   return !P.refl_general;
 }
 

@@ -275,10 +275,8 @@ __device__ inline double beta_of(const Ctrl* c, double rz, double zw, bool* ok) 
   return -zw / c->delta;
 }
 
-// FFT normal operator limits: L <= 2304 for n <= 2048, K <= 63 (zero
-// boundary n + h, reflexive n + 2h, rounded up to a 7-smooth length)
-constexpr int FFT_MAX_RADICES = 12;
-constexpr int FFT_MAX_L = 2304;
+// radices of the FFT form's transform length (three stages)
+constexpr int FFT_MAX_RADICES = 3;
 
 // ---------------------------------------------------------------------------
 // plan
@@ -474,13 +472,20 @@ hipError_t build_mfma_taps(const Plan& P, hipStream_t s);
 
 // FFT form of w = A^T A p + lam2 p with the partials of p.w (fft.hip); the
 // plan's FFT length and radices, and the twiddle / PSF-spectrum tables
-// (g_scratch: K (L/2 + 1) complex FP64)
+// (g_scratch: K (L/2 + 1) complex FP64).  The lengths come from a fixed
+// menu; -1: no menu length is long enough (no FFT form for the plan).
 int fft_length(int n, int k);
 int fft_radices(int L, int* rad);
+// the longer of the two boundaries' lengths that exist (the size of the FFT
+// tables and work arrays), 0 when neither does
+int fft_table_length(int n, int k);
 hipError_t build_fft_tables(const Plan& P, const double* psf_dev, void* g_scratch,
                             hipStream_t s);
 hipError_t launch_fft_normal(const Plan& P, const float* p, float* w, float lam2, hipStream_t s,
                              int* nb, const Ctrl* ctrl, bool with_partials = true);
+// the same with the direction step p = z + beta p folded into its first pass
+// (zero boundary; beta from nbz partials of r.z, z.Hp; publishes)
+hipError_t launch_fft_normal_dir(const Plan& P, float lam2, int nbz, hipStream_t s, int* nb);
 // A^T u alone by FFTs into out (the reflexive boundary's A^T for any PSF)
 hipError_t launch_fft_at(const Plan& P, const float* u, float* out, hipStream_t s);
 // the right-hand side, the true residual from u = b - A x in P.q, and the

@@ -394,6 +394,89 @@ __global__ __launch_bounds__(C::NT) void fft_rows_fwd_kernel(const float* __rest
   split_store<C>(A, line0, nl, rows, S, g.spitch);
 }
 
+// The first row pass with the direction step of the iteration before it
+// folded in (zero boundary): every workgroup sums the nbz partials of r.z
+// and z.Hp of the preconditioner's last GEMM in the scalar step's order
+// and takes beta from them, forms p = z + beta p on its rows (each element
+// read and written by one thread) and transforms the new p; workgroup 0
+// stores r.z, z.Hp, beta (or the breakdown) and publishes.  The loads of z
+// and the old p are issued before the partials are summed.
+struct DirStep {
+  const float* z;
+  Ctrl* ctrl;
+  const double* partials;
+  int nbz;
+  CtrlMirror* mirror;
+};
+
+template <class C>
+__global__ __launch_bounds__(C::NT) void fft_rows_fwd_dir_kernel(float* __restrict__ p, FftGeom g,
+                                                               float2* __restrict__ S, DirStep ds) {
+  if (ds.ctrl->done != RUNNING) return;
+  extern __shared__ float2 fft_lds[];
+  __shared__ double sh[C::NT / 64 + 1];
+  float2* tw = fft_lds;
+  float2* A = tw + C::L;
+  float2* Bf = A + C::B * C::LP;
+  const int n = g.n, nl = (n + 1) / 2;
+  const int grp = xcd_line_group((nl + C::B - 1) / C::B);
+  if (grp < 0) return;                 // never workgroup 0
+  const int line0 = grp * C::B;
+  TwLoad<C::NT, C::TWN> ts;
+  ts.load(g.tw, C::L);
+  // this thread's task of stage 1 (one per thread): line b, positions
+  // j + r L/R1; z and the old p of rows 2 line, 2 line + 1 there
+  constexpr int R = C::R1, J = C::L / R;
+  const int q = threadIdx.x, b = q % C::B, j = q / C::B, line = line0 + b;
+  const bool task = q < C::B * J, rows_in = line < nl;
+  const int sa = 2 * line, sb = sa + 1;
+  float pa[R], pb[R], za[R], zb[R];
+  static_for<0, R>([&](auto r) {
+    const int t = j + decltype(r)::value * J;
+    const bool in = task && rows_in && t < n;
+    pa[r] = in ? p[(size_t)sa * n + t] : 0.f;
+    za[r] = in ? ds.z[(size_t)sa * n + t] : 0.f;
+    pb[r] = (in && sb < n) ? p[(size_t)sb * n + t] : 0.f;
+    zb[r] = (in && sb < n) ? ds.z[(size_t)sb * n + t] : 0.f;
+  });
+  const double rz = fold_slot<C::NT>(ds.partials, SLOT_RZ, ds.nbz, sh);
+  const double zw = fold_slot<C::NT>(ds.partials, SLOT_ZW, ds.nbz, sh);
+  bool ok;
+  const double beta = beta_of(ds.ctrl, rz, zw, &ok);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ds.ctrl->rz = rz;
+    ds.ctrl->zw = zw;
+    if (ok) ds.ctrl->beta = beta;
+    else ds.ctrl->done = BREAKDOWN;
+    if (ds.mirror != nullptr) publish_mirror(ds.ctrl, ds.mirror);
+  }
+  if (!ok) return;
+  const float bt = (float)beta;
+  ts.store(tw, C::L);
+  if (task) {
+    float2 v[R];
+    static_for<0, R>([&](auto r) {
+      const int t = j + decltype(r)::value * J;
+      v[r] = make_float2(fmaf(bt, pa[r], za[r]), fmaf(bt, pb[r], zb[r]));
+      if (rows_in && t < n) {
+        p[(size_t)sa * n + t] = v[r].x;
+        if (sb < n) p[(size_t)sb * n + t] = v[r].y;
+      }
+    });
+    dft_dir<R, false>(v);
+    static_for<0, R>([&](auto r) { A[b * C::LP + j * R + decltype(r)::value] = v[r]; });
+  }
+  __syncthreads();
+  sh_stage<C, C::R2, C::R1, false>([&](int bb, int t) { return A[bb * C::LP + t]; },
+                                   [&](int bb, int t, float2 v) { Bf[bb * C::LP + t] = v; }, tw);
+  __syncthreads();
+  sh_stage<C, C::R3, C::R1 * C::R2, false>([&](int bb, int t) { return Bf[bb * C::LP + t]; },
+                                           [&](int bb, int t, float2 v) { A[bb * C::LP + t] = v; },
+                                           tw);
+  __syncthreads();
+  split_store<C>(A, line0, nl, n, S, g.spitch);
+}
+
 // Column pass: column k of S (its in_rows row slots, slot s at the circular
 // row position s - in_off, the rest zero), its transform times the PSF
 // spectrum (or its conjugate), the inverse; rows 0 .. n-1 kept, or with fold
@@ -613,7 +696,8 @@ __global__ void fft_psf_cols_kernel(const double2* __restrict__ G, int K, int L,
 // ---------------------------------------------------------------------------
 // the transform lengths L = R1 R2 R3 the kernels are built for (radices of
 // the three Stockham stages), in increasing order; the largest covers the
-// reflexive boundary's n + 2h at n = 2048, K = 63 (L <= FFT_MAX_L)
+// reflexive boundary's n + 2h at n = 2048, K = 63, and a plan that needs a
+// longer one has no FFT form
 #define KPCG_FFT_SIZES(X)                                                                      \
   X(4, 4, 4) X(4, 4, 6) X(4, 4, 8) X(4, 6, 6) X(4, 6, 8) X(4, 8, 8) X(4, 8, 10) X(6, 8, 8)    \
   X(6, 8, 10) X(6, 9, 10) X(7, 8, 10) X(8, 8, 9) X(7, 8, 12) X(8, 8, 12) X(7, 8, 16)          \
@@ -643,6 +727,12 @@ int fft_length(int n, int k) { return fft_menu_length(n + (k - 1) / 2); }
 // convolved with the PSF must not wrap onto the image, L >= n + 2h
 int fft_length_reflexive(int n, int k) { return fft_menu_length(n + 2 * ((k - 1) / 2)); }
 
+int fft_table_length(int n, int k) {
+  const int a = fft_length(n, k), b = fft_length_reflexive(n, k);
+  const int m = a > b ? a : b;
+  return m > 0 ? m : 0;
+}
+
 // the radices of L's three stages, or -1
 int fft_radices(int L, int* rad) {
   for (const FftSize& z : kFftSizes)
@@ -671,6 +761,7 @@ static FftGeom geom(const Plan& P) {
 
 hipError_t build_fft_tables(const Plan& P, const double* psf_dev, void* g_scratch,
                             hipStream_t s) {
+  if (P.fft_L <= 0) return hipSuccess;     // no FFT form at this size
   const int L = P.fft_L, F = L / 2 + 1, K = P.k;
   hipLaunchKernelGGL(fft_tw_kernel, dim3((L + 255) / 256), dim3(256), 0, s, L,
                      reinterpret_cast<float2*>(P.fft_tw));
@@ -696,10 +787,11 @@ static hipError_t grant_lds(Kern kern, size_t lds) {
 template <class C>
 static hipError_t run_fft(const Plan& P, const FftGeom& g, int mode, const float* p, float* w,
                           float lam2, double* partials, const Ctrl* ctrl, int* nb,
-                          hipStream_t s) {
+                          const DirStep* dir, hipStream_t s) {
   static bool granted = false;
   if (!granted) {
     hipError_t e = grant_lds(fft_rows_fwd_kernel<C>, C::LDS);
+    if (e == hipSuccess) e = grant_lds(fft_rows_fwd_dir_kernel<C>, C::LDS);
     if (e == hipSuccess) e = grant_lds(fft_cols_kernel<C>, C::LDS);
     if (e == hipSuccess) e = grant_lds(fft_rows_mid_kernel<C>, C::LDS);
     if (e == hipSuccess) e = grant_lds(fft_rows_out_kernel<C>, C::LDS);
@@ -716,8 +808,12 @@ static hipError_t run_fft(const Plan& P, const FftGeom& g, int mode, const float
   const int gr = ((n + 1) / 2 + C::B - 1) / C::B;
   auto pad8 = [](int v) { return (v + 7) / 8 * 8; };
   const int gc = (C::F + C::B - 1) / C::B;
-  hipLaunchKernelGGL(fft_rows_fwd_kernel<C>, dim3(pad8(gr_in)), dim3(C::NT), C::LDS, s, p, g, ext, S,
-                     ctrl);
+  if (dir != nullptr)
+    hipLaunchKernelGGL(fft_rows_fwd_dir_kernel<C>, dim3(pad8(gr_in)), dim3(C::NT), C::LDS, s,
+                       const_cast<float*>(p), g, S, *dir);
+  else
+    hipLaunchKernelGGL(fft_rows_fwd_kernel<C>, dim3(pad8(gr_in)), dim3(C::NT), C::LDS, s, p, g,
+                       ext, S, ctrl);
   if (mode == 0) {
     hipLaunchKernelGGL(fft_cols_kernel<C>, dim3(gc), dim3(C::NT), C::LDS, s, S, g, rows_in,
                        ext ? g.h : 0, Ht, 0, 0, T, ctrl);
@@ -732,11 +828,12 @@ static hipError_t run_fft(const Plan& P, const FftGeom& g, int mode, const float
 }
 
 static hipError_t dispatch_fft(const Plan& P, int mode, const float* p, float* w, float lam2,
-                               double* partials, const Ctrl* ctrl, int* nb, hipStream_t s) {
+                               double* partials, const Ctrl* ctrl, int* nb, const DirStep* dir,
+                               hipStream_t s) {
   const FftGeom g = geom(P);
 #define KPCG_FFT_CASE(a, b, c)                                                   \
   if (P.fft_rad[0] == a && P.fft_rad[1] == b && P.fft_rad[2] == c && g.L == a * b * c) \
-    return run_fft<Sh3<a, b, c>>(P, g, mode, p, w, lam2, partials, ctrl, nb, s);
+    return run_fft<Sh3<a, b, c>>(P, g, mode, p, w, lam2, partials, ctrl, nb, dir, s);
   KPCG_FFT_SIZES(KPCG_FFT_CASE)
 #undef KPCG_FFT_CASE
   return hipErrorInvalidValue;
@@ -748,12 +845,29 @@ static hipError_t dispatch_fft(const Plan& P, int mode, const float* p, float* w
 // them, and the passes of A^T fold the correlation back onto the image.
 hipError_t launch_fft_normal(const Plan& P, const float* p, float* w, float lam2, hipStream_t s,
                              int* nb, const Ctrl* ctrl, bool with_partials) {
-  return dispatch_fft(P, 0, p, w, lam2, with_partials ? P.partials : nullptr, ctrl, nb, s);
+  return dispatch_fft(P, 0, p, w, lam2, with_partials ? P.partials : nullptr, ctrl, nb, nullptr,
+                      s);
+}
+
+// The iteration's matvec half with the direction step before it: p = z +
+// beta p in the first row pass (beta from the nbz partials of r.z and z.Hp
+// of the preconditioner's last GEMM; publishes), then w = A^T A p + lam2 p
+// with the partials of p . w (zero boundary only: each element of p is read
+// by one thread).
+hipError_t launch_fft_normal_dir(const Plan& P, float lam2, int nbz, hipStream_t s, int* nb) {
+  if (P.bc != KP_BC_ZERO || nbz > MAX_PARTIALS) return hipErrorInvalidValue;
+  DirStep d;
+  d.z = P.z;
+  d.ctrl = P.ctrl;
+  d.partials = P.partials;
+  d.nbz = nbz;
+  d.mirror = P.mirror_dev;
+  return dispatch_fft(P, 0, P.p, P.w, lam2, P.partials, P.ctrl, nb, &d, s);
 }
 
 // out = A^T u alone; no control-block test, no partials.
 hipError_t launch_fft_at(const Plan& P, const float* u, float* out, hipStream_t s) {
-  return dispatch_fft(P, 1, u, out, 0.0f, nullptr, nullptr, nullptr, s);
+  return dispatch_fft(P, 1, u, out, 0.0f, nullptr, nullptr, nullptr, nullptr, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -469,7 +469,7 @@ static size_t scratch_layout(int n, int K, size_t rocws, char* base, SetupScratc
   Q.pall = (double*)take(8 * 2 * KK);
   Q.G2 = (double*)take(8 * 2 * KK * (size_t)n);
   Q.D64 = (double*)take(8 * nn);
-  Q.fftG = take(16 * (size_t)K * (size_t)(fft_length_reflexive(n, K) / 2 + 1));
+  Q.fftG = take(16 * (size_t)K * (size_t)(fft_table_length(n, K) / 2 + 1));
   return (cur + 255) / 256 * 256;
 }
 

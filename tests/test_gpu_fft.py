@@ -134,3 +134,52 @@ def test_fft_normal_every_menu_length(L):
     e = rel(got, ref)
     say(f"menu L={L} n={n} K={k} bc={bc}: |fft - ref| {e:.2e}")
     assert e <= 1e-5
+
+
+# (solver, preconditioner, tol, bar): at lambda = 0.02 cond(H) is about
+# 2.5e3, so the tolerances sit 1-2 decades below the bars
+FFT_MODES = {"pcg16": ("KP_PCG", "KP_P16", 1e-7, 1e-4), "fpcg16": ("KP_FPCG", "KP_P16", 1e-7, 1e-4),
+             "pcg32": ("KP_PCG", "KP_P32", 1e-8, 1e-5), "fpcg32": ("KP_FPCG", "KP_P32", 1e-8, 1e-5),
+             "fpcg8": ("KP_FPCG", "KP_P8", 1e-7, 1e-4), "fpcg16_diag": ("KP_FPCG", "KP_P16", 1e-7, 1e-4)}
+
+
+@pytest.mark.parametrize("mode_name", list(FFT_MODES))
+def test_fft_solves_every_preconditioned_mode(mode_name):
+    """PCG and FPCG with H p by the FFT passes on a zero-boundary plan, where
+    the direction step p = z + beta p of each iteration runs in the first
+    pass of the next H p: every preconditioner precision (and the exact
+    diagonal) reaches x_lambda at 256^2, K = 21 with one history entry per
+    iteration; a solve cut at maxit = 3 stops at KP_MAXIT after exactly three
+    iterations, reporting the oracle's ||c - H x|| / ||c|| of its x; a warm
+    start from the solution converges again within a few iterations."""
+    torch = require_gpu()
+    import paper_2311_15393_amd as K
+    solver, prec, tol, bar = FFT_MODES[mode_name]
+    mode = getattr(K, solver) | getattr(K, prec)
+    if mode_name.endswith("_diag"):
+        mode |= K.KP_EXACT_DIAG
+    n, k, lam = 256, 21, 0.02            # n: a multiple of the FP8 GEMM tiles
+    psf = _psf(k, 11)
+    prob = S.make_problem(n, psf, np.random.default_rng(5), 0.01, None, 6, "fft")
+    b64 = prob.b.astype(np.float64)
+    ref = SV.x_lambda(psf, b64, lam)
+    c = O.blur_t(psf, b64)
+    with K.Plan(psf, n) as plan:
+        plan.set_normal_op(K.KP_NORMAL_FFT)
+        b = to_dev(prob.b)
+        x, info = plan.solve(b, lam, tol=tol, maxit=3000, mode=mode, history=True)
+        err = rel(to_host(x), ref)
+        say(f"{mode_name} via FFT: iters={info.iters} repl={info.replacements} err={err:.2e}")
+        assert info.status == K.KP_OK and err <= bar
+        assert info.history_rec.size == info.iters + 1 and np.all(np.isfinite(info.history_rec))
+        x3, info3 = plan.solve(b, lam, tol=tol, maxit=3, mode=mode | K.KP_NO_FALLBACK,
+                               raise_on_fail=False)
+        x3_64 = to_host(x3).astype(np.float64)
+        r_or = np.linalg.norm(c - O.normal_op(psf, lam, x3_64)) / np.linalg.norm(c)
+        say(f"  maxit 3: status={info3.status} relres {info3.relres_true:.4e} oracle {r_or:.4e}")
+        assert info3.status == K.KP_MAXIT and info3.iters == 3
+        assert abs(info3.relres_true - r_or) <= 1e-2 * r_or
+        xw = x.clone()
+        xw, infow = plan.solve(b, lam, tol=tol, maxit=3000, mode=mode | K.KP_WARM, x=xw)
+        say(f"  warm start: iters={infow.iters}")
+        assert infow.status == K.KP_OK and infow.iters <= 3 and rel(to_host(xw), ref) <= bar
