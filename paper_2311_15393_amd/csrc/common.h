@@ -205,6 +205,40 @@ __device__ inline double fold_slot(const double* __restrict__ partials, int slot
   return sh[NT / 64];
 }
 
+// Two slots at once (one round of partial loads, one block reduction),
+// each summed exactly as fold_slot sums it.  sh: 2 (NT / 64 + 1) doubles.
+template <int NT>
+__device__ inline double2 fold_slot2(const double* __restrict__ partials, int slot_a, int slot_b,
+                                     int nb, double* sh) {
+  double a = 0.0, b = 0.0;
+  if (threadIdx.x < FOLD_T)
+    for (int i = threadIdx.x; i < nb; i += FOLD_T) {
+      a += partials[slot_a * MAX_PARTIALS + i];
+      b += partials[slot_b * MAX_PARTIALS + i];
+    }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sh[2 * wid] = a;
+    sh[2 * wid + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+      ta += sh[2 * w];
+      tb += sh[2 * w + 1];
+    }
+    sh[2 * (NT / 64)] = ta;
+    sh[2 * (NT / 64) + 1] = tb;
+  }
+  __syncthreads();
+  return make_double2(sh[2 * (NT / 64)], sh[2 * (NT / 64) + 1]);
+}
+
 // r.z of the current direction: the last direction step's (PCG, FPCG) or
 // ||r||^2 (CG)
 __device__ inline double step_rho(const Ctrl* c) { return c->solver == KP_CG ? c->rho : c->rz; }

@@ -414,7 +414,7 @@ __global__ __launch_bounds__(C::NT) void fft_rows_fwd_dir_kernel(float* __restri
                                                                float2* __restrict__ S, DirStep ds) {
   if (ds.ctrl->done != RUNNING) return;
   extern __shared__ float2 fft_lds[];
-  __shared__ double sh[C::NT / 64 + 1];
+  __shared__ double sh[2 * (C::NT / 64 + 1)];
   float2* tw = fft_lds;
   float2* A = tw + C::L;
   float2* Bf = A + C::B * C::LP;
@@ -439,8 +439,8 @@ __global__ __launch_bounds__(C::NT) void fft_rows_fwd_dir_kernel(float* __restri
     pb[r] = (in && sb < n) ? p[(size_t)sb * n + t] : 0.f;
     zb[r] = (in && sb < n) ? ds.z[(size_t)sb * n + t] : 0.f;
   });
-  const double rz = fold_slot<C::NT>(ds.partials, SLOT_RZ, ds.nbz, sh);
-  const double zw = fold_slot<C::NT>(ds.partials, SLOT_ZW, ds.nbz, sh);
+  const double2 f = fold_slot2<C::NT>(ds.partials, SLOT_RZ, SLOT_ZW, ds.nbz, sh);
+  const double rz = f.x, zw = f.y;
   bool ok;
   const double beta = beta_of(ds.ctrl, rz, zw, &ok);
   if (blockIdx.x == 0 && threadIdx.x == 0) {

@@ -97,9 +97,9 @@ __global__ __launch_bounds__(VT) void pupdate_fold_kernel(float* __restrict__ p,
                                                           int nbz,
                                                           CtrlMirror* __restrict__ mirror) {
   if (ctrl->done != RUNNING) return;
-  __shared__ double sh[VT / 64 + 1];
-  const double rz = fold_slot<VT>(partials, SLOT_RZ, nbz, sh);
-  const double zw = fold_slot<VT>(partials, SLOT_ZW, nbz, sh);
+  __shared__ double sh[2 * (VT / 64 + 1)];
+  const double2 f = fold_slot2<VT>(partials, SLOT_RZ, SLOT_ZW, nbz, sh);
+  const double rz = f.x, zw = f.y;
   bool ok;
   const double beta = beta_of(ctrl, rz, zw, &ok);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
