@@ -86,17 +86,20 @@ VECTOR_KERNELS = {
 # cols, rows_out) at the 1024^2, K=63 workload, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE) of `python bench.py --profile-only --modes
 # fp16_kp_fpcg --steps 2 --warmup 1`, the mean per launch of each pass scaled
-# by the calibration copy, summed over the passes of one H p.  Null when the
-# FFT source differs from the one measured (sha256 of fft.hip) or the plan's
-# transform length differs.
+# by the calibration copy, summed over the passes of one H p.  The unit is
+# the plain H p that kp_time_normal times (in that run's solves the profiler's
+# per-launch cost makes the setup pick the direct form, so the FFT launches
+# counted are the timing and autotuning ones).  Null when the FFT source
+# differs from the one measured (sha256 of fft.hip) or the plan's transform
+# length differs.
 FFT_TRAFFIC = {
     "fft_length": 1080,
     # per launch of each pass, as counted
-    "fetch_kib_raw": {"rows_fwd": 2147.5, "cols": 4609.4, "rows_mid": 2285.0, "rows_out": 4322.0},
+    "fetch_kib_raw": {"rows_fwd": 2143.1, "cols": 4611.9, "rows_mid": 2285.0, "rows_out": 4322.0},
     "write_kib_raw": {"rows_fwd": 4395.5, "cols": 4328.0, "rows_mid": 4395.5, "rows_out": 4098.0},
     "fetch_scale": 1.99978, "write_scale": 1.0,              # copy bytes / counter
-    "bytes_per_unit": 58867383,                               # one H p (two column passes)
-    "sources_sha256": "3198dbc3e091a224b9d8ef9e88b4f895ec0f40197654cd78155aa6c4840c99cb",
+    "bytes_per_unit": 58868555,                               # one H p (two column passes)
+    "sources_sha256": "af40b8b56832e968bc44c155f7279219a68aa9c6b8c6b481a021afdd48a2d2d1",
 }
 
 
