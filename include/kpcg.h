@@ -224,8 +224,9 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t *out);
  * FP32-class blur for tol >= 1e-7 and in FP64 below (a reflexive plan whose
  * PSF is not symmetric: by FFTs, tol < 1e-7 gives KP_ERR_UNSUPPORTED).
  * Later recomputations
- * add H (x - x_a) to the last true residual at x_a (FP32 matvecs on the step,
- * FP64 sums) once that residual is below 1e-2 ||A^T b||.
+ * subtract H (x - x_a) from the last true residual r_a at x_a (FP32 matvecs
+ * on the step, FP64 sums) once ||r_a|| is below min(1e-2, 1e4 tol) ||A^T b||
+ * (those matvecs err by up to about 1e-5 ||r_a||).
  *
  *   b       device, n*n float32 data
  *   lambda  > 0, tol > 0 (relative to ||A^T b||), maxit >= 1
@@ -279,7 +280,9 @@ int discrepancy_lambda(kp_plan_t plan, const float *b, const double *grid,
  * launches: item i solves with plan plans[plan_of_item[i]] (its PSF and
  * image size), data b[i], parameter lambdas[i], writing x[i].  All items
  * share tol, maxit and mode (solver and preconditioner bits and
- * KP_EXACT_DIAG as pcg_solve; KP_P8 is not supported here; with KP_WARM
+ * KP_EXACT_DIAG as pcg_solve; with KP_P8 every item's n must be a multiple
+ * of 128, else KP_ERR_UNSUPPORTED, and there is no FP32 restart of items
+ * that fail, which end with KP_MAXIT; with KP_WARM
  * every x[i] holds its item's initial guess, whose residual is a full FP64
  * true residual, e.g. the solution at the neighbouring lambda of a sweep;
  * KP_BATCH_EAGER launches the

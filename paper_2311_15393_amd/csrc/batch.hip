@@ -20,6 +20,7 @@
 #include "blur_core.h"
 #include "blur_mfma.h"
 #include "gemm_core.h"
+#include "gemm_fp8.h"
 
 namespace kpcg {
 
@@ -37,6 +38,9 @@ struct ItemDesc {
   const double *taps64, *taps64_flip;
   const _Float16 *VcT16, *Vc16, *Vr16, *VrT16;
   const float *VcT32, *Vc32, *Vr32, *VrT32;
+  const uint8_t *VcT8, *Vc8, *Vr8, *VrT8;        // e4m3 codes and their block exponents
+  const uint8_t *VcT8s, *Vc8s, *Vr8s, *VrT8s;
+  uint8_t *t1s, *t2s, *t3s;                      // block exponents of the FP8 intermediates
   const float *sc2, *sr2;
   const float* d0;                           // exact KP-basis diagonal (KP_EXACT_DIAG) or null
   const float* b;
@@ -249,6 +253,43 @@ __global__ __launch_bounds__(GT) void gemm_batched_kernel(const ItemDesc* __rest
   }
 }
 
+// the same four stages in FP8 (e4m3 codes with E8M0 block exponents, the
+// plan's chain of gemm_fp8.hip) over the same 64 x 64 tile table; the FP32
+// residual is quantised per block while staged, so no residual scale
+template <int STAGE>
+__global__ __launch_bounds__(G8T) void gemm8_batched_kernel(const ItemDesc* __restrict__ items,
+                                                            const TileRef* __restrict__ tiles,
+                                                            int mode) {
+  const TileRef tr = tiles[blockIdx.x];
+  const ItemDesc& it = items[tr.item];
+  if (!item_active(it.ctrl, mode)) return;
+  const int ty = tr.t / it.ntx_gemm, tx = tr.t - ty * it.ntx_gemm;
+  const int m0 = ty * B8M, n0 = tx * B8N;
+  uint8_t* t1 = reinterpret_cast<uint8_t*>(it.t1);
+  uint8_t* t2 = reinterpret_cast<uint8_t*>(it.t2);
+  uint8_t* t3 = reinterpret_cast<uint8_t*>(it.t3);
+  Gemm8Args a{};
+  a.n = it.n;
+  a.sc2 = it.sc2;
+  a.sr2 = it.sr2;
+  a.d0 = it.d0;
+  a.lam2 = it.lam2f;
+  if constexpr (STAGE == 1) {
+    a.A = it.VcT8; a.As = it.VcT8s; a.Bf32 = it.r; a.C = t1; a.Cs = it.t1s;
+    gemm8_tile<true, E8_ROWS>(a, m0, n0, it.ctrl, nullptr, 0, NoFold8{});
+  } else if constexpr (STAGE == 2) {
+    a.A = t1; a.As = it.t1s; a.B = it.VrT8; a.Bs = it.VrT8s; a.C = t2; a.Cs = it.t2s;
+    gemm8_tile<false, E8_SPRIME_T>(a, m0, n0, it.ctrl, nullptr, 0, NoFold8{});
+  } else if constexpr (STAGE == 3) {
+    a.A = it.Vc8; a.As = it.Vc8s; a.B = t2; a.Bs = it.t2s; a.C = t3; a.Cs = it.t3s;
+    gemm8_tile<false, E8_ROWS>(a, m0, n0, it.ctrl, nullptr, 0, NoFold8{});
+  } else {
+    a.A = t3; a.As = it.t3s; a.B = it.Vr8; a.Bs = it.Vr8s; a.z = it.z; a.r = it.r; a.w = it.w;
+    gemm8_tile<false, E8_FINAL>(a, m0, n0, it.ctrl, it.partials + SLOT_RZ * MAXP_ITEM + tr.t,
+                                MAXP_ITEM, NoFold8{});
+  }
+}
+
 // ---------------------------------------------------------------------------
 // batched vector kernels (one block per VCH floats of an item)
 // ---------------------------------------------------------------------------
@@ -406,7 +447,7 @@ __global__ __launch_bounds__(256) void scalar_batched_kernel(const ItemDesc* __r
     case SC_TRUE:
     case SC_TRUE_FAST:
       c->true_rr = S;
-      c->anchor = S <= ANCHOR_REL * ANCHOR_REL * c->gamma0sq ? 1 : 0;
+      c->anchor = anchor_eligible(c, S) ? 1 : 0;
       c->rr = S;
       c->repl2 = REPLACE_DROP * REPLACE_DROP * S;
       set_scales(c, S);
@@ -633,10 +674,24 @@ static hipError_t precond_b(const Batch& B, int mode) {
 }
 
 // z = M^{-1} r, r.z, beta, p = z + beta p (or the CG direction update)
+static hipError_t precond8_b(const Batch& B, int mode) {
+  hipLaunchKernelGGL(gemm8_batched_kernel<1>, dim3(B.n_gemm), dim3(G8T), 0, B.s, B.d_items,
+                     B.t_gemm, mode);
+  hipLaunchKernelGGL(gemm8_batched_kernel<2>, dim3(B.n_gemm), dim3(G8T), 0, B.s, B.d_items,
+                     B.t_gemm, mode);
+  hipLaunchKernelGGL(gemm8_batched_kernel<3>, dim3(B.n_gemm), dim3(G8T), 0, B.s, B.d_items,
+                     B.t_gemm, mode);
+  hipLaunchKernelGGL(gemm8_batched_kernel<4>, dim3(B.n_gemm), dim3(G8T), 0, B.s, B.d_items,
+                     B.t_gemm, mode);
+  return hipGetLastError();
+}
+
 static hipError_t tail_b(const Batch& B, int mode) {
   hipError_t e;
   if (B.solver == KP_CG) return vec_launch<VK_PUPDATE_R>(B, mode);
-  e = B.prec == KP_P16 ? precond_b<_Float16>(B, mode) : precond_b<float>(B, mode);
+  e = B.prec == KP_P16  ? precond_b<_Float16>(B, mode)
+      : B.prec == KP_P8 ? precond8_b(B, mode)
+                        : precond_b<float>(B, mode);
   if (e != hipSuccess) return e;
   if ((e = scalar_launch(B, SC_BETA, mode)) != hipSuccess) return e;
   return vec_launch<VK_PUPDATE_Z>(B, mode);
@@ -799,6 +854,7 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
     total += align(nn * 4) * 5;              // r p q w z
     total += align(nn * 8) * 4;              // x64 y64 xa64 ra64
     total += align(nn * 4) * 3;              // t1 t2 t3
+    total += align((nn + 31) / 32) * 3;      // their FP8 block exponents
     total += align(sizeof(double) * NSLOTS * MAXP_ITEM);
   }
   const size_t off_ctrl = total;
@@ -858,6 +914,9 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
     d.ntx_gemm = (n + BN - 1) / BN;
     d.nb_gemm = d.ntx_gemm * ((n + BM - 1) / BM);
     d.nb_vec = (n * n + VCH - 1) / VCH;
+    // the FP8 chain takes whole 128-wide contraction steps (as a plan's does)
+    static_assert(BM == B8M && BN == B8N, "the FP8 stages share the GEMM tile table");
+    if (B.prec == KP_P8 && !fp8_supported_size(n)) return KP_ERR_UNSUPPORTED;
     ntab += (size_t)d.nb_blur + d.nb_fast + d.nb_blur64 + d.nb_gemm + d.nb_vec + 1;
     if (d.nb_blur > MAXP_ITEM || d.nb_blur64 > MAXP_ITEM || d.nb_gemm > MAXP_ITEM ||
         d.nb_vec > MAXP_ITEM || d.nb_fast > MAXP_ITEM)
@@ -894,6 +953,8 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
     d.x64 = (double*)take(nn * 8); d.y64 = (double*)take(nn * 8);
     d.xa64 = (double*)take(nn * 8); d.ra64 = (double*)take(nn * 8);
     d.t1 = take(nn * 4); d.t2 = take(nn * 4); d.t3 = take(nn * 4);
+    d.t1s = (uint8_t*)take((nn + 31) / 32); d.t2s = (uint8_t*)take((nn + 31) / 32);
+    d.t3s = (uint8_t*)take((nn + 31) / 32);
     d.partials = (double*)take(sizeof(double) * NSLOTS * MAXP_ITEM);
     d.ctrl = B.d_ctrl + i;
     d.lam2 = lambdas[i] * lambdas[i];
@@ -903,6 +964,8 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
     d.VcT16 = (const _Float16*)P.VcT16; d.Vc16 = (const _Float16*)P.Vc16;
     d.Vr16 = (const _Float16*)P.Vr16; d.VrT16 = (const _Float16*)P.VrT16;
     d.VcT32 = P.VcT32; d.Vc32 = P.Vc32; d.Vr32 = P.Vr32; d.VrT32 = P.VrT32;
+    d.VcT8 = P.VcT8; d.Vc8 = P.Vc8; d.Vr8 = P.Vr8; d.VrT8 = P.VrT8;
+    d.VcT8s = P.VcT8s; d.Vc8s = P.Vc8s; d.Vr8s = P.Vr8s; d.VrT8s = P.VrT8s;
     d.sc2 = P.sc2; d.sr2 = P.sr2;
     d.d0 = (mode & KP_EXACT_DIAG) ? P.d0 : nullptr;
     d.b = b[i];

@@ -467,8 +467,9 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   // on the fast blur from TR_FAST_TOL on, else in FP64.
   // After one at x_a (residual r_a), later ones are computed as
   // r_a - H (x - x_a) with FP32 matvecs on the small step x - x_a: exact in
-  // exact arithmetic, with an error of ~1e-6 ||r_a||.  Used once
-  // ||r_a|| <= ANCHOR_REL ||A^T b||, so the error stays ~1e-9 ||A^T b||.
+  // exact arithmetic, with an error of up to ~1e-5 ||r_a||.  Used once
+  // ||r_a|| <= min(ANCHOR_REL, ANCHOR_TOL tol) ||A^T b||, so the error stays
+  // below a tenth of the tolerance.
   const int trmode =
       tol >= (blur_cfg_is_mfma(P.blur_cfg) ? TR_FASTU_TOL_MFMA : TR_FASTU_TOL_VALU) ? TR_FAST_ALL
       : tol >= TR_FAST_TOL                                                        ? TR_FAST_AT
@@ -723,7 +724,6 @@ static int batched_args(const kp_plan_t* plans, int nplans, const int* plan_of_i
   if ((mode & ~(KP_SOLVER_MASK | KP_PREC_MASK | KP_WARM | KP_BATCH_EAGER | KP_EXACT_DIAG)) != 0)
     return KP_ERR_ARG;
   if ((mode & KP_SOLVER_MASK) == 3 || (mode & KP_PREC_MASK) == KP_PREC_MASK) return KP_ERR_ARG;
-  if ((mode & KP_PREC_MASK) == KP_P8) return KP_ERR_UNSUPPORTED;
   ps.resize(nplans);
   for (int i = 0; i < nplans; ++i) {
     if (!plans[i]) return KP_ERR_ARG;

@@ -101,8 +101,13 @@ struct CtrlMirror {
 constexpr unsigned MIRROR_PUB_MASK = (1u << 24) - 1u;
 
 // A true residual r_a at x_a anchors later ones, r = r_a - H (x - x_a) with
-// FP32 matvecs on the step, once ||r_a|| <= ANCHOR_REL ||A^T b||.
+// FP32 matvecs on the step, once ||r_a|| <= ANCHOR_REL ||A^T b|| and
+// ||r_a|| <= ANCHOR_TOL tol ||A^T b||.  The FP32-class matvecs err by up to
+// about 1e-5 ||r_a|| (7e-6 measured on a reflexive FP16 solve at tol 2e-8),
+// so the second bound keeps the anchored residual within a tenth of the
+// tolerance; the first decides at loose tolerances.
 constexpr double ANCHOR_REL = 1e-2;
+constexpr double ANCHOR_TOL = 1e4;
 
 // True residuals are formed as A^T u - lambda^2 x from u = b - A x (FP64).
 // For tolerances >= TR_FAST_TOL the A^T u product runs on the FP32-class
@@ -278,12 +283,18 @@ __device__ inline void apply_rr(Ctrl* c, double S) {
   if (c->hist != nullptr && c->iter >= 0 && c->iter < KP_HIST_MAX) c->hist[c->iter] = S;
 }
 
+// Whether a true residual with ||r||^2 = true_rr may anchor the next ones.
+__device__ inline bool anchor_eligible(const Ctrl* c, double true_rr) {
+  const double lim = fmin(ANCHOR_REL * ANCHOR_REL, ANCHOR_TOL * ANCHOR_TOL * c->tol_rel2);
+  return true_rr <= lim * c->gamma0sq;
+}
+
 // The new state to the host mirror (one thread).
 __device__ inline void publish_mirror(Ctrl* __restrict__ c, CtrlMirror* __restrict__ mirror) {
   const unsigned p = ((unsigned)c->pub + 1u) & MIRROR_PUB_MASK;
   c->pub = (int)p;
   const bool tol_hit = c->rr <= c->tol2;
-  const bool anchor_ok = c->repl > 0 && c->true_rr <= ANCHOR_REL * ANCHOR_REL * c->gamma0sq;
+  const bool anchor_ok = c->repl > 0 && anchor_eligible(c, c->true_rr);
   const unsigned long long w =
       (unsigned long long)p | ((unsigned long long)(c->iter & 0xffffff) << 24) |
       ((unsigned long long)(c->done & 0xf) << 48) | ((unsigned long long)tol_hit << 52) |

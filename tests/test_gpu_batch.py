@@ -115,10 +115,38 @@ def test_batched_rejects_bad_arguments():
     with pytest.raises(KPError) as ei:
         solve_batched([plan], [b], [-1.0], [0], mode=KP_FPCG | KP_P16)
     assert ei.value.status == KP_ERR_ARG
+    # the FP8 chain needs n to be a multiple of 128 (this item: 64)
     with pytest.raises(KPError) as ei:
         solve_batched([plan], [b], [0.01], [0], mode=KP_FPCG | KP_P8)
     assert ei.value.status == KP_ERR_UNSUPPORTED
     plan.close()
+
+
+def test_batched_fp8_items_match_oracle():
+    """FP8-KP FPCG in the batch (items of 128^2 and 256^2, two lambda each):
+    every item meets the FP16 bar against x_lambda, and takes about as many
+    iterations as the same solve by pcg_solve with the plan's FP8 chain (a
+    wrong stage, exponent block or tile mapping in the batched chain would
+    change the preconditioner and with it the iteration count)."""
+    require_gpu()
+    from paper_2311_15393_amd import KP_FPCG, KP_NO_FALLBACK, KP_OK, KP_P8, Plan
+    probs, items = _small_batch()
+    items = [(p, lam) for p, lam in items if probs[p].n % 128 == 0]
+    assert len(items) == 4
+    plans = [Plan(p.psf, p.n) for p in probs]
+    tol = 1e-8
+    xs, infos, st = _run(plans, probs, items, KP_FPCG | KP_P8, tol, maxit=2000)
+    assert st == KP_OK
+    for (p, lam), x, inf in zip(items, xs, infos):
+        _, one = plans[p].solve(to_dev(probs[p].b), lam, tol=tol, maxit=2000,
+                                mode=KP_FPCG | KP_P8 | KP_NO_FALLBACK)
+        err = rel(x, _xlam(probs, p, lam))
+        say(f"  fp8 n={probs[p].n} lam={lam}: batch iters={inf.iters} single iters={one.iters} "
+            f"err={err:.2e}")
+        assert inf.status == KP_OK and inf.relres_true <= tol and err <= 1e-4
+        assert abs(inf.iters - one.iters) <= max(3, 0.3 * one.iters)
+    for pl in plans:
+        pl.close()
 
 
 def test_uneven_batch_sample_full_sizes():
