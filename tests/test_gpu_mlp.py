@@ -109,8 +109,9 @@ def test_gradients_match_oracle(nb):
     FP32 and FP64 pre-activations round to neighbouring FP16 values (one
     FP16 ulp, 2^-11 relative, for a small fraction of entries); 1e-3 per
     tensor bounds both with a wide margin.  Entry by entry, no gradient may
-    be off by more than 5e-3 of its tensor's largest entry (a single wrong
-    entry of a 256 x 256 tensor could hide in the normwise figure)."""
+    be off by more than 1e-3 of its tensor's largest entry (a single wrong
+    entry of a 256 x 256 tensor could hide in the normwise figure; measured
+    at most 3.5e-5)."""
     require_gpu()
     loss, g, ref_loss, ref = _grad_case(nb, 11 + nb)
     assert abs(loss - ref_loss) <= 1e-5 * max(ref_loss, 1e-12)
@@ -122,7 +123,7 @@ def test_gradients_match_oracle(nb):
         say(f"nb={nb} layer {li + 1}: dW rel {eW:.1e} (entrywise {mW:.1e}), "
             f"db rel {eb:.1e} (entrywise {mb:.1e})")
         assert eW <= 1e-3 and eb <= 1e-3
-        assert mW <= 5e-3 and mb <= 5e-3
+        assert mW <= 1e-3 and mb <= 1e-3
 
 
 def test_adam_steps_match_oracle():
