@@ -491,7 +491,18 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
   // follows a tail.  For CG an iteration publishes once (||r||).  Kernels
   // enqueued after the device has marked the solve PENDING or finished exit
   // at once and publish nothing.
-  constexpr unsigned LOOKAHEAD = 2;
+  // With the direction step in the first FFT pass the two publications of
+  // an iteration come at the start of each half, so one publication ahead
+  // is half an iteration of queued work (~50 us at 1024^2), more than the
+  // host needs to react; two kept up to ten kernels queued beyond a
+  // publication that marks the solve PENDING, all of which then ran as
+  // no-ops before the true residual (seeds 0-7 of the large workload:
+  // 1.147-1.169 ms median with one, 1.177-1.185 ms with two, 1.179-1.186 ms
+  // with three, same box).  Otherwise a publication ends a unit (CG's
+  // residual-norm step, the direction update), and with one ahead the queue
+  // would run dry at every publication: two.
+  const bool dir = dir_in_matvec(P, solver);
+  const unsigned LOOKAHEAD = dir ? 1u : 2u;
   Snap m{};
   unsigned seen = 0;             // the last publication read (mod 2^24)
   unsigned enq = 0;              // publications enqueued, if every unit runs
@@ -507,7 +518,6 @@ int solve_once(kp_plan_t plan, const float* b, double lambda, double tol, int ma
     bump();
     ++replacements;
   }
-  const bool dir = dir_in_matvec(P, solver);
   // first direction p = z_0 (CG: p = r_0)
   HIPCHK(enqueue_tail(P, solver, prec, lam2, s));
   if (solver != KP_CG && !dir) bump();
