@@ -218,10 +218,25 @@ __global__ __launch_bounds__(MB_NT) void blur_mfma_batched_kernel(
 // ---------------------------------------------------------------------------
 // batched GEMM stages of the preconditioner solve
 // ---------------------------------------------------------------------------
-template <typename T, int STAGE>
-__global__ __launch_bounds__(GT) void gemm_batched_kernel(const ItemDesc* __restrict__ items,
-                                                          const TileRef* __restrict__ tiles,
-                                                          int mode) {
+// One GEMM tile of the batch: the 256-thread tile of gemm_core.h (KS = 1)
+// or the tile with its contraction split over KS wave groups (dynamic LDS
+// `lds`), which hides the k-loop's global latency when the live items leave
+// CUs without a tile.
+template <typename T, bool BF, class Epi, int KS>
+__device__ __forceinline__ void batched_tile(const T* A, const void* B, int n, int m0, int n0,
+                                             Epi epi, float bscale, float oscale, double* pout,
+                                             char* lds) {
+  if constexpr (KS == 1)
+    gemm_tile<T, BF, Epi>(A, B, n, m0, n0, epi, bscale, oscale, pout, MAXP_ITEM);
+  else
+    gemm_tile_splitk<T, BF, Epi, KS>(A, B, n, m0, n0, epi, bscale, oscale, pout, MAXP_ITEM, lds);
+}
+
+template <typename T, int STAGE, int KS>
+__global__ __launch_bounds__(GT * KS) void gemm_batched_kernel(const ItemDesc* __restrict__ items,
+                                                               const TileRef* __restrict__ tiles,
+                                                               int mode) {
+  extern __shared__ __align__(16) char gk_lds[];      // split-K stages (KS > 1)
   const TileRef tr = tiles[blockIdx.x];
   const ItemDesc& it = items[tr.item];
   if (!item_active(it.ctrl, mode)) return;
@@ -237,19 +252,20 @@ __global__ __launch_bounds__(GT) void gemm_batched_kernel(const ItemDesc* __rest
   const T* Vr = f16 ? (const T*)it.Vr16 : (const T*)it.Vr32;
   const T* VrT = f16 ? (const T*)it.VrT16 : (const T*)it.VrT32;
   if constexpr (STAGE == 1) {
-    gemm_tile<T, true, GEpiStore<T>>(VcT, it.r, n, m0, n0, GEpiStore<T>{t1, n},
-                                     it.ctrl->pscale, 1.0f, nullptr, MAXP_ITEM);
+    batched_tile<T, true, GEpiStore<T>, KS>(VcT, it.r, n, m0, n0, GEpiStore<T>{t1, n},
+                                            it.ctrl->pscale, 1.0f, nullptr, gk_lds);
   } else if constexpr (STAGE == 2) {
-    gemm_tile<T, false, GEpiSPrimeT<T>>(t1, VrT, n, m0, n0,
-                                        GEpiSPrimeT<T>{t2, it.sc2, it.sr2, it.lam2f, n, it.d0}, 1.0f,
-                                        1.0f, nullptr, MAXP_ITEM);
+    batched_tile<T, false, GEpiSPrimeT<T>, KS>(
+        t1, VrT, n, m0, n0, GEpiSPrimeT<T>{t2, it.sc2, it.sr2, it.lam2f, n, it.d0}, 1.0f, 1.0f,
+        nullptr, gk_lds);
   } else if constexpr (STAGE == 3) {
-    gemm_tile<T, false, GEpiStore<T>>(Vc, t2, n, m0, n0, GEpiStore<T>{t3, n}, 1.0f, 1.0f,
-                                      nullptr, MAXP_ITEM);
+    batched_tile<T, false, GEpiStore<T>, KS>(Vc, t2, n, m0, n0, GEpiStore<T>{t3, n}, 1.0f, 1.0f,
+                                             nullptr, gk_lds);
   } else {
-    gemm_tile<T, false, GEpiFinal<true>>(t3, Vr, n, m0, n0, GEpiFinal<true>{it.z, it.r, it.w, n},
-                                         1.0f, it.ctrl->zscale,
-                                         it.partials + SLOT_RZ * MAXP_ITEM + tr.t, MAXP_ITEM);
+    batched_tile<T, false, GEpiFinal<true>, KS>(t3, Vr, n, m0, n0,
+                                                GEpiFinal<true>{it.z, it.r, it.w, n}, 1.0f,
+                                                it.ctrl->zscale,
+                                                it.partials + SLOT_RZ * MAXP_ITEM + tr.t, gk_lds);
   }
 }
 
@@ -656,21 +672,52 @@ static hipError_t scalar_launch(const Batch& B, int kind, int mode) {
   return hipGetLastError();
 }
 
+// Split-K tiles (two wave groups, 80 KiB of LDS: two workgroups per CU)
+// once the live items have at most two GEMM tiles per CU; below that a
+// 256-thread tile alone on its CU waits on its k-loop's global latency.
+constexpr int BATCH_KS = 2;
+constexpr int BATCH_SPLITK_TILES = 512;
+
+template <typename T, int KS>
+static hipError_t precond_stages_b(const Batch& B, int mode) {
+  hipError_t e;
+  const size_t lds = KS > 1 ? gemm_splitk_lds<T>(KS) : 0;
+  hipLaunchKernelGGL((gemm_batched_kernel<T, 1, KS>), dim3(B.n_gemm), dim3(GT * KS), lds, B.s,
+                     B.d_items, B.t_gemm, mode);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((gemm_batched_kernel<T, 2, KS>), dim3(B.n_gemm), dim3(GT * KS), lds, B.s,
+                     B.d_items, B.t_gemm, mode);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((gemm_batched_kernel<T, 3, KS>), dim3(B.n_gemm), dim3(GT * KS), lds, B.s,
+                     B.d_items, B.t_gemm, mode);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((gemm_batched_kernel<T, 4, KS>), dim3(B.n_gemm), dim3(GT * KS), lds, B.s,
+                     B.d_items, B.t_gemm, mode);
+  return hipGetLastError();
+}
+
+// LDS opt-in of the split-K stages, before graph capture
+template <typename T>
+static hipError_t ensure_splitk_b() {
+  static bool granted = false;
+  if (granted) return hipSuccess;
+  const int lds = (int)gemm_splitk_lds<T>(BATCH_KS);
+  const void* k[4] = {reinterpret_cast<const void*>(gemm_batched_kernel<T, 1, BATCH_KS>),
+                      reinterpret_cast<const void*>(gemm_batched_kernel<T, 2, BATCH_KS>),
+                      reinterpret_cast<const void*>(gemm_batched_kernel<T, 3, BATCH_KS>),
+                      reinterpret_cast<const void*>(gemm_batched_kernel<T, 4, BATCH_KS>)};
+  for (const void* f : k) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+  }
+  granted = true;
+  return hipSuccess;
+}
+
 template <typename T>
 static hipError_t precond_b(const Batch& B, int mode) {
-  hipError_t e;
-  hipLaunchKernelGGL((gemm_batched_kernel<T, 1>), dim3(B.n_gemm), dim3(GT), 0, B.s, B.d_items,
-                     B.t_gemm, mode);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((gemm_batched_kernel<T, 2>), dim3(B.n_gemm), dim3(GT), 0, B.s, B.d_items,
-                     B.t_gemm, mode);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((gemm_batched_kernel<T, 3>), dim3(B.n_gemm), dim3(GT), 0, B.s, B.d_items,
-                     B.t_gemm, mode);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((gemm_batched_kernel<T, 4>), dim3(B.n_gemm), dim3(GT), 0, B.s, B.d_items,
-                     B.t_gemm, mode);
-  return hipGetLastError();
+  if (B.n_gemm <= BATCH_SPLITK_TILES) return precond_stages_b<T, BATCH_KS>(B, mode);
+  return precond_stages_b<T, 1>(B, mode);
 }
 
 // z = M^{-1} r, r.z, beta, p = z + beta p (or the CG direction update)
@@ -1008,6 +1055,8 @@ int batched_solve(Plan* const* plans, const int* plan_of_item, int nitems, int m
   BCHK(hipMemcpyAsync(B.d_ctrl, B.h_ctrl, sizeof(Ctrl) * nitems, hipMemcpyHostToDevice, B.s));
   BCHK(hipStreamSynchronize(B.s));
 
+  BCHK(ensure_splitk_b<_Float16>());
+  BCHK(ensure_splitk_b<float>());
   // x_0 = 0 (or the caller's x), r = c = A^T b, ||c||; for a warm start
   // the residual r = c - H x_0 is a full FP64 true residual (which may find
   // the item converged already); then the first direction
