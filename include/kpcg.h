@@ -71,9 +71,7 @@ extern "C" {
                                    such a plan's solves use KP_NORMAL_FFT
                                    and tol >= 1e-7, and the FP64 normal
                                    operator, the direct normal form and
-                                   batched solves give KP_ERR_UNSUPPORTED,
-                                   and so does kp_setup where n + K - 1
-                                   exceeds the FFT menu's 2160          */
+                                   batched solves give KP_ERR_UNSUPPORTED  */
 #define KP_SETUP_LOWP   0x100   /* flag OR-ed into kp_setup's bc: reduced-
                                    precision construction of S, V_r, V_c
                                    (Section 3 leaves computing them in half
@@ -515,7 +513,7 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int *prev);
  *  - KP_NORMAL_FFT: zero-padded FFTs (Section 2.3 names FFTs for
  *    structured A; Section 5.2's cost model assumes cheap matvecs): with L
  *    the smallest length >= n + (K-1)/2 in a fixed menu of 28 products of
- *    three radices (64 .. 2160; none beyond: no FFT form) and Hc the L x L
+ *    three radices (64 .. 2160, enough for n <= 2048, K <= 63) and Hc the L x L
  *    DFT of the PSF wrapped around the origin, A p = crop(IDFT(Hc .*
  *    DFT(pad p))) and A^T q = crop(IDFT(conj(Hc) .* DFT(pad q))) on the
  *    n x n window (exact: every wrapped tap lands in the zero pad).  For
@@ -526,10 +524,8 @@ int kp_set_blur_config(kp_plan_t plan, int cfg, int *prev);
  *    Stockham FFTs in LDS; FP32 with the PSF spectrum and twiddles
  *    computed in FP64.
  * kp_setup times both on the plan and the solver uses the faster.  The FFT
- * form is offered for KP_BC_ZERO and KP_BC_REFLEXIVE plans whose length
- * is on the menu (otherwise, and for periodic plans: direct; forcing FFT
- * gives KP_ERR_UNSUPPORTED, kp_plan_info reports fft_length 0); a reflexive
- * plan whose
+ * form is offered for KP_BC_ZERO and KP_BC_REFLEXIVE plans (periodic:
+ * direct; forcing FFT gives KP_ERR_UNSUPPORTED); a reflexive plan whose
  * PSF is not symmetric has the FFT form only (forcing direct gives
  * KP_ERR_UNSUPPORTED).
  * kp_set_normal_op forces a form for pcg_solve's iterations (true residuals

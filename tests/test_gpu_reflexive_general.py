@@ -233,8 +233,9 @@ def test_reflexive_general_refusals():
     """What a plan whose A^T is not a blur cannot do is refused with
     KP_ERR_UNSUPPORTED: the direct normal operator, the FP64 normal
     operator, tolerances below 1e-7 (their true residuals would need A^T in
-    FP64), batched solves, and plans at sizes with no FFT length; K > n
-    stays an argument error."""
+    FP64) and batched solves; K > n stays an argument error, K above
+    KP_MAX_PSF is unsupported, and the largest plan (2048^2, K = 63) has
+    its FFT length."""
     torch = require_gpu()
     from paper_2311_15393_amd import (KP_BC_REFLEXIVE, KP_FPCG, KP_NORMAL_DIRECT, KP_P16,
                                       KPError, Plan, solve_batched)
@@ -258,8 +259,12 @@ def test_reflexive_general_refusals():
     with pytest.raises(KPError) as ei:
         Plan(_asym(17, 0), 15, bc=KP_BC_REFLEXIVE)
     assert ei.value.status == KP_ERR_ARG
-    # n + 2h = 2198 is beyond the FFT length menu (largest 2160): with no
-    # FFT form such a PSF has no A^T at all
+    # supports above KP_MAX_PSF (63) are refused outright; up to it every
+    # n <= 2048 has an FFT length (n + 2h <= 2110 against the menu's 2160)
+    from paper_2311_15393_amd.kpcg import workspace_size
     with pytest.raises(KPError) as ei:
-        Plan(_asym(1099, 2), 1100, bc=KP_BC_REFLEXIVE)
+        Plan(_asym(65, 2), 100, bc=KP_BC_REFLEXIVE)
     assert ei.value.status == KP_ERR_UNSUPPORTED
+    with Plan(_asym(63, 3), 2048, bc=KP_BC_REFLEXIVE) as big:
+        assert big.query()["fft_length"] == 2160 and big.query()["normal_op"] == 1
+    assert workspace_size(2048, 63) > 0
