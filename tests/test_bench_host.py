@@ -41,3 +41,20 @@ def test_fft_normal_equals_oracle(n, k, pad):
     ref = SV.NormalOperator(psf, n, 0.0, use_fft=False).H(p)
     # the spectrum is of the FP32-rounded PSF
     assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+def test_fft_normal_bytes_counts_each_pass():
+    """Algorithmic bytes of one H p by the five FFT passes, counted pass by
+    pass: rows_fwd reads p (4 n^2) and writes the half spectra S (8 F n);
+    each column pass reads its F lines (8 F n) and the PSF spectrum (8 F L)
+    and writes T (8 F n); rows_mid reads T and writes S (8 F n each);
+    rows_out reads T (8 F n) and p (4 n^2) and writes w (4 n^2)."""
+    for n, L in ((1024, 1080), (2048, 2100), (100, 128)):
+        F = L // 2 + 1
+        per_pass = [4 * n * n + 8 * F * n,
+                    8 * F * n + 8 * F * L + 8 * F * n,
+                    8 * F * n + 8 * F * n,
+                    8 * F * n + 8 * F * L + 8 * F * n,
+                    8 * F * n + 4 * n * n + 4 * n * n]
+        assert bench.fft_normal_bytes(n, L) == sum(per_pass)
+    assert bench.fft_normal_bytes(1024, 1080) == 57386368
