@@ -55,13 +55,14 @@ def test_fft_normal_matches_oracle(n, k):
 
 
 @pytest.mark.parametrize("n,k,mode_name", [(256, 31, "fpcg16"), (1024, 63, "fpcg16"),
-                                           (200, 15, "pcg32"), (129, 23, "fpcg16"),
-                                           (64, 15, "cg")])
+                                           (1536, 31, "fpcg16"), (200, 15, "pcg32"),
+                                           (129, 23, "fpcg16"), (64, 15, "cg")])
 def test_solve_with_fft_normal(n, k, mode_name):
     """Solves whose iterations use the FFT form reach x_lambda (1e-4 for the
     FP16 preconditioner and CG, 1e-5 for FP32), certified by true
     residuals on the blurs; n = 129 leaves the last line of every row pass
-    (the one that also takes the direction step) with a single real row.  CG runs to a tighter tolerance: without a
+    (the one that also takes the direction step) with a single real row,
+    and n = 1536 (L = 1600) runs the passes with one line per workgroup.  CG runs to a tighter tolerance: without a
     preconditioner the error is up to cond(H) times the relative residual
     (about 2.5e3 here)."""
     torch = require_gpu()
