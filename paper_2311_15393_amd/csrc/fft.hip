@@ -303,12 +303,20 @@ __device__ __forceinline__ void sh_stage(Src&& src, Dst&& dst, const float2* tw)
   }
 }
 
+struct NoStep {
+  __device__ void operator()() const {}
+};
+
 // A whole transform: stage 1 from src into X, stage 2 from X into Y, stage
 // 3 from Y into dst, with barriers between them.  src must not read X.
-template <class C, bool INV, class Src, class Dst>
+// after1 runs between stage 1 (which reads no twiddles) and its barrier: a
+// pass stores its twiddle table to LDS there, so that waiting for the table
+// does not hold back the issue of stage 1's global loads.
+template <class C, bool INV, class Src, class Dst, class After1 = NoStep>
 __device__ __forceinline__ void sh_transform(Src&& src, float2* X, float2* Y, Dst&& dst,
-                                             const float2* tw) {
+                                             const float2* tw, After1 after1 = {}) {
   sh_stage<C, C::R1, 1, INV>(src, [&](int b, int t, float2 v) { X[b * C::LP + t] = v; }, tw);
+  after1();
   __syncthreads();
   sh_stage<C, C::R2, C::R1, INV>([&](int b, int t) { return X[b * C::LP + t]; },
                                  [&](int b, int t, float2 v) { Y[b * C::LP + t] = v; }, tw);
@@ -335,21 +343,21 @@ __device__ inline void split_store(const float2* Z, int line0, int nl, int rows,
   }
 }
 
-// The Hermitian-extended spectrum of rows ra (real part) and rb (imaginary
-// part, rb < 0: zero) at frequency kap: Z = A + i B from the half spectra
-// stored in T[k][row].
+// The Hermitian-extended spectrum of rows ra (real part, ra < 0: zero) and
+// rb (imaginary part, rb < 0: zero) at frequency kap: Z = A + i B from the
+// half spectra stored in T[k][row].  Only the loads sit under the guards:
+// arithmetic on a loaded value inside its guard makes the compiler wait for
+// that load before issuing the next, one memory latency per element.
 template <class C>
 __device__ inline float2 row_spectrum(const float2* __restrict__ T, int tpitch, int ra, int rb,
                                       int kap) {
   const bool low = kap < C::F;
   const int kk = low ? kap : C::L - kap;
-  float2 A = T[(size_t)kk * tpitch + ra];
-  float2 Bv = rb >= 0 ? T[(size_t)kk * tpitch + rb] : make_float2(0.f, 0.f);
-  if (!low) {
-    A.y = -A.y;
-    Bv.y = -Bv.y;
-  }
-  return make_float2(A.x - Bv.y, A.y + Bv.x);
+  float2 A = make_float2(0.f, 0.f), Bv = A;
+  if (ra >= 0) A = T[(size_t)kk * tpitch + ra];
+  if (rb >= 0) Bv = T[(size_t)kk * tpitch + rb];
+  const float ay = low ? A.y : -A.y, by = low ? Bv.y : -Bv.y;
+  return make_float2(A.x - by, ay + Bv.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -388,8 +396,8 @@ __global__ __launch_bounds__(C::NT) void fft_rows_fwd_kernel(const float* __rest
     if (sb < rows) x.y = p[(size_t)(ext ? refl_index(sb - h, n) : sb) * n + jj];
     return x;
   };
-  ts.store(tw, C::L);          // first read in stage 2, after a barrier
-  sh_transform<C, false>(src, A, Bf, [&](int b, int t, float2 v) { A[b * C::LP + t] = v; }, tw);
+  sh_transform<C, false>(src, A, Bf, [&](int b, int t, float2 v) { A[b * C::LP + t] = v; }, tw,
+                         [&] { ts.store(tw, C::L); });
   __syncthreads();
   split_store<C>(A, line0, nl, rows, S, g.spitch);
 }
@@ -497,16 +505,15 @@ __global__ __launch_bounds__(C::NT) void fft_cols_kernel(const float2* __restric
   const int n = g.n, k0 = blockIdx.x * C::B;
   TwLoad<C::NT, C::TWN> ts;
   ts.load(g.tw, C::L);
-  // the PSF spectrum of this thread's elements of the product below
+  // the PSF spectrum of this thread's elements of the product below (only
+  // the loads under the guard, conjugated at the product, so that the loads
+  // are all in flight together)
   float2 hv[C::EPT];
 #pragma unroll
   for (int i = 0; i < C::EPT; ++i) {
     const int q = threadIdx.x + i * C::NT, b = q % C::B, t = q / C::B, k = k0 + b;
     hv[i] = make_float2(0.f, 0.f);
-    if (q < C::B * C::L && k < C::F) {
-      hv[i] = Ht[(size_t)k * C::L + t];
-      if (conjH) hv[i].y = -hv[i].y;
-    }
+    if (q < C::B * C::L && k < C::F) hv[i] = Ht[(size_t)k * C::L + t];
   }
   auto src = [&](int b, int t) -> float2 {
     const int k = k0 + b;
@@ -514,13 +521,15 @@ __global__ __launch_bounds__(C::NT) void fft_cols_kernel(const float2* __restric
     return (k < C::F && sl >= 0 && sl < in_rows) ? S[(size_t)k * g.spitch + sl]
                                                  : make_float2(0.f, 0.f);
   };
-  ts.store(tw, C::L);
-  sh_transform<C, false>(src, A, Bf, [&](int b, int t, float2 v) { A[b * C::LP + t] = v; }, tw);
+  sh_transform<C, false>(src, A, Bf, [&](int b, int t, float2 v) { A[b * C::LP + t] = v; }, tw,
+                         [&] { ts.store(tw, C::L); });
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < C::EPT; ++i) {
     const int q = threadIdx.x + i * C::NT, b = q % C::B, t = q / C::B;
-    if (q < C::B * C::L) A[b * C::LP + t] = cmul(A[b * C::LP + t], hv[i]);
+    float2 hq = hv[i];
+    if (conjH) hq.y = -hq.y;
+    if (q < C::B * C::L) A[b * C::LP + t] = cmul(A[b * C::LP + t], hq);
   }
   __syncthreads();
   auto srcA = [&](int b, int t) { return A[b * C::LP + t]; };
@@ -561,13 +570,13 @@ __global__ __launch_bounds__(C::NT) void fft_rows_mid_kernel(const float2* __res
   TwLoad<C::NT, C::TWN> ts;
   ts.load(g.tw, C::L);
   auto src = [&](int b, int kap) -> float2 {
-    const int line = line0 + b, ra = 2 * line, rb = ra + 1 < n ? ra + 1 : -1;
-    if (line >= nl) return make_float2(0.f, 0.f);
+    const int line = line0 + b, live = line < nl;
+    const int ra = live ? 2 * line : -1, rb = live && 2 * line + 1 < n ? 2 * line + 1 : -1;
     return row_spectrum<C>(T, g.tpitch, ra, rb, kap);
   };
-  ts.store(tw, C::L);
   // A p of the line's two rows (real, imaginary part) into A
-  sh_transform<C, true>(src, A, Bf, [&](int b, int t, float2 v) { A[b * C::LP + t] = v; }, tw);
+  sh_transform<C, true>(src, A, Bf, [&](int b, int t, float2 v) { A[b * C::LP + t] = v; }, tw,
+                        [&] { ts.store(tw, C::L); });
   __syncthreads();
   // columns >= n cut, re-padded; forward transform into Bf
   auto srcc = [&](int b, int t) -> float2 {
@@ -612,12 +621,12 @@ __global__ __launch_bounds__(C::NT) void fft_rows_out_kernel(
     pb[i] = (ok && rb < n) ? p[(size_t)rb * n + j] : 0.f;
   }
   auto src = [&](int b, int kap) -> float2 {
-    const int line = line0 + b, ra = 2 * line, rb = ra + 1 < n ? ra + 1 : -1;
-    if (line >= nl) return make_float2(0.f, 0.f);
+    const int line = line0 + b, live = line < nl;
+    const int ra = live ? 2 * line : -1, rb = live && 2 * line + 1 < n ? 2 * line + 1 : -1;
     return row_spectrum<C>(T, g.tpitch, ra, rb, kap);
   };
-  ts.store(tw, C::L);
-  sh_transform<C, true>(src, A, Bf, [&](int b, int t, float2 v) { A[b * C::LP + t] = v; }, tw);
+  sh_transform<C, true>(src, A, Bf, [&](int b, int t, float2 v) { A[b * C::LP + t] = v; }, tw,
+                        [&] { ts.store(tw, C::L); });
   __syncthreads();
   const int hf = fold ? g.h : 0;
   double dsum = 0.0;
