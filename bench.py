@@ -72,13 +72,13 @@ BLUR_TRAFFIC = {
 # measured (sha256 of batch.hip).
 VECTOR_KERNELS = {
     "workload": "16 items of 1024^2 (~1 GiB of item vectors), profiles/vector_kernels_batch16_1024_hbm.md",
-    "update": {"kernel": "vec_batched_kernel<0>", "avg_us": 83.89, "bytes_per_launch": 536870912,
-               "achieved_TBps": 6.400, "frac_of_8TBps": 0.800,
-               "traffic": {"fetch_bytes": 336250368, "write_bytes": 202136269}},
-    "pupdate": {"kernel": "vec_batched_kernel<1>", "avg_us": 34.43, "bytes_per_launch": 201326592,
-                "achieved_TBps": 5.848, "frac_of_8TBps": 0.731,
-                "traffic": {"fetch_bytes": 134860800, "write_bytes": 67108864}},
-    "sources_sha256": "6be39aeb601c4ef8cc814655e97845f5f147644b9c802ab7624f7c48723099a5",
+    "update": {"kernel": "vec_batched_kernel<0>", "avg_us": 83.24, "bytes_per_launch": 536870912,
+               "achieved_TBps": 6.450, "frac_of_8TBps": 0.806,
+               "traffic": {"fetch_bytes": 336246474, "write_bytes": 202213344}},
+    "pupdate": {"kernel": "vec_batched_kernel<1>", "avg_us": 35.75, "bytes_per_launch": 201326592,
+                "achieved_TBps": 5.632, "frac_of_8TBps": 0.704,
+                "traffic": {"fetch_bytes": 134845617, "write_bytes": 67108864}},
+    "sources_sha256": "d8fca763271cf33e80eff01f5104fb099d6a1429e3f0db134c5cf7e616a19724",
 }
 
 
@@ -95,11 +95,11 @@ VECTOR_KERNELS = {
 FFT_TRAFFIC = {
     "fft_length": 1080,
     # per launch of each pass, as counted
-    "fetch_kib_raw": {"rows_fwd": 2143.1, "cols": 4611.9, "rows_mid": 2285.0, "rows_out": 4322.0},
+    "fetch_kib_raw": {"rows_fwd": 2147.5, "cols": 4603.4, "rows_mid": 2284.0, "rows_out": 4321.0},
     "write_kib_raw": {"rows_fwd": 4395.5, "cols": 4328.0, "rows_mid": 4395.5, "rows_out": 4098.0},
-    "fetch_scale": 1.99978, "write_scale": 1.0,              # copy bytes / counter
-    "bytes_per_unit": 58868555,                               # one H p (two column passes)
-    "sources_sha256": "af40b8b56832e968bc44c155f7279219a68aa9c6b8c6b481a021afdd48a2d2d1",
+    "fetch_scale": 1.99980, "write_scale": 1.0,              # copy bytes / counter
+    "bytes_per_unit": 58838967,                               # one H p (two column passes)
+    "sources_sha256": "6fe31db9b15111f1d66bef874e00ee7822668847df497f4859a7519f01f1b7cb",
 }
 
 
