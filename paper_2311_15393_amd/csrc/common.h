@@ -320,6 +320,49 @@ __device__ inline double beta_of(const Ctrl* c, double rz, double zw, bool* ok) 
   return -zw / c->delta;
 }
 
+// The control-block fields from which the folded scalar steps decide (the
+// state after ||r||^2, the step length, beta), read by every workgroup at
+// its kernel's start, before its first global loads.  Read after the fold,
+// each would add a memory latency to every workgroup's path, since each read
+// hangs on a branch over the one before.  A kernel that takes the snapshot
+// uses only fields that none of its own workgroups writes (block 0's step
+// writes others), so every workgroup sees what the kernels before it left.
+struct StepIn {
+  double tol2, repl2, rho, rz, delta;
+  int solver, prec, first, fr_next;
+};
+
+__device__ inline StepIn step_in(const Ctrl* c) {
+  StepIn k;
+  k.tol2 = c->tol2;
+  k.repl2 = c->repl2;
+  k.rho = c->rho;
+  k.rz = c->rz;
+  k.delta = c->delta;
+  k.solver = c->solver;
+  k.prec = c->prec;
+  k.first = c->first;
+  k.fr_next = c->fr_next;
+  return k;
+}
+
+// rr_state, beta_of and step_rho on a snapshot taken by step_in
+__device__ inline int rr_state(const StepIn& k, double S) {
+  if (!isfinite(S)) return BREAKDOWN;
+  if (S <= k.tol2 || S <= k.repl2) return PENDING;
+  return RUNNING;
+}
+
+__device__ inline double beta_of(const StepIn& k, double rz, double zw, bool* ok) {
+  *ok = (rz > 0.0) && isfinite(rz) && isfinite(zw);
+  if (!*ok) return 0.0;
+  if (k.first) return 0.0;
+  if (k.solver == KP_PCG || k.fr_next) return rz / k.rho;
+  return -zw / k.delta;
+}
+
+__device__ inline double step_rho(const StepIn& k) { return k.solver == KP_CG ? k.rho : k.rz; }
+
 // radices of the FFT form's transform length (three stages)
 constexpr int FFT_MAX_RADICES = 3;
 

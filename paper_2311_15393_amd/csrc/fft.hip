@@ -421,6 +421,7 @@ template <class C>
 __global__ __launch_bounds__(C::NT) void fft_rows_fwd_dir_kernel(float* __restrict__ p, FftGeom g,
                                                                float2* __restrict__ S, DirStep ds) {
   if (ds.ctrl->done != RUNNING) return;
+  const StepIn kin = step_in(ds.ctrl);
   extern __shared__ float2 fft_lds[];
   __shared__ double sh[2 * (C::NT / 64 + 1)];
   float2* tw = fft_lds;
@@ -450,7 +451,7 @@ __global__ __launch_bounds__(C::NT) void fft_rows_fwd_dir_kernel(float* __restri
   const double2 f = fold_slot2<C::NT>(ds.partials, SLOT_RZ, SLOT_ZW, ds.nbz, sh);
   const double rz = f.x, zw = f.y;
   bool ok;
-  const double beta = beta_of(ds.ctrl, rz, zw, &ok);
+  const double beta = beta_of(kin, rz, zw, &ok);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ds.ctrl->rz = rz;
     ds.ctrl->zw = zw;

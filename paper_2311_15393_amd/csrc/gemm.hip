@@ -44,6 +44,7 @@ struct RrFold {
   int nb;
   CtrlMirror* mirror;
   bool scale;
+  StepIn kin;             // taken at the kernel's start
   __device__ bool operator()(float& bscale, char* lds) const {
     double* sh = reinterpret_cast<double*>(lds);
     const double S = fold_slot<GT * GEMM_KS>(partials, SLOT_RR, nb, sh);
@@ -51,8 +52,8 @@ struct RrFold {
       apply_rr(ctrl, S);
       if (mirror != nullptr) publish_mirror(ctrl, mirror);
     }
-    if (rr_state(ctrl, S) != RUNNING) return false;    // the same decision in every block
-    if (scale) bscale = ctrl->prec == KP_P16 ? fp16_residual_scale(S) : 1.0f;
+    if (rr_state(kin, S) != RUNNING) return false;     // the same decision in every block
+    if (scale) bscale = kin.prec == KP_P16 ? fp16_residual_scale(S) : 1.0f;
     return true;
   }
 };
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(GT * GEMM_KS) void gemm_kernel(const T* __restrict_
   const float oscale = (scale_mode & 2) ? ctrl->zscale : 1.0f;
   const int bid = blockIdx.y * gridDim.x + blockIdx.x;
   if (fold_rr > 0) {
-    RrFold f{ctrl, partials, fold_rr, mirror, (scale_mode & 1) != 0};
+    RrFold f{ctrl, partials, fold_rr, mirror, (scale_mode & 1) != 0, step_in(ctrl)};
     gemm_tile_splitk<T, B_FROM_F32, Epi, GEMM_KS, RrFold>(
         A, Bsrc, n, blockIdx.y * BM, blockIdx.x * BN, epi, bscale, oscale,
         partials + SLOT_RZ * MAX_PARTIALS + bid, MAX_PARTIALS, gemm_lds, f);

@@ -12,6 +12,7 @@ struct Fp8RrFold {
   const double* partials;
   int nb;
   CtrlMirror* mirror;
+  StepIn kin;             // taken at the kernel's start
   __device__ bool operator()() const {
     __shared__ double fsh[G8T / 64 + 1];
     const double S = fold_slot<G8T>(partials, SLOT_RR, nb, fsh);
@@ -19,7 +20,7 @@ struct Fp8RrFold {
       apply_rr(ctrl, S);
       if (mirror != nullptr) publish_mirror(ctrl, mirror);
     }
-    return rr_state(ctrl, S) == RUNNING;                // the same decision in every block
+    return rr_state(kin, S) == RUNNING;                 // the same decision in every block
   }
 };
 
@@ -32,7 +33,7 @@ __global__ __launch_bounds__(G8T) void gemm8_kernel(Gemm8Args g, Ctrl* ctrl, int
   double* pout = partials + SLOT_RZ * MAX_PARTIALS + blockIdx.y * gridDim.x + blockIdx.x;
   if (fold_rr > 0)
     gemm8_tile<B_F32, EPI>(g, m0, n0, ctrl, pout, MAX_PARTIALS,
-                           Fp8RrFold{ctrl, partials, fold_rr, mirror});
+                           Fp8RrFold{ctrl, partials, fold_rr, mirror, step_in(ctrl)});
   else
     gemm8_tile<B_F32, EPI>(g, m0, n0, ctrl, pout, MAX_PARTIALS, NoFold8{});
 }

@@ -97,11 +97,12 @@ __global__ __launch_bounds__(VT) void pupdate_fold_kernel(float* __restrict__ p,
                                                           int nbz,
                                                           CtrlMirror* __restrict__ mirror) {
   if (ctrl->done != RUNNING) return;
+  const StepIn kin = step_in(ctrl);
   __shared__ double sh[2 * (VT / 64 + 1)];
   const double2 f = fold_slot2<VT>(partials, SLOT_RZ, SLOT_ZW, nbz, sh);
   const double rz = f.x, zw = f.y;
   bool ok;
-  const double beta = beta_of(ctrl, rz, zw, &ok);
+  const double beta = beta_of(kin, rz, zw, &ok);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctrl->rz = rz;
     ctrl->zw = zw;
@@ -328,6 +329,7 @@ __global__ __launch_bounds__(VT) void update_alpha_kernel(double* __restrict__ x
                                                           Ctrl* ctrl, double* partials, int nbd,
                                                           CtrlMirror* __restrict__ mirror) {
   if (ctrl->done != RUNNING) return;
+  const StepIn kin = step_in(ctrl);
   __shared__ double shd[VT / 64];
   __shared__ double s_delta;
   const double S0 = sum_slot(partials, SLOT_DELTA, nbd, shd);     // valid in thread 0
@@ -343,7 +345,7 @@ __global__ __launch_bounds__(VT) void update_alpha_kernel(double* __restrict__ x
     }
     return;
   }
-  const double ad = step_rho(ctrl) / S;
+  const double ad = step_rho(kin) / S;
   if (lead) {
     ctrl->delta = S;
     ctrl->alpha = ad;
