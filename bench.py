@@ -98,8 +98,8 @@ FFT_TRAFFIC = {
     "fetch_kib_raw": {"rows_fwd": 2147.5, "cols": 4603.4, "rows_mid": 2284.0, "rows_out": 4321.0},
     "write_kib_raw": {"rows_fwd": 4395.5, "cols": 4328.0, "rows_mid": 4395.5, "rows_out": 4098.0},
     "fetch_scale": 1.99980, "write_scale": 1.0,              # copy bytes / counter
-    "bytes_per_unit": 58838967,                               # one H p (two column passes)
-    "sources_sha256": "6fe31db9b15111f1d66bef874e00ee7822668847df497f4859a7519f01f1b7cb",
+    "bytes_per_unit": 58839282,                               # one H p (two column passes)
+    "sources_sha256": "811831aed68c29598ca98eddc4ed2bc2b91094ae2751949d262646995a7b65d2",
 }
 
 
