@@ -194,54 +194,91 @@ __device__ inline void set_scales(Ctrl* c, double rr) {
 // measured far slower than a second launch.)
 // ---------------------------------------------------------------------------
 constexpr int FOLD_T = 256;            // threads that read partials, as the scalar step
+constexpr int FOLD_W = FOLD_T / 64;    // ... and their waves
 
-// Sum of the nb partials of `slot`: threads below FOLD_T stride over them
-// as the scalar step does, then the block sum (the other threads add exact
-// zeros).  Returned to every thread through sh[NT / 64 + 1].
+// Doubles of LDS scratch a fold in a block of NT threads needs (fold_slot2:
+// twice as many).
+template <int NT>
+constexpr int fold_sh() {
+  return (NT / 64 > FOLD_W ? NT / 64 : FOLD_W) + 1;
+}
+
+// Sum of the nb partials of `slot` in the scalar step's order, whatever the
+// block size NT: FOLD_T virtual threads stride over the partials (virtual
+// thread v sums partials v, v + FOLD_T, ... from zero), each virtual wave of
+// 64 is reduced by one real wave (real wave w takes virtual waves w,
+// w + NT/64, ...: a block of fewer than FOLD_T threads covers them all), and
+// the FOLD_W wave totals are added in order.  Returned to every thread
+// through sh[fold_sh<NT>()].
 template <int NT>
 __device__ inline double fold_slot(const double* __restrict__ partials, int slot, int nb,
                                    double* sh) {
-  double s = 0.0;
-  if (threadIdx.x < FOLD_T)
-    for (int i = threadIdx.x; i < nb; i += FOLD_T) s += partials[slot * MAX_PARTIALS + i];
-  const double t = block_sum<NT>(s, sh);
-  if (threadIdx.x == 0) sh[NT / 64] = t;
+  constexpr int RW = NT / 64, PER = (FOLD_W + RW - 1) / RW;   // virtual waves per real wave
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double v[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int vw = wid + k * RW;
+    double s = 0.0;
+    if (vw < FOLD_W)
+      for (int i = vw * 64 + lane; i < nb; i += FOLD_T) s += partials[slot * MAX_PARTIALS + i];
+    v[k] = wave_sum(s);
+  }
+  __syncthreads();                     // sh may still be read by an earlier reduction
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (lane == 0 && wid + k * RW < FOLD_W) sh[wid + k * RW] = v[k];
   __syncthreads();
-  return sh[NT / 64];
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < FOLD_W; ++w) t += sh[w];
+    sh[FOLD_W] = t;
+  }
+  __syncthreads();
+  return sh[FOLD_W];
 }
 
 // Two slots at once (one round of partial loads, one block reduction),
-// each summed exactly as fold_slot sums it.  sh: 2 (NT / 64 + 1) doubles.
+// each summed exactly as fold_slot sums it.  sh: 2 fold_sh<NT>() doubles.
 template <int NT>
 __device__ inline double2 fold_slot2(const double* __restrict__ partials, int slot_a, int slot_b,
                                      int nb, double* sh) {
-  double a = 0.0, b = 0.0;
-  if (threadIdx.x < FOLD_T)
-    for (int i = threadIdx.x; i < nb; i += FOLD_T) {
-      a += partials[slot_a * MAX_PARTIALS + i];
-      b += partials[slot_b * MAX_PARTIALS + i];
-    }
-  a = wave_sum(a);
-  b = wave_sum(b);
+  constexpr int RW = NT / 64, PER = (FOLD_W + RW - 1) / RW;   // virtual waves per real wave
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) {
-    sh[2 * wid] = a;
-    sh[2 * wid + 1] = b;
+  double va[PER], vb[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int vw = wid + k * RW;
+    double a = 0.0, b = 0.0;
+    if (vw < FOLD_W)
+      for (int i = vw * 64 + lane; i < nb; i += FOLD_T) {
+        a += partials[slot_a * MAX_PARTIALS + i];
+        b += partials[slot_b * MAX_PARTIALS + i];
+      }
+    va[k] = wave_sum(a);
+    vb[k] = wave_sum(b);
   }
+  __syncthreads();                     // sh may still be read by an earlier reduction
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (lane == 0 && wid + k * RW < FOLD_W) {
+      sh[2 * (wid + k * RW)] = va[k];
+      sh[2 * (wid + k * RW) + 1] = vb[k];
+    }
   __syncthreads();
   if (threadIdx.x == 0) {
     double ta = 0.0, tb = 0.0;
 #pragma unroll
-    for (int w = 0; w < NT / 64; ++w) {
+    for (int w = 0; w < FOLD_W; ++w) {
       ta += sh[2 * w];
       tb += sh[2 * w + 1];
     }
-    sh[2 * (NT / 64)] = ta;
-    sh[2 * (NT / 64) + 1] = tb;
+    sh[2 * FOLD_W] = ta;
+    sh[2 * FOLD_W + 1] = tb;
   }
   __syncthreads();
-  return make_double2(sh[2 * (NT / 64)], sh[2 * (NT / 64) + 1]);
+  return make_double2(sh[2 * FOLD_W], sh[2 * FOLD_W + 1]);
 }
 
 // r.z of the current direction: the last direction step's (PCG, FPCG) or

@@ -423,7 +423,7 @@ __global__ __launch_bounds__(C::NT) void fft_rows_fwd_dir_kernel(float* __restri
   if (ds.ctrl->done != RUNNING) return;
   const StepIn kin = step_in(ds.ctrl);
   extern __shared__ float2 fft_lds[];
-  __shared__ double sh[2 * (C::NT / 64 + 1)];
+  __shared__ double sh[2 * fold_sh<C::NT>()];
   float2* tw = fft_lds;
   float2* A = tw + C::L;
   float2* Bf = A + C::B * C::LP;

@@ -14,7 +14,7 @@ struct Fp8RrFold {
   CtrlMirror* mirror;
   StepIn kin;             // taken at the kernel's start
   __device__ bool operator()() const {
-    __shared__ double fsh[G8T / 64 + 1];
+    __shared__ double fsh[fold_sh<G8T>()];
     const double S = fold_slot<G8T>(partials, SLOT_RR, nb, fsh);
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
       apply_rr(ctrl, S);

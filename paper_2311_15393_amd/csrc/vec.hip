@@ -98,7 +98,7 @@ __global__ __launch_bounds__(VT) void pupdate_fold_kernel(float* __restrict__ p,
                                                           CtrlMirror* __restrict__ mirror) {
   if (ctrl->done != RUNNING) return;
   const StepIn kin = step_in(ctrl);
-  __shared__ double sh[2 * (VT / 64 + 1)];
+  __shared__ double sh[2 * fold_sh<VT>()];
   const double2 f = fold_slot2<VT>(partials, SLOT_RZ, SLOT_ZW, nbz, sh);
   const double rz = f.x, zw = f.y;
   bool ok;
