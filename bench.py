@@ -95,11 +95,11 @@ VECTOR_KERNELS = {
 FFT_TRAFFIC = {
     "fft_length": 1080,
     # per launch of each pass, as counted
-    "fetch_kib_raw": {"rows_fwd": 2147.5, "cols": 4603.4, "rows_mid": 2284.0, "rows_out": 4321.0},
+    "fetch_kib_raw": {"rows_fwd": 2147.6, "cols": 4611.4, "rows_mid": 2279.0, "rows_out": 4323.5},
     "write_kib_raw": {"rows_fwd": 4395.5, "cols": 4328.0, "rows_mid": 4395.5, "rows_out": 4098.0},
     "fetch_scale": 1.99980, "write_scale": 1.0,              # copy bytes / counter
-    "bytes_per_unit": 58839282,                               # one H p (two column passes)
-    "sources_sha256": "811831aed68c29598ca98eddc4ed2bc2b91094ae2751949d262646995a7b65d2",
+    "bytes_per_unit": 58866873,                               # one H p (two column passes)
+    "sources_sha256": "ff14c3948e211595118c07693ceac7577a3244fc8d8f3c9b2b04bcdf794797ae",
 }
 
 

@@ -209,7 +209,8 @@ constexpr int fold_sh() {
 // 64 is reduced by one real wave (real wave w takes virtual waves w,
 // w + NT/64, ...: a block of fewer than FOLD_T threads covers them all), and
 // the FOLD_W wave totals are added in order.  Returned to every thread
-// through sh[fold_sh<NT>()].
+// through sh[fold_sh<NT>()], which is free again on return (the first GEMM
+// stages its operands into the same LDS).
 template <int NT>
 __device__ inline double fold_slot(const double* __restrict__ partials, int slot, int nb,
                                    double* sh) {
@@ -236,7 +237,9 @@ __device__ inline double fold_slot(const double* __restrict__ partials, int slot
     sh[FOLD_W] = t;
   }
   __syncthreads();
-  return sh[FOLD_W];
+  const double r = sh[FOLD_W];
+  __syncthreads();                     // every thread has read it: the caller may reuse sh
+  return r;
 }
 
 // Two slots at once (one round of partial loads, one block reduction),
@@ -278,7 +281,9 @@ __device__ inline double2 fold_slot2(const double* __restrict__ partials, int sl
     sh[2 * FOLD_W + 1] = tb;
   }
   __syncthreads();
-  return make_double2(sh[2 * FOLD_W], sh[2 * FOLD_W + 1]);
+  const double2 r = make_double2(sh[2 * FOLD_W], sh[2 * FOLD_W + 1]);
+  __syncthreads();                     // every thread has read it: the caller may reuse sh
+  return r;
 }
 
 // r.z of the current direction: the last direction step's (PCG, FPCG) or
