@@ -209,3 +209,29 @@ def test_fft_solves_every_preconditioned_mode(mode_name):
         xw, infow = plan.solve(b, lam, tol=tol, maxit=3000, mode=mode | K.KP_WARM, x=xw)
         say(f"  warm start: iters={infow.iters}")
         assert infow.status == K.KP_OK and infow.iters <= 3 and rel(to_host(xw), ref) <= bar
+
+
+@pytest.mark.parametrize("n,k", [(1024, 63), (1536, 31)])
+def test_fft_solves_are_bitwise_reproducible(n, k):
+    """Two FP16-KP FPCG solves of one problem through the FFT form, each
+    from x = 0, give the same x bit for bit and the same iteration count:
+    every reduction (the folds in the direction step, the first GEMM and the
+    update, each in the scalar step's order) is deterministic, and no kernel
+    reads LDS or partials another workgroup may still be writing.  n = 1536
+    runs the direction step's fold in blocks of 192 threads."""
+    torch = require_gpu()
+    import paper_2311_15393_amd as K
+    psf = _psf(k, 3 * n + k)
+    prob = S.make_problem(n, psf, np.random.default_rng(n + 7), 0.01, None, n + 7, "fft")
+    with K.Plan(psf, n) as plan:
+        plan.set_normal_op(K.KP_NORMAL_FFT)
+        b = to_dev(prob.b)
+        outs = []
+        for _ in range(2):
+            x = torch.zeros_like(b)
+            x, info = plan.solve(b, 0.02, tol=1e-6, maxit=500, mode=K.KP_FPCG | K.KP_P16, x=x)
+            outs.append((to_host(x), info.iters, info.status))
+    say(f"n={n} K={k}: iterations {outs[0][1]}, {outs[1][1]}")
+    assert outs[0][2] == K.KP_OK and outs[1][2] == K.KP_OK
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0].view(np.uint32), outs[1][0].view(np.uint32))
