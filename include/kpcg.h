@@ -228,8 +228,10 @@ int kp_plan_query(kp_plan_t plan, kp_plan_info_t *out);
  *
  *   b       device, n*n float32 data
  *   lambda  > 0, tol > 0 (relative to ||A^T b||), maxit >= 1
- *   x       device, n*n float32: initial guess if mode & KP_WARM, else
- *           ignored (x_0 = 0); on return the last iterate
+ *   x       device, n*n float32, not aliasing b: initial guess if
+ *           mode & KP_WARM, else ignored (x_0 = 0); on return the last
+ *           iterate (written in FP32 while the solve runs: b is read by
+ *           every true residual)
  *   info    out (may be NULL)
  * If a solve with the FP16 or FP8 preconditioner ends in KP_MAXIT or
  * KP_BREAKDOWN (with a finite iterate), it is restarted from its last
